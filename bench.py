@@ -1,0 +1,211 @@
+#!/usr/bin/env python3
+"""Benchmark: ms per time step of the subspace-accelerated sequence solver on one MI355X.
+
+Workload (one GPU): the 512 x 512 advection-diffusion sequence A(t_i) x = b(t_i)
+(n = 262 144, 1 308 672 nonzeros, FP64), history M = 20, SRHT sketch s = 80,
+Galerkin projection, GMRES(30) to ||b - A x|| <= 1e-8 ||b||.  A step is one pass of
+the whole hot path: initial guess (sketched QR basis, SpMM + Gram, reduced solve,
+x0) -> Krylov solve -> history push (copy + sketch + QRCP).  All A(t_i), b(t_i) of
+the run are assembled on the host and copied to HBM before timing.
+
+Prints ONE JSON line (see the keys at the end of main()).
+"""
+
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import os
+import statistics
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+METRIC = "ms/timestep + Krylov iters at relres 1e-8, learned/mixed vs plain; SpMV GB/s"
+HBM_PEAK_GBS = 8000.0
+
+
+def log(*a):
+    print("[bench]", *a, file=sys.stderr, flush=True)
+
+
+def assemble(problem, steps):
+    import numpy as np
+
+    vals, rhs = [], []
+    for i in range(steps):
+        vals.append(problem.matrix(i).val)
+        rhs.append(problem.rhs(i))
+    return np.stack(vals), np.stack(rhs)
+
+
+def run_sequence(sacc, torch, A, vals_d, rhs_d, method, steps, warmup, guess="projection"):
+    """Run warmup + steps; returns per-step infos of the timed steps and the wall time."""
+    seq = sacc.Sequence(A.n, method["M"], s=method["s"], sketch=method["sketch"], solver=method["solver"],
+                        restart=method["restart"], tol=method["tol"], seed=method["method_seed"], guess=guess)
+    x = torch.empty(A.n, dtype=torch.float64, device="cuda")
+    infos = []
+
+    def step(i):
+        A.val.copy_(vals_d[i])
+        b = rhs_d[i]
+        seq.initial_guess(A, b, x, info=False)
+        _, inf = seq.solve(A, b, x)
+        seq.push(x)
+        return inf
+
+    for i in range(warmup):
+        step(i)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for i in range(warmup, warmup + steps):
+        infos.append(step(i))
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    return infos, wall
+
+
+def spmv_gbps(sacc, torch, A, reps=200):
+    x = torch.randn(A.n, dtype=torch.float64, device="cuda")
+    y = torch.empty_like(x)
+    for _ in range(10):
+        sacc.spmv(A, x, y)
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        sacc.spmv(A, x, y)
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / reps
+    nbytes = A.nnz * (A.val.element_size() + 4) + 4 * (A.n + 1) + 2 * 8 * A.n
+    return nbytes / (ms * 1e-3) / 1e9, ms, nbytes
+
+
+def cpu_baseline(problem, method, start, seconds):
+    """The oracle on the host: history warm-started from sparse-LU solutions of the M
+    steps before `start` (untimed), then steps start, start+1, ... timed until
+    `seconds` of CPU work have been spent."""
+    import numpy as np
+    import scipy.sparse.linalg as spla
+
+    from oracle.sequence import make_sequence
+
+    seq = make_sequence(problem, method)
+    for i in range(start - method["M"], start):
+        A = problem.matrix(i).to_scipy().tocsc()
+        seq.push(spla.splu(A).solve(problem.rhs(i)))
+    times, iters = [], []
+    i = start
+    spent = 0.0
+    while spent < seconds and i < problem.steps:
+        A = problem.matrix(i).to_scipy()
+        b = problem.rhs(i)
+        t0 = time.perf_counter()
+        _, _, info = seq.step(A, b)
+        dt = time.perf_counter() - t0
+        times.append(dt)
+        iters.append(info["iters"])
+        spent += dt
+        i += 1
+    try:
+        from threadpoolctl import threadpool_info
+
+        threads = max([p.get("num_threads", 1) for p in threadpool_info()] or [1])
+    except Exception:
+        threads = 1
+    return dict(value=1e3 * float(np.mean(times)), unit="ms/timestep", cores=int(threads), kind="oracle",
+                sample=f"steps {start}..{i - 1} of the same sequence ({len(times)} steps, "
+                       f"{spent:.1f} s), history warm-started from sparse-LU solutions of steps "
+                       f"{start - method['M']}..{start - 1}; mean oracle iterations {np.mean(iters):.1f}; "
+                       f"host os.cpu_count()={os.cpu_count()}, BLAS threads {threads}, SciPy SpMV single-threaded")
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=100)
+    ap.add_argument("--warmup", type=int, default=40)
+    ap.add_argument("--cpu-seconds", type=float, default=20.0)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-comparators", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py: this build runs on one GPU; --gpus {args.gpus} is not supported "
+              "(independent sequences would shard across GPUs with no communication).", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    import paper_2309_02156_amd as sacc
+    from gen import config
+
+    p, method = config(1)
+    total = args.warmup + args.steps
+    if total > p.steps:
+        raise SystemExit(f"warmup + steps must be <= {p.steps}")
+    log("assembling", total, "steps on the host")
+    vals, rhs = assemble(p, total)
+    rowptr, col = p.pattern()
+    A = sacc.DeviceCSR(rowptr, col, vals[0])
+    vals_d = torch.as_tensor(vals).cuda()
+    rhs_d = torch.as_tensor(rhs).cuda()
+    torch.cuda.synchronize()
+
+    log("timed run: projection")
+    infos, wall = run_sequence(sacc, torch, A, vals_d, rhs_d, method, args.steps, args.warmup)
+    ms_step = 1e3 * wall / args.steps
+    iters = [d["iters"] for d in infos]
+    relres = [d["relres"] for d in infos]
+    log(f"ms/step {ms_step:.3f}, iters/step {np.mean(iters):.2f}")
+
+    comparators = {}
+    if not args.no_comparators:
+        for kind in ("previous",):
+            log("comparator run:", kind)
+            ci, cw = run_sequence(sacc, torch, A, vals_d, rhs_d, method, args.steps, args.warmup, guess=kind)
+            comparators[kind] = dict(ms_per_step=1e3 * cw / args.steps,
+                                     iters_per_step=float(np.mean([d["iters"] for d in ci])))
+
+    gbs, spmv_ms, spmv_bytes = spmv_gbps(sacc, torch, A)
+    log(f"SpMV {gbs:.0f} GB/s ({spmv_ms * 1e3:.1f} us)")
+
+    cpu = None
+    if not args.no_cpu_baseline:
+        log("cpu baseline (oracle)")
+        cpu = cpu_baseline(p, method, args.warmup, args.cpu_seconds)
+
+    out = {
+        "metric": METRIC,
+        "value": round(ms_step, 4),
+        "unit": "ms/timestep",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms_step, 4),
+        "higher_is_better": False,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": "advdiff2d 512x512 (n=262144, nnz=1308672), M=20, SRHT s=80, "
+                               "Galerkin, GMRES(30), relres 1e-8, FP64",
+                   "steps_timed": f"{args.warmup}..{args.warmup + args.steps - 1}"},
+        "krylov_iters_per_step": round(float(np.mean(iters)), 3),
+        "relres_max": float(max(relres)),
+        "spmv_gbps": round(gbs, 1),
+        "comparators": comparators,
+        "roofline": {"bound": "hbm", "achieved": round(gbs, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": round(gbs / HBM_PEAK_GBS, 4), "traffic": None, "kernel": "spmv"},
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,169 @@
+/*
+ * sacc - subspace-accelerated Krylov solves for sequences of sparse linear systems
+ * A(t_i) x(t_i) = b(t_i), i = 0, 1, 2, ... (Guido, Kressner, Ricci, arXiv 2309.02156,
+ * Section 1 eq. (seq)), on AMD Instinct MI355X (gfx950).
+ *
+ * Per step the library computes an initial guess x0 in the span of the M most recent
+ * solutions (Alg. 1 steps 1-3; basis from the randomized range finder of Section 2.2
+ * orthonormalised by a sketched QR) and then runs CG or restarted GMRES from it
+ * (Alg. 1 step 4).  All arithmetic of a step runs in HIP kernels on the device.
+ *
+ * Conventions for every entry point:
+ *   - Pointers named *_dev are device pointers (hipMalloc'd memory or a torch CUDA
+ *     tensor's data_ptr()); everything else is host memory.
+ *   - Vectors are dense, contiguous, length n, float64 unless stated otherwise.
+ *   - A CSR matrix has int32 row pointers (n + 1) and int32 column indices (nnz),
+ *     values float64 or float32 (val_is_fp32).  Columns need not be sorted.
+ *   - `stream` is a hipStream_t passed as void* (NULL = the default stream).  All
+ *     device work of a call is enqueued on that stream; pointers must stay valid until
+ *     that work has completed.  One sequence is used by one stream at a time.
+ *   - Return codes: 0 success; SA_NOTCONV (positive) when maxit was reached (x holds
+ *     the last iterate); negative codes are errors and leave no work half-enqueued
+ *     on argument errors.  No C++ exception crosses this interface.
+ *   - The library allocates device memory only in sa_init_sequence (small control
+ *     blocks); the large buffers live in the caller's workspace.
+ */
+#ifndef SACC_H
+#define SACC_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ---- status codes -------------------------------------------------------------- */
+#define SA_OK 0
+#define SA_NOTCONV 1       /* maxit reached; x holds the last iterate                  */
+#define SA_EINVAL (-1)     /* bad argument: shape, size, dtype, m > M, s < M, ...       */
+#define SA_ENOMEM (-2)     /* workspace smaller than sa_workspace_bytes reports         */
+#define SA_EHIP (-3)       /* a HIP runtime call failed                                 */
+#define SA_ESTATE (-4)     /* call out of order (e.g. push before init)                 */
+#define SA_EBREAKDOWN (-5) /* CG: p^T A p <= 0 or not finite; GMRES: non-finite residual */
+
+/* ---- enumerations (stored as int32 in the structs) ----------------------------- */
+#define SA_FP64 0          /* every vector and reduction in float64                     */
+#define SA_MIXED 1         /* FP32 matrix/history/inner Krylov, FP64 refinement + small */
+
+#define SA_CG 0            /* conjugate gradients (Hestenes-Stiefel), SPD A             */
+#define SA_GMRES 1         /* restarted GMRES(restart), classical Gram-Schmidt twice    */
+
+#define SA_GALERKIN 0      /* reduced problem Q^T A Q y = Q^T b                         */
+#define SA_MINRES 1        /* reduced problem min ||A Q y - b||_2 (Section 2)           */
+
+#define SA_SKETCH_GAUSSIAN 0 /* S[r, j] Gaussian from Philox4x64-10 + Box-Muller      */
+#define SA_SKETCH_SRHT 1     /* S = s^-1/2 R H D, n a power of two                     */
+
+#define SA_GUESS_PROJECTION 0 /* the method: x0 = Q y                                  */
+#define SA_GUESS_ZERO 1       /* x0 = 0                                                 */
+#define SA_GUESS_PREVIOUS 2   /* x0 = x(t_{i-1}), the paper's Baseline (Sections 4-5)   */
+
+/* ---- configuration ------------------------------------------------------------- */
+typedef struct {
+  int64_t n;              /* system size                                              */
+  int32_t M;              /* history length (number of previous solutions kept), 1..64 */
+  int32_t s;              /* sketch rows, M <= s <= 256 (2M Gaussian, 4M SRHT typical) */
+  int32_t sketch;         /* SA_SKETCH_*                                               */
+  int32_t projection;     /* SA_GALERKIN or SA_MINRES                                  */
+  int32_t solver;         /* SA_CG or SA_GMRES                                         */
+  int32_t restart;        /* GMRES restart length, 1..64                               */
+  double tol;             /* stop when ||b - A x||_2 <= tol ||b||_2                   */
+  int32_t maxit;          /* iteration cap (A-products for CG, Arnoldi steps GMRES)    */
+  int32_t precision;      /* SA_FP64 or SA_MIXED                                       */
+  double inner_tol;       /* mixed: inner solve tolerance relative to current residual */
+  int32_t max_refine;     /* mixed: cap on refinement sweeps                           */
+  int32_t guess;          /* SA_GUESS_*                                                */
+  double rank_tol_sketch; /* QRCP truncation |R_jj| > tau |R_11| (<= 0: default)      */
+  double rank_tol_chol;   /* pivoted-Cholesky truncation relative to max diag (<= 0: default) */
+  uint64_t seed;          /* key of the sketch's random entries                        */
+  int32_t poll;           /* Krylov iterations enqueued between host convergence polls (<= 0: default) */
+  int32_t reserved;
+} sa_config;
+
+typedef struct {
+  int64_t n;
+  int64_t nnz;
+  const int32_t *rowptr_dev; /* n + 1 entries, rowptr[0] = 0, non-decreasing          */
+  const int32_t *col_dev;    /* nnz entries in [0, n)                                 */
+  const void *val_dev;       /* nnz values, float64 or float32                        */
+  int32_t val_is_fp32;
+  int32_t reserved;
+} sa_csr;
+
+typedef struct {
+  int32_t iters;         /* Krylov iterations of the last solve (summed over restarts, inner sweeps) */
+  int32_t restarts;      /* GMRES restarts / CG restarts after a failed true-residual check */
+  int32_t refinements;   /* mixed: outer refinement sweeps                             */
+  int32_t k_eff;         /* basis dimension used by the last initial guess             */
+  int32_t k_sketch;      /* rank kept by the sketched QRCP                            */
+  int32_t used_fallback; /* 1 if the guess fell back to x(t_{i-1}) (non-finite basis)  */
+  int32_t status;        /* return code of the last solve                             */
+  int32_t history;       /* number of history columns used (min(pushes, M))            */
+  double relres0;        /* ||b - A x0|| / ||b|| at the start of the last solve        */
+  double relres;         /* final ||b - A x|| / ||b|| (true residual)                  */
+  float ms_guess;        /* device time of the last initial guess                     */
+  float ms_solve;        /* device time of the last solve                             */
+} sa_info;
+
+typedef struct sa_seq sa_seq;
+
+/* Bytes of device workspace one sequence with this configuration needs.
+ * Errors: SA_EINVAL for an invalid configuration. */
+int sa_workspace_bytes(const sa_config *cfg, size_t *bytes);
+
+/* Create a sequence with an empty history (Section 2: X holds the M most recent
+ * solutions).  dev_ws (caller-owned, >= sa_workspace_bytes, 256-byte aligned) must
+ * outlive the sequence.  The sketch's row sample (SRHT) is drawn here on the host.
+ * Errors: SA_EINVAL, SA_ENOMEM (ws_bytes too small), SA_EHIP. */
+int sa_init_sequence(const sa_config *cfg, void *dev_ws, size_t ws_bytes, void *stream,
+                     sa_seq **out);
+
+/* Append the solution x(t_{i-1}) to the history, dropping the oldest one when M are
+ * held (the sliding window of Section 2.1), and sketch it (S x) for the next QR.
+ * x_dev: n values, float64 (SA_FP64) or float64 as well in SA_MIXED (stored as FP32).
+ * Asynchronous.  Errors: SA_EINVAL (null), SA_ESTATE (destroyed sequence). */
+int sa_push_solution(sa_seq *q, const void *x_dev, void *stream);
+
+/* Initial guess of Alg. 1 for the system (A, b): basis Q of span(history) from the
+ * sketched QR (Alg. 1 step 2, Section 2.2), reduced problem (Alg. 1 step 3; Galerkin
+ * or minimum residual per the config) and x0 = Q y.  Empty history gives x0 = 0.
+ * b_dev, x0_dev: float64, length n.  Asynchronous; if info is non-NULL the call waits
+ * for the stream and fills k_eff, k_sketch, history, used_fallback, ms_guess.
+ * Errors: SA_EINVAL (shape mismatch), SA_EHIP. */
+int sa_initial_guess(sa_seq *q, const sa_csr *A, const void *b_dev, void *x0_dev,
+                     sa_info *info, void *stream);
+
+/* Krylov solve of A x = b from the iterate in x_dev (Alg. 1 step 4): CG or GMRES per
+ * the config, stopping on ||b - A x||_2 <= tol ||b||_2 checked before the first
+ * iteration and confirmed with the true residual.  x_dev: float64, in = x0, out = x.
+ * Waits for the stream; fills info if non-NULL (iters, restarts, refinements,
+ * relres0, relres, status, ms_solve).  Returns SA_OK, SA_NOTCONV or an error code. */
+int sa_solve(sa_seq *q, const sa_csr *A, const void *b_dev, void *x_dev, sa_info *info,
+             void *stream);
+
+/* Release the sequence's host state and control blocks (not the workspace). */
+int sa_destroy_sequence(sa_seq *q);
+
+/* Human-readable name of a status code (static string). */
+const char *sa_status_string(int code);
+
+/* y = A x, the building block of every Krylov iteration (Section 1).  x_dev, y_dev:
+ * float64, length n; A values float64 or float32.  Asynchronous.
+ * Errors: SA_EINVAL, SA_EHIP. */
+int sa_spmv(const sa_csr *A, const void *x_dev, void *y_dev, void *stream);
+
+/* Copy internal state to host memory for inspection:
+ *   what = 0: SX, s x M float64 column-major, columns in ring-slot order;
+ *   what = 1: X, n x M float64 column-major (SA_FP64) in ring-slot order;
+ *   what = 2: coefficients c of the last guess in history (ring-slot) coordinates,
+ *             M float64 (x0 = X c);
+ *   what = 3: ring order, M int32: slot of the oldest .. newest column (-1 unused).
+ * Waits for the stream.  Errors: SA_EINVAL (bytes too small or unknown what). */
+int sa_copy_state(sa_seq *q, int what, void *host_dst, size_t bytes, void *stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* SACC_H */

@@ -1,0 +1,8 @@
+"""MI355X-native subspace-accelerated solver for sequences of sparse linear systems.
+
+HIP kernels for gfx950 behind a C-ABI (include/sacc.h, libsacc.so); this package is a
+thin binding: ``Sequence`` (push / initial_guess / solve), ``DeviceCSR`` and ``spmv``.
+"""
+
+from .native import SaccError  # noqa: F401
+from .sequence import DeviceCSR, Sequence, spmv  # noqa: F401

@@ -1,0 +1,420 @@
+// C-ABI of the sequence solver: sequence state, workspace carving and the per-step
+// orchestration of the device kernels (Alg. 1 of arXiv 2309.02156, Section 2).
+#include <hip/hip_runtime.h>
+#include <stddef.h>
+#include <stdint.h>
+#include <string.h>
+
+#include <new>
+#include <vector>
+
+#include "../../include/sacc.h"
+#include "kernels.h"
+
+using namespace sacc;
+
+struct sa_seq {
+  sa_config cfg;
+  char *ws = nullptr;
+  size_t ws_bytes = 0;
+  double *X = nullptr, *SX = nullptr, *Q1 = nullptr, *kry = nullptr, *partials = nullptr;
+  long long *srht_rows = nullptr;
+  Ctl *ctl = nullptr;   // device control block
+  int *hbuf = nullptr;  // pinned host mirror of the solver state
+  long long pushes = 0;
+  double tau_s = 1e-12, tau_c = 1e-12;
+  hipEvent_t ev[4] = {nullptr, nullptr, nullptr, nullptr};
+  bool alive = true;
+};
+
+namespace {
+
+constexpr size_t ALIGN = 256;
+inline size_t up(size_t v) { return (v + ALIGN - 1) / ALIGN * ALIGN; }
+
+// Host Philox4x64-10 (Salmon et al., SC'11): used for the SRHT row sample only.
+void philox4x64_host(uint64_t c[4], uint64_t k0, uint64_t k1) {
+  const uint64_t M0 = 0xD2E7470EE14C6C93ull, M1 = 0xCA5A826395121157ull;
+  const uint64_t W0 = 0x9E3779B97F4A7C15ull, W1 = 0xBB67AE8584CAA73Bull;
+  for (int r = 0; r < 10; ++r) {
+    if (r > 0) {
+      k0 += W0;
+      k1 += W1;
+    }
+    unsigned __int128 p0 = (unsigned __int128)M0 * c[0];
+    unsigned __int128 p1 = (unsigned __int128)M1 * c[2];
+    uint64_t hi0 = (uint64_t)(p0 >> 64), lo0 = (uint64_t)p0;
+    uint64_t hi1 = (uint64_t)(p1 >> 64), lo1 = (uint64_t)p1;
+    uint64_t n0 = hi1 ^ c[1] ^ k0, n2 = hi0 ^ c[3] ^ k1;
+    c[0] = n0;
+    c[1] = lo1;
+    c[2] = n2;
+    c[3] = lo0;
+  }
+}
+
+// s distinct rows of 0..n-1: partial Fisher-Yates, step i swaps i with
+// i + ((word0 >> 32) * (n - i) >> 32), word0 from block (i, 0, STREAM_SRHT_ROWS, 0).
+void srht_rows_host(int64_t n, int s, uint64_t seed, std::vector<long long> &out) {
+  std::vector<long long> perm((size_t)n);
+  for (int64_t i = 0; i < n; ++i) perm[(size_t)i] = i;
+  out.resize(s);
+  for (int i = 0; i < s; ++i) {
+    uint64_t c[4] = {(uint64_t)i, 0, (uint64_t)STREAM_SRHT_ROWS, 0};
+    philox4x64_host(c, seed, 0);
+    uint64_t hi = c[0] >> 32;
+    int64_t j = i + (int64_t)((hi * (uint64_t)(n - i)) >> 32);
+    long long t = perm[(size_t)i];
+    perm[(size_t)i] = perm[(size_t)j];
+    perm[(size_t)j] = t;
+    out[i] = perm[(size_t)i];
+  }
+}
+
+struct Layout {
+  size_t X, SX, Q1, kry, partials, rows, total;
+};
+
+int validate(const sa_config *c) {
+  if (!c) return SA_EINVAL;
+  if (c->n < 1 || c->n > ((int64_t)1 << 31) - 1) return SA_EINVAL;
+  if (c->M < 1 || c->M > 32) return SA_EINVAL;
+  if (c->s < c->M || c->s > MAXS || (int64_t)c->s * c->M > 8192) return SA_EINVAL;
+  if (c->sketch != SA_SKETCH_GAUSSIAN && c->sketch != SA_SKETCH_SRHT) return SA_EINVAL;
+  if (c->sketch == SA_SKETCH_SRHT && (c->n & (c->n - 1)) != 0) return SA_EINVAL;
+  if (c->sketch == SA_SKETCH_SRHT && c->s > c->n) return SA_EINVAL;
+  if (c->projection != SA_GALERKIN) return SA_EINVAL;
+  if (c->solver != SA_CG && c->solver != SA_GMRES) return SA_EINVAL;
+  if (c->solver == SA_GMRES && (c->restart < 1 || c->restart > MAXR)) return SA_EINVAL;
+  if (!(c->tol > 0.0) || c->maxit < 0) return SA_EINVAL;
+  if (c->precision != SA_FP64) return SA_EINVAL;
+  if (c->guess < SA_GUESS_PROJECTION || c->guess > SA_GUESS_PREVIOUS) return SA_EINVAL;
+  return SA_OK;
+}
+
+Layout layout(const sa_config *c) {
+  Layout L;
+  const size_t n = (size_t)c->n, M = (size_t)c->M;
+  size_t off = 0;
+  L.X = off;
+  off += up(n * M * sizeof(double));
+  L.SX = off;
+  off += up((size_t)c->s * M * sizeof(double));
+  L.Q1 = off;
+  off += up(n * M * sizeof(double));
+  L.kry = off;
+  size_t kv = c->solver == SA_GMRES ? (size_t)(c->restart + 1) : 3;
+  off += up(n * kv * sizeof(double));
+  L.partials = off;
+  off += up(partials_doubles(c->n, c->M, c->s) * sizeof(double));
+  L.rows = off;
+  off += up((size_t)c->s * sizeof(long long));
+  L.total = off;
+  return L;
+}
+
+inline int hipok(hipError_t e) { return e == hipSuccess ? SA_OK : SA_EHIP; }
+#define HIP_TRY(expr)                      \
+  do {                                     \
+    hipError_t e_ = (expr);                \
+    if (e_ != hipSuccess) return SA_EHIP;  \
+  } while (0)
+
+int check_csr(const sa_seq *q, const sa_csr *A) {
+  if (!A || !A->rowptr_dev || !A->col_dev || !A->val_dev) return SA_EINVAL;
+  if (A->n != q->cfg.n || A->nnz < 0) return SA_EINVAL;
+  return SA_OK;
+}
+
+CsrView view(const sa_csr *A) {
+  CsrView v;
+  v.n = A->n;
+  v.nnz = A->nnz;
+  v.rowptr = A->rowptr_dev;
+  v.col = A->col_dev;
+  v.val = A->val_dev;
+  v.fp32 = A->val_is_fp32 ? 1 : 0;
+  return v;
+}
+
+inline int count(const sa_seq *q) { return (int)(q->pushes < q->cfg.M ? q->pushes : q->cfg.M); }
+
+// solver state mirror: state, iters, restarts, maxit, active, jend, restart, pad
+int poll(sa_seq *q, hipStream_t st) {
+  HIP_TRY(hipMemcpyAsync(q->hbuf, &q->ctl->state, 8 * sizeof(int), hipMemcpyDeviceToHost, st));
+  HIP_TRY(hipStreamSynchronize(st));
+  return SA_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int sa_workspace_bytes(const sa_config *cfg, size_t *bytes) {
+  int rc = validate(cfg);
+  if (rc != SA_OK) return rc;
+  if (!bytes) return SA_EINVAL;
+  *bytes = layout(cfg).total;
+  return SA_OK;
+}
+
+int sa_init_sequence(const sa_config *cfg, void *dev_ws, size_t ws_bytes, void *stream, sa_seq **out) {
+  int rc = validate(cfg);
+  if (rc != SA_OK) return rc;
+  if (!out || !dev_ws || ((uintptr_t)dev_ws % ALIGN) != 0) return SA_EINVAL;
+  Layout L = layout(cfg);
+  if (ws_bytes < L.total) return SA_ENOMEM;
+  hipStream_t st = (hipStream_t)stream;
+  sa_seq *q = new (std::nothrow) sa_seq();
+  if (!q) return SA_ENOMEM;
+  q->cfg = *cfg;
+  if (q->cfg.poll <= 0) q->cfg.poll = 8;
+  q->tau_s = cfg->rank_tol_sketch > 0.0 ? cfg->rank_tol_sketch : 1e-12;
+  q->tau_c = cfg->rank_tol_chol > 0.0 ? cfg->rank_tol_chol : 1e-12;
+  q->ws = (char *)dev_ws;
+  q->ws_bytes = ws_bytes;
+  q->X = (double *)(q->ws + L.X);
+  q->SX = (double *)(q->ws + L.SX);
+  q->Q1 = (double *)(q->ws + L.Q1);
+  q->kry = (double *)(q->ws + L.kry);
+  q->partials = (double *)(q->ws + L.partials);
+  q->srht_rows = (long long *)(q->ws + L.rows);
+  bool ok = hipMalloc((void **)&q->ctl, sizeof(Ctl)) == hipSuccess &&
+            hipHostMalloc((void **)&q->hbuf, 64 * sizeof(int), hipHostMallocDefault) == hipSuccess;
+  for (int e = 0; ok && e < 4; ++e) ok = hipEventCreate(&q->ev[e]) == hipSuccess;
+  if (!ok) {
+    sa_destroy_sequence(q);
+    return SA_EHIP;
+  }
+  Ctl *h = new (std::nothrow) Ctl();
+  if (!h) {
+    sa_destroy_sequence(q);
+    return SA_ENOMEM;
+  }
+  memset((void *)h, 0, sizeof(Ctl));
+  h->tol = cfg->tol;
+  h->maxit = cfg->maxit;
+  h->restart = cfg->restart;
+  h->newest = -1;
+  h->state = ST_CONV;
+  std::vector<long long> rows;
+  if (cfg->sketch == SA_SKETCH_SRHT) srht_rows_host(cfg->n, cfg->s, cfg->seed, rows);
+  hipError_t e = hipMemcpyAsync(q->ctl, h, sizeof(Ctl), hipMemcpyHostToDevice, st);
+  if (e == hipSuccess && !rows.empty())
+    e = hipMemcpyAsync(q->srht_rows, rows.data(), rows.size() * sizeof(long long), hipMemcpyHostToDevice, st);
+  if (e == hipSuccess) e = hipMemsetAsync(q->X, 0, (size_t)cfg->n * cfg->M * sizeof(double), st);
+  if (e == hipSuccess) e = hipMemsetAsync(q->SX, 0, (size_t)cfg->s * cfg->M * sizeof(double), st);
+  if (e == hipSuccess) e = hipStreamSynchronize(st);
+  delete h;
+  if (e != hipSuccess) {
+    sa_destroy_sequence(q);
+    return SA_EHIP;
+  }
+  *out = q;
+  return SA_OK;
+}
+
+int sa_push_solution(sa_seq *q, const void *x_dev, void *stream) {
+  if (!q || !q->alive) return SA_ESTATE;
+  if (!x_dev) return SA_EINVAL;
+  hipStream_t st = (hipStream_t)stream;
+  const sa_config &c = q->cfg;
+  const int slot = (int)(q->pushes % c.M);
+  HIP_TRY(launch_push((const double *)x_dev, q->X, q->SX, c.n, slot, c.s, c.sketch, c.seed, q->srht_rows,
+                      q->partials, q->ctl, st));
+  q->pushes += 1;
+  HIP_TRY(launch_qrcp(q->SX, c.s, count(q), slot, q->tau_s, q->partials, c.n, q->ctl, st));
+  return SA_OK;
+}
+
+int sa_initial_guess(sa_seq *q, const sa_csr *A, const void *b_dev, void *x0_dev, sa_info *info, void *stream) {
+  if (!q || !q->alive) return SA_ESTATE;
+  int rc = check_csr(q, A);
+  if (rc != SA_OK) return rc;
+  if (!b_dev || !x0_dev) return SA_EINVAL;
+  hipStream_t st = (hipStream_t)stream;
+  const sa_config &c = q->cfg;
+  const int cnt = count(q);
+  const size_t nb = (size_t)c.n * sizeof(double);
+  if (info) HIP_TRY(hipEventRecord(q->ev[0], st));
+  const int newest = cnt > 0 ? (int)((q->pushes - 1) % c.M) : -1;
+  if (cnt == 0 || c.guess == SA_GUESS_ZERO) {
+    HIP_TRY(hipMemsetAsync(x0_dev, 0, nb, st));
+  } else if (c.guess == SA_GUESS_PREVIOUS) {
+    HIP_TRY(hipMemcpyAsync(x0_dev, q->X + (size_t)newest * c.n, nb, hipMemcpyDeviceToDevice, st));
+  } else {
+    CsrView v = view(A);
+    int nblk = 0;
+    HIP_TRY(launch_basis(q->X, q->Q1, c.n, cnt, q->ctl, st));
+    HIP_TRY(launch_spmm_gram(v, q->Q1, (const double *)b_dev, cnt, 0, q->partials, &nblk, q->ctl, st));
+    HIP_TRY(launch_colsum(q->partials, nblk, cnt * (2 * cnt + 1), q->ctl, st));
+    HIP_TRY(launch_small_solve(cnt, 0, c.solver == SA_CG ? 1 : 0, q->tau_c, q->ctl, st));
+    HIP_TRY(launch_x0(q->Q1, q->X, (double *)x0_dev, c.n, q->ctl, st));
+  }
+  if (info) {
+    HIP_TRY(hipEventRecord(q->ev[1], st));
+    HIP_TRY(hipMemcpyAsync(q->hbuf + 16, &q->ctl->k, 4 * sizeof(int), hipMemcpyDeviceToHost, st));
+    HIP_TRY(hipStreamSynchronize(st));
+    float ms = 0.f;
+    HIP_TRY(hipEventElapsedTime(&ms, q->ev[0], q->ev[1]));
+    const bool proj = cnt > 0 && c.guess == SA_GUESS_PROJECTION;
+    info->k_sketch = proj ? q->hbuf[16] : 0;
+    info->k_eff = proj ? q->hbuf[17] : 0;
+    info->used_fallback = proj ? q->hbuf[18] : 0;
+    info->history = cnt;
+    info->ms_guess = ms;
+  }
+  return SA_OK;
+}
+
+int sa_solve(sa_seq *q, const sa_csr *A, const void *b_dev, void *x_dev, sa_info *info, void *stream) {
+  if (!q || !q->alive) return SA_ESTATE;
+  int rc = check_csr(q, A);
+  if (rc != SA_OK) return rc;
+  if (!b_dev || !x_dev) return SA_EINVAL;
+  hipStream_t st = (hipStream_t)stream;
+  const sa_config &c = q->cfg;
+  const int64_t n = c.n;
+  CsrView v = view(A);
+  const double *b = (const double *)b_dev;
+  double *x = (double *)x_dev;
+  if (info) HIP_TRY(hipEventRecord(q->ev[2], st));
+  int *hs = q->hbuf;
+  if (c.solver == SA_CG) {
+    double *r = q->kry, *p = q->kry + n, *qq = q->kry + 2 * n;
+    int k = 0;             // iterations enqueued (device numbering, 1-based per iteration)
+    bool p_fresh = true;   // p = r: the next iteration needs no direction update
+    HIP_TRY(launch_cg_start_k(v, b, x, r, p, 0, k, q->partials, q->ctl, st));
+    if ((rc = poll(q, st)) != SA_OK) return rc;
+    // every pass either advances the device iteration count or leaves a final state;
+    // the bound only protects against a corrupted control block
+    const long long max_pass = (long long)c.maxit + 16;
+    for (long long pass = 0;; ++pass) {
+      if (pass > max_pass || hs[0] < ST_RUN || hs[0] > ST_ZERO_RHS) return SA_EHIP;
+      if (hs[0] == ST_RUN) {
+        for (int t = 0; t < c.poll && k < c.maxit; ++t) {
+          ++k;
+          HIP_TRY(launch_cg_iter_k(v, x, r, p, qq, k, p_fresh ? 0 : 1, t > 0 ? 1 : 0, q->partials, q->ctl, st));
+          p_fresh = false;
+        }
+        HIP_TRY(launch_cg_close_k(q->partials, n, k, q->ctl, st));
+        if ((rc = poll(q, st)) != SA_OK) return rc;
+        k = hs[1];  // iterations actually performed (later launches of the batch were no-ops)
+      }
+      if (hs[0] == ST_CHECK) {
+        HIP_TRY(launch_cg_start_k(v, b, x, r, p, 1, k, q->partials, q->ctl, st));
+        if ((rc = poll(q, st)) != SA_OK) return rc;
+        p_fresh = true;
+      }
+      if (hs[0] == ST_CONV || hs[0] == ST_ZERO_RHS) break;
+      if (hs[0] == ST_MAXIT || hs[0] == ST_BREAK) {
+        HIP_TRY(launch_cg_start_k(v, b, x, r, p, 2, k, q->partials, q->ctl, st));
+        if ((rc = poll(q, st)) != SA_OK) return rc;
+        break;
+      }
+    }
+  } else {
+    double *V = q->kry;
+    HIP_TRY(launch_gm_start(v, b, x, V, 0, q->partials, q->ctl, st));
+    if ((rc = poll(q, st)) != SA_OK) return rc;
+    long long cycles = 0;
+    int total = 0;  // Arnoldi steps performed so far
+    while (hs[0] == ST_RUN) {
+      if (++cycles > (long long)c.maxit + 16) return SA_EHIP;  // each cycle adds >= 1 iteration
+      int j = 0;
+      while (j < c.restart) {
+        for (int t = 0; t < c.poll && j < c.restart; ++t, ++j) {
+          ++total;
+          HIP_TRY(launch_gm_step_it(v, V, j, total, t > 0 ? 1 : 0, q->partials, q->ctl, st));
+        }
+        HIP_TRY(launch_gm_close_it(q->partials, n, j - 1, total, q->ctl, st));
+        if ((rc = poll(q, st)) != SA_OK) return rc;
+        if (!hs[4] || hs[0] != ST_RUN) break;
+      }
+      total = hs[1];
+      HIP_TRY(launch_gm_update(x, V, n, c.restart, q->ctl, st));
+      HIP_TRY(launch_gm_start(v, b, x, V, 1, q->partials, q->ctl, st));
+      if ((rc = poll(q, st)) != SA_OK) return rc;
+    }
+  }
+  const int state = hs[0];
+  if (state < ST_RUN || state > ST_ZERO_RHS) return SA_EHIP;
+  if (state == ST_ZERO_RHS) HIP_TRY(hipMemsetAsync(x, 0, (size_t)n * sizeof(double), st));
+  int ret = SA_OK;
+  if (state == ST_MAXIT) ret = SA_NOTCONV;
+  if (state == ST_BREAK) ret = SA_EBREAKDOWN;
+  if (info) {
+    HIP_TRY(hipEventRecord(q->ev[3], st));
+    double d[4];  // bnorm, relres0, relres, tol
+    HIP_TRY(hipMemcpyAsync(d, &q->ctl->bnorm, sizeof(d), hipMemcpyDeviceToHost, st));
+    HIP_TRY(hipStreamSynchronize(st));
+    float ms = 0.f;
+    HIP_TRY(hipEventElapsedTime(&ms, q->ev[2], q->ev[3]));
+    info->iters = hs[1];
+    info->restarts = hs[2];
+    info->refinements = 0;
+    info->relres0 = d[1];
+    info->relres = state == ST_ZERO_RHS ? 0.0 : d[2];
+    info->status = ret;
+    info->ms_solve = ms;
+  }
+  return ret;
+}
+
+int sa_destroy_sequence(sa_seq *q) {
+  if (!q) return SA_EINVAL;
+  q->alive = false;
+  if (q->ctl) (void)hipFree(q->ctl);
+  if (q->hbuf) (void)hipHostFree(q->hbuf);
+  for (int e = 0; e < 4; ++e)
+    if (q->ev[e]) (void)hipEventDestroy(q->ev[e]);
+  delete q;
+  return SA_OK;
+}
+
+const char *sa_status_string(int code) {
+  switch (code) {
+    case SA_OK: return "ok";
+    case SA_NOTCONV: return "not converged within maxit";
+    case SA_EINVAL: return "invalid argument";
+    case SA_ENOMEM: return "workspace too small";
+    case SA_EHIP: return "HIP runtime error";
+    case SA_ESTATE: return "call out of order";
+    case SA_EBREAKDOWN: return "breakdown";
+    default: return "unknown status";
+  }
+}
+
+int sa_spmv(const sa_csr *A, const void *x_dev, void *y_dev, void *stream) {
+  if (!A || !A->rowptr_dev || !A->col_dev || !A->val_dev || !x_dev || !y_dev || A->n < 0) return SA_EINVAL;
+  if (A->n == 0) return SA_OK;
+  return hipok(launch_spmv(view(A), (const double *)x_dev, (double *)y_dev, (hipStream_t)stream));
+}
+
+int sa_copy_state(sa_seq *q, int what, void *host_dst, size_t bytes, void *stream) {
+  if (!q || !q->alive) return SA_ESTATE;
+  if (!host_dst) return SA_EINVAL;
+  hipStream_t st = (hipStream_t)stream;
+  const sa_config &c = q->cfg;
+  if (what == 0 || what == 1 || what == 2) {
+    size_t need = what == 0 ? (size_t)c.s * c.M * sizeof(double)
+                 : what == 1 ? (size_t)c.n * c.M * sizeof(double)
+                             : (size_t)c.M * sizeof(double);
+    if (bytes < need) return SA_EINVAL;
+    const void *src = what == 0 ? (const void *)q->SX : what == 1 ? (const void *)q->X : (const void *)q->ctl->cX;
+    HIP_TRY(hipMemcpyAsync(host_dst, src, need, hipMemcpyDeviceToHost, st));
+    HIP_TRY(hipStreamSynchronize(st));
+    return SA_OK;
+  }
+  if (what == 3) {
+    if (bytes < (size_t)c.M * sizeof(int32_t)) return SA_EINVAL;
+    int32_t *o = (int32_t *)host_dst;
+    const int cnt = count(q);
+    for (int i = 0; i < c.M; ++i) o[i] = -1;
+    for (int i = 0; i < cnt; ++i) o[i] = (int32_t)((q->pushes - cnt + i) % c.M);
+    return SA_OK;
+  }
+  return SA_EINVAL;
+}
+
+}  // extern "C"

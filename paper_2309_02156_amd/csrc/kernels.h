@@ -1,0 +1,75 @@
+// Host-callable launchers of the device kernels (one sequence, FP64 vectors).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "common.h"
+
+namespace sacc {
+
+struct CsrView {
+  int64_t n, nnz;
+  const int *rowptr, *col;
+  const void *val;
+  int fp32;
+};
+
+// y = A x
+hipError_t launch_spmv(const CsrView &A, const double *x, double *y, hipStream_t st);
+
+// history push: X[:, slot] = x and SX[:, slot] = S x  (Gaussian or SRHT sketch)
+hipError_t launch_push(const double *x, double *X, double *SX, int64_t n, int slot, int s, int sketch,
+                       uint64_t seed, const long long *srht_rows, double *partials, Ctl *ctl,
+                       hipStream_t st);
+
+// finish the push (reduce the sketch partials into SX[:, newest]), then QR with column
+// pivoting of SX[:, 0:cnt] -> k, T1 (in ctl)
+hipError_t launch_qrcp(double *SX, int s, int cnt, int newest, double tau, const double *partials, int64_t n,
+                       Ctl *ctl, hipStream_t st);
+
+// Q1 = X T1 (first ctl->k columns)
+hipError_t launch_basis(const double *X, double *Q1, int64_t n, int cnt, Ctl *ctl, hipStream_t st);
+
+// partials of Q1^T [Q1 | A Q1 | b] (and [A Q1]^T [A Q1 | b] for minimum residual)
+hipError_t launch_spmm_gram(const CsrView &A, const double *Q1, const double *b, int cnt, int minres,
+                            double *partials, int *nblk_out, Ctl *ctl, hipStream_t st);
+
+// column sums of partials[nblk][W] -> ctl->gram
+hipError_t launch_colsum(const double *partials, int nblk, int W, Ctl *ctl, hipStream_t st);
+
+// pivoted Cholesky of G, reduced solve -> c, cX, k2, fallback
+hipError_t launch_small_solve(int cnt, int minres, int spd, double tau_c, Ctl *ctl, hipStream_t st);
+
+// x0 = Q1 c (or the fallback)
+hipError_t launch_x0(const double *Q1, const double *X, double *x0, int64_t n, Ctl *ctl, hipStream_t st);
+
+// Krylov kernels.  Cross-block results travel through per-block partial sums that
+// the next kernel reduces (kernel boundaries order them); two partial buffers
+// alternate.  A 1-block "close" kernel ends each batch so the host can poll.
+//
+// CG: start(mode) -> start_close; per iteration [dir] qp xr; batch end: close.
+//   mode 0 start, 1 true-residual confirmation, 2 final residual only.
+// k = iterations completed before the call (start / confirm / final) or the number
+// of the iteration being launched (iter, 1-based), or the last one (close).
+hipError_t launch_cg_start_k(const CsrView &A, const double *b, const double *x, double *r, double *p, int mode,
+                             int k, double *partials, Ctl *ctl, hipStream_t st);
+// one iteration; with_dir = 0 right after start/confirm (p = r); fresh = 1 when the
+// previous iteration has not been closed (dir reduces its partials itself)
+hipError_t launch_cg_iter_k(const CsrView &A, double *x, double *r, double *p, double *q, int k, int with_dir,
+                            int fresh, double *partials, Ctl *ctl, hipStream_t st);
+hipError_t launch_cg_close_k(double *partials, int64_t n, int k, Ctl *ctl, hipStream_t st);
+
+// GMRES(m), classical Gram-Schmidt applied twice.  it = global iteration number.
+hipError_t launch_gm_start(const CsrView &A, const double *b, const double *x, double *V, int restart_mode,
+                           double *partials, Ctl *ctl, hipStream_t st);
+hipError_t launch_gm_step_it(const CsrView &A, double *V, int j, int it, int fresh, double *partials, Ctl *ctl,
+                             hipStream_t st);
+hipError_t launch_gm_close_it(double *partials, int64_t n, int j, int it, Ctl *ctl, hipStream_t st);
+hipError_t launch_gm_update(double *x, const double *V, int64_t n, int restart, Ctl *ctl, hipStream_t st);
+size_t krylov_partials_doubles();
+
+// partial-buffer size (doubles) the launchers above need for a problem of size n
+size_t partials_doubles(int64_t n, int M, int s);
+
+}  // namespace sacc

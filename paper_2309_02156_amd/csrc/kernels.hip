@@ -1,0 +1,753 @@
+// Device kernels of one time step for FP64 vectors (A may hold FP32 values).
+//
+// Step layout (Alg. 1 of arXiv 2309.02156, Section 2):
+//   push      X[:, slot] = x(t_{i-1});  SX[:, slot] = S x(t_{i-1})     (history window)
+//   qrcp      QR with column pivoting of SX -> rank k, T1 = P R11^-1    (sketched QR)
+//   basis     Q1 = X T1                                                 (n x k)
+//   spmm_gram per row tile: W = A Q1 in registers, MFMA-accumulated Q1^T [Q1 | W | b]
+//   small     pivoted Cholesky of G = Q1^T Q1 (Cholesky-QR finish), reduced Galerkin
+//             system R2^-T (Q1^T A Q1) R2^-1 y = R2^-T Q1^T b, c = R2^-1 y
+//   x0        x0 = Q1 c
+//   Krylov    CG (3 kernels / iteration) or GMRES with classical Gram-Schmidt applied
+//             twice (3 kernels / Arnoldi step), device-side scalars and stopping tests.
+//
+// Reductions are deterministic: per-block partial sums in fixed order, reduced by the
+// last block to arrive (or a column-sum kernel), never by floating-point atomics.
+#include <math.h>
+
+#include "common.h"
+#include "kernels.h"
+
+namespace sacc {
+
+typedef double d4 __attribute__((ext_vector_type(4)));
+
+template <typename VT>
+__device__ inline double row_dot(const int *__restrict__ rowptr, const int *__restrict__ col,
+                                 const VT *__restrict__ val, const double *__restrict__ x, int64_t i) {
+  const int p0 = rowptr[i], p1 = rowptr[i + 1];
+  double s = 0.0;
+  for (int p = p0; p < p1; ++p) s += (double)val[p] * x[col[p]];
+  return s;
+}
+
+__device__ inline void wave_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+#define GRID_ROWS(i, n) \
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < (n); i += (int64_t)gridDim.x * blockDim.x)
+
+// ============================================================================ SpMV
+template <typename VT>
+__global__ __launch_bounds__(TPB) void k_spmv(const int *rowptr, const int *col, const VT *val,
+                                              const double *x, double *y, int64_t n) {
+  GRID_ROWS(i, n) y[i] = row_dot(rowptr, col, val, x, i);
+}
+
+hipError_t launch_spmv(const CsrView &A, const double *x, double *y, hipStream_t st) {
+  int nb = stream_blocks(A.n);
+  if (A.fp32)
+    hipLaunchKernelGGL(k_spmv<float>, dim3(nb), dim3(TPB), 0, st, A.rowptr, A.col, (const float *)A.val, x,
+                       y, A.n);
+  else
+    hipLaunchKernelGGL(k_spmv<double>, dim3(nb), dim3(TPB), 0, st, A.rowptr, A.col, (const double *)A.val, x,
+                       y, A.n);
+  return hipGetLastError();
+}
+
+// ============================================================================ push + sketch
+// Grid (nbx, ceil(s / SKETCH_RG)): block row-group g accumulates rows [16 g, 16 g + 16)
+// of S x; group 0 also copies x into the history slot.  The last block reduces.
+template <int SK>
+__global__ __launch_bounds__(TPB) void k_push(const double *x, double *X, double *SX, int64_t n, int slot,
+                                              int s, uint64_t seed, const long long *rows,
+                                              double *partials, Ctl *ctl) {
+  __shared__ double red[NWAVE * SKETCH_RG];
+  __shared__ double outv[MAXS];
+  __shared__ double scratch[TPB];
+  const int g = blockIdx.y, r0 = g * SKETCH_RG;
+  const int rc = (s - r0) < SKETCH_RG ? (s - r0) : SKETCH_RG;
+  double acc[SKETCH_RG];
+#pragma unroll
+  for (int r = 0; r < SKETCH_RG; ++r) acc[r] = 0.0;
+  long long myrows[SKETCH_RG];
+  if (SK == 1) {
+#pragma unroll
+    for (int r = 0; r < SKETCH_RG; ++r) myrows[r] = (r < rc) ? rows[r0 + r] : 0;
+  }
+  GRID_ROWS(j, n) {
+    const double xj = x[j];
+    if (g == 0) X[(size_t)slot * n + j] = xj;
+    if (SK == 0) {
+#pragma unroll
+      for (int q = 0; q < SKETCH_RG / 4; ++q) {
+        if (4 * q < rc) {
+          double gq[4];
+          normals4((uint64_t)j, (uint64_t)((r0 >> 2) + q), STREAM_GAUSS_SKETCH, seed, gq);
+#pragma unroll
+          for (int l = 0; l < 4; ++l) acc[4 * q + l] += gq[l] * xj;
+        }
+      }
+    } else {
+      const double d = srht_sign((uint64_t)j, seed) * xj;
+#pragma unroll
+      for (int r = 0; r < SKETCH_RG; ++r)
+        acc[r] += (__popcll((unsigned long long)myrows[r] & (unsigned long long)j) & 1) ? -d : d;
+    }
+  }
+  const int blk = blockIdx.y * gridDim.x + blockIdx.x;
+  (void)outv;
+  (void)scratch;
+  (void)SX;
+  (void)ctl;
+  // per-block partial sums; the QRCP kernel that follows reduces them into SX[:, slot]
+  block_sum_store<SKETCH_RG>(acc, rc, red, partials + (size_t)blk * SKETCH_RG);
+}
+
+int push_blocks_x(int64_t n, int s) {
+  const int ng = (s + SKETCH_RG - 1) / SKETCH_RG;
+  int nbx = stream_blocks(n);
+  if (nbx * ng > MAXBLK) nbx = MAXBLK / ng > 0 ? MAXBLK / ng : 1;
+  return nbx;
+}
+
+hipError_t launch_push(const double *x, double *X, double *SX, int64_t n, int slot, int s, int sketch,
+                       uint64_t seed, const long long *srht_rows, double *partials, Ctl *ctl,
+                       hipStream_t st) {
+  const int ng = (s + SKETCH_RG - 1) / SKETCH_RG;
+  const int nbx = push_blocks_x(n, s);
+  if (sketch == 0)
+    hipLaunchKernelGGL(k_push<0>, dim3(nbx, ng), dim3(TPB), 0, st, x, X, SX, n, slot, s, seed, srht_rows,
+                       partials, ctl);
+  else
+    hipLaunchKernelGGL(k_push<1>, dim3(nbx, ng), dim3(TPB), 0, st, x, X, SX, n, slot, s, seed, srht_rows,
+                       partials, ctl);
+  return hipGetLastError();
+}
+
+// ============================================================================ sketched QRCP
+// One workgroup.  Householder QR with column pivoting (largest remaining column norm,
+// recomputed exactly at every step; ties pick the lowest index) of Y = SX[:, 0:cnt],
+// diag(R) >= 0, rank k = leading count of |R_jj| > tau |R_11|, T1 = P R11^-1.
+__global__ __launch_bounds__(TPB) void k_qrcp(double *SX, int s, int cnt, int newest, double tau,
+                                              const double *partials, int nbx, Ctl *ctl) {
+  extern __shared__ double sh[];
+  double *Y = sh;                  // s x cnt, ld s
+  double *Ri = sh + (size_t)s * cnt;  // cnt x cnt inverse, ld cnt
+  __shared__ double nrm[MAXM];
+  __shared__ double v[MAXS];
+  __shared__ double scratch[TPB];
+  __shared__ int perm[MAXM];
+  __shared__ int s_piv, s_bad, s_newest_bad, s_k;
+  __shared__ double s_tauh;
+  const int tid = threadIdx.x, lane = tid % WAVE, wid = tid / WAVE;
+  if (tid == 0) {
+    s_bad = 0;
+    s_newest_bad = 0;
+  }
+  // finish the push: SX[:, newest] = (sum over push blocks of the sketch partials) / sqrt(s)
+  const int ng = (s + SKETCH_RG - 1) / SKETCH_RG;
+  for (int g = 0; g < ng; ++g) {
+    const int r0 = g * SKETCH_RG;
+    const int rc = (s - r0) < SKETCH_RG ? (s - r0) : SKETCH_RG;
+    final_sum(partials + (size_t)g * nbx * SKETCH_RG, nbx, SKETCH_RG, rc, v + r0, scratch);
+  }
+  const double inv = 1.0 / sqrt((double)s);
+  for (int r = tid; r < s; r += blockDim.x) SX[(size_t)newest * s + r] = v[r] * inv;
+  __syncthreads();
+  for (int e = tid; e < s * cnt; e += blockDim.x) {
+    double y = (e / s == newest) ? v[e % s] * inv : SX[e];
+    Y[e] = y;
+    if (!isfinite(y)) {
+      s_bad = 1;
+      if (e / s == newest) s_newest_bad = 1;
+    }
+  }
+  for (int c = tid; c < cnt; c += blockDim.x) perm[c] = c;
+  __syncthreads();
+  if (tid == 0) {
+    ctl->newest = newest;
+    ctl->newest_ok = s_newest_bad ? 0 : 1;
+  }
+  if (s_bad) {
+    if (tid == 0) {
+      ctl->k = 0;
+      ctl->nonfinite = 1;
+    }
+    return;
+  }
+  int jj = 0;
+  for (; jj < cnt; ++jj) {
+    // exact column norms over rows jj..s-1 of the remaining columns
+    for (int c = jj + wid; c < cnt; c += NWAVE) {
+      double a = 0.0;
+      for (int r = jj + lane; r < s; r += WAVE) {
+        double y = Y[(size_t)c * s + r];
+        a += y * y;
+      }
+      a = wave_sum(a);
+      if (lane == 0) nrm[c] = a;
+    }
+    __syncthreads();
+    if (tid == 0) {
+      int p = jj;
+      for (int c = jj + 1; c < cnt; ++c)
+        if (nrm[c] > nrm[p]) p = c;
+      s_piv = p;
+      int t = perm[jj];
+      perm[jj] = perm[p];
+      perm[p] = t;
+    }
+    __syncthreads();
+    const int p = s_piv;
+    if (p != jj)
+      for (int r = tid; r < s; r += blockDim.x) {
+        double t = Y[(size_t)jj * s + r];
+        Y[(size_t)jj * s + r] = Y[(size_t)p * s + r];
+        Y[(size_t)p * s + r] = t;
+      }
+    __syncthreads();
+    const double alpha = sqrt(nrm[p]);
+    const double x0 = Y[(size_t)jj * s + jj];
+    if (alpha == 0.0) {
+      // the rest is zero: R_jj = 0 onward
+      for (int c = jj + tid; c < cnt; c += blockDim.x) Y[(size_t)c * s + c] = 0.0;
+      __syncthreads();
+      break;
+    }
+    const double beta = x0 >= 0.0 ? -alpha : alpha;  // R_jj (sign fixed below)
+    const double v0 = x0 - beta;
+    for (int r = jj + tid; r < s; r += blockDim.x) v[r] = (r == jj) ? v0 : Y[(size_t)jj * s + r];
+    if (tid == 0) s_tauh = 2.0 / (v0 * v0 + (alpha * alpha - x0 * x0));
+    __syncthreads();
+    const double tauh = s_tauh;
+    for (int c = jj + 1 + wid; c < cnt; c += NWAVE) {
+      double d = 0.0;
+      for (int r = jj + lane; r < s; r += WAVE) d += v[r] * Y[(size_t)c * s + r];
+      d = wave_sum(d) * tauh;
+      for (int r = jj + lane; r < s; r += WAVE) Y[(size_t)c * s + r] -= d * v[r];
+    }
+    if (tid == 0) Y[(size_t)jj * s + jj] = beta;
+    __syncthreads();
+  }
+  // sign convention diag(R) >= 0: negate rows with a negative diagonal
+  for (int r = wid; r < cnt; r += NWAVE) {
+    const bool neg = Y[(size_t)r * s + r] < 0.0;
+    if (neg)
+      for (int c = r + lane; c < cnt; c += WAVE) Y[(size_t)c * s + r] = -Y[(size_t)c * s + r];
+  }
+  __syncthreads();
+  if (tid == 0) {
+    const double r00 = fabs(Y[0]);
+    int k = 0;
+    if (r00 > 0.0)
+      while (k < cnt && fabs(Y[(size_t)k * s + k]) > tau * r00) ++k;
+    s_k = k;
+  }
+  __syncthreads();
+  const int k = s_k;
+  // R11^-1, one column per thread (upper triangular back substitution)
+  for (int c = tid; c < k; c += blockDim.x) {
+    for (int i = 0; i < k; ++i) Ri[i + c * k] = 0.0;
+    Ri[c + c * k] = 1.0 / Y[(size_t)c * s + c];
+    for (int i = c - 1; i >= 0; --i) {
+      double acc = 0.0;
+      for (int l = i + 1; l <= c; ++l) acc += Y[(size_t)l * s + i] * Ri[l + c * k];
+      Ri[i + c * k] = -acc / Y[(size_t)i * s + i];
+    }
+  }
+  __syncthreads();
+  for (int e = tid; e < MAXM * MAXM; e += blockDim.x) ctl->T1[e] = 0.0;
+  __syncthreads();
+  for (int e = tid; e < k * k; e += blockDim.x) {
+    const int i = e % k, c = e / k;
+    if (i <= c) ctl->T1[perm[i] + c * MAXM] = Ri[i + c * k];
+  }
+  if (tid == 0) {
+    ctl->k = k;
+    ctl->nonfinite = 0;
+  }
+}
+
+hipError_t launch_qrcp(double *SX, int s, int cnt, int newest, double tau, const double *partials, int64_t n,
+                       Ctl *ctl, hipStream_t st) {
+  size_t lds = ((size_t)s * cnt + (size_t)cnt * cnt) * sizeof(double);
+  hipLaunchKernelGGL(k_qrcp, dim3(1), dim3(TPB), lds, st, SX, s, cnt, newest, tau, partials, push_blocks_x(n, s),
+                     ctl);
+  return hipGetLastError();
+}
+
+// ============================================================================ basis Q1 = X T1
+template <int MC>
+__global__ __launch_bounds__(TPB) void k_basis(const double *X, double *Q1, int64_t n, int cnt, const Ctl *ctl) {
+  __shared__ double T[MC * MC];
+  const int k = ctl->k;
+  for (int e = threadIdx.x; e < MC * MC; e += blockDim.x) {
+    const int l = e % MC, c = e / MC;
+    T[e] = (l < cnt && c < k) ? ctl->T1[l + c * MAXM] : 0.0;
+  }
+  __syncthreads();
+  GRID_ROWS(i, n) {
+    double xr[MC];
+#pragma unroll
+    for (int l = 0; l < MC; ++l) xr[l] = (l < cnt) ? X[(size_t)l * n + i] : 0.0;
+    for (int c = 0; c < k; ++c) {
+      double q = 0.0;
+#pragma unroll
+      for (int l = 0; l < MC; ++l) q += xr[l] * T[l + c * MC];
+      Q1[(size_t)c * n + i] = q;
+    }
+  }
+}
+
+hipError_t launch_basis(const double *X, double *Q1, int64_t n, int cnt, Ctl *ctl, hipStream_t st) {
+  const int nb = stream_blocks(n);
+  if (cnt <= 16)
+    hipLaunchKernelGGL(k_basis<16>, dim3(nb), dim3(TPB), 0, st, X, Q1, n, cnt, ctl);
+  else
+    hipLaunchKernelGGL(k_basis<32>, dim3(nb), dim3(TPB), 0, st, X, Q1, n, cnt, ctl);
+  return hipGetLastError();
+}
+
+// ============================================================================ SpMM + Gram (MFMA)
+// Each wave owns 64-row tiles.  Lane = row: w = (A Q1)_row in registers.  The tile
+// [Q1 | W | b] (64 rows x (2 cnt + 1) columns) is staged in the wave's LDS and
+// Q1_tile^T [Q1 | W | b]_tile is accumulated with v_mfma_f64_16x16x4f64 over 16 steps
+// of 4 rows.  Columns >= k of the Q1 and W blocks are zero.  Operand layout of the
+// 16x16x4 f64 instruction: A[i][kq] from lane i + 16 kq, B[kq][j] from lane j + 16 kq,
+// D[lane / 16 + 4 v][lane % 16] in accumulator element v.
+constexpr int GRAM_TPB = 128;
+constexpr int GRAM_NW = GRAM_TPB / WAVE;
+constexpr int GRAM_LDT = WAVE + 1;
+constexpr int GRAM_MAXBLK = 768;
+
+template <typename VT, int MC>
+__global__ __launch_bounds__(GRAM_TPB) void k_spmm_gram(const int *rowptr, const int *col, const VT *val,
+                                                        const double *Q1, const double *b, int64_t n, int cnt,
+                                                        double *partials, const Ctl *ctl) {
+  extern __shared__ double lds[];
+  constexpr int NA = MC / 16;
+  constexpr int NB = (2 * MC + 1 + 15) / 16;
+  const int k = ctl->k;
+  const int nbc = 2 * cnt + 1;
+  const int lane = threadIdx.x % WAVE, wid = threadIdx.x / WAVE;
+  double *T = lds + (size_t)wid * nbc * GRAM_LDT;
+  const int na = (k + 15) / 16, nb = (nbc + 15) / 16;
+  d4 acc[NA][NB];
+#pragma unroll
+  for (int a = 0; a < NA; ++a)
+#pragma unroll
+    for (int bq = 0; bq < NB; ++bq) acc[a][bq] = (d4){0.0, 0.0, 0.0, 0.0};
+  const int64_t ntiles = (n + WAVE - 1) / WAVE;
+  for (int64_t t = (int64_t)blockIdx.x * GRAM_NW + wid; t < ntiles; t += (int64_t)gridDim.x * GRAM_NW) {
+    const int64_t i = t * WAVE + lane;
+    double w[MC];
+#pragma unroll
+    for (int c = 0; c < MC; ++c) w[c] = 0.0;
+    if (i < n) {
+      const int p0 = rowptr[i], p1 = rowptr[i + 1];
+      for (int p = p0; p < p1; ++p) {
+        const double av = (double)val[p];
+        const int64_t jc = col[p];
+#pragma unroll
+        for (int c = 0; c < MC; ++c)
+          if (c < k) w[c] += av * Q1[(size_t)c * n + jc];
+      }
+    }
+#pragma unroll
+    for (int c = 0; c < MC; ++c) {
+      if (c < cnt) {
+        const bool ok = (c < k) && (i < n);
+        T[c * GRAM_LDT + lane] = ok ? Q1[(size_t)c * n + i] : 0.0;
+        T[(cnt + c) * GRAM_LDT + lane] = ok ? w[c] : 0.0;
+      }
+    }
+    T[(2 * cnt) * GRAM_LDT + lane] = (i < n) ? b[i] : 0.0;
+    wave_sync();
+    const int li = lane % 16, kq = lane / 16;
+#pragma unroll 4
+    for (int ks = 0; ks < WAVE / 4; ++ks) {
+      const int r = ks * 4 + kq;
+      double av[NA], bv[NB];
+#pragma unroll
+      for (int a = 0; a < NA; ++a) {
+        const int c = a * 16 + li;
+        av[a] = (a < na && c < k) ? T[c * GRAM_LDT + r] : 0.0;
+      }
+#pragma unroll
+      for (int bq = 0; bq < NB; ++bq) {
+        const int c = bq * 16 + li;
+        bv[bq] = (bq < nb && c < nbc) ? T[c * GRAM_LDT + r] : 0.0;
+      }
+#pragma unroll
+      for (int a = 0; a < NA; ++a)
+#pragma unroll
+        for (int bq = 0; bq < NB; ++bq)
+          if (a < na && bq < nb) acc[a][bq] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[a], bv[bq], acc[a][bq], 0, 0, 0);
+    }
+    wave_sync();
+  }
+  // combine the waves of the block, then write this block's partial P[a + col * cnt]
+  __syncthreads();
+  double *P = lds;  // reuse: GRAM_NW x (NA*16) x (NB*16)
+  constexpr int PA = NA * 16, PB = NB * 16;
+#pragma unroll
+  for (int a = 0; a < NA; ++a)
+#pragma unroll
+    for (int bq = 0; bq < NB; ++bq)
+#pragma unroll
+      for (int vv = 0; vv < 4; ++vv) {
+        const int row = a * 16 + lane / 16 + 4 * vv, colx = bq * 16 + lane % 16;
+        P[(size_t)wid * PA * PB + row + colx * PA] = acc[a][bq][vv];
+      }
+  __syncthreads();
+  const int W = cnt * nbc;
+  double *out = partials + (size_t)blockIdx.x * W;
+  for (int e = threadIdx.x; e < W; e += blockDim.x) {
+    const int a = e % cnt, colx = e / cnt;
+    double sum = 0.0;
+    if (a < k && a < PA && colx < PB)
+      for (int ww = 0; ww < GRAM_NW; ++ww) sum += P[(size_t)ww * PA * PB + a + colx * PA];
+    out[e] = sum;
+  }
+}
+
+hipError_t launch_spmm_gram(const CsrView &A, const double *Q1, const double *b, int cnt, int minres,
+                            double *partials, int *nblk_out, Ctl *ctl, hipStream_t st) {
+  (void)minres;
+  const int64_t ntiles = (A.n + WAVE - 1) / WAVE;
+  int64_t nb = (ntiles + GRAM_NW - 1) / GRAM_NW;
+  if (nb > GRAM_MAXBLK) nb = GRAM_MAXBLK;
+  if (nb < 1) nb = 1;
+  const int nbc = 2 * cnt + 1;
+  const int mc = cnt <= 16 ? 16 : 32;
+  const size_t tile = (size_t)GRAM_NW * nbc * GRAM_LDT;
+  const size_t comb = (size_t)GRAM_NW * (mc) * (((2 * mc + 1 + 15) / 16) * 16);
+  const size_t lds = (tile > comb ? tile : comb) * sizeof(double);
+  *nblk_out = (int)nb;
+  if (A.fp32) {
+    if (mc == 16)
+      hipLaunchKernelGGL((k_spmm_gram<float, 16>), dim3(nb), dim3(GRAM_TPB), lds, st, A.rowptr, A.col,
+                         (const float *)A.val, Q1, b, A.n, cnt, partials, ctl);
+    else
+      hipLaunchKernelGGL((k_spmm_gram<float, 32>), dim3(nb), dim3(GRAM_TPB), lds, st, A.rowptr, A.col,
+                         (const float *)A.val, Q1, b, A.n, cnt, partials, ctl);
+  } else {
+    if (mc == 16)
+      hipLaunchKernelGGL((k_spmm_gram<double, 16>), dim3(nb), dim3(GRAM_TPB), lds, st, A.rowptr, A.col,
+                         (const double *)A.val, Q1, b, A.n, cnt, partials, ctl);
+    else
+      hipLaunchKernelGGL((k_spmm_gram<double, 32>), dim3(nb), dim3(GRAM_TPB), lds, st, A.rowptr, A.col,
+                         (const double *)A.val, Q1, b, A.n, cnt, partials, ctl);
+  }
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------- column sums
+// gram[e] = sum_b partials[b][e]; block = 16 entries x 16 block-groups.
+__global__ __launch_bounds__(TPB) void k_colsum(const double *partials, int nblk, int W, Ctl *ctl) {
+  __shared__ double sc[TPB];
+  const int e = blockIdx.x * 16 + threadIdx.x % 16, grp = threadIdx.x / 16;
+  double s = 0.0;
+  if (e < W)
+    for (int b = grp; b < nblk; b += 16) s += partials[(size_t)b * W + e];
+  sc[threadIdx.x] = s;
+  __syncthreads();
+  for (int off = 8; off > 0; off >>= 1) {
+    if (grp < off) sc[threadIdx.x] += sc[threadIdx.x + off * 16];
+    __syncthreads();
+  }
+  if (threadIdx.x < 16 && e < W) ctl->gram[e] = sc[threadIdx.x];
+}
+
+hipError_t launch_colsum(const double *partials, int nblk, int W, Ctl *ctl, hipStream_t st) {
+  hipLaunchKernelGGL(k_colsum, dim3((W + 15) / 16), dim3(TPB), 0, st, partials, nblk, W, ctl);
+  return hipGetLastError();
+}
+
+// ============================================================================ small reduced solve
+// One workgroup.  gram holds P = Q1^T [Q1 | W | b] with ld cnt: G = P[:, 0:k],
+// Ht = P[:, cnt:cnt+k], gt = P[:, 2 cnt].  Pivoted Cholesky of G with threshold
+// tau_c max(diag G) gives R2 (k2 x k2) and perm2; H = R2^-T Ht_pp R2^-1,
+// g = R2^-T gt_p; H y = g by Cholesky (SPD path) or LU with partial pivoting;
+// c[perm2[i]] = (R2^-1 y)_i, cX = T1 c.
+__global__ __launch_bounds__(TPB) void k_small_solve(int cnt, int spd, double tau_c, Ctl *ctl) {
+  extern __shared__ double sh[];
+  const int k = ctl->k;
+  const int tid = threadIdx.x;
+  __shared__ int perm[MAXM];
+  __shared__ int ipiv[MAXM];
+  __shared__ double gv[MAXM], yv[MAXM], cv[MAXM];
+  __shared__ int s_k2, s_stop, s_fail, s_p;
+  __shared__ double s_dmax;
+  double *Gm = sh;                  // k x k, ld k  (-> R2 in its leading k2 x k2, upper part)
+  double *Ri = sh + (size_t)k * k;  // k2 x k2, ld k
+  double *Hm = sh + (size_t)2 * k * k;  // k x k, ld k
+  const double *P = ctl->gram;
+  if (k == 0) {
+    for (int c = tid; c < MAXM; c += blockDim.x) {
+      ctl->c[c] = 0.0;
+      ctl->cX[c] = 0.0;
+    }
+    if (tid == 0) {
+      ctl->k2 = 0;
+      ctl->fallback = ctl->nonfinite;
+    }
+    return;
+  }
+  for (int e = tid; e < k * k; e += blockDim.x) {
+    const int a = e % k, b = e / k;
+    Gm[a + b * k] = P[a + b * cnt];
+  }
+  for (int a = tid; a < k; a += blockDim.x) perm[a] = a;
+  if (tid == 0) {
+    s_fail = 0;
+    s_stop = 0;
+    double dm = 0.0;
+    for (int a = 0; a < k; ++a) dm = fmax(dm, P[a + a * cnt]);
+    s_dmax = dm;
+    s_k2 = k;
+  }
+  __syncthreads();
+  // pivoted Cholesky, outer-product form, in place on the full symmetric matrix
+  for (int j = 0; j < k; ++j) {
+    if (tid == 0) {
+      int p = j;
+      for (int a = j + 1; a < k; ++a)
+        if (Gm[a + a * k] > Gm[p + p * k]) p = a;
+      s_p = p;
+      if (!(Gm[p + p * k] > tau_c * s_dmax)) {
+        s_stop = 1;
+        s_k2 = j;
+      } else if (p != j) {
+        int t = perm[j];
+        perm[j] = perm[p];
+        perm[p] = t;
+      }
+    }
+    __syncthreads();
+    if (s_stop) break;
+    const int p = s_p;
+    if (p != j) {
+      for (int a = tid; a < k; a += blockDim.x) {  // swap rows j, p
+        double t = Gm[j + a * k];
+        Gm[j + a * k] = Gm[p + a * k];
+        Gm[p + a * k] = t;
+      }
+      __syncthreads();
+      for (int a = tid; a < k; a += blockDim.x) {  // swap columns j, p
+        double t = Gm[a + j * k];
+        Gm[a + j * k] = Gm[a + p * k];
+        Gm[a + p * k] = t;
+      }
+      __syncthreads();
+    }
+    const double d = sqrt(Gm[j + j * k]);
+    __syncthreads();
+    for (int a = j + 1 + tid; a < k; a += blockDim.x) Gm[j + a * k] /= d;
+    if (tid == 0) Gm[j + j * k] = d;
+    __syncthreads();
+    for (int e = tid; e < (k - j - 1) * (k - j - 1); e += blockDim.x) {
+      const int a = j + 1 + e % (k - j - 1), b = j + 1 + e / (k - j - 1);
+      Gm[a + b * k] -= Gm[j + a * k] * Gm[j + b * k];
+    }
+    __syncthreads();
+  }
+  const int k2 = s_k2;
+  // Ri = R2^-1 (upper triangular, ld k)
+  for (int c = tid; c < k2; c += blockDim.x) {
+    for (int i = 0; i < k2; ++i) Ri[i + c * k] = 0.0;
+    Ri[c + c * k] = 1.0 / Gm[c + c * k];
+    for (int i = c - 1; i >= 0; --i) {
+      double acc = 0.0;
+      for (int l = i + 1; l <= c; ++l) acc += Gm[i + l * k] * Ri[l + c * k];
+      Ri[i + c * k] = -acc / Gm[i + i * k];
+    }
+  }
+  __syncthreads();
+  // Hm = Ht_pp Ri  (Ht_pp[a][b] = Ht[perm a][perm b]); reuse Gm for the result of Ri^T (.)
+  for (int e = tid; e < k2 * k2; e += blockDim.x) {
+    const int a = e % k2, b = e / k2;
+    double acc = 0.0;
+    for (int l = 0; l <= b; ++l) acc += P[perm[a] + (cnt + perm[l]) * cnt] * Ri[l + b * k];
+    Hm[a + b * k] = acc;
+  }
+  for (int a = tid; a < k2; a += blockDim.x) {
+    double acc = 0.0;
+    for (int l = 0; l <= a; ++l) acc += Ri[l + a * k] * P[perm[l] + (2 * cnt) * cnt];
+    gv[a] = acc;
+  }
+  __syncthreads();
+  for (int e = tid; e < k2 * k2; e += blockDim.x) {
+    const int a = e % k2, b = e / k2;
+    double acc = 0.0;
+    for (int l = 0; l <= a; ++l) acc += Ri[l + a * k] * Hm[l + b * k];
+    Gm[a + b * k] = acc;  // H (k2 x k2, ld k)
+  }
+  __syncthreads();
+  if (spd) {
+    for (int e = tid; e < k2 * k2; e += blockDim.x) {
+      const int a = e % k2, b = e / k2;
+      if (a < b) {
+        const double m = 0.5 * (Gm[a + b * k] + Gm[b + a * k]);
+        Gm[a + b * k] = m;
+        Gm[b + a * k] = m;
+      }
+    }
+    __syncthreads();
+    // Cholesky H = L L^T in the lower triangle
+    for (int j = 0; j < k2; ++j) {
+      if (tid == 0) {
+        const double d = Gm[j + j * k];
+        if (!(d > 0.0) || !isfinite(d)) s_fail = 1;
+        Gm[j + j * k] = sqrt(d);
+      }
+      __syncthreads();
+      if (s_fail) break;
+      const double d = Gm[j + j * k];
+      for (int a = j + 1 + tid; a < k2; a += blockDim.x) Gm[a + j * k] /= d;
+      __syncthreads();
+      for (int e = tid; e < (k2 - j - 1) * (k2 - j - 1); e += blockDim.x) {
+        const int a = j + 1 + e % (k2 - j - 1), b = j + 1 + e / (k2 - j - 1);
+        if (a >= b) Gm[a + b * k] -= Gm[a + j * k] * Gm[b + j * k];
+      }
+      __syncthreads();
+    }
+    if (tid == 0 && !s_fail) {
+      for (int a = 0; a < k2; ++a) {
+        double acc = gv[a];
+        for (int l = 0; l < a; ++l) acc -= Gm[a + l * k] * yv[l];
+        yv[a] = acc / Gm[a + a * k];
+      }
+      for (int a = k2 - 1; a >= 0; --a) {
+        double acc = yv[a];
+        for (int l = a + 1; l < k2; ++l) acc -= Gm[l + a * k] * yv[l];
+        yv[a] = acc / Gm[a + a * k];
+      }
+    }
+  } else {
+    // LU with partial pivoting, row interchanges applied to the whole rows
+    for (int j = 0; j < k2; ++j) {
+      if (tid == 0) {
+        int p = j;
+        for (int a = j + 1; a < k2; ++a)
+          if (fabs(Gm[a + j * k]) > fabs(Gm[p + j * k])) p = a;
+        ipiv[j] = p;
+        if (!(Gm[p + j * k] != 0.0) || !isfinite(Gm[p + j * k])) s_fail = 1;
+        if (p != j) {
+          double t = gv[j];
+          gv[j] = gv[p];
+          gv[p] = t;
+        }
+      }
+      __syncthreads();
+      if (s_fail) break;
+      const int p = ipiv[j];
+      if (p != j)
+        for (int b = tid; b < k2; b += blockDim.x) {
+          double t = Gm[j + b * k];
+          Gm[j + b * k] = Gm[p + b * k];
+          Gm[p + b * k] = t;
+        }
+      __syncthreads();
+      const double d = Gm[j + j * k];
+      for (int a = j + 1 + tid; a < k2; a += blockDim.x) Gm[a + j * k] /= d;
+      __syncthreads();
+      for (int e = tid; e < (k2 - j - 1) * (k2 - j - 1); e += blockDim.x) {
+        const int a = j + 1 + e % (k2 - j - 1), b = j + 1 + e / (k2 - j - 1);
+        Gm[a + b * k] -= Gm[a + j * k] * Gm[j + b * k];
+      }
+      __syncthreads();
+    }
+    if (tid == 0 && !s_fail) {
+      for (int a = 0; a < k2; ++a) {
+        double acc = gv[a];
+        for (int l = 0; l < a; ++l) acc -= Gm[a + l * k] * yv[l];
+        yv[a] = acc;
+      }
+      for (int a = k2 - 1; a >= 0; --a) {
+        double acc = yv[a];
+        for (int l = a + 1; l < k2; ++l) acc -= Gm[a + l * k] * yv[l];
+        yv[a] = acc / Gm[a + a * k];
+      }
+    }
+  }
+  __syncthreads();
+  for (int a = tid; a < MAXM; a += blockDim.x) cv[a] = 0.0;
+  __syncthreads();
+  if (!s_fail)
+    for (int a = tid; a < k2; a += blockDim.x) {
+      double acc = 0.0;
+      for (int l = a; l < k2; ++l) acc += Ri[a + l * k] * yv[l];
+      cv[perm[a]] = acc;
+    }
+  __syncthreads();
+  if (tid == 0) {
+    int bad = s_fail;
+    for (int a = 0; a < k; ++a)
+      if (!isfinite(cv[a])) bad = 1;
+    s_fail = bad;
+  }
+  __syncthreads();
+  for (int a = tid; a < MAXM; a += blockDim.x) ctl->c[a] = s_fail ? 0.0 : cv[a];
+  for (int l = tid; l < MAXM; l += blockDim.x) {
+    double acc = 0.0;
+    if (!s_fail && l < cnt)
+      for (int c = 0; c < k; ++c) acc += ctl->T1[l + c * MAXM] * cv[c];
+    ctl->cX[l] = acc;
+  }
+  if (tid == 0) {
+    ctl->k2 = k2;
+    ctl->fallback = s_fail;
+  }
+}
+
+hipError_t launch_small_solve(int cnt, int minres, int spd, double tau_c, Ctl *ctl, hipStream_t st) {
+  (void)minres;
+  size_t lds = (size_t)3 * cnt * cnt * sizeof(double);
+  if (lds == 0) lds = sizeof(double);
+  hipLaunchKernelGGL(k_small_solve, dim3(1), dim3(TPB), lds, st, cnt, spd, tau_c, ctl);
+  return hipGetLastError();
+}
+
+// ============================================================================ x0
+template <int MC>
+__global__ __launch_bounds__(TPB) void k_x0(const double *Q1, const double *X, double *x0, int64_t n,
+                                            const Ctl *ctl) {
+  __shared__ double cc[MC];
+  const int k = ctl->k;
+  const int fb = ctl->fallback;
+  const int newest = ctl->newest;
+  const int newest_ok = ctl->newest_ok;
+  for (int c = threadIdx.x; c < MC; c += blockDim.x) cc[c] = (c < k) ? ctl->c[c] : 0.0;
+  __syncthreads();
+  GRID_ROWS(i, n) {
+    double s = 0.0;
+    if (fb) {
+      s = (newest >= 0 && newest_ok) ? X[(size_t)newest * n + i] : 0.0;
+    } else {
+      for (int c = 0; c < k; ++c) s += Q1[(size_t)c * n + i] * cc[c];
+    }
+    x0[i] = s;
+  }
+}
+
+hipError_t launch_x0(const double *Q1, const double *X, double *x0, int64_t n, Ctl *ctl, hipStream_t st) {
+  hipLaunchKernelGGL(k_x0<MAXM>, dim3(stream_blocks(n)), dim3(TPB), 0, st, Q1, X, x0, n, ctl);
+  return hipGetLastError();
+}
+
+size_t partials_doubles(int64_t n, int M, int s) {
+  (void)n;
+  size_t a = krylov_partials_doubles();                                 // Krylov dots
+  size_t b = (size_t)MAXBLK * SKETCH_RG;                                // sketch
+  size_t c = (size_t)GRAM_MAXBLK * M * (2 * M + 1);                     // Gram
+  (void)s;
+  size_t m = a > b ? a : b;
+  return m > c ? m : c;
+}
+
+}  // namespace sacc

@@ -1,0 +1,168 @@
+"""Python front end over the C-ABI: device CSR matrices and sequences.
+
+PyTorch supplies device memory and the current stream only; every step of the
+method runs in the library's HIP kernels.
+"""
+
+from __future__ import annotations
+
+import ctypes
+from typing import Optional
+
+import numpy as np
+import torch
+
+from . import native as nv
+
+_SKETCH = {"gaussian": nv.SA_SKETCH_GAUSSIAN, "srht": nv.SA_SKETCH_SRHT}
+_SOLVER = {"cg": nv.SA_CG, "gmres": nv.SA_GMRES}
+_PREC = {"fp64": nv.SA_FP64, "mixed": nv.SA_MIXED}
+_PROJ = {"galerkin": nv.SA_GALERKIN, "minres": nv.SA_MINRES}
+_GUESS = {"projection": nv.SA_GUESS_PROJECTION, "zero": nv.SA_GUESS_ZERO,
+          "previous": nv.SA_GUESS_PREVIOUS}
+
+
+def _stream(stream=None) -> int:
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return s.cuda_stream
+
+
+def _ptr(t: torch.Tensor) -> int:
+    if not t.is_cuda or not t.is_contiguous():
+        raise ValueError("expected a contiguous device tensor")
+    return t.data_ptr()
+
+
+class DeviceCSR:
+    """CSR matrix resident in device memory (int32 indices, float64 or float32 values)."""
+
+    def __init__(self, rowptr, col, val, device="cuda"):
+        self.rowptr = torch.as_tensor(np.asarray(rowptr, dtype=np.int32)).to(device)
+        self.col = torch.as_tensor(np.asarray(col, dtype=np.int32)).to(device)
+        v = np.asarray(val)
+        if v.dtype not in (np.float64, np.float32):
+            v = v.astype(np.float64)
+        self.val = torch.as_tensor(v).to(device)
+        self.n = int(self.rowptr.numel() - 1)
+        self.nnz = int(self.col.numel())
+
+    @classmethod
+    def from_csr(cls, A, device="cuda"):
+        return cls(A.rowptr, A.col, A.val, device)
+
+    def set_values(self, val):
+        """Overwrite the values in place (same pattern), e.g. for the next time step."""
+        v = torch.as_tensor(np.ascontiguousarray(val))
+        if v.numel() != self.nnz:
+            raise ValueError("value count does not match the pattern")
+        self.val.copy_(v.to(self.val.dtype))
+
+    def c_struct(self) -> nv.SaCsr:
+        return nv.SaCsr(self.n, self.nnz, _ptr(self.rowptr), _ptr(self.col), _ptr(self.val),
+                        1 if self.val.dtype == torch.float32 else 0, 0)
+
+
+def spmv(A: DeviceCSR, x: torch.Tensor, y: Optional[torch.Tensor] = None, stream=None) -> torch.Tensor:
+    """y = A x through sa_spmv."""
+    if y is None:
+        y = torch.empty_like(x)
+    s = A.c_struct()
+    nv.check(nv.lib().sa_spmv(ctypes.byref(s), _ptr(x), _ptr(y), _stream(stream)), "sa_spmv")
+    return y
+
+
+class Sequence:
+    """One sequence of systems A(t_i) x = b(t_i) handled by the library."""
+
+    def __init__(self, n: int, M: int, s: Optional[int] = None, sketch: str = "gaussian",
+                 solver: str = "cg", restart: int = 30, tol: float = 1e-8, maxit: int = 200000,
+                 precision: str = "fp64", projection: str = "galerkin", guess: str = "projection",
+                 seed: int = 0, rank_tol_sketch: float = 0.0, rank_tol_chol: float = 0.0,
+                 inner_tol: float = 1e-4, max_refine: int = 10, poll: int = 0, device="cuda",
+                 stream=None):
+        self.n, self.M = n, M
+        self.s = 2 * M if s is None else s
+        self.cfg = nv.SaConfig(
+            n=n, M=M, s=self.s, sketch=_SKETCH[sketch], projection=_PROJ[projection],
+            solver=_SOLVER[solver], restart=restart, tol=tol, maxit=maxit,
+            precision=_PREC[precision], inner_tol=inner_tol, max_refine=max_refine,
+            guess=_GUESS[guess], rank_tol_sketch=rank_tol_sketch, rank_tol_chol=rank_tol_chol,
+            seed=seed, poll=poll, reserved=0)
+        L = nv.lib()
+        nbytes = ctypes.c_size_t(0)
+        nv.check(L.sa_workspace_bytes(ctypes.byref(self.cfg), ctypes.byref(nbytes)), "sa_workspace_bytes")
+        self.workspace = torch.empty(int(nbytes.value), dtype=torch.uint8, device=device)
+        self.stream = stream
+        h = ctypes.c_void_p(0)
+        nv.check(L.sa_init_sequence(ctypes.byref(self.cfg), _ptr(self.workspace), nbytes,
+                                    _stream(stream), ctypes.byref(h)), "sa_init_sequence")
+        self._h = h
+
+    def close(self):
+        if getattr(self, "_h", None) and self._h.value:
+            nv.lib().sa_destroy_sequence(self._h)
+            self._h = ctypes.c_void_p(0)
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    # ------------------------------------------------------------------ steps
+    def push(self, x: torch.Tensor):
+        nv.check(nv.lib().sa_push_solution(self._h, _ptr(x), _stream(self.stream)), "sa_push_solution")
+
+    def initial_guess(self, A: DeviceCSR, b: torch.Tensor, x0: Optional[torch.Tensor] = None,
+                      info: bool = True):
+        if x0 is None:
+            x0 = torch.empty_like(b)
+        inf = nv.SaInfo()
+        s = A.c_struct()
+        nv.check(nv.lib().sa_initial_guess(self._h, ctypes.byref(s), _ptr(b), _ptr(x0),
+                                           ctypes.byref(inf) if info else None,
+                                           _stream(self.stream)), "sa_initial_guess")
+        return x0, (inf.as_dict() if info else None)
+
+    def solve(self, A: DeviceCSR, b: torch.Tensor, x: torch.Tensor, info: bool = True,
+              allow=(nv.SA_OK, nv.SA_NOTCONV, nv.SA_EBREAKDOWN)):
+        inf = nv.SaInfo()
+        s = A.c_struct()
+        rc = nv.lib().sa_solve(self._h, ctypes.byref(s), _ptr(b), _ptr(x),
+                               ctypes.byref(inf) if info else None, _stream(self.stream))
+        nv.check(rc, "sa_solve", allow)
+        d = inf.as_dict() if info else {}
+        d["rc"] = rc
+        return x, d
+
+    def step(self, A: DeviceCSR, b: torch.Tensor, x: Optional[torch.Tensor] = None):
+        """initial guess -> solve -> push; returns (x, merged info)."""
+        x, g = self.initial_guess(A, b, x)
+        x, s = self.solve(A, b, x)
+        self.push(x)
+        for key in ("k_eff", "k_sketch", "used_fallback", "history", "ms_guess"):
+            s[key] = g[key]
+        return x, s
+
+    # ------------------------------------------------------------------ inspection
+    def copy_state(self, what: str) -> np.ndarray:
+        L = nv.lib()
+        if what == "SX":
+            out = np.empty((self.M, self.s), dtype=np.float64)
+            code = 0
+        elif what == "X":
+            out = np.empty((self.M, self.n), dtype=np.float64)
+            code = 1
+        elif what == "cX":
+            out = np.empty(self.M, dtype=np.float64)
+            code = 2
+        elif what == "order":
+            out = np.empty(self.M, dtype=np.int32)
+            code = 3
+        else:
+            raise ValueError(what)
+        nv.check(L.sa_copy_state(self._h, code, out.ctypes.data, out.nbytes, _stream(self.stream)),
+                 "sa_copy_state")
+        if what in ("SX", "X"):
+            return out.T.copy()   # column-major on the device -> (rows, M)
+        return out
