@@ -12,6 +12,11 @@ confirmation fails the solver continues from the true residual.
   matrix, |g_{j+1}| as the residual estimate, restart from the true residual.  One
   iteration = one Arnoldi step; the count sums over restarts.
 
+``store`` models where a vector is written to memory: every vector the solver keeps
+(x, r, p, q; the Arnoldi vectors) passes through it.  It is the identity for FP64 runs
+and a round trip through float32 for the inner solves of the mixed mode (all
+arithmetic stays in float64 between stores).
+
 Both return (x, info) with info = dict(iters, restarts, relres, relres0, status),
 status 0 converged, 1 not converged within maxit, -5 breakdown (CG p^T A p <= 0 or
 not finite).  A zero right-hand side returns x = 0 with zero iterations.
@@ -28,15 +33,20 @@ def _norm(v):
     return float(np.sqrt(np.dot(v, v)))
 
 
-def cg(A, b, x0, tol: float, maxit: int = 100000):
+def _identity(v):
+    return v
+
+
+def cg(A, b, x0, tol: float, maxit: int = 100000, store=None):
     """Hestenes-Stiefel conjugate gradients from x0."""
+    st = _identity if store is None else store
     b = np.asarray(b, dtype=np.float64)
-    x = np.array(x0, dtype=np.float64, copy=True)
+    x = st(np.array(x0, dtype=np.float64, copy=True))
     bnorm = _norm(b)
     if bnorm == 0.0:
         return np.zeros_like(b), dict(iters=0, restarts=0, relres=0.0, relres0=0.0, status=CONVERGED)
     thresh = tol * bnorm
-    r = b - A @ x
+    r = st(b - A @ x)
     rho = float(np.dot(r, r))
     relres0 = np.sqrt(rho) / bnorm
     it = 0
@@ -46,18 +56,18 @@ def cg(A, b, x0, tol: float, maxit: int = 100000):
     p = r.copy()
     status = NOTCONV
     while it < maxit:
-        q = A @ p
+        q = st(A @ p)
         pq = float(np.dot(p, q))
         if not (pq > 0.0) or not np.isfinite(pq):
             status = BREAKDOWN
             break
         alpha = rho / pq
-        x += alpha * p
-        r -= alpha * q
+        x = st(x + alpha * p)
+        r = st(r - alpha * q)
         rho_new = float(np.dot(r, r))
         it += 1
         if np.sqrt(rho_new) <= thresh:
-            r = b - A @ x
+            r = st(b - A @ x)
             rho = float(np.dot(r, r))
             if np.sqrt(rho) <= thresh:
                 status = CONVERGED
@@ -67,7 +77,7 @@ def cg(A, b, x0, tol: float, maxit: int = 100000):
             continue
         beta = rho_new / rho
         rho = rho_new
-        p = r + beta * p
+        p = st(r + beta * p)
     rt = b - A @ x
     return x, dict(iters=it, restarts=restarts, relres=_norm(rt) / bnorm, relres0=relres0,
                    status=status)
@@ -81,16 +91,17 @@ def givens(a: float, b: float):
     return a / rho, b / rho, rho
 
 
-def gmres(A, b, x0, tol: float, restart: int = 30, maxit: int = 100000):
+def gmres(A, b, x0, tol: float, restart: int = 30, maxit: int = 100000, store=None):
     """Restarted GMRES(restart) with modified Gram-Schmidt Arnoldi and Givens rotations."""
+    st = _identity if store is None else store
     b = np.asarray(b, dtype=np.float64)
-    x = np.array(x0, dtype=np.float64, copy=True)
+    x = st(np.array(x0, dtype=np.float64, copy=True))
     n = b.shape[0]
     bnorm = _norm(b)
     if bnorm == 0.0:
         return np.zeros_like(b), dict(iters=0, restarts=0, relres=0.0, relres0=0.0, status=CONVERGED)
     thresh = tol * bnorm
-    r = b - A @ x
+    r = st(b - A @ x)
     beta = _norm(r)
     relres0 = beta / bnorm
     total = 0
@@ -103,14 +114,15 @@ def gmres(A, b, x0, tol: float, restart: int = 30, maxit: int = 100000):
         cs = np.zeros(m)
         sn = np.zeros(m)
         g = np.zeros(m + 1)
-        V[:, 0] = r / beta
+        V[:, 0] = st(r / beta)
         g[0] = beta
         jend = 0
         for j in range(m):
-            w = A @ V[:, j]
+            w = st(A @ V[:, j])
             for l in range(j + 1):
                 H[l, j] = float(np.dot(V[:, l], w))
                 w -= H[l, j] * V[:, l]
+            w = st(w)
             H[j + 1, j] = _norm(w)
             for l in range(j):
                 t = cs[l] * H[l, j] + sn[l] * H[l + 1, j]
@@ -125,12 +137,12 @@ def gmres(A, b, x0, tol: float, restart: int = 30, maxit: int = 100000):
             jend = j + 1
             if abs(g[j + 1]) <= thresh or hnext == 0.0 or total >= maxit:
                 break
-            V[:, j + 1] = w / hnext
+            V[:, j + 1] = st(w / hnext)
         y = np.zeros(jend)
         for i in range(jend - 1, -1, -1):
             y[i] = (g[i] - np.dot(H[i, i + 1:jend], y[i + 1:jend])) / H[i, i]
-        x += V[:, :jend] @ y
-        r = b - A @ x
+        x = st(x + V[:, :jend] @ y)
+        r = st(b - A @ x)
         beta = _norm(r)
         cycles += 1
         if beta <= thresh:

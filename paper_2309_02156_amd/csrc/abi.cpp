@@ -15,13 +15,19 @@ using namespace sacc;
 
 struct sa_seq {
   sa_config cfg;
+  bool mixed = false;  // SA_MIXED: FP32 history / basis / inner Krylov vectors
   char *ws = nullptr;
   size_t ws_bytes = 0;
-  double *X = nullptr, *SX = nullptr, *Q1 = nullptr, *kry = nullptr, *partials = nullptr;
+  void *X = nullptr, *Q1 = nullptr;  // double or float storage
+  double *SX = nullptr, *partials = nullptr;
+  void *kry = nullptr;               // Krylov vectors (double, or float for inner solves)
+  float *r32 = nullptr, *d32 = nullptr;  // mixed: inner right-hand side and correction
   long long *srht_rows = nullptr;
-  Ctl *ctl = nullptr;   // device control block
-  int *hbuf = nullptr;  // pinned host mirror of the solver state
+  Ctl *ctl = nullptr;     // device control block (projection + outer solve)
+  Ctl *ctl_in = nullptr;  // device control block of the inner solves (mixed)
+  int *hbuf = nullptr;    // pinned host mirror of solver state
   long long pushes = 0;
+  int64_t ld = 0;  // leading dimension of X, Q1 and the Krylov vectors
   double tau_s = 1e-12, tau_c = 1e-12;
   hipEvent_t ev[4] = {nullptr, nullptr, nullptr, nullptr};
   bool alive = true;
@@ -72,7 +78,7 @@ void srht_rows_host(int64_t n, int s, uint64_t seed, std::vector<long long> &out
 }
 
 struct Layout {
-  size_t X, SX, Q1, kry, partials, rows, total;
+  size_t X, SX, Q1, kry, partials, rows, r32, d32, total;
 };
 
 int validate(const sa_config *c) {
@@ -87,28 +93,40 @@ int validate(const sa_config *c) {
   if (c->solver != SA_CG && c->solver != SA_GMRES) return SA_EINVAL;
   if (c->solver == SA_GMRES && (c->restart < 1 || c->restart > MAXR)) return SA_EINVAL;
   if (!(c->tol > 0.0) || c->maxit < 0) return SA_EINVAL;
-  if (c->precision != SA_FP64) return SA_EINVAL;
+  if (c->precision != SA_FP64 && c->precision != SA_MIXED) return SA_EINVAL;
+  if (c->precision == SA_MIXED && (!(c->inner_tol > 0.0) || !(c->inner_tol < 1.0) || c->max_refine < 1))
+    return SA_EINVAL;
   if (c->guess < SA_GUESS_PROJECTION || c->guess > SA_GUESS_PREVIOUS) return SA_EINVAL;
   return SA_OK;
 }
 
 Layout layout(const sa_config *c) {
   Layout L;
-  const size_t n = (size_t)c->n, M = (size_t)c->M;
+  const size_t M = (size_t)c->M;
+  const bool mixed = c->precision == SA_MIXED;
+  const size_t w = mixed ? sizeof(float) : sizeof(double);  // history / basis / Krylov word
+  const size_t ld = (size_t)padded_ld(c->n);
   size_t off = 0;
   L.X = off;
-  off += up(n * M * sizeof(double));
+  off += up(ld * M * w);
   L.SX = off;
   off += up((size_t)c->s * M * sizeof(double));
   L.Q1 = off;
-  off += up(n * M * sizeof(double));
+  off += up(ld * M * w);
   L.kry = off;
-  size_t kv = c->solver == SA_GMRES ? (size_t)(c->restart + 1) : 3;
-  off += up(n * kv * sizeof(double));
+  const size_t kv = c->solver == SA_GMRES ? (size_t)(c->restart + 1) : 3;
+  off += up(ld * kv * w);
   L.partials = off;
   off += up(partials_doubles(c->n, c->M, c->s) * sizeof(double));
   L.rows = off;
   off += up((size_t)c->s * sizeof(long long));
+  L.r32 = L.d32 = 0;
+  if (mixed) {
+    L.r32 = off;
+    off += up(ld * sizeof(float));
+    L.d32 = off;
+    off += up(ld * sizeof(float));
+  }
   L.total = off;
   return L;
 }
@@ -119,10 +137,16 @@ inline int hipok(hipError_t e) { return e == hipSuccess ? SA_OK : SA_EHIP; }
     hipError_t e_ = (expr);                \
     if (e_ != hipSuccess) return SA_EHIP;  \
   } while (0)
+#define SA_TRY(expr)             \
+  do {                           \
+    int rc_ = (expr);            \
+    if (rc_ != SA_OK) return rc_; \
+  } while (0)
 
 int check_csr(const sa_seq *q, const sa_csr *A) {
   if (!A || !A->rowptr_dev || !A->col_dev || !A->val_dev) return SA_EINVAL;
   if (A->n != q->cfg.n || A->nnz < 0) return SA_EINVAL;
+  if (q->mixed && !A->val_is_fp32) return SA_EINVAL;  // the mixed mode solves A32
   return SA_OK;
 }
 
@@ -139,10 +163,137 @@ CsrView view(const sa_csr *A) {
 
 inline int count(const sa_seq *q) { return (int)(q->pushes < q->cfg.M ? q->pushes : q->cfg.M); }
 
-// solver state mirror: state, iters, restarts, maxit, active, jend, restart, pad
-int poll(sa_seq *q, hipStream_t st) {
-  HIP_TRY(hipMemcpyAsync(q->hbuf, &q->ctl->state, 8 * sizeof(int), hipMemcpyDeviceToHost, st));
+// solver state mirror of a control block: state, iters, restarts, maxit, active, jend
+int poll(sa_seq *q, Ctl *ctl, hipStream_t st) {
+  HIP_TRY(hipMemcpyAsync(q->hbuf, &ctl->state, 8 * sizeof(int), hipMemcpyDeviceToHost, st));
   HIP_TRY(hipStreamSynchronize(st));
+  return SA_OK;
+}
+
+int init_ctl(Ctl **out, double tol, int maxit, int restart, hipStream_t st) {
+  Ctl *d = nullptr;
+  if (hipMalloc((void **)&d, sizeof(Ctl)) != hipSuccess) return SA_EHIP;
+  Ctl *h = new (std::nothrow) Ctl();
+  if (!h) {
+    (void)hipFree(d);
+    return SA_ENOMEM;
+  }
+  memset((void *)h, 0, sizeof(Ctl));
+  h->tol = tol;
+  h->maxit = maxit;
+  h->restart = restart;
+  h->newest = -1;
+  h->state = ST_CONV;
+  hipError_t e = hipMemcpyAsync(d, h, sizeof(Ctl), hipMemcpyHostToDevice, st);
+  if (e == hipSuccess) e = hipStreamSynchronize(st);
+  delete h;
+  if (e != hipSuccess) {
+    (void)hipFree(d);
+    return SA_EHIP;
+  }
+  *out = d;
+  return SA_OK;
+}
+
+// ---------------------------------------------------------------------------- Krylov host loops
+// CG on control block `ctl` for A x = b from the iterate in x; final state in q->hbuf[0],
+// iterations in q->hbuf[1], restarts in q->hbuf[2].
+template <typename TV>
+int run_cg(sa_seq *q, const CsrView &v, Ctl *ctl, const TV *b, TV *x, int maxit, hipStream_t st) {
+  const sa_config &c = q->cfg;
+  int *hs = q->hbuf;
+  TV *r = (TV *)q->kry, *p = r + q->ld, *qq = r + 2 * q->ld;
+  int k = 0;            // iterations enqueued (device numbering, 1-based per iteration)
+  bool p_fresh = true;  // p = r: the next iteration needs no direction update
+  HIP_TRY(launch_cg_start_k<TV>(v, b, x, r, p, 0, k, q->partials, ctl, st));
+  SA_TRY(poll(q, ctl, st));
+  // every pass either advances the device iteration count or leaves a final state;
+  // the bound only protects against a corrupted control block
+  const long long max_pass = (long long)maxit + 16;
+  for (long long pass = 0;; ++pass) {
+    if (pass > max_pass || hs[0] < ST_RUN || hs[0] > ST_ZERO_RHS) return SA_EHIP;
+    if (hs[0] == ST_RUN) {
+      for (int t = 0; t < c.poll && k < maxit; ++t) {
+        ++k;
+        HIP_TRY(launch_cg_iter_k<TV>(v, x, r, p, qq, k, p_fresh ? 0 : 1, t > 0 ? 1 : 0, q->partials, ctl, st));
+        p_fresh = false;
+      }
+      HIP_TRY(launch_cg_close_k(q->partials, v.n, k, ctl, st));
+      SA_TRY(poll(q, ctl, st));
+      k = hs[1];  // iterations actually performed (later launches of the batch were no-ops)
+    }
+    if (hs[0] == ST_CHECK) {
+      HIP_TRY(launch_cg_start_k<TV>(v, b, x, r, p, 1, k, q->partials, ctl, st));
+      SA_TRY(poll(q, ctl, st));
+      p_fresh = true;
+    }
+    if (hs[0] == ST_CONV || hs[0] == ST_ZERO_RHS) break;
+    if (hs[0] == ST_MAXIT || hs[0] == ST_BREAK) {
+      HIP_TRY(launch_cg_start_k<TV>(v, b, x, r, p, 2, k, q->partials, ctl, st));
+      SA_TRY(poll(q, ctl, st));
+      break;
+    }
+  }
+  return SA_OK;
+}
+
+template <typename TV>
+int run_gmres(sa_seq *q, const CsrView &v, Ctl *ctl, const TV *b, TV *x, int maxit, hipStream_t st) {
+  const sa_config &c = q->cfg;
+  int *hs = q->hbuf;
+  TV *V = (TV *)q->kry;
+  HIP_TRY(launch_gm_start<TV>(v, b, x, V, 0, q->partials, ctl, st));
+  SA_TRY(poll(q, ctl, st));
+  long long cycles = 0;
+  int total = 0;  // Arnoldi steps performed so far
+  while (hs[0] == ST_RUN) {
+    if (++cycles > (long long)maxit + 16) return SA_EHIP;  // each cycle adds >= 1 iteration
+    int j = 0;
+    while (j < c.restart) {
+      for (int t = 0; t < c.poll && j < c.restart; ++t, ++j) {
+        ++total;
+        HIP_TRY(launch_gm_step_it<TV>(v, V, q->ld, j, total, t > 0 ? 1 : 0, q->partials, ctl, st));
+      }
+      HIP_TRY(launch_gm_close_it(q->partials, v.n, j - 1, total, ctl, st));
+      SA_TRY(poll(q, ctl, st));
+      if (!hs[4] || hs[0] != ST_RUN) break;
+    }
+    total = hs[1];
+    HIP_TRY(launch_gm_update<TV>(x, V, v.n, q->ld, c.restart, ctl, st));
+    HIP_TRY(launch_gm_start<TV>(v, b, x, V, 1, q->partials, ctl, st));
+    SA_TRY(poll(q, ctl, st));
+  }
+  return SA_OK;
+}
+
+template <typename TV>
+int run_krylov(sa_seq *q, const CsrView &v, Ctl *ctl, const TV *b, TV *x, int maxit, hipStream_t st) {
+  return q->cfg.solver == SA_CG ? run_cg<TV>(q, v, ctl, b, x, maxit, st) : run_gmres<TV>(q, v, ctl, b, x, maxit, st);
+}
+
+// read (bnorm, relres0, relres) of a control block
+int read_norms(sa_seq *q, Ctl *ctl, double d[4], hipStream_t st) {
+  HIP_TRY(hipMemcpyAsync(d, &ctl->bnorm, 4 * sizeof(double), hipMemcpyDeviceToHost, st));
+  HIP_TRY(hipStreamSynchronize(st));
+  return SA_OK;
+}
+
+int status_of(int state) {
+  if (state == ST_MAXIT) return SA_NOTCONV;
+  if (state == ST_BREAK) return SA_EBREAKDOWN;
+  return SA_OK;
+}
+
+// Alg. 1 steps 2-3 on the device: Q1 = X T1, SpMM + Gram, reduced solve, x0 = Q1 c.
+template <typename TX>
+int guess_projection(sa_seq *q, const CsrView &v, const double *b, double *x0, int cnt, hipStream_t st) {
+  const sa_config &c = q->cfg;
+  int nblk = 0;
+  HIP_TRY(launch_basis<TX>((const TX *)q->X, (TX *)q->Q1, c.n, q->ld, cnt, q->ctl, st));
+  HIP_TRY(launch_spmm_gram<TX>(v, (const TX *)q->Q1, q->ld, b, cnt, 0, q->partials, &nblk, q->ctl, st));
+  HIP_TRY(launch_colsum(q->partials, nblk, cnt * (2 * cnt + 1), q->ctl, st));
+  HIP_TRY(launch_small_solve(cnt, 0, c.solver == SA_CG ? 1 : 0, q->tau_c, q->ctl, st));
+  HIP_TRY(launch_x0<TX>((const TX *)q->Q1, (const TX *)q->X, x0, c.n, q->ld, q->ctl, st));
   return SA_OK;
 }
 
@@ -168,44 +319,40 @@ int sa_init_sequence(const sa_config *cfg, void *dev_ws, size_t ws_bytes, void *
   sa_seq *q = new (std::nothrow) sa_seq();
   if (!q) return SA_ENOMEM;
   q->cfg = *cfg;
+  q->mixed = cfg->precision == SA_MIXED;
   if (q->cfg.poll <= 0) q->cfg.poll = 8;
   q->tau_s = cfg->rank_tol_sketch > 0.0 ? cfg->rank_tol_sketch : 1e-12;
   q->tau_c = cfg->rank_tol_chol > 0.0 ? cfg->rank_tol_chol : 1e-12;
   q->ws = (char *)dev_ws;
   q->ws_bytes = ws_bytes;
-  q->X = (double *)(q->ws + L.X);
+  q->ld = padded_ld(cfg->n);
+  q->X = q->ws + L.X;
   q->SX = (double *)(q->ws + L.SX);
-  q->Q1 = (double *)(q->ws + L.Q1);
-  q->kry = (double *)(q->ws + L.kry);
+  q->Q1 = q->ws + L.Q1;
+  q->kry = q->ws + L.kry;
   q->partials = (double *)(q->ws + L.partials);
   q->srht_rows = (long long *)(q->ws + L.rows);
-  bool ok = hipMalloc((void **)&q->ctl, sizeof(Ctl)) == hipSuccess &&
-            hipHostMalloc((void **)&q->hbuf, 64 * sizeof(int), hipHostMallocDefault) == hipSuccess;
+  if (q->mixed) {
+    q->r32 = (float *)(q->ws + L.r32);
+    q->d32 = (float *)(q->ws + L.d32);
+  }
+  bool ok = hipHostMalloc((void **)&q->hbuf, 64 * sizeof(int), hipHostMallocDefault) == hipSuccess;
   for (int e = 0; ok && e < 4; ++e) ok = hipEventCreate(&q->ev[e]) == hipSuccess;
+  if (ok) ok = init_ctl(&q->ctl, cfg->tol, cfg->maxit, cfg->restart, st) == SA_OK;
+  if (ok && q->mixed) ok = init_ctl(&q->ctl_in, cfg->inner_tol, cfg->maxit, cfg->restart, st) == SA_OK;
   if (!ok) {
     sa_destroy_sequence(q);
     return SA_EHIP;
   }
-  Ctl *h = new (std::nothrow) Ctl();
-  if (!h) {
-    sa_destroy_sequence(q);
-    return SA_ENOMEM;
-  }
-  memset((void *)h, 0, sizeof(Ctl));
-  h->tol = cfg->tol;
-  h->maxit = cfg->maxit;
-  h->restart = cfg->restart;
-  h->newest = -1;
-  h->state = ST_CONV;
   std::vector<long long> rows;
   if (cfg->sketch == SA_SKETCH_SRHT) srht_rows_host(cfg->n, cfg->s, cfg->seed, rows);
-  hipError_t e = hipMemcpyAsync(q->ctl, h, sizeof(Ctl), hipMemcpyHostToDevice, st);
-  if (e == hipSuccess && !rows.empty())
+  hipError_t e = hipSuccess;
+  if (!rows.empty())
     e = hipMemcpyAsync(q->srht_rows, rows.data(), rows.size() * sizeof(long long), hipMemcpyHostToDevice, st);
-  if (e == hipSuccess) e = hipMemsetAsync(q->X, 0, (size_t)cfg->n * cfg->M * sizeof(double), st);
+  const size_t w = q->mixed ? sizeof(float) : sizeof(double);
+  if (e == hipSuccess) e = hipMemsetAsync(q->X, 0, (size_t)q->ld * cfg->M * w, st);
   if (e == hipSuccess) e = hipMemsetAsync(q->SX, 0, (size_t)cfg->s * cfg->M * sizeof(double), st);
   if (e == hipSuccess) e = hipStreamSynchronize(st);
-  delete h;
   if (e != hipSuccess) {
     sa_destroy_sequence(q);
     return SA_EHIP;
@@ -220,8 +367,12 @@ int sa_push_solution(sa_seq *q, const void *x_dev, void *stream) {
   hipStream_t st = (hipStream_t)stream;
   const sa_config &c = q->cfg;
   const int slot = (int)(q->pushes % c.M);
-  HIP_TRY(launch_push((const double *)x_dev, q->X, q->SX, c.n, slot, c.s, c.sketch, c.seed, q->srht_rows,
-                      q->partials, q->ctl, st));
+  if (q->mixed)
+    HIP_TRY(launch_push<float>((const double *)x_dev, (float *)q->X, q->SX, c.n, q->ld, slot, c.s, c.sketch, c.seed,
+                               q->srht_rows, q->partials, q->ctl, st));
+  else
+    HIP_TRY(launch_push<double>((const double *)x_dev, (double *)q->X, q->SX, c.n, q->ld, slot, c.s, c.sketch,
+                                c.seed, q->srht_rows, q->partials, q->ctl, st));
   q->pushes += 1;
   HIP_TRY(launch_qrcp(q->SX, c.s, count(q), slot, q->tau_s, q->partials, c.n, q->ctl, st));
   return SA_OK;
@@ -241,15 +392,17 @@ int sa_initial_guess(sa_seq *q, const sa_csr *A, const void *b_dev, void *x0_dev
   if (cnt == 0 || c.guess == SA_GUESS_ZERO) {
     HIP_TRY(hipMemsetAsync(x0_dev, 0, nb, st));
   } else if (c.guess == SA_GUESS_PREVIOUS) {
-    HIP_TRY(hipMemcpyAsync(x0_dev, q->X + (size_t)newest * c.n, nb, hipMemcpyDeviceToDevice, st));
+    if (q->mixed)
+      HIP_TRY(launch_to_double<float>((const float *)q->X + (size_t)newest * q->ld, (double *)x0_dev, c.n, st));
+    else
+      HIP_TRY(hipMemcpyAsync(x0_dev, (const double *)q->X + (size_t)newest * q->ld, nb, hipMemcpyDeviceToDevice,
+                             st));
   } else {
     CsrView v = view(A);
-    int nblk = 0;
-    HIP_TRY(launch_basis(q->X, q->Q1, c.n, cnt, q->ctl, st));
-    HIP_TRY(launch_spmm_gram(v, q->Q1, (const double *)b_dev, cnt, 0, q->partials, &nblk, q->ctl, st));
-    HIP_TRY(launch_colsum(q->partials, nblk, cnt * (2 * cnt + 1), q->ctl, st));
-    HIP_TRY(launch_small_solve(cnt, 0, c.solver == SA_CG ? 1 : 0, q->tau_c, q->ctl, st));
-    HIP_TRY(launch_x0(q->Q1, q->X, (double *)x0_dev, c.n, q->ctl, st));
+    if (q->mixed)
+      SA_TRY(guess_projection<float>(q, v, (const double *)b_dev, (double *)x0_dev, cnt, st));
+    else
+      SA_TRY(guess_projection<double>(q, v, (const double *)b_dev, (double *)x0_dev, cnt, st));
   }
   if (info) {
     HIP_TRY(hipEventRecord(q->ev[1], st));
@@ -267,6 +420,44 @@ int sa_initial_guess(sa_seq *q, const sa_csr *A, const void *b_dev, void *x0_dev
   return SA_OK;
 }
 
+// Mixed mode: FP64 iterative refinement around FP32-stored inner solves of A32 d = r.
+static int solve_mixed(sa_seq *q, const CsrView &v, const double *b, double *x, int *iters, int *restarts,
+                       int *sweeps, hipStream_t st) {
+  const sa_config &c = q->cfg;
+  int *hs = q->hbuf;
+  *iters = *restarts = *sweeps = 0;
+  for (int sweep = 0;; ++sweep) {
+    HIP_TRY(launch_ir_resid(v, b, x, q->r32, q->partials, sweep, c.max_refine, q->ctl, st));
+    SA_TRY(poll(q, q->ctl, st));
+    const int outer = hs[0];
+    if (outer < ST_RUN || outer > ST_ZERO_RHS) return SA_EHIP;
+    if (outer != ST_RUN || *iters >= c.maxit) {
+      if (outer == ST_RUN) {  // iteration budget spent: report as not converged
+        const int st_maxit = ST_MAXIT;
+        HIP_TRY(hipMemcpyAsync(&q->ctl->state, &st_maxit, sizeof(int), hipMemcpyHostToDevice, st));
+        HIP_TRY(hipStreamSynchronize(st));
+        hs[0] = ST_MAXIT;
+      }
+      break;
+    }
+    // inner solve from d = 0 with the remaining iteration budget
+    hs[40] = c.maxit - *iters;
+    HIP_TRY(hipMemcpyAsync(&q->ctl_in->maxit, hs + 40, sizeof(int), hipMemcpyHostToDevice, st));
+    HIP_TRY(hipMemsetAsync(q->d32, 0, (size_t)c.n * sizeof(float), st));
+    SA_TRY(run_krylov<float>(q, v, q->ctl_in, q->r32, q->d32, c.maxit - *iters, st));
+    const int inner_state = hs[0];
+    *iters += hs[1];
+    *restarts += hs[2];
+    if (inner_state == ST_BREAK) {
+      hs[0] = ST_BREAK;
+      return SA_OK;
+    }
+    HIP_TRY(launch_ir_update(x, q->d32, c.n, st));
+    *sweeps = sweep + 1;
+  }
+  return SA_OK;
+}
+
 int sa_solve(sa_seq *q, const sa_csr *A, const void *b_dev, void *x_dev, sa_info *info, void *stream) {
   if (!q || !q->alive) return SA_ESTATE;
   int rc = check_csr(q, A);
@@ -280,79 +471,27 @@ int sa_solve(sa_seq *q, const sa_csr *A, const void *b_dev, void *x_dev, sa_info
   double *x = (double *)x_dev;
   if (info) HIP_TRY(hipEventRecord(q->ev[2], st));
   int *hs = q->hbuf;
-  if (c.solver == SA_CG) {
-    double *r = q->kry, *p = q->kry + n, *qq = q->kry + 2 * n;
-    int k = 0;             // iterations enqueued (device numbering, 1-based per iteration)
-    bool p_fresh = true;   // p = r: the next iteration needs no direction update
-    HIP_TRY(launch_cg_start_k(v, b, x, r, p, 0, k, q->partials, q->ctl, st));
-    if ((rc = poll(q, st)) != SA_OK) return rc;
-    // every pass either advances the device iteration count or leaves a final state;
-    // the bound only protects against a corrupted control block
-    const long long max_pass = (long long)c.maxit + 16;
-    for (long long pass = 0;; ++pass) {
-      if (pass > max_pass || hs[0] < ST_RUN || hs[0] > ST_ZERO_RHS) return SA_EHIP;
-      if (hs[0] == ST_RUN) {
-        for (int t = 0; t < c.poll && k < c.maxit; ++t) {
-          ++k;
-          HIP_TRY(launch_cg_iter_k(v, x, r, p, qq, k, p_fresh ? 0 : 1, t > 0 ? 1 : 0, q->partials, q->ctl, st));
-          p_fresh = false;
-        }
-        HIP_TRY(launch_cg_close_k(q->partials, n, k, q->ctl, st));
-        if ((rc = poll(q, st)) != SA_OK) return rc;
-        k = hs[1];  // iterations actually performed (later launches of the batch were no-ops)
-      }
-      if (hs[0] == ST_CHECK) {
-        HIP_TRY(launch_cg_start_k(v, b, x, r, p, 1, k, q->partials, q->ctl, st));
-        if ((rc = poll(q, st)) != SA_OK) return rc;
-        p_fresh = true;
-      }
-      if (hs[0] == ST_CONV || hs[0] == ST_ZERO_RHS) break;
-      if (hs[0] == ST_MAXIT || hs[0] == ST_BREAK) {
-        HIP_TRY(launch_cg_start_k(v, b, x, r, p, 2, k, q->partials, q->ctl, st));
-        if ((rc = poll(q, st)) != SA_OK) return rc;
-        break;
-      }
-    }
+  int iters = 0, restarts = 0, sweeps = 0;
+  if (q->mixed) {
+    SA_TRY(solve_mixed(q, v, b, x, &iters, &restarts, &sweeps, st));
   } else {
-    double *V = q->kry;
-    HIP_TRY(launch_gm_start(v, b, x, V, 0, q->partials, q->ctl, st));
-    if ((rc = poll(q, st)) != SA_OK) return rc;
-    long long cycles = 0;
-    int total = 0;  // Arnoldi steps performed so far
-    while (hs[0] == ST_RUN) {
-      if (++cycles > (long long)c.maxit + 16) return SA_EHIP;  // each cycle adds >= 1 iteration
-      int j = 0;
-      while (j < c.restart) {
-        for (int t = 0; t < c.poll && j < c.restart; ++t, ++j) {
-          ++total;
-          HIP_TRY(launch_gm_step_it(v, V, j, total, t > 0 ? 1 : 0, q->partials, q->ctl, st));
-        }
-        HIP_TRY(launch_gm_close_it(q->partials, n, j - 1, total, q->ctl, st));
-        if ((rc = poll(q, st)) != SA_OK) return rc;
-        if (!hs[4] || hs[0] != ST_RUN) break;
-      }
-      total = hs[1];
-      HIP_TRY(launch_gm_update(x, V, n, c.restart, q->ctl, st));
-      HIP_TRY(launch_gm_start(v, b, x, V, 1, q->partials, q->ctl, st));
-      if ((rc = poll(q, st)) != SA_OK) return rc;
-    }
+    SA_TRY(run_krylov<double>(q, v, q->ctl, b, x, c.maxit, st));
+    iters = hs[1];
+    restarts = hs[2];
   }
   const int state = hs[0];
   if (state < ST_RUN || state > ST_ZERO_RHS) return SA_EHIP;
   if (state == ST_ZERO_RHS) HIP_TRY(hipMemsetAsync(x, 0, (size_t)n * sizeof(double), st));
-  int ret = SA_OK;
-  if (state == ST_MAXIT) ret = SA_NOTCONV;
-  if (state == ST_BREAK) ret = SA_EBREAKDOWN;
+  const int ret = status_of(state);
   if (info) {
     HIP_TRY(hipEventRecord(q->ev[3], st));
     double d[4];  // bnorm, relres0, relres, tol
-    HIP_TRY(hipMemcpyAsync(d, &q->ctl->bnorm, sizeof(d), hipMemcpyDeviceToHost, st));
-    HIP_TRY(hipStreamSynchronize(st));
+    SA_TRY(read_norms(q, q->ctl, d, st));
     float ms = 0.f;
     HIP_TRY(hipEventElapsedTime(&ms, q->ev[2], q->ev[3]));
-    info->iters = hs[1];
-    info->restarts = hs[2];
-    info->refinements = 0;
+    info->iters = iters;
+    info->restarts = restarts;
+    info->refinements = sweeps;
     info->relres0 = d[1];
     info->relres = state == ST_ZERO_RHS ? 0.0 : d[2];
     info->status = ret;
@@ -365,6 +504,7 @@ int sa_destroy_sequence(sa_seq *q) {
   if (!q) return SA_EINVAL;
   q->alive = false;
   if (q->ctl) (void)hipFree(q->ctl);
+  if (q->ctl_in) (void)hipFree(q->ctl_in);
   if (q->hbuf) (void)hipHostFree(q->hbuf);
   for (int e = 0; e < 4; ++e)
     if (q->ev[e]) (void)hipEventDestroy(q->ev[e]);
@@ -396,13 +536,18 @@ int sa_copy_state(sa_seq *q, int what, void *host_dst, size_t bytes, void *strea
   if (!host_dst) return SA_EINVAL;
   hipStream_t st = (hipStream_t)stream;
   const sa_config &c = q->cfg;
+  const size_t w = q->mixed ? sizeof(float) : sizeof(double);
   if (what == 0 || what == 1 || what == 2) {
     size_t need = what == 0 ? (size_t)c.s * c.M * sizeof(double)
-                 : what == 1 ? (size_t)c.n * c.M * sizeof(double)
+                 : what == 1 ? (size_t)c.n * c.M * w
                              : (size_t)c.M * sizeof(double);
     if (bytes < need) return SA_EINVAL;
-    const void *src = what == 0 ? (const void *)q->SX : what == 1 ? (const void *)q->X : (const void *)q->ctl->cX;
-    HIP_TRY(hipMemcpyAsync(host_dst, src, need, hipMemcpyDeviceToHost, st));
+    if (what == 1)
+      HIP_TRY(hipMemcpy2DAsync(host_dst, (size_t)c.n * w, q->X, (size_t)q->ld * w, (size_t)c.n * w, (size_t)c.M,
+                               hipMemcpyDeviceToHost, st));
+    else
+      HIP_TRY(hipMemcpyAsync(host_dst, what == 0 ? (const void *)q->SX : (const void *)q->ctl->cX, need,
+                             hipMemcpyDeviceToHost, st));
     HIP_TRY(hipStreamSynchronize(st));
     return SA_OK;
   }

@@ -124,6 +124,39 @@ __device__ inline void final_sum(const double *partials, int nblk, int W, int kc
   }
 }
 
+// ---------------------------------------------------------------- CSR stream SpMV
+constexpr int SPMV_CAP = 4096;  // nonzeros of one row tile staged in LDS (32 KB)
+
+// (A x)_i for row i = r0 + threadIdx.x of the row tile [r0, r0 + blockDim.x) (0 beyond
+// n).  Every thread of the block must call it for the same r0.  The tile's val/col
+// are read with consecutive threads on consecutive nonzeros (coalesced) and the
+// products staged in LDS; each thread then sums its row in column order.  Tiles with
+// more than SPMV_CAP nonzeros read their rows directly.
+template <typename VT, typename TX>
+__device__ inline double tile_spmv(const int *__restrict__ rowptr, const int *__restrict__ col,
+                                   const VT *__restrict__ val, const TX *__restrict__ x, int64_t n,
+                                   int64_t r0, double *prod) {
+  const int t = threadIdx.x;
+  const int64_t i = r0 + t;
+  const int64_t rl = (r0 + (int64_t)blockDim.x < n) ? r0 + (int64_t)blockDim.x : n;
+  const int p0 = rowptr[r0], p1 = rowptr[rl];
+  int a = 0, b = 0;
+  if (i < n) {
+    a = rowptr[i];
+    b = rowptr[i + 1];
+  }
+  double s = 0.0;
+  if (p1 - p0 <= SPMV_CAP) {
+    for (int p = p0 + t; p < p1; p += blockDim.x) prod[p - p0] = (double)val[p] * (double)x[col[p]];
+    __syncthreads();
+    for (int p = a; p < b; ++p) s += prod[p - p0];
+    __syncthreads();
+  } else {
+    for (int p = a; p < b; ++p) s += (double)val[p] * (double)x[col[p]];
+  }
+  return s;
+}
+
 // ---------------------------------------------------------------- Philox4x64-10
 // Salmon, Moraes, Dror, Shaw, "Parallel random numbers: as easy as 1, 2, 3", SC'11.
 struct U64x4 {

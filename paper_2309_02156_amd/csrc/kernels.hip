@@ -44,7 +44,11 @@ __device__ inline void wave_sync() {
 template <typename VT>
 __global__ __launch_bounds__(TPB) void k_spmv(const int *rowptr, const int *col, const VT *val,
                                               const double *x, double *y, int64_t n) {
-  GRID_ROWS(i, n) y[i] = row_dot(rowptr, col, val, x, i);
+  __shared__ double prod[SPMV_CAP];
+  for (int64_t r0 = (int64_t)blockIdx.x * TPB; r0 < n; r0 += (int64_t)gridDim.x * TPB) {
+    const double s = tile_spmv(rowptr, col, val, x, n, r0, prod);
+    if (r0 + threadIdx.x < n) y[r0 + threadIdx.x] = s;
+  }
 }
 
 hipError_t launch_spmv(const CsrView &A, const double *x, double *y, hipStream_t st) {
@@ -61,8 +65,8 @@ hipError_t launch_spmv(const CsrView &A, const double *x, double *y, hipStream_t
 // ============================================================================ push + sketch
 // Grid (nbx, ceil(s / SKETCH_RG)): block row-group g accumulates rows [16 g, 16 g + 16)
 // of S x; group 0 also copies x into the history slot.  The last block reduces.
-template <int SK>
-__global__ __launch_bounds__(TPB) void k_push(const double *x, double *X, double *SX, int64_t n, int slot,
+template <int SK, typename TX>
+__global__ __launch_bounds__(TPB) void k_push(const double *x, TX *X, double *SX, int64_t n, int64_t ld, int slot,
                                               int s, uint64_t seed, const long long *rows,
                                               double *partials, Ctl *ctl) {
   __shared__ double red[NWAVE * SKETCH_RG];
@@ -79,8 +83,10 @@ __global__ __launch_bounds__(TPB) void k_push(const double *x, double *X, double
     for (int r = 0; r < SKETCH_RG; ++r) myrows[r] = (r < rc) ? rows[r0 + r] : 0;
   }
   GRID_ROWS(j, n) {
-    const double xj = x[j];
-    if (g == 0) X[(size_t)slot * n + j] = xj;
+    // the stored (possibly FP32-rounded) column is what gets sketched
+    const TX xs = (TX)x[j];
+    const double xj = (double)xs;
+    if (g == 0) X[(size_t)slot * ld + j] = xs;
     if (SK == 0) {
 #pragma unroll
       for (int q = 0; q < SKETCH_RG / 4; ++q) {
@@ -114,17 +120,17 @@ int push_blocks_x(int64_t n, int s) {
   return nbx;
 }
 
-hipError_t launch_push(const double *x, double *X, double *SX, int64_t n, int slot, int s, int sketch,
-                       uint64_t seed, const long long *srht_rows, double *partials, Ctl *ctl,
-                       hipStream_t st) {
+template <typename TX>
+hipError_t launch_push(const double *x, TX *X, double *SX, int64_t n, int64_t ld, int slot, int s, int sketch,
+                       uint64_t seed, const long long *srht_rows, double *partials, Ctl *ctl, hipStream_t st) {
   const int ng = (s + SKETCH_RG - 1) / SKETCH_RG;
   const int nbx = push_blocks_x(n, s);
   if (sketch == 0)
-    hipLaunchKernelGGL(k_push<0>, dim3(nbx, ng), dim3(TPB), 0, st, x, X, SX, n, slot, s, seed, srht_rows,
-                       partials, ctl);
+    hipLaunchKernelGGL((k_push<0, TX>), dim3(nbx, ng), dim3(TPB), 0, st, x, X, SX, n, ld, slot, s, seed,
+                       srht_rows, partials, ctl);
   else
-    hipLaunchKernelGGL(k_push<1>, dim3(nbx, ng), dim3(TPB), 0, st, x, X, SX, n, slot, s, seed, srht_rows,
-                       partials, ctl);
+    hipLaunchKernelGGL((k_push<1, TX>), dim3(nbx, ng), dim3(TPB), 0, st, x, X, SX, n, ld, slot, s, seed,
+                       srht_rows, partials, ctl);
   return hipGetLastError();
 }
 
@@ -281,8 +287,9 @@ hipError_t launch_qrcp(double *SX, int s, int cnt, int newest, double tau, const
 }
 
 // ============================================================================ basis Q1 = X T1
-template <int MC>
-__global__ __launch_bounds__(TPB) void k_basis(const double *X, double *Q1, int64_t n, int cnt, const Ctl *ctl) {
+template <int MC, typename TX>
+__global__ __launch_bounds__(TPB) void k_basis(const TX *X, TX *Q1, int64_t n, int64_t ld, int cnt,
+                                               const Ctl *ctl) {
   __shared__ double T[MC * MC];
   const int k = ctl->k;
   for (int e = threadIdx.x; e < MC * MC; e += blockDim.x) {
@@ -293,22 +300,23 @@ __global__ __launch_bounds__(TPB) void k_basis(const double *X, double *Q1, int6
   GRID_ROWS(i, n) {
     double xr[MC];
 #pragma unroll
-    for (int l = 0; l < MC; ++l) xr[l] = (l < cnt) ? X[(size_t)l * n + i] : 0.0;
+    for (int l = 0; l < MC; ++l) xr[l] = (l < cnt) ? (double)X[(size_t)l * ld + i] : 0.0;
     for (int c = 0; c < k; ++c) {
       double q = 0.0;
 #pragma unroll
       for (int l = 0; l < MC; ++l) q += xr[l] * T[l + c * MC];
-      Q1[(size_t)c * n + i] = q;
+      Q1[(size_t)c * ld + i] = (TX)q;
     }
   }
 }
 
-hipError_t launch_basis(const double *X, double *Q1, int64_t n, int cnt, Ctl *ctl, hipStream_t st) {
+template <typename TX>
+hipError_t launch_basis(const TX *X, TX *Q1, int64_t n, int64_t ld, int cnt, Ctl *ctl, hipStream_t st) {
   const int nb = stream_blocks(n);
   if (cnt <= 16)
-    hipLaunchKernelGGL(k_basis<16>, dim3(nb), dim3(TPB), 0, st, X, Q1, n, cnt, ctl);
+    hipLaunchKernelGGL((k_basis<16, TX>), dim3(nb), dim3(TPB), 0, st, X, Q1, n, ld, cnt, ctl);
   else
-    hipLaunchKernelGGL(k_basis<32>, dim3(nb), dim3(TPB), 0, st, X, Q1, n, cnt, ctl);
+    hipLaunchKernelGGL((k_basis<32, TX>), dim3(nb), dim3(TPB), 0, st, X, Q1, n, ld, cnt, ctl);
   return hipGetLastError();
 }
 
@@ -324,10 +332,10 @@ constexpr int GRAM_NW = GRAM_TPB / WAVE;
 constexpr int GRAM_LDT = WAVE + 1;
 constexpr int GRAM_MAXBLK = 768;
 
-template <typename VT, int MC>
+template <typename VT, int MC, typename TX>
 __global__ __launch_bounds__(GRAM_TPB) void k_spmm_gram(const int *rowptr, const int *col, const VT *val,
-                                                        const double *Q1, const double *b, int64_t n, int cnt,
-                                                        double *partials, const Ctl *ctl) {
+                                                        const TX *Q1, const double *b, int64_t n, int64_t ld,
+                                                        int cnt, double *partials, const Ctl *ctl) {
   extern __shared__ double lds[];
   constexpr int NA = MC / 16;
   constexpr int NB = (2 * MC + 1 + 15) / 16;
@@ -354,14 +362,14 @@ __global__ __launch_bounds__(GRAM_TPB) void k_spmm_gram(const int *rowptr, const
         const int64_t jc = col[p];
 #pragma unroll
         for (int c = 0; c < MC; ++c)
-          if (c < k) w[c] += av * Q1[(size_t)c * n + jc];
+          if (c < k) w[c] += av * (double)Q1[(size_t)c * ld + jc];
       }
     }
 #pragma unroll
     for (int c = 0; c < MC; ++c) {
       if (c < cnt) {
         const bool ok = (c < k) && (i < n);
-        T[c * GRAM_LDT + lane] = ok ? Q1[(size_t)c * n + i] : 0.0;
+        T[c * GRAM_LDT + lane] = ok ? (double)Q1[(size_t)c * ld + i] : 0.0;
         T[(cnt + c) * GRAM_LDT + lane] = ok ? w[c] : 0.0;
       }
     }
@@ -415,7 +423,8 @@ __global__ __launch_bounds__(GRAM_TPB) void k_spmm_gram(const int *rowptr, const
   }
 }
 
-hipError_t launch_spmm_gram(const CsrView &A, const double *Q1, const double *b, int cnt, int minres,
+template <typename TX>
+hipError_t launch_spmm_gram(const CsrView &A, const TX *Q1, int64_t ld, const double *b, int cnt, int minres,
                             double *partials, int *nblk_out, Ctl *ctl, hipStream_t st) {
   (void)minres;
   const int64_t ntiles = (A.n + WAVE - 1) / WAVE;
@@ -430,18 +439,18 @@ hipError_t launch_spmm_gram(const CsrView &A, const double *Q1, const double *b,
   *nblk_out = (int)nb;
   if (A.fp32) {
     if (mc == 16)
-      hipLaunchKernelGGL((k_spmm_gram<float, 16>), dim3(nb), dim3(GRAM_TPB), lds, st, A.rowptr, A.col,
-                         (const float *)A.val, Q1, b, A.n, cnt, partials, ctl);
+      hipLaunchKernelGGL((k_spmm_gram<float, 16, TX>), dim3(nb), dim3(GRAM_TPB), lds, st, A.rowptr, A.col,
+                         (const float *)A.val, Q1, b, A.n, ld, cnt, partials, ctl);
     else
-      hipLaunchKernelGGL((k_spmm_gram<float, 32>), dim3(nb), dim3(GRAM_TPB), lds, st, A.rowptr, A.col,
-                         (const float *)A.val, Q1, b, A.n, cnt, partials, ctl);
+      hipLaunchKernelGGL((k_spmm_gram<float, 32, TX>), dim3(nb), dim3(GRAM_TPB), lds, st, A.rowptr, A.col,
+                         (const float *)A.val, Q1, b, A.n, ld, cnt, partials, ctl);
   } else {
     if (mc == 16)
-      hipLaunchKernelGGL((k_spmm_gram<double, 16>), dim3(nb), dim3(GRAM_TPB), lds, st, A.rowptr, A.col,
-                         (const double *)A.val, Q1, b, A.n, cnt, partials, ctl);
+      hipLaunchKernelGGL((k_spmm_gram<double, 16, TX>), dim3(nb), dim3(GRAM_TPB), lds, st, A.rowptr, A.col,
+                         (const double *)A.val, Q1, b, A.n, ld, cnt, partials, ctl);
     else
-      hipLaunchKernelGGL((k_spmm_gram<double, 32>), dim3(nb), dim3(GRAM_TPB), lds, st, A.rowptr, A.col,
-                         (const double *)A.val, Q1, b, A.n, cnt, partials, ctl);
+      hipLaunchKernelGGL((k_spmm_gram<double, 32, TX>), dim3(nb), dim3(GRAM_TPB), lds, st, A.rowptr, A.col,
+                         (const double *)A.val, Q1, b, A.n, ld, cnt, partials, ctl);
   }
   return hipGetLastError();
 }
@@ -486,7 +495,9 @@ __global__ __launch_bounds__(TPB) void k_small_solve(int cnt, int spd, double ta
   double *Gm = sh;                  // k x k, ld k  (-> R2 in its leading k2 x k2, upper part)
   double *Ri = sh + (size_t)k * k;  // k2 x k2, ld k
   double *Hm = sh + (size_t)2 * k * k;  // k x k, ld k
-  const double *P = ctl->gram;
+  double *P = sh + (size_t)3 * cnt * cnt;  // LDS copy of the reduced Gram block (ld cnt)
+  for (int e = tid; e < cnt * (2 * cnt + 1); e += blockDim.x) P[e] = ctl->gram[e];
+  __syncthreads();
   if (k == 0) {
     for (int c = tid; c < MAXM; c += blockDim.x) {
       ctl->c[c] = 0.0;
@@ -707,15 +718,15 @@ __global__ __launch_bounds__(TPB) void k_small_solve(int cnt, int spd, double ta
 
 hipError_t launch_small_solve(int cnt, int minres, int spd, double tau_c, Ctl *ctl, hipStream_t st) {
   (void)minres;
-  size_t lds = (size_t)3 * cnt * cnt * sizeof(double);
+  size_t lds = ((size_t)3 * cnt * cnt + (size_t)cnt * (2 * cnt + 1)) * sizeof(double);
   if (lds == 0) lds = sizeof(double);
   hipLaunchKernelGGL(k_small_solve, dim3(1), dim3(TPB), lds, st, cnt, spd, tau_c, ctl);
   return hipGetLastError();
 }
 
 // ============================================================================ x0
-template <int MC>
-__global__ __launch_bounds__(TPB) void k_x0(const double *Q1, const double *X, double *x0, int64_t n,
+template <int MC, typename TX>
+__global__ __launch_bounds__(TPB) void k_x0(const TX *Q1, const TX *X, double *x0, int64_t n, int64_t ld,
                                             const Ctl *ctl) {
   __shared__ double cc[MC];
   const int k = ctl->k;
@@ -727,18 +738,112 @@ __global__ __launch_bounds__(TPB) void k_x0(const double *Q1, const double *X, d
   GRID_ROWS(i, n) {
     double s = 0.0;
     if (fb) {
-      s = (newest >= 0 && newest_ok) ? X[(size_t)newest * n + i] : 0.0;
+      s = (newest >= 0 && newest_ok) ? (double)X[(size_t)newest * ld + i] : 0.0;
     } else {
-      for (int c = 0; c < k; ++c) s += Q1[(size_t)c * n + i] * cc[c];
+      for (int c = 0; c < k; ++c) s += (double)Q1[(size_t)c * ld + i] * cc[c];
     }
     x0[i] = s;
   }
 }
 
-hipError_t launch_x0(const double *Q1, const double *X, double *x0, int64_t n, Ctl *ctl, hipStream_t st) {
-  hipLaunchKernelGGL(k_x0<MAXM>, dim3(stream_blocks(n)), dim3(TPB), 0, st, Q1, X, x0, n, ctl);
+template <typename TX>
+hipError_t launch_x0(const TX *Q1, const TX *X, double *x0, int64_t n, int64_t ld, Ctl *ctl, hipStream_t st) {
+  hipLaunchKernelGGL((k_x0<MAXM, TX>), dim3(stream_blocks(n)), dim3(TPB), 0, st, Q1, X, x0, n, ld, ctl);
   return hipGetLastError();
 }
+
+// y = (double) x  (the "previous solution" guess from an FP32 history column)
+template <typename TX>
+__global__ __launch_bounds__(TPB) void k_to_double(const TX *x, double *y, int64_t n) {
+  GRID_ROWS(i, n) y[i] = (double)x[i];
+}
+
+template <typename TX>
+hipError_t launch_to_double(const TX *x, double *y, int64_t n, hipStream_t st) {
+  hipLaunchKernelGGL(k_to_double<TX>, dim3(stream_blocks(n)), dim3(TPB), 0, st, x, y, n);
+  return hipGetLastError();
+}
+
+// ============================================================================ iterative refinement
+// Outer residual of the mixed mode: r = b - A32 x in FP64 (the FP32 matrix values are
+// exact in FP64), the inner right-hand side r32 = fl32(r), and partial sums of
+// ||r||^2 and ||b||^2.
+template <typename VT>
+__global__ __launch_bounds__(TPB) void k_ir_resid(const int *rowptr, const int *col, const VT *val,
+                                                  const double *b, const double *x, float *r32, int64_t n,
+                                                  double *partials) {
+  __shared__ double red[NWAVE * 2];
+  __shared__ double prod[SPMV_CAP];
+  double acc[2] = {0.0, 0.0};
+  for (int64_t r0 = (int64_t)blockIdx.x * TPB; r0 < n; r0 += (int64_t)gridDim.x * TPB) {
+    const double ax = tile_spmv(rowptr, col, val, x, n, r0, prod);
+    const int64_t i = r0 + threadIdx.x;
+    if (i < n) {
+      const double bi = b[i], ri = bi - ax;
+      r32[i] = (float)ri;
+      acc[0] += ri * ri;
+      acc[1] += bi * bi;
+    }
+  }
+  block_sum_store<2>(acc, 2, red, partials + (size_t)blockIdx.x * 2);
+}
+
+// One block: the outer stopping test ||r|| <= tol ||b|| (first sweep also sets ||b||
+// and relres0).  sweep = refinement sweeps done; state RUN means "refine again".
+__global__ __launch_bounds__(TPB) void k_ir_close(const double *partials, int nblk, int sweep, int max_refine,
+                                                  Ctl *ctl) {
+  __shared__ double outv[2];
+  __shared__ double scratch[TPB];
+  final_sum(partials, nblk, 2, 2, outv, scratch);
+  if (threadIdx.x != 0) return;
+  if (sweep == 0) ctl->bnorm = sqrt(outv[1]);
+  const double bn = ctl->bnorm, nr = sqrt(outv[0]);
+  const double rel = bn > 0.0 ? nr / bn : 0.0;
+  ctl->relres = rel;
+  if (sweep == 0) ctl->relres0 = rel;
+  if (bn == 0.0)
+    ctl->state = ST_ZERO_RHS;
+  else if (nr <= ctl->tol * bn)
+    ctl->state = ST_CONV;
+  else if (!isfinite(nr))
+    ctl->state = ST_BREAK;
+  else
+    ctl->state = sweep >= max_refine ? ST_MAXIT : ST_RUN;
+}
+
+__global__ __launch_bounds__(TPB) void k_ir_update(double *x, const float *d, int64_t n) {
+  GRID_ROWS(i, n) x[i] += (double)d[i];
+}
+
+hipError_t launch_ir_resid(const CsrView &A, const double *b, const double *x, float *r32, double *partials,
+                           int sweep, int max_refine, Ctl *ctl, hipStream_t st) {
+  const int nb = stream_blocks(A.n);
+  if (A.fp32)
+    hipLaunchKernelGGL(k_ir_resid<float>, dim3(nb), dim3(TPB), 0, st, A.rowptr, A.col, (const float *)A.val, b,
+                       x, r32, A.n, partials);
+  else
+    hipLaunchKernelGGL(k_ir_resid<double>, dim3(nb), dim3(TPB), 0, st, A.rowptr, A.col, (const double *)A.val,
+                       b, x, r32, A.n, partials);
+  hipLaunchKernelGGL(k_ir_close, dim3(1), dim3(TPB), 0, st, partials, nb, sweep, max_refine, ctl);
+  return hipGetLastError();
+}
+
+hipError_t launch_ir_update(double *x, const float *d, int64_t n, hipStream_t st) {
+  hipLaunchKernelGGL(k_ir_update, dim3(stream_blocks(n)), dim3(TPB), 0, st, x, d, n);
+  return hipGetLastError();
+}
+
+#define SACC_INSTANTIATE_PROJ(TX)                                                                              \
+  template hipError_t launch_push<TX>(const double *, TX *, double *, int64_t, int64_t, int, int, int, uint64_t, \
+                                      const long long *, double *, Ctl *, hipStream_t);                        \
+  template hipError_t launch_basis<TX>(const TX *, TX *, int64_t, int64_t, int, Ctl *, hipStream_t);           \
+  template hipError_t launch_spmm_gram<TX>(const CsrView &, const TX *, int64_t, const double *, int, int,    \
+                                           double *, int *, Ctl *, hipStream_t);                               \
+  template hipError_t launch_x0<TX>(const TX *, const TX *, double *, int64_t, int64_t, Ctl *, hipStream_t);   \
+  template hipError_t launch_to_double<TX>(const TX *, double *, int64_t, hipStream_t);
+
+SACC_INSTANTIATE_PROJ(double)
+SACC_INSTANTIATE_PROJ(float)
 
 size_t partials_doubles(int64_t n, int M, int s) {
   (void)n;

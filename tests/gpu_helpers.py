@@ -32,3 +32,25 @@ def relres(A, x, b) -> float:
 
 def print_case(*args):
     print("[case]", *args, flush=True)
+
+
+def reversed_order(A):
+    """The same CSR matrix with each row's entries stored (and summed) in reverse
+    order: a rounding-only perturbation of every product A x."""
+    import scipy.sparse as sp
+
+    A = A.tocsr()
+    ip = A.indptr
+    idx = np.concatenate([np.arange(ip[i + 1] - 1, ip[i] - 1, -1) for i in range(A.shape[0])]) \
+        if A.nnz else np.zeros(0, dtype=np.int64)
+    R = sp.csr_matrix((A.data[idx], A.indices[idx], ip), shape=A.shape)
+    R.has_canonical_format = False
+    return R
+
+
+def rounding_spread(solve, A, *args, **kw):
+    """(x, info, spread): the oracle's result and how far a rounding-only perturbation of
+    the same run (reversed summation order in A x) moves its iterate."""
+    x1, info = solve(A, *args, **kw)
+    x2, _ = solve(reversed_order(A), *args, **kw)
+    return x1, info, float(np.linalg.norm(x1 - x2))

@@ -27,7 +27,7 @@ from oracle import basis as obs
 from oracle import krylov as okr
 from oracle.sequence import Sequence as OSeq
 from oracle.sketch import Sketch
-from tests.gpu_helpers import dev, host, method_kwargs, print_case
+from tests.gpu_helpers import dev, host, method_kwargs, print_case, rounding_spread
 
 pytestmark = pytest.mark.gpu
 
@@ -217,13 +217,14 @@ def test_full_size_guess_and_one_cycle(sacc):
     Q = B.Q()
     r = b - As @ x0
     assert np.linalg.norm(Q.T @ r) <= 1e-10 * np.linalg.norm(b)
-    # one GMRES(30) cycle from the same start on both sides
-    xo, oinfo = okr.gmres(As, b, g.x0, m["tol"], 30, maxit=30)
+    # one GMRES(30) cycle from the same start on both sides; the bound is 10x the
+    # oracle's own rounding sensitivity (reversed summation order in A x)
+    xo, oinfo, spread = rounding_spread(okr.gmres, As, b, g.x0, m["tol"], 30, maxit=30)
     xd, sinfo = gseq.solve(Ad, dev(b), dev(g.x0))
     assert sinfo["iters"] == oinfo["iters"] == 30 and sinfo["rc"] == 1
     xg = host(xd)
-    assert np.linalg.norm(xg - xo) <= 1e-9 * np.linalg.norm(xo)
-    assert abs(sinfo["relres"] - oinfo["relres"]) <= 1e-6 * oinfo["relres"]
+    print_case("one cycle: diff / spread / |x|", np.linalg.norm(xg - xo), spread, np.linalg.norm(xo))
+    assert np.linalg.norm(xg - xo) <= 10 * max(spread, 1e-12 * np.linalg.norm(xo))
 
 
 # ---------------------------------------------------------------------------- edge cases
@@ -353,24 +354,23 @@ def test_m1_and_ring_wraparound(sacc):
 @pytest.mark.parametrize("N", [64, 256, 362, 512])
 @pytest.mark.parametrize("maxit", [1, 2, 8, 9, 17, 30])
 def test_gmres_iterates_match(sacc, N, maxit):
-    """GMRES(30) from x0 = 0 stopped after `maxit` Arnoldi steps: same iterate as the
-    oracle (exact arithmetic agrees; rounding differs), across one and two rows per thread
-    and across polled batches of 8 steps."""
+    """GMRES(30) from x0 = 0 stopped after `maxit` Arnoldi steps (one and two rows per
+    thread; inside and across polled batches of 8 steps): the iterate agrees with the
+    oracle's within 10x the oracle's own rounding sensitivity (its iterate under a
+    reversed summation order of A x), floored at 1e-12 relative."""
     print_case("gmres iterate", N, maxit)
     p, m = config(1, N)
     A = p.matrix(40)
     As = A.to_scipy()
     b = p.rhs(40)
-    xo, oinfo = okr.gmres(As, b, np.zeros(p.n), 1e-14, 30, maxit=maxit)
+    xo, oinfo, spread = rounding_spread(okr.gmres, As, b, np.zeros(p.n), 1e-14, 30, maxit=maxit)
     seq = sacc.Sequence(p.n, 2, s=4, solver="gmres", restart=30, tol=1e-14, maxit=maxit)
     xd, sinfo = seq.solve(sacc.DeviceCSR.from_csr(A), dev(b), dev(np.zeros(p.n)))
     xg = host(xd)
     assert sinfo["iters"] == oinfo["iters"] == maxit
-    err = np.linalg.norm(xg - xo) / np.linalg.norm(xo)
-    print_case("rel diff", err, sinfo["relres"], oinfo["relres"])
-    # modified vs classical-twice Gram-Schmidt on the CPU differ by <= 2.2e-11 up to 17
-    # steps and by up to 1.8e-7 at 30 steps on these operators (loss of orthogonality)
-    assert err <= (1e-9 if maxit <= 17 else 1e-6)
+    err = np.linalg.norm(xg - xo)
+    print_case("diff / spread / |x|", err, spread, np.linalg.norm(xo))
+    assert err <= 10 * max(spread, 1e-12 * np.linalg.norm(xo))
 
 
 @pytest.mark.parametrize("N", [64, 512])
@@ -381,11 +381,11 @@ def test_cg_iterates_match(sacc, N, maxit):
     A = p.matrix(3)
     As = A.to_scipy()
     b = p.rhs(3)
-    xo, oinfo = okr.cg(As, b, np.zeros(p.n), 1e-14, maxit=maxit)
+    xo, oinfo, spread = rounding_spread(okr.cg, As, b, np.zeros(p.n), 1e-14, maxit=maxit)
     seq = sacc.Sequence(p.n, 2, s=4, solver="cg", tol=1e-14, maxit=maxit)
     xd, sinfo = seq.solve(sacc.DeviceCSR.from_csr(A), dev(b), dev(np.zeros(p.n)))
     xg = host(xd)
     assert sinfo["iters"] == oinfo["iters"] == maxit
-    err = np.linalg.norm(xg - xo) / np.linalg.norm(xo)
-    print_case("rel diff", err)
-    assert err <= 1e-9
+    err = np.linalg.norm(xg - xo)
+    print_case("diff / spread / |x|", err, spread, np.linalg.norm(xo))
+    assert err <= 10 * max(spread, 1e-12 * np.linalg.norm(xo))
