@@ -44,7 +44,9 @@ extern "C" {
 
 /* ---- enumerations (stored as int32 in the structs) ----------------------------- */
 #define SA_FP64 0          /* every vector and reduction in float64                     */
-#define SA_MIXED 1         /* FP32 matrix/history/inner Krylov, FP64 refinement + small */
+#define SA_MIXED 1         /* float32 matrix values (val_is_fp32 = 1), history, basis and
+                              inner Krylov vectors; float64 arithmetic in registers, the
+                              small dense solves and the outer iterative refinement      */
 
 #define SA_CG 0            /* conjugate gradients (Hestenes-Stiefel), SPD A             */
 #define SA_GMRES 1         /* restarted GMRES(restart), classical Gram-Schmidt twice    */
@@ -62,17 +64,18 @@ extern "C" {
 /* ---- configuration ------------------------------------------------------------- */
 typedef struct {
   int64_t n;              /* system size                                              */
-  int32_t M;              /* history length (number of previous solutions kept), 1..64 */
-  int32_t s;              /* sketch rows, M <= s <= 256 (2M Gaussian, 4M SRHT typical) */
+  int32_t M;              /* history length (number of previous solutions kept), 1..32 */
+  int32_t s;              /* sketch rows, M <= s <= 256, s*M <= 8192; SRHT: s <= n     */
   int32_t sketch;         /* SA_SKETCH_*                                               */
-  int32_t projection;     /* SA_GALERKIN or SA_MINRES                                  */
+  int32_t projection;     /* SA_GALERKIN (SA_MINRES is rejected with SA_EINVAL)        */
   int32_t solver;         /* SA_CG or SA_GMRES                                         */
   int32_t restart;        /* GMRES restart length, 1..64                               */
   double tol;             /* stop when ||b - A x||_2 <= tol ||b||_2                   */
   int32_t maxit;          /* iteration cap (A-products for CG, Arnoldi steps GMRES)    */
   int32_t precision;      /* SA_FP64 or SA_MIXED                                       */
-  double inner_tol;       /* mixed: inner solve tolerance relative to current residual */
-  int32_t max_refine;     /* mixed: cap on refinement sweeps                           */
+  double inner_tol;       /* mixed: inner solve tolerance relative to the current
+                             residual, in (0, 1)                                      */
+  int32_t max_refine;     /* mixed: cap on refinement sweeps, >= 1                     */
   int32_t guess;          /* SA_GUESS_*                                                */
   double rank_tol_sketch; /* QRCP truncation |R_jj| > tau |R_11| (<= 0: default)      */
   double rank_tol_chol;   /* pivoted-Cholesky truncation relative to max diag (<= 0: default) */
@@ -121,7 +124,8 @@ int sa_init_sequence(const sa_config *cfg, void *dev_ws, size_t ws_bytes, void *
 
 /* Append the solution x(t_{i-1}) to the history, dropping the oldest one when M are
  * held (the sliding window of Section 2.1), and sketch it (S x) for the next QR.
- * x_dev: n values, float64 (SA_FP64) or float64 as well in SA_MIXED (stored as FP32).
+ * x_dev: n float64 values; SA_MIXED stores them rounded to float32 and sketches the
+ * stored values.
  * Asynchronous.  Errors: SA_EINVAL (null), SA_ESTATE (destroyed sequence). */
 int sa_push_solution(sa_seq *q, const void *x_dev, void *stream);
 
@@ -137,6 +141,9 @@ int sa_initial_guess(sa_seq *q, const sa_csr *A, const void *b_dev, void *x0_dev
 /* Krylov solve of A x = b from the iterate in x_dev (Alg. 1 step 4): CG or GMRES per
  * the config, stopping on ||b - A x||_2 <= tol ||b||_2 checked before the first
  * iteration and confirmed with the true residual.  x_dev: float64, in = x0, out = x.
+ * SA_MIXED: A must carry float32 values; each refinement sweep forms r = b - A x in
+ * float64, stops on the test above, else solves A d = fl32(r) with float32-stored
+ * vectors to inner_tol and updates x += d (iters sums the inner iterations).
  * Waits for the stream; fills info if non-NULL (iters, restarts, refinements,
  * relres0, relres, status, ms_solve).  Returns SA_OK, SA_NOTCONV or an error code. */
 int sa_solve(sa_seq *q, const sa_csr *A, const void *b_dev, void *x_dev, sa_info *info,
@@ -155,7 +162,8 @@ int sa_spmv(const sa_csr *A, const void *x_dev, void *y_dev, void *stream);
 
 /* Copy internal state to host memory for inspection:
  *   what = 0: SX, s x M float64 column-major, columns in ring-slot order;
- *   what = 1: X, n x M float64 column-major (SA_FP64) in ring-slot order;
+ *   what = 1: X, n x M column-major in ring-slot order, float64 (SA_FP64) or
+ *             float32 (SA_MIXED);
  *   what = 2: coefficients c of the last guess in history (ring-slot) coordinates,
  *             M float64 (x0 = X c);
  *   what = 3: ring order, M int32: slot of the oldest .. newest column (-1 unused).

@@ -110,12 +110,13 @@ class Basis:
 
 
 def sketched_basis(X: np.ndarray, SX: np.ndarray, Z: np.ndarray | None = None,
-                   tau_s: float = 1e-12, tau_c: float = 1e-12) -> Basis:
+                   tau_s: float = 1e-12, tau_c: float = 1e-12, store=None) -> Basis:
     """Alg. 1 step 2 with the randomized range finder and a sketched QR.
 
     X is the n x M history, SX = S X its sketch (s x M), Z the M x m range-finder
-    matrix (None means Z = I).  Parity: pinned by the plain-definition, orthonormality
-    and basis-invariance tests.
+    matrix (None means Z = I).  ``store`` rounds Q1 where it is written to memory (the
+    identity in FP64; float32 in the mixed mode), before its Gram matrix is formed.
+    Parity: pinned by the plain-definition, orthonormality and basis-invariance tests.
     """
     M = X.shape[1]
     Y = SX if Z is None else SX @ Z
@@ -131,6 +132,8 @@ def sketched_basis(X: np.ndarray, SX: np.ndarray, Z: np.ndarray | None = None,
         R11inv = sla.solve_triangular(R[:k, :k], np.eye(k))
         T1 = Zm[:, perm[:k]] @ R11inv
     Q1 = X @ T1
+    if store is not None:
+        Q1 = store(Q1)
     G = Q1.T @ Q1
     R2, perm2, k2 = pivoted_cholesky(G, tau_c)
     return Basis(T1, Q1, k, R2, perm2, k2)
@@ -180,19 +183,19 @@ def reduced_solve(A, b: np.ndarray, B: Basis, projection: str = "galerkin",
 
 
 def initial_guess(A, b, X, SX, Z=None, projection="galerkin", spd=True,
-                  tau_s=1e-12, tau_c=1e-12) -> Guess:
+                  tau_s=1e-12, tau_c=1e-12, store=None) -> Guess:
     """x0 of Alg. 1 from a history X (n x M, any column order) and its sketch SX.
 
     Empty or rank-zero history gives x0 = 0.  A non-finite sketch or reduced solution
     falls back to the newest history column (the paper's "Baseline" guess, Section 4),
     which the caller passes as the last column of X, or to 0 if that column is not
-    finite either.
+    finite either.  ``store`` as in ``sketched_basis``.
     """
     n, M = X.shape
     if M == 0:
         return Guess(np.zeros(n), 0, 0, np.zeros(0), np.zeros(0), False)
     if np.all(np.isfinite(SX)):
-        B = sketched_basis(X, SX, Z, tau_s, tau_c)
+        B = sketched_basis(X, SX, Z, tau_s, tau_c, store)
         c = reduced_solve(A, b, B, projection, spd) if np.all(np.isfinite(B.Q1)) else None
         x0 = B.Q1 @ c if c is not None else None
         if x0 is not None and np.all(np.isfinite(x0)):

@@ -8,6 +8,11 @@ sketched matrix S X never needs a pass over X.
 
 Guess kinds: "projection" (the method), "zero" (x0 = 0) and "previous" (x0 = x(t_{i-1}),
 the paper's Baseline of Sections 4 and 5).
+
+Precision "fp64" (the paper's setting) or "mixed" (not in the paper): the history and
+the basis Q1 are stored in float32 (the sketch is taken of the stored column), the
+matrix carries float32 values, and each system is solved by FP64 iterative refinement
+around float32-stored inner Krylov solves (``mixed.solve_ir``).
 """
 
 from __future__ import annotations
@@ -18,6 +23,7 @@ import numpy as np
 
 from . import basis as bs
 from . import krylov as kr
+from . import mixed as mx
 from .sketch import Sketch
 
 
@@ -25,13 +31,18 @@ class Sequence:
     def __init__(self, n: int, M: int, sketch: str = "gaussian", s: int | None = None,
                  seed: int = 0, solver: str = "cg", restart: int = 30, tol: float = 1e-8,
                  maxit: int = 200000, projection: str = "galerkin", tau_s: float = 1e-12,
-                 tau_c: float = 1e-12, m: int | None = None, guess: str = "projection"):
+                 tau_c: float = 1e-12, m: int | None = None, guess: str = "projection",
+                 precision: str = "fp64", inner_tol: float = 1e-4, max_refine: int = 10):
         self.n, self.M = n, M
         self.m = M if m is None else m
         self.s = 2 * M if s is None else s
         self.solver, self.restart, self.tol, self.maxit = solver, restart, tol, maxit
         self.projection, self.tau_s, self.tau_c, self.guess = projection, tau_s, tau_c, guess
         self.seed = seed
+        if precision not in ("fp64", "mixed"):
+            raise ValueError(precision)
+        self.precision, self.inner_tol, self.max_refine = precision, inner_tol, max_refine
+        self.store = mx.fl32 if precision == "mixed" else None
         self.S = Sketch(sketch, n, self.s, seed)
         self.cols: list[np.ndarray] = []
         self.scols: list[np.ndarray] = []
@@ -40,6 +51,8 @@ class Sequence:
     # ------------------------------------------------------------------ history
     def push(self, x: np.ndarray):
         x = np.array(x, dtype=np.float64, copy=True)
+        if self.store is not None:
+            x = self.store(x)
         self.cols.append(x)
         self.scols.append(self.S.apply(x))
         if len(self.cols) > self.M:
@@ -66,9 +79,13 @@ class Sequence:
         if self.Z is not None:
             Z = self.Z[self.M - k_h:, :] if k_h < self.M else self.Z
         return bs.initial_guess(A, b, X, SX, Z, self.projection, self.solver == "cg",
-                                self.tau_s, self.tau_c)
+                                self.tau_s, self.tau_c, self.store)
 
     def solve(self, A, b, x0):
+        """Krylov solve from x0; in the mixed mode A must carry float32 values."""
+        if self.precision == "mixed":
+            return mx.solve_ir(A, b, x0, self.tol, self.solver, self.restart, self.inner_tol,
+                               self.max_refine, self.maxit)
         if self.solver == "cg":
             return kr.cg(A, b, x0, self.tol, self.maxit)
         return kr.gmres(A, b, x0, self.tol, self.restart, self.maxit)

@@ -82,6 +82,7 @@ class Sequence:
                  stream=None):
         self.n, self.M = n, M
         self.s = 2 * M if s is None else s
+        self.precision = precision
         self.cfg = nv.SaConfig(
             n=n, M=M, s=self.s, sketch=_SKETCH[sketch], projection=_PROJ[projection],
             solver=_SOLVER[solver], restart=restart, tol=tol, maxit=maxit,
@@ -150,8 +151,8 @@ class Sequence:
         if what == "SX":
             out = np.empty((self.M, self.s), dtype=np.float64)
             code = 0
-        elif what == "X":
-            out = np.empty((self.M, self.n), dtype=np.float64)
+        elif what == "X":   # float32 storage in the mixed mode
+            out = np.empty((self.M, self.n), dtype=np.float32 if self.precision == "mixed" else np.float64)
             code = 1
         elif what == "cX":
             out = np.empty(self.M, dtype=np.float64)
