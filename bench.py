@@ -43,10 +43,13 @@ def assemble(problem, steps):
     return np.stack(vals), np.stack(rhs)
 
 
-def run_sequence(sacc, torch, A, vals_d, rhs_d, method, steps, warmup, guess="projection"):
-    """Run warmup + steps; returns per-step infos of the timed steps and the wall time."""
+def run_sequence(sacc, torch, A, vals_d, rhs_d, method, steps, warmup, guess="projection", precision="fp64",
+                 profile=False):
+    """Run warmup + steps; returns per-step infos of the timed steps, the wall time and
+    (profile=True) the kernel timing records of the timed steps."""
     seq = sacc.Sequence(A.n, method["M"], s=method["s"], sketch=method["sketch"], solver=method["solver"],
-                        restart=method["restart"], tol=method["tol"], seed=method["method_seed"], guess=guess)
+                        restart=method["restart"], tol=method["tol"], seed=method["method_seed"], guess=guess,
+                        precision=precision)
     x = torch.empty(A.n, dtype=torch.float64, device="cuda")
     infos = []
 
@@ -60,13 +63,19 @@ def run_sequence(sacc, torch, A, vals_d, rhs_d, method, steps, warmup, guess="pr
 
     for i in range(warmup):
         step(i)
+        if (i + 1) % 25 == 0:
+            log(f"  warmup step {i + 1}/{warmup}")
+    if profile:
+        seq.profile_enable(True)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for i in range(warmup, warmup + steps):
         infos.append(step(i))
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
-    return infos, wall
+    prof = seq.profile_read() if profile else None
+    seq.close()
+    return infos, wall, prof
 
 
 def spmv_gbps(sacc, torch, A, reps=200):
@@ -158,19 +167,43 @@ def main():
     torch.cuda.synchronize()
 
     log("timed run: projection")
-    infos, wall = run_sequence(sacc, torch, A, vals_d, rhs_d, method, args.steps, args.warmup)
+    infos, wall, _ = run_sequence(sacc, torch, A, vals_d, rhs_d, method, args.steps, args.warmup)
     ms_step = 1e3 * wall / args.steps
     iters = [d["iters"] for d in infos]
     relres = [d["relres"] for d in infos]
     log(f"ms/step {ms_step:.3f}, iters/step {np.mean(iters):.2f}")
+    log("iters per step:", " ".join(str(i) for i in iters))
+
+    # the same steps again with HIP events around each launch of the dominant kernels
+    log("instrumented run (per-kernel HIP events)")
+    _, pwall, prof = run_sequence(sacc, torch, A, vals_d, rhs_d, method, args.steps, args.warmup, profile=True)
+    dom = max(prof, key=lambda r: r["ms"])
+    dom_us = 1e3 * dom["ms"] / dom["launches"]
+    dom_gbs = dom["bytes"] / (dom["ms"] * 1e-3) / 1e9
+    for r in sorted(prof, key=lambda r: -r["ms"]):
+        log(f"  {r['name']}: {r['launches']} launches, {1e3 * r['ms'] / r['launches']:.2f} us avg, "
+            f"{r['bytes'] / (r['ms'] * 1e-3) / 1e9:.0f} GB/s")
 
     comparators = {}
     if not args.no_comparators:
         for kind in ("previous",):
             log("comparator run:", kind)
-            ci, cw = run_sequence(sacc, torch, A, vals_d, rhs_d, method, args.steps, args.warmup, guess=kind)
+            ci, cw, _ = run_sequence(sacc, torch, A, vals_d, rhs_d, method, args.steps, args.warmup, guess=kind)
             comparators[kind] = dict(ms_per_step=1e3 * cw / args.steps,
                                      iters_per_step=float(np.mean([d["iters"] for d in ci])))
+        # mixed precision on the same sequence with float32 matrix values
+        log("comparator run: mixed")
+        A32 = sacc.DeviceCSR(rowptr, col, vals[0].astype(np.float32))
+        vals32_d = vals_d.float()
+        ci, cw, _ = run_sequence(sacc, torch, A32, vals32_d, rhs_d, method, args.steps, args.warmup,
+                                 precision="mixed")
+        comparators["mixed"] = dict(ms_per_step=1e3 * cw / args.steps,
+                                    iters_per_step=float(np.mean([d["iters"] for d in ci])),
+                                    refinements_per_step=float(np.mean([d["refinements"] for d in ci])),
+                                    relres_max=float(max(d["relres"] for d in ci)),
+                                    note="float32 values, history, basis and inner Krylov vectors; "
+                                         "FP64 refinement to the same 1e-8 (against the float32 operator)")
+        del A32, vals32_d
 
     gbs, spmv_ms, spmv_bytes = spmv_gbps(sacc, torch, A)
     log(f"SpMV {gbs:.0f} GB/s ({spmv_ms * 1e3:.1f} us)")
@@ -200,8 +233,10 @@ def main():
         "relres_max": float(max(relres)),
         "spmv_gbps": round(gbs, 1),
         "comparators": comparators,
-        "roofline": {"bound": "hbm", "achieved": round(gbs, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": round(gbs / HBM_PEAK_GBS, 4), "traffic": None, "kernel": "spmv"},
+        "roofline": {"bound": "hbm", "achieved": round(dom_gbs, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": round(dom_gbs / HBM_PEAK_GBS, 4), "traffic": None, "kernel": dom["name"],
+                     "avg_us": round(dom_us, 3), "launches": dom["launches"],
+                     "instrumented_ms_per_step": round(1e3 * pwall / args.steps, 4)},
         "cpu_baseline": cpu,
     }
     print(json.dumps(out), flush=True)

@@ -81,7 +81,8 @@ typedef struct {
   double rank_tol_chol;   /* pivoted-Cholesky truncation relative to max diag (<= 0: default) */
   uint64_t seed;          /* key of the sketch's random entries                        */
   int32_t poll;           /* Krylov iterations enqueued between host convergence polls (<= 0: default) */
-  int32_t reserved;
+  int32_t inner_maxit;    /* mixed: iteration cap of one inner solve (<= 0: 10 GMRES
+                             cycles, or 1000 CG iterations)                          */
 } sa_config;
 
 typedef struct {
@@ -108,6 +109,14 @@ typedef struct {
   float ms_guess;        /* device time of the last initial guess                     */
   float ms_solve;        /* device time of the last solve                             */
 } sa_info;
+
+/* Timing record of one kernel (sa_profile_read). */
+typedef struct {
+  char name[48];     /* kernel and template arguments, e.g. "k_gm_f<double, double, 32>" */
+  int64_t launches;  /* launches that did their work (early-exit launches excluded)      */
+  double ms;         /* summed device time between HIP events around each launch        */
+  double bytes;      /* summed algorithmic HBM bytes (each operand byte counted once)     */
+} sa_kernel_prof;
 
 typedef struct sa_seq sa_seq;
 
@@ -143,7 +152,9 @@ int sa_initial_guess(sa_seq *q, const sa_csr *A, const void *b_dev, void *x0_dev
  * iteration and confirmed with the true residual.  x_dev: float64, in = x0, out = x.
  * SA_MIXED: A must carry float32 values; each refinement sweep forms r = b - A x in
  * float64, stops on the test above, else solves A d = fl32(r) with float32-stored
- * vectors to inner_tol and updates x += d (iters sums the inner iterations).
+ * vectors until the solver's own residual estimate is below inner_tol ||fl32(r)|| (no
+ * true-residual confirmation: the next sweep's residual checks the result) or
+ * inner_maxit iterations, and updates x += d (iters sums the inner iterations).
  * Waits for the stream; fills info if non-NULL (iters, restarts, refinements,
  * relres0, relres, status, ms_solve).  Returns SA_OK, SA_NOTCONV or an error code. */
 int sa_solve(sa_seq *q, const sa_csr *A, const void *b_dev, void *x_dev, sa_info *info,
@@ -159,6 +170,18 @@ const char *sa_status_string(int code);
  * float64, length n; A values float64 or float32.  Asynchronous.
  * Errors: SA_EINVAL, SA_EHIP. */
 int sa_spmv(const sa_csr *A, const void *x_dev, void *y_dev, void *stream);
+
+/* Measurement of the Krylov solve's dominant kernels (the SpMV-carrying kernel of
+ * each GMRES Arnoldi step and of each CG iteration): with enable = 1, every later
+ * sa_solve records HIP events on its stream around each launch of those kernels and
+ * keeps the launches that did their work, with their algorithmic bytes.  Enabling
+ * (or disabling) clears the records.  Adds an event pair per launch; intended for
+ * measurement runs.  Errors: SA_ESTATE, SA_EHIP. */
+int sa_profile_enable(sa_seq *q, int enable);
+
+/* Copy up to max records to out; *count = number of records held.
+ * Errors: SA_ESTATE, SA_EINVAL. */
+int sa_profile_read(sa_seq *q, sa_kernel_prof *out, int max, int *count);
 
 /* Copy internal state to host memory for inspection:
  *   what = 0: SX, s x M float64 column-major, columns in ring-slot order;

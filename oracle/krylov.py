@@ -12,6 +12,10 @@ confirmation fails the solver continues from the true residual.
   matrix, |g_{j+1}| as the residual estimate, restart from the true residual.  One
   iteration = one Arnoldi step; the count sums over restarts.
 
+``confirm=False`` (inner solves of the mixed mode) accepts the recursive estimate:
+CG stops on its recursive residual and GMRES after the cycle whose estimate met the
+tolerance, without the true-residual check.
+
 ``store`` models where a vector is written to memory: every vector the solver keeps
 (x, r, p, q; the Arnoldi vectors) passes through it.  It is the identity for FP64 runs
 and a round trip through float32 for the inner solves of the mixed mode (all
@@ -37,7 +41,7 @@ def _identity(v):
     return v
 
 
-def cg(A, b, x0, tol: float, maxit: int = 100000, store=None):
+def cg(A, b, x0, tol: float, maxit: int = 100000, store=None, confirm: bool = True):
     """Hestenes-Stiefel conjugate gradients from x0."""
     st = _identity if store is None else store
     b = np.asarray(b, dtype=np.float64)
@@ -67,6 +71,9 @@ def cg(A, b, x0, tol: float, maxit: int = 100000, store=None):
         rho_new = float(np.dot(r, r))
         it += 1
         if np.sqrt(rho_new) <= thresh:
+            if not confirm:
+                status = CONVERGED
+                break
             r = st(b - A @ x)
             rho = float(np.dot(r, r))
             if np.sqrt(rho) <= thresh:
@@ -91,7 +98,8 @@ def givens(a: float, b: float):
     return a / rho, b / rho, rho
 
 
-def gmres(A, b, x0, tol: float, restart: int = 30, maxit: int = 100000, store=None):
+def gmres(A, b, x0, tol: float, restart: int = 30, maxit: int = 100000, store=None,
+          confirm: bool = True):
     """Restarted GMRES(restart) with modified Gram-Schmidt Arnoldi and Givens rotations."""
     st = _identity if store is None else store
     b = np.asarray(b, dtype=np.float64)
@@ -145,7 +153,7 @@ def gmres(A, b, x0, tol: float, restart: int = 30, maxit: int = 100000, store=No
         r = st(b - A @ x)
         beta = _norm(r)
         cycles += 1
-        if beta <= thresh:
+        if beta <= thresh or (not confirm and abs(g[jend]) <= thresh and np.isfinite(beta)):
             status = CONVERGED
         elif not np.isfinite(beta):
             status = BREAKDOWN

@@ -4,9 +4,12 @@ Not in the paper.  The system solved is A32 = fl32(A) (the FP32 matrix values ar
 exact in FP64).  Each sweep forms the true residual r = b - A32 x in FP64 and stops when
 ||r|| <= tol ||b||; otherwise it solves A32 d = fl32(r) with CG or GMRES whose vectors
 are stored in FP32 (``fl32`` at every store, FP64 arithmetic between stores) to the
-inner tolerance relative to ||fl32(r)||, and updates x += d in FP64.  The iteration
-count is the sum of the inner iterations; the refinement count is the number of
-sweeps that ran an inner solve.
+inner tolerance relative to ||fl32(r)|| as judged by the solver's own recursive
+estimate (no true-residual confirmation: the next sweep's FP64 residual is the check),
+or at most ``inner_maxit`` iterations (default 10 GMRES cycles or 1000 CG iterations,
+since float32 storage can keep the inner residual above the inner tolerance), and
+updates x += d in FP64.  The iteration count is the sum of the inner iterations; the
+refinement count is the number of sweeps that ran an inner solve.
 
 Parity: the rounding points follow the description above; the iteration counts are
 checked against the HIP path within one per step and the final residual against the
@@ -25,8 +28,15 @@ def fl32(v) -> np.ndarray:
     return np.asarray(v, dtype=np.float32).astype(np.float64)
 
 
+def inner_cap(solver: str, restart: int, inner_maxit: int = 0) -> int:
+    if inner_maxit > 0:
+        return inner_maxit
+    return 10 * restart if solver == "gmres" else 1000
+
+
 def solve_ir(A32, b, x0, tol: float, solver: str = "cg", restart: int = 30,
-             inner_tol: float = 1e-4, max_refine: int = 10, maxit: int = 100000):
+             inner_tol: float = 1e-4, max_refine: int = 10, maxit: int = 100000,
+             inner_maxit: int = 0):
     b = np.asarray(b, dtype=np.float64)
     x = np.array(x0, dtype=np.float64, copy=True)
     bnorm = float(np.linalg.norm(b))
@@ -52,10 +62,12 @@ def solve_ir(A32, b, x0, tol: float, solver: str = "cg", restart: int = 30,
         if sweep == max_refine or iters >= maxit:
             break
         r32 = fl32(r)
+        cap = min(maxit - iters, inner_cap(solver, restart, inner_maxit))
         if solver == "cg":
-            d, info = kr.cg(A32, r32, np.zeros_like(b), inner_tol, maxit - iters, store=fl32)
+            d, info = kr.cg(A32, r32, np.zeros_like(b), inner_tol, cap, store=fl32, confirm=False)
         else:
-            d, info = kr.gmres(A32, r32, np.zeros_like(b), inner_tol, restart, maxit - iters, store=fl32)
+            d, info = kr.gmres(A32, r32, np.zeros_like(b), inner_tol, restart, cap, store=fl32,
+                               confirm=False)
         iters += info["iters"]
         restarts += info["restarts"]
         if info["status"] == kr.BREAKDOWN:

@@ -6,12 +6,24 @@
 #include <string.h>
 
 #include <new>
+#include <string>
 #include <vector>
 
 #include "../../include/sacc.h"
 #include "kernels.h"
 
 using namespace sacc;
+
+// Per-kernel timing of the dominant Krylov kernels (sa_profile_enable): HIP events
+// around each launch, kept only for launches that logged real work.
+struct KernelProfile {
+  bool on = false;
+  std::vector<hipEvent_t> ev;  // two per timed launch
+  std::vector<int> cls;        // record index per timed launch
+  std::vector<double> bytes;   // algorithmic bytes per timed launch
+  int n = 0;                   // timed launches of the current solve
+  std::vector<sa_kernel_prof> rec;
+};
 
 struct sa_seq {
   sa_config cfg;
@@ -30,6 +42,8 @@ struct sa_seq {
   int64_t ld = 0;  // leading dimension of X, Q1 and the Krylov vectors
   double tau_s = 1e-12, tau_c = 1e-12;
   hipEvent_t ev[4] = {nullptr, nullptr, nullptr, nullptr};
+  hipEvent_t evp[2] = {nullptr, nullptr};  // look-ahead poll slots
+  KernelProfile prof;
   bool alive = true;
 };
 
@@ -114,7 +128,8 @@ Layout layout(const sa_config *c) {
   L.Q1 = off;
   off += up(ld * M * w);
   L.kry = off;
-  const size_t kv = c->solver == SA_GMRES ? (size_t)(c->restart + 1) : 3;
+  // GMRES: V (restart + 1 columns) and a scratch column; CG: r, two p, q
+  const size_t kv = c->solver == SA_GMRES ? (size_t)(c->restart + 2) : 4;
   off += up(ld * kv * w);
   L.partials = off;
   off += up(partials_doubles(c->n, c->M, c->s) * sizeof(double));
@@ -170,7 +185,7 @@ int poll(sa_seq *q, Ctl *ctl, hipStream_t st) {
   return SA_OK;
 }
 
-int init_ctl(Ctl **out, double tol, int maxit, int restart, hipStream_t st) {
+int init_ctl(Ctl **out, double tol, int maxit, int restart, int trust_est, hipStream_t st) {
   Ctl *d = nullptr;
   if (hipMalloc((void **)&d, sizeof(Ctl)) != hipSuccess) return SA_EHIP;
   Ctl *h = new (std::nothrow) Ctl();
@@ -182,6 +197,7 @@ int init_ctl(Ctl **out, double tol, int maxit, int restart, hipStream_t st) {
   h->tol = tol;
   h->maxit = maxit;
   h->restart = restart;
+  h->trust_est = trust_est;
   h->newest = -1;
   h->state = ST_CONV;
   hipError_t e = hipMemcpyAsync(d, h, sizeof(Ctl), hipMemcpyHostToDevice, st);
@@ -198,72 +214,165 @@ int init_ctl(Ctl **out, double tol, int maxit, int restart, hipStream_t st) {
 // ---------------------------------------------------------------------------- Krylov host loops
 // CG on control block `ctl` for A x = b from the iterate in x; final state in q->hbuf[0],
 // iterations in q->hbuf[1], restarts in q->hbuf[2].
+// ---- kernel timing
+constexpr int PROF_LAUNCHES = 1024;
+
+int prof_class(sa_seq *q, const std::string &name) {
+  auto &rec = q->prof.rec;
+  for (size_t i = 0; i < rec.size(); ++i)
+    if (name == rec[i].name) return (int)i;
+  sa_kernel_prof r;
+  memset(&r, 0, sizeof(r));
+  strncpy(r.name, name.c_str(), sizeof(r.name) - 1);
+  rec.push_back(r);
+  return (int)rec.size() - 1;
+}
+
+// a timing slot for the next launch, or null when timing is off or the slots are used up
+const KTiming *prof_slot(sa_seq *q, const std::string &name, double bytes, KTiming *tm) {
+  KernelProfile &P = q->prof;
+  if (!P.on || P.n >= PROF_LAUNCHES || P.n >= WORK_LOG) return nullptr;
+  const int i = P.n++;
+  P.cls[i] = prof_class(q, name);
+  P.bytes[i] = bytes;
+  tm->e0 = P.ev[2 * i];
+  tm->e1 = P.ev[2 * i + 1];
+  tm->lidx = i;
+  return tm;
+}
+
+int prof_begin(sa_seq *q, Ctl *ctl, hipStream_t st) {
+  if (!q->prof.on) return SA_OK;
+  q->prof.n = 0;
+  HIP_TRY(hipMemsetAsync(ctl->work_log, 0, sizeof(ctl->work_log), st));
+  return SA_OK;
+}
+
+// after the solve has completed on the stream
+int prof_end(sa_seq *q, Ctl *ctl, hipStream_t st) {
+  KernelProfile &P = q->prof;
+  if (!P.on || P.n == 0) return SA_OK;
+  std::vector<int> log(P.n);
+  HIP_TRY(hipMemcpyAsync(log.data(), ctl->work_log, P.n * sizeof(int), hipMemcpyDeviceToHost, st));
+  HIP_TRY(hipStreamSynchronize(st));
+  for (int i = 0; i < P.n; ++i) {
+    if (!log[i]) continue;
+    float ms = 0.f;
+    HIP_TRY(hipEventElapsedTime(&ms, P.ev[2 * i], P.ev[2 * i + 1]));
+    sa_kernel_prof &r = P.rec[P.cls[i]];
+    r.launches += 1;
+    r.ms += ms;
+    r.bytes += P.bytes[i];
+  }
+  P.n = 0;
+  return SA_OK;
+}
+
+inline const char *tname(size_t w) { return w == 4 ? "float" : "double"; }
+
+// Look-ahead polling: the state words are copied into host slot s behind the work
+// enqueued so far; the host waits for the previous slot only, so one batch is always
+// queued on the device while the host decides.
+int poll_post(sa_seq *q, Ctl *ctl, int s, hipStream_t st) {
+  HIP_TRY(hipMemcpyAsync(q->hbuf + 16 + 8 * s, &ctl->state, 8 * sizeof(int), hipMemcpyDeviceToHost, st));
+  HIP_TRY(hipEventRecord(q->evp[s], st));
+  return SA_OK;
+}
+
+// waits for slot s; *done = the solver left the RUN state (or the words are corrupt)
+int poll_done(sa_seq *q, int s, bool *done) {
+  HIP_TRY(hipEventSynchronize(q->evp[s]));
+  const int state = q->hbuf[16 + 8 * s];
+  *done = state != ST_RUN;
+  return SA_OK;
+}
+
+struct Poller {
+  sa_seq *q;
+  Ctl *ctl;
+  hipStream_t st;
+  int pending = -1, slot = 1;
+  // post a poll behind the enqueued work; true when an earlier poll says stop
+  int point(bool *stop) {
+    slot ^= 1;
+    SA_TRY(poll_post(q, ctl, slot, st));
+    *stop = false;
+    if (pending >= 0) SA_TRY(poll_done(q, pending, stop));
+    pending = slot;
+    return SA_OK;
+  }
+};
+
+// CG to the tolerance (or maxit); final state words in q->hbuf[0..7].
 template <typename TV>
 int run_cg(sa_seq *q, const CsrView &v, Ctl *ctl, const TV *b, TV *x, int maxit, hipStream_t st) {
   const sa_config &c = q->cfg;
   int *hs = q->hbuf;
-  TV *r = (TV *)q->kry, *p = r + q->ld, *qq = r + 2 * q->ld;
-  int k = 0;            // iterations enqueued (device numbering, 1-based per iteration)
-  bool p_fresh = true;  // p = r: the next iteration needs no direction update
-  HIP_TRY(launch_cg_start_k<TV>(v, b, x, r, p, 0, k, q->partials, ctl, st));
-  SA_TRY(poll(q, ctl, st));
-  // every pass either advances the device iteration count or leaves a final state;
-  // the bound only protects against a corrupted control block
-  const long long max_pass = (long long)maxit + 16;
-  for (long long pass = 0;; ++pass) {
-    if (pass > max_pass || hs[0] < ST_RUN || hs[0] > ST_ZERO_RHS) return SA_EHIP;
-    if (hs[0] == ST_RUN) {
-      for (int t = 0; t < c.poll && k < maxit; ++t) {
-        ++k;
-        HIP_TRY(launch_cg_iter_k<TV>(v, x, r, p, qq, k, p_fresh ? 0 : 1, t > 0 ? 1 : 0, q->partials, ctl, st));
-        p_fresh = false;
-      }
-      HIP_TRY(launch_cg_close_k(q->partials, v.n, k, ctl, st));
-      SA_TRY(poll(q, ctl, st));
-      k = hs[1];  // iterations actually performed (later launches of the batch were no-ops)
+  TV *r = (TV *)q->kry, *p2 = r + q->ld, *qq = r + 3 * q->ld;
+  SA_TRY(prof_begin(q, ctl, st));
+  const size_t w = sizeof(TV), wv = v.fp32 ? 4 : 8;
+  const double csr = 4.0 * (v.n + 1) + (4.0 + wv) * v.nnz;
+  const std::string pname = std::string("k_cg_p<") + tname(wv) + ", " + tname(w) + ">";
+  HIP_TRY(launch_cg_start_k<TV>(v, b, x, r, 0, q->partials, ctl, st));
+  Poller pl{q, ctl, st};
+  bool stop = false;
+  SA_TRY(pl.point(&stop));
+  // each batch either performs an iteration or ends the solve
+  for (long long batch = 0; !stop; ++batch) {
+    if (batch > (long long)maxit + 4) return SA_EHIP;
+    for (int t = 0; t < c.poll; ++t) {
+      KTiming tm;
+      // gathers r and p, writes p and q
+      const KTiming *tp = prof_slot(q, pname, csr + 4.0 * w * v.n, &tm);
+      HIP_TRY(launch_cg_iter<TV>(v, x, r, p2, qq, q->partials, ctl, st, tp));
     }
-    if (hs[0] == ST_CHECK) {
-      HIP_TRY(launch_cg_start_k<TV>(v, b, x, r, p, 1, k, q->partials, ctl, st));
-      SA_TRY(poll(q, ctl, st));
-      p_fresh = true;
-    }
-    if (hs[0] == ST_CONV || hs[0] == ST_ZERO_RHS) break;
-    if (hs[0] == ST_MAXIT || hs[0] == ST_BREAK) {
-      HIP_TRY(launch_cg_start_k<TV>(v, b, x, r, p, 2, k, q->partials, ctl, st));
-      SA_TRY(poll(q, ctl, st));
-      break;
-    }
+    HIP_TRY(launch_cg_start_k<TV>(v, b, x, r, 1, q->partials, ctl, st));  // confirm a CHECK
+    SA_TRY(pl.point(&stop));
   }
-  return SA_OK;
+  SA_TRY(poll(q, ctl, st));
+  if (hs[0] == ST_MAXIT || hs[0] == ST_BREAK) {
+    HIP_TRY(launch_cg_start_k<TV>(v, b, x, r, 2, q->partials, ctl, st));
+    SA_TRY(poll(q, ctl, st));
+  }
+  return prof_end(q, ctl, st);
 }
 
+// GMRES(m) to the tolerance (or maxit); final state words in q->hbuf[0..7].
 template <typename TV>
 int run_gmres(sa_seq *q, const CsrView &v, Ctl *ctl, const TV *b, TV *x, int maxit, hipStream_t st) {
   const sa_config &c = q->cfg;
-  int *hs = q->hbuf;
   TV *V = (TV *)q->kry;
+  TV *T = V + (size_t)(c.restart + 1) * q->ld;
+  SA_TRY(prof_begin(q, ctl, st));
+  const size_t w = sizeof(TV), wv = v.fp32 ? 4 : 8;
+  const double csr = 4.0 * (v.n + 1) + (4.0 + wv) * v.nnz;
   HIP_TRY(launch_gm_start<TV>(v, b, x, V, 0, q->partials, ctl, st));
-  SA_TRY(poll(q, ctl, st));
-  long long cycles = 0;
-  int total = 0;  // Arnoldi steps performed so far
-  while (hs[0] == ST_RUN) {
-    if (++cycles > (long long)maxit + 16) return SA_EHIP;  // each cycle adds >= 1 iteration
-    int j = 0;
-    while (j < c.restart) {
-      for (int t = 0; t < c.poll && j < c.restart; ++t, ++j) {
-        ++total;
-        HIP_TRY(launch_gm_step_it<TV>(v, V, q->ld, j, total, t > 0 ? 1 : 0, q->partials, ctl, st));
+  Poller pl{q, ctl, st};
+  bool stop = false;
+  // every cycle either adds an iteration or ends the solve in its first step
+  for (long long cycle = 0; !stop; ++cycle) {
+    if (cycle > (long long)maxit + 4) return SA_EHIP;
+    for (int j = 0; j < c.restart && !stop; ++j) {
+      KTiming tm;
+      const KTiming *tp = nullptr;
+      if (q->prof.on) {
+        // SpMV of the source column, columns 0..j-1, the finalised column and y
+        const int rb = j <= 8 ? 8 : (j <= 16 ? 16 : 32);
+        const double bytes = csr + (j == 0 ? 2.0 : (double)(j + 3)) * w * v.n;
+        const std::string name = std::string("k_gm_f<") + tname(wv) + ", " + tname(w) + ", " + std::to_string(rb) + ">";
+        tp = prof_slot(q, name, bytes, &tm);
       }
-      HIP_TRY(launch_gm_close_it(q->partials, v.n, j - 1, total, ctl, st));
-      SA_TRY(poll(q, ctl, st));
-      if (!hs[4] || hs[0] != ST_RUN) break;
+      HIP_TRY(launch_gm_step<TV>(v, V, T, q->ld, j, cycle > 0 ? 1 : 0, q->partials, ctl, st, tp));
+      if ((j + 1) % c.poll == 0 && j + 1 < c.restart) SA_TRY(pl.point(&stop));
     }
-    total = hs[1];
+    if (stop) break;
+    HIP_TRY(launch_gm_finish<TV>(v, V, T, q->ld, c.restart, q->partials, ctl, st));
     HIP_TRY(launch_gm_update<TV>(x, V, v.n, q->ld, c.restart, ctl, st));
     HIP_TRY(launch_gm_start<TV>(v, b, x, V, 1, q->partials, ctl, st));
-    SA_TRY(poll(q, ctl, st));
+    SA_TRY(pl.point(&stop));
   }
-  return SA_OK;
+  SA_TRY(poll(q, ctl, st));
+  return prof_end(q, ctl, st);
 }
 
 template <typename TV>
@@ -338,8 +447,9 @@ int sa_init_sequence(const sa_config *cfg, void *dev_ws, size_t ws_bytes, void *
   }
   bool ok = hipHostMalloc((void **)&q->hbuf, 64 * sizeof(int), hipHostMallocDefault) == hipSuccess;
   for (int e = 0; ok && e < 4; ++e) ok = hipEventCreate(&q->ev[e]) == hipSuccess;
-  if (ok) ok = init_ctl(&q->ctl, cfg->tol, cfg->maxit, cfg->restart, st) == SA_OK;
-  if (ok && q->mixed) ok = init_ctl(&q->ctl_in, cfg->inner_tol, cfg->maxit, cfg->restart, st) == SA_OK;
+  for (int e = 0; ok && e < 2; ++e) ok = hipEventCreateWithFlags(&q->evp[e], hipEventDisableTiming) == hipSuccess;
+  if (ok) ok = init_ctl(&q->ctl, cfg->tol, cfg->maxit, cfg->restart, 0, st) == SA_OK;
+  if (ok && q->mixed) ok = init_ctl(&q->ctl_in, cfg->inner_tol, cfg->maxit, cfg->restart, 1, st) == SA_OK;
   if (!ok) {
     sa_destroy_sequence(q);
     return SA_EHIP;
@@ -421,6 +531,13 @@ int sa_initial_guess(sa_seq *q, const sa_csr *A, const void *b_dev, void *x0_dev
 }
 
 // Mixed mode: FP64 iterative refinement around FP32-stored inner solves of A32 d = r.
+// iterations of one inner solve: inner_maxit, or by default 10 GMRES cycles / 1000 CG
+// iterations (float32 storage may keep the inner residual from ever reaching inner_tol)
+static int inner_cap(const sa_config &c) {
+  if (c.inner_maxit > 0) return c.inner_maxit;
+  return c.solver == SA_GMRES ? 10 * c.restart : 1000;
+}
+
 static int solve_mixed(sa_seq *q, const CsrView &v, const double *b, double *x, int *iters, int *restarts,
                        int *sweeps, hipStream_t st) {
   const sa_config &c = q->cfg;
@@ -440,11 +557,11 @@ static int solve_mixed(sa_seq *q, const CsrView &v, const double *b, double *x, 
       }
       break;
     }
-    // inner solve from d = 0 with the remaining iteration budget
-    hs[40] = c.maxit - *iters;
+    // inner solve from d = 0 with the remaining iteration budget, at most inner_maxit
+    hs[40] = c.maxit - *iters < inner_cap(c) ? c.maxit - *iters : inner_cap(c);
     HIP_TRY(hipMemcpyAsync(&q->ctl_in->maxit, hs + 40, sizeof(int), hipMemcpyHostToDevice, st));
     HIP_TRY(hipMemsetAsync(q->d32, 0, (size_t)c.n * sizeof(float), st));
-    SA_TRY(run_krylov<float>(q, v, q->ctl_in, q->r32, q->d32, c.maxit - *iters, st));
+    SA_TRY(run_krylov<float>(q, v, q->ctl_in, q->r32, q->d32, hs[40], st));
     const int inner_state = hs[0];
     *iters += hs[1];
     *restarts += hs[2];
@@ -508,7 +625,36 @@ int sa_destroy_sequence(sa_seq *q) {
   if (q->hbuf) (void)hipHostFree(q->hbuf);
   for (int e = 0; e < 4; ++e)
     if (q->ev[e]) (void)hipEventDestroy(q->ev[e]);
+  for (int e = 0; e < 2; ++e)
+    if (q->evp[e]) (void)hipEventDestroy(q->evp[e]);
+  for (auto &e : q->prof.ev)
+    if (e) (void)hipEventDestroy(e);
   delete q;
+  return SA_OK;
+}
+
+int sa_profile_enable(sa_seq *q, int enable) {
+  if (!q || !q->alive) return SA_ESTATE;
+  KernelProfile &P = q->prof;
+  if (enable && P.ev.empty()) {
+    P.ev.assign(2 * PROF_LAUNCHES, nullptr);
+    for (auto &e : P.ev)
+      if (hipEventCreate(&e) != hipSuccess) return SA_EHIP;
+    P.cls.assign(PROF_LAUNCHES, 0);
+    P.bytes.assign(PROF_LAUNCHES, 0.0);
+  }
+  P.on = enable != 0;
+  P.n = 0;
+  P.rec.clear();
+  return SA_OK;
+}
+
+int sa_profile_read(sa_seq *q, sa_kernel_prof *out, int max, int *count) {
+  if (!q || !q->alive) return SA_ESTATE;
+  if (!count || max < 0 || (max > 0 && !out)) return SA_EINVAL;
+  const int n = (int)q->prof.rec.size();
+  *count = n;
+  for (int i = 0; i < n && i < max; ++i) out[i] = q->prof.rec[i];
   return SA_OK;
 }
 

@@ -13,8 +13,9 @@ constexpr int NWAVE = TPB / WAVE;
 constexpr int MAXBLK = 512;       // cap on blocks of a streaming kernel (grid-stride beyond)
 constexpr int MAXM = 64;          // longest history
 constexpr int MAXS = 256;         // most sketch rows
-constexpr int MAXR = 64;          // longest GMRES cycle
+constexpr int MAXR = 32;          // longest GMRES cycle
 constexpr int SKETCH_RG = 16;     // sketch rows per block row-group
+constexpr int WORK_LOG = 4096;    // timed launches logged per solve
 
 // Solver states kept in the device control block.
 enum : int {
@@ -34,7 +35,13 @@ struct Ctl {
   double bnorm, relres0, relres, tol;
   int state, iters, restarts, maxit;
   int active, jend, restart, pad0;
-  double rho[4], beta[4];       // CG: r^T r and beta of iteration k in slot k & 3
+  int kcur;                     // CG: number of the iteration in flight
+  int fresh_at;                 // CG: iteration whose direction restarts from p = r
+  int ibase;                    // GMRES: iterations done before the current cycle
+  int trust_est;                // inner solves: accept the recursive residual estimate
+  int conv_pending;             // GMRES: the last cycle ended on the estimate (trust_est)
+  int pad2;
+  double rho[4];                // CG: r^T r after iteration k in slot k & 3
   double h1[MAXR + 1];          // GMRES: first Gram-Schmidt pass of the current step
   double cs[MAXR], sn[MAXR];    // Givens rotations
   double gam[MAXR + 1];         // rotated right-hand side (final entries)
@@ -49,6 +56,8 @@ struct Ctl {
   double c[MAXM];          // x0 = Q1 c
   double cX[MAXM];         // x0 = X cX (ring-slot coordinates)
   double gram[MAXM * MAXM * 3 + 2 * MAXM];  // reduced G | Ht | gt  (| K | ht for MINRES)
+  // kernel timing: launch l of a timed solve sets work_log[l] = 1 when it did its work
+  int work_log[WORK_LOG];
 };
 
 // ---------------------------------------------------------------- launch geometry
@@ -65,23 +74,46 @@ __device__ inline double wave_sum(double v) {
   return v;
 }
 
-// Block-reduce K per-thread values (fixed butterfly + fixed wave order) and store the
-// block's sums at out[0..kc).  `red` is LDS of at least NWAVE * K doubles.
-template <int K>
-__device__ inline void block_sum_store(const double (&v)[K], int kc, double *red, double *out) {
-  const int lane = threadIdx.x % WAVE, wid = threadIdx.x / WAVE;
+// Sums over the 64 lanes of a wave of K per-lane values (K a power of two <= 64) by
+// recursive halving: at each exchange a lane keeps half of its entries and adds its
+// partner's copy of that half, so K - 1 + log2(64 / K) exchanges replace 6 K.  On
+// return lane l holds in v[0] the total of entry l / (64 / K).  Fixed order.
+template <int K, int H>
+__device__ inline void wave_halving_step(double (&v)[K], int lane) {
+  if constexpr (H >= 1) {
+    constexpr int O = WAVE * H / K;  // partner offset of this step: 32, 16, ...
+    const bool up = (lane & O) != 0;
 #pragma unroll
-  for (int e = 0; e < K; ++e) {
-    if (e < kc) {
-      double s = wave_sum(v[e]);
-      if (lane == 0) red[wid * K + e] = s;
+    for (int i = 0; i < H; ++i) {
+      const double send = up ? v[i] : v[i + H];
+      const double keep = up ? v[i + H] : v[i];
+      v[i] = keep + __shfl_xor(send, O, WAVE);
     }
+    wave_halving_step<K, H / 2>(v, lane);
   }
+}
+
+template <int K>
+__device__ inline void wave_sum_multi(double (&v)[K]) {
+  static_assert(K >= 1 && K <= WAVE && (K & (K - 1)) == 0, "K must be a power of two <= 64");
+  wave_halving_step<K, K / 2>(v, (int)(threadIdx.x % WAVE));
+#pragma unroll
+  for (int o = WAVE / K / 2; o >= 1; o /= 2) v[0] += __shfl_xor(v[0], o, WAVE);
+}
+
+// Block-reduce K per-thread values (K a power of two; fixed butterfly and fixed wave
+// order) and store the block's sums at out[0..kc).  `red` is LDS of at least
+// (blockDim.x / 64) * K doubles.  The values in v are consumed.
+template <int K>
+__device__ inline void block_sum_store(double (&v)[K], int kc, double *red, double *out) {
+  const int lane = threadIdx.x % WAVE, wid = threadIdx.x / WAVE, nw = blockDim.x / WAVE;
+  constexpr int STEP = WAVE / K;
+  wave_sum_multi<K>(v);
+  if (lane % STEP == 0) red[wid * K + lane / STEP] = v[0];
   __syncthreads();
   for (int e = threadIdx.x; e < kc; e += blockDim.x) {
     double s = 0.0;
-#pragma unroll
-    for (int w = 0; w < NWAVE; ++w) s += red[w * K + e];
+    for (int w = 0; w < nw; ++w) s += red[w * K + e];
     out[e] = s;
   }
 }
@@ -90,30 +122,34 @@ __device__ inline void block_sum_store(const double (&v)[K], int kc, double *red
 // writes back the L2): a kernel's per-block partial rows are reduced by the next
 // kernel, whose launch orders them.
 //
-// Sums over nblk rows of partials[nblk][W] for entries e < kc, in
-// a fixed order (strided per-thread sums, then a fixed tree), into LDS out[0..kc).
-// `scratch` is LDS of blockDim.x doubles; blockDim.x must be a power of two.
+// Sums over nblk rows of partials[nblk][W] for entries e < kc, in a fixed order
+// (per-thread sums over a strided set of rows, all loads of a thread issued
+// together, then a fixed tree), into LDS out[0..kc).  `scratch` is LDS of blockDim.x
+// doubles; blockDim.x must be a power of two.
 __device__ inline void final_sum(const double *partials, int nblk, int W, int kc, double *out,
                                  double *scratch) {
-  for (int e0 = 0; e0 < kc; e0 += 32) {
-    const int ec = kc - e0 < 32 ? kc - e0 : 32;
+  constexpr int U = 32;
+  for (int e0 = 0; e0 < kc; e0 += WAVE) {
+    const int ec = kc - e0 < WAVE ? kc - e0 : WAVE;
     int ep = 1;
     while (ep < ec) ep <<= 1;
     const int ngrp = blockDim.x / ep;
     const int e = threadIdx.x % ep, grp = threadIdx.x / ep;
-    // four independent accumulators keep several loads in flight
-    double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
+    double s = 0.0;
     if (e < ec) {
-      int b = grp;
-      for (; b + 3 * ngrp < nblk; b += 4 * ngrp) {
-        s0 += partials[(size_t)b * W + e0 + e];
-        s1 += partials[(size_t)(b + ngrp) * W + e0 + e];
-        s2 += partials[(size_t)(b + 2 * ngrp) * W + e0 + e];
-        s3 += partials[(size_t)(b + 3 * ngrp) * W + e0 + e];
+      for (int b0 = grp; b0 < nblk; b0 += U * ngrp) {
+        double t[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+          const int b = b0 + u * ngrp;
+          const double x = partials[(size_t)(b < nblk ? b : nblk - 1) * W + e0 + e];
+          t[u] = b < nblk ? x : 0.0;
+        }
+#pragma unroll
+        for (int u = 0; u < U; ++u) s += t[u];
       }
-      for (; b < nblk; b += ngrp) s0 += partials[(size_t)b * W + e0 + e];
     }
-    scratch[threadIdx.x] = (s0 + s1) + (s2 + s3);
+    scratch[threadIdx.x] = s;
     __syncthreads();
     for (int off = ngrp / 2; off > 0; off >>= 1) {
       if (grp < off) scratch[threadIdx.x] += scratch[threadIdx.x + off * ep];
@@ -127,18 +163,22 @@ __device__ inline void final_sum(const double *partials, int nblk, int W, int kc
 // ---------------------------------------------------------------- CSR stream SpMV
 constexpr int SPMV_CAP = 4096;  // nonzeros of one row tile staged in LDS (32 KB)
 
-// (A x)_i for row i = r0 + threadIdx.x of the row tile [r0, r0 + blockDim.x) (0 beyond
-// n).  Every thread of the block must call it for the same r0.  The tile's val/col
-// are read with consecutive threads on consecutive nonzeros (coalesced) and the
-// products staged in LDS; each thread then sums its row in column order.  Tiles with
-// more than SPMV_CAP nonzeros read their rows directly.
-template <typename VT, typename TX>
-__device__ inline double tile_spmv(const int *__restrict__ rowptr, const int *__restrict__ col,
-                                   const VT *__restrict__ val, const TX *__restrict__ x, int64_t n,
-                                   int64_t r0, double *prod) {
+// (A x)_i for row i = r0 + threadIdx.x of the row tile [r0, r0 + NT) (0 beyond n),
+// NT = threads of the block.  Every thread of the block must call it for the same r0.
+// The tile's col/val are read with consecutive threads on consecutive nonzeros
+// (coalesced), all of a thread's loads issued before the first is used (indices past
+// the tile re-read its last entry and are dropped), then the gathers, and the
+// products are staged in LDS; each thread sums its row in column order.  Tiles with
+// more than SPMV_CAP nonzeros read their rows directly.  `gx(c)` returns the source
+// vector's entry c in double.
+template <int NT, typename VT, typename G>
+__device__ inline double tile_spmv_g(const int *__restrict__ rowptr, const int *__restrict__ col,
+                                     const VT *__restrict__ val, const G &gx, int64_t n, int64_t r0,
+                                     double *prod) {
+  constexpr int U = SPMV_CAP / NT;
   const int t = threadIdx.x;
   const int64_t i = r0 + t;
-  const int64_t rl = (r0 + (int64_t)blockDim.x < n) ? r0 + (int64_t)blockDim.x : n;
+  const int64_t rl = (r0 + (int64_t)NT < n) ? r0 + (int64_t)NT : n;
   const int p0 = rowptr[r0], p1 = rowptr[rl];
   int a = 0, b = 0;
   if (i < n) {
@@ -146,15 +186,46 @@ __device__ inline double tile_spmv(const int *__restrict__ rowptr, const int *__
     b = rowptr[i + 1];
   }
   double s = 0.0;
-  if (p1 - p0 <= SPMV_CAP) {
-    for (int p = p0 + t; p < p1; p += blockDim.x) prod[p - p0] = (double)val[p] * (double)x[col[p]];
+  const int cnt = p1 - p0;
+  if (cnt <= SPMV_CAP) {
+    if (cnt > 0) {
+      int cc[U];
+      double vv[U], xx[U];
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        const int p = p0 + t + u * NT;
+        const int pc = p < p1 ? p : p1 - 1;
+        cc[u] = col[pc];
+        vv[u] = (double)val[pc];
+      }
+#pragma unroll
+      for (int u = 0; u < U; ++u) xx[u] = gx(cc[u]);
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        const int p = p0 + t + u * NT;
+        if (p < p1) prod[p - p0] = vv[u] * xx[u];
+      }
+    }
     __syncthreads();
     for (int p = a; p < b; ++p) s += prod[p - p0];
     __syncthreads();
   } else {
-    for (int p = a; p < b; ++p) s += (double)val[p] * (double)x[col[p]];
+    for (int p = a; p < b; ++p) s += (double)val[p] * gx(col[p]);
   }
   return s;
+}
+
+template <typename TX>
+struct Gather1 {
+  const TX *__restrict__ x;
+  __device__ double operator()(int c) const { return (double)x[c]; }
+};
+
+template <int NT, typename VT, typename TX>
+__device__ inline double tile_spmv(const int *__restrict__ rowptr, const int *__restrict__ col,
+                                   const VT *__restrict__ val, const TX *__restrict__ x, int64_t n,
+                                   int64_t r0, double *prod) {
+  return tile_spmv_g<NT>(rowptr, col, val, Gather1<TX>{x}, n, r0, prod);
 }
 
 // ---------------------------------------------------------------- Philox4x64-10

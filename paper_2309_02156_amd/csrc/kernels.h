@@ -56,33 +56,42 @@ hipError_t launch_ir_resid(const CsrView &A, const double *b, const double *x, f
                            int sweep, int max_refine, Ctl *ctl, hipStream_t st);
 hipError_t launch_ir_update(double *x, const float *d, int64_t n, hipStream_t st);
 
-// Krylov kernels.  Cross-block results travel through per-block partial sums that
-// the next kernel reduces (kernel boundaries order them); two partial buffers
-// alternate.  A 1-block "close" kernel ends each batch so the host can poll.
-//
-// CG: start(mode) -> start_close; per iteration [dir] qp xr; batch end: close.
-//   mode 0 start, 1 true-residual confirmation, 2 final residual only.
-// k = iterations completed before the call (start / confirm / final) or the number
-// of the iteration being launched (iter, 1-based), or the last one (close).
-// TV = vector storage type (double, or float for the inner solves of the mixed mode).
-template <typename TV>
-hipError_t launch_cg_start_k(const CsrView &A, const TV *b, const TV *x, TV *r, TV *p, int mode, int k,
-                             double *partials, Ctl *ctl, hipStream_t st);
-// one iteration; with_dir = 0 right after start/confirm (p = r); fresh = 1 when the
-// previous iteration has not been closed (dir reduces its partials itself)
-template <typename TV>
-hipError_t launch_cg_iter_k(const CsrView &A, TV *x, TV *r, TV *p, TV *q, int k, int with_dir, int fresh,
-                            double *partials, Ctl *ctl, hipStream_t st);
-hipError_t launch_cg_close_k(double *partials, int64_t n, int k, Ctl *ctl, hipStream_t st);
+// Optional timing of one launch: HIP events recorded around it on its stream, and the
+// index under which the kernel logs that it did its work (Ctl::work_log).
+struct KTiming {
+  hipEvent_t e0, e1;
+  int lidx;
+};
 
-// GMRES(m), classical Gram-Schmidt applied twice.  it = global iteration number.
+// Krylov kernels (device-driven: every kernel returns at once unless the control
+// block says there is work, so batches may be enqueued ahead of a poll).
+// TV = vector storage type (double, or float for the inner solves of the mixed mode).
+//
+// CG: start(mode) [+ one-block close]; then iterations (two kernels each); after a
+// batch, start(mode 1) confirms a recursive-residual stop (no-op unless CHECK).
+//   mode 0 start, 1 true-residual confirmation, 2 final residual only.
+// p2 holds the two alternating direction vectors (p2 and p2 + padded_ld(n)).
+template <typename TV>
+hipError_t launch_cg_start_k(const CsrView &A, const TV *b, const TV *x, TV *r, int mode, double *partials,
+                             Ctl *ctl, hipStream_t st);
+// tm (may be null) times the direction/SpMV kernel of the iteration
+template <typename TV>
+hipError_t launch_cg_iter(const CsrView &A, TV *x, TV *r, TV *p2, TV *q, double *partials, Ctl *ctl,
+                          hipStream_t st, const KTiming *tm = nullptr);
+
+// GMRES(m), classical Gram-Schmidt applied twice.  A cycle: start (residual into
+// V[:, 0]), steps j = 0..m-1 (first_mode 0 for the first cycle of a solve, 1 for a
+// restart), finish (closes step m - 1), update (x += V y).  T is a scratch vector.
 template <typename TV>
 hipError_t launch_gm_start(const CsrView &A, const TV *b, const TV *x, TV *V, int restart_mode, double *partials,
                            Ctl *ctl, hipStream_t st);
+// tm (may be null) times the step's first kernel (SpMV, finalisation, first dots)
 template <typename TV>
-hipError_t launch_gm_step_it(const CsrView &A, TV *V, int64_t ld, int j, int it, int fresh, double *partials,
-                             Ctl *ctl, hipStream_t st);
-hipError_t launch_gm_close_it(double *partials, int64_t n, int j, int it, Ctl *ctl, hipStream_t st);
+hipError_t launch_gm_step(const CsrView &A, TV *V, TV *T, int64_t ld, int j, int first_mode, double *partials,
+                          Ctl *ctl, hipStream_t st, const KTiming *tm = nullptr);
+template <typename TV>
+hipError_t launch_gm_finish(const CsrView &A, TV *V, TV *T, int64_t ld, int m, double *partials, Ctl *ctl,
+                            hipStream_t st);
 template <typename TV>
 hipError_t launch_gm_update(TV *x, const TV *V, int64_t n, int64_t ld, int restart, Ctl *ctl, hipStream_t st);
 size_t krylov_partials_doubles();

@@ -46,7 +46,7 @@ __global__ __launch_bounds__(TPB) void k_spmv(const int *rowptr, const int *col,
                                               const double *x, double *y, int64_t n) {
   __shared__ double prod[SPMV_CAP];
   for (int64_t r0 = (int64_t)blockIdx.x * TPB; r0 < n; r0 += (int64_t)gridDim.x * TPB) {
-    const double s = tile_spmv(rowptr, col, val, x, n, r0, prod);
+    const double s = tile_spmv<TPB>(rowptr, col, val, x, n, r0, prod);
     if (r0 + threadIdx.x < n) y[r0 + threadIdx.x] = s;
   }
 }
@@ -776,7 +776,7 @@ __global__ __launch_bounds__(TPB) void k_ir_resid(const int *rowptr, const int *
   __shared__ double prod[SPMV_CAP];
   double acc[2] = {0.0, 0.0};
   for (int64_t r0 = (int64_t)blockIdx.x * TPB; r0 < n; r0 += (int64_t)gridDim.x * TPB) {
-    const double ax = tile_spmv(rowptr, col, val, x, n, r0, prod);
+    const double ax = tile_spmv<TPB>(rowptr, col, val, x, n, r0, prod);
     const int64_t i = r0 + threadIdx.x;
     if (i < n) {
       const double bi = b[i], ri = bi - ax;

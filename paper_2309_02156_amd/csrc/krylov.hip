@@ -6,15 +6,16 @@
 // mode); every arithmetic operation is carried out in double from the stored
 // operands and rounded to TV only when a vector is stored.
 //
+// The iteration is driven from the device: every kernel reads the solver state from
+// the control block and returns at once when there is nothing left to do, so the
+// host can enqueue whole batches (and a batch ahead) without waiting for a poll.
+//
 // No block waits on another block inside a kernel.  Each streaming kernel writes one
-// row of per-block partial sums; the next kernel (or a one-block "close" kernel at the
-// end of a polled batch) reduces those rows in a fixed order in every block and
-// derives the same scalars everywhere.  Three partial buffers rotate so a kernel
-// never overwrites rows that blocks of the same kernel still read.  Within a kernel,
-// block 0 persists scalars only into fields that no block of that kernel reads:
-// CG keeps rho / beta in rings indexed by the host-supplied iteration number, GMRES
-// keeps the raw Hessenberg column, the rotated column and the rotated right-hand side
-// in separate arrays.  The run flag is read once per block into LDS.
+// row of per-block partial sums; the next kernel reduces those rows in a fixed order
+// in every block and derives the same scalars everywhere.  Two partial buffers
+// alternate so a kernel never overwrites rows that blocks of the same kernel still
+// read.  Within a kernel, block 0 persists scalars only into fields that no block of
+// that kernel reads.
 #include <math.h>
 
 #include "common.h"
@@ -34,7 +35,6 @@ static inline int kblocks(int64_t n) {
 }
 static inline double *PA(double *P) { return P; }
 static inline double *PB(double *P) { return P + (size_t)KMAXBLK * KW; }
-static inline double *PC(double *P) { return P + (size_t)2 * KMAXBLK * KW; }
 
 #define KROWS(i, n) \
   for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < (n); i += (int64_t)gridDim.x * blockDim.x)
@@ -44,21 +44,27 @@ static inline double *PC(double *P) { return P + (size_t)2 * KMAXBLK * KW; }
 #define KTILES(r0, n) \
   for (int64_t r0 = (int64_t)blockIdx.x * KTPB; r0 < (n); r0 += (int64_t)gridDim.x * KTPB)
 
-// block sums of K per-thread values -> out[0..kc) (fixed butterfly, fixed wave order)
+// block sums of K per-thread values -> out[0..kc) (K a power of two)
 template <int K>
-__device__ inline void kstore(const double (&v)[K], int kc, double *red, double *out) {
+__device__ inline void kstore(double (&v)[K], int kc, double *red, double *out) {
+  block_sum_store<K>(v, kc, red, out);
+}
+
+// block sums of two values and RB dots -> out[0], out[1], out[2 + k] (first kc entries)
+template <int RB>
+__device__ inline void kstore2(double (&ex)[2], double (&dots)[RB], int kc, double *red, double *out) {
   const int lane = threadIdx.x % WAVE, wid = threadIdx.x / WAVE;
-#pragma unroll
-  for (int e = 0; e < K; ++e)
-    if (e < kc) {
-      const double s = wave_sum(v[e]);
-      if (lane == 0) red[wid * K + e] = s;
-    }
+  constexpr int STEP = WAVE / RB;
+  wave_sum_multi<2>(ex);
+  wave_sum_multi<RB>(dots);
+  double *rw = red + wid * (RB + 2);
+  if (lane % 32 == 0) rw[lane / 32] = ex[0];
+  if (lane % STEP == 0) rw[2 + lane / STEP] = dots[0];
   __syncthreads();
   for (int e = threadIdx.x; e < kc; e += blockDim.x) {
     double s = 0.0;
 #pragma unroll
-    for (int w = 0; w < KNW; ++w) s += red[w * K + e];
+    for (int w = 0; w < KNW; ++w) s += red[w * (RB + 2) + e];
     out[e] = s;
   }
 }
@@ -71,10 +77,55 @@ __device__ inline bool block_running(const Ctl *ctl, bool need_active) {
   return s_run != 0;
 }
 
+// Stopping test on a true residual ||r||^2 = rho (and ||b||^2 = bb when first): the
+// state after a start (mode 0), after a confirmation (mode 1, runs only in state
+// CHECK) or the final residual (mode 2, norms only).  k = iterations done.
+// accept: the recursive estimate already met the tolerance and the control block
+// trusts it (inner solves of the mixed mode), so the solve ends converged.  Returns
+// the new state; `persist` writes it (one thread of one block).
+__device__ inline int residual_decide(double rho, double bb, int mode, Ctl *ctl, bool persist, bool accept = false) {
+  const int k = mode == 0 ? 0 : ctl->iters;
+  const double bn = mode == 0 ? sqrt(bb) : ctl->bnorm;
+  const double nr = sqrt(rho);
+  const double rel = bn > 0.0 ? nr / bn : 0.0;
+  int st;
+  if (bn == 0.0)
+    st = ST_ZERO_RHS;
+  else if (nr <= ctl->tol * bn)
+    st = ST_CONV;
+  else if (!isfinite(nr))
+    st = ST_BREAK;
+  else
+    st = (k >= ctl->maxit) ? ST_MAXIT : ST_RUN;
+  if (accept && mode == 1 && (st == ST_RUN || st == ST_MAXIT)) st = ST_CONV;
+  if (persist) {
+    if (mode == 0) {
+      ctl->bnorm = bn;
+      ctl->relres0 = rel;
+      ctl->iters = 0;
+      ctl->restarts = 0;
+    }
+    ctl->relres = rel;
+    if (mode != 2) ctl->state = st;
+    if (mode == 1 && st == ST_RUN) ctl->restarts += 1;
+  }
+  return st;
+}
+
 // ============================================================================ CG
+// Two streaming kernels per iteration k (1-based, numbered on the device):
+//   cg_p(k):  r_{k-1}^T r_{k-1} from the previous partials -> stopping test, beta;
+//             p_k = r + beta p_{k-1} (p double-buffered by the parity of k) and
+//             q = A p_k, the SpMV gathering r + beta p_{k-1} for the neighbours;
+//             partial p_k^T q.
+//   cg_xr(k): alpha = r^T r / p^T q; x += alpha p; r -= alpha q; partial r^T r.
+// start: r = b - A x with partial ||r||^2, ||b||^2; a one-block close decides.  After a
+// recursive-residual stop (state CHECK) the host's batch-end confirmation recomputes
+// the true residual; if it fails the direction restarts (p = r).
+
 template <typename VT, typename TV>
 __global__ __launch_bounds__(KTPB) void k_cg_start(const int *rowptr, const int *col, const VT *val,
-                                                   const TV *b, const TV *x, TV *r, TV *p, int64_t n, int mode,
+                                                   const TV *b, const TV *x, TV *r, int64_t n, int mode,
                                                    double *Pout, const Ctl *ctl) {
   __shared__ double red[KNW * 2];
   __shared__ double prod[SPMV_CAP];
@@ -84,15 +135,12 @@ __global__ __launch_bounds__(KTPB) void k_cg_start(const int *rowptr, const int 
   if (!s_go) return;
   double acc[2] = {0.0, 0.0};
   KTILES(r0, n) {
-    const double ax = tile_spmv(rowptr, col, val, x, n, r0, prod);
+    const double ax = tile_spmv<KTPB>(rowptr, col, val, x, n, r0, prod);
     const int64_t i = r0 + threadIdx.x;
     if (i < n) {
       const double bi = (double)b[i];
       const TV rs = (TV)(bi - ax);
-      if (mode != 2) {
-        r[i] = rs;
-        p[i] = rs;
-      }
+      if (mode != 2) r[i] = rs;
       const double ri = (double)rs;
       acc[0] += ri * ri;
       acc[1] += bi * bi;
@@ -101,9 +149,7 @@ __global__ __launch_bounds__(KTPB) void k_cg_start(const int *rowptr, const int 
   kstore<2>(acc, 2, red, Pout + (size_t)blockIdx.x * KW);
 }
 
-// one block: the stopping test before iteration 1 (mode 0), the confirmation of a
-// recursive-residual stop (mode 1), or the final residual (mode 2).  k = iterations done.
-__global__ __launch_bounds__(KTPB) void k_cg_start_close(const double *Pin, int nblk, int mode, int k, Ctl *ctl) {
+__global__ __launch_bounds__(KTPB) void k_cg_start_close(const double *Pin, int nblk, int mode, Ctl *ctl) {
   __shared__ double outv[2];
   __shared__ double scratch[KTPB];
   __shared__ int s_go;
@@ -112,67 +158,106 @@ __global__ __launch_bounds__(KTPB) void k_cg_start_close(const double *Pin, int 
   if (!s_go) return;
   final_sum(Pin, nblk, KW, 2, outv, scratch);
   if (threadIdx.x != 0) return;
-  const double rho = outv[0];
-  if (mode == 0) {
-    ctl->bnorm = sqrt(outv[1]);
-    ctl->iters = 0;
-    ctl->restarts = 0;
-  }
-  const double bn = ctl->bnorm, nr = sqrt(rho);
-  const double rel = bn > 0.0 ? nr / bn : 0.0;
-  ctl->relres = rel;
-  if (mode == 0) ctl->relres0 = rel;
-  if (mode == 2) return;
-  ctl->rho[k & 3] = rho;
-  if (bn == 0.0)
-    ctl->state = ST_ZERO_RHS;
-  else if (nr <= ctl->tol * bn)
-    ctl->state = ST_CONV;
-  else if (!isfinite(nr))
-    ctl->state = ST_BREAK;
-  else {
-    if (mode == 1) ctl->restarts += 1;
-    ctl->state = (k >= ctl->maxit) ? ST_MAXIT : ST_RUN;
+  const int st = residual_decide(outv[0], outv[1], mode, ctl, true, ctl->trust_est != 0);
+  if (mode != 2 && st == ST_RUN) {
+    const int k = ctl->iters;
+    ctl->rho[k & 3] = outv[0];
+    ctl->fresh_at = k + 1;
   }
 }
 
+template <typename TV>
+struct GatherDir {
+  const TV *__restrict__ r;
+  const TV *__restrict__ p;
+  double beta;
+  int fresh;
+  // the direction entry as it is stored (rounded to TV), so q = A p uses the same p
+  __device__ double operator()(int c) const {
+    return fresh ? (double)r[c] : (double)(TV)((double)r[c] + beta * (double)p[c]);
+  }
+};
+
 template <typename VT, typename TV>
-__global__ __launch_bounds__(KTPB) void k_cg_qp(const int *rowptr, const int *col, const VT *val, const TV *p,
-                                                TV *q, int64_t n, double *Pout, const Ctl *ctl) {
+__global__ __launch_bounds__(KTPB) void k_cg_p(const int *rowptr, const int *col, const VT *val, const TV *r,
+                                               TV *P0, TV *P1, TV *q, int64_t n, const double *Pin, int nblk,
+                                               double *Pout, Ctl *ctl, int lidx) {
   __shared__ double red[KNW];
+  __shared__ double outv[1];
+  __shared__ double scratch[KTPB];
   __shared__ double prod[SPMV_CAP];
-  if (!block_running(ctl, false)) return;
+  __shared__ int s_k, s_fresh, s_go, s_cont;
+  __shared__ double s_beta;
+  if (threadIdx.x == 0) {
+    s_go = ctl->state == ST_RUN;
+    s_k = ctl->iters + 1;
+    s_fresh = (s_k == ctl->fresh_at);
+  }
+  __syncthreads();
+  if (!s_go) return;
+  const int k = s_k, fresh = s_fresh;
+  if (!fresh) final_sum(Pin, nblk, KW, 1, outv, scratch);
+  if (threadIdx.x == 0) {
+    int st = ST_RUN;
+    double beta = 0.0;
+    if (!fresh) {
+      const double rho = outv[0];
+      if (sqrt(rho) <= ctl->tol * ctl->bnorm)
+        st = ST_CHECK;
+      else if (!isfinite(rho))
+        st = ST_BREAK;
+      else
+        beta = rho / ctl->rho[(k - 2) & 3];
+      if (blockIdx.x == 0) ctl->rho[(k - 1) & 3] = rho;
+    }
+    if (st == ST_RUN && k - 1 >= ctl->maxit) st = ST_MAXIT;
+    if (blockIdx.x == 0) {
+      if (st != ST_RUN) ctl->state = st;
+      ctl->kcur = k;
+    }
+    s_cont = st == ST_RUN;
+    s_beta = beta;
+  }
+  __syncthreads();
+  if (!s_cont) return;
+  if (lidx >= 0 && blockIdx.x == 0 && threadIdx.x == 0) ctl->work_log[lidx] = 1;
+  const double beta = s_beta;
+  const TV *pin = (k & 1) ? P0 : P1;
+  TV *pout = (k & 1) ? P1 : P0;
+  const GatherDir<TV> gx{r, pin, beta, fresh};
   double acc[1] = {0.0};
   KTILES(r0, n) {
-    const double qi = tile_spmv(rowptr, col, val, p, n, r0, prod);
+    const double qi = tile_spmv_g<KTPB>(rowptr, col, val, gx, n, r0, prod);
     const int64_t i = r0 + threadIdx.x;
     if (i < n) {
+      const TV ps = (TV)gx((int)i);  // exact: gx already rounds to TV
+      pout[i] = ps;
       const TV qs = (TV)qi;
       q[i] = qs;
-      acc[0] += (double)p[i] * (double)qs;
+      acc[0] += (double)ps * (double)qs;
     }
   }
   kstore<1>(acc, 1, red, Pout + (size_t)blockIdx.x * KW);
 }
 
-// iteration k: alpha = rho_{k-1} / p^T q; x += alpha p; r -= alpha q; partial r^T r
 template <typename TV>
-__global__ __launch_bounds__(KTPB) void k_cg_xr(TV *x, TV *r, const TV *p, const TV *q, int64_t n,
-                                                const double *Pin, int nblk, int k, double *Pout, Ctl *ctl) {
+__global__ __launch_bounds__(KTPB) void k_cg_xr(TV *x, TV *r, const TV *P0, const TV *P1, const TV *q, int64_t n,
+                                                const double *Pin, int nblk, double *Pout, Ctl *ctl) {
   __shared__ double red[KNW];
   __shared__ double outv[1];
   __shared__ double scratch[KTPB];
+  __shared__ int s_k;
   if (!block_running(ctl, false)) return;
+  if (threadIdx.x == 0) s_k = ctl->kcur;
   final_sum(Pin, nblk, KW, 1, outv, scratch);
+  const int k = s_k;
   const double pq = outv[0];
   if (!(pq > 0.0) || !isfinite(pq)) {
-    if (blockIdx.x == 0 && threadIdx.x == 0) {
-      ctl->iters = k - 1;
-      ctl->state = ST_BREAK;
-    }
+    if (blockIdx.x == 0 && threadIdx.x == 0) ctl->state = ST_BREAK;
     return;
   }
   const double alpha = ctl->rho[(k - 1) & 3] / pq;
+  const TV *p = (k & 1) ? P1 : P0;
   double acc[1] = {0.0};
   KROWS(i, n) {
     x[i] = (TV)((double)x[i] + alpha * (double)p[i]);
@@ -182,109 +267,65 @@ __global__ __launch_bounds__(KTPB) void k_cg_xr(TV *x, TV *r, const TV *p, const
     acc[0] += ri * ri;
   }
   kstore<1>(acc, 1, red, Pout + (size_t)blockIdx.x * KW);
-}
-
-// decision after iteration k from r_k^T r_k; persisted by one thread of block 0 only.
-// returns true when iterating stops (state changes).
-__device__ inline bool cg_decide(double rn, int k, Ctl *ctl, bool persist, double *beta_out) {
-  const double bn = ctl->bnorm;
-  int st = ST_RUN;
-  double beta = 0.0;
-  if (sqrt(rn) <= ctl->tol * bn)
-    st = ST_CHECK;
-  else if (!isfinite(rn))
-    st = ST_BREAK;
-  else {
-    beta = rn / ctl->rho[(k - 1) & 3];
-    if (k >= ctl->maxit) st = ST_MAXIT;
-  }
-  if (persist) {
-    ctl->iters = k;
-    ctl->rho[k & 3] = rn;
-    ctl->beta[k & 3] = beta;
-    if (st != ST_RUN) ctl->state = st;
-  }
-  *beta_out = beta;
-  return st != ST_RUN;
-}
-
-// p = r + beta_k p before iteration k + 1.  fresh: iteration k is not closed yet, so
-// reduce its r^T r partials here and take the stopping decision (same in every block).
-template <typename TV>
-__global__ __launch_bounds__(KTPB) void k_cg_dir(TV *p, const TV *r, int64_t n, const double *Pin, int nblk, int k,
-                                                 int fresh, Ctl *ctl) {
-  __shared__ double outv[1];
-  __shared__ double scratch[KTPB];
-  __shared__ double s_beta;
-  __shared__ int s_stop;
-  if (!block_running(ctl, false)) return;
-  if (fresh) {
-    final_sum(Pin, nblk, KW, 1, outv, scratch);
-    if (threadIdx.x == 0) {
-      double beta;
-      s_stop = cg_decide(outv[0], k, ctl, blockIdx.x == 0, &beta);
-      s_beta = beta;
-    }
-    __syncthreads();
-    if (s_stop) return;
-  } else {
-    if (threadIdx.x == 0) s_beta = ctl->beta[k & 3];
-    __syncthreads();
-  }
-  const double beta = s_beta;
-  KROWS(i, n) p[i] = (TV)((double)r[i] + beta * (double)p[i]);
-}
-
-__global__ __launch_bounds__(KTPB) void k_cg_close(const double *Pin, int nblk, int k, Ctl *ctl) {
-  __shared__ double outv[1];
-  __shared__ double scratch[KTPB];
-  if (!block_running(ctl, false)) return;
-  final_sum(Pin, nblk, KW, 1, outv, scratch);
-  if (threadIdx.x == 0) {
-    double beta;
-    cg_decide(outv[0], k, ctl, true, &beta);
-  }
+  if (blockIdx.x == 0 && threadIdx.x == 0) ctl->iters = k;
 }
 
 template <typename TV>
-hipError_t launch_cg_start_k(const CsrView &A, const TV *b, const TV *x, TV *r, TV *p, int mode, int k,
-                             double *partials, Ctl *ctl, hipStream_t st) {
+hipError_t launch_cg_start_k(const CsrView &A, const TV *b, const TV *x, TV *r, int mode, double *partials, Ctl *ctl,
+                             hipStream_t st) {
   const int nb = kblocks(A.n);
   if (A.fp32)
     hipLaunchKernelGGL((k_cg_start<float, TV>), dim3(nb), dim3(KTPB), 0, st, A.rowptr, A.col,
-                       (const float *)A.val, b, x, r, p, A.n, mode, PA(partials), ctl);
+                       (const float *)A.val, b, x, r, A.n, mode, PA(partials), ctl);
   else
     hipLaunchKernelGGL((k_cg_start<double, TV>), dim3(nb), dim3(KTPB), 0, st, A.rowptr, A.col,
-                       (const double *)A.val, b, x, r, p, A.n, mode, PA(partials), ctl);
-  hipLaunchKernelGGL(k_cg_start_close, dim3(1), dim3(KTPB), 0, st, PA(partials), nb, mode, k, ctl);
+                       (const double *)A.val, b, x, r, A.n, mode, PA(partials), ctl);
+  hipLaunchKernelGGL(k_cg_start_close, dim3(1), dim3(KTPB), 0, st, PA(partials), nb, mode, ctl);
   return hipGetLastError();
 }
 
-// iteration k (1-based): [dir] qp xr
 template <typename TV>
-hipError_t launch_cg_iter_k(const CsrView &A, TV *x, TV *r, TV *p, TV *q, int k, int with_dir, int fresh,
-                            double *partials, Ctl *ctl, hipStream_t st) {
+hipError_t launch_cg_iter(const CsrView &A, TV *x, TV *r, TV *p2, TV *q, double *partials, Ctl *ctl,
+                          hipStream_t st, const KTiming *tm) {
   const int nb = kblocks(A.n);
-  if (with_dir)
-    hipLaunchKernelGGL(k_cg_dir<TV>, dim3(nb), dim3(KTPB), 0, st, p, r, A.n, PB(partials), nb, k - 1, fresh,
-                       ctl);
+  const int64_t ld = padded_ld(A.n);
+  TV *P0 = p2, *P1 = p2 + ld;
+  const int lidx = tm ? tm->lidx : -1;
+  if (tm) (void)hipEventRecord(tm->e0, st);
   if (A.fp32)
-    hipLaunchKernelGGL((k_cg_qp<float, TV>), dim3(nb), dim3(KTPB), 0, st, A.rowptr, A.col, (const float *)A.val,
-                       p, q, A.n, PA(partials), ctl);
+    hipLaunchKernelGGL((k_cg_p<float, TV>), dim3(nb), dim3(KTPB), 0, st, A.rowptr, A.col, (const float *)A.val, r,
+                       P0, P1, q, A.n, PA(partials), nb, PB(partials), ctl, lidx);
   else
-    hipLaunchKernelGGL((k_cg_qp<double, TV>), dim3(nb), dim3(KTPB), 0, st, A.rowptr, A.col,
-                       (const double *)A.val, p, q, A.n, PA(partials), ctl);
-  hipLaunchKernelGGL(k_cg_xr<TV>, dim3(nb), dim3(KTPB), 0, st, x, r, p, q, A.n, PA(partials), nb, k,
-                     PB(partials), ctl);
-  return hipGetLastError();
-}
-
-hipError_t launch_cg_close_k(double *partials, int64_t n, int k, Ctl *ctl, hipStream_t st) {
-  hipLaunchKernelGGL(k_cg_close, dim3(1), dim3(KTPB), 0, st, PB(partials), kblocks(n), k, ctl);
+    hipLaunchKernelGGL((k_cg_p<double, TV>), dim3(nb), dim3(KTPB), 0, st, A.rowptr, A.col,
+                       (const double *)A.val, r, P0, P1, q, A.n, PA(partials), nb, PB(partials), ctl, lidx);
+  if (tm) (void)hipEventRecord(tm->e1, st);
+  hipLaunchKernelGGL(k_cg_xr<TV>, dim3(nb), dim3(KTPB), 0, st, x, r, P0, P1, q, A.n, PB(partials), nb,
+                     PA(partials), ctl);
   return hipGetLastError();
 }
 
 // ============================================================================ GMRES
+// One cycle of GMRES(m), CGS2, two streaming kernels per Arnoldi step.  Columns of V
+// are kept raw with a scale: v_l = vs[l] V[:, l].  T is a scratch column.
+//
+//   F(j): finalise column j, w''_j = w'_j - sum_{l<j} g_l v_l, where w'_j (in T) is the
+//         once-orthogonalised vector of step j-1 and g its second-pass coefficients
+//         (reduced from G(j-1)'s partials; column j-1 of H is h1 + g); ||w''_j||^2;
+//         y = A w''_j evaluated as A w'_j - sum_{l<j} g_l A v_l with the Arnoldi
+//         relation A v_l = sum_{k<=l} H_kl v_k + w''_{l+1}, so the SpMV reads the
+//         complete w'_j; y (raw) into V[:, j+1]; partial dots V[:, k]^T y, k <= j.
+//   G(j): beta_j = ||w''_j|| closes step j-1 (Givens rotation, residual estimate,
+//         end-of-cycle test); h1 = V_j^T A v_j; w'_{j+1} = A v_j - V h1 into T;
+//         partial dots V[:, k]^T w'_{j+1} (the second pass of step j).
+// F(0) instead reduces the start kernel's partials (||r||^2, ||b||^2) and opens the
+// cycle.  After G(m-1): F(m) in finalise-only mode and a one-block close of step m-1;
+// then the update x += V y.  The pair (F, G) reads V twice per step, the same as
+// CGS2 needs for its two projections, and the second projection of step j shares
+// the pass of the SpMV of step j + 1.
+//
+// Partial rows: start [||r||^2, ||b||^2] -> PA; F: [||w''_j||^2, V_j^T y, V_{0..j-1}^T y]
+// -> PB; G: [V_{0..j}^T w'] -> PA.
+
 template <typename VT, typename TV>
 __global__ __launch_bounds__(KTPB) void k_gm_start(const int *rowptr, const int *col, const VT *val,
                                                    const TV *b, const TV *x, TV *V, int64_t n, int restart_mode,
@@ -297,7 +338,7 @@ __global__ __launch_bounds__(KTPB) void k_gm_start(const int *rowptr, const int 
   if (!s_go) return;
   double acc[2] = {0.0, 0.0};
   KTILES(r0, n) {
-    const double ax = tile_spmv(rowptr, col, val, x, n, r0, prod);
+    const double ax = tile_spmv<KTPB>(rowptr, col, val, x, n, r0, prod);
     const int64_t i = r0 + threadIdx.x;
     if (i < n) {
       const double bi = (double)b[i];
@@ -311,44 +352,7 @@ __global__ __launch_bounds__(KTPB) void k_gm_start(const int *rowptr, const int 
   kstore<2>(acc, 2, red, Pout + (size_t)blockIdx.x * KW);
 }
 
-// one block: stopping test on the (true) residual and set-up of a new cycle
-__global__ __launch_bounds__(KTPB) void k_gm_start_close(const double *Pin, int nblk, int restart_mode, Ctl *ctl) {
-  __shared__ double outv[2];
-  __shared__ double scratch[KTPB];
-  __shared__ int s_go;
-  if (threadIdx.x == 0) s_go = !restart_mode || ctl->state == ST_RUN;
-  __syncthreads();
-  if (!s_go) return;
-  final_sum(Pin, nblk, KW, 2, outv, scratch);
-  if (threadIdx.x != 0) return;
-  if (!restart_mode) {
-    ctl->bnorm = sqrt(outv[1]);
-    ctl->iters = 0;
-    ctl->restarts = 0;
-  }
-  const double beta = sqrt(outv[0]), bn = ctl->bnorm;
-  const double rel = bn > 0.0 ? beta / bn : 0.0;
-  ctl->relres = rel;
-  if (!restart_mode) ctl->relres0 = rel;
-  if (bn == 0.0)
-    ctl->state = ST_ZERO_RHS;
-  else if (beta <= ctl->tol * bn)
-    ctl->state = ST_CONV;
-  else if (!isfinite(beta))
-    ctl->state = ST_BREAK;
-  else if (ctl->iters >= ctl->maxit)
-    ctl->state = ST_MAXIT;
-  else {
-    if (restart_mode) ctl->restarts += 1;
-    ctl->state = ST_RUN;
-    ctl->active = 1;
-    ctl->jend = 0;
-    ctl->gnext[0] = beta;
-    ctl->vs[0] = 1.0 / beta;
-  }
-}
-
-// Close Arnoldi step j given hn = ||w_j||: rotate the raw column j, new Givens
+// Close Arnoldi step j given hn = ||w''_{j+1}||: rotate the raw column j, new Givens
 // rotation, rotated right-hand side, cycle-end test.  `it` = global iteration number
 // of step j (1-based).  Called by all threads of a block: the inputs are staged in
 // LDS in parallel, thread 0 does the scalar recurrence from LDS.  Every block computes
@@ -383,8 +387,8 @@ __device__ inline bool gm_close_block(int j, double hn, int it, Ctl *ctl, bool p
     col[j] = rr;
     const double gj = s_gj;
     const double gam_j = c * gj, gnext = -s * gj;
-    const bool end = fabs(gnext) <= ctl->tol * ctl->bnorm || hn == 0.0 || it >= ctl->maxit ||
-                     j + 1 >= ctl->restart || !isfinite(gnext);
+    const bool est_conv = fabs(gnext) <= ctl->tol * ctl->bnorm;
+    const bool end = est_conv || hn == 0.0 || it >= ctl->maxit || j + 1 >= ctl->restart || !isfinite(gnext);
     *s_vs = hn > 0.0 ? 1.0 / hn : 0.0;
     s_endf = end ? 1 : 0;
     if (persist) {
@@ -396,6 +400,7 @@ __device__ inline bool gm_close_block(int j, double hn, int it, Ctl *ctl, bool p
       ctl->iters = it;
       ctl->jend = j + 1;
       if (end) ctl->active = 0;
+      if (est_conv && ctl->trust_est) ctl->conv_pending = 1;
     }
   }
   __syncthreads();
@@ -404,120 +409,191 @@ __device__ inline bool gm_close_block(int j, double hn, int it, Ctl *ctl, bool p
   return s_endf != 0;
 }
 
-// step j, kernel 1: [close step j-1 if fresh] w = A v_j into V[:, j+1]; partials V_l^T w
+// F(j); mode 0: first cycle, 1: restart cycle (both only matter for j = 0), 2: the
+// finalise-only step j = m.
 template <typename VT, typename TV, int RB>
-__global__ __launch_bounds__(KTPB) void k_gm_a1(const int *rowptr, const int *col, const VT *val, TV *V, int64_t n,
-                                                int64_t ld, int j, int it, int fresh, const double *Pin, int nblk,
-                                                double *Pout, Ctl *ctl) {
-  __shared__ double red[KNW * RB];
-  __shared__ double outv[1];
+__global__ __launch_bounds__(KTPB) void k_gm_f(const int *rowptr, const int *col, const VT *val, TV *V, TV *T,
+                                               int64_t n, int64_t ld, int j, int mode, const double *Pin, int nblk,
+                                               double *Pout, Ctl *ctl, int lidx) {
+  const int LD = MAXR + 1;
+  __shared__ double red[KNW * (RB + 2)];
+  __shared__ double outv[RB + 2];
   __shared__ double scratch[KTPB];
   __shared__ double prod[SPMV_CAP];
-  __shared__ double s_vs;
-  if (!block_running(ctl, true)) return;
-  if (fresh) {
-    final_sum(Pin, nblk, KW, 1, outv, scratch);
-    if (gm_close_block(j - 1, sqrt(outv[0]), it - 1, ctl, blockIdx.x == 0, &s_vs)) return;
+  __shared__ double gsh[RB], fco[RB], cco[RB + 1];
+  __shared__ int s_go, s_open;
+  if (j == 0) {
+    // open the cycle from the start kernel's partials
+    if (threadIdx.x == 0) s_go = (mode == 0) || ctl->state == ST_RUN;
+    __syncthreads();
+    if (!s_go) return;
+    final_sum(Pin, nblk, KW, 2, outv, scratch);
+    if (threadIdx.x == 0) {
+      const bool persist = blockIdx.x == 0;
+      const bool accept = mode != 0 && ctl->trust_est && ctl->conv_pending;
+      const int st = residual_decide(outv[0], outv[1], mode == 0 ? 0 : 1, ctl, persist, accept);
+      if (persist && st == ST_RUN) {
+        ctl->conv_pending = 0;
+        const double beta = sqrt(outv[0]);
+        ctl->active = 1;
+        ctl->jend = 0;
+        ctl->ibase = mode == 0 ? 0 : ctl->iters;
+        ctl->gnext[0] = beta;
+        ctl->vs[0] = 1.0 / beta;
+      }
+      s_open = st == ST_RUN;
+    }
+    __syncthreads();
+    if (!s_open) return;
+    for (int l = threadIdx.x; l <= RB; l += blockDim.x) {
+      if (l < RB) fco[l] = 0.0;
+      cco[l] = 0.0;
+    }
   } else {
-    if (threadIdx.x == 0) s_vs = ctl->vs[j];
+    if (!block_running(ctl, true)) return;
+    final_sum(Pin, nblk, KW, j, outv, scratch);
+    // second-pass coefficients of w'_j and the completed column j - 1 of H
+    for (int l = threadIdx.x; l < RB; l += blockDim.x) {
+      const double g = (l < j) ? outv[l] * ctl->vs[l] : 0.0;
+      gsh[l] = g;
+      fco[l] = (l < j) ? g * ctl->vs[l] : 0.0;
+      if (blockIdx.x == 0 && l < j) ctl->Hraw[l + (j - 1) * LD] = ctl->h1[l] + g;
+    }
+    __syncthreads();
+    if (mode != 2) {
+      // coefficients of A (sum_{l<j} g_l v_l) on the raw columns 0..j
+      for (int k = threadIdx.x; k <= RB; k += blockDim.x) {
+        double c = 0.0;
+        if (k < j) {
+          double s = 0.0;
+          for (int l = k; l < j; ++l) {
+            const double h = (l == j - 1) ? ctl->h1[k] + gsh[k] : ctl->Hraw[k + l * LD];
+            s += gsh[l] * h;
+          }
+          c = s * ctl->vs[k];
+        }
+        if (k >= 1 && k <= j) c += gsh[k - 1];
+        cco[k] = c;
+      }
+    }
     __syncthreads();
   }
-  const double vsj = s_vs;
-  const TV *vj = V + (size_t)j * ld;
-  TV *w = V + (size_t)(j + 1) * ld;
-  double acc[RB];
+  if (lidx >= 0 && blockIdx.x == 0 && threadIdx.x == 0) ctl->work_log[lidx] = 1;
+  const TV *src = (j == 0) ? V : T;
+  TV *wcol = V + (size_t)j * ld;
+  TV *ycol = V + (size_t)(j + 1) * ld;
+  const double cj = cco[j < RB ? j : RB];
+  double ex[2] = {0.0, 0.0};  // ||w''_j||^2, V[:, j]^T y
+  double acc[RB];             // V[:, k]^T y, k < j
 #pragma unroll
   for (int l = 0; l < RB; ++l) acc[l] = 0.0;
   KTILES(r0, n) {
-    const double s = tile_spmv(rowptr, col, val, vj, n, r0, prod) * vsj;
     const int64_t i = r0 + threadIdx.x;
-    if (i < n) {
-      const TV ws = (TV)s;
-      w[i] = ws;
-      const double wd = (double)ws;
+    const int64_t ic = i < n ? i : n - 1;
+    // the row's column values are requested before the SpMV so their latency overlaps
+    // its loads; every load is issued (columns past the live ones re-read a live
+    // column and are masked), so no branch separates them
+    double vl[RB];
 #pragma unroll
-      for (int l = 0; l < RB; ++l)
-        if (l <= j) acc[l] += (double)V[(size_t)l * ld + i] * wd;
+    for (int k = 0; k < RB; ++k) {
+      const double v = (double)V[(size_t)(k < j ? k : (j > 0 ? j - 1 : 0)) * ld + ic];
+      vl[k] = (k < j) ? v : 0.0;
+    }
+    const double s0 = (double)src[ic];
+    double ax = 0.0;
+    if (mode != 2) ax = tile_spmv<KTPB>(rowptr, col, val, src, n, r0, prod);
+    if (i < n) {
+      double w = s0;
+#pragma unroll
+      for (int k = 0; k < RB; ++k) w -= fco[k] * vl[k];
+      const TV ws = (TV)w;
+      if (j > 0 && mode != 2) wcol[i] = ws;
+      const double wd = (double)ws;
+      ex[0] += wd * wd;
+      if (mode != 2) {
+        double y = ax - cj * wd;
+#pragma unroll
+        for (int k = 0; k < RB; ++k) y -= cco[k] * vl[k];
+        const TV ys = (TV)y;
+        ycol[i] = ys;
+        const double yd = (double)ys;
+        ex[1] += wd * yd;
+#pragma unroll
+        for (int k = 0; k < RB; ++k) acc[k] += vl[k] * yd;
+      }
     }
   }
-  kstore<RB>(acc, j + 1, red, Pout + (size_t)blockIdx.x * KW);
+  kstore2<RB>(ex, acc, mode == 2 ? 1 : j + 2, red, Pout + (size_t)blockIdx.x * KW);
 }
 
-// kernel 2: h1 = reduce(partials) * vs; w -= sum h1_l v_l; partials V_l^T w
+// G(j)
 template <typename TV, int RB>
-__global__ __launch_bounds__(KTPB) void k_gm_a2(TV *V, int64_t n, int64_t ld, int j, const double *Pin, int nblk,
-                                                double *Pout, Ctl *ctl) {
+__global__ __launch_bounds__(KTPB) void k_gm_g(const TV *V, TV *T, int64_t n, int64_t ld, int j, const double *Pin,
+                                               int nblk, double *Pout, Ctl *ctl) {
   __shared__ double red[KNW * RB];
-  __shared__ double outv[RB];
+  __shared__ double outv[RB + 2];
   __shared__ double scratch[KTPB];
   __shared__ double coef[RB];
+  __shared__ double s_vs;
+  __shared__ int s_ibase;
   if (!block_running(ctl, true)) return;
-  final_sum(Pin, nblk, KW, j + 1, outv, scratch);
-  for (int l = threadIdx.x; l < RB; l += blockDim.x) {
-    const double h1 = (l <= j) ? outv[l] * ctl->vs[l] : 0.0;
-    coef[l] = h1 * ((l <= j) ? ctl->vs[l] : 0.0);
-    if (blockIdx.x == 0 && l <= j) ctl->h1[l] = h1;
+  if (threadIdx.x == 0) s_ibase = ctl->ibase;
+  final_sum(Pin, nblk, KW, j + 2, outv, scratch);
+  if (j > 0) {
+    if (gm_close_block(j - 1, sqrt(outv[0]), s_ibase + j, ctl, blockIdx.x == 0, &s_vs)) return;
+  } else {
+    if (threadIdx.x == 0) s_vs = ctl->vs[0];
+    __syncthreads();
+  }
+  const double vsj = s_vs;
+  // h1_k = v_k^T A v_j = vs[k] vs[j] V[:, k]^T y
+  for (int k = threadIdx.x; k < RB; k += blockDim.x) {
+    double c = 0.0;
+    if (k <= j) {
+      const double vk = (k == j) ? vsj : ctl->vs[k];
+      const double dk = (k == j) ? outv[1] : outv[2 + k];
+      const double h1 = vk * dk * vsj;
+      if (blockIdx.x == 0) ctl->h1[k] = h1;
+      c = h1 * vk;
+    }
+    coef[k] = c;
   }
   __syncthreads();
-  TV *w = V + (size_t)(j + 1) * ld;
+  const TV *ycol = V + (size_t)(j + 1) * ld;
   double acc[RB];
 #pragma unroll
   for (int l = 0; l < RB; ++l) acc[l] = 0.0;
+#pragma unroll 1
   KROWS(i, n) {
+    // compiler barrier: re-read the LDS coefficients per row instead of holding all of
+    // them in registers next to the column values and the partial dots
+    __asm__ volatile("" ::: "memory");
     double vl[RB];
-    double wi = (double)w[i];
 #pragma unroll
-    for (int l = 0; l < RB; ++l) {
-      vl[l] = (l <= j) ? (double)V[(size_t)l * ld + i] : 0.0;
-      wi -= coef[l] * vl[l];
+    for (int k = 0; k < RB; ++k) {
+      const double v = (double)V[(size_t)(k <= j ? k : j) * ld + i];
+      vl[k] = (k <= j) ? v : 0.0;
     }
-    const TV ws = (TV)wi;
-    w[i] = ws;
+    double w = vsj * (double)ycol[i];
+#pragma unroll
+    for (int k = 0; k < RB; ++k) w -= coef[k] * vl[k];
+    const TV ws = (TV)w;
+    T[i] = ws;
     const double wd = (double)ws;
 #pragma unroll
-    for (int l = 0; l < RB; ++l) acc[l] += vl[l] * wd;
+    for (int k = 0; k < RB; ++k) acc[k] += vl[k] * wd;
   }
   kstore<RB>(acc, j + 1, red, Pout + (size_t)blockIdx.x * KW);
 }
 
-// kernel 3: h2 = reduce(partials) * vs; raw column j = h1 + h2; w -= sum h2_l v_l; partial ||w||^2
-template <typename TV, int RB>
-__global__ __launch_bounds__(KTPB) void k_gm_a3(TV *V, int64_t n, int64_t ld, int j, const double *Pin, int nblk,
-                                                double *Pout, Ctl *ctl) {
-  __shared__ double red[KNW];
-  __shared__ double outv[RB];
-  __shared__ double scratch[KTPB];
-  __shared__ double coef[RB];
-  if (!block_running(ctl, true)) return;
-  final_sum(Pin, nblk, KW, j + 1, outv, scratch);
-  for (int l = threadIdx.x; l < RB; l += blockDim.x) {
-    const double h2 = (l <= j) ? outv[l] * ctl->vs[l] : 0.0;
-    coef[l] = h2 * ((l <= j) ? ctl->vs[l] : 0.0);
-    if (blockIdx.x == 0 && l <= j) ctl->Hraw[l + j * (MAXR + 1)] = ctl->h1[l] + h2;
-  }
-  __syncthreads();
-  TV *w = V + (size_t)(j + 1) * ld;
-  double acc[1] = {0.0};
-  KROWS(i, n) {
-    double wi = (double)w[i];
-#pragma unroll
-    for (int l = 0; l < RB; ++l)
-      if (l <= j) wi -= coef[l] * (double)V[(size_t)l * ld + i];
-    const TV ws = (TV)wi;
-    w[i] = ws;
-    const double wd = (double)ws;
-    acc[0] += wd * wd;
-  }
-  kstore<1>(acc, 1, red, Pout + (size_t)blockIdx.x * KW);
-}
-
-__global__ __launch_bounds__(KTPB) void k_gm_close(const double *Pin, int nblk, int j, int it, Ctl *ctl) {
+// close of the last step of a cycle (after the finalise-only F(m))
+__global__ __launch_bounds__(KTPB) void k_gm_close(const double *Pin, int nblk, int j, Ctl *ctl) {
   __shared__ double outv[1];
   __shared__ double scratch[KTPB];
   __shared__ double s_vs;
   if (!block_running(ctl, true)) return;
   final_sum(Pin, nblk, KW, 1, outv, scratch);
-  gm_close_block(j, sqrt(outv[0]), it, ctl, true, &s_vs);
+  gm_close_block(j, sqrt(outv[0]), ctl->ibase + j + 1, ctl, true, &s_vs);
 }
 
 // End of a cycle: every block solves R y = gam (m x m upper triangular, staged in
@@ -549,11 +625,14 @@ __global__ __launch_bounds__(KTPB) void k_gm_update(TV *x, const TV *V, int64_t 
     for (int i = m; i < RB; ++i) coef[i] = 0.0;
   }
   __syncthreads();
+  if (m == 0) return;
   KROWS(i, n) {
     double s = (double)x[i];
 #pragma unroll
-    for (int l = 0; l < RB; ++l)
-      if (l < m) s += coef[l] * (double)V[(size_t)l * ld + i];
+    for (int l = 0; l < RB; ++l) {
+      const double v = (double)V[(size_t)(l < m ? l : m - 1) * ld + i];
+      s += (l < m) ? coef[l] * v : 0.0;
+    }
     x[i] = (TV)s;
   }
 }
@@ -568,65 +647,87 @@ hipError_t launch_gm_start(const CsrView &A, const TV *b, const TV *x, TV *V, in
   else
     hipLaunchKernelGGL((k_gm_start<double, TV>), dim3(nb), dim3(KTPB), 0, st, A.rowptr, A.col,
                        (const double *)A.val, b, x, V, A.n, restart_mode, PA(partials), ctl);
-  hipLaunchKernelGGL(k_gm_start_close, dim3(1), dim3(KTPB), 0, st, PA(partials), nb, restart_mode, ctl);
   return hipGetLastError();
 }
 
 template <typename TV, int RB>
-static void gm_step_rb(const CsrView &A, TV *V, int64_t ld, int j, int it, int fresh, double *partials, Ctl *ctl,
-                       hipStream_t st) {
+static void gm_f_rb(const CsrView &A, TV *V, TV *T, int64_t ld, int j, int mode, double *partials, Ctl *ctl,
+                    hipStream_t st, const KTiming *tm = nullptr) {
   const int nb = kblocks(A.n);
+  const int lidx = tm ? tm->lidx : -1;
+  if (tm) (void)hipEventRecord(tm->e0, st);
   if (A.fp32)
-    hipLaunchKernelGGL((k_gm_a1<float, TV, RB>), dim3(nb), dim3(KTPB), 0, st, A.rowptr, A.col,
-                       (const float *)A.val, V, A.n, ld, j, it, fresh, PC(partials), nb, PA(partials), ctl);
+    hipLaunchKernelGGL((k_gm_f<float, TV, RB>), dim3(nb), dim3(KTPB), 0, st, A.rowptr, A.col, (const float *)A.val,
+                       V, T, A.n, ld, j, mode, PA(partials), nb, PB(partials), ctl, lidx);
   else
-    hipLaunchKernelGGL((k_gm_a1<double, TV, RB>), dim3(nb), dim3(KTPB), 0, st, A.rowptr, A.col,
-                       (const double *)A.val, V, A.n, ld, j, it, fresh, PC(partials), nb, PA(partials), ctl);
-  hipLaunchKernelGGL((k_gm_a2<TV, RB>), dim3(nb), dim3(KTPB), 0, st, V, A.n, ld, j, PA(partials), nb,
-                     PB(partials), ctl);
-  hipLaunchKernelGGL((k_gm_a3<TV, RB>), dim3(nb), dim3(KTPB), 0, st, V, A.n, ld, j, PB(partials), nb,
-                     PC(partials), ctl);
+    hipLaunchKernelGGL((k_gm_f<double, TV, RB>), dim3(nb), dim3(KTPB), 0, st, A.rowptr, A.col,
+                       (const double *)A.val, V, T, A.n, ld, j, mode, PA(partials), nb, PB(partials), ctl, lidx);
+  if (tm) (void)hipEventRecord(tm->e1, st);
 }
 
-// it = global iteration number of step j (1-based)
+// Arnoldi step j of a cycle: F(j), G(j).  first_mode: 0 first cycle, 1 restart
+// (used at j = 0).
 template <typename TV>
-hipError_t launch_gm_step_it(const CsrView &A, TV *V, int64_t ld, int j, int it, int fresh, double *partials,
-                             Ctl *ctl, hipStream_t st) {
-  if (j < 16)
-    gm_step_rb<TV, 16>(A, V, ld, j, it, fresh, partials, ctl, st);
-  else if (j < 32)
-    gm_step_rb<TV, 32>(A, V, ld, j, it, fresh, partials, ctl, st);
+hipError_t launch_gm_step(const CsrView &A, TV *V, TV *T, int64_t ld, int j, int first_mode, double *partials,
+                          Ctl *ctl, hipStream_t st, const KTiming *tm) {
+  const int nb = kblocks(A.n);
+  const int mode = j == 0 ? first_mode : 0;
+  if (j <= 8)
+    gm_f_rb<TV, 8>(A, V, T, ld, j, mode, partials, ctl, st, tm);
+  else if (j <= 16)
+    gm_f_rb<TV, 16>(A, V, T, ld, j, mode, partials, ctl, st, tm);
   else
-    gm_step_rb<TV, 64>(A, V, ld, j, it, fresh, partials, ctl, st);
+    gm_f_rb<TV, 32>(A, V, T, ld, j, mode, partials, ctl, st, tm);
+  if (j < 8)
+    hipLaunchKernelGGL((k_gm_g<TV, 8>), dim3(nb), dim3(KTPB), 0, st, V, T, A.n, ld, j, PB(partials), nb,
+                       PA(partials), ctl);
+  else if (j < 16)
+    hipLaunchKernelGGL((k_gm_g<TV, 16>), dim3(nb), dim3(KTPB), 0, st, V, T, A.n, ld, j, PB(partials), nb,
+                       PA(partials), ctl);
+  else
+    hipLaunchKernelGGL((k_gm_g<TV, 32>), dim3(nb), dim3(KTPB), 0, st, V, T, A.n, ld, j, PB(partials), nb,
+                       PA(partials), ctl);
   return hipGetLastError();
 }
 
-hipError_t launch_gm_close_it(double *partials, int64_t n, int j, int it, Ctl *ctl, hipStream_t st) {
-  hipLaunchKernelGGL(k_gm_close, dim3(1), dim3(KTPB), 0, st, PC(partials), kblocks(n), j, it, ctl);
+// end of a cycle of m steps: F(m) finalise-only, close of step m - 1
+template <typename TV>
+hipError_t launch_gm_finish(const CsrView &A, TV *V, TV *T, int64_t ld, int m, double *partials, Ctl *ctl,
+                            hipStream_t st) {
+  const int nb = kblocks(A.n);
+  if (m <= 8)
+    gm_f_rb<TV, 8>(A, V, T, ld, m, 2, partials, ctl, st);
+  else if (m <= 16)
+    gm_f_rb<TV, 16>(A, V, T, ld, m, 2, partials, ctl, st);
+  else
+    gm_f_rb<TV, 32>(A, V, T, ld, m, 2, partials, ctl, st);
+  hipLaunchKernelGGL(k_gm_close, dim3(1), dim3(KTPB), 0, st, PB(partials), nb, m - 1, ctl);
   return hipGetLastError();
 }
 
 template <typename TV>
 hipError_t launch_gm_update(TV *x, const TV *V, int64_t n, int64_t ld, int restart, Ctl *ctl, hipStream_t st) {
   const int nb = kblocks(n);
-  if (restart <= 16)
+  if (restart <= 8)
+    hipLaunchKernelGGL((k_gm_update<TV, 8>), dim3(nb), dim3(KTPB), 0, st, x, V, n, ld, ctl);
+  else if (restart <= 16)
     hipLaunchKernelGGL((k_gm_update<TV, 16>), dim3(nb), dim3(KTPB), 0, st, x, V, n, ld, ctl);
-  else if (restart <= 32)
-    hipLaunchKernelGGL((k_gm_update<TV, 32>), dim3(nb), dim3(KTPB), 0, st, x, V, n, ld, ctl);
   else
-    hipLaunchKernelGGL((k_gm_update<TV, 64>), dim3(nb), dim3(KTPB), 0, st, x, V, n, ld, ctl);
+    hipLaunchKernelGGL((k_gm_update<TV, 32>), dim3(nb), dim3(KTPB), 0, st, x, V, n, ld, ctl);
   return hipGetLastError();
 }
 
 #define SACC_INSTANTIATE_KRYLOV(TV)                                                                              \
-  template hipError_t launch_cg_start_k<TV>(const CsrView &, const TV *, const TV *, TV *, TV *, int, int,       \
-                                            double *, Ctl *, hipStream_t);                                       \
-  template hipError_t launch_cg_iter_k<TV>(const CsrView &, TV *, TV *, TV *, TV *, int, int, int, double *,     \
-                                           Ctl *, hipStream_t);                                                  \
+  template hipError_t launch_cg_start_k<TV>(const CsrView &, const TV *, const TV *, TV *, int, double *, Ctl *, \
+                                            hipStream_t);                                                        \
+  template hipError_t launch_cg_iter<TV>(const CsrView &, TV *, TV *, TV *, TV *, double *, Ctl *, hipStream_t,  \
+                                         const KTiming *);                                                       \
   template hipError_t launch_gm_start<TV>(const CsrView &, const TV *, const TV *, TV *, int, double *, Ctl *,   \
                                           hipStream_t);                                                          \
-  template hipError_t launch_gm_step_it<TV>(const CsrView &, TV *, int64_t, int, int, int, double *, Ctl *,      \
-                                            hipStream_t);                                                        \
+  template hipError_t launch_gm_step<TV>(const CsrView &, TV *, TV *, int64_t, int, int, double *, Ctl *,        \
+                                         hipStream_t, const KTiming *);                                          \
+  template hipError_t launch_gm_finish<TV>(const CsrView &, TV *, TV *, int64_t, int, double *, Ctl *,           \
+                                           hipStream_t);                                                         \
   template hipError_t launch_gm_update<TV>(TV *, const TV *, int64_t, int64_t, int, Ctl *, hipStream_t);
 
 SACC_INSTANTIATE_KRYLOV(double)
@@ -637,6 +738,6 @@ SACC_INSTANTIATE_KRYLOV(float)
 // power of two apart map onto the same memory channels)
 int64_t padded_ld(int64_t n) { return (n + 511) / 512 * 512 + 576; }
 
-size_t krylov_partials_doubles() { return (size_t)3 * KMAXBLK * KW; }
+size_t krylov_partials_doubles() { return (size_t)2 * KMAXBLK * KW; }
 
 }  // namespace sacc

@@ -21,7 +21,8 @@ SA_SKETCH_GAUSSIAN, SA_SKETCH_SRHT = 0, 1
 SA_GUESS_PROJECTION, SA_GUESS_ZERO, SA_GUESS_PREVIOUS = 0, 1, 2
 
 EXPORTS = ("sa_workspace_bytes", "sa_init_sequence", "sa_push_solution", "sa_initial_guess",
-           "sa_solve", "sa_destroy_sequence", "sa_status_string", "sa_spmv", "sa_copy_state")
+           "sa_solve", "sa_destroy_sequence", "sa_status_string", "sa_spmv", "sa_copy_state",
+           "sa_profile_enable", "sa_profile_read")
 
 
 class SaConfig(ctypes.Structure):
@@ -32,7 +33,7 @@ class SaConfig(ctypes.Structure):
         ("precision", ctypes.c_int32), ("inner_tol", ctypes.c_double),
         ("max_refine", ctypes.c_int32), ("guess", ctypes.c_int32),
         ("rank_tol_sketch", ctypes.c_double), ("rank_tol_chol", ctypes.c_double),
-        ("seed", ctypes.c_uint64), ("poll", ctypes.c_int32), ("reserved", ctypes.c_int32),
+        ("seed", ctypes.c_uint64), ("poll", ctypes.c_int32), ("inner_maxit", ctypes.c_int32),
     ]
 
 
@@ -54,6 +55,13 @@ class SaInfo(ctypes.Structure):
 
     def as_dict(self) -> dict:
         return {name: getattr(self, name) for name, _ in self._fields_}
+
+
+class SaKernelProf(ctypes.Structure):
+    _fields_ = [
+        ("name", ctypes.c_char * 48), ("launches", ctypes.c_int64), ("ms", ctypes.c_double),
+        ("bytes", ctypes.c_double),
+    ]
 
 
 _lib = None
@@ -80,6 +88,8 @@ def lib() -> ctypes.CDLL:
     L.sa_status_string.restype = ctypes.c_char_p
     L.sa_spmv.argtypes = [P(SaCsr), vp, vp, vp]
     L.sa_copy_state.argtypes = [vp, i32, vp, sz, vp]
+    L.sa_profile_enable.argtypes = [vp, i32]
+    L.sa_profile_read.argtypes = [vp, P(SaKernelProf), i32, P(i32)]
     for name in EXPORTS:
         if name != "sa_status_string":
             getattr(L, name).restype = i32

@@ -78,7 +78,7 @@ class Sequence:
                  solver: str = "cg", restart: int = 30, tol: float = 1e-8, maxit: int = 200000,
                  precision: str = "fp64", projection: str = "galerkin", guess: str = "projection",
                  seed: int = 0, rank_tol_sketch: float = 0.0, rank_tol_chol: float = 0.0,
-                 inner_tol: float = 1e-4, max_refine: int = 10, poll: int = 0, device="cuda",
+                 inner_tol: float = 1e-4, max_refine: int = 10, inner_maxit: int = 0, poll: int = 0, device="cuda",
                  stream=None):
         self.n, self.M = n, M
         self.s = 2 * M if s is None else s
@@ -88,7 +88,7 @@ class Sequence:
             solver=_SOLVER[solver], restart=restart, tol=tol, maxit=maxit,
             precision=_PREC[precision], inner_tol=inner_tol, max_refine=max_refine,
             guess=_GUESS[guess], rank_tol_sketch=rank_tol_sketch, rank_tol_chol=rank_tol_chol,
-            seed=seed, poll=poll, reserved=0)
+            seed=seed, poll=poll, inner_maxit=inner_maxit)
         L = nv.lib()
         nbytes = ctypes.c_size_t(0)
         nv.check(L.sa_workspace_bytes(ctypes.byref(self.cfg), ctypes.byref(nbytes)), "sa_workspace_bytes")
@@ -146,6 +146,20 @@ class Sequence:
         return x, s
 
     # ------------------------------------------------------------------ inspection
+    def profile_enable(self, enable: bool = True):
+        """Time the dominant Krylov kernels of later solves (HIP events per launch)."""
+        nv.check(nv.lib().sa_profile_enable(self._h, 1 if enable else 0), "sa_profile_enable")
+
+    def profile_read(self) -> list:
+        """[{name, launches, ms, bytes}] for the kernels timed since profile_enable."""
+        L = nv.lib()
+        cnt = ctypes.c_int32(0)
+        nv.check(L.sa_profile_read(self._h, None, 0, ctypes.byref(cnt)), "sa_profile_read")
+        arr = (nv.SaKernelProf * max(cnt.value, 1))()
+        nv.check(L.sa_profile_read(self._h, arr, cnt.value, ctypes.byref(cnt)), "sa_profile_read")
+        return [dict(name=r.name.decode(), launches=int(r.launches), ms=float(r.ms), bytes=float(r.bytes))
+                for r in arr[:cnt.value]]
+
     def copy_state(self, what: str) -> np.ndarray:
         L = nv.lib()
         if what == "SX":

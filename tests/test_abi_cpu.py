@@ -42,7 +42,7 @@ def test_every_declared_symbol_is_exported(nv):
 def _cfg(nv, **over):
     kw = dict(n=4096, M=10, s=20, sketch=0, projection=0, solver=0, restart=30, tol=1e-10, maxit=100,
               precision=0, inner_tol=1e-4, max_refine=10, guess=0, rank_tol_sketch=0.0,
-              rank_tol_chol=0.0, seed=0, poll=0, reserved=0)
+              rank_tol_chol=0.0, seed=0, poll=0, inner_maxit=0)
     kw.update(over)
     return nv.SaConfig(**kw)
 
@@ -93,9 +93,11 @@ def test_struct_layout_matches_header(nv, tmp_path):
 #include "sacc.h"
 #define P(T, f) printf(#T "." #f " %zu\n", offsetof(T, f));
 int main(void) {
-  printf("sa_config %zu\nsa_csr %zu\nsa_info %zu\n", sizeof(sa_config), sizeof(sa_csr), sizeof(sa_info));
+  printf("sa_config %zu\nsa_csr %zu\nsa_info %zu\nsa_kernel_prof %zu\n", sizeof(sa_config), sizeof(sa_csr),
+         sizeof(sa_info), sizeof(sa_kernel_prof));
   P(sa_config, tol) P(sa_config, seed) P(sa_config, poll) P(sa_config, rank_tol_chol)
   P(sa_csr, val_dev) P(sa_csr, val_is_fp32) P(sa_info, relres0) P(sa_info, ms_solve)
+  P(sa_kernel_prof, launches) P(sa_kernel_prof, ms) P(sa_kernel_prof, bytes)
   return 0;
 }
 """)
@@ -105,10 +107,12 @@ int main(void) {
     assert int(lines["sa_config"]) == ctypes.sizeof(nv.SaConfig)
     assert int(lines["sa_csr"]) == ctypes.sizeof(nv.SaCsr)
     assert int(lines["sa_info"]) == ctypes.sizeof(nv.SaInfo)
+    assert int(lines["sa_kernel_prof"]) == ctypes.sizeof(nv.SaKernelProf)
     for key, v in lines.items():
         if "." in key:
             struct, field = key.split(".")
-            cls = {"sa_config": nv.SaConfig, "sa_csr": nv.SaCsr, "sa_info": nv.SaInfo}[struct]
+            cls = {"sa_config": nv.SaConfig, "sa_csr": nv.SaCsr, "sa_info": nv.SaInfo,
+                   "sa_kernel_prof": nv.SaKernelProf}[struct]
             assert getattr(cls, field).offset == int(v), key
 
 

@@ -69,9 +69,10 @@ def test_ir_contracts_per_sweep(solver):
 
 def test_ir_single_sweep_is_one_inner_solve():
     """With one sweep from x0 = 0 the answer is the inner solve of A d = fl32(b): its
-    relative residual is at the inner tolerance up to float32 rounding of b."""
+    true relative residual is at the inner tolerance up to float32 rounding of b and
+    the float32 drift of the recursive residual the inner solve stops on."""
     A, b, _ = _system(0, 24)
-    inner = 1e-5
+    inner = 1e-4
     x, info = mx.solve_ir(A, b, np.zeros_like(b), 1e-300, "cg", inner_tol=inner, max_refine=1)
     rel = np.linalg.norm(b - A @ x) / np.linalg.norm(b)
     assert rel <= inner * 1.5
