@@ -112,6 +112,11 @@ __device__ inline int residual_decide(double rho, double bb, int mode, Ctl *ctl,
   return st;
 }
 
+// entry e (0..3) of a 4-entry register array without dynamic indexing
+__device__ inline double pick4(const double (&r)[4], int e) {
+  return e == 0 ? r[0] : (e == 1 ? r[1] : (e == 2 ? r[2] : r[3]));
+}
+
 // ============================================================================ CG
 // Two streaming kernels per iteration k (1-based, numbered on the device):
 //   cg_p(k):  r_{k-1}^T r_{k-1} from the previous partials -> stopping test, beta;
@@ -186,12 +191,21 @@ __global__ __launch_bounds__(KTPB) void k_cg_p(const int *rowptr, const int *col
   __shared__ double outv[1];
   __shared__ double scratch[KTPB];
   __shared__ double prod[SPMV_CAP];
-  __shared__ int s_k, s_fresh, s_go, s_cont;
-  __shared__ double s_beta;
+  __shared__ int s_k, s_fresh, s_go, s_cont, s_maxit;
+  __shared__ double s_beta, s_tolb, s_rho2;
   if (threadIdx.x == 0) {
-    s_go = ctl->state == ST_RUN;
-    s_k = ctl->iters + 1;
-    s_fresh = (s_k == ctl->fresh_at);
+    // every control-block read of the kernel, issued together
+    const int st = ctl->state, it = ctl->iters, fa = ctl->fresh_at, mx = ctl->maxit;
+    const double tol = ctl->tol, bn = ctl->bnorm;
+    double r4[4];
+#pragma unroll
+    for (int e = 0; e < 4; ++e) r4[e] = ctl->rho[e];
+    s_go = st == ST_RUN;
+    s_k = it + 1;
+    s_fresh = (it + 1 == fa);
+    s_maxit = mx;
+    s_tolb = tol * bn;
+    s_rho2 = pick4(r4, (it + 3) & 3);  // rho of iteration k - 2 = it - 1
   }
   __syncthreads();
   if (!s_go) return;
@@ -202,15 +216,15 @@ __global__ __launch_bounds__(KTPB) void k_cg_p(const int *rowptr, const int *col
     double beta = 0.0;
     if (!fresh) {
       const double rho = outv[0];
-      if (sqrt(rho) <= ctl->tol * ctl->bnorm)
+      if (sqrt(rho) <= s_tolb)
         st = ST_CHECK;
       else if (!isfinite(rho))
         st = ST_BREAK;
       else
-        beta = rho / ctl->rho[(k - 2) & 3];
+        beta = rho / s_rho2;
       if (blockIdx.x == 0) ctl->rho[(k - 1) & 3] = rho;
     }
-    if (st == ST_RUN && k - 1 >= ctl->maxit) st = ST_MAXIT;
+    if (st == ST_RUN && k - 1 >= s_maxit) st = ST_MAXIT;
     if (blockIdx.x == 0) {
       if (st != ST_RUN) ctl->state = st;
       ctl->kcur = k;
@@ -246,9 +260,19 @@ __global__ __launch_bounds__(KTPB) void k_cg_xr(TV *x, TV *r, const TV *P0, cons
   __shared__ double red[KNW];
   __shared__ double outv[1];
   __shared__ double scratch[KTPB];
-  __shared__ int s_k;
-  if (!block_running(ctl, false)) return;
-  if (threadIdx.x == 0) s_k = ctl->kcur;
+  __shared__ int s_k, s_go;
+  __shared__ double s_rho;
+  if (threadIdx.x == 0) {
+    const int st = ctl->state, k = ctl->kcur;
+    double r4[4];
+#pragma unroll
+    for (int e = 0; e < 4; ++e) r4[e] = ctl->rho[e];
+    s_go = st == ST_RUN;
+    s_k = k;
+    s_rho = pick4(r4, (k - 1) & 3);
+  }
+  __syncthreads();
+  if (!s_go) return;
   final_sum(Pin, nblk, KW, 1, outv, scratch);
   const int k = s_k;
   const double pq = outv[0];
@@ -256,7 +280,7 @@ __global__ __launch_bounds__(KTPB) void k_cg_xr(TV *x, TV *r, const TV *P0, cons
     if (blockIdx.x == 0 && threadIdx.x == 0) ctl->state = ST_BREAK;
     return;
   }
-  const double alpha = ctl->rho[(k - 1) & 3] / pq;
+  const double alpha = s_rho / pq;
   const TV *p = (k & 1) ? P1 : P0;
   double acc[1] = {0.0};
   KROWS(i, n) {
@@ -352,32 +376,55 @@ __global__ __launch_bounds__(KTPB) void k_gm_start(const int *rowptr, const int 
   kstore<2>(acc, 2, red, Pout + (size_t)blockIdx.x * KW);
 }
 
-// Close Arnoldi step j given hn = ||w''_{j+1}||: rotate the raw column j, new Givens
-// rotation, rotated right-hand side, cycle-end test.  `it` = global iteration number
-// of step j (1-based).  Called by all threads of a block: the inputs are staged in
-// LDS in parallel, thread 0 does the scalar recurrence from LDS.  Every block computes
-// the same result; only `persist` (block 0) writes.  Returns the cycle-end flag; the
-// scale of the next basis vector is left in *s_vs (LDS).
-__device__ inline bool gm_close_block(int j, double hn, int it, Ctl *ctl, bool persist, double *s_vs) {
+// Inputs of the close of step j, staged into LDS by all threads at once (the control
+// block was written by earlier kernels, so each read is a trip to memory; issuing
+// them together costs one).
+struct CloseIn {
+  double col[MAXR + 1], cs[MAXR], sn[MAXR];
+  double gj, tolb;
+  int maxit, restart, trust;
+};
+
+__device__ inline void close_stage(int j, const Ctl *ctl, CloseIn *ci) {
   const int LD = MAXR + 1;
-  __shared__ double col[MAXR + 1], cs[MAXR], sn[MAXR];
-  __shared__ double s_gj;
-  __shared__ int s_endf;
-  for (int l = threadIdx.x; l <= j; l += blockDim.x) col[l] = ctl->Hraw[l + j * LD];
-  for (int l = threadIdx.x; l < j; l += blockDim.x) {
-    cs[l] = ctl->cs[l];
-    sn[l] = ctl->sn[l];
+  const int t = threadIdx.x;
+  if (t <= j) ci->col[t] = ctl->Hraw[t + j * LD];
+  if (t < j) {
+    ci->cs[t] = ctl->cs[t];
+    ci->sn[t] = ctl->sn[t];
   }
-  if (threadIdx.x == 0) s_gj = ctl->gnext[j];
-  __syncthreads();
+  if (t == WAVE) {
+    const double gj = ctl->gnext[j], tol = ctl->tol, bn = ctl->bnorm;
+    const int maxit = ctl->maxit, restart = ctl->restart, trust = ctl->trust_est;
+    ci->gj = gj;
+    ci->tolb = tol * bn;
+    ci->maxit = maxit;
+    ci->restart = restart;
+    ci->trust = trust;
+  }
+}
+
+// Close Arnoldi step j given hn = ||w''_{j+1}|| from the staged inputs: rotate the raw
+// column j, new Givens rotation, rotated right-hand side, cycle-end test.  `it` =
+// global iteration number of step j (1-based).  Called by all threads of a block after
+// close_stage and a barrier; thread 0 runs the scalar recurrence with the carried
+// entry in a register.  Every block computes the same result; only `persist` (block
+// 0) writes.  Returns the cycle-end flag; the scale of the next basis vector is left
+// in *s_vs (LDS).
+__device__ inline bool gm_close_block(int j, double hn, int it, CloseIn *ci, Ctl *ctl, bool persist,
+                                      double *s_vs) {
+  const int LD = MAXR + 1;
+  __shared__ int s_endf;
   if (threadIdx.x == 0) {
+    double *col = ci->col;
     col[j + 1] = hn;
+    double cur = col[0];
     for (int l = 0; l < j; ++l) {
-      const double t = cs[l] * col[l] + sn[l] * col[l + 1];
-      col[l + 1] = -sn[l] * col[l] + cs[l] * col[l + 1];
-      col[l] = t;
+      const double nxt = col[l + 1], c = ci->cs[l], s = ci->sn[l];
+      col[l] = c * cur + s * nxt;
+      cur = -s * cur + c * nxt;
     }
-    const double a = col[j];
+    const double a = cur;
     const double rr = hypot(a, hn);
     double c = 1.0, s = 0.0;
     if (rr != 0.0) {
@@ -385,10 +432,10 @@ __device__ inline bool gm_close_block(int j, double hn, int it, Ctl *ctl, bool p
       s = hn / rr;
     }
     col[j] = rr;
-    const double gj = s_gj;
+    const double gj = ci->gj;
     const double gam_j = c * gj, gnext = -s * gj;
-    const bool est_conv = fabs(gnext) <= ctl->tol * ctl->bnorm;
-    const bool end = est_conv || hn == 0.0 || it >= ctl->maxit || j + 1 >= ctl->restart || !isfinite(gnext);
+    const bool est_conv = fabs(gnext) <= ci->tolb;
+    const bool end = est_conv || hn == 0.0 || it >= ci->maxit || j + 1 >= ci->restart || !isfinite(gnext);
     *s_vs = hn > 0.0 ? 1.0 / hn : 0.0;
     s_endf = end ? 1 : 0;
     if (persist) {
@@ -400,12 +447,12 @@ __device__ inline bool gm_close_block(int j, double hn, int it, Ctl *ctl, bool p
       ctl->iters = it;
       ctl->jend = j + 1;
       if (end) ctl->active = 0;
-      if (est_conv && ctl->trust_est) ctl->conv_pending = 1;
+      if (est_conv && ci->trust) ctl->conv_pending = 1;
     }
   }
   __syncthreads();
   if (persist)
-    for (int l = threadIdx.x; l <= j; l += blockDim.x) ctl->R[l + j * LD] = col[l];
+    for (int l = threadIdx.x; l <= j; l += blockDim.x) ctl->R[l + j * LD] = ci->col[l];
   return s_endf != 0;
 }
 
@@ -430,7 +477,8 @@ __global__ __launch_bounds__(KTPB) void k_gm_f(const int *rowptr, const int *col
     final_sum(Pin, nblk, KW, 2, outv, scratch);
     if (threadIdx.x == 0) {
       const bool persist = blockIdx.x == 0;
-      const bool accept = mode != 0 && ctl->trust_est && ctl->conv_pending;
+      const int trust = ctl->trust_est, pend = ctl->conv_pending;
+      const bool accept = mode != 0 && trust && pend;
       const int st = residual_decide(outv[0], outv[1], mode == 0 ? 0 : 1, ctl, persist, accept);
       if (persist && st == ST_RUN) {
         ctl->conv_pending = 0;
@@ -450,14 +498,26 @@ __global__ __launch_bounds__(KTPB) void k_gm_f(const int *rowptr, const int *col
       cco[l] = 0.0;
     }
   } else {
-    if (!block_running(ctl, true)) return;
+    // one trip to memory for the run flag and the scalars of the previous steps
+    __shared__ double Hs[(MAXR + 1) * MAXR], vsh[MAXR + 1], h1s[MAXR + 1];
+    if (threadIdx.x == 0) s_go = (ctl->state == ST_RUN) && ctl->active;
+    for (int e = threadIdx.x; e < (j - 1) * LD; e += blockDim.x) Hs[e] = ctl->Hraw[e];
+    if (threadIdx.x < j) {
+      vsh[threadIdx.x] = ctl->vs[threadIdx.x];
+      h1s[threadIdx.x] = ctl->h1[threadIdx.x];
+    }
+    __syncthreads();
+    if (!s_go) return;
     final_sum(Pin, nblk, KW, j, outv, scratch);
     // second-pass coefficients of w'_j and the completed column j - 1 of H
     for (int l = threadIdx.x; l < RB; l += blockDim.x) {
-      const double g = (l < j) ? outv[l] * ctl->vs[l] : 0.0;
+      const double g = (l < j) ? outv[l] * vsh[l] : 0.0;
       gsh[l] = g;
-      fco[l] = (l < j) ? g * ctl->vs[l] : 0.0;
-      if (blockIdx.x == 0 && l < j) ctl->Hraw[l + (j - 1) * LD] = ctl->h1[l] + g;
+      fco[l] = (l < j) ? g * vsh[l] : 0.0;
+      if (l < j) {
+        Hs[l + (j - 1) * LD] = h1s[l] + g;
+        if (blockIdx.x == 0) ctl->Hraw[l + (j - 1) * LD] = h1s[l] + g;
+      }
     }
     __syncthreads();
     if (mode != 2) {
@@ -466,11 +526,9 @@ __global__ __launch_bounds__(KTPB) void k_gm_f(const int *rowptr, const int *col
         double c = 0.0;
         if (k < j) {
           double s = 0.0;
-          for (int l = k; l < j; ++l) {
-            const double h = (l == j - 1) ? ctl->h1[k] + gsh[k] : ctl->Hraw[k + l * LD];
-            s += gsh[l] * h;
-          }
-          c = s * ctl->vs[k];
+#pragma unroll 4
+          for (int l = k; l < j; ++l) s += gsh[l] * Hs[k + l * LD];
+          c = s * vsh[k];
         }
         if (k >= 1 && k <= j) c += gsh[k - 1];
         cco[k] = c;
@@ -535,14 +593,24 @@ __global__ __launch_bounds__(KTPB) void k_gm_g(const TV *V, TV *T, int64_t n, in
   __shared__ double scratch[KTPB];
   __shared__ double coef[RB];
   __shared__ double s_vs;
-  __shared__ int s_ibase;
-  if (!block_running(ctl, true)) return;
-  if (threadIdx.x == 0) s_ibase = ctl->ibase;
+  __shared__ double vsh[MAXR + 1];
+  __shared__ int s_ibase, s_go;
+  __shared__ CloseIn ci;
+  // one trip to memory for the run flag, the close inputs and the column scales
+  if (threadIdx.x == 0) {
+    const int st = ctl->state, act = ctl->active, ib = ctl->ibase;
+    s_go = (st == ST_RUN) && act;
+    s_ibase = ib;
+  }
+  if (j > 0) close_stage(j - 1, ctl, &ci);
+  if (threadIdx.x <= j) vsh[threadIdx.x] = ctl->vs[threadIdx.x];
+  __syncthreads();
+  if (!s_go) return;
   final_sum(Pin, nblk, KW, j + 2, outv, scratch);
   if (j > 0) {
-    if (gm_close_block(j - 1, sqrt(outv[0]), s_ibase + j, ctl, blockIdx.x == 0, &s_vs)) return;
+    if (gm_close_block(j - 1, sqrt(outv[0]), s_ibase + j, &ci, ctl, blockIdx.x == 0, &s_vs)) return;
   } else {
-    if (threadIdx.x == 0) s_vs = ctl->vs[0];
+    if (threadIdx.x == 0) s_vs = vsh[0];
     __syncthreads();
   }
   const double vsj = s_vs;
@@ -550,7 +618,7 @@ __global__ __launch_bounds__(KTPB) void k_gm_g(const TV *V, TV *T, int64_t n, in
   for (int k = threadIdx.x; k < RB; k += blockDim.x) {
     double c = 0.0;
     if (k <= j) {
-      const double vk = (k == j) ? vsj : ctl->vs[k];
+      const double vk = (k == j) ? vsj : vsh[k];
       const double dk = (k == j) ? outv[1] : outv[2 + k];
       const double h1 = vk * dk * vsj;
       if (blockIdx.x == 0) ctl->h1[k] = h1;
@@ -591,9 +659,18 @@ __global__ __launch_bounds__(KTPB) void k_gm_close(const double *Pin, int nblk, 
   __shared__ double outv[1];
   __shared__ double scratch[KTPB];
   __shared__ double s_vs;
-  if (!block_running(ctl, true)) return;
+  __shared__ int s_go, s_ibase;
+  __shared__ CloseIn ci;
+  if (threadIdx.x == 0) {
+    const int st = ctl->state, act = ctl->active, ib = ctl->ibase;
+    s_go = (st == ST_RUN) && act;
+    s_ibase = ib;
+  }
+  close_stage(j, ctl, &ci);
+  __syncthreads();
+  if (!s_go) return;
   final_sum(Pin, nblk, KW, 1, outv, scratch);
-  gm_close_block(j, sqrt(outv[0]), ctl->ibase + j + 1, ctl, true, &s_vs);
+  gm_close_block(j, sqrt(outv[0]), s_ibase + j + 1, &ci, ctl, true, &s_vs);
 }
 
 // End of a cycle: every block solves R y = gam (m x m upper triangular, staged in
@@ -605,24 +682,34 @@ __global__ __launch_bounds__(KTPB) void k_gm_update(TV *x, const TV *V, int64_t 
   __shared__ double Rs[RB * RB];
   __shared__ double gs[RB];
   __shared__ int s_m;
-  if (threadIdx.x == 0) s_m = (ctl->state == ST_RUN) ? ctl->jend : -1;
+  __shared__ double vsh[RB];
+  if (threadIdx.x == 0) {
+    const int st = ctl->state, je = ctl->jend;
+    s_m = (st == ST_RUN) ? je : -1;
+  }
+  // stage the whole triangle, right-hand side and scales at once (unused entries are
+  // never read)
+  for (int e = threadIdx.x; e < RB * RB; e += blockDim.x) {
+    const int i = e % RB, l = e / RB;
+    Rs[i + l * RB] = (i <= l) ? ctl->R[i + l * LD] : 0.0;
+  }
+  if (threadIdx.x < RB) {
+    gs[threadIdx.x] = ctl->gam[threadIdx.x];
+    vsh[threadIdx.x] = ctl->vs[threadIdx.x];
+  }
   __syncthreads();
   const int m = s_m;
   if (m < 0) return;
-  for (int e = threadIdx.x; e < m * m; e += blockDim.x) {
-    const int i = e % m, l = e / m;
-    Rs[i + l * RB] = (i <= l) ? ctl->R[i + l * LD] : 0.0;
-  }
-  for (int l = threadIdx.x; l < RB; l += blockDim.x) gs[l] = (l < m) ? ctl->gam[l] : 0.0;
-  __syncthreads();
-  if (threadIdx.x == 0) {
+  // R y = gam by columns on one wave: lane l keeps the right-hand side entry l
+  if (threadIdx.x < WAVE) {
+    const int l = threadIdx.x;
+    double g = (l < m) ? gs[l] : 0.0;
     for (int i = m - 1; i >= 0; --i) {
-      double acc = gs[i];
-      for (int l = i + 1; l < m; ++l) acc -= Rs[i + l * RB] * coef[l];
-      coef[i] = acc / Rs[i + i * RB];
+      const double yi = __shfl(g, i, WAVE) / Rs[i + i * RB];
+      if (l < i) g -= Rs[l + i * RB] * yi;
+      if (l == i) coef[i] = yi * vsh[i];
     }
-    for (int i = 0; i < m; ++i) coef[i] *= ctl->vs[i];
-    for (int i = m; i < RB; ++i) coef[i] = 0.0;
+    if (l >= m && l < RB) coef[l] = 0.0;
   }
   __syncthreads();
   if (m == 0) return;
