@@ -95,6 +95,60 @@ def spmv_gbps(sacc, torch, A, reps=200):
     return nbytes / (ms * 1e-3) / 1e9, ms, nbytes
 
 
+def mixed_3d(sacc, torch, np, warmup, steps):
+    """ms/step of the mixed mode against plain FP64 on the 128^3 float32-valued sequence."""
+    from gen import config
+
+    p3, m3 = config(2)
+    log(f"mixed_3d: assembling {warmup + steps} steps of the 128^3 sequence")
+    vals32, rhs3 = [], []
+    for i in range(warmup + steps):
+        vals32.append(p3.matrix(i, fp32=True).val)
+        rhs3.append(p3.rhs(i))
+    vals32 = np.stack(vals32)
+    rowptr3, col3 = p3.pattern()
+    v32_d = torch.as_tensor(vals32).cuda()
+    rhs_d = torch.as_tensor(np.stack(rhs3)).cuda()
+    out = {"workload": f"lognormal3d 128^3 (n={p3.n}), M={m3['M']}, Gaussian s={m3['s']}, Galerkin, CG, "
+                       f"relres {m3['tol']:g}, float32 operator", "steps_timed": f"{warmup}..{warmup + steps - 1}"}
+    for prec in ("fp64", "mixed"):
+        log(f"mixed_3d: {prec} run")
+        vd = v32_d if prec == "mixed" else v32_d.double()
+        A3 = sacc.DeviceCSR(rowptr3, col3, vals32[0] if prec == "mixed" else vals32[0].astype(np.float64))
+        ci, cw, _ = run_sequence(sacc, torch, A3, vd, rhs_d, m3, steps, warmup, precision=prec)
+        out[prec] = dict(ms_per_step=round(1e3 * cw / steps, 4),
+                         iters_per_step=float(np.mean([d["iters"] for d in ci])),
+                         refinements_per_step=float(np.mean([d["refinements"] for d in ci])),
+                         relres_max=float(max(d["relres"] for d in ci)))
+        del A3, vd
+    out["speedup_mixed_vs_fp64"] = round(out["fp64"]["ms_per_step"] / out["mixed"]["ms_per_step"], 3)
+    return out
+
+
+def committed_traffic(kernel):
+    """HBM bytes per launch of `kernel` from the committed counter summary, or None when
+    there is none or the kernel sources have changed since the counters were taken."""
+    import hashlib
+    import re
+
+    base = kernel.split("<")[0]
+    path = os.path.join(ROOT, "profiles", f"{base}_advdiff512_traffic.md")
+    if not os.path.exists(path):
+        return None
+    text = open(path).read()
+    if f"# HBM traffic of {kernel} " not in text:
+        return None
+    m_t = re.search(r"^traffic_bytes_per_launch: (\d+)", text, re.M)
+    m_h = re.search(r"^kernel_source_sha256: ([0-9a-f]+)", text, re.M)
+    if not m_t or not m_h:
+        return None
+    h = hashlib.sha256()
+    for f in ("krylov.hip", "common.h"):
+        with open(os.path.join(ROOT, "paper_2309_02156_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return int(m_t.group(1)) if h.hexdigest() == m_h.group(1) else None
+
+
 def cpu_baseline(problem, method, start, seconds):
     """The oracle on the host: history warm-started from sparse-LU solutions of the M
     steps before `start` (untimed), then steps start, start+1, ... timed until
@@ -142,6 +196,10 @@ def main():
     ap.add_argument("--cpu-seconds", type=float, default=20.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-comparators", action="store_true")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="run 3 plain 256 MiB device copies first (reference for HBM byte counters)")
+    ap.add_argument("--mixed-warmup", type=int, default=32)
+    ap.add_argument("--mixed-steps", type=int, default=8)
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py: this build runs on one GPU; --gpus {args.gpus} is not supported "
@@ -165,6 +223,15 @@ def main():
     vals_d = torch.as_tensor(vals).cuda()
     rhs_d = torch.as_tensor(rhs).cuda()
     torch.cuda.synchronize()
+
+    if args.copy_calibration:
+        src = torch.empty(32 << 20, dtype=torch.float64, device="cuda").fill_(1.0)
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        log("copy calibration: 3 copies of 268435456 bytes")
+        del src, dst
 
     log("timed run: projection")
     infos, wall, _ = run_sequence(sacc, torch, A, vals_d, rhs_d, method, args.steps, args.warmup)
@@ -191,19 +258,11 @@ def main():
             ci, cw, _ = run_sequence(sacc, torch, A, vals_d, rhs_d, method, args.steps, args.warmup, guess=kind)
             comparators[kind] = dict(ms_per_step=1e3 * cw / args.steps,
                                      iters_per_step=float(np.mean([d["iters"] for d in ci])))
-        # mixed precision on the same sequence with float32 matrix values
-        log("comparator run: mixed")
-        A32 = sacc.DeviceCSR(rowptr, col, vals[0].astype(np.float32))
-        vals32_d = vals_d.float()
-        ci, cw, _ = run_sequence(sacc, torch, A32, vals32_d, rhs_d, method, args.steps, args.warmup,
-                                 precision="mixed")
-        comparators["mixed"] = dict(ms_per_step=1e3 * cw / args.steps,
-                                    iters_per_step=float(np.mean([d["iters"] for d in ci])),
-                                    refinements_per_step=float(np.mean([d["refinements"] for d in ci])),
-                                    relres_max=float(max(d["relres"] for d in ci)),
-                                    note="float32 values, history, basis and inner Krylov vectors; "
-                                         "FP64 refinement to the same 1e-8 (against the float32 operator)")
-        del A32, vals32_d
+        # mixed precision where it is meant to run: the 128^3 float32-valued 3-D sequence
+        # (CG, M = 30, Gaussian s = 60), against the plain FP64 method on the same
+        # operator (the float32 values upcast), both to relres 1e-8
+        comparators["mixed_3d"] = mixed_3d(sacc, torch, np, args.mixed_warmup, args.mixed_steps)
+
 
     gbs, spmv_ms, spmv_bytes = spmv_gbps(sacc, torch, A)
     log(f"SpMV {gbs:.0f} GB/s ({spmv_ms * 1e3:.1f} us)")
@@ -234,7 +293,8 @@ def main():
         "spmv_gbps": round(gbs, 1),
         "comparators": comparators,
         "roofline": {"bound": "hbm", "achieved": round(dom_gbs, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": round(dom_gbs / HBM_PEAK_GBS, 4), "traffic": None, "kernel": dom["name"],
+                     "frac": round(dom_gbs / HBM_PEAK_GBS, 4), "traffic": committed_traffic(dom["name"]),
+                     "kernel": dom["name"], "bytes_per_launch": round(dom["bytes"] / dom["launches"]),
                      "avg_us": round(dom_us, 3), "launches": dom["launches"],
                      "instrumented_ms_per_step": round(1e3 * pwall / args.steps, 4)},
         "cpu_baseline": cpu,

@@ -186,9 +186,15 @@ class SeqProblem:
             return faces
         # lognormal node values live on the padded grid, index order [iz, iy, ix]
         ln = self._ln_nodes() if self.lognormal != 0.0 else None
+        g1 = np.arange(1, self.N + 1, dtype=np.float64)
         for d in [(0, 0, -1), (0, -1, 0), (-1, 0, 0), (1, 0, 0), (0, 1, 0), (0, 0, 1)]:
-            kf = self.kcoef((gx + 0.5 * d[0]) * h, (gy + 0.5 * d[1]) * h,
-                            (gz + 0.5 * d[2]) * h, t)
+            # the 3-D k is a product of one factor per axis: evaluate the factors on the
+            # 1-D face coordinates and broadcast (same values and operation order as
+            # kcoef on the full grid)
+            sa = np.sin(TWO_PI * ((g1 + 0.5 * d[0]) * h) + t)
+            sb = np.sin(TWO_PI * ((g1 + 0.5 * d[1]) * h))
+            sc = np.sin(TWO_PI * ((g1 + 0.5 * d[2]) * h))
+            kf = (1.0 + ((0.5 * sa[None, None, :]) * sb[None, :, None]) * sc[:, None, None]).reshape(-1)
             if ln is not None:
                 centre = ln[1:-1, 1:-1, 1:-1]
                 nb = ln[1 + d[2]:ln.shape[0] - 1 + d[2], 1 + d[1]:ln.shape[1] - 1 + d[1],

@@ -173,10 +173,10 @@ int sa_spmv(const sa_csr *A, const void *x_dev, void *y_dev, void *stream);
 
 /* Measurement of the Krylov solve's dominant kernels (the SpMV-carrying kernel of
  * each GMRES Arnoldi step and of each CG iteration): with enable = 1, every later
- * sa_solve records HIP events on its stream around each launch of those kernels and
- * keeps the launches that did their work, with their algorithmic bytes.  Enabling
- * (or disabling) clears the records.  Adds an event pair per launch; intended for
- * measurement runs.  Errors: SA_ESTATE, SA_EHIP. */
+ * sa_solve launches those kernels with HIP start/stop events recorded by the launch
+ * itself (hipExtLaunchKernel) on its stream and keeps the launches that did their
+ * work, with their algorithmic bytes.  Enabling (or disabling) clears the records.
+ * Intended for measurement runs.  Errors: SA_ESTATE, SA_EHIP. */
 int sa_profile_enable(sa_seq *q, int enable);
 
 /* Copy up to max records to out; *count = number of records held.

@@ -163,55 +163,78 @@ __device__ inline void final_sum(const double *partials, int nblk, int W, int kc
 // ---------------------------------------------------------------- CSR stream SpMV
 constexpr int SPMV_CAP = 4096;  // nonzeros of one row tile staged in LDS (32 KB)
 
-// (A x)_i for row i = r0 + threadIdx.x of the row tile [r0, r0 + NT) (0 beyond n),
-// NT = threads of the block.  Every thread of the block must call it for the same r0.
-// The tile's col/val are read with consecutive threads on consecutive nonzeros
-// (coalesced), all of a thread's loads issued before the first is used (indices past
+// CSR row tile [r0, r0 + NT) for NT = threads of the block, row i = r0 + threadIdx.x.
+// Stage: the tile's col/val are read with consecutive threads on consecutive nonzeros
+// (coalesced), a chunk of C per thread issued before the first is used (indices past
 // the tile re-read its last entry and are dropped), then the gathers, and the
-// products are staged in LDS; each thread sums its row in column order.  Tiles with
-// more than SPMV_CAP nonzeros read their rows directly.  `gx(c)` returns the source
-// vector's entry c in double.
+// products are written to LDS.  Sum (after a barrier): each thread adds its row in
+// column order.  Tiles with more than SPMV_CAP nonzeros read their rows directly in
+// the sum.  `gx(c)` returns the source vector's entry c in double.  Every thread of
+// the block must take part, for the same r0.
+struct TileRows {
+  int a, b, p0, direct;
+};
+
 template <int NT, typename VT, typename G>
-__device__ inline double tile_spmv_g(const int *__restrict__ rowptr, const int *__restrict__ col,
-                                     const VT *__restrict__ val, const G &gx, int64_t n, int64_t r0,
-                                     double *prod) {
-  constexpr int U = SPMV_CAP / NT;
+__device__ inline TileRows tile_spmv_stage(const int *__restrict__ rowptr, const int *__restrict__ col,
+                                           const VT *__restrict__ val, const G &gx, int64_t n, int64_t r0,
+                                           double *prod) {
+  constexpr int C = 6;
   const int t = threadIdx.x;
   const int64_t i = r0 + t;
   const int64_t rl = (r0 + (int64_t)NT < n) ? r0 + (int64_t)NT : n;
   const int p0 = rowptr[r0], p1 = rowptr[rl];
-  int a = 0, b = 0;
+  TileRows tr{0, 0, p0, 0};
   if (i < n) {
-    a = rowptr[i];
-    b = rowptr[i + 1];
+    tr.a = rowptr[i];
+    tr.b = rowptr[i + 1];
   }
-  double s = 0.0;
-  const int cnt = p1 - p0;
-  if (cnt <= SPMV_CAP) {
-    if (cnt > 0) {
-      int cc[U];
-      double vv[U], xx[U];
+  if (p1 - p0 > SPMV_CAP) {
+    tr.direct = 1;
+    return tr;
+  }
+  for (int base = p0; base < p1; base += C * NT) {
+    int cc[C];
+    double vv[C], xx[C];
 #pragma unroll
-      for (int u = 0; u < U; ++u) {
-        const int p = p0 + t + u * NT;
-        const int pc = p < p1 ? p : p1 - 1;
-        cc[u] = col[pc];
-        vv[u] = (double)val[pc];
-      }
-#pragma unroll
-      for (int u = 0; u < U; ++u) xx[u] = gx(cc[u]);
-#pragma unroll
-      for (int u = 0; u < U; ++u) {
-        const int p = p0 + t + u * NT;
-        if (p < p1) prod[p - p0] = vv[u] * xx[u];
-      }
+    for (int u = 0; u < C; ++u) {
+      const int p = base + t + u * NT;
+      const int pc = p < p1 ? p : p1 - 1;
+      cc[u] = col[pc];
+      vv[u] = (double)val[pc];
     }
-    __syncthreads();
-    for (int p = a; p < b; ++p) s += prod[p - p0];
-    __syncthreads();
-  } else {
-    for (int p = a; p < b; ++p) s += (double)val[p] * gx(col[p]);
+#pragma unroll
+    for (int u = 0; u < C; ++u) xx[u] = gx(cc[u]);
+#pragma unroll
+    for (int u = 0; u < C; ++u) {
+      const int p = base + t + u * NT;
+      if (p < p1) prod[p - p0] = vv[u] * xx[u];
+    }
   }
+  return tr;
+}
+
+template <typename VT, typename G>
+__device__ inline double tile_spmv_sum(const TileRows &tr, const int *__restrict__ col, const VT *__restrict__ val,
+                                       const G &gx, const double *prod) {
+  double s = 0.0;
+  if (!tr.direct) {
+    for (int p = tr.a; p < tr.b; ++p) s += prod[p - tr.p0];
+  } else {
+    for (int p = tr.a; p < tr.b; ++p) s += (double)val[p] * gx(col[p]);
+  }
+  return s;
+}
+
+// (A x)_i of the tile in one call (stage, barrier, sum, barrier)
+template <int NT, typename VT, typename G>
+__device__ inline double tile_spmv_g(const int *__restrict__ rowptr, const int *__restrict__ col,
+                                     const VT *__restrict__ val, const G &gx, int64_t n, int64_t r0,
+                                     double *prod) {
+  const TileRows tr = tile_spmv_stage<NT>(rowptr, col, val, gx, n, r0, prod);
+  __syncthreads();
+  const double s = tile_spmv_sum(tr, col, val, gx, prod);
+  __syncthreads();
   return s;
 }
 

@@ -56,8 +56,9 @@ hipError_t launch_ir_resid(const CsrView &A, const double *b, const double *x, f
                            int sweep, int max_refine, Ctl *ctl, hipStream_t st);
 hipError_t launch_ir_update(double *x, const float *d, int64_t n, hipStream_t st);
 
-// Optional timing of one launch: HIP events recorded around it on its stream, and the
-// index under which the kernel logs that it did its work (Ctl::work_log).
+// Optional timing of one launch: HIP start/stop events recorded by the launch itself
+// (hipExtLaunchKernel), and the index under which the kernel logs that it did its
+// work (Ctl::work_log).
 struct KTiming {
   hipEvent_t e0, e1;
   int lidx;

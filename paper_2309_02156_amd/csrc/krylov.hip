@@ -16,6 +16,7 @@
 // alternate so a kernel never overwrites rows that blocks of the same kernel still
 // read.  Within a kernel, block 0 persists scalars only into fields that no block of
 // that kernel reads.
+#include <hip/hip_ext.h>
 #include <math.h>
 
 #include "common.h"
@@ -314,15 +315,15 @@ hipError_t launch_cg_iter(const CsrView &A, TV *x, TV *r, TV *p2, TV *q, double 
   const int nb = kblocks(A.n);
   const int64_t ld = padded_ld(A.n);
   TV *P0 = p2, *P1 = p2 + ld;
+  // timed launches record their start/stop events in the kernel's own dispatch
+  hipEvent_t e0 = tm ? tm->e0 : nullptr, e1 = tm ? tm->e1 : nullptr;
   const int lidx = tm ? tm->lidx : -1;
-  if (tm) (void)hipEventRecord(tm->e0, st);
   if (A.fp32)
-    hipLaunchKernelGGL((k_cg_p<float, TV>), dim3(nb), dim3(KTPB), 0, st, A.rowptr, A.col, (const float *)A.val, r,
-                       P0, P1, q, A.n, PA(partials), nb, PB(partials), ctl, lidx);
+    hipExtLaunchKernelGGL((k_cg_p<float, TV>), dim3(nb), dim3(KTPB), 0, st, e0, e1, 0, A.rowptr, A.col,
+                          (const float *)A.val, r, P0, P1, q, A.n, PA(partials), nb, PB(partials), ctl, lidx);
   else
-    hipLaunchKernelGGL((k_cg_p<double, TV>), dim3(nb), dim3(KTPB), 0, st, A.rowptr, A.col,
-                       (const double *)A.val, r, P0, P1, q, A.n, PA(partials), nb, PB(partials), ctl, lidx);
-  if (tm) (void)hipEventRecord(tm->e1, st);
+    hipExtLaunchKernelGGL((k_cg_p<double, TV>), dim3(nb), dim3(KTPB), 0, st, e0, e1, 0, A.rowptr, A.col,
+                          (const double *)A.val, r, P0, P1, q, A.n, PA(partials), nb, PB(partials), ctl, lidx);
   hipLaunchKernelGGL(k_cg_xr<TV>, dim3(nb), dim3(KTPB), 0, st, x, r, P0, P1, q, A.n, PB(partials), nb,
                      PA(partials), ctl);
   return hipGetLastError();
@@ -741,15 +742,15 @@ template <typename TV, int RB>
 static void gm_f_rb(const CsrView &A, TV *V, TV *T, int64_t ld, int j, int mode, double *partials, Ctl *ctl,
                     hipStream_t st, const KTiming *tm = nullptr) {
   const int nb = kblocks(A.n);
+  // timed launches record their start/stop events in the kernel's own dispatch
+  hipEvent_t e0 = tm ? tm->e0 : nullptr, e1 = tm ? tm->e1 : nullptr;
   const int lidx = tm ? tm->lidx : -1;
-  if (tm) (void)hipEventRecord(tm->e0, st);
   if (A.fp32)
-    hipLaunchKernelGGL((k_gm_f<float, TV, RB>), dim3(nb), dim3(KTPB), 0, st, A.rowptr, A.col, (const float *)A.val,
-                       V, T, A.n, ld, j, mode, PA(partials), nb, PB(partials), ctl, lidx);
+    hipExtLaunchKernelGGL((k_gm_f<float, TV, RB>), dim3(nb), dim3(KTPB), 0, st, e0, e1, 0, A.rowptr, A.col,
+                          (const float *)A.val, V, T, A.n, ld, j, mode, PA(partials), nb, PB(partials), ctl, lidx);
   else
-    hipLaunchKernelGGL((k_gm_f<double, TV, RB>), dim3(nb), dim3(KTPB), 0, st, A.rowptr, A.col,
-                       (const double *)A.val, V, T, A.n, ld, j, mode, PA(partials), nb, PB(partials), ctl, lidx);
-  if (tm) (void)hipEventRecord(tm->e1, st);
+    hipExtLaunchKernelGGL((k_gm_f<double, TV, RB>), dim3(nb), dim3(KTPB), 0, st, e0, e1, 0, A.rowptr, A.col,
+                          (const double *)A.val, V, T, A.n, ld, j, mode, PA(partials), nb, PB(partials), ctl, lidx);
 }
 
 // Arnoldi step j of a cycle: F(j), G(j).  first_mode: 0 first cycle, 1 restart
