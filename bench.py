@@ -125,6 +125,86 @@ def mixed_3d(sacc, torch, np, warmup, steps):
     return out
 
 
+def learned_cmp(sacc, torch, np, n_train, n_eval, epochs=60, batch=32, n_hist=8):
+    """The learned guess on the 512 x 512 sequence: the plain method runs steps
+    0 .. n_train - 1 while the targets are recorded, the MLP (162 -> 256 x 3 -> 20, SiLU,
+    bf16 weights, Adam) is trained on them with the library's kernels, then steps
+    n_train .. n_train + n_eval - 1 run with the learned guess, against the plain method
+    on the same steps."""
+    from gen import config
+    from gen.mlp_init import mlp_init
+
+    p, m = config(1)
+    M = m["M"]
+    total = n_train + n_eval
+    log(f"learned: assembling {total} steps")
+    vals, rhs = assemble(p, total)
+    rowptr, col = p.pattern()
+    A = sacc.DeviceCSR(rowptr, col, vals[0])
+    vals_d = torch.as_tensor(vals).cuda()
+    rhs_d = torch.as_tensor(rhs).cuda()
+    del vals, rhs
+    sizes = [n_hist * M + 2, 256, 256, 256, M]
+    mlp = sacc.MLP(sizes, mlp_init(sizes, 9), max_batch=batch, lr=1e-3)
+    kw = dict(s=m["s"], sketch=m["sketch"], solver=m["solver"], restart=m["restart"], tol=m["tol"],
+              seed=m["method_seed"])
+    seq = sacc.Sequence(A.n, M, **kw)
+    seq.learned_attach(mlp, n_hist)
+    plain = sacc.Sequence(A.n, M, **kw)
+    x = torch.empty(A.n, dtype=torch.float64, device="cuda")
+    xp = torch.empty_like(x)
+
+    def step(s, i, xx):
+        A.val.copy_(vals_d[i])
+        b = rhs_d[i]
+        s.set_time(p.t(i))
+        _, g = s.initial_guess(A, b, xx)
+        _, inf = s.solve(A, b, xx)
+        s.push(xx)
+        return g, inf
+
+    targets = []
+    for i in range(n_train):
+        step(seq, i, x)
+        targets.append(seq.last_target())
+        step(plain, i, xp)
+    F = np.array([np.concatenate(targets[i - n_hist:i] + [np.array([np.sin(p.t(i)), np.cos(p.t(i))])])
+                  for i in range(n_hist + M, n_train)])
+    T = np.array(targets[n_hist + M:n_train])
+    mlp.set_scaling(F.mean(0), F.std(0) + 1e-6, T.mean(0), T.std(0) + 1e-6)
+    Fd = torch.as_tensor(F.astype(np.float32)).cuda()
+    Td = torch.as_tensor(T.astype(np.float32)).cuda()
+    loss = torch.zeros(1, dtype=torch.float32, device="cuda")
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    losses = []
+    for e in range(epochs):
+        perm = torch.as_tensor(np.random.default_rng([10, e]).permutation(F.shape[0]), device="cuda")
+        for s0 in range(0, F.shape[0] - batch + 1, batch):
+            idx = perm[s0:s0 + batch]
+            mlp.train_step(Fd[idx].contiguous(), Td[idx].contiguous(), loss)
+        losses.append(float(loss.item()))
+    torch.cuda.synchronize()
+    train_s = time.perf_counter() - t0
+    out = {}
+    for name, s, xx in (("learned", seq, x), ("plain", plain, xp)):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        its, used = [], []
+        for i in range(n_train, total):
+            g, inf = step(s, i, xx)
+            its.append(inf["iters"])
+            used.append(g.get("used_learned", 0))
+        torch.cuda.synchronize()
+        out[name] = dict(ms_per_step=round(1e3 * (time.perf_counter() - t0) / n_eval, 4),
+                         iters_per_step=float(np.mean(its)), learned_accepted=int(sum(used)))
+    out.update(workload=f"advdiff2d 512x512, M={M}, GMRES(30), relres 1e-8, FP64; trained on the targets of "
+                        f"steps {n_hist + M}..{n_train - 1}, evaluated on steps {n_train}..{total - 1}",
+               mlp="162 -> 256 -> 256 -> 256 -> 20, SiLU, bf16 weights, Adam lr 1e-3",
+               train_seconds=round(train_s, 3), loss_first=losses[0], loss_last=losses[-1])
+    return out
+
+
 def committed_traffic(kernel):
     """HBM bytes per launch of `kernel` from the committed counter summary, or None when
     there is none or the kernel sources have changed since the counters were taken."""
@@ -198,6 +278,8 @@ def main():
     ap.add_argument("--no-comparators", action="store_true")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="run 3 plain 256 MiB device copies first (reference for HBM byte counters)")
+    ap.add_argument("--learned-train", type=int, default=200)
+    ap.add_argument("--learned-eval", type=int, default=100)
     ap.add_argument("--mixed-warmup", type=int, default=32)
     ap.add_argument("--mixed-steps", type=int, default=8)
     args = ap.parse_args()
@@ -262,6 +344,8 @@ def main():
         # (CG, M = 30, Gaussian s = 60), against the plain FP64 method on the same
         # operator (the float32 values upcast), both to relres 1e-8
         comparators["mixed_3d"] = mixed_3d(sacc, torch, np, args.mixed_warmup, args.mixed_steps)
+        # learned coefficient predictor on the 512 x 512 sequence
+        comparators["learned"] = learned_cmp(sacc, torch, np, args.learned_train, args.learned_eval)
 
 
     gbs, spmv_ms, spmv_bytes = spmv_gbps(sacc, torch, A)

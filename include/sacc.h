@@ -108,6 +108,8 @@ typedef struct {
   double relres;         /* final ||b - A x|| / ||b|| (true residual)                  */
   float ms_guess;        /* device time of the last initial guess                     */
   float ms_solve;        /* device time of the last solve                             */
+  int32_t used_learned;  /* 1 if the last guess kept the learned prediction            */
+  int32_t reserved;
 } sa_info;
 
 /* Timing record of one kernel (sa_profile_read). */
@@ -183,13 +185,70 @@ int sa_profile_enable(sa_seq *q, int enable);
  * Errors: SA_ESTATE, SA_EINVAL. */
 int sa_profile_read(sa_seq *q, sa_kernel_prof *out, int max, int *count);
 
+/* ---- learned coefficient predictor (not in the paper) ------------------------------
+ * A small MLP that predicts the coefficients of the next solution in the history
+ * basis from the coefficients of the previous steps (see sa_learned_attach).  Weights
+ * are float32 masters used in bfloat16 (round to nearest even); products accumulate in
+ * float32; SiLU hidden activations; mean-squared-error loss; Adam. */
+typedef struct sa_mlp sa_mlp;
+typedef struct {
+  int32_t n_in;      /* inputs (n_hist * M + 2 for the learned guess)                  */
+  int32_t n_hidden;  /* width of every hidden layer                                    */
+  int32_t n_layers;  /* hidden layers (n_layers + 1 linear layers, at most 8)          */
+  int32_t n_out;     /* outputs (M for the learned guess)                              */
+  int32_t max_batch; /* rows per forward / training call                               */
+  float lr, beta1, beta2, eps;  /* Adam                                                */
+  int32_t reserved;
+} sa_mlp_config;
+
+/* Create an MLP with initial parameters (host, float32, layer by layer: W_l row-major
+ * out x in, then b_l).  Allocates its device memory.  Scaling starts as identity.
+ * Errors: SA_EINVAL, SA_ENOMEM, SA_EHIP. */
+int sa_mlp_create(const sa_mlp_config *cfg, const float *init_params, sa_mlp **out);
+int sa_mlp_destroy(sa_mlp *m);
+
+/* Standardisation of inputs and outputs: the network sees (x - mu_in) / sd_in and is
+ * trained on (t - mu_out) / sd_out; predictions are mapped back.  Host float32 arrays
+ * of n_in and n_out entries, sd > 0.  Synchronous.  Errors: SA_EINVAL, SA_EHIP. */
+int sa_mlp_set_scaling(sa_mlp *m, const float *mu_in, const float *sd_in, const float *mu_out,
+                       const float *sd_out);
+
+/* Forward pass of batch rows x_dev (device, float32, batch x n_in, raw) into y_dev
+ * (device, float32, batch x n_out, standardised outputs).  Asynchronous. */
+int sa_mlp_forward(sa_mlp *m, const float *x_dev, int batch, float *y_dev, void *stream);
+
+/* One Adam step on the batch (x_dev raw inputs, t_dev raw targets, device float32);
+ * loss_dev (device float, may be NULL) receives the standardised mean squared error
+ * before the step.  Asynchronous.  Errors: SA_EINVAL, SA_EHIP. */
+int sa_mlp_train_step(sa_mlp *m, const float *x_dev, const float *t_dev, int batch, float *loss_dev,
+                      void *stream);
+
+/* Copy parameters (what = 0), the last gradients (1) or the Adam moments (2, 3) to host
+ * (count >= number of parameters).  Waits for the stream. */
+int sa_mlp_get(sa_mlp *m, int what, float *host, size_t count, void *stream);
+
+/* Attach a predictor to a fresh sequence (before its first push; guess must be
+ * SA_GUESS_PROJECTION).  From then on every push records the step's target, the
+ * sketched least-squares coordinates (lag order) of the pushed solution in the history
+ * that step used, and once n_hist targets exist every initial guess also evaluates the
+ * MLP on the last n_hist targets and sin t, cos t (t from sa_set_time), forms
+ * x_pred = X c_pred and keeps it instead of the projection when ||b - A x_pred|| is
+ * smaller (info->used_learned).  m = NULL detaches.  m must have n_in = n_hist M + 2 and
+ * n_out = M.  Errors: SA_EINVAL, SA_ESTATE. */
+int sa_learned_attach(sa_seq *q, sa_mlp *m, int n_hist);
+
+/* Time t of the next system, for the learned guess's inputs.  Errors: SA_ESTATE. */
+int sa_set_time(sa_seq *q, double t);
+
 /* Copy internal state to host memory for inspection:
  *   what = 0: SX, s x M float64 column-major, columns in ring-slot order;
  *   what = 1: X, n x M column-major in ring-slot order, float64 (SA_FP64) or
  *             float32 (SA_MIXED);
  *   what = 2: coefficients c of the last guess in history (ring-slot) coordinates,
  *             M float64 (x0 = X c);
- *   what = 3: ring order, M int32: slot of the oldest .. newest column (-1 unused).
+ *   what = 3: ring order, M int32: slot of the oldest .. newest column (-1 unused);
+ *   what = 4: the learned target of the last push, M float64 in lag order
+ *             (SA_ESTATE without an attached predictor or before the first push).
  * Waits for the stream.  Errors: SA_EINVAL (bytes too small or unknown what). */
 int sa_copy_state(sa_seq *q, int what, void *host_dst, size_t bytes, void *stream);
 

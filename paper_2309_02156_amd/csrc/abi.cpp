@@ -25,6 +25,18 @@ struct KernelProfile {
   std::vector<sa_kernel_prof> rec;
 };
 
+// Learned coefficient predictor: an MLP with its parameters, Adam state, scaling of
+// inputs and outputs and per-layer work buffers for up to max_batch rows (device).
+struct sa_mlp {
+  MlpDims d{};
+  MlpBuffers b{};
+  float *mu_in = nullptr, *sd_in = nullptr, *mu_out = nullptr, *sd_out = nullptr;
+  float *xraw = nullptr;  // one raw output row for the learned guess
+  float lr = 1e-3f, beta1 = 0.9f, beta2 = 0.999f, eps = 1e-8f;
+  int t = 0;  // Adam steps taken
+  std::vector<void *> allocs;
+};
+
 struct sa_seq {
   sa_config cfg;
   bool mixed = false;  // SA_MIXED: FP32 history / basis / inner Krylov vectors
@@ -44,6 +56,10 @@ struct sa_seq {
   hipEvent_t ev[4] = {nullptr, nullptr, nullptr, nullptr};
   hipEvent_t evp[2] = {nullptr, nullptr};  // look-ahead poll slots
   KernelProfile prof;
+  sa_mlp *mlp = nullptr;  // learned guess (sa_learned_attach)
+  int lhist = 0;          // targets per MLP input
+  long long ltargets = 0; // targets written (one per push while attached)
+  double t_now = 0.0;     // time of the next system (sa_set_time)
   bool alive = true;
 };
 
@@ -406,6 +422,27 @@ int guess_projection(sa_seq *q, const CsrView &v, const double *b, double *x0, i
   return SA_OK;
 }
 
+// Learned guess on top of the projection: MLP input from the last lhist targets and
+// the time, prediction x_pred = X c, kept instead of the projection's x0 when its
+// residual is smaller.  The Krylov vectors' memory serves as scratch for x_pred.
+int guess_learned(sa_seq *q, const CsrView &v, const double *b, double *x0, int cnt, hipStream_t st) {
+  const sa_config &c = q->cfg;
+  sa_mlp *m = q->mlp;
+  const int newest = (int)((q->pushes - 1) % c.M);
+  double *xp = (double *)q->kry;
+  HIP_TRY(launch_learn_features(q->ctl, q->lhist, c.M, (int)q->ltargets, q->t_now, m->mu_in, m->sd_in, m->b.xs, st));
+  HIP_TRY(launch_mlp_forward(m->d, m->b, 1, st));
+  const float *y = m->b.act[m->d.n_layers];
+  if (q->mixed)
+    HIP_TRY(launch_learn_xpred<float>((const float *)q->X, c.n, q->ld, cnt, newest, c.M, y, m->mu_out, m->sd_out, xp,
+                                      st));
+  else
+    HIP_TRY(launch_learn_xpred<double>((const double *)q->X, c.n, q->ld, cnt, newest, c.M, y, m->mu_out, m->sd_out,
+                                       xp, st));
+  HIP_TRY(launch_learn_pick(v, b, x0, xp, q->partials, q->ctl, st));
+  return SA_OK;
+}
+
 }  // namespace
 
 extern "C" {
@@ -483,6 +520,15 @@ int sa_push_solution(sa_seq *q, const void *x_dev, void *stream) {
   else
     HIP_TRY(launch_push<double>((const double *)x_dev, (double *)q->X, q->SX, c.n, q->ld, slot, c.s, c.sketch,
                                 c.seed, q->srht_rows, q->partials, q->ctl, st));
+  if (q->mlp) {
+    // target of the step whose solution this is: its sketched least-squares
+    // coordinates in that step's history (before this push changes SX and T1)
+    const int cnt_old = count(q);
+    const int newest_old = cnt_old > 0 ? (int)((q->pushes - 1) % c.M) : -1;
+    HIP_TRY(launch_learn_target(q->SX, c.s, q->partials, push_blocks_x(c.n, c.s), cnt_old, newest_old, c.M,
+                                (int)(q->ltargets % LHIST_MAX), q->ctl, st));
+    q->ltargets += 1;
+  }
   q->pushes += 1;
   HIP_TRY(launch_qrcp(q->SX, c.s, count(q), slot, q->tau_s, q->partials, c.n, q->ctl, st));
   return SA_OK;
@@ -513,6 +559,7 @@ int sa_initial_guess(sa_seq *q, const sa_csr *A, const void *b_dev, void *x0_dev
       SA_TRY(guess_projection<float>(q, v, (const double *)b_dev, (double *)x0_dev, cnt, st));
     else
       SA_TRY(guess_projection<double>(q, v, (const double *)b_dev, (double *)x0_dev, cnt, st));
+    if (q->mlp && q->ltargets >= q->lhist) SA_TRY(guess_learned(q, v, (const double *)b_dev, (double *)x0_dev, cnt, st));
   }
   if (info) {
     HIP_TRY(hipEventRecord(q->ev[1], st));
@@ -525,6 +572,13 @@ int sa_initial_guess(sa_seq *q, const sa_csr *A, const void *b_dev, void *x0_dev
     info->k_eff = proj ? q->hbuf[17] : 0;
     info->used_fallback = proj ? q->hbuf[18] : 0;
     info->history = cnt;
+    info->used_learned = 0;
+    if (q->mlp && proj && q->ltargets >= q->lhist) {
+      int used = 0;
+      HIP_TRY(hipMemcpyAsync(&used, &q->ctl->learned_used, sizeof(int), hipMemcpyDeviceToHost, st));
+      HIP_TRY(hipStreamSynchronize(st));
+      info->used_learned = used;
+    }
     info->ms_guess = ms;
   }
   return SA_OK;
@@ -633,6 +687,153 @@ int sa_destroy_sequence(sa_seq *q) {
   return SA_OK;
 }
 
+// ---------------------------------------------------------------- learned predictor
+static void mlp_free(sa_mlp *m) {
+  for (void *p : m->allocs) (void)hipFree(p);
+  m->allocs.clear();
+}
+
+static float *mlp_alloc(sa_mlp *m, size_t count, bool *ok) {
+  void *p = nullptr;
+  if (!*ok || hipMalloc(&p, count * sizeof(float)) != hipSuccess) {
+    *ok = false;
+    return nullptr;
+  }
+  m->allocs.push_back(p);
+  return (float *)p;
+}
+
+int sa_mlp_create(const sa_mlp_config *cfg, const float *init_params, sa_mlp **out) {
+  if (!cfg || !init_params || !out) return SA_EINVAL;
+  if (cfg->n_in < 1 || cfg->n_hidden < 1 || cfg->n_out < 1 || cfg->n_layers < 0 ||
+      cfg->n_layers + 1 > MLP_MAXL || cfg->max_batch < 1 || !(cfg->lr >= 0.f))
+    return SA_EINVAL;
+  sa_mlp *m = new (std::nothrow) sa_mlp();
+  if (!m) return SA_ENOMEM;
+  m->d = MlpDims{cfg->n_in, cfg->n_hidden, cfg->n_layers, cfg->n_out, cfg->max_batch};
+  m->lr = cfg->lr;
+  m->beta1 = cfg->beta1;
+  m->beta2 = cfg->beta2;
+  m->eps = cfg->eps;
+  const size_t np = mlp_param_count(m->d);
+  const int B = cfg->max_batch;
+  const int wmax = cfg->n_hidden > cfg->n_out ? (cfg->n_hidden > cfg->n_in ? cfg->n_hidden : cfg->n_in)
+                                              : (cfg->n_out > cfg->n_in ? cfg->n_out : cfg->n_in);
+  bool ok = true;
+  m->b.P = mlp_alloc(m, np, &ok);
+  m->b.G = mlp_alloc(m, np, &ok);
+  m->b.am = mlp_alloc(m, np, &ok);
+  m->b.av = mlp_alloc(m, np, &ok);
+  m->b.xs = mlp_alloc(m, (size_t)B * cfg->n_in, &ok);
+  m->b.ts = mlp_alloc(m, (size_t)B * cfg->n_out, &ok);
+  for (int l = 0; l <= cfg->n_layers; ++l) {
+    const int w = l == cfg->n_layers ? cfg->n_out : cfg->n_hidden;
+    m->b.z[l] = mlp_alloc(m, (size_t)B * w, &ok);
+    m->b.act[l] = mlp_alloc(m, (size_t)B * w, &ok);
+  }
+  m->b.dz[0] = mlp_alloc(m, (size_t)B * wmax, &ok);
+  m->b.dz[1] = mlp_alloc(m, (size_t)B * wmax, &ok);
+  m->mu_in = mlp_alloc(m, cfg->n_in, &ok);
+  m->sd_in = mlp_alloc(m, cfg->n_in, &ok);
+  m->mu_out = mlp_alloc(m, cfg->n_out, &ok);
+  m->sd_out = mlp_alloc(m, cfg->n_out, &ok);
+  m->xraw = mlp_alloc(m, cfg->n_in, &ok);
+  if (ok) {
+    std::vector<float> zero(np, 0.f), one_in(cfg->n_in, 1.f), one_out(cfg->n_out, 1.f);
+    ok = hipMemcpy(m->b.P, init_params, np * sizeof(float), hipMemcpyHostToDevice) == hipSuccess &&
+         hipMemcpy(m->b.am, zero.data(), np * sizeof(float), hipMemcpyHostToDevice) == hipSuccess &&
+         hipMemcpy(m->b.av, zero.data(), np * sizeof(float), hipMemcpyHostToDevice) == hipSuccess &&
+         hipMemcpy(m->b.G, zero.data(), np * sizeof(float), hipMemcpyHostToDevice) == hipSuccess &&
+         hipMemcpy(m->mu_in, zero.data(), cfg->n_in * sizeof(float), hipMemcpyHostToDevice) == hipSuccess &&
+         hipMemcpy(m->sd_in, one_in.data(), cfg->n_in * sizeof(float), hipMemcpyHostToDevice) == hipSuccess &&
+         hipMemcpy(m->mu_out, zero.data(), cfg->n_out * sizeof(float), hipMemcpyHostToDevice) == hipSuccess &&
+         hipMemcpy(m->sd_out, one_out.data(), cfg->n_out * sizeof(float), hipMemcpyHostToDevice) == hipSuccess;
+  }
+  if (!ok) {
+    mlp_free(m);
+    delete m;
+    return SA_EHIP;
+  }
+  *out = m;
+  return SA_OK;
+}
+
+int sa_mlp_destroy(sa_mlp *m) {
+  if (!m) return SA_EINVAL;
+  mlp_free(m);
+  delete m;
+  return SA_OK;
+}
+
+int sa_mlp_set_scaling(sa_mlp *m, const float *mu_in, const float *sd_in, const float *mu_out, const float *sd_out) {
+  if (!m || !mu_in || !sd_in || !mu_out || !sd_out) return SA_EINVAL;
+  for (int j = 0; j < m->d.n_in; ++j)
+    if (!(sd_in[j] > 0.f)) return SA_EINVAL;
+  for (int j = 0; j < m->d.n_out; ++j)
+    if (!(sd_out[j] > 0.f)) return SA_EINVAL;
+  const size_t a = m->d.n_in * sizeof(float), b = m->d.n_out * sizeof(float);
+  HIP_TRY(hipMemcpy(m->mu_in, mu_in, a, hipMemcpyHostToDevice));
+  HIP_TRY(hipMemcpy(m->sd_in, sd_in, a, hipMemcpyHostToDevice));
+  HIP_TRY(hipMemcpy(m->mu_out, mu_out, b, hipMemcpyHostToDevice));
+  HIP_TRY(hipMemcpy(m->sd_out, sd_out, b, hipMemcpyHostToDevice));
+  return SA_OK;
+}
+
+int sa_mlp_forward(sa_mlp *m, const float *x_dev, int batch, float *y_dev, void *stream) {
+  if (!m || !x_dev || !y_dev || batch < 1 || batch > m->d.max_batch) return SA_EINVAL;
+  hipStream_t st = (hipStream_t)stream;
+  HIP_TRY(launch_mlp_scale(x_dev, batch, m->d.n_in, m->mu_in, m->sd_in, m->b.xs, st));
+  HIP_TRY(launch_mlp_forward(m->d, m->b, batch, st));
+  HIP_TRY(hipMemcpyAsync(y_dev, m->b.act[m->d.n_layers], (size_t)batch * m->d.n_out * sizeof(float),
+                         hipMemcpyDeviceToDevice, st));
+  return SA_OK;
+}
+
+int sa_mlp_train_step(sa_mlp *m, const float *x_dev, const float *t_dev, int batch, float *loss_dev, void *stream) {
+  if (!m || !x_dev || !t_dev || batch < 1 || batch > m->d.max_batch) return SA_EINVAL;
+  hipStream_t st = (hipStream_t)stream;
+  HIP_TRY(launch_mlp_scale(x_dev, batch, m->d.n_in, m->mu_in, m->sd_in, m->b.xs, st));
+  HIP_TRY(launch_mlp_scale(t_dev, batch, m->d.n_out, m->mu_out, m->sd_out, m->b.ts, st));
+  HIP_TRY(launch_mlp_forward(m->d, m->b, batch, st));
+  HIP_TRY(launch_mlp_backward(m->d, m->b, batch, loss_dev, st));
+  m->t += 1;
+  HIP_TRY(launch_mlp_adam(m->d, m->b, m->lr, m->beta1, m->beta2, m->eps, m->t, st));
+  return SA_OK;
+}
+
+int sa_mlp_get(sa_mlp *m, int what, float *host, size_t count, void *stream) {
+  if (!m || !host) return SA_EINVAL;
+  const size_t np = mlp_param_count(m->d);
+  const float *src = what == 0 ? m->b.P : what == 1 ? m->b.G : what == 2 ? m->b.am : what == 3 ? m->b.av : nullptr;
+  if (!src || count < np) return SA_EINVAL;
+  hipStream_t st = (hipStream_t)stream;
+  HIP_TRY(hipMemcpyAsync(host, src, np * sizeof(float), hipMemcpyDeviceToHost, st));
+  HIP_TRY(hipStreamSynchronize(st));
+  return SA_OK;
+}
+
+int sa_learned_attach(sa_seq *q, sa_mlp *m, int n_hist) {
+  if (!q || !q->alive) return SA_ESTATE;
+  if (!m) {
+    q->mlp = nullptr;
+    return SA_OK;
+  }
+  if (n_hist < 1 || n_hist > LHIST_MAX || m->d.n_in != n_hist * q->cfg.M + 2 || m->d.n_out != q->cfg.M ||
+      q->cfg.guess != SA_GUESS_PROJECTION)
+    return SA_EINVAL;
+  if (q->pushes != 0) return SA_ESTATE;
+  q->mlp = m;
+  q->lhist = n_hist;
+  q->ltargets = 0;
+  return SA_OK;
+}
+
+int sa_set_time(sa_seq *q, double t) {
+  if (!q || !q->alive) return SA_ESTATE;
+  q->t_now = t;
+  return SA_OK;
+}
+
 int sa_profile_enable(sa_seq *q, int enable) {
   if (!q || !q->alive) return SA_ESTATE;
   KernelProfile &P = q->prof;
@@ -683,6 +884,14 @@ int sa_copy_state(sa_seq *q, int what, void *host_dst, size_t bytes, void *strea
   hipStream_t st = (hipStream_t)stream;
   const sa_config &c = q->cfg;
   const size_t w = q->mixed ? sizeof(float) : sizeof(double);
+  if (what == 4) {  // the learned target written by the last push (M float64, lag order)
+    if (!q->mlp || q->ltargets == 0) return SA_ESTATE;
+    if (bytes < (size_t)c.M * sizeof(double)) return SA_EINVAL;
+    HIP_TRY(hipMemcpyAsync(host_dst, q->ctl->lhist + (size_t)((q->ltargets - 1) % LHIST_MAX) * MAXM,
+                           (size_t)c.M * sizeof(double), hipMemcpyDeviceToHost, st));
+    HIP_TRY(hipStreamSynchronize(st));
+    return SA_OK;
+  }
   if (what == 0 || what == 1 || what == 2) {
     size_t need = what == 0 ? (size_t)c.s * c.M * sizeof(double)
                  : what == 1 ? (size_t)c.n * c.M * w

@@ -16,6 +16,7 @@ constexpr int MAXS = 256;         // most sketch rows
 constexpr int MAXR = 32;          // longest GMRES cycle
 constexpr int SKETCH_RG = 16;     // sketch rows per block row-group
 constexpr int WORK_LOG = 4096;    // timed launches logged per solve
+constexpr int LHIST_MAX = 16;     // ring of learned-predictor targets
 
 // Solver states kept in the device control block.
 enum : int {
@@ -58,6 +59,10 @@ struct Ctl {
   double gram[MAXM * MAXM * 3 + 2 * MAXM];  // reduced G | Ht | gt  (| K | ht for MINRES)
   // kernel timing: launch l of a timed solve sets work_log[l] = 1 when it did its work
   int work_log[WORK_LOG];
+  // learned predictor: targets of past steps (lag order), last decision and residuals
+  double lhist[LHIST_MAX * MAXM];
+  double learned_r2[2];
+  int learned_used, pad3;
 };
 
 // ---------------------------------------------------------------- launch geometry
@@ -66,6 +71,10 @@ inline int stream_blocks(int64_t n) {
   if (b < 1) b = 1;
   return (int)(b > MAXBLK ? MAXBLK : b);
 }
+
+// grid-stride loop over rows
+#define GRID_ROWS(i, n) \
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < (n); i += (int64_t)gridDim.x * blockDim.x)
 
 // ---------------------------------------------------------------- reductions
 __device__ inline double wave_sum(double v) {

@@ -24,6 +24,9 @@ template <typename TX>
 hipError_t launch_push(const double *x, TX *X, double *SX, int64_t n, int64_t ld, int slot, int s, int sketch,
                        uint64_t seed, const long long *srht_rows, double *partials, Ctl *ctl, hipStream_t st);
 
+// blocks along n of the push kernel (its partial rows per row group)
+int push_blocks_x(int64_t n, int s);
+
 // finish the push (reduce the sketch partials into SX[:, newest]), then QR with column
 // pivoting of SX[:, 0:cnt] -> k, T1 (in ctl)
 hipError_t launch_qrcp(double *SX, int s, int cnt, int newest, double tau, const double *partials, int64_t n,
@@ -96,6 +99,35 @@ hipError_t launch_gm_finish(const CsrView &A, TV *V, TV *T, int64_t ld, int m, d
 template <typename TV>
 hipError_t launch_gm_update(TV *x, const TV *V, int64_t n, int64_t ld, int restart, Ctl *ctl, hipStream_t st);
 size_t krylov_partials_doubles();
+
+// ---- learned coefficient predictor (MLP) and the learned initial guess
+constexpr int MLP_MAXL = 8;  // linear layers at most
+struct MlpDims {
+  int n_in, n_hidden, n_layers, n_out, max_batch;  // n_layers hidden layers, n_layers + 1 linear layers
+};
+// device buffers: parameters (per layer W (out x in, row-major) then b), gradients, Adam
+// moments, standardised input / target rows, per-layer pre-activations z and outputs act
+// (act[n_layers] is the network output), two gradient buffers
+struct MlpBuffers {
+  float *P, *G, *am, *av, *xs, *ts;
+  float *z[MLP_MAXL], *act[MLP_MAXL];
+  float *dz[2];
+};
+size_t mlp_param_count(const MlpDims &d);
+hipError_t launch_mlp_forward(const MlpDims &d, const MlpBuffers &m, int B, hipStream_t st);
+hipError_t launch_mlp_backward(const MlpDims &d, const MlpBuffers &m, int B, float *loss, hipStream_t st);
+hipError_t launch_mlp_adam(const MlpDims &d, const MlpBuffers &m, float lr, float b1, float b2, float eps, int t,
+                           hipStream_t st);
+hipError_t launch_mlp_scale(const float *X, int B, int D, const float *mu, const float *sd, float *Y, hipStream_t st);
+hipError_t launch_learn_target(const double *SX, int s, const double *partials, int nbx, int cnt_old, int newest_old,
+                               int M, int pos, Ctl *ctl, hipStream_t st);
+hipError_t launch_learn_features(const Ctl *ctl, int H, int M, int pos, double t, const float *mu, const float *sd,
+                                 float *xs, hipStream_t st);
+template <typename TX>
+hipError_t launch_learn_xpred(const TX *X, int64_t n, int64_t ld, int cnt, int newest, int M, const float *y,
+                              const float *mu, const float *sd, double *xp, hipStream_t st);
+hipError_t launch_learn_pick(const CsrView &A, const double *b, double *x0, const double *xp, double *partials,
+                             Ctl *ctl, hipStream_t st);
 
 // leading dimension of the column-major history, basis and Krylov blocks
 int64_t padded_ld(int64_t n);

@@ -22,7 +22,8 @@ SA_GUESS_PROJECTION, SA_GUESS_ZERO, SA_GUESS_PREVIOUS = 0, 1, 2
 
 EXPORTS = ("sa_workspace_bytes", "sa_init_sequence", "sa_push_solution", "sa_initial_guess",
            "sa_solve", "sa_destroy_sequence", "sa_status_string", "sa_spmv", "sa_copy_state",
-           "sa_profile_enable", "sa_profile_read")
+           "sa_profile_enable", "sa_profile_read", "sa_mlp_create", "sa_mlp_destroy", "sa_mlp_set_scaling",
+           "sa_mlp_forward", "sa_mlp_train_step", "sa_mlp_get", "sa_learned_attach", "sa_set_time")
 
 
 class SaConfig(ctypes.Structure):
@@ -51,10 +52,20 @@ class SaInfo(ctypes.Structure):
         ("k_eff", ctypes.c_int32), ("k_sketch", ctypes.c_int32), ("used_fallback", ctypes.c_int32),
         ("status", ctypes.c_int32), ("history", ctypes.c_int32), ("relres0", ctypes.c_double),
         ("relres", ctypes.c_double), ("ms_guess", ctypes.c_float), ("ms_solve", ctypes.c_float),
+        ("used_learned", ctypes.c_int32), ("reserved", ctypes.c_int32),
     ]
 
     def as_dict(self) -> dict:
         return {name: getattr(self, name) for name, _ in self._fields_}
+
+
+class SaMlpConfig(ctypes.Structure):
+    _fields_ = [
+        ("n_in", ctypes.c_int32), ("n_hidden", ctypes.c_int32), ("n_layers", ctypes.c_int32),
+        ("n_out", ctypes.c_int32), ("max_batch", ctypes.c_int32), ("lr", ctypes.c_float),
+        ("beta1", ctypes.c_float), ("beta2", ctypes.c_float), ("eps", ctypes.c_float),
+        ("reserved", ctypes.c_int32),
+    ]
 
 
 class SaKernelProf(ctypes.Structure):
@@ -90,6 +101,15 @@ def lib() -> ctypes.CDLL:
     L.sa_copy_state.argtypes = [vp, i32, vp, sz, vp]
     L.sa_profile_enable.argtypes = [vp, i32]
     L.sa_profile_read.argtypes = [vp, P(SaKernelProf), i32, P(i32)]
+    fp = ctypes.POINTER(ctypes.c_float)
+    L.sa_mlp_create.argtypes = [P(SaMlpConfig), fp, P(vp)]
+    L.sa_mlp_destroy.argtypes = [vp]
+    L.sa_mlp_set_scaling.argtypes = [vp, fp, fp, fp, fp]
+    L.sa_mlp_forward.argtypes = [vp, vp, i32, vp, vp]
+    L.sa_mlp_train_step.argtypes = [vp, vp, vp, i32, vp, vp]
+    L.sa_mlp_get.argtypes = [vp, i32, fp, sz, vp]
+    L.sa_learned_attach.argtypes = [vp, vp, i32]
+    L.sa_set_time.argtypes = [vp, ctypes.c_double]
     for name in EXPORTS:
         if name != "sa_status_string":
             getattr(L, name).restype = i32

@@ -141,9 +141,23 @@ class Sequence:
         x, g = self.initial_guess(A, b, x)
         x, s = self.solve(A, b, x)
         self.push(x)
-        for key in ("k_eff", "k_sketch", "used_fallback", "history", "ms_guess"):
+        for key in ("k_eff", "k_sketch", "used_fallback", "history", "ms_guess", "used_learned"):
             s[key] = g[key]
         return x, s
+
+    # ------------------------------------------------------------------ learned guess
+    def learned_attach(self, mlp: "MLP", n_hist: int = 8):
+        """Use the predictor for the initial guesses from now on (fresh sequence)."""
+        nv.check(nv.lib().sa_learned_attach(self._h, mlp._h if mlp is not None else None, n_hist),
+                 "sa_learned_attach")
+        self._mlp = mlp
+
+    def set_time(self, t: float):
+        nv.check(nv.lib().sa_set_time(self._h, float(t)), "sa_set_time")
+
+    def last_target(self) -> np.ndarray:
+        """The learned target written by the last push (M coefficients, lag order)."""
+        return self.copy_state("target")
 
     # ------------------------------------------------------------------ inspection
     def profile_enable(self, enable: bool = True):
@@ -174,10 +188,80 @@ class Sequence:
         elif what == "order":
             out = np.empty(self.M, dtype=np.int32)
             code = 3
+        elif what == "target":
+            out = np.empty(self.M, dtype=np.float64)
+            code = 4
         else:
             raise ValueError(what)
         nv.check(L.sa_copy_state(self._h, code, out.ctypes.data, out.nbytes, _stream(self.stream)),
                  "sa_copy_state")
         if what in ("SX", "X"):
             return out.T.copy()   # column-major on the device -> (rows, M)
+        return out
+
+
+class MLP:
+    """The coefficient-predictor MLP on the device (sa_mlp_*)."""
+
+    def __init__(self, sizes, params, max_batch: int = 256, lr: float = 1e-3, beta1: float = 0.9,
+                 beta2: float = 0.999, eps: float = 1e-8):
+        """sizes = [n_in, hidden, ..., hidden, n_out]; params = [(W_l, b_l)] (float32)."""
+        hidden = sizes[1:-1]
+        if len(set(hidden)) > 1:
+            raise ValueError("all hidden layers have one width")
+        self.sizes = list(sizes)
+        self.cfg = nv.SaMlpConfig(n_in=sizes[0], n_hidden=hidden[0] if hidden else sizes[-1],
+                                  n_layers=len(hidden), n_out=sizes[-1], max_batch=max_batch, lr=lr,
+                                  beta1=beta1, beta2=beta2, eps=eps, reserved=0)
+        flat = np.concatenate([np.concatenate([np.asarray(W, np.float32).ravel(), np.asarray(b, np.float32)])
+                               for W, b in params]).astype(np.float32)
+        self.n_params = flat.size
+        h = ctypes.c_void_p(0)
+        nv.check(nv.lib().sa_mlp_create(ctypes.byref(self.cfg), flat.ctypes.data_as(ctypes.POINTER(ctypes.c_float)),
+                                        ctypes.byref(h)), "sa_mlp_create")
+        self._h = h
+
+    def close(self):
+        if getattr(self, "_h", None) and self._h.value:
+            nv.lib().sa_mlp_destroy(self._h)
+            self._h = ctypes.c_void_p(0)
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def set_scaling(self, mu_in, sd_in, mu_out, sd_out):
+        arrs = [np.ascontiguousarray(a, dtype=np.float32) for a in (mu_in, sd_in, mu_out, sd_out)]
+        fp = ctypes.POINTER(ctypes.c_float)
+        nv.check(nv.lib().sa_mlp_set_scaling(self._h, *[a.ctypes.data_as(fp) for a in arrs]), "sa_mlp_set_scaling")
+
+    def forward(self, x: torch.Tensor, stream=None) -> torch.Tensor:
+        """Standardised outputs for raw float32 rows x (device)."""
+        y = torch.empty(x.shape[0], self.sizes[-1], dtype=torch.float32, device=x.device)
+        nv.check(nv.lib().sa_mlp_forward(self._h, _ptr(x), x.shape[0], _ptr(y), _stream(stream)), "sa_mlp_forward")
+        return y
+
+    def train_step(self, x: torch.Tensor, t: torch.Tensor, loss: Optional[torch.Tensor] = None, stream=None):
+        nv.check(nv.lib().sa_mlp_train_step(self._h, _ptr(x), _ptr(t), x.shape[0],
+                                            _ptr(loss) if loss is not None else None, _stream(stream)),
+                 "sa_mlp_train_step")
+
+    def get(self, what: str = "params") -> np.ndarray:
+        code = {"params": 0, "grads": 1, "adam_m": 2, "adam_v": 3}[what]
+        out = np.empty(self.n_params, dtype=np.float32)
+        nv.check(nv.lib().sa_mlp_get(self._h, code, out.ctypes.data_as(ctypes.POINTER(ctypes.c_float)), out.size,
+                                     _stream(None)), "sa_mlp_get")
+        return out
+
+    def unflatten(self, flat: np.ndarray):
+        """[(W_l, b_l)] views of a flat parameter (or gradient) vector."""
+        out, o = [], 0
+        for fin, fout in zip(self.sizes[:-1], self.sizes[1:]):
+            W = flat[o:o + fin * fout].reshape(fout, fin)
+            o += fin * fout
+            b = flat[o:o + fout]
+            o += fout
+            out.append((W, b))
         return out

@@ -76,6 +76,25 @@ def test_null_handles_and_status_strings(nv):
         s = L.sa_status_string(code).decode()
         assert s and s != "unknown status"
     assert L.sa_status_string(99).decode() == "unknown status"
+    # measurement and predictor entry points validate before touching the device
+    cnt = ctypes.c_int32(0)
+    assert L.sa_profile_enable(None, 1) == nv.SA_ESTATE
+    assert L.sa_profile_read(None, None, 0, ctypes.byref(cnt)) == nv.SA_ESTATE
+    assert L.sa_learned_attach(None, None, 8) == nv.SA_ESTATE
+    assert L.sa_set_time(None, 0.0) == nv.SA_ESTATE
+    assert L.sa_mlp_destroy(None) == nv.SA_EINVAL
+    assert L.sa_mlp_forward(None, None, 1, None, None) == nv.SA_EINVAL
+    assert L.sa_mlp_train_step(None, None, None, 1, None, None) == nv.SA_EINVAL
+    assert L.sa_mlp_get(None, 0, None, 0, None) == nv.SA_EINVAL
+    assert L.sa_mlp_set_scaling(None, None, None, None, None) == nv.SA_EINVAL
+    m = ctypes.c_void_p(0)
+    bad = nv.SaMlpConfig(n_in=4, n_hidden=8, n_layers=9, n_out=2, max_batch=4, lr=1e-3, beta1=0.9, beta2=0.999,
+                         eps=1e-8, reserved=0)
+    w = (ctypes.c_float * 16)()
+    assert L.sa_mlp_create(ctypes.byref(bad), w, ctypes.byref(m)) == nv.SA_EINVAL
+    bad.n_layers, bad.max_batch = 2, 0
+    assert L.sa_mlp_create(ctypes.byref(bad), w, ctypes.byref(m)) == nv.SA_EINVAL
+    assert L.sa_mlp_create(None, w, ctypes.byref(m)) == nv.SA_EINVAL
     h = ctypes.c_void_p(0)
     ws = ctypes.create_string_buffer(64)
     # misaligned / undersized workspaces are rejected before any device call
@@ -98,6 +117,8 @@ int main(void) {
   P(sa_config, tol) P(sa_config, seed) P(sa_config, poll) P(sa_config, rank_tol_chol)
   P(sa_csr, val_dev) P(sa_csr, val_is_fp32) P(sa_info, relres0) P(sa_info, ms_solve)
   P(sa_kernel_prof, launches) P(sa_kernel_prof, ms) P(sa_kernel_prof, bytes)
+  P(sa_info, used_learned) P(sa_mlp_config, lr) P(sa_mlp_config, eps) P(sa_mlp_config, max_batch)
+  printf("sa_mlp_config %zu\n", sizeof(sa_mlp_config));
   return 0;
 }
 """)
@@ -108,11 +129,12 @@ int main(void) {
     assert int(lines["sa_csr"]) == ctypes.sizeof(nv.SaCsr)
     assert int(lines["sa_info"]) == ctypes.sizeof(nv.SaInfo)
     assert int(lines["sa_kernel_prof"]) == ctypes.sizeof(nv.SaKernelProf)
+    assert int(lines["sa_mlp_config"]) == ctypes.sizeof(nv.SaMlpConfig)
     for key, v in lines.items():
         if "." in key:
             struct, field = key.split(".")
             cls = {"sa_config": nv.SaConfig, "sa_csr": nv.SaCsr, "sa_info": nv.SaInfo,
-                   "sa_kernel_prof": nv.SaKernelProf}[struct]
+                   "sa_kernel_prof": nv.SaKernelProf, "sa_mlp_config": nv.SaMlpConfig}[struct]
             assert getattr(cls, field).offset == int(v), key
 
 
