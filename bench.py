@@ -111,10 +111,11 @@ def mixed_3d(sacc, torch, np, warmup, steps):
     rhs_d = torch.as_tensor(np.stack(rhs3)).cuda()
     out = {"workload": f"lognormal3d 128^3 (n={p3.n}), M={m3['M']}, Gaussian s={m3['s']}, Galerkin, CG, "
                        f"relres {m3['tol']:g}, float32 operator", "steps_timed": f"{warmup}..{warmup + steps - 1}"}
-    for prec in ("fp64", "mixed"):
+    for prec in ("fp64", "mixed", "mixed_krylov"):
         log(f"mixed_3d: {prec} run")
-        vd = v32_d if prec == "mixed" else v32_d.double()
-        A3 = sacc.DeviceCSR(rowptr3, col3, vals32[0] if prec == "mixed" else vals32[0].astype(np.float64))
+        f32 = prec != "fp64"
+        vd = v32_d if f32 else v32_d.double()
+        A3 = sacc.DeviceCSR(rowptr3, col3, vals32[0] if f32 else vals32[0].astype(np.float64))
         ci, cw, _ = run_sequence(sacc, torch, A3, vd, rhs_d, m3, steps, warmup, precision=prec)
         out[prec] = dict(ms_per_step=round(1e3 * cw / steps, 4),
                          iters_per_step=float(np.mean([d["iters"] for d in ci])),
@@ -122,6 +123,7 @@ def mixed_3d(sacc, torch, np, warmup, steps):
                          relres_max=float(max(d["relres"] for d in ci)))
         del A3, vd
     out["speedup_mixed_vs_fp64"] = round(out["fp64"]["ms_per_step"] / out["mixed"]["ms_per_step"], 3)
+    out["speedup_mixed_krylov_vs_fp64"] = round(out["fp64"]["ms_per_step"] / out["mixed_krylov"]["ms_per_step"], 3)
     return out
 
 
@@ -205,6 +207,72 @@ def learned_cmp(sacc, torch, np, n_train, n_eval, epochs=60, batch=32, n_hist=8)
     return out
 
 
+def batch_cmp(sacc, torch, np, warmup, steps, max_streams=4, seed=4, nseq=64, precision=None):
+    """The batched workload: 64 independent 2-D sequences (sides U{96..768}, M in
+    {8, 16, 24}, half advective with GMRES(30), the rest CG), float32 values with FP64
+    refinement to 1e-8, stepped together by the library's batch driver on up to
+    max_streams streams; the plan is tuned on the steps after the histories fill.
+    Matrix values of every step come from each sequence's affine value basis and the
+    right-hand sides from the generator, staged in HBM before the timed steps."""
+    from gen import batch_problems
+
+    probs = batch_problems(seed=seed, nseq=nseq, steps=warmup + steps)
+    total = warmup + steps
+    log(f"batch: staging {total} steps of {nseq} sequences")
+    seqs, pats, vals, rhs, xs = [], [], [], [], []
+    nnz_tot, n_tot = 0, 0
+    for p, m in probs:
+        rowptr, col = p.pattern()
+        Bv = torch.as_tensor(p.value_basis()).cuda()
+        C = torch.as_tensor(np.stack([p.value_coefs(i) for i in range(total)])).cuda()
+        vals.append((C @ Bv).float())          # total x nnz, float32 values
+        del Bv, C
+        rhs.append(torch.as_tensor(np.stack([p.rhs(i) for i in range(total)])).cuda())
+        pats.append((torch.as_tensor(rowptr).cuda(), torch.as_tensor(col).cuda()))
+        xs.append(torch.zeros(p.n, dtype=torch.float64, device="cuda"))
+        seqs.append(sacc.Sequence(p.n, m["M"], s=m["s"], sketch=m["sketch"], solver=m["solver"],
+                                  restart=m["restart"], tol=m["tol"], seed=m["method_seed"],
+                                  precision=precision or m["prec"], max_refine=m["max_refine"]))
+        nnz_tot += int(col.size)
+        n_tot += p.n
+    batch = sacc.Batch(seqs, max_streams=max_streams, tune_warmup=max(m["M"] for _, m in probs))
+
+    class View:  # a CSR view on one staged step (no copy)
+        def __init__(self, rp, cl, v):
+            self.rowptr, self.col, self.val = rp, cl, v
+            self.n, self.nnz = rp.numel() - 1, cl.numel()
+
+        def c_struct(self):
+            return sacc.DeviceCSR.c_struct(self)
+
+    def run(i):
+        As = [View(pats[j][0], pats[j][1], vals[j][i]) for j in range(nseq)]
+        bs = [rhs[j][i] for j in range(nseq)]
+        return batch.step(As, bs, xs)
+
+    for i in range(warmup):
+        run(i)
+        if (i + 1) % 10 == 0:
+            log(f"  batch warmup step {i + 1}/{warmup}, plan {batch.plan()}")
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    its, rel, st = 0, 0.0, []
+    for i in range(warmup, total):
+        infos = run(i)
+        its += sum(d["iters"] for d in infos)
+        rel = max(rel, max(d["relres"] for d in infos))
+        st += [d["status"] for d in infos]
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    return dict(workload=f"{nseq} sequences, sides U{{96..768}} (seed {seed}), n total {n_tot}, nnz total {nnz_tot}, "
+                         f"M in {{8,16,24}}, half GMRES(30) / half CG, float32 operator and Krylov vectors + FP64 "
+                         f"refinement ({precision or probs[0][1]['prec']}, at most "
+                         f"{probs[0][1]['max_refine']} sweeps), relres 1e-8",
+                steps_timed=f"{warmup}..{total - 1}", ms_per_step=round(1e3 * wall / steps, 3),
+                krylov_iters_per_step=its / steps, relres_max=rel,
+                not_converged=int(sum(1 for s_ in st if s_ != 0)), plan=batch.plan())
+
+
 def committed_traffic(kernel):
     """HBM bytes per launch of `kernel` from the committed counter summary, or None when
     there is none or the kernel sources have changed since the counters were taken."""
@@ -278,6 +346,9 @@ def main():
     ap.add_argument("--no-comparators", action="store_true")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="run 3 plain 256 MiB device copies first (reference for HBM byte counters)")
+    ap.add_argument("--batch-warmup", type=int, default=31)
+    ap.add_argument("--batch-steps", type=int, default=10)
+    ap.add_argument("--only-batch", action="store_true", help="run only the batched workload")
     ap.add_argument("--learned-train", type=int, default=200)
     ap.add_argument("--learned-eval", type=int, default=100)
     ap.add_argument("--mixed-warmup", type=int, default=32)
@@ -293,6 +364,10 @@ def main():
 
     import paper_2309_02156_amd as sacc
     from gen import config
+
+    if args.only_batch:
+        print(json.dumps({"batch64": batch_cmp(sacc, torch, np, args.batch_warmup, args.batch_steps)}), flush=True)
+        return
 
     p, method = config(1)
     total = args.warmup + args.steps
@@ -340,12 +415,27 @@ def main():
             ci, cw, _ = run_sequence(sacc, torch, A, vals_d, rhs_d, method, args.steps, args.warmup, guess=kind)
             comparators[kind] = dict(ms_per_step=1e3 * cw / args.steps,
                                      iters_per_step=float(np.mean([d["iters"] for d in ci])))
+        # float32 operator / Krylov vectors with FP64 history and refinement on the same
+        # 512 x 512 sequence (its float32-valued operator)
+        log("comparator run: mixed_krylov (512 x 512)")
+        A32 = sacc.DeviceCSR(rowptr, col, vals[0].astype(np.float32))
+        v32 = vals_d.float()
+        ci, cw, _ = run_sequence(sacc, torch, A32, v32, rhs_d, method, args.steps, args.warmup,
+                                 precision="mixed_krylov")
+        comparators["mixed_krylov_2d"] = dict(ms_per_step=round(1e3 * cw / args.steps, 4),
+                                              iters_per_step=float(np.mean([d["iters"] for d in ci])),
+                                              refinements_per_step=float(np.mean([d["refinements"] for d in ci])),
+                                              relres_max=float(max(d["relres"] for d in ci)),
+                                              note="float32 operator values; relres against it")
+        del A32, v32
         # mixed precision where it is meant to run: the 128^3 float32-valued 3-D sequence
         # (CG, M = 30, Gaussian s = 60), against the plain FP64 method on the same
         # operator (the float32 values upcast), both to relres 1e-8
         comparators["mixed_3d"] = mixed_3d(sacc, torch, np, args.mixed_warmup, args.mixed_steps)
         # learned coefficient predictor on the 512 x 512 sequence
         comparators["learned"] = learned_cmp(sacc, torch, np, args.learned_train, args.learned_eval)
+        # 64 independent sequences stepped together
+        comparators["batch64"] = batch_cmp(sacc, torch, np, args.batch_warmup, args.batch_steps)
 
 
     gbs, spmv_ms, spmv_bytes = spmv_gbps(sacc, torch, A)

@@ -234,6 +234,50 @@ class SeqProblem:
         want32 = self.fp32_values if fp32 is None else fp32
         return CSR(self.n, rowptr, col, val.astype(np.float32) if want32 else val)
 
+    def value_basis(self):
+        """2-D workloads: CSR values of A(t) as sum_k coef_k(t) B[k] (B: 7 x nnz).
+
+        A(t) = D0 + cos(t + phi3) D1 + c(t) I + |v_x| / h I + v_x+ / h (-W) + v_x- / h E
+        + |v_y| / h I + v_y+ / h (-S) + v_y- / h N, with D0, D1 the diffusion part split by
+        k = 1 + cos(t + phi3) K(x, y) and W, E, S, N the indicator of each stencil slot;
+        `value_coefs(i)` gives the 7 coefficients.  Equal to `matrix(i)` up to rounding.
+        """
+        assert self.dim == 2, "the affine value basis is defined for the 2-D workloads"
+        self.pattern()
+        mask = self._pattern[2]
+        h = self.h
+        inv_h2 = 1.0 / (h * h)
+        gx, gy, _ = self._node_index_coords()
+        p1, p2, _, _ = self.coef_phase
+        n, nst = self.n, 5
+        D0 = np.zeros((n, nst))
+        D1 = np.zeros((n, nst))
+        slots = [0, 1, 3, 4]  # S, W, E, N
+        for slot, d in zip(slots, [(0, -1), (-1, 0), (1, 0), (0, 1)]):
+            x = (gx + 0.5 * d[0]) * h
+            y = (gy + 0.5 * d[1]) * h
+            K = 0.5 * np.sin(TWO_PI * x + p1) * np.cos(TWO_PI * y + p2)
+            D0[:, slot] = -inv_h2
+            D1[:, slot] = -K * inv_h2
+            D0[:, 2] += inv_h2
+            D1[:, 2] += K * inv_h2
+        E = [np.zeros((n, nst)) for _ in range(5)]   # I, -W, E, -S, N
+        E[0][:, 2] = 1.0
+        E[1][:, 1] = -1.0
+        E[2][:, 3] = 1.0
+        E[3][:, 0] = -1.0
+        E[4][:, 4] = 1.0
+        return np.stack([D0[mask], D1[mask], E[0][mask], E[1][mask], E[2][mask], E[3][mask], E[4][mask]])
+
+    def value_coefs(self, i: int) -> np.ndarray:
+        """Coefficients of `value_basis` at t_i."""
+        t = self.t(i)
+        h = self.h
+        vx, vy = self.velocity(t)
+        diag = self.ccoef(t) + (abs(vx) + abs(vy)) / h
+        return np.array([1.0, math.cos(t + self.coef_phase[2]), diag, max(vx, 0.0) / h, min(vx, 0.0) / h,
+                         max(vy, 0.0) / h, min(vy, 0.0) / h])
+
     def rhs(self, i: int) -> np.ndarray:
         """b(t_i): sum of Gaussian bumps with centres moving on a circle of radius 0.25."""
         t = self.t(i)
@@ -323,7 +367,10 @@ def batch_problems(seed: int = 4, nseq: int = 64, lo: int = 96, hi: int = 768,
                        bump_phase=(ph[4],), bump_sigma=(0.1,), coef_phase=ph[:4],
                        fp32_values=True)
         M = int(Ms[j])
+        # unpreconditioned GMRES(30) needs up to ~7000 iterations per step on the largest
+        # advective grids: with inner solves capped at 10 cycles the refinement sweeps
+        # must allow that many iterations
         m = dict(M=M, sketch="gaussian", s=2 * M, solver="gmres" if adv[j] else "cg",
-                 restart=30, tol=1e-8, prec="mixed", method_seed=seed * 1000 + j)
+                 restart=30, tol=1e-8, prec="mixed_krylov", max_refine=100, method_seed=seed * 1000 + j)
         out.append((p, m))
     return out

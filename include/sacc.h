@@ -47,6 +47,10 @@ extern "C" {
 #define SA_MIXED 1         /* float32 matrix values (val_is_fp32 = 1), history, basis and
                               inner Krylov vectors; float64 arithmetic in registers, the
                               small dense solves and the outer iterative refinement      */
+#define SA_MIXED_KRYLOV 2  /* as SA_MIXED but history and basis in float64: the initial
+                              guess keeps FP64 accuracy (float32 storage of the history
+                              puts rounding noise of relative size 6e-8 into every guess,
+                              amplified by the operator in the residual)                */
 
 #define SA_CG 0            /* conjugate gradients (Hestenes-Stiefel), SPD A             */
 #define SA_GMRES 1         /* restarted GMRES(restart), classical Gram-Schmidt twice    */
@@ -72,7 +76,7 @@ typedef struct {
   int32_t restart;        /* GMRES restart length, 1..64                               */
   double tol;             /* stop when ||b - A x||_2 <= tol ||b||_2                   */
   int32_t maxit;          /* iteration cap (A-products for CG, Arnoldi steps GMRES)    */
-  int32_t precision;      /* SA_FP64 or SA_MIXED                                       */
+  int32_t precision;      /* SA_FP64, SA_MIXED or SA_MIXED_KRYLOV                      */
   double inner_tol;       /* mixed: inner solve tolerance relative to the current
                              residual, in (0, 1)                                      */
   int32_t max_refine;     /* mixed: cap on refinement sweeps, >= 1                     */
@@ -136,7 +140,7 @@ int sa_init_sequence(const sa_config *cfg, void *dev_ws, size_t ws_bytes, void *
 /* Append the solution x(t_{i-1}) to the history, dropping the oldest one when M are
  * held (the sliding window of Section 2.1), and sketch it (S x) for the next QR.
  * x_dev: n float64 values; SA_MIXED stores them rounded to float32 and sketches the
- * stored values.
+ * stored values (SA_FP64 and SA_MIXED_KRYLOV keep them in float64).
  * Asynchronous.  Errors: SA_EINVAL (null), SA_ESTATE (destroyed sequence). */
 int sa_push_solution(sa_seq *q, const void *x_dev, void *stream);
 
@@ -152,7 +156,7 @@ int sa_initial_guess(sa_seq *q, const sa_csr *A, const void *b_dev, void *x0_dev
 /* Krylov solve of A x = b from the iterate in x_dev (Alg. 1 step 4): CG or GMRES per
  * the config, stopping on ||b - A x||_2 <= tol ||b||_2 checked before the first
  * iteration and confirmed with the true residual.  x_dev: float64, in = x0, out = x.
- * SA_MIXED: A must carry float32 values; each refinement sweep forms r = b - A x in
+ * SA_MIXED, SA_MIXED_KRYLOV: A must carry float32 values; each refinement sweep forms r = b - A x in
  * float64, stops on the test above, else solves A d = fl32(r) with float32-stored
  * vectors until the solver's own residual estimate is below inner_tol ||fl32(r)|| (no
  * true-residual confirmation: the next sweep's residual checks the result) or
@@ -240,10 +244,35 @@ int sa_learned_attach(sa_seq *q, sa_mlp *m, int n_hist);
 /* Time t of the next system, for the learned guess's inputs.  Errors: SA_ESTATE. */
 int sa_set_time(sa_seq *q, double t);
 
+/* ---- batches of independent sequences (Section 5: many plane sequences at once) ----
+ * One step of every sequence of the batch (initial guess into x[i], solve, push of the
+ * solution), the sequences spread over up to max_streams HIP streams owned by the batch
+ * (one host thread each) so that small sequences run concurrently; sequences go to
+ * streams longest-first by the estimated cost nnz x (iterations of their last step +
+ * 10).  The plan (streams used, Krylov poll batch) is tuned on the steps after the
+ * first tune_warmup ones: each step from then on times one candidate plan, per Krylov
+ * iteration of the batch, until all candidates are timed; the fastest is kept. */
+typedef struct sa_batch sa_batch;
+
+/* seqs: nseq sequences created by sa_init_sequence (not owned; each must not be used
+ * elsewhere while the batch steps).  Errors: SA_EINVAL, SA_ENOMEM, SA_EHIP. */
+int sa_batch_create(sa_seq *const *seqs, int nseq, int max_streams, int tune_warmup, sa_batch **out);
+int sa_batch_destroy(sa_batch *b);
+
+/* A[i], rhs[i] (float64, device), x[i] (float64, device; out: the solution); info
+ * (nseq entries, may be NULL) receives each sequence's solve info.  Synchronous.
+ * Returns SA_OK when every sequence's guess, solve and push ran (a solve that stopped
+ * at maxit or broke down is reported in its info.status), else the first error. */
+int sa_batch_step(sa_batch *b, const sa_csr *const *A, const void *const *rhs, void *const *x,
+                  sa_info *info);
+
+/* The plan in use and whether tuning has finished. */
+int sa_batch_plan(const sa_batch *b, int *streams, int *poll, int *tuned);
+
 /* Copy internal state to host memory for inspection:
  *   what = 0: SX, s x M float64 column-major, columns in ring-slot order;
- *   what = 1: X, n x M column-major in ring-slot order, float64 (SA_FP64) or
- *             float32 (SA_MIXED);
+ *   what = 1: X, n x M column-major in ring-slot order, float32 for SA_MIXED, else
+ *             float64;
  *   what = 2: coefficients c of the last guess in history (ring-slot) coordinates,
  *             M float64 (x0 = X c);
  *   what = 3: ring order, M int32: slot of the oldest .. newest column (-1 unused);

@@ -12,7 +12,8 @@ the paper's Baseline of Sections 4 and 5).
 Precision "fp64" (the paper's setting) or "mixed" (not in the paper): the history and
 the basis Q1 are stored in float32 (the sketch is taken of the stored column), the
 matrix carries float32 values, and each system is solved by FP64 iterative refinement
-around float32-stored inner Krylov solves (``mixed.solve_ir``).
+around float32-stored inner Krylov solves (``mixed.solve_ir``).  Precision "mixed_krylov"
+keeps the history and basis in float64 and otherwise equals "mixed".
 """
 
 from __future__ import annotations
@@ -39,7 +40,7 @@ class Sequence:
         self.solver, self.restart, self.tol, self.maxit = solver, restart, tol, maxit
         self.projection, self.tau_s, self.tau_c, self.guess = projection, tau_s, tau_c, guess
         self.seed = seed
-        if precision not in ("fp64", "mixed"):
+        if precision not in ("fp64", "mixed", "mixed_krylov"):
             raise ValueError(precision)
         self.precision, self.inner_tol, self.max_refine = precision, inner_tol, max_refine
         self.store = mx.fl32 if precision == "mixed" else None
@@ -83,7 +84,7 @@ class Sequence:
 
     def solve(self, A, b, x0):
         """Krylov solve from x0; in the mixed mode A must carry float32 values."""
-        if self.precision == "mixed":
+        if self.precision != "fp64":
             return mx.solve_ir(A, b, x0, self.tol, self.solver, self.restart, self.inner_tol,
                                self.max_refine, self.maxit)
         if self.solver == "cg":

@@ -6,4 +6,4 @@ coefficient-predictor ``MLP``.
 """
 
 from .native import SaccError  # noqa: F401
-from .sequence import MLP, DeviceCSR, Sequence, spmv  # noqa: F401
+from .sequence import MLP, Batch, DeviceCSR, Sequence, spmv  # noqa: F401

@@ -5,8 +5,11 @@
 #include <stdint.h>
 #include <string.h>
 
+#include <algorithm>
+#include <chrono>
 #include <new>
 #include <string>
+#include <thread>
 #include <vector>
 
 #include "../../include/sacc.h"
@@ -39,7 +42,8 @@ struct sa_mlp {
 
 struct sa_seq {
   sa_config cfg;
-  bool mixed = false;  // SA_MIXED: FP32 history / basis / inner Krylov vectors
+  bool mixed = false;  // SA_MIXED or SA_MIXED_KRYLOV: float32 operator and inner Krylov vectors, FP64 refinement
+  bool x32 = false;    // SA_MIXED: history and basis stored in float32 too
   char *ws = nullptr;
   size_t ws_bytes = 0;
   void *X = nullptr, *Q1 = nullptr;  // double or float storage
@@ -123,8 +127,8 @@ int validate(const sa_config *c) {
   if (c->solver != SA_CG && c->solver != SA_GMRES) return SA_EINVAL;
   if (c->solver == SA_GMRES && (c->restart < 1 || c->restart > MAXR)) return SA_EINVAL;
   if (!(c->tol > 0.0) || c->maxit < 0) return SA_EINVAL;
-  if (c->precision != SA_FP64 && c->precision != SA_MIXED) return SA_EINVAL;
-  if (c->precision == SA_MIXED && (!(c->inner_tol > 0.0) || !(c->inner_tol < 1.0) || c->max_refine < 1))
+  if (c->precision != SA_FP64 && c->precision != SA_MIXED && c->precision != SA_MIXED_KRYLOV) return SA_EINVAL;
+  if (c->precision != SA_FP64 && (!(c->inner_tol > 0.0) || !(c->inner_tol < 1.0) || c->max_refine < 1))
     return SA_EINVAL;
   if (c->guess < SA_GUESS_PROJECTION || c->guess > SA_GUESS_PREVIOUS) return SA_EINVAL;
   return SA_OK;
@@ -133,20 +137,21 @@ int validate(const sa_config *c) {
 Layout layout(const sa_config *c) {
   Layout L;
   const size_t M = (size_t)c->M;
-  const bool mixed = c->precision == SA_MIXED;
-  const size_t w = mixed ? sizeof(float) : sizeof(double);  // history / basis / Krylov word
+  const bool mixed = c->precision != SA_FP64;
+  const size_t wx = c->precision == SA_MIXED ? sizeof(float) : sizeof(double);  // history / basis word
+  const size_t wk = mixed ? sizeof(float) : sizeof(double);                      // Krylov word
   const size_t ld = (size_t)padded_ld(c->n);
   size_t off = 0;
   L.X = off;
-  off += up(ld * M * w);
+  off += up(ld * M * wx);
   L.SX = off;
   off += up((size_t)c->s * M * sizeof(double));
   L.Q1 = off;
-  off += up(ld * M * w);
+  off += up(ld * M * wx);
   L.kry = off;
   // GMRES: V (restart + 1 columns) and a scratch column; CG: r, two p, q
   const size_t kv = c->solver == SA_GMRES ? (size_t)(c->restart + 2) : 4;
-  off += up(ld * kv * w);
+  off += up(ld * kv * wk);
   L.partials = off;
   off += up(partials_doubles(c->n, c->M, c->s) * sizeof(double));
   L.rows = off;
@@ -433,7 +438,7 @@ int guess_learned(sa_seq *q, const CsrView &v, const double *b, double *x0, int 
   HIP_TRY(launch_learn_features(q->ctl, q->lhist, c.M, (int)q->ltargets, q->t_now, m->mu_in, m->sd_in, m->b.xs, st));
   HIP_TRY(launch_mlp_forward(m->d, m->b, 1, st));
   const float *y = m->b.act[m->d.n_layers];
-  if (q->mixed)
+  if (q->x32)
     HIP_TRY(launch_learn_xpred<float>((const float *)q->X, c.n, q->ld, cnt, newest, c.M, y, m->mu_out, m->sd_out, xp,
                                       st));
   else
@@ -465,7 +470,8 @@ int sa_init_sequence(const sa_config *cfg, void *dev_ws, size_t ws_bytes, void *
   sa_seq *q = new (std::nothrow) sa_seq();
   if (!q) return SA_ENOMEM;
   q->cfg = *cfg;
-  q->mixed = cfg->precision == SA_MIXED;
+  q->mixed = cfg->precision != SA_FP64;
+  q->x32 = cfg->precision == SA_MIXED;
   if (q->cfg.poll <= 0) q->cfg.poll = 8;
   q->tau_s = cfg->rank_tol_sketch > 0.0 ? cfg->rank_tol_sketch : 1e-12;
   q->tau_c = cfg->rank_tol_chol > 0.0 ? cfg->rank_tol_chol : 1e-12;
@@ -496,7 +502,7 @@ int sa_init_sequence(const sa_config *cfg, void *dev_ws, size_t ws_bytes, void *
   hipError_t e = hipSuccess;
   if (!rows.empty())
     e = hipMemcpyAsync(q->srht_rows, rows.data(), rows.size() * sizeof(long long), hipMemcpyHostToDevice, st);
-  const size_t w = q->mixed ? sizeof(float) : sizeof(double);
+  const size_t w = q->x32 ? sizeof(float) : sizeof(double);
   if (e == hipSuccess) e = hipMemsetAsync(q->X, 0, (size_t)q->ld * cfg->M * w, st);
   if (e == hipSuccess) e = hipMemsetAsync(q->SX, 0, (size_t)cfg->s * cfg->M * sizeof(double), st);
   if (e == hipSuccess) e = hipStreamSynchronize(st);
@@ -514,7 +520,7 @@ int sa_push_solution(sa_seq *q, const void *x_dev, void *stream) {
   hipStream_t st = (hipStream_t)stream;
   const sa_config &c = q->cfg;
   const int slot = (int)(q->pushes % c.M);
-  if (q->mixed)
+  if (q->x32)
     HIP_TRY(launch_push<float>((const double *)x_dev, (float *)q->X, q->SX, c.n, q->ld, slot, c.s, c.sketch, c.seed,
                                q->srht_rows, q->partials, q->ctl, st));
   else
@@ -548,14 +554,14 @@ int sa_initial_guess(sa_seq *q, const sa_csr *A, const void *b_dev, void *x0_dev
   if (cnt == 0 || c.guess == SA_GUESS_ZERO) {
     HIP_TRY(hipMemsetAsync(x0_dev, 0, nb, st));
   } else if (c.guess == SA_GUESS_PREVIOUS) {
-    if (q->mixed)
+    if (q->x32)
       HIP_TRY(launch_to_double<float>((const float *)q->X + (size_t)newest * q->ld, (double *)x0_dev, c.n, st));
     else
       HIP_TRY(hipMemcpyAsync(x0_dev, (const double *)q->X + (size_t)newest * q->ld, nb, hipMemcpyDeviceToDevice,
                              st));
   } else {
     CsrView v = view(A);
-    if (q->mixed)
+    if (q->x32)
       SA_TRY(guess_projection<float>(q, v, (const double *)b_dev, (double *)x0_dev, cnt, st));
     else
       SA_TRY(guess_projection<double>(q, v, (const double *)b_dev, (double *)x0_dev, cnt, st));
@@ -883,7 +889,7 @@ int sa_copy_state(sa_seq *q, int what, void *host_dst, size_t bytes, void *strea
   if (!host_dst) return SA_EINVAL;
   hipStream_t st = (hipStream_t)stream;
   const sa_config &c = q->cfg;
-  const size_t w = q->mixed ? sizeof(float) : sizeof(double);
+  const size_t w = q->x32 ? sizeof(float) : sizeof(double);
   if (what == 4) {  // the learned target written by the last push (M float64, lag order)
     if (!q->mlp || q->ltargets == 0) return SA_ESTATE;
     if (bytes < (size_t)c.M * sizeof(double)) return SA_EINVAL;
@@ -915,6 +921,163 @@ int sa_copy_state(sa_seq *q, int what, void *host_dst, size_t bytes, void *strea
     return SA_OK;
   }
   return SA_EINVAL;
+}
+
+}  // extern "C"
+
+// ============================================================================ batches
+// Batched execution of many independent sequences (the paper's Section 5 setting:
+// 64 independent poloidal-plane sequences advanced together): one step of every
+// sequence, spread over several HIP streams so the small per-sequence kernels of
+// different sequences run concurrently, with a longest-processing-time assignment of
+// sequences to streams and a plan (streams, poll batch) chosen by timing candidates
+// on the first steps after the histories are full.
+
+namespace batchplan {
+
+struct Plan {
+  int streams, poll;
+};
+
+// candidates the autotuner times, one step each (after the history is full)
+const Plan kCandidates[] = {{1, 8}, {2, 8}, {4, 8}, {4, 4}, {4, 16}, {4, 30}, {2, 16}};
+constexpr int kNumCandidates = sizeof(kCandidates) / sizeof(kCandidates[0]);
+
+}  // namespace batchplan
+
+using batchplan::Plan;
+using batchplan::kCandidates;
+using batchplan::kNumCandidates;
+
+struct sa_batch {
+  std::vector<sa_seq *> seqs;
+  std::vector<hipStream_t> streams;
+  std::vector<double> cost;  // estimated cost of a sequence's step (nnz x (iterations + 10))
+  Plan plan{4, 8};
+  int tune_next = 0;        // next candidate to time; kNumCandidates when tuned
+  int tune_warm = 0;        // steps before timing starts (history filling)
+  double tune_best = 1e300;
+  Plan tune_best_plan{4, 8};
+  long long steps = 0;
+};
+
+extern "C" {
+
+int sa_batch_create(sa_seq *const *seqs, int nseq, int max_streams, int tune_warmup, sa_batch **out) {
+  if (!seqs || nseq < 1 || !out || max_streams < 1 || max_streams > 16 || tune_warmup < 0) return SA_EINVAL;
+  for (int i = 0; i < nseq; ++i)
+    if (!seqs[i]) return SA_EINVAL;
+  sa_batch *b = new (std::nothrow) sa_batch();
+  if (!b) return SA_ENOMEM;
+  b->seqs.assign(seqs, seqs + nseq);
+  b->cost.assign(nseq, 1.0);
+  b->streams.resize(max_streams, nullptr);
+  for (auto &s : b->streams)
+    if (hipStreamCreateWithFlags(&s, hipStreamNonBlocking) != hipSuccess) {
+      for (auto &t : b->streams)
+        if (t) (void)hipStreamDestroy(t);
+      delete b;
+      return SA_EHIP;
+    }
+  b->plan = Plan{max_streams, 8};
+  b->tune_warm = tune_warmup;
+  b->tune_next = 0;
+  *out = b;
+  return SA_OK;
+}
+
+int sa_batch_destroy(sa_batch *b) {
+  if (!b) return SA_EINVAL;
+  for (auto &s : b->streams)
+    if (s) (void)hipStreamDestroy(s);
+  delete b;
+  return SA_OK;
+}
+
+int sa_batch_plan(const sa_batch *b, int *streams, int *poll, int *tuned) {
+  if (!b || !streams || !poll || !tuned) return SA_EINVAL;
+  *streams = b->plan.streams;
+  *poll = b->plan.poll;
+  *tuned = b->tune_next >= kNumCandidates ? 1 : 0;
+  return SA_OK;
+}
+
+int sa_batch_step(sa_batch *b, const sa_csr *const *A, const void *const *rhs, void *const *x, sa_info *info) {
+  if (!b || !A || !rhs || !x) return SA_EINVAL;
+  const int nseq = (int)b->seqs.size();
+  for (int i = 0; i < nseq; ++i)
+    if (!A[i] || !rhs[i] || !x[i]) return SA_EINVAL;
+  // plan of this step: a candidate while tuning, else the chosen one
+  const bool timing = b->steps >= b->tune_warm && b->tune_next < kNumCandidates;
+  Plan plan = b->plan;
+  if (timing) plan = kCandidates[b->tune_next];
+  if (plan.streams > (int)b->streams.size()) plan.streams = (int)b->streams.size();
+  // longest processing time first: sequences by decreasing cost to the least loaded stream
+  std::vector<int> order(nseq);
+  for (int i = 0; i < nseq; ++i) order[i] = i;
+  std::sort(order.begin(), order.end(), [&](int a, int c) { return b->cost[a] > b->cost[c]; });
+  std::vector<std::vector<int>> lists(plan.streams);
+  std::vector<double> load(plan.streams, 0.0);
+  for (int i : order) {
+    int best = 0;
+    for (int s = 1; s < plan.streams; ++s)
+      if (load[s] < load[best]) best = s;
+    lists[best].push_back(i);
+    load[best] += b->cost[i];
+  }
+  std::vector<sa_info> inf(nseq);
+  std::vector<int> rc(plan.streams, SA_OK);
+  auto worker = [&](int s) {
+    hipStream_t st = b->streams[s];
+    for (int i : lists[s]) {
+      sa_seq *q = b->seqs[i];
+      q->cfg.poll = plan.poll;
+      memset(&inf[i], 0, sizeof(sa_info));
+      sa_info g;
+      int r = sa_initial_guess(q, A[i], rhs[i], x[i], &g, st);
+      if (r == SA_OK) {
+        r = sa_solve(q, A[i], rhs[i], x[i], &inf[i], st);
+        if (r == SA_NOTCONV || r == SA_EBREAKDOWN) r = SA_OK;  // reported in info
+      }
+      if (r == SA_OK) r = sa_push_solution(q, x[i], st);
+      if (r == SA_OK) r = hipStreamSynchronize(st) == hipSuccess ? SA_OK : SA_EHIP;
+      inf[i].k_eff = g.k_eff;
+      inf[i].k_sketch = g.k_sketch;
+      inf[i].used_fallback = g.used_fallback;
+      inf[i].history = g.history;
+      inf[i].ms_guess = g.ms_guess;
+      if (r != SA_OK) {
+        rc[s] = r;
+        return;
+      }
+    }
+  };
+  const auto t0 = std::chrono::steady_clock::now();
+  std::vector<std::thread> th;
+  for (int s = 1; s < plan.streams; ++s) th.emplace_back(worker, s);
+  worker(0);
+  for (auto &t : th) t.join();
+  const double sec = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+  for (int s = 0; s < plan.streams; ++s)
+    if (rc[s] != SA_OK) return rc[s];
+  long long its = 0;
+  for (int i = 0; i < nseq; ++i) {
+    its += inf[i].iters;
+    b->cost[i] = (double)A[i]->nnz * (double)(inf[i].iters + 10);
+  }
+  if (timing) {
+    // seconds per Krylov iteration of the whole batch (steps differ in iterations)
+    const double per = sec / (double)(its > 0 ? its : 1);
+    if (per < b->tune_best) {
+      b->tune_best = per;
+      b->tune_best_plan = plan;
+    }
+    if (++b->tune_next >= kNumCandidates) b->plan = b->tune_best_plan;
+  }
+  b->steps += 1;
+  if (info)
+    for (int i = 0; i < nseq; ++i) info[i] = inf[i];
+  return SA_OK;
 }
 
 }  // extern "C"

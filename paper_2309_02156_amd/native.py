@@ -14,7 +14,7 @@ LIB_PATH = os.path.join(HERE, "libsacc.so")
 
 SA_OK, SA_NOTCONV = 0, 1
 SA_EINVAL, SA_ENOMEM, SA_EHIP, SA_ESTATE, SA_EBREAKDOWN = -1, -2, -3, -4, -5
-SA_FP64, SA_MIXED = 0, 1
+SA_FP64, SA_MIXED, SA_MIXED_KRYLOV = 0, 1, 2
 SA_CG, SA_GMRES = 0, 1
 SA_GALERKIN, SA_MINRES = 0, 1
 SA_SKETCH_GAUSSIAN, SA_SKETCH_SRHT = 0, 1
@@ -23,7 +23,8 @@ SA_GUESS_PROJECTION, SA_GUESS_ZERO, SA_GUESS_PREVIOUS = 0, 1, 2
 EXPORTS = ("sa_workspace_bytes", "sa_init_sequence", "sa_push_solution", "sa_initial_guess",
            "sa_solve", "sa_destroy_sequence", "sa_status_string", "sa_spmv", "sa_copy_state",
            "sa_profile_enable", "sa_profile_read", "sa_mlp_create", "sa_mlp_destroy", "sa_mlp_set_scaling",
-           "sa_mlp_forward", "sa_mlp_train_step", "sa_mlp_get", "sa_learned_attach", "sa_set_time")
+           "sa_mlp_forward", "sa_mlp_train_step", "sa_mlp_get", "sa_learned_attach", "sa_set_time",
+           "sa_batch_create", "sa_batch_destroy", "sa_batch_step", "sa_batch_plan")
 
 
 class SaConfig(ctypes.Structure):
@@ -110,6 +111,10 @@ def lib() -> ctypes.CDLL:
     L.sa_mlp_get.argtypes = [vp, i32, fp, sz, vp]
     L.sa_learned_attach.argtypes = [vp, vp, i32]
     L.sa_set_time.argtypes = [vp, ctypes.c_double]
+    L.sa_batch_create.argtypes = [P(vp), i32, i32, i32, P(vp)]
+    L.sa_batch_destroy.argtypes = [vp]
+    L.sa_batch_step.argtypes = [vp, P(vp), P(vp), P(vp), P(SaInfo)]
+    L.sa_batch_plan.argtypes = [vp, P(i32), P(i32), P(i32)]
     for name in EXPORTS:
         if name != "sa_status_string":
             getattr(L, name).restype = i32

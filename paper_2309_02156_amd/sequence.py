@@ -16,7 +16,7 @@ from . import native as nv
 
 _SKETCH = {"gaussian": nv.SA_SKETCH_GAUSSIAN, "srht": nv.SA_SKETCH_SRHT}
 _SOLVER = {"cg": nv.SA_CG, "gmres": nv.SA_GMRES}
-_PREC = {"fp64": nv.SA_FP64, "mixed": nv.SA_MIXED}
+_PREC = {"fp64": nv.SA_FP64, "mixed": nv.SA_MIXED, "mixed_krylov": nv.SA_MIXED_KRYLOV}
 _PROJ = {"galerkin": nv.SA_GALERKIN, "minres": nv.SA_MINRES}
 _GUESS = {"projection": nv.SA_GUESS_PROJECTION, "zero": nv.SA_GUESS_ZERO,
           "previous": nv.SA_GUESS_PREVIOUS}
@@ -265,3 +265,44 @@ class MLP:
             o += fout
             out.append((W, b))
         return out
+
+
+class Batch:
+    """Many independent sequences stepped together (sa_batch_*)."""
+
+    def __init__(self, seqs, max_streams: int = 4, tune_warmup: int = 0):
+        self.seqs = list(seqs)
+        arr = (ctypes.c_void_p * len(self.seqs))(*[s._h.value for s in self.seqs])
+        h = ctypes.c_void_p(0)
+        nv.check(nv.lib().sa_batch_create(arr, len(self.seqs), max_streams, tune_warmup, ctypes.byref(h)),
+                 "sa_batch_create")
+        self._h = h
+
+    def close(self):
+        if getattr(self, "_h", None) and self._h.value:
+            nv.lib().sa_batch_destroy(self._h)
+            self._h = ctypes.c_void_p(0)
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def step(self, As, bs, xs):
+        """One step of every sequence; As: DeviceCSR list, bs / xs: float64 device tensors
+        (xs receive the solutions).  Returns the list of info dicts."""
+        n = len(self.seqs)
+        structs = [A.c_struct() for A in As]
+        Aarr = (ctypes.c_void_p * n)(*[ctypes.addressof(s) for s in structs])
+        barr = (ctypes.c_void_p * n)(*[_ptr(b) for b in bs])
+        xarr = (ctypes.c_void_p * n)(*[_ptr(x) for x in xs])
+        infos = (nv.SaInfo * n)()
+        torch.cuda.synchronize()
+        nv.check(nv.lib().sa_batch_step(self._h, Aarr, barr, xarr, infos), "sa_batch_step")
+        return [i.as_dict() for i in infos]
+
+    def plan(self):
+        s, p, t = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32()
+        nv.check(nv.lib().sa_batch_plan(self._h, ctypes.byref(s), ctypes.byref(p), ctypes.byref(t)), "sa_batch_plan")
+        return dict(streams=s.value, poll=p.value, tuned=bool(t.value))

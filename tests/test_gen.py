@@ -124,3 +124,16 @@ def test_batch_workload_shape():
     # deterministic
     again = batch_problems()
     assert [p.N for p, _ in again] == sides.tolist()
+
+
+def test_affine_value_basis_reproduces_assembly():
+    """The 2-D matrices are affine in a few time-dependent scalars; the basis form used
+    to stage long runs on the device equals the direct assembly to rounding."""
+    from gen import batch_problems
+
+    cases = [config(0, N=20)[0], config(1, N=32)[0]] + [p for p, _ in batch_problems(nseq=3, lo=16, hi=40)]
+    for p in cases:
+        B = p.value_basis()
+        for i in (0, 7, 33):
+            ref = p.matrix(i, fp32=False).val
+            assert np.max(np.abs(p.value_coefs(i) @ B - ref)) <= 1e-14 * np.max(np.abs(ref))

@@ -5,7 +5,7 @@ Bars: forward outputs and gradients of the MLP with the same bf16-used weights w
 1e-3 relative (float32 accumulation against float64); Adam parameter trajectories
 within 1e-2 of the oracle's displacement; targets (sketched least-squares
 coordinates) define the same sketched fit S X c on the same injected history, within
-ten times the oracle's own change under a 1e-15 relative perturbation of the sketch
+ten times the oracle's own change under a 1e-13 relative perturbation of the sketch
 (the coefficients of a nearly collinear history are ill-conditioned); the learned guess
 never has a larger residual than the projection's (safeguard) and takes the same
 decision as the oracle's when the two residuals differ by more than 1e-3.  The gain of
@@ -166,12 +166,13 @@ def test_targets_and_learned_guess(sacc):
         if SXs.shape[1] > 0:
             # coefficients of a nearly collinear history are ill-conditioned; compare the
             # sketched fits S X c they define, against 10x the oracle's own change under
-            # a rounding-level perturbation of the sketch (1e-15 relative)
+            # a rounding-level perturbation of the sketch (1e-13 relative: the two sides
+            # run different Householder QR codes)
             k = SXs.shape[1]
             fit_g, fit_o = SXs @ tg[:k], SXs @ to[:k]
             Sx = oseq.S.apply(np.asarray(sols[i], dtype=np.float64))
             rng = np.random.default_rng(i)
-            SXp = SXs * (1 + 1e-15 * rng.standard_normal(SXs.shape))
+            SXp = SXs * (1 + 1e-13 * rng.standard_normal(SXs.shape))
             tp = sketched_ls_target(np.zeros((1, k)), SXp, Sx)  # only SX enters the target
             spread = np.linalg.norm(SXs @ tp - fit_o)
             bound = 10 * spread + 1e-12 * np.linalg.norm(fit_o)

@@ -35,9 +35,9 @@ def sacc():
     return pkg
 
 
-def _oseq(p, m):
+def _oseq(p, m, precision="mixed"):
     return OSeq(p.n, m["M"], m["sketch"], m["s"], m["method_seed"], m["solver"], m["restart"], m["tol"],
-                precision="mixed")
+                precision=precision)
 
 
 def _A(p, i):
@@ -45,19 +45,20 @@ def _A(p, i):
     return A, A.to_scipy().astype(np.float64)
 
 
-@pytest.mark.parametrize("k,N,steps", [(0, 48, 14), (1, 64, 24), (2, 16, 34)])
-def test_mixed_stepwise(sacc, k, N, steps):
-    """Same injected (float32-stored) history on both sides: guess, ranks, counts."""
-    print_case("mixed stepwise", k, N, steps)
+@pytest.mark.parametrize("k,N,steps,prec", [(0, 48, 14, "mixed"), (1, 64, 24, "mixed"), (2, 16, 34, "mixed"),
+                                           (1, 64, 24, "mixed_krylov"), (2, 16, 34, "mixed_krylov")])
+def test_mixed_stepwise(sacc, k, N, steps, prec):
+    """Same injected history on both sides: guess, ranks, counts."""
+    print_case("mixed stepwise", k, N, steps, prec)
     p, m = config(k, N)
-    ref = _oseq(p, m)
+    ref = _oseq(p, m, prec)
     sols = []
     for i in range(steps):
         _, As = _A(p, i)
         x, _, _ = ref.step(As, p.rhs(i))
         sols.append(x)
-    gseq = sacc.Sequence(p.n, **method_kwargs(m, precision="mixed"))
-    oseq = _oseq(p, m)
+    gseq = sacc.Sequence(p.n, **method_kwargs(m, precision=prec))
+    oseq = _oseq(p, m, prec)
     rows = []
     for i in range(steps):
         A, As = _A(p, i)
@@ -89,12 +90,12 @@ def test_mixed_stepwise(sacc, k, N, steps):
                      float(np.linalg.norm(xg - xo) / max(np.linalg.norm(xo), 1e-300))))
         oseq.push(sols[i])
         gseq.push(dev(sols[i]))
-    # history stored as float32 on the device equals the oracle's stored columns
+    # the stored history (float32 for "mixed") equals the oracle's stored columns
     X = gseq.copy_state("X")
     order = gseq.copy_state("order")
     Xo, _ = oseq.history()
     used = [s for s in order if s >= 0]
-    assert X.dtype == np.float32
+    assert X.dtype == (np.float32 if prec == "mixed" else np.float64)
     assert np.array_equal(X[:, used].astype(np.float64), Xo)
     print_case("(step, iters gpu, iters oracle, sweeps gpu, sweeps oracle, |dx|/|x|)", rows)
 
