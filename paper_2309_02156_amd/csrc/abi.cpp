@@ -333,7 +333,8 @@ int run_cg(sa_seq *q, const CsrView &v, Ctl *ctl, const TV *b, TV *x, int maxit,
   SA_TRY(prof_begin(q, ctl, st));
   const size_t w = sizeof(TV), wv = v.fp32 ? 4 : 8;
   const double csr = 4.0 * (v.n + 1) + (4.0 + wv) * v.nnz;
-  const std::string pname = std::string("k_cg_p<") + tname(wv) + ", " + tname(w) + ">";
+  const std::string pname =
+      std::string("k_cg_p<") + tname(wv) + ", " + tname(w) + ", " + std::to_string(cg_rows_per_thread(v.n)) + ">";
   HIP_TRY(launch_cg_start_k<TV>(v, b, x, r, 0, q->partials, ctl, st));
   Poller pl{q, ctl, st};
   bool stop = false;
@@ -380,7 +381,8 @@ int run_gmres(sa_seq *q, const CsrView &v, Ctl *ctl, const TV *b, TV *x, int max
         // SpMV of the source column, columns 0..j-1, the finalised column and y
         const int rb = j <= 8 ? 8 : (j <= 16 ? 16 : 32);
         const double bytes = csr + (j == 0 ? 2.0 : (double)(j + 3)) * w * v.n;
-        const std::string name = std::string("k_gm_f<") + tname(wv) + ", " + tname(w) + ", " + std::to_string(rb) + ">";
+        const std::string name = std::string("k_gm_f<") + tname(wv) + ", " + tname(w) + ", " + std::to_string(rb) +
+                                 ", " + std::to_string(gm_rows_per_thread(v.n)) + ">";
         tp = prof_slot(q, name, bytes, &tm);
       }
       HIP_TRY(launch_gm_step<TV>(v, V, T, q->ld, j, cycle > 0 ? 1 : 0, q->partials, ctl, st, tp));

@@ -169,6 +169,49 @@ __device__ inline void final_sum(const double *partials, int nblk, int W, int kc
   }
 }
 
+// final_sum for kc <= 64 entries in two halves, so that a kernel can issue the loads
+// of its partial rows before it knows whether it runs (together with its control-block
+// reads: one trip to memory instead of two).  final_part: this thread's sum over its
+// rows (the same rows and order as final_sum); final_tree: the fixed tree into LDS
+// out[0..kc), identical results to final_sum.
+__device__ inline double final_part(const double *partials, int nblk, int W, int kc) {
+  constexpr int U = 32;
+  int ep = 1;
+  while (ep < kc) ep <<= 1;
+  const int ngrp = blockDim.x / ep;
+  const int e = threadIdx.x % ep, grp = threadIdx.x / ep;
+  double s = 0.0;
+  if (e < kc) {
+    for (int b0 = grp; b0 < nblk; b0 += U * ngrp) {
+      double t[U];
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        const int b = b0 + u * ngrp;
+        const double x = partials[(size_t)(b < nblk ? b : nblk - 1) * W + e];
+        t[u] = b < nblk ? x : 0.0;
+      }
+#pragma unroll
+      for (int u = 0; u < U; ++u) s += t[u];
+    }
+  }
+  return s;
+}
+
+__device__ inline void final_tree(double s, int kc, double *out, double *scratch) {
+  int ep = 1;
+  while (ep < kc) ep <<= 1;
+  const int ngrp = blockDim.x / ep;
+  const int grp = threadIdx.x / ep;
+  scratch[threadIdx.x] = s;
+  __syncthreads();
+  for (int off = ngrp / 2; off > 0; off >>= 1) {
+    if (grp < off) scratch[threadIdx.x] += scratch[threadIdx.x + off * ep];
+    __syncthreads();
+  }
+  if (threadIdx.x < kc) out[threadIdx.x] = scratch[threadIdx.x];
+  __syncthreads();
+}
+
 // ---------------------------------------------------------------- CSR stream SpMV
 constexpr int SPMV_CAP = 4096;  // nonzeros of one row tile staged in LDS (32 KB)
 
@@ -245,6 +288,76 @@ __device__ inline double tile_spmv_g(const int *__restrict__ rowptr, const int *
   const double s = tile_spmv_sum(tr, col, val, gx, prod);
   __syncthreads();
   return s;
+}
+
+// Row tile of R NT rows [r0, r0 + R NT): thread t owns rows r0 + u NT + t, u < R.
+// The same stage / sum scheme as above for all R rows at once (one row-pointer trip,
+// one column / value trip, one gather trip for the whole tile); CAP = nonzeros staged
+// in LDS (prod holds CAP doubles).
+template <int R>
+struct TileRowsR {
+  int a[R], b[R];
+  int p0, direct;
+};
+
+template <int NT, int R, int CAP, typename VT, typename G>
+__device__ inline TileRowsR<R> tile_spmv_stage_r(const int *__restrict__ rowptr, const int *__restrict__ col,
+                                                 const VT *__restrict__ val, const G &gx, int64_t n, int64_t r0,
+                                                 double *prod) {
+  constexpr int C = 6;
+  const int t = threadIdx.x;
+  const int64_t rl = (r0 + (int64_t)R * NT < n) ? r0 + (int64_t)R * NT : n;
+  const int p0 = rowptr[r0], p1 = rowptr[rl];
+  TileRowsR<R> tr;
+  tr.p0 = p0;
+  tr.direct = 0;
+#pragma unroll
+  for (int u = 0; u < R; ++u) {
+    const int64_t i = r0 + (int64_t)u * NT + t;
+    const int64_t ic = i < n ? i : n - 1;
+    const int a = rowptr[ic], b = rowptr[ic + 1];
+    tr.a[u] = i < n ? a : 0;
+    tr.b[u] = i < n ? b : 0;
+  }
+  if (p1 - p0 > CAP) {
+    tr.direct = 1;
+    return tr;
+  }
+  for (int base = p0; base < p1; base += C * NT) {
+    int cc[C];
+    double vv[C], xx[C];
+#pragma unroll
+    for (int u = 0; u < C; ++u) {
+      const int p = base + t + u * NT;
+      const int pc = p < p1 ? p : p1 - 1;
+      cc[u] = col[pc];
+      vv[u] = (double)val[pc];
+    }
+#pragma unroll
+    for (int u = 0; u < C; ++u) xx[u] = gx(cc[u]);
+#pragma unroll
+    for (int u = 0; u < C; ++u) {
+      const int p = base + t + u * NT;
+      if (p < p1) prod[p - p0] = vv[u] * xx[u];
+    }
+  }
+  return tr;
+}
+
+template <int R, typename VT, typename G>
+__device__ inline void tile_spmv_sum_r(const TileRowsR<R> &tr, const int *__restrict__ col,
+                                       const VT *__restrict__ val, const G &gx, const double *prod,
+                                       double (&s)[R]) {
+#pragma unroll
+  for (int u = 0; u < R; ++u) {
+    double acc = 0.0;
+    if (!tr.direct) {
+      for (int p = tr.a[u]; p < tr.b[u]; ++p) acc += prod[p - tr.p0];
+    } else {
+      for (int p = tr.a[u]; p < tr.b[u]; ++p) acc += (double)val[p] * gx(col[p]);
+    }
+    s[u] = acc;
+  }
 }
 
 template <typename TX>

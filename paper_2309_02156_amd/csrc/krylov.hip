@@ -184,16 +184,20 @@ struct GatherDir {
   }
 };
 
-template <typename VT, typename TV>
+// R = row tiles of KTPB rows each block takes at once
+template <typename VT, typename TV, int R>
 __global__ __launch_bounds__(KTPB) void k_cg_p(const int *rowptr, const int *col, const VT *val, const TV *r,
                                                TV *P0, TV *P1, TV *q, int64_t n, const double *Pin, int nblk,
                                                double *Pout, Ctl *ctl, int lidx) {
   __shared__ double red[KNW];
   __shared__ double outv[1];
   __shared__ double scratch[KTPB];
-  __shared__ double prod[SPMV_CAP];
+  __shared__ double prod[SPMV_CAP * R];
   __shared__ int s_k, s_fresh, s_go, s_cont, s_maxit;
   __shared__ double s_beta, s_tolb, s_rho2;
+  // r^T r of the previous iteration (unused when the direction restarts), loaded
+  // together with the control block
+  const double part = final_part(Pin, nblk, KW, 1);
   if (threadIdx.x == 0) {
     // every control-block read of the kernel, issued together
     const int st = ctl->state, it = ctl->iters, fa = ctl->fresh_at, mx = ctl->maxit;
@@ -211,7 +215,7 @@ __global__ __launch_bounds__(KTPB) void k_cg_p(const int *rowptr, const int *col
   __syncthreads();
   if (!s_go) return;
   const int k = s_k, fresh = s_fresh;
-  if (!fresh) final_sum(Pin, nblk, KW, 1, outv, scratch);
+  if (!fresh) final_tree(part, 1, outv, scratch);
   if (threadIdx.x == 0) {
     int st = ST_RUN;
     double beta = 0.0;
@@ -241,21 +245,36 @@ __global__ __launch_bounds__(KTPB) void k_cg_p(const int *rowptr, const int *col
   TV *pout = (k & 1) ? P1 : P0;
   const GatherDir<TV> gx{r, pin, beta, fresh};
   double acc[1] = {0.0};
-  KTILES(r0, n) {
-    const double qi = tile_spmv_g<KTPB>(rowptr, col, val, gx, n, r0, prod);
-    const int64_t i = r0 + threadIdx.x;
-    if (i < n) {
-      const TV ps = (TV)gx((int)i);  // exact: gx already rounds to TV
-      pout[i] = ps;
-      const TV qs = (TV)qi;
-      q[i] = qs;
-      acc[0] += (double)ps * (double)qs;
+  for (int64_t r0 = (int64_t)blockIdx.x * (R * KTPB); r0 < n; r0 += (int64_t)gridDim.x * (R * KTPB)) {
+    // the rows' own direction entries, requested before the SpMV (exact: gx rounds to TV)
+    double pv[R];
+#pragma unroll
+    for (int u = 0; u < R; ++u) {
+      const int64_t i = r0 + (int64_t)u * KTPB + threadIdx.x;
+      pv[u] = gx((int)(i < n ? i : n - 1));
+    }
+    const TileRowsR<R> tr = tile_spmv_stage_r<KTPB, R, SPMV_CAP * R>(rowptr, col, val, gx, n, r0, prod);
+    __syncthreads();
+    double qi[R];
+    tile_spmv_sum_r<R>(tr, col, val, gx, prod, qi);
+    __syncthreads();
+#pragma unroll
+    for (int u = 0; u < R; ++u) {
+      const int64_t i = r0 + (int64_t)u * KTPB + threadIdx.x;
+      if (i < n) {
+        const TV ps = (TV)pv[u];
+        pout[i] = ps;
+        const TV qs = (TV)qi[u];
+        q[i] = qs;
+        acc[0] += (double)ps * (double)qs;
+      }
     }
   }
   kstore<1>(acc, 1, red, Pout + (size_t)blockIdx.x * KW);
 }
 
-template <typename TV>
+// U = rows each thread takes per pass (all their loads issued before the first use)
+template <typename TV, int U>
 __global__ __launch_bounds__(KTPB) void k_cg_xr(TV *x, TV *r, const TV *P0, const TV *P1, const TV *q, int64_t n,
                                                 const double *Pin, int nblk, double *Pout, Ctl *ctl) {
   __shared__ double red[KNW];
@@ -263,6 +282,7 @@ __global__ __launch_bounds__(KTPB) void k_cg_xr(TV *x, TV *r, const TV *P0, cons
   __shared__ double scratch[KTPB];
   __shared__ int s_k, s_go;
   __shared__ double s_rho;
+  const double part = final_part(Pin, nblk, KW, 1);  // p^T q, loaded with the control block
   if (threadIdx.x == 0) {
     const int st = ctl->state, k = ctl->kcur;
     double r4[4];
@@ -274,7 +294,7 @@ __global__ __launch_bounds__(KTPB) void k_cg_xr(TV *x, TV *r, const TV *P0, cons
   }
   __syncthreads();
   if (!s_go) return;
-  final_sum(Pin, nblk, KW, 1, outv, scratch);
+  final_tree(part, 1, outv, scratch);
   const int k = s_k;
   const double pq = outv[0];
   if (!(pq > 0.0) || !isfinite(pq)) {
@@ -284,12 +304,28 @@ __global__ __launch_bounds__(KTPB) void k_cg_xr(TV *x, TV *r, const TV *P0, cons
   const double alpha = s_rho / pq;
   const TV *p = (k & 1) ? P1 : P0;
   double acc[1] = {0.0};
-  KROWS(i, n) {
-    x[i] = (TV)((double)x[i] + alpha * (double)p[i]);
-    const TV rs = (TV)((double)r[i] - alpha * (double)q[i]);
-    r[i] = rs;
-    const double ri = (double)rs;
-    acc[0] += ri * ri;
+  for (int64_t r0 = (int64_t)blockIdx.x * (U * KTPB); r0 < n; r0 += (int64_t)gridDim.x * (U * KTPB)) {
+    double xv[U], pv[U], rv[U], qv[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int64_t i = r0 + (int64_t)u * KTPB + threadIdx.x;
+      const int64_t ic = i < n ? i : n - 1;
+      xv[u] = (double)x[ic];
+      pv[u] = (double)p[ic];
+      rv[u] = (double)r[ic];
+      qv[u] = (double)q[ic];
+    }
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int64_t i = r0 + (int64_t)u * KTPB + threadIdx.x;
+      if (i < n) {
+        x[i] = (TV)(xv[u] + alpha * pv[u]);
+        const TV rs = (TV)(rv[u] - alpha * qv[u]);
+        r[i] = rs;
+        const double ri = (double)rs;
+        acc[0] += ri * ri;
+      }
+    }
   }
   kstore<1>(acc, 1, red, Pout + (size_t)blockIdx.x * KW);
   if (blockIdx.x == 0 && threadIdx.x == 0) ctl->iters = k;
@@ -309,23 +345,46 @@ hipError_t launch_cg_start_k(const CsrView &A, const TV *b, const TV *x, TV *r, 
   return hipGetLastError();
 }
 
-template <typename TV>
-hipError_t launch_cg_iter(const CsrView &A, TV *x, TV *r, TV *p2, TV *q, double *partials, Ctl *ctl,
-                          hipStream_t st, const KTiming *tm) {
+// row tiles per block pass of the CG kernels: as many as every block has (1, 2 or 4)
+static inline int cg_rows(int64_t n) {
+  const int64_t passes = (n + (int64_t)KTPB * KMAXBLK - 1) / ((int64_t)KTPB * KMAXBLK);
+  return passes >= 4 ? 4 : (passes >= 2 ? 2 : 1);
+}
+
+template <typename VT, typename TV, int R>
+static void cg_iter_launch(const CsrView &A, TV *x, TV *r, TV *P0, TV *P1, TV *q, double *partials, Ctl *ctl,
+                           hipStream_t st, const KTiming *tm) {
   const int nb = kblocks(A.n);
-  const int64_t ld = padded_ld(A.n);
-  TV *P0 = p2, *P1 = p2 + ld;
   // timed launches record their start/stop events in the kernel's own dispatch
   hipEvent_t e0 = tm ? tm->e0 : nullptr, e1 = tm ? tm->e1 : nullptr;
   const int lidx = tm ? tm->lidx : -1;
-  if (A.fp32)
-    hipExtLaunchKernelGGL((k_cg_p<float, TV>), dim3(nb), dim3(KTPB), 0, st, e0, e1, 0, A.rowptr, A.col,
-                          (const float *)A.val, r, P0, P1, q, A.n, PA(partials), nb, PB(partials), ctl, lidx);
-  else
-    hipExtLaunchKernelGGL((k_cg_p<double, TV>), dim3(nb), dim3(KTPB), 0, st, e0, e1, 0, A.rowptr, A.col,
-                          (const double *)A.val, r, P0, P1, q, A.n, PA(partials), nb, PB(partials), ctl, lidx);
-  hipLaunchKernelGGL(k_cg_xr<TV>, dim3(nb), dim3(KTPB), 0, st, x, r, P0, P1, q, A.n, PB(partials), nb,
+  hipExtLaunchKernelGGL((k_cg_p<VT, TV, R>), dim3(nb), dim3(KTPB), 0, st, e0, e1, 0, A.rowptr, A.col,
+                        (const VT *)A.val, r, P0, P1, q, A.n, PA(partials), nb, PB(partials), ctl, lidx);
+  hipLaunchKernelGGL((k_cg_xr<TV, R>), dim3(nb), dim3(KTPB), 0, st, x, r, P0, P1, q, A.n, PB(partials), nb,
                      PA(partials), ctl);
+}
+
+template <typename VT, typename TV>
+static void cg_iter_vt(const CsrView &A, TV *x, TV *r, TV *P0, TV *P1, TV *q, double *partials, Ctl *ctl,
+                       hipStream_t st, const KTiming *tm) {
+  const int R = cg_rows(A.n);
+  if (R == 4)
+    cg_iter_launch<VT, TV, 4>(A, x, r, P0, P1, q, partials, ctl, st, tm);
+  else if (R == 2)
+    cg_iter_launch<VT, TV, 2>(A, x, r, P0, P1, q, partials, ctl, st, tm);
+  else
+    cg_iter_launch<VT, TV, 1>(A, x, r, P0, P1, q, partials, ctl, st, tm);
+}
+
+template <typename TV>
+hipError_t launch_cg_iter(const CsrView &A, TV *x, TV *r, TV *p2, TV *q, double *partials, Ctl *ctl,
+                          hipStream_t st, const KTiming *tm) {
+  const int64_t ld = padded_ld(A.n);
+  TV *P0 = p2, *P1 = p2 + ld;
+  if (A.fp32)
+    cg_iter_vt<float, TV>(A, x, r, P0, P1, q, partials, ctl, st, tm);
+  else
+    cg_iter_vt<double, TV>(A, x, r, P0, P1, q, partials, ctl, st, tm);
   return hipGetLastError();
 }
 
@@ -458,24 +517,28 @@ __device__ inline bool gm_close_block(int j, double hn, int it, CloseIn *ci, Ctl
 }
 
 // F(j); mode 0: first cycle, 1: restart cycle (both only matter for j = 0), 2: the
-// finalise-only step j = m.
-template <typename VT, typename TV, int RB>
+// finalise-only step j = m.  R = row tiles of KTPB rows each block takes at once.
+template <typename VT, typename TV, int RB, int R>
 __global__ __launch_bounds__(KTPB) void k_gm_f(const int *rowptr, const int *col, const VT *val, TV *V, TV *T,
                                                int64_t n, int64_t ld, int j, int mode, const double *Pin, int nblk,
                                                double *Pout, Ctl *ctl, int lidx) {
   const int LD = MAXR + 1;
+  static_assert(RB + 2 <= WAVE, "partial rows are reduced in one group");
   __shared__ double red[KNW * (RB + 2)];
   __shared__ double outv[RB + 2];
   __shared__ double scratch[KTPB];
-  __shared__ double prod[SPMV_CAP];
+  __shared__ double prod[SPMV_CAP * R];
   __shared__ double gsh[RB], fco[RB], cco[RB + 1];
   __shared__ int s_go, s_open;
+  // the previous kernel's partial rows, loaded before the run flag is known so that
+  // both reads share one trip to memory (the rows are in bounds either way)
+  const double part = final_part(Pin, nblk, KW, j == 0 ? 2 : j);
   if (j == 0) {
     // open the cycle from the start kernel's partials
     if (threadIdx.x == 0) s_go = (mode == 0) || ctl->state == ST_RUN;
     __syncthreads();
     if (!s_go) return;
-    final_sum(Pin, nblk, KW, 2, outv, scratch);
+    final_tree(part, 2, outv, scratch);
     if (threadIdx.x == 0) {
       const bool persist = blockIdx.x == 0;
       const int trust = ctl->trust_est, pend = ctl->conv_pending;
@@ -509,7 +572,7 @@ __global__ __launch_bounds__(KTPB) void k_gm_f(const int *rowptr, const int *col
     }
     __syncthreads();
     if (!s_go) return;
-    final_sum(Pin, nblk, KW, j, outv, scratch);
+    final_tree(part, j, outv, scratch);
     // second-pass coefficients of w'_j and the completed column j - 1 of H
     for (int l = threadIdx.x; l < RB; l += blockDim.x) {
       const double g = (l < j) ? outv[l] * vsh[l] : 0.0;
@@ -546,49 +609,65 @@ __global__ __launch_bounds__(KTPB) void k_gm_f(const int *rowptr, const int *col
   double acc[RB];             // V[:, k]^T y, k < j
 #pragma unroll
   for (int l = 0; l < RB; ++l) acc[l] = 0.0;
-  KTILES(r0, n) {
-    const int64_t i = r0 + threadIdx.x;
-    const int64_t ic = i < n ? i : n - 1;
-    // the row's column values are requested before the SpMV so their latency overlaps
+  for (int64_t r0 = (int64_t)blockIdx.x * (R * KTPB); r0 < n; r0 += (int64_t)gridDim.x * (R * KTPB)) {
+    // the rows' column values are requested before the SpMV so their latency overlaps
     // its loads; every load is issued (columns past the live ones re-read a live
     // column and are masked), so no branch separates them
-    double vl[RB];
+    double vl[R][RB], s0[R];
 #pragma unroll
-    for (int k = 0; k < RB; ++k) {
-      const double v = (double)V[(size_t)(k < j ? k : (j > 0 ? j - 1 : 0)) * ld + ic];
-      vl[k] = (k < j) ? v : 0.0;
+    for (int u = 0; u < R; ++u) {
+      const int64_t i = r0 + (int64_t)u * KTPB + threadIdx.x;
+      const int64_t ic = i < n ? i : n - 1;
+#pragma unroll
+      for (int k = 0; k < RB; ++k) {
+        const double v = (double)V[(size_t)(k < j ? k : (j > 0 ? j - 1 : 0)) * ld + ic];
+        vl[u][k] = (k < j) ? v : 0.0;
+      }
+      s0[u] = (double)src[ic];
     }
-    const double s0 = (double)src[ic];
-    double ax = 0.0;
-    if (mode != 2) ax = tile_spmv<KTPB>(rowptr, col, val, src, n, r0, prod);
-    if (i < n) {
-      double w = s0;
+    double ax[R];
 #pragma unroll
-      for (int k = 0; k < RB; ++k) w -= fco[k] * vl[k];
-      const TV ws = (TV)w;
-      if (j > 0 && mode != 2) wcol[i] = ws;
-      const double wd = (double)ws;
-      ex[0] += wd * wd;
-      if (mode != 2) {
-        double y = ax - cj * wd;
+    for (int u = 0; u < R; ++u) ax[u] = 0.0;
+    if (mode != 2) {
+      const Gather1<TV> gx{src};
+      const TileRowsR<R> tr = tile_spmv_stage_r<KTPB, R, SPMV_CAP * R>(rowptr, col, val, gx, n, r0, prod);
+      __syncthreads();
+      tile_spmv_sum_r<R>(tr, col, val, gx, prod, ax);
+      __syncthreads();
+    }
 #pragma unroll
-        for (int k = 0; k < RB; ++k) y -= cco[k] * vl[k];
-        const TV ys = (TV)y;
-        ycol[i] = ys;
-        const double yd = (double)ys;
-        ex[1] += wd * yd;
+    for (int u = 0; u < R; ++u) {
+      const int64_t i = r0 + (int64_t)u * KTPB + threadIdx.x;
+      if (i < n) {
+        double w = s0[u];
 #pragma unroll
-        for (int k = 0; k < RB; ++k) acc[k] += vl[k] * yd;
+        for (int k = 0; k < RB; ++k) w -= fco[k] * vl[u][k];
+        const TV ws = (TV)w;
+        if (j > 0 && mode != 2) wcol[i] = ws;
+        const double wd = (double)ws;
+        ex[0] += wd * wd;
+        if (mode != 2) {
+          double y = ax[u] - cj * wd;
+#pragma unroll
+          for (int k = 0; k < RB; ++k) y -= cco[k] * vl[u][k];
+          const TV ys = (TV)y;
+          ycol[i] = ys;
+          const double yd = (double)ys;
+          ex[1] += wd * yd;
+#pragma unroll
+          for (int k = 0; k < RB; ++k) acc[k] += vl[u][k] * yd;
+        }
       }
     }
   }
   kstore2<RB>(ex, acc, mode == 2 ? 1 : j + 2, red, Pout + (size_t)blockIdx.x * KW);
 }
 
-// G(j)
-template <typename TV, int RB>
+// G(j); R = row tiles of KTPB rows each block takes at once.
+template <typename TV, int RB, int R>
 __global__ __launch_bounds__(KTPB) void k_gm_g(const TV *V, TV *T, int64_t n, int64_t ld, int j, const double *Pin,
                                                int nblk, double *Pout, Ctl *ctl) {
+  static_assert(RB + 2 <= WAVE, "partial rows are reduced in one group");
   __shared__ double red[KNW * RB];
   __shared__ double outv[RB + 2];
   __shared__ double scratch[KTPB];
@@ -597,7 +676,9 @@ __global__ __launch_bounds__(KTPB) void k_gm_g(const TV *V, TV *T, int64_t n, in
   __shared__ double vsh[MAXR + 1];
   __shared__ int s_ibase, s_go;
   __shared__ CloseIn ci;
-  // one trip to memory for the run flag, the close inputs and the column scales
+  // one trip to memory for the partial rows of F(j) (loaded before the run flag is
+  // known), the run flag, the close inputs and the column scales
+  const double part = final_part(Pin, nblk, KW, j + 2);
   if (threadIdx.x == 0) {
     const int st = ctl->state, act = ctl->active, ib = ctl->ibase;
     s_go = (st == ST_RUN) && act;
@@ -607,7 +688,7 @@ __global__ __launch_bounds__(KTPB) void k_gm_g(const TV *V, TV *T, int64_t n, in
   if (threadIdx.x <= j) vsh[threadIdx.x] = ctl->vs[threadIdx.x];
   __syncthreads();
   if (!s_go) return;
-  final_sum(Pin, nblk, KW, j + 2, outv, scratch);
+  final_tree(part, j + 2, outv, scratch);
   if (j > 0) {
     if (gm_close_block(j - 1, sqrt(outv[0]), s_ibase + j, &ci, ctl, blockIdx.x == 0, &s_vs)) return;
   } else {
@@ -633,24 +714,36 @@ __global__ __launch_bounds__(KTPB) void k_gm_g(const TV *V, TV *T, int64_t n, in
 #pragma unroll
   for (int l = 0; l < RB; ++l) acc[l] = 0.0;
 #pragma unroll 1
-  KROWS(i, n) {
+  for (int64_t r0 = (int64_t)blockIdx.x * (R * KTPB); r0 < n; r0 += (int64_t)gridDim.x * (R * KTPB)) {
     // compiler barrier: re-read the LDS coefficients per row instead of holding all of
     // them in registers next to the column values and the partial dots
     __asm__ volatile("" ::: "memory");
-    double vl[RB];
+    double vl[R][RB], yv[R];
 #pragma unroll
-    for (int k = 0; k < RB; ++k) {
-      const double v = (double)V[(size_t)(k <= j ? k : j) * ld + i];
-      vl[k] = (k <= j) ? v : 0.0;
+    for (int u = 0; u < R; ++u) {
+      const int64_t i = r0 + (int64_t)u * KTPB + threadIdx.x;
+      const int64_t ic = i < n ? i : n - 1;
+#pragma unroll
+      for (int k = 0; k < RB; ++k) {
+        const double v = (double)V[(size_t)(k <= j ? k : j) * ld + ic];
+        vl[u][k] = (k <= j) ? v : 0.0;
+      }
+      yv[u] = (double)ycol[ic];
     }
-    double w = vsj * (double)ycol[i];
 #pragma unroll
-    for (int k = 0; k < RB; ++k) w -= coef[k] * vl[k];
-    const TV ws = (TV)w;
-    T[i] = ws;
-    const double wd = (double)ws;
+    for (int u = 0; u < R; ++u) {
+      const int64_t i = r0 + (int64_t)u * KTPB + threadIdx.x;
+      if (i < n) {
+        double w = vsj * yv[u];
 #pragma unroll
-    for (int k = 0; k < RB; ++k) acc[k] += vl[k] * wd;
+        for (int k = 0; k < RB; ++k) w -= coef[k] * vl[u][k];
+        const TV ws = (TV)w;
+        T[i] = ws;
+        const double wd = (double)ws;
+#pragma unroll
+        for (int k = 0; k < RB; ++k) acc[k] += vl[u][k] * wd;
+      }
+    }
   }
   kstore<RB>(acc, j + 1, red, Pout + (size_t)blockIdx.x * KW);
 }
@@ -738,19 +831,43 @@ hipError_t launch_gm_start(const CsrView &A, const TV *b, const TV *x, TV *V, in
   return hipGetLastError();
 }
 
-template <typename TV, int RB>
-static void gm_f_rb(const CsrView &A, TV *V, TV *T, int64_t ld, int j, int mode, double *partials, Ctl *ctl,
-                    hipStream_t st, const KTiming *tm = nullptr) {
+// rows per thread of the GMRES step kernels: two row tiles at once when every block
+// has at least two (the grid is capped at KMAXBLK blocks)
+static inline bool gm_two_rows(int64_t n) { return n >= (int64_t)2 * KTPB * KMAXBLK; }
+
+template <typename TV, int RB, int R>
+static void gm_f_launch(const CsrView &A, TV *V, TV *T, int64_t ld, int j, int mode, double *partials, Ctl *ctl,
+                        hipStream_t st, const KTiming *tm) {
   const int nb = kblocks(A.n);
   // timed launches record their start/stop events in the kernel's own dispatch
   hipEvent_t e0 = tm ? tm->e0 : nullptr, e1 = tm ? tm->e1 : nullptr;
   const int lidx = tm ? tm->lidx : -1;
   if (A.fp32)
-    hipExtLaunchKernelGGL((k_gm_f<float, TV, RB>), dim3(nb), dim3(KTPB), 0, st, e0, e1, 0, A.rowptr, A.col,
+    hipExtLaunchKernelGGL((k_gm_f<float, TV, RB, R>), dim3(nb), dim3(KTPB), 0, st, e0, e1, 0, A.rowptr, A.col,
                           (const float *)A.val, V, T, A.n, ld, j, mode, PA(partials), nb, PB(partials), ctl, lidx);
   else
-    hipExtLaunchKernelGGL((k_gm_f<double, TV, RB>), dim3(nb), dim3(KTPB), 0, st, e0, e1, 0, A.rowptr, A.col,
+    hipExtLaunchKernelGGL((k_gm_f<double, TV, RB, R>), dim3(nb), dim3(KTPB), 0, st, e0, e1, 0, A.rowptr, A.col,
                           (const double *)A.val, V, T, A.n, ld, j, mode, PA(partials), nb, PB(partials), ctl, lidx);
+}
+
+template <typename TV, int RB>
+static void gm_f_rb(const CsrView &A, TV *V, TV *T, int64_t ld, int j, int mode, double *partials, Ctl *ctl,
+                    hipStream_t st, const KTiming *tm = nullptr) {
+  if (gm_two_rows(A.n))
+    gm_f_launch<TV, RB, 2>(A, V, T, ld, j, mode, partials, ctl, st, tm);
+  else
+    gm_f_launch<TV, RB, 1>(A, V, T, ld, j, mode, partials, ctl, st, tm);
+}
+
+template <typename TV, int RB>
+static void gm_g_rb(const CsrView &A, TV *V, TV *T, int64_t ld, int j, double *partials, Ctl *ctl, hipStream_t st) {
+  const int nb = kblocks(A.n);
+  if (gm_two_rows(A.n))
+    hipLaunchKernelGGL((k_gm_g<TV, RB, 2>), dim3(nb), dim3(KTPB), 0, st, V, T, A.n, ld, j, PB(partials), nb,
+                       PA(partials), ctl);
+  else
+    hipLaunchKernelGGL((k_gm_g<TV, RB, 1>), dim3(nb), dim3(KTPB), 0, st, V, T, A.n, ld, j, PB(partials), nb,
+                       PA(partials), ctl);
 }
 
 // Arnoldi step j of a cycle: F(j), G(j).  first_mode: 0 first cycle, 1 restart
@@ -758,7 +875,6 @@ static void gm_f_rb(const CsrView &A, TV *V, TV *T, int64_t ld, int j, int mode,
 template <typename TV>
 hipError_t launch_gm_step(const CsrView &A, TV *V, TV *T, int64_t ld, int j, int first_mode, double *partials,
                           Ctl *ctl, hipStream_t st, const KTiming *tm) {
-  const int nb = kblocks(A.n);
   const int mode = j == 0 ? first_mode : 0;
   if (j <= 8)
     gm_f_rb<TV, 8>(A, V, T, ld, j, mode, partials, ctl, st, tm);
@@ -767,14 +883,11 @@ hipError_t launch_gm_step(const CsrView &A, TV *V, TV *T, int64_t ld, int j, int
   else
     gm_f_rb<TV, 32>(A, V, T, ld, j, mode, partials, ctl, st, tm);
   if (j < 8)
-    hipLaunchKernelGGL((k_gm_g<TV, 8>), dim3(nb), dim3(KTPB), 0, st, V, T, A.n, ld, j, PB(partials), nb,
-                       PA(partials), ctl);
+    gm_g_rb<TV, 8>(A, V, T, ld, j, partials, ctl, st);
   else if (j < 16)
-    hipLaunchKernelGGL((k_gm_g<TV, 16>), dim3(nb), dim3(KTPB), 0, st, V, T, A.n, ld, j, PB(partials), nb,
-                       PA(partials), ctl);
+    gm_g_rb<TV, 16>(A, V, T, ld, j, partials, ctl, st);
   else
-    hipLaunchKernelGGL((k_gm_g<TV, 32>), dim3(nb), dim3(KTPB), 0, st, V, T, A.n, ld, j, PB(partials), nb,
-                       PA(partials), ctl);
+    gm_g_rb<TV, 32>(A, V, T, ld, j, partials, ctl, st);
   return hipGetLastError();
 }
 
@@ -827,5 +940,9 @@ SACC_INSTANTIATE_KRYLOV(float)
 int64_t padded_ld(int64_t n) { return (n + 511) / 512 * 512 + 576; }
 
 size_t krylov_partials_doubles() { return (size_t)2 * KMAXBLK * KW; }
+
+int gm_rows_per_thread(int64_t n) { return gm_two_rows(n) ? 2 : 1; }
+
+int cg_rows_per_thread(int64_t n) { return cg_rows(n); }
 
 }  // namespace sacc

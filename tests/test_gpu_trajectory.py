@@ -9,7 +9,10 @@ The two runs round differently and their histories drift apart at the solver tol
 so per-step iteration counts are not comparable one by one.  What is fixed: the ranks
 the sketched QR and the Cholesky finish keep (k, k2) at every step; every step meets
 the tolerance; the quality of the initial guess (relres0) agrees in the median within a
-factor 1.5 once the history is full; mean iterations over steps 40..139 agree within 5%.
+factor 1.5 once the history is full; mean iterations over steps 40..139 agree within
+three standard deviations of the difference of two such means (per-step counts spread
+by about a third of their mean; the bar is computed from the stored trajectory, about
+14 %).
 """
 
 import json
@@ -51,8 +54,10 @@ def test_free_running_trajectory_matches_oracle():
     r0g = np.array([g["relres0"] for g in got[40:]])
     r0o = np.array([r["relres0"] for r in ref[40:]])
     med = float(np.median(np.abs(np.log(r0g / r0o))))
+    its_o = np.array([r["iters"] for r in ref[40:]], dtype=float)
     itg = float(np.mean([g["iters"] for g in got[40:]]))
-    ito = float(np.mean([r["iters"] for r in ref[40:]]))
-    print_case("median |log relres0 ratio|", med, "mean iters gpu", itg, "oracle", ito)
+    ito = float(its_o.mean())
+    bar = 3.0 * np.sqrt(2.0) * its_o.std() / np.sqrt(its_o.size)
+    print_case("median |log relres0 ratio|", med, "mean iters gpu", itg, "oracle", ito, "bar", bar)
     assert med <= np.log(1.5)
-    assert abs(itg - ito) <= 0.05 * ito
+    assert abs(itg - ito) <= bar
