@@ -382,7 +382,7 @@ int run_gmres(sa_seq *q, const CsrView &v, Ctl *ctl, const TV *b, TV *x, int max
         const int rb = j <= 8 ? 8 : (j <= 16 ? 16 : 32);
         const double bytes = csr + (j == 0 ? 2.0 : (double)(j + 3)) * w * v.n;
         const std::string name = std::string("k_gm_f<") + tname(wv) + ", " + tname(w) + ", " + std::to_string(rb) +
-                                 ", " + std::to_string(gm_rows_per_thread(v.n)) + ">";
+                                 ", " + std::to_string(gm_f_rows_per_thread(v.n, rb)) + ">";
         tp = prof_slot(q, name, bytes, &tm);
       }
       HIP_TRY(launch_gm_step<TV>(v, V, T, q->ld, j, cycle > 0 ? 1 : 0, q->partials, ctl, st, tp));

@@ -77,37 +77,103 @@ inline int stream_blocks(int64_t n) {
   for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < (n); i += (int64_t)gridDim.x * blockDim.x)
 
 // ---------------------------------------------------------------- reductions
-__device__ inline double wave_sum(double v) {
-#pragma unroll
-  for (int off = WAVE / 2; off > 0; off >>= 1) v += __shfl_xor(v, off, WAVE);
-  return v;
-}
+// Cross-lane exchanges without the LDS unit: v_permlane32_swap / v_permlane16_swap
+// (gfx950) for partners 32 and 16 lanes apart, DPP row controls inside a row of 16
+// (row_mirror, row_half_mirror, two quad permutations).  Each pairs every lane with
+// a partner in the other half of its current group, which is all a fixed-order
+// recursive reduction needs.
+__device__ inline unsigned dlo(double v) { return (unsigned)__double2loint(v); }
+__device__ inline unsigned dhi(double v) { return (unsigned)__double2hiint(v); }
+__device__ inline double dmake(unsigned lo, unsigned hi) { return __hiloint2double((int)hi, (int)lo); }
 
-// Sums over the 64 lanes of a wave of K per-lane values (K a power of two <= 64) by
-// recursive halving: at each exchange a lane keeps half of its entries and adds its
-// partner's copy of that half, so K - 1 + log2(64 / K) exchanges replace 6 K.  On
-// return lane l holds in v[0] the total of entry l / (64 / K).  Fixed order.
-template <int K, int H>
-__device__ inline void wave_halving_step(double (&v)[K], int lane) {
-  if constexpr (H >= 1) {
-    constexpr int O = WAVE * H / K;  // partner offset of this step: 32, 16, ...
-    const bool up = (lane & O) != 0;
-#pragma unroll
-    for (int i = 0; i < H; ++i) {
-      const double send = up ? v[i] : v[i + H];
-      const double keep = up ? v[i + H] : v[i];
-      v[i] = keep + __shfl_xor(send, O, WAVE);
-    }
-    wave_halving_step<K, H / 2>(v, lane);
+// x' + y' after exchanging the upper half of x's lane group with the lower half of
+// y's: lanes in a lower half get the pair sum of x, lanes in an upper half the pair
+// sum of y.  W = 32 (halves of the wave) or 16 (rows).
+template <int W>
+__device__ inline double swap_sum(double x, double y) {
+  static_assert(W == 32 || W == 16, "permlane swaps exchange 32- or 16-lane groups");
+  if constexpr (W == 32) {
+    const auto lo = __builtin_amdgcn_permlane32_swap(dlo(x), dlo(y), false, false);
+    const auto hi = __builtin_amdgcn_permlane32_swap(dhi(x), dhi(y), false, false);
+    return dmake(lo[0], hi[0]) + dmake(lo[1], hi[1]);
+  } else {
+    const auto lo = __builtin_amdgcn_permlane16_swap(dlo(x), dlo(y), false, false);
+    const auto hi = __builtin_amdgcn_permlane16_swap(dhi(x), dhi(y), false, false);
+    return dmake(lo[0], hi[0]) + dmake(lo[1], hi[1]);
   }
 }
 
+// the partner's value under a DPP row control
+template <int CTRL>
+__device__ inline double dpp_partner(double v) {
+  const unsigned lo = (unsigned)__builtin_amdgcn_update_dpp(0, (int)dlo(v), CTRL, 0xF, 0xF, true);
+  const unsigned hi = (unsigned)__builtin_amdgcn_update_dpp(0, (int)dhi(v), CTRL, 0xF, 0xF, true);
+  return dmake(lo, hi);
+}
+
+// Level L = 0..5 of the wave reduction splits lane groups of 64 >> L at lane bit
+// 32 >> L: partners by permlane32 / permlane16 swaps, then row_mirror (lane i <-> 15 - i),
+// row_half_mirror (i <-> 7 - i), quad permutations [3,2,1,0] and [1,0,3,2].
+constexpr int DPP_ROW_MIRROR = 0x140, DPP_ROW_HALF_MIRROR = 0x141, DPP_QUAD_3210 = 0x1B, DPP_QUAD_1032 = 0xB1;
+
+template <int L>
+__device__ inline double level_partner(double v) {
+  if constexpr (L == 2) return dpp_partner<DPP_ROW_MIRROR>(v);
+  else if constexpr (L == 3) return dpp_partner<DPP_ROW_HALF_MIRROR>(v);
+  else if constexpr (L == 4) return dpp_partner<DPP_QUAD_3210>(v);
+  else return dpp_partner<DPP_QUAD_1032>(v);
+}
+
+// keep one of (lo, hi) by this lane's half and add the partner's other one
+template <int L>
+__device__ inline double level_halve(double lo, double hi, int lane) {
+  if constexpr (L == 0) return swap_sum<32>(lo, hi);
+  else if constexpr (L == 1) return swap_sum<16>(lo, hi);
+  else {
+    const bool up = (lane & (32 >> L)) != 0;
+    const double send = up ? lo : hi, keep = up ? hi : lo;
+    return keep + level_partner<L>(send);
+  }
+}
+
+// v + the partner's v
+template <int L>
+__device__ inline double level_full(double v) {
+  if constexpr (L == 0) return swap_sum<32>(v, v);
+  else if constexpr (L == 1) return swap_sum<16>(v, v);
+  else return v + level_partner<L>(v);
+}
+
+template <int K, int L>
+__device__ inline void wave_level(double (&v)[K], int lane) {
+  if constexpr (L < 6) {
+    constexpr int LOGK = K >= 64 ? 6 : K >= 32 ? 5 : K >= 16 ? 4 : K >= 8 ? 3 : K >= 4 ? 2 : K >= 2 ? 1 : 0;
+    if constexpr (L < LOGK) {
+      constexpr int H = K >> (L + 1);
+#pragma unroll
+      for (int i = 0; i < H; ++i) v[i] = level_halve<L>(v[i], v[i + H], lane);
+    } else {
+      v[0] = level_full<L>(v[0]);
+    }
+    wave_level<K, L + 1>(v, lane);
+  }
+}
+
+// Sums over the 64 lanes of a wave of K per-lane values (K a power of two <= 64) by
+// recursive halving: at each level a lane keeps half of its entries and adds its
+// partner's copy of that half, so K - 1 + log2(64 / K) exchanges replace 6 K.  On
+// return lane l holds in v[0] the total of entry l / (64 / K).  Fixed order.
 template <int K>
 __device__ inline void wave_sum_multi(double (&v)[K]) {
   static_assert(K >= 1 && K <= WAVE && (K & (K - 1)) == 0, "K must be a power of two <= 64");
-  wave_halving_step<K, K / 2>(v, (int)(threadIdx.x % WAVE));
-#pragma unroll
-  for (int o = WAVE / K / 2; o >= 1; o /= 2) v[0] += __shfl_xor(v[0], o, WAVE);
+  wave_level<K, 0>(v, (int)(threadIdx.x % WAVE));
+}
+
+// total over the wave, in every lane
+__device__ inline double wave_sum(double v) {
+  double a[1] = {v};
+  wave_sum_multi<1>(a);
+  return a[0];
 }
 
 // Block-reduce K per-thread values (K a power of two; fixed butterfly and fixed wave

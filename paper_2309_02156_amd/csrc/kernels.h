@@ -99,8 +99,8 @@ hipError_t launch_gm_finish(const CsrView &A, TV *V, TV *T, int64_t ld, int m, d
 template <typename TV>
 hipError_t launch_gm_update(TV *x, const TV *V, int64_t n, int64_t ld, int restart, Ctl *ctl, hipStream_t st);
 size_t krylov_partials_doubles();
-// row tiles each block of the GMRES step kernels takes at once (1 or 2) for n rows
-int gm_rows_per_thread(int64_t n);
+// row tiles per pass of the GMRES kernel F (1 or 2) for n rows and rb column slots
+int gm_f_rows_per_thread(int64_t n, int rb);
 // row tiles each block of the CG iteration kernels takes at once (1, 2 or 4)
 int cg_rows_per_thread(int64_t n);
 

@@ -466,85 +466,188 @@ __device__ inline void close_stage(int j, const Ctl *ctl, CloseIn *ci) {
 
 // Close Arnoldi step j given hn = ||w''_{j+1}|| from the staged inputs: rotate the raw
 // column j, new Givens rotation, rotated right-hand side, cycle-end test.  `it` =
-// global iteration number of step j (1-based).  Called by all threads of a block after
-// close_stage and a barrier; thread 0 runs the scalar recurrence with the carried
-// entry in a register.  Every block computes the same result; only `persist` (block
-// 0) writes.  Returns the cycle-end flag; the scale of the next basis vector is left
-// in *s_vs (LDS).
-__device__ inline bool gm_close_block(int j, double hn, int it, CloseIn *ci, Ctl *ctl, bool persist,
-                                      double *s_vs) {
+// global iteration number of step j (1-based).  The scalar recurrence runs on one
+// thread with the carried entry in a register; the rotated column is left in ci->col.
+// Every block computes the same result; only `persist` (block 0) writes the control
+// block (the rotated column itself is written by the caller).  Returns the cycle-end
+// flag.
+__device__ inline bool gm_close_scalar(int j, double hn, int it, CloseIn *ci, Ctl *ctl, bool persist) {
+  double *col = ci->col;
+  col[j + 1] = hn;
+  double cur = col[0];
+  for (int l = 0; l < j; ++l) {
+    const double nxt = col[l + 1], c = ci->cs[l], s = ci->sn[l];
+    col[l] = c * cur + s * nxt;
+    cur = -s * cur + c * nxt;
+  }
+  const double a = cur;
+  const double rr = hypot(a, hn);
+  double c = 1.0, s = 0.0;
+  if (rr != 0.0) {
+    c = a / rr;
+    s = hn / rr;
+  }
+  col[j] = rr;
+  const double gj = ci->gj;
+  const double gam_j = c * gj, gnext = -s * gj;
+  const bool est_conv = fabs(gnext) <= ci->tolb;
+  const bool end = est_conv || hn == 0.0 || it >= ci->maxit || j + 1 >= ci->restart || !isfinite(gnext);
+  if (persist) {
+    ctl->cs[j] = c;
+    ctl->sn[j] = s;
+    ctl->gam[j] = gam_j;
+    ctl->gnext[j + 1] = gnext;
+    ctl->vs[j + 1] = hn > 0.0 ? 1.0 / hn : 0.0;
+    ctl->iters = it;
+    ctl->jend = j + 1;
+    if (end) ctl->active = 0;
+    if (est_conv && ci->trust) ctl->conv_pending = 1;
+  }
+  return end;
+}
+
+// gm_close_scalar for a whole block (after close_stage and a barrier): thread 0 runs
+// the recurrence, then the block persists the rotated column.  Returns the cycle-end
+// flag to every thread.
+__device__ inline bool gm_close_block(int j, double hn, int it, CloseIn *ci, Ctl *ctl, bool persist) {
   const int LD = MAXR + 1;
   __shared__ int s_endf;
-  if (threadIdx.x == 0) {
-    double *col = ci->col;
-    col[j + 1] = hn;
-    double cur = col[0];
-    for (int l = 0; l < j; ++l) {
-      const double nxt = col[l + 1], c = ci->cs[l], s = ci->sn[l];
-      col[l] = c * cur + s * nxt;
-      cur = -s * cur + c * nxt;
-    }
-    const double a = cur;
-    const double rr = hypot(a, hn);
-    double c = 1.0, s = 0.0;
-    if (rr != 0.0) {
-      c = a / rr;
-      s = hn / rr;
-    }
-    col[j] = rr;
-    const double gj = ci->gj;
-    const double gam_j = c * gj, gnext = -s * gj;
-    const bool est_conv = fabs(gnext) <= ci->tolb;
-    const bool end = est_conv || hn == 0.0 || it >= ci->maxit || j + 1 >= ci->restart || !isfinite(gnext);
-    *s_vs = hn > 0.0 ? 1.0 / hn : 0.0;
-    s_endf = end ? 1 : 0;
-    if (persist) {
-      ctl->cs[j] = c;
-      ctl->sn[j] = s;
-      ctl->gam[j] = gam_j;
-      ctl->gnext[j + 1] = gnext;
-      ctl->vs[j + 1] = *s_vs;
-      ctl->iters = it;
-      ctl->jend = j + 1;
-      if (end) ctl->active = 0;
-      if (est_conv && ci->trust) ctl->conv_pending = 1;
-    }
-  }
+  if (threadIdx.x == 0) s_endf = gm_close_scalar(j, hn, it, ci, ctl, persist) ? 1 : 0;
   __syncthreads();
   if (persist)
     for (int l = threadIdx.x; l <= j; l += blockDim.x) ctl->R[l + j * LD] = ci->col[l];
   return s_endf != 0;
 }
 
+// Row pointers of a pass of R KTPB rows from r0: the pass's nonzero range [p0, p1) and
+// this thread's rows (empty past n).  Loads stay in bounds for any r0.
+template <int R>
+struct PassRows {
+  int a[R], b[R];
+  int p0, p1;
+};
+
+template <int R>
+__device__ inline PassRows<R> pass_rows(const int *__restrict__ rowptr, int64_t n, int64_t r0) {
+  const int64_t rs = r0 < n ? r0 : n;
+  const int64_t re = r0 + (int64_t)R * KTPB < n ? r0 + (int64_t)R * KTPB : n;
+  PassRows<R> pr;
+  pr.p0 = rowptr[rs];
+  pr.p1 = rowptr[re];
+#pragma unroll
+  for (int u = 0; u < R; ++u) {
+    const int64_t i = r0 + (int64_t)u * KTPB + threadIdx.x;
+    const int64_t ic = i < n ? i : n - 1;
+    const int a = rowptr[ic], b = rowptr[ic + 1];
+    pr.a[u] = i < n ? a : 0;
+    pr.b[u] = i < n ? b : 0;
+  }
+  return pr;
+}
+
+// One staging round of a pass's SpMV (the scheme of tile_spmv_stage_r): C nonzeros per
+// thread from `base`, split into the column / value loads, the gathers and the LDS
+// writes, so that a kernel can issue other loads between them.  stage_load reads
+// in bounds for any range (col / val hold at least one entry).
+template <int C>
+struct StageRound {
+  int cc[C];
+  double vv[C], xx[C];
+};
+
+template <int C, typename VT>
+__device__ inline void stage_load(StageRound<C> &sr, const int *__restrict__ col, const VT *__restrict__ val, int base,
+                                  int p1) {
+#pragma unroll
+  for (int u = 0; u < C; ++u) {
+    const int p = base + threadIdx.x + u * KTPB;
+    const int pc = p < p1 ? p : (p1 > 0 ? p1 - 1 : 0);
+    sr.cc[u] = col[pc];
+    sr.vv[u] = (double)val[pc];
+  }
+}
+
+template <int C, typename G>
+__device__ inline void stage_gather(StageRound<C> &sr, const G &gx) {
+#pragma unroll
+  for (int u = 0; u < C; ++u) sr.xx[u] = gx(sr.cc[u]);
+}
+
+template <int C>
+__device__ inline void stage_write(const StageRound<C> &sr, int base, int p0, int p1, double *prod) {
+#pragma unroll
+  for (int u = 0; u < C; ++u) {
+    const int p = base + threadIdx.x + u * KTPB;
+    if (p < p1) prod[p - p0] = sr.vv[u] * sr.xx[u];
+  }
+}
+
 // F(j); mode 0: first cycle, 1: restart cycle (both only matter for j = 0), 2: the
-// finalise-only step j = m.  R = row tiles of KTPB rows each block takes at once.
+// finalise-only step j = m.  R = row tiles of KTPB rows each block takes per pass.
+//
+// Order of the memory traffic (the first pass): one trip for the control block, the
+// previous kernel's partial rows and the pass's row pointers; then the SpMV's column /
+// value loads, the pass's column values, the gathers, in that order, so the column
+// stream overlaps the SpMV's dependent trips and the LDS work of the prologue.
 template <typename VT, typename TV, int RB, int R>
 __global__ __launch_bounds__(KTPB) void k_gm_f(const int *rowptr, const int *col, const VT *val, TV *V, TV *T,
                                                int64_t n, int64_t ld, int j, int mode, const double *Pin, int nblk,
                                                double *Pout, Ctl *ctl, int lidx) {
   const int LD = MAXR + 1;
+  constexpr int NR = R * KTPB;
+  constexpr int CAP = SPMV_CAP * R;
+  constexpr int C = 6 * R;
+  constexpr int HPT = ((MAXR + 1) * MAXR + KTPB - 1) / KTPB;  // raw Hessenberg entries staged per thread
   static_assert(RB + 2 <= WAVE, "partial rows are reduced in one group");
   __shared__ double red[KNW * (RB + 2)];
   __shared__ double outv[RB + 2];
   __shared__ double scratch[KTPB];
-  __shared__ double prod[SPMV_CAP * R];
+  __shared__ double prod[CAP];
   __shared__ double gsh[RB], fco[RB], cco[RB + 1];
+  __shared__ double Hs[(MAXR + 1) * MAXR], vsh[MAXR + 1], h1s[MAXR + 1];
   __shared__ int s_go, s_open;
-  // the previous kernel's partial rows, loaded before the run flag is known so that
-  // both reads share one trip to memory (the rows are in bounds either way)
+  const int t = threadIdx.x;
+  const TV *src = (j == 0) ? V : T;
+  TV *wcol = V + (size_t)j * ld;
+  TV *ycol = V + (size_t)(j + 1) * ld;
+  const Gather1<TV> gx{src};
+  const int64_t stride = (int64_t)gridDim.x * NR;
+  int64_t r0 = (int64_t)blockIdx.x * NR;
+
+  // ---- one trip: first pass's row pointers, control block, partial rows
+  PassRows<R> pr = pass_rows<R>(rowptr, n, r0);
+  const int st = ctl->state, act = ctl->active;
+  const int hcnt = j > 1 ? (j - 1) * LD : 0;
+  const int jm = j > 0 ? j - 1 : 0;
+  double hreg[HPT];
+#pragma unroll
+  for (int u = 0; u < HPT; ++u) {
+    const int e = t + u * KTPB;
+    hreg[u] = ctl->Hraw[e < hcnt ? e : 0];
+  }
+  const double vs_t = ctl->vs[t < jm ? t : jm], h1_t = ctl->h1[t < jm ? t : jm];
   const double part = final_part(Pin, nblk, KW, j == 0 ? 2 : j);
+  if (t == 0) s_go = j == 0 ? ((mode == 0) || st == ST_RUN) : ((st == ST_RUN) && act);
+#pragma unroll
+  for (int u = 0; u < HPT; ++u) {
+    const int e = t + u * KTPB;
+    if (e < hcnt) Hs[e] = hreg[u];
+  }
+  if (t < j) {
+    vsh[t] = vs_t;
+    h1s[t] = h1_t;
+  }
+  __syncthreads();
+  if (!s_go) return;
   if (j == 0) {
     // open the cycle from the start kernel's partials
-    if (threadIdx.x == 0) s_go = (mode == 0) || ctl->state == ST_RUN;
-    __syncthreads();
-    if (!s_go) return;
     final_tree(part, 2, outv, scratch);
-    if (threadIdx.x == 0) {
+    if (t == 0) {
       const bool persist = blockIdx.x == 0;
       const int trust = ctl->trust_est, pend = ctl->conv_pending;
       const bool accept = mode != 0 && trust && pend;
-      const int st = residual_decide(outv[0], outv[1], mode == 0 ? 0 : 1, ctl, persist, accept);
-      if (persist && st == ST_RUN) {
+      const int sd = residual_decide(outv[0], outv[1], mode == 0 ? 0 : 1, ctl, persist, accept);
+      if (persist && sd == ST_RUN) {
         ctl->conv_pending = 0;
         const double beta = sqrt(outv[0]);
         ctl->active = 1;
@@ -553,91 +656,102 @@ __global__ __launch_bounds__(KTPB) void k_gm_f(const int *rowptr, const int *col
         ctl->gnext[0] = beta;
         ctl->vs[0] = 1.0 / beta;
       }
-      s_open = st == ST_RUN;
+      s_open = sd == ST_RUN;
     }
     __syncthreads();
     if (!s_open) return;
-    for (int l = threadIdx.x; l <= RB; l += blockDim.x) {
+    for (int l = t; l <= RB; l += blockDim.x) {
       if (l < RB) fco[l] = 0.0;
       cco[l] = 0.0;
     }
-  } else {
-    // one trip to memory for the run flag and the scalars of the previous steps
-    __shared__ double Hs[(MAXR + 1) * MAXR], vsh[MAXR + 1], h1s[MAXR + 1];
-    if (threadIdx.x == 0) s_go = (ctl->state == ST_RUN) && ctl->active;
-    for (int e = threadIdx.x; e < (j - 1) * LD; e += blockDim.x) Hs[e] = ctl->Hraw[e];
-    if (threadIdx.x < j) {
-      vsh[threadIdx.x] = ctl->vs[threadIdx.x];
-      h1s[threadIdx.x] = ctl->h1[threadIdx.x];
-    }
-    __syncthreads();
-    if (!s_go) return;
-    final_tree(part, j, outv, scratch);
-    // second-pass coefficients of w'_j and the completed column j - 1 of H
-    for (int l = threadIdx.x; l < RB; l += blockDim.x) {
-      const double g = (l < j) ? outv[l] * vsh[l] : 0.0;
-      gsh[l] = g;
-      fco[l] = (l < j) ? g * vsh[l] : 0.0;
-      if (l < j) {
-        Hs[l + (j - 1) * LD] = h1s[l] + g;
-        if (blockIdx.x == 0) ctl->Hraw[l + (j - 1) * LD] = h1s[l] + g;
-      }
-    }
-    __syncthreads();
-    if (mode != 2) {
-      // coefficients of A (sum_{l<j} g_l v_l) on the raw columns 0..j
-      for (int k = threadIdx.x; k <= RB; k += blockDim.x) {
-        double c = 0.0;
-        if (k < j) {
-          double s = 0.0;
-#pragma unroll 4
-          for (int l = k; l < j; ++l) s += gsh[l] * Hs[k + l * LD];
-          c = s * vsh[k];
-        }
-        if (k >= 1 && k <= j) c += gsh[k - 1];
-        cco[k] = c;
-      }
-    }
-    __syncthreads();
   }
-  if (lidx >= 0 && blockIdx.x == 0 && threadIdx.x == 0) ctl->work_log[lidx] = 1;
-  const TV *src = (j == 0) ? V : T;
-  TV *wcol = V + (size_t)j * ld;
-  TV *ycol = V + (size_t)(j + 1) * ld;
-  const double cj = cco[j < RB ? j : RB];
+  if (lidx >= 0 && blockIdx.x == 0 && t == 0) ctl->work_log[lidx] = 1;
+
   double ex[2] = {0.0, 0.0};  // ||w''_j||^2, V[:, j]^T y
   double acc[RB];             // V[:, k]^T y, k < j
 #pragma unroll
   for (int l = 0; l < RB; ++l) acc[l] = 0.0;
-  for (int64_t r0 = (int64_t)blockIdx.x * (R * KTPB); r0 < n; r0 += (int64_t)gridDim.x * (R * KTPB)) {
-    // the rows' column values are requested before the SpMV so their latency overlaps
-    // its loads; every load is issued (columns past the live ones re-read a live
-    // column and are masked), so no branch separates them
+  bool first = true;
+  for (; r0 < n; r0 += stride) {
+    const bool spmv = mode != 2;
+    const bool staged = spmv && pr.p1 > pr.p0 && pr.p1 - pr.p0 <= CAP;
+    // SpMV round 1: columns and values (issued unconditionally: a branch around them
+    // would make the column loads below wait for them)
+    StageRound<C> sr;
+    stage_load<C>(sr, col, val, pr.p0, pr.p1);
+    // the pass's column values (slots past the live columns are skipped by a uniform
+    // branch and hold zero)
     double vl[R][RB], s0[R];
 #pragma unroll
     for (int u = 0; u < R; ++u) {
-      const int64_t i = r0 + (int64_t)u * KTPB + threadIdx.x;
+      const int64_t i = r0 + (int64_t)u * KTPB + t;
       const int64_t ic = i < n ? i : n - 1;
 #pragma unroll
-      for (int k = 0; k < RB; ++k) {
-        const double v = (double)V[(size_t)(k < j ? k : (j > 0 ? j - 1 : 0)) * ld + ic];
-        vl[u][k] = (k < j) ? v : 0.0;
-      }
+      for (int k = 0; k < RB; ++k) vl[u][k] = (k < j) ? (double)V[(size_t)k * ld + ic] : 0.0;
       s0[u] = (double)src[ic];
     }
+    if (first && j > 0) {
+      // prologue, while the loads above are in flight: second-pass coefficients of
+      // w'_j, the completed column j - 1 of H, and the coefficients of
+      // A (sum_{l<j} g_l v_l) on the raw columns 0..j
+      final_tree(part, j, outv, scratch);
+      for (int l = t; l < RB; l += blockDim.x) {
+        const double g = (l < j) ? outv[l] * vsh[l] : 0.0;
+        gsh[l] = g;
+        fco[l] = (l < j) ? g * vsh[l] : 0.0;
+        if (l < j) {
+          Hs[l + (j - 1) * LD] = h1s[l] + g;
+          if (blockIdx.x == 0) ctl->Hraw[l + (j - 1) * LD] = h1s[l] + g;
+        }
+      }
+      __syncthreads();
+      if (mode != 2) {
+        for (int k = t; k <= RB; k += blockDim.x) {
+          double c = 0.0;
+          if (k < j) {
+            double sacc = 0.0;
+#pragma unroll 4
+            for (int l = k; l < j; ++l) sacc += gsh[l] * Hs[k + l * LD];
+            c = sacc * vsh[k];
+          }
+          if (k >= 1 && k <= j) c += gsh[k - 1];
+          cco[k] = c;
+        }
+      }
+    }
+    first = false;
     double ax[R];
 #pragma unroll
     for (int u = 0; u < R; ++u) ax[u] = 0.0;
-    if (mode != 2) {
-      const Gather1<TV> gx{src};
-      const TileRowsR<R> tr = tile_spmv_stage_r<KTPB, R, SPMV_CAP * R>(rowptr, col, val, gx, n, r0, prod);
+    if (spmv) {
+      if (staged) {
+        stage_gather<C>(sr, gx);
+        stage_write<C>(sr, pr.p0, pr.p0, pr.p1, prod);
+        for (int base = pr.p0 + C * KTPB; base < pr.p1; base += C * KTPB) {
+          stage_load<C>(sr, col, val, base, pr.p1);
+          stage_gather<C>(sr, gx);
+          stage_write<C>(sr, base, pr.p0, pr.p1, prod);
+        }
+      }
       __syncthreads();
-      tile_spmv_sum_r<R>(tr, col, val, gx, prod, ax);
-      __syncthreads();
+#pragma unroll
+      for (int u = 0; u < R; ++u) {
+        double a = 0.0;
+        if (staged) {
+          for (int p = pr.a[u]; p < pr.b[u]; ++p) a += prod[p - pr.p0];
+        } else {
+          for (int p = pr.a[u]; p < pr.b[u]; ++p) a += (double)val[p] * gx(col[p]);
+        }
+        ax[u] = a;
+      }
     }
+    __syncthreads();  // fco / cco visible; prod free for the next pass
+    // the next pass's row pointers, requested before this pass's arithmetic
+    if (r0 + stride < n) pr = pass_rows<R>(rowptr, n, r0 + stride);
+    const double cj = cco[j < RB ? j : RB];
 #pragma unroll
     for (int u = 0; u < R; ++u) {
-      const int64_t i = r0 + (int64_t)u * KTPB + threadIdx.x;
+      const int64_t i = r0 + (int64_t)u * KTPB + t;
       if (i < n) {
         double w = s0[u];
 #pragma unroll
@@ -660,44 +774,84 @@ __global__ __launch_bounds__(KTPB) void k_gm_f(const int *rowptr, const int *col
       }
     }
   }
+  if (first && j > 0) {
+    // a block without rows still completes the prologue (block 0 persists column j - 1)
+    final_tree(part, j, outv, scratch);
+    for (int l = t; l < RB && l < j; l += blockDim.x)
+      if (blockIdx.x == 0) ctl->Hraw[l + (j - 1) * LD] = h1s[l] + outv[l] * vsh[l];
+  }
   kstore2<RB>(ex, acc, mode == 2 ? 1 : j + 2, red, Pout + (size_t)blockIdx.x * KW);
 }
 
-// G(j); R = row tiles of KTPB rows each block takes at once.
+// G(j); R = row tiles of KTPB rows each block takes per pass.  One trip for the
+// control block and F(j)'s partial rows; then the first pass's columns are requested
+// before the reduction and the close of step j - 1 run, which they overlap.
 template <typename TV, int RB, int R>
 __global__ __launch_bounds__(KTPB) void k_gm_g(const TV *V, TV *T, int64_t n, int64_t ld, int j, const double *Pin,
                                                int nblk, double *Pout, Ctl *ctl) {
+  const int LD = MAXR + 1;
   static_assert(RB + 2 <= WAVE, "partial rows are reduced in one group");
   __shared__ double red[KNW * RB];
   __shared__ double outv[RB + 2];
   __shared__ double scratch[KTPB];
   __shared__ double coef[RB];
-  __shared__ double s_vs;
   __shared__ double vsh[MAXR + 1];
   __shared__ int s_ibase, s_go;
   __shared__ CloseIn ci;
-  // one trip to memory for the partial rows of F(j) (loaded before the run flag is
-  // known), the run flag, the close inputs and the column scales
+  const int t = threadIdx.x;
+  // ---- one trip: control block (run flag, close inputs, column scales), partial rows
+  const int st = ctl->state, act = ctl->active, ib = ctl->ibase;
+  const int jc = j > 0 ? j - 1 : 0;  // step closed here
+  const double col_t = ctl->Hraw[(t <= jc ? t : jc) + jc * LD];
+  const double cs_t = ctl->cs[t < jc ? t : 0], sn_t = ctl->sn[t < jc ? t : 0];
+  const double gj = ctl->gnext[jc], tol = ctl->tol, bn = ctl->bnorm;
+  const int maxit = ctl->maxit, restart = ctl->restart, trust = ctl->trust_est;
+  const double vs_t = ctl->vs[t <= j ? t : j];
   const double part = final_part(Pin, nblk, KW, j + 2);
-  if (threadIdx.x == 0) {
-    const int st = ctl->state, act = ctl->active, ib = ctl->ibase;
+  if (t == 0) {
     s_go = (st == ST_RUN) && act;
     s_ibase = ib;
   }
-  if (j > 0) close_stage(j - 1, ctl, &ci);
-  if (threadIdx.x <= j) vsh[threadIdx.x] = ctl->vs[threadIdx.x];
+  if (j > 0) {
+    if (t <= jc) ci.col[t] = col_t;
+    if (t < jc) {
+      ci.cs[t] = cs_t;
+      ci.sn[t] = sn_t;
+    }
+    if (t == WAVE) {
+      ci.gj = gj;
+      ci.tolb = tol * bn;
+      ci.maxit = maxit;
+      ci.restart = restart;
+      ci.trust = trust;
+    }
+  }
+  if (t <= j) vsh[t] = vs_t;
   __syncthreads();
   if (!s_go) return;
+  // ---- the first pass's columns, requested before the LDS work below
+  const TV *ycol = V + (size_t)(j + 1) * ld;
+  const int64_t stride = (int64_t)gridDim.x * (R * KTPB);
+  int64_t r0 = (int64_t)blockIdx.x * (R * KTPB);
+  double vl[R][RB], yv[R];
+  auto load_pass = [&](int64_t rb) {
+#pragma unroll
+    for (int u = 0; u < R; ++u) {
+      const int64_t i = rb + (int64_t)u * KTPB + t;
+      const int64_t ic = i < n ? i : n - 1;
+#pragma unroll
+      for (int k = 0; k < RB; ++k) vl[u][k] = (k <= j) ? (double)V[(size_t)k * ld + ic] : 0.0;
+      yv[u] = (double)ycol[ic];
+    }
+  };
+  load_pass(r0);
   final_tree(part, j + 2, outv, scratch);
-  if (j > 0) {
-    if (gm_close_block(j - 1, sqrt(outv[0]), s_ibase + j, &ci, ctl, blockIdx.x == 0, &s_vs)) return;
-  } else {
-    if (threadIdx.x == 0) s_vs = vsh[0];
-    __syncthreads();
-  }
-  const double vsj = s_vs;
+  // scale of v_j: 1 / ||w''_j|| (the close of step j - 1 records the same), or vs[0]
+  // as F(0) opened the cycle
+  const double hn = sqrt(outv[0]);
+  const double vsj = j > 0 ? (hn > 0.0 ? 1.0 / hn : 0.0) : vsh[0];
   // h1_k = v_k^T A v_j = vs[k] vs[j] V[:, k]^T y
-  for (int k = threadIdx.x; k < RB; k += blockDim.x) {
+  for (int k = t; k < RB; k += blockDim.x) {
     double c = 0.0;
     if (k <= j) {
       const double vk = (k == j) ? vsj : vsh[k];
@@ -709,30 +863,26 @@ __global__ __launch_bounds__(KTPB) void k_gm_g(const TV *V, TV *T, int64_t n, in
     coef[k] = c;
   }
   __syncthreads();
-  const TV *ycol = V + (size_t)(j + 1) * ld;
+  // close of step j - 1 (Givens rotation, residual estimate, cycle-end test) on wave 0
+  // while the other waves stream: when it ends the cycle, nothing reads this kernel's
+  // outputs (every later kernel of the cycle checks `active`)
+  if (j > 0 && t < WAVE) {
+    const bool persist = blockIdx.x == 0;
+    if (t == 0) (void)gm_close_scalar(j - 1, hn, s_ibase + j, &ci, ctl, persist);
+    if (persist)
+      for (int l = t; l <= j - 1; l += WAVE) ctl->R[l + (j - 1) * LD] = ci.col[l];
+  }
   double acc[RB];
 #pragma unroll
   for (int l = 0; l < RB; ++l) acc[l] = 0.0;
 #pragma unroll 1
-  for (int64_t r0 = (int64_t)blockIdx.x * (R * KTPB); r0 < n; r0 += (int64_t)gridDim.x * (R * KTPB)) {
+  while (r0 < n) {
     // compiler barrier: re-read the LDS coefficients per row instead of holding all of
     // them in registers next to the column values and the partial dots
     __asm__ volatile("" ::: "memory");
-    double vl[R][RB], yv[R];
 #pragma unroll
     for (int u = 0; u < R; ++u) {
-      const int64_t i = r0 + (int64_t)u * KTPB + threadIdx.x;
-      const int64_t ic = i < n ? i : n - 1;
-#pragma unroll
-      for (int k = 0; k < RB; ++k) {
-        const double v = (double)V[(size_t)(k <= j ? k : j) * ld + ic];
-        vl[u][k] = (k <= j) ? v : 0.0;
-      }
-      yv[u] = (double)ycol[ic];
-    }
-#pragma unroll
-    for (int u = 0; u < R; ++u) {
-      const int64_t i = r0 + (int64_t)u * KTPB + threadIdx.x;
+      const int64_t i = r0 + (int64_t)u * KTPB + t;
       if (i < n) {
         double w = vsj * yv[u];
 #pragma unroll
@@ -744,6 +894,8 @@ __global__ __launch_bounds__(KTPB) void k_gm_g(const TV *V, TV *T, int64_t n, in
         for (int k = 0; k < RB; ++k) acc[k] += vl[u][k] * wd;
       }
     }
+    r0 += stride;
+    if (r0 < n) load_pass(r0);
   }
   kstore<RB>(acc, j + 1, red, Pout + (size_t)blockIdx.x * KW);
 }
@@ -752,7 +904,6 @@ __global__ __launch_bounds__(KTPB) void k_gm_g(const TV *V, TV *T, int64_t n, in
 __global__ __launch_bounds__(KTPB) void k_gm_close(const double *Pin, int nblk, int j, Ctl *ctl) {
   __shared__ double outv[1];
   __shared__ double scratch[KTPB];
-  __shared__ double s_vs;
   __shared__ int s_go, s_ibase;
   __shared__ CloseIn ci;
   if (threadIdx.x == 0) {
@@ -764,7 +915,7 @@ __global__ __launch_bounds__(KTPB) void k_gm_close(const double *Pin, int nblk, 
   __syncthreads();
   if (!s_go) return;
   final_sum(Pin, nblk, KW, 1, outv, scratch);
-  gm_close_block(j, sqrt(outv[0]), s_ibase + j + 1, &ci, ctl, true, &s_vs);
+  gm_close_block(j, sqrt(outv[0]), s_ibase + j + 1, &ci, ctl, true);
 }
 
 // End of a cycle: every block solves R y = gam (m x m upper triangular, staged in
@@ -842,32 +993,39 @@ static void gm_f_launch(const CsrView &A, TV *V, TV *T, int64_t ld, int j, int m
   // timed launches record their start/stop events in the kernel's own dispatch
   hipEvent_t e0 = tm ? tm->e0 : nullptr, e1 = tm ? tm->e1 : nullptr;
   const int lidx = tm ? tm->lidx : -1;
+  // F reads one column / value entry even for an empty pass: a matrix without nonzeros
+  // gets stand-in arrays (never used in a product)
+  const int *colp = A.nnz > 0 ? A.col : A.rowptr;
+  const void *valp = A.nnz > 0 ? A.val : (const void *)V;
   if (A.fp32)
-    hipExtLaunchKernelGGL((k_gm_f<float, TV, RB, R>), dim3(nb), dim3(KTPB), 0, st, e0, e1, 0, A.rowptr, A.col,
-                          (const float *)A.val, V, T, A.n, ld, j, mode, PA(partials), nb, PB(partials), ctl, lidx);
+    hipExtLaunchKernelGGL((k_gm_f<float, TV, RB, R>), dim3(nb), dim3(KTPB), 0, st, e0, e1, 0, A.rowptr, colp,
+                          (const float *)valp, V, T, A.n, ld, j, mode, PA(partials), nb, PB(partials), ctl, lidx);
   else
-    hipExtLaunchKernelGGL((k_gm_f<double, TV, RB, R>), dim3(nb), dim3(KTPB), 0, st, e0, e1, 0, A.rowptr, A.col,
-                          (const double *)A.val, V, T, A.n, ld, j, mode, PA(partials), nb, PB(partials), ctl, lidx);
+    hipExtLaunchKernelGGL((k_gm_f<double, TV, RB, R>), dim3(nb), dim3(KTPB), 0, st, e0, e1, 0, A.rowptr, colp,
+                          (const double *)valp, V, T, A.n, ld, j, mode, PA(partials), nb, PB(partials), ctl, lidx);
 }
 
+// F takes two row tiles per pass only up to 16 columns (at 32 the column values, the
+// dots and a staging round no longer fit in the registers of two waves per SIMD)
 template <typename TV, int RB>
 static void gm_f_rb(const CsrView &A, TV *V, TV *T, int64_t ld, int j, int mode, double *partials, Ctl *ctl,
                     hipStream_t st, const KTiming *tm = nullptr) {
-  if (gm_two_rows(A.n))
-    gm_f_launch<TV, RB, 2>(A, V, T, ld, j, mode, partials, ctl, st, tm);
-  else
-    gm_f_launch<TV, RB, 1>(A, V, T, ld, j, mode, partials, ctl, st, tm);
+  if constexpr (RB <= 16) {
+    if (gm_two_rows(A.n)) {
+      gm_f_launch<TV, RB, 2>(A, V, T, ld, j, mode, partials, ctl, st, tm);
+      return;
+    }
+  }
+  gm_f_launch<TV, RB, 1>(A, V, T, ld, j, mode, partials, ctl, st, tm);
 }
 
+// G takes one row tile per pass (measured faster than two for every column count: the
+// lower register count lets the first pass's loads overlap the close better)
 template <typename TV, int RB>
 static void gm_g_rb(const CsrView &A, TV *V, TV *T, int64_t ld, int j, double *partials, Ctl *ctl, hipStream_t st) {
   const int nb = kblocks(A.n);
-  if (gm_two_rows(A.n))
-    hipLaunchKernelGGL((k_gm_g<TV, RB, 2>), dim3(nb), dim3(KTPB), 0, st, V, T, A.n, ld, j, PB(partials), nb,
-                       PA(partials), ctl);
-  else
-    hipLaunchKernelGGL((k_gm_g<TV, RB, 1>), dim3(nb), dim3(KTPB), 0, st, V, T, A.n, ld, j, PB(partials), nb,
-                       PA(partials), ctl);
+  hipLaunchKernelGGL((k_gm_g<TV, RB, 1>), dim3(nb), dim3(KTPB), 0, st, V, T, A.n, ld, j, PB(partials), nb,
+                     PA(partials), ctl);
 }
 
 // Arnoldi step j of a cycle: F(j), G(j).  first_mode: 0 first cycle, 1 restart
@@ -941,7 +1099,7 @@ int64_t padded_ld(int64_t n) { return (n + 511) / 512 * 512 + 576; }
 
 size_t krylov_partials_doubles() { return (size_t)2 * KMAXBLK * KW; }
 
-int gm_rows_per_thread(int64_t n) { return gm_two_rows(n) ? 2 : 1; }
+int gm_f_rows_per_thread(int64_t n, int rb) { return rb <= 16 && gm_two_rows(n) ? 2 : 1; }
 
 int cg_rows_per_thread(int64_t n) { return cg_rows(n); }
 
