@@ -4,9 +4,9 @@
  * Section 1 eq. (seq)), on AMD Instinct MI355X (gfx950).
  *
  * Per step the library computes an initial guess x0 in the span of the M most recent
- * solutions (Alg. 1 steps 1-3; basis from the randomized range finder of Section 2.2
+ * solutions (Alg. 1 (history, basis and reduced problem); basis from the randomized range finder of Section 2.2
  * orthonormalised by a sketched QR) and then runs CG or restarted GMRES from it
- * (Alg. 1 step 4).  All arithmetic of a step runs in HIP kernels on the device.
+ * (Alg. 1 (Krylov solve)).  All arithmetic of a step runs in HIP kernels on the device.
  *
  * Conventions for every entry point:
  *   - Pointers named *_dev are device pointers (hipMalloc'd memory or a torch CUDA
@@ -145,7 +145,7 @@ int sa_init_sequence(const sa_config *cfg, void *dev_ws, size_t ws_bytes, void *
 int sa_push_solution(sa_seq *q, const void *x_dev, void *stream);
 
 /* Initial guess of Alg. 1 for the system (A, b): basis Q of span(history) from the
- * sketched QR (Alg. 1 step 2, Section 2.2), reduced problem (Alg. 1 step 3; Galerkin
+ * sketched QR (Alg. 1 (basis), Section 2.2), reduced problem (Alg. 1 (reduced problem); Galerkin
  * or minimum residual per the config) and x0 = Q y.  Empty history gives x0 = 0.
  * b_dev, x0_dev: float64, length n.  Asynchronous; if info is non-NULL the call waits
  * for the stream and fills k_eff, k_sketch, history, used_fallback, ms_guess.
@@ -153,7 +153,7 @@ int sa_push_solution(sa_seq *q, const void *x_dev, void *stream);
 int sa_initial_guess(sa_seq *q, const sa_csr *A, const void *b_dev, void *x0_dev,
                      sa_info *info, void *stream);
 
-/* Krylov solve of A x = b from the iterate in x_dev (Alg. 1 step 4): CG or GMRES per
+/* Krylov solve of A x = b from the iterate in x_dev (Alg. 1 (Krylov solve)): CG or GMRES per
  * the config, stopping on ||b - A x||_2 <= tol ||b||_2 checked before the first
  * iteration and confirmed with the true residual.  x_dev: float64, in = x0, out = x.
  * SA_MIXED, SA_MIXED_KRYLOV: A must carry float32 values; each refinement sweep forms r = b - A x in

@@ -11,13 +11,13 @@ What each module follows (sections / equations / algorithms of arXiv 2309.02156)
 * ``philox``   - the counter-based generator the method's random draws come from
                  (Philox4x64-10 of Salmon et al., SC'11) and Box-Muller normals.
 * ``sketch``   - the left sketch S (Gaussian or subsampled randomized Hadamard).
-* ``basis``    - Alg. 1 step 2 with the randomized range finder of Section 2.2
-                 (Alg. 3, lines 2-4 and 11), the sketched-QR orthonormalisation, the
-                 reduced problem of Alg. 1 step 3 (Section 2 minimum residual, plus
+* ``basis``    - Alg. 1 (basis) with the randomized range finder of Section 2.2
+                 (Alg. 3 (initialisation and reduced QR of Omega)), the sketched-QR orthonormalisation, the
+                 reduced problem of Alg. 1 (reduced problem) (Section 2 minimum residual, plus
                  the Galerkin variant), POD (Alg. 2) and the literal progressive
-                 update of Alg. 3 (lines 6-9) with periodic refresh.
+                 update of Alg. 3 (rank-one updates of Omega) with periodic refresh.
 * ``krylov``   - CG (Hestenes-Stiefel) and restarted GMRES (Saad-Schultz) with
-                 modified Gram-Schmidt and Givens rotations (Section 1, Alg. 1 step 4).
+                 modified Gram-Schmidt and Givens rotations (Section 1, Alg. 1 (Krylov solve)).
 * ``sequence`` - the per-step driver of Alg. 1 over a stream of systems (eq. (seq)).
 * ``theory``   - the bounds of Theorems 1 and 2 and eq. (errorrandsvd), used as pins.
 

@@ -1,9 +1,9 @@
-"""Basis generation and the reduced problem (Alg. 1 steps 2-3, Algs. 2 and 3).
+"""Basis generation and the reduced problem (Alg. 1 (basis and reduced problem), Algs. 2 and 3).
 
 The step of Alg. 1 that this module implements, for a history X = [x(t_{i-M}) | ... |
 x(t_{i-1})] (Section 2), is
 
-1. basis Q of a subspace S of span(X) (Alg. 1 step 2):
+1. basis Q of a subspace S of span(X) (Alg. 1 (basis)):
    * randomized range finder (Section 2.2, Alg. 3): Omega = X Z with Z Gaussian
      (M x m); Z = I when m = M, which spans the same space;
    * orthonormalisation by a sketched QR: QR with column pivoting of the small matrix
@@ -11,7 +11,7 @@ x(t_{i-1})] (Section 2), is
      Q1 = Omega P R11^-1 is then nearly orthonormal, and a pivoted Cholesky factor of
      G = Q1^T Q1 (threshold tau_c relative to the largest diagonal entry) finishes it,
      Q = Q1 P2 R2^-1 with k' columns;
-2. reduced problem (Alg. 1 step 3): with W = A Q,
+2. reduced problem (Alg. 1 (reduced problem)): with W = A Q,
    * minimum residual (the paper's choice, Section 2): min_z || W z - b ||_2, solved
      through the normal equations W^T W z = W^T b;
    * Galerkin: Q^T A Q y = Q^T b (Cholesky for the SPD / CG path, LU with partial
@@ -20,7 +20,7 @@ x(t_{i-1})] (Section 2), is
 
 Also here: the plain definitions the method reaches when span(X) is numerically full
 rank (used as pins), POD (Alg. 2, eq. (optpod)) and the literal progressive update of
-Alg. 3 lines 6-9 with periodic refresh (Section 2.2, last paragraph).
+Alg. 3 (rank-one updates of Omega) with periodic refresh (Section 2.2, last paragraph).
 """
 
 from __future__ import annotations
@@ -111,7 +111,7 @@ class Basis:
 
 def sketched_basis(X: np.ndarray, SX: np.ndarray, Z: np.ndarray | None = None,
                    tau_s: float = 1e-12, tau_c: float = 1e-12, store=None) -> Basis:
-    """Alg. 1 step 2 with the randomized range finder and a sketched QR.
+    """Alg. 1 (basis) with the randomized range finder and a sketched QR.
 
     X is the n x M history, SX = S X its sketch (s x M), Z the M x m range-finder
     matrix (None means Z = I).  ``store`` rounds Q1 where it is written to memory (the
@@ -151,7 +151,7 @@ class Guess:
 
 def reduced_solve(A, b: np.ndarray, B: Basis, projection: str = "galerkin",
                   spd: bool = True):
-    """Alg. 1 step 3: the reduced system on span(Q) and its coefficients c (x0 = Q1 c).
+    """Alg. 1 (reduced problem): the reduced system on span(Q) and its coefficients c (x0 = Q1 c).
 
     Galerkin: (Q^T A Q) y = Q^T b; minimum residual: (W^T W) y = W^T b with W = A Q.
     """
@@ -256,10 +256,10 @@ def range_finder_z(M: int, m: int, seed: int, epoch: int, row0: int = 0) -> np.n
 
 
 class ProgressiveSketch:
-    """Omega = X Z kept up to date by rank-one updates (Alg. 3 lines 5-9).
+    """Omega = X Z kept up to date by rank-one updates (Alg. 3 (rank-one updates of Omega)).
 
     Every ``refresh`` pushes (and at the first full window) Z is redrawn and Omega is
-    recomputed from scratch (Alg. 3 lines 2-4; Section 2.2 last paragraph and the
+    recomputed from scratch (Alg. 3 (initialisation of Omega); Section 2.2 last paragraph and the
     50-step refresh of Section 4).  Between refreshes: Omega -= x_old z_1^T; the rows of
     Z shift up by one; a new row z_M is drawn; Omega += x_new z_M^T.  Parity: the
     mathematical equivalence with the from-scratch sketch (Section 2.2) is the pin.
@@ -304,6 +304,6 @@ class ProgressiveSketch:
         return np.stack(self.cols, 1)
 
     def basis(self) -> np.ndarray:
-        """Reduced QR of Omega (Alg. 3 line 11)."""
+        """Reduced QR of Omega (Alg. 3 (reduced QR of Omega))."""
         Q, _ = np.linalg.qr(self.Omega)
         return Q

@@ -1,4 +1,4 @@
-"""Krylov solvers seeded by the initial guess (Alg. 1 step 4; Section 1).
+"""Krylov solvers seeded by the initial guess (Alg. 1 (Krylov solve); Section 1).
 
 Stopping rule (the paper states none): ||b - A x||_2 <= tol ||b||_2, checked before the
 first iteration, so a good enough initial guess costs zero iterations (the paper

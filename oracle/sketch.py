@@ -1,7 +1,7 @@
 """Left sketch S (s x n) applied to history columns.
 
 The paper sketches the history from the right, Omega = X Z (Section 2.2, eq.
-(currenttimestep)), and orthonormalises Omega with a reduced QR (Alg. 3 line 11).
+(currenttimestep)), and orthonormalises Omega with a reduced QR (Alg. 3 (reduced QR of Omega)).
 This project keeps that randomized range finder for m < M and, for the
 orthonormalisation itself, uses a left subspace embedding S: the R factor of the
 small matrix S X (Z) is computed and X is preconditioned by it (randomized

@@ -416,7 +416,7 @@ int status_of(int state) {
   return SA_OK;
 }
 
-// Alg. 1 steps 2-3 on the device: Q1 = X T1, SpMM + Gram, reduced solve, x0 = Q1 c.
+// Alg. 1 (basis and reduced problem) on the device: Q1 = X T1, SpMM + Gram, reduced solve, x0 = Q1 c.
 template <typename TX>
 int guess_projection(sa_seq *q, const CsrView &v, const double *b, double *x0, int cnt, hipStream_t st) {
   const sa_config &c = q->cfg;

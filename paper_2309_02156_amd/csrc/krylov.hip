@@ -1,5 +1,5 @@
 // Krylov kernels: CG (Hestenes-Stiefel) and GMRES(m) with classical Gram-Schmidt
-// applied twice (Alg. 1 step 4 of arXiv 2309.02156; stopping rule ||b - A x|| <=
+// applied twice (Alg. 1 (Krylov solve) of arXiv 2309.02156; stopping rule ||b - A x|| <=
 // tol ||b||, tested before the first iteration and confirmed with the true residual).
 //
 // Vectors are stored as TV (double, or float for the inner solves of the mixed

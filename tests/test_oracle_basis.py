@@ -1,4 +1,4 @@
-"""Pins of the oracle's basis and reduced problem (Alg. 1 steps 2-3, Algs. 2-3).
+"""Pins of the oracle's basis and reduced problem (Alg. 1 (basis and reduced problem), Algs. 2-3).
 
 Each test checks the oracle against something other than itself: the plain
 definitions computed by dense SVD / least squares, closed forms (M = 1, polynomial
@@ -228,7 +228,7 @@ def test_pod_optimality_identity():
 
 
 def test_progressive_update_matches_scratch():
-    """Alg. 3 lines 6-9 keep Omega = X Z exactly in exact arithmetic (Section 2.2)."""
+    """Alg. 3 (rank-one updates of Omega) keep Omega = X Z exactly in exact arithmetic (Section 2.2)."""
     rng = np.random.default_rng(15)
     n, M, m = 300, 8, 4
     ps = bs.ProgressiveSketch(n, M, m, seed=3, refresh=50)
