@@ -84,7 +84,7 @@ typedef struct {
   double rank_tol_sketch; /* QRCP truncation |R_jj| > tau |R_11| (<= 0: default)      */
   double rank_tol_chol;   /* pivoted-Cholesky truncation relative to max diag (<= 0: default) */
   uint64_t seed;          /* key of the sketch's random entries                        */
-  int32_t poll;           /* Krylov iterations enqueued between host convergence polls (<= 0: default) */
+  int32_t poll;           /* Krylov steps the host may enqueue ahead of the device (<= 0: default 8) */
   int32_t inner_maxit;    /* mixed: iteration cap of one inner solve (<= 0: 10 GMRES
                              cycles, or 1000 CG iterations)                          */
 } sa_config;
@@ -249,7 +249,7 @@ int sa_set_time(sa_seq *q, double t);
  * solution), the sequences spread over up to max_streams HIP streams owned by the batch
  * (one host thread each) so that small sequences run concurrently; sequences go to
  * streams longest-first by the estimated cost nnz x (iterations of their last step +
- * 10).  The plan (streams used, Krylov poll batch) is tuned on the steps after the
+ * 10).  The plan (streams used, Krylov steps enqueued ahead) is tuned on the steps after the
  * first tune_warmup ones: each step from then on times one candidate plan, per Krylov
  * iteration of the batch, until all candidates are timed; the fastest is kept. */
 typedef struct sa_batch sa_batch;

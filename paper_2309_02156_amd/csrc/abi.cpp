@@ -7,6 +7,7 @@
 
 #include <algorithm>
 #include <chrono>
+#include <climits>
 #include <new>
 #include <string>
 #include <thread>
@@ -54,11 +55,11 @@ struct sa_seq {
   Ctl *ctl = nullptr;     // device control block (projection + outer solve)
   Ctl *ctl_in = nullptr;  // device control block of the inner solves (mixed)
   int *hbuf = nullptr;    // pinned host mirror of solver state
+  unsigned long long *mir[2] = {nullptr, nullptr};  // progress words of ctl and ctl_in (pinned)
   long long pushes = 0;
   int64_t ld = 0;  // leading dimension of X, Q1 and the Krylov vectors
   double tau_s = 1e-12, tau_c = 1e-12;
   hipEvent_t ev[4] = {nullptr, nullptr, nullptr, nullptr};
-  hipEvent_t evp[2] = {nullptr, nullptr};  // look-ahead poll slots
   KernelProfile prof;
   sa_mlp *mlp = nullptr;  // learned guess (sa_learned_attach)
   int lhist = 0;          // targets per MLP input
@@ -206,15 +207,25 @@ int poll(sa_seq *q, Ctl *ctl, hipStream_t st) {
   return SA_OK;
 }
 
-int init_ctl(Ctl **out, double tol, int maxit, int restart, int trust_est, hipStream_t st) {
+// control block in device memory, with its progress word in pinned host memory
+int init_ctl(Ctl **out, unsigned long long **mir_out, double tol, int maxit, int restart, int trust_est,
+             hipStream_t st) {
   Ctl *d = nullptr;
-  if (hipMalloc((void **)&d, sizeof(Ctl)) != hipSuccess) return SA_EHIP;
+  unsigned long long *mh = nullptr, *md = nullptr;
+  if (hipHostMalloc((void **)&mh, 64, hipHostMallocDefault) != hipSuccess) return SA_EHIP;
+  *mh = 0;
+  if (hipHostGetDevicePointer((void **)&md, mh, 0) != hipSuccess || hipMalloc((void **)&d, sizeof(Ctl)) != hipSuccess) {
+    (void)hipHostFree(mh);
+    return SA_EHIP;
+  }
   Ctl *h = new (std::nothrow) Ctl();
   if (!h) {
     (void)hipFree(d);
+    (void)hipHostFree(mh);
     return SA_ENOMEM;
   }
   memset((void *)h, 0, sizeof(Ctl));
+  h->mirror = md;
   h->tol = tol;
   h->maxit = maxit;
   h->restart = restart;
@@ -226,9 +237,11 @@ int init_ctl(Ctl **out, double tol, int maxit, int restart, int trust_est, hipSt
   delete h;
   if (e != hipSuccess) {
     (void)hipFree(d);
+    (void)hipHostFree(mh);
     return SA_EHIP;
   }
   *out = d;
+  *mir_out = mh;
   return SA_OK;
 }
 
@@ -291,38 +304,52 @@ int prof_end(sa_seq *q, Ctl *ctl, hipStream_t st) {
 
 inline const char *tname(size_t w) { return w == 4 ? "float" : "double"; }
 
-// Look-ahead polling: the state words are copied into host slot s behind the work
-// enqueued so far; the host waits for the previous slot only, so one batch is always
-// queued on the device while the host decides.
-int poll_post(sa_seq *q, Ctl *ctl, int s, hipStream_t st) {
-  HIP_TRY(hipMemcpyAsync(q->hbuf + 16 + 8 * s, &ctl->state, 8 * sizeof(int), hipMemcpyDeviceToHost, st));
-  HIP_TRY(hipEventRecord(q->evp[s], st));
-  return SA_OK;
-}
-
-// waits for slot s; *done = the solver left the RUN state (or the words are corrupt)
-int poll_done(sa_seq *q, int s, bool *done) {
-  HIP_TRY(hipEventSynchronize(q->evp[s]));
-  const int state = q->hbuf[16 + 8 * s];
-  *done = state != ST_RUN;
-  return SA_OK;
-}
-
-struct Poller {
-  sa_seq *q;
-  Ctl *ctl;
-  hipStream_t st;
-  int pending = -1, slot = 1;
-  // post a poll behind the enqueued work; true when an earlier poll says stop
-  int point(bool *stop) {
-    slot ^= 1;
-    SA_TRY(poll_post(q, ctl, slot, st));
-    *stop = false;
-    if (pending >= 0) SA_TRY(poll_done(q, pending, stop));
-    pending = slot;
-    return SA_OK;
+// Progress of a solve as the device reports it.  The host enqueues a solve step by
+// step and tags each step kernel with a serial number; the kernel writes the serial and
+// what it saw (solve stopped, GMRES cycle ended, CG check pending) into the control
+// block's progress word in pinned host memory.  The host stays at most `poll` steps (and
+// at least the reporting interval) in front of the device and stops enqueueing as soon as the device reports the end of
+// the solve (or of a GMRES cycle), without copies or events inside the loop.  It only
+// waits on the device's own progress: once the stream is idle every kernel has run,
+// and if the word still lags the state is read from the control block instead.  The
+// final state of a solve is always read from the control block.
+struct Progress {
+  volatile unsigned long long *w;
+  int serial = 0;  // last serial handed out
+  void reset() {
+    *w = 0ull;
+    serial = 0;
   }
+  int next() { return ++serial; }
 };
+
+inline Progress progress_of(sa_seq *q, Ctl *ctl) { return Progress{ctl == q->ctl ? q->mir[0] : q->mir[1]}; }
+
+// Waits until the device has run the step with serial `target`, or reports a flag in
+// `mask` (MIR_CYCLE_END counts only from serial `cycle_first` on), or the stream is idle.
+int progress_wait(sa_seq *q, Ctl *ctl, const Progress &pg, int target, int cycle_first, unsigned mask,
+                  hipStream_t st, int *seen, unsigned *flags) {
+  for (unsigned spin = 1;; ++spin) {
+    const unsigned long long v = *pg.w;
+    *seen = (int)(v >> 32);
+    *flags = (unsigned)v;
+    if (*seen >= target) return SA_OK;
+    const unsigned f = *flags & mask & (*seen >= cycle_first ? ~0u : ~(unsigned)MIR_CYCLE_END);
+    if (f) return SA_OK;
+    if ((spin & 127) == 0) {
+      const hipError_t e = hipStreamQuery(st);
+      if (e == hipSuccess) {
+        SA_TRY(poll(q, ctl, st));
+        const int state = q->hbuf[0];
+        *seen = pg.serial;
+        *flags = state == ST_RUN ? 0u : (state == ST_CHECK ? (unsigned)MIR_CHECK : (unsigned)MIR_STOPPED);
+        return SA_OK;
+      }
+      if (e != hipErrorNotReady) return SA_EHIP;
+    }
+    __builtin_ia32_pause();
+  }
+}
 
 // CG to the tolerance (or maxit); final state words in q->hbuf[0..7].
 template <typename TV>
@@ -335,21 +362,31 @@ int run_cg(sa_seq *q, const CsrView &v, Ctl *ctl, const TV *b, TV *x, int maxit,
   const double csr = 4.0 * (v.n + 1) + (4.0 + wv) * v.nnz;
   const std::string pname =
       std::string("k_cg_p<") + tname(wv) + ", " + tname(w) + ", " + std::to_string(cg_rows_per_thread(v.n)) + ">";
-  HIP_TRY(launch_cg_start_k<TV>(v, b, x, r, 0, q->partials, ctl, st));
-  Poller pl{q, ctl, st};
-  bool stop = false;
-  SA_TRY(pl.point(&stop));
-  // each batch either performs an iteration or ends the solve
-  for (long long batch = 0; !stop; ++batch) {
-    if (batch > (long long)maxit + 4) return SA_EHIP;
-    for (int t = 0; t < c.poll; ++t) {
-      KTiming tm;
-      // gathers r and p, writes p and q
-      const KTiming *tp = prof_slot(q, pname, csr + 4.0 * w * v.n, &tm);
-      HIP_TRY(launch_cg_iter<TV>(v, x, r, p2, qq, q->partials, ctl, st, tp));
+  Progress pg = progress_of(q, ctl);
+  pg.reset();
+  const int ahead = c.poll > MIR_EVERY ? c.poll : MIR_EVERY;
+  HIP_TRY(launch_cg_start_k<TV>(v, b, x, r, 0, q->partials, ctl, st, pg.next()));
+  // every launched iteration is productive, or a no-op while a check or the end of the
+  // solve is on its way to the host (at most `poll` of them each time)
+  const long long cap = 2LL * maxit + 64LL * c.poll + 1024;
+  for (long long launched = 0;; ++launched) {
+    if (launched > cap) return SA_EHIP;
+    int seen;
+    unsigned fl;
+    SA_TRY(progress_wait(q, ctl, pg, pg.serial - ahead, INT_MAX, MIR_STOPPED | MIR_CHECK, st, &seen, &fl));
+    if (fl & MIR_STOPPED) break;
+    if (fl & MIR_CHECK) {
+      // the recursive residual met the tolerance: confirm with the true residual and
+      // wait for the decision
+      HIP_TRY(launch_cg_start_k<TV>(v, b, x, r, 1, q->partials, ctl, st, pg.next()));
+      SA_TRY(progress_wait(q, ctl, pg, pg.serial, INT_MAX, MIR_STOPPED, st, &seen, &fl));
+      if (fl & MIR_STOPPED) break;
+      continue;
     }
-    HIP_TRY(launch_cg_start_k<TV>(v, b, x, r, 1, q->partials, ctl, st));  // confirm a CHECK
-    SA_TRY(pl.point(&stop));
+    KTiming tm;
+    // gathers r and p, writes p and q
+    const KTiming *tp = prof_slot(q, pname, csr + 4.0 * w * v.n, &tm);
+    HIP_TRY(launch_cg_iter<TV>(v, x, r, p2, qq, q->partials, ctl, st, tp, pg.next()));
   }
   SA_TRY(poll(q, ctl, st));
   if (hs[0] == ST_MAXIT || hs[0] == ST_BREAK) {
@@ -368,13 +405,24 @@ int run_gmres(sa_seq *q, const CsrView &v, Ctl *ctl, const TV *b, TV *x, int max
   SA_TRY(prof_begin(q, ctl, st));
   const size_t w = sizeof(TV), wv = v.fp32 ? 4 : 8;
   const double csr = 4.0 * (v.n + 1) + (4.0 + wv) * v.nnz;
+  Progress pg = progress_of(q, ctl);
+  pg.reset();
+  const int ahead = c.poll > MIR_EVERY ? c.poll : MIR_EVERY;
   HIP_TRY(launch_gm_start<TV>(v, b, x, V, 0, q->partials, ctl, st));
-  Poller pl{q, ctl, st};
   bool stop = false;
   // every cycle either adds an iteration or ends the solve in its first step
   for (long long cycle = 0; !stop; ++cycle) {
     if (cycle > (long long)maxit + 4) return SA_EHIP;
-    for (int j = 0; j < c.restart && !stop; ++j) {
+    const int first = pg.serial + 1;
+    for (int j = 0; j < c.restart; ++j) {
+      int seen;
+      unsigned fl;
+      SA_TRY(progress_wait(q, ctl, pg, pg.serial - ahead, first, MIR_STOPPED | MIR_CYCLE_END, st, &seen, &fl));
+      if (fl & MIR_STOPPED) {
+        stop = true;
+        break;
+      }
+      if ((fl & MIR_CYCLE_END) && seen >= first) break;  // the rest of this cycle would be no-ops
       KTiming tm;
       const KTiming *tp = nullptr;
       if (q->prof.on) {
@@ -385,14 +433,12 @@ int run_gmres(sa_seq *q, const CsrView &v, Ctl *ctl, const TV *b, TV *x, int max
                                  ", " + std::to_string(gm_f_rows_per_thread(v.n, rb)) + ">";
         tp = prof_slot(q, name, bytes, &tm);
       }
-      HIP_TRY(launch_gm_step<TV>(v, V, T, q->ld, j, cycle > 0 ? 1 : 0, q->partials, ctl, st, tp));
-      if ((j + 1) % c.poll == 0 && j + 1 < c.restart) SA_TRY(pl.point(&stop));
+      HIP_TRY(launch_gm_step<TV>(v, V, T, q->ld, j, cycle > 0 ? 1 : 0, q->partials, ctl, st, tp, pg.next()));
     }
     if (stop) break;
     HIP_TRY(launch_gm_finish<TV>(v, V, T, q->ld, c.restart, q->partials, ctl, st));
     HIP_TRY(launch_gm_update<TV>(x, V, v.n, q->ld, c.restart, ctl, st));
     HIP_TRY(launch_gm_start<TV>(v, b, x, V, 1, q->partials, ctl, st));
-    SA_TRY(pl.point(&stop));
   }
   SA_TRY(poll(q, ctl, st));
   return prof_end(q, ctl, st);
@@ -492,9 +538,9 @@ int sa_init_sequence(const sa_config *cfg, void *dev_ws, size_t ws_bytes, void *
   }
   bool ok = hipHostMalloc((void **)&q->hbuf, 64 * sizeof(int), hipHostMallocDefault) == hipSuccess;
   for (int e = 0; ok && e < 4; ++e) ok = hipEventCreate(&q->ev[e]) == hipSuccess;
-  for (int e = 0; ok && e < 2; ++e) ok = hipEventCreateWithFlags(&q->evp[e], hipEventDisableTiming) == hipSuccess;
-  if (ok) ok = init_ctl(&q->ctl, cfg->tol, cfg->maxit, cfg->restart, 0, st) == SA_OK;
-  if (ok && q->mixed) ok = init_ctl(&q->ctl_in, cfg->inner_tol, cfg->maxit, cfg->restart, 1, st) == SA_OK;
+  if (ok) ok = init_ctl(&q->ctl, &q->mir[0], cfg->tol, cfg->maxit, cfg->restart, 0, st) == SA_OK;
+  if (ok && q->mixed)
+    ok = init_ctl(&q->ctl_in, &q->mir[1], cfg->inner_tol, cfg->maxit, cfg->restart, 1, st) == SA_OK;
   if (!ok) {
     sa_destroy_sequence(q);
     return SA_EHIP;
@@ -685,10 +731,10 @@ int sa_destroy_sequence(sa_seq *q) {
   if (q->ctl) (void)hipFree(q->ctl);
   if (q->ctl_in) (void)hipFree(q->ctl_in);
   if (q->hbuf) (void)hipHostFree(q->hbuf);
+  for (auto m : q->mir)
+    if (m) (void)hipHostFree(m);
   for (int e = 0; e < 4; ++e)
     if (q->ev[e]) (void)hipEventDestroy(q->ev[e]);
-  for (int e = 0; e < 2; ++e)
-    if (q->evp[e]) (void)hipEventDestroy(q->evp[e]);
   for (auto &e : q->prof.ev)
     if (e) (void)hipEventDestroy(e);
   delete q;

@@ -43,6 +43,7 @@ struct Ctl {
   int conv_pending;             // GMRES: the last cycle ended on the estimate (trust_est)
   int pad2;
   double rho[4];                // CG: r^T r after iteration k in slot k & 3
+  unsigned long long *mirror;   // host-visible progress word (pinned host memory), or null
   double h1[MAXR + 1];          // GMRES: first Gram-Schmidt pass of the current step
   double cs[MAXR], sn[MAXR];    // Givens rotations
   double gam[MAXR + 1];         // rotated right-hand side (final entries)
@@ -64,6 +65,19 @@ struct Ctl {
   double learned_r2[2];
   int learned_used, pad3;
 };
+
+// Progress word the host reads while it enqueues a solve (pinned host memory, one
+// 64-bit store, so the serial and the flags arrive together): the serial number the
+// host gave the last step kernel that ran, and what that kernel saw.  A kernel cannot
+// complete before its store to host memory is acknowledged, so steps without news
+// report only every MIR_EVERY serials; any flag is reported at once.
+enum : unsigned { MIR_STOPPED = 1u, MIR_CYCLE_END = 2u, MIR_CHECK = 4u };
+constexpr int MIR_EVERY = 8;
+
+__device__ inline void mirror_report(unsigned long long *m, int serial, unsigned flags) {
+  if (m && serial > 0 && (flags != 0u || serial % MIR_EVERY == 0))
+    *(volatile unsigned long long *)m = ((unsigned long long)(unsigned)serial << 32) | flags;
+}
 
 // ---------------------------------------------------------------- launch geometry
 inline int stream_blocks(int64_t n) {

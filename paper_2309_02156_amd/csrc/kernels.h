@@ -77,11 +77,12 @@ struct KTiming {
 // p2 holds the two alternating direction vectors (p2 and p2 + padded_ld(n)).
 template <typename TV>
 hipError_t launch_cg_start_k(const CsrView &A, const TV *b, const TV *x, TV *r, int mode, double *partials,
-                             Ctl *ctl, hipStream_t st);
-// tm (may be null) times the direction/SpMV kernel of the iteration
+                             Ctl *ctl, hipStream_t st, int serial = 0);
+// tm (may be null) times the direction/SpMV kernel of the iteration.  serial > 0: the
+// step's kernel reports serial and what it saw in the control block's progress word
 template <typename TV>
 hipError_t launch_cg_iter(const CsrView &A, TV *x, TV *r, TV *p2, TV *q, double *partials, Ctl *ctl,
-                          hipStream_t st, const KTiming *tm = nullptr);
+                          hipStream_t st, const KTiming *tm = nullptr, int serial = 0);
 
 // GMRES(m), classical Gram-Schmidt applied twice.  A cycle: start (residual into
 // V[:, 0]), steps j = 0..m-1 (first_mode 0 for the first cycle of a solve, 1 for a
@@ -92,7 +93,7 @@ hipError_t launch_gm_start(const CsrView &A, const TV *b, const TV *x, TV *V, in
 // tm (may be null) times the step's first kernel (SpMV, finalisation, first dots)
 template <typename TV>
 hipError_t launch_gm_step(const CsrView &A, TV *V, TV *T, int64_t ld, int j, int first_mode, double *partials,
-                          Ctl *ctl, hipStream_t st, const KTiming *tm = nullptr);
+                          Ctl *ctl, hipStream_t st, const KTiming *tm = nullptr, int serial = 0);
 template <typename TV>
 hipError_t launch_gm_finish(const CsrView &A, TV *V, TV *T, int64_t ld, int m, double *partials, Ctl *ctl,
                             hipStream_t st);

@@ -155,13 +155,20 @@ __global__ __launch_bounds__(KTPB) void k_cg_start(const int *rowptr, const int 
   kstore<2>(acc, 2, red, Pout + (size_t)blockIdx.x * KW);
 }
 
-__global__ __launch_bounds__(KTPB) void k_cg_start_close(const double *Pin, int nblk, int mode, Ctl *ctl) {
+__global__ __launch_bounds__(KTPB) void k_cg_start_close(const double *Pin, int nblk, int mode, Ctl *ctl,
+                                                         int serial) {
   __shared__ double outv[2];
   __shared__ double scratch[KTPB];
-  __shared__ int s_go;
-  if (threadIdx.x == 0) s_go = (mode != 1) || (ctl->state == ST_CHECK);
+  __shared__ int s_go, s_st;
+  if (threadIdx.x == 0) {
+    s_st = ctl->state;
+    s_go = (mode != 1) || (s_st == ST_CHECK);
+  }
   __syncthreads();
-  if (!s_go) return;
+  if (!s_go) {
+    if (threadIdx.x == 0) mirror_report(ctl->mirror, serial, s_st == ST_RUN ? 0u : MIR_STOPPED);
+    return;
+  }
   final_sum(Pin, nblk, KW, 2, outv, scratch);
   if (threadIdx.x != 0) return;
   const int st = residual_decide(outv[0], outv[1], mode, ctl, true, ctl->trust_est != 0);
@@ -170,6 +177,7 @@ __global__ __launch_bounds__(KTPB) void k_cg_start_close(const double *Pin, int 
     ctl->rho[k & 3] = outv[0];
     ctl->fresh_at = k + 1;
   }
+  if (mode != 2) mirror_report(ctl->mirror, serial, st == ST_RUN ? 0u : MIR_STOPPED);
 }
 
 template <typename TV>
@@ -276,11 +284,11 @@ __global__ __launch_bounds__(KTPB) void k_cg_p(const int *rowptr, const int *col
 // U = rows each thread takes per pass (all their loads issued before the first use)
 template <typename TV, int U>
 __global__ __launch_bounds__(KTPB) void k_cg_xr(TV *x, TV *r, const TV *P0, const TV *P1, const TV *q, int64_t n,
-                                                const double *Pin, int nblk, double *Pout, Ctl *ctl) {
+                                                const double *Pin, int nblk, double *Pout, Ctl *ctl, int serial) {
   __shared__ double red[KNW];
   __shared__ double outv[1];
   __shared__ double scratch[KTPB];
-  __shared__ int s_k, s_go;
+  __shared__ int s_k, s_go, s_st;
   __shared__ double s_rho;
   const double part = final_part(Pin, nblk, KW, 1);  // p^T q, loaded with the control block
   if (threadIdx.x == 0) {
@@ -289,16 +297,24 @@ __global__ __launch_bounds__(KTPB) void k_cg_xr(TV *x, TV *r, const TV *P0, cons
 #pragma unroll
     for (int e = 0; e < 4; ++e) r4[e] = ctl->rho[e];
     s_go = st == ST_RUN;
+    s_st = st;
     s_k = k;
     s_rho = pick4(r4, (k - 1) & 3);
   }
   __syncthreads();
-  if (!s_go) return;
+  if (!s_go) {
+    if (blockIdx.x == 0 && threadIdx.x == 0)
+      mirror_report(ctl->mirror, serial, s_st == ST_CHECK ? MIR_CHECK : MIR_STOPPED);
+    return;
+  }
   final_tree(part, 1, outv, scratch);
   const int k = s_k;
   const double pq = outv[0];
   if (!(pq > 0.0) || !isfinite(pq)) {
-    if (blockIdx.x == 0 && threadIdx.x == 0) ctl->state = ST_BREAK;
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+      ctl->state = ST_BREAK;
+      mirror_report(ctl->mirror, serial, MIR_STOPPED);
+    }
     return;
   }
   const double alpha = s_rho / pq;
@@ -328,12 +344,15 @@ __global__ __launch_bounds__(KTPB) void k_cg_xr(TV *x, TV *r, const TV *P0, cons
     }
   }
   kstore<1>(acc, 1, red, Pout + (size_t)blockIdx.x * KW);
-  if (blockIdx.x == 0 && threadIdx.x == 0) ctl->iters = k;
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    ctl->iters = k;
+    mirror_report(ctl->mirror, serial, 0u);
+  }
 }
 
 template <typename TV>
 hipError_t launch_cg_start_k(const CsrView &A, const TV *b, const TV *x, TV *r, int mode, double *partials, Ctl *ctl,
-                             hipStream_t st) {
+                             hipStream_t st, int serial) {
   const int nb = kblocks(A.n);
   if (A.fp32)
     hipLaunchKernelGGL((k_cg_start<float, TV>), dim3(nb), dim3(KTPB), 0, st, A.rowptr, A.col,
@@ -341,7 +360,7 @@ hipError_t launch_cg_start_k(const CsrView &A, const TV *b, const TV *x, TV *r, 
   else
     hipLaunchKernelGGL((k_cg_start<double, TV>), dim3(nb), dim3(KTPB), 0, st, A.rowptr, A.col,
                        (const double *)A.val, b, x, r, A.n, mode, PA(partials), ctl);
-  hipLaunchKernelGGL(k_cg_start_close, dim3(1), dim3(KTPB), 0, st, PA(partials), nb, mode, ctl);
+  hipLaunchKernelGGL(k_cg_start_close, dim3(1), dim3(KTPB), 0, st, PA(partials), nb, mode, ctl, serial);
   return hipGetLastError();
 }
 
@@ -353,7 +372,7 @@ static inline int cg_rows(int64_t n) {
 
 template <typename VT, typename TV, int R>
 static void cg_iter_launch(const CsrView &A, TV *x, TV *r, TV *P0, TV *P1, TV *q, double *partials, Ctl *ctl,
-                           hipStream_t st, const KTiming *tm) {
+                           hipStream_t st, const KTiming *tm, int serial) {
   const int nb = kblocks(A.n);
   // timed launches record their start/stop events in the kernel's own dispatch
   hipEvent_t e0 = tm ? tm->e0 : nullptr, e1 = tm ? tm->e1 : nullptr;
@@ -361,30 +380,30 @@ static void cg_iter_launch(const CsrView &A, TV *x, TV *r, TV *P0, TV *P1, TV *q
   hipExtLaunchKernelGGL((k_cg_p<VT, TV, R>), dim3(nb), dim3(KTPB), 0, st, e0, e1, 0, A.rowptr, A.col,
                         (const VT *)A.val, r, P0, P1, q, A.n, PA(partials), nb, PB(partials), ctl, lidx);
   hipLaunchKernelGGL((k_cg_xr<TV, R>), dim3(nb), dim3(KTPB), 0, st, x, r, P0, P1, q, A.n, PB(partials), nb,
-                     PA(partials), ctl);
+                     PA(partials), ctl, serial);
 }
 
 template <typename VT, typename TV>
 static void cg_iter_vt(const CsrView &A, TV *x, TV *r, TV *P0, TV *P1, TV *q, double *partials, Ctl *ctl,
-                       hipStream_t st, const KTiming *tm) {
+                       hipStream_t st, const KTiming *tm, int serial) {
   const int R = cg_rows(A.n);
   if (R == 4)
-    cg_iter_launch<VT, TV, 4>(A, x, r, P0, P1, q, partials, ctl, st, tm);
+    cg_iter_launch<VT, TV, 4>(A, x, r, P0, P1, q, partials, ctl, st, tm, serial);
   else if (R == 2)
-    cg_iter_launch<VT, TV, 2>(A, x, r, P0, P1, q, partials, ctl, st, tm);
+    cg_iter_launch<VT, TV, 2>(A, x, r, P0, P1, q, partials, ctl, st, tm, serial);
   else
-    cg_iter_launch<VT, TV, 1>(A, x, r, P0, P1, q, partials, ctl, st, tm);
+    cg_iter_launch<VT, TV, 1>(A, x, r, P0, P1, q, partials, ctl, st, tm, serial);
 }
 
 template <typename TV>
 hipError_t launch_cg_iter(const CsrView &A, TV *x, TV *r, TV *p2, TV *q, double *partials, Ctl *ctl,
-                          hipStream_t st, const KTiming *tm) {
+                          hipStream_t st, const KTiming *tm, int serial) {
   const int64_t ld = padded_ld(A.n);
   TV *P0 = p2, *P1 = p2 + ld;
   if (A.fp32)
-    cg_iter_vt<float, TV>(A, x, r, P0, P1, q, partials, ctl, st, tm);
+    cg_iter_vt<float, TV>(A, x, r, P0, P1, q, partials, ctl, st, tm, serial);
   else
-    cg_iter_vt<double, TV>(A, x, r, P0, P1, q, partials, ctl, st, tm);
+    cg_iter_vt<double, TV>(A, x, r, P0, P1, q, partials, ctl, st, tm, serial);
   return hipGetLastError();
 }
 
@@ -788,7 +807,7 @@ __global__ __launch_bounds__(KTPB) void k_gm_f(const int *rowptr, const int *col
 // before the reduction and the close of step j - 1 run, which they overlap.
 template <typename TV, int RB, int R>
 __global__ __launch_bounds__(KTPB) void k_gm_g(const TV *V, TV *T, int64_t n, int64_t ld, int j, const double *Pin,
-                                               int nblk, double *Pout, Ctl *ctl) {
+                                               int nblk, double *Pout, Ctl *ctl, int serial) {
   const int LD = MAXR + 1;
   static_assert(RB + 2 <= WAVE, "partial rows are reduced in one group");
   __shared__ double red[KNW * RB];
@@ -801,6 +820,7 @@ __global__ __launch_bounds__(KTPB) void k_gm_g(const TV *V, TV *T, int64_t n, in
   const int t = threadIdx.x;
   // ---- one trip: control block (run flag, close inputs, column scales), partial rows
   const int st = ctl->state, act = ctl->active, ib = ctl->ibase;
+  unsigned long long *const mir = ctl->mirror;
   const int jc = j > 0 ? j - 1 : 0;  // step closed here
   const double col_t = ctl->Hraw[(t <= jc ? t : jc) + jc * LD];
   const double cs_t = ctl->cs[t < jc ? t : 0], sn_t = ctl->sn[t < jc ? t : 0];
@@ -828,7 +848,10 @@ __global__ __launch_bounds__(KTPB) void k_gm_g(const TV *V, TV *T, int64_t n, in
   }
   if (t <= j) vsh[t] = vs_t;
   __syncthreads();
-  if (!s_go) return;
+  if (!s_go) {
+    if (blockIdx.x == 0 && t == 0) mirror_report(mir, serial, st != ST_RUN ? MIR_STOPPED : MIR_CYCLE_END);
+    return;
+  }
   // ---- the first pass's columns, requested before the LDS work below
   const TV *ycol = V + (size_t)(j + 1) * ld;
   const int64_t stride = (int64_t)gridDim.x * (R * KTPB);
@@ -868,9 +891,14 @@ __global__ __launch_bounds__(KTPB) void k_gm_g(const TV *V, TV *T, int64_t n, in
   // outputs (every later kernel of the cycle checks `active`)
   if (j > 0 && t < WAVE) {
     const bool persist = blockIdx.x == 0;
-    if (t == 0) (void)gm_close_scalar(j - 1, hn, s_ibase + j, &ci, ctl, persist);
+    if (t == 0) {
+      const bool end = gm_close_scalar(j - 1, hn, s_ibase + j, &ci, ctl, persist);
+      if (persist) mirror_report(mir, serial, end ? MIR_CYCLE_END : 0u);
+    }
     if (persist)
       for (int l = t; l <= j - 1; l += WAVE) ctl->R[l + (j - 1) * LD] = ci.col[l];
+  } else if (j == 0 && blockIdx.x == 0 && t == 0) {
+    mirror_report(mir, serial, 0u);
   }
   double acc[RB];
 #pragma unroll
@@ -1022,17 +1050,18 @@ static void gm_f_rb(const CsrView &A, TV *V, TV *T, int64_t ld, int j, int mode,
 // G takes one row tile per pass (measured faster than two for every column count: the
 // lower register count lets the first pass's loads overlap the close better)
 template <typename TV, int RB>
-static void gm_g_rb(const CsrView &A, TV *V, TV *T, int64_t ld, int j, double *partials, Ctl *ctl, hipStream_t st) {
+static void gm_g_rb(const CsrView &A, TV *V, TV *T, int64_t ld, int j, double *partials, Ctl *ctl, hipStream_t st,
+                    int serial) {
   const int nb = kblocks(A.n);
   hipLaunchKernelGGL((k_gm_g<TV, RB, 1>), dim3(nb), dim3(KTPB), 0, st, V, T, A.n, ld, j, PB(partials), nb,
-                     PA(partials), ctl);
+                     PA(partials), ctl, serial);
 }
 
 // Arnoldi step j of a cycle: F(j), G(j).  first_mode: 0 first cycle, 1 restart
 // (used at j = 0).
 template <typename TV>
 hipError_t launch_gm_step(const CsrView &A, TV *V, TV *T, int64_t ld, int j, int first_mode, double *partials,
-                          Ctl *ctl, hipStream_t st, const KTiming *tm) {
+                          Ctl *ctl, hipStream_t st, const KTiming *tm, int serial) {
   const int mode = j == 0 ? first_mode : 0;
   if (j <= 8)
     gm_f_rb<TV, 8>(A, V, T, ld, j, mode, partials, ctl, st, tm);
@@ -1041,11 +1070,11 @@ hipError_t launch_gm_step(const CsrView &A, TV *V, TV *T, int64_t ld, int j, int
   else
     gm_f_rb<TV, 32>(A, V, T, ld, j, mode, partials, ctl, st, tm);
   if (j < 8)
-    gm_g_rb<TV, 8>(A, V, T, ld, j, partials, ctl, st);
+    gm_g_rb<TV, 8>(A, V, T, ld, j, partials, ctl, st, serial);
   else if (j < 16)
-    gm_g_rb<TV, 16>(A, V, T, ld, j, partials, ctl, st);
+    gm_g_rb<TV, 16>(A, V, T, ld, j, partials, ctl, st, serial);
   else
-    gm_g_rb<TV, 32>(A, V, T, ld, j, partials, ctl, st);
+    gm_g_rb<TV, 32>(A, V, T, ld, j, partials, ctl, st, serial);
   return hipGetLastError();
 }
 
@@ -1078,13 +1107,13 @@ hipError_t launch_gm_update(TV *x, const TV *V, int64_t n, int64_t ld, int resta
 
 #define SACC_INSTANTIATE_KRYLOV(TV)                                                                              \
   template hipError_t launch_cg_start_k<TV>(const CsrView &, const TV *, const TV *, TV *, int, double *, Ctl *, \
-                                            hipStream_t);                                                        \
+                                            hipStream_t, int);                                                   \
   template hipError_t launch_cg_iter<TV>(const CsrView &, TV *, TV *, TV *, TV *, double *, Ctl *, hipStream_t,  \
-                                         const KTiming *);                                                       \
+                                         const KTiming *, int);                                                  \
   template hipError_t launch_gm_start<TV>(const CsrView &, const TV *, const TV *, TV *, int, double *, Ctl *,   \
                                           hipStream_t);                                                          \
   template hipError_t launch_gm_step<TV>(const CsrView &, TV *, TV *, int64_t, int, int, double *, Ctl *,        \
-                                         hipStream_t, const KTiming *);                                          \
+                                         hipStream_t, const KTiming *, int);                                     \
   template hipError_t launch_gm_finish<TV>(const CsrView &, TV *, TV *, int64_t, int, double *, Ctl *,           \
                                            hipStream_t);                                                         \
   template hipError_t launch_gm_update<TV>(TV *, const TV *, int64_t, int64_t, int, Ctl *, hipStream_t);
