@@ -307,8 +307,8 @@ inline const char *tname(size_t w) { return w == 4 ? "float" : "double"; }
 // Progress of a solve as the device reports it.  The host enqueues a solve step by
 // step and tags each step kernel with a serial number; the kernel writes the serial and
 // what it saw (solve stopped, GMRES cycle ended, CG check pending) into the control
-// block's progress word in pinned host memory.  The host stays at most `poll` steps (and
-// at least the reporting interval) in front of the device and stops enqueueing as soon as the device reports the end of
+// block's progress word in pinned host memory.  The host keeps up to `poll` (at least
+// MIR_EVERY) steps in front of the device and stops enqueueing as soon as the device reports the end of
 // the solve (or of a GMRES cycle), without copies or events inside the loop.  It only
 // waits on the device's own progress: once the stream is idle every kernel has run,
 // and if the word still lags the state is read from the control block instead.  The
@@ -364,7 +364,7 @@ int run_cg(sa_seq *q, const CsrView &v, Ctl *ctl, const TV *b, TV *x, int maxit,
       std::string("k_cg_p<") + tname(wv) + ", " + tname(w) + ", " + std::to_string(cg_rows_per_thread(v.n)) + ">";
   Progress pg = progress_of(q, ctl);
   pg.reset();
-  const int ahead = c.poll > MIR_EVERY ? c.poll : MIR_EVERY;
+  const int ahead = c.poll > MIR_EVERY ? c.poll : MIR_EVERY;  // progress arrives every MIR_EVERY steps
   HIP_TRY(launch_cg_start_k<TV>(v, b, x, r, 0, q->partials, ctl, st, pg.next()));
   // every launched iteration is productive, or a no-op while a check or the end of the
   // solve is on its way to the host (at most `poll` of them each time)
@@ -407,7 +407,7 @@ int run_gmres(sa_seq *q, const CsrView &v, Ctl *ctl, const TV *b, TV *x, int max
   const double csr = 4.0 * (v.n + 1) + (4.0 + wv) * v.nnz;
   Progress pg = progress_of(q, ctl);
   pg.reset();
-  const int ahead = c.poll > MIR_EVERY ? c.poll : MIR_EVERY;
+  const int ahead = c.poll > MIR_EVERY ? c.poll : MIR_EVERY;  // progress arrives every MIR_EVERY steps
   HIP_TRY(launch_gm_start<TV>(v, b, x, V, 0, q->partials, ctl, st));
   bool stop = false;
   // every cycle either adds an iteration or ends the solve in its first step
