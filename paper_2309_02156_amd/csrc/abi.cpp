@@ -329,6 +329,12 @@ inline Progress progress_of(sa_seq *q, Ctl *ctl) { return Progress{ctl == q->ctl
 // `mask` (MIR_CYCLE_END counts only from serial `cycle_first` on), or the stream is idle.
 int progress_wait(sa_seq *q, Ctl *ctl, const Progress &pg, int target, int cycle_first, unsigned mask,
                   hipStream_t st, int *seen, unsigned *flags) {
+  // the stream is asked whether it is idle only after 50 us without news, then every
+  // 50 us (the query takes the runtime's locks, which other threads launching on
+  // other streams need)
+  using clk = std::chrono::steady_clock;
+  const auto t0 = clk::now();
+  auto next_check = t0 + std::chrono::microseconds(50);
   for (unsigned spin = 1;; ++spin) {
     const unsigned long long v = *pg.w;
     *seen = (int)(v >> 32);
@@ -336,7 +342,8 @@ int progress_wait(sa_seq *q, Ctl *ctl, const Progress &pg, int target, int cycle
     if (*seen >= target) return SA_OK;
     const unsigned f = *flags & mask & (*seen >= cycle_first ? ~0u : ~(unsigned)MIR_CYCLE_END);
     if (f) return SA_OK;
-    if ((spin & 127) == 0) {
+    if ((spin & 31) == 0 && clk::now() >= next_check) {
+      next_check = clk::now() + std::chrono::microseconds(50);
       const hipError_t e = hipStreamQuery(st);
       if (e == hipSuccess) {
         SA_TRY(poll(q, ctl, st));
@@ -346,6 +353,7 @@ int progress_wait(sa_seq *q, Ctl *ctl, const Progress &pg, int target, int cycle
         return SA_OK;
       }
       if (e != hipErrorNotReady) return SA_EHIP;
+      std::this_thread::yield();
     }
     __builtin_ia32_pause();
   }

@@ -601,13 +601,31 @@ __device__ inline void stage_write(const StageRound<C> &sr, int base, int p0, in
   }
 }
 
+// Column value of slot k when the live columns are 0..live-1 (live >= 0), zero past
+// them.  Double: a uniform branch skips the load.  Float: the compiler makes every
+// guarded 32-bit load wait for its data before the next one is issued, so every load
+// is issued instead (slots past the live columns re-read column max(live - 1, 0)) and
+// masked.
+template <typename TV>
+__device__ inline TV slot_load(const TV *V, int64_t ld, int64_t i, int k, int live) {
+  if constexpr (sizeof(TV) == 8) {
+    return k < live ? V[(size_t)k * ld + i] : (TV)0;
+  } else {
+    const int kc = k < live ? k : (live > 0 ? live - 1 : 0);
+    const TV v = V[(size_t)kc * ld + i];
+    return k < live ? v : (TV)0;
+  }
+}
+
 // F(j); mode 0: first cycle, 1: restart cycle (both only matter for j = 0), 2: the
 // finalise-only step j = m.  R = row tiles of KTPB rows each block takes per pass.
 //
 // Order of the memory traffic (the first pass): one trip for the control block, the
 // previous kernel's partial rows and the pass's row pointers; then the SpMV's column /
-// value loads, the pass's column values, the gathers, in that order, so the column
-// stream overlaps the SpMV's dependent trips and the LDS work of the prologue.
+// value loads, the pass's column values and the gathers (from 16 slots on the gathers
+// before the column values), so the column stream overlaps the SpMV's dependent trips
+// and the LDS work of the prologue.  The gathers read in bounds for any pass: column
+// indices come from clamped in-range loads.
 template <typename VT, typename TV, int RB, int R>
 __global__ __launch_bounds__(KTPB) void k_gm_f(const int *rowptr, const int *col, const VT *val, TV *V, TV *T,
                                                int64_t n, int64_t ld, int j, int mode, const double *Pin, int nblk,
@@ -698,15 +716,21 @@ __global__ __launch_bounds__(KTPB) void k_gm_f(const int *rowptr, const int *col
     // would make the column loads below wait for them)
     StageRound<C> sr;
     stage_load<C>(sr, col, val, pr.p0, pr.p1);
+    // with 16 or more slots the gathers go out before the column stream too (their LDS
+    // write and the row sums then overlap the stream; measured faster there, slower at 8)
+    constexpr bool gathers_first = RB >= 16;
+    if constexpr (gathers_first) stage_gather<C>(sr, gx);
     // the pass's column values (slots past the live columns are skipped by a uniform
     // branch and hold zero)
-    double vl[R][RB], s0[R];
+    // (kept in the stored type and widened where used)
+    TV vl[R][RB];
+    double s0[R];
 #pragma unroll
     for (int u = 0; u < R; ++u) {
       const int64_t i = r0 + (int64_t)u * KTPB + t;
       const int64_t ic = i < n ? i : n - 1;
 #pragma unroll
-      for (int k = 0; k < RB; ++k) vl[u][k] = (k < j) ? (double)V[(size_t)k * ld + ic] : 0.0;
+      for (int k = 0; k < RB; ++k) vl[u][k] = slot_load(V, ld, ic, k, j);
       s0[u] = (double)src[ic];
     }
     if (first && j > 0) {
@@ -744,7 +768,7 @@ __global__ __launch_bounds__(KTPB) void k_gm_f(const int *rowptr, const int *col
     for (int u = 0; u < R; ++u) ax[u] = 0.0;
     if (spmv) {
       if (staged) {
-        stage_gather<C>(sr, gx);
+        if constexpr (!gathers_first) stage_gather<C>(sr, gx);
         stage_write<C>(sr, pr.p0, pr.p0, pr.p1, prod);
         for (int base = pr.p0 + C * KTPB; base < pr.p1; base += C * KTPB) {
           stage_load<C>(sr, col, val, base, pr.p1);
@@ -774,7 +798,7 @@ __global__ __launch_bounds__(KTPB) void k_gm_f(const int *rowptr, const int *col
       if (i < n) {
         double w = s0[u];
 #pragma unroll
-        for (int k = 0; k < RB; ++k) w -= fco[k] * vl[u][k];
+        for (int k = 0; k < RB; ++k) w -= fco[k] * (double)vl[u][k];
         const TV ws = (TV)w;
         if (j > 0 && mode != 2) wcol[i] = ws;
         const double wd = (double)ws;
@@ -782,13 +806,13 @@ __global__ __launch_bounds__(KTPB) void k_gm_f(const int *rowptr, const int *col
         if (mode != 2) {
           double y = ax[u] - cj * wd;
 #pragma unroll
-          for (int k = 0; k < RB; ++k) y -= cco[k] * vl[u][k];
+          for (int k = 0; k < RB; ++k) y -= cco[k] * (double)vl[u][k];
           const TV ys = (TV)y;
           ycol[i] = ys;
           const double yd = (double)ys;
           ex[1] += wd * yd;
 #pragma unroll
-          for (int k = 0; k < RB; ++k) acc[k] += vl[u][k] * yd;
+          for (int k = 0; k < RB; ++k) acc[k] += (double)vl[u][k] * yd;
         }
       }
     }
@@ -856,15 +880,16 @@ __global__ __launch_bounds__(KTPB) void k_gm_g(const TV *V, TV *T, int64_t n, in
   const TV *ycol = V + (size_t)(j + 1) * ld;
   const int64_t stride = (int64_t)gridDim.x * (R * KTPB);
   int64_t r0 = (int64_t)blockIdx.x * (R * KTPB);
-  double vl[R][RB], yv[R];
+  // column values kept in the stored type and widened where used
+  TV vl[R][RB], yv[R];
   auto load_pass = [&](int64_t rb) {
 #pragma unroll
     for (int u = 0; u < R; ++u) {
       const int64_t i = rb + (int64_t)u * KTPB + t;
       const int64_t ic = i < n ? i : n - 1;
 #pragma unroll
-      for (int k = 0; k < RB; ++k) vl[u][k] = (k <= j) ? (double)V[(size_t)k * ld + ic] : 0.0;
-      yv[u] = (double)ycol[ic];
+      for (int k = 0; k < RB; ++k) vl[u][k] = slot_load(V, ld, ic, k, j + 1);
+      yv[u] = ycol[ic];
     }
   };
   load_pass(r0);
@@ -904,7 +929,7 @@ __global__ __launch_bounds__(KTPB) void k_gm_g(const TV *V, TV *T, int64_t n, in
 #pragma unroll
   for (int l = 0; l < RB; ++l) acc[l] = 0.0;
 #pragma unroll 1
-  while (r0 < n) {
+  for (; r0 < n;) {
     // compiler barrier: re-read the LDS coefficients per row instead of holding all of
     // them in registers next to the column values and the partial dots
     __asm__ volatile("" ::: "memory");
@@ -912,18 +937,19 @@ __global__ __launch_bounds__(KTPB) void k_gm_g(const TV *V, TV *T, int64_t n, in
     for (int u = 0; u < R; ++u) {
       const int64_t i = r0 + (int64_t)u * KTPB + t;
       if (i < n) {
-        double w = vsj * yv[u];
+        double w = vsj * (double)yv[u];
 #pragma unroll
-        for (int k = 0; k < RB; ++k) w -= coef[k] * vl[u][k];
+        for (int k = 0; k < RB; ++k) w -= coef[k] * (double)vl[u][k];
         const TV ws = (TV)w;
         T[i] = ws;
         const double wd = (double)ws;
 #pragma unroll
-        for (int k = 0; k < RB; ++k) acc[k] += vl[u][k] * wd;
+        for (int k = 0; k < RB; ++k) acc[k] += (double)vl[u][k] * wd;
       }
     }
     r0 += stride;
-    if (r0 < n) load_pass(r0);
+    if (r0 >= n) break;
+    load_pass(r0);
   }
   kstore<RB>(acc, j + 1, red, Pout + (size_t)blockIdx.x * KW);
 }
