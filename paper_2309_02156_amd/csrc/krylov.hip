@@ -972,9 +972,17 @@ __global__ __launch_bounds__(KTPB) void k_gm_close(const double *Pin, int nblk, 
   gm_close_block(j, sqrt(outv[0]), s_ibase + j + 1, &ci, ctl, true);
 }
 
+// lane i's value of v, in every lane (i uniform)
+__device__ inline double lane_bcast(double v, int i) {
+  const int lo = __builtin_amdgcn_readlane((int)dlo(v), i), hi = __builtin_amdgcn_readlane((int)dhi(v), i);
+  return dmake((unsigned)lo, (unsigned)hi);
+}
+
 // End of a cycle: every block solves R y = gam (m x m upper triangular, staged in
-// LDS) and adds x += sum_l y_l v_l for its rows.
-template <typename TV, int RB>
+// LDS) and adds x += sum_l y_l v_l for its rows.  The block's column values are
+// requested before the triangular solve, which runs while they arrive; R = row tiles
+// per pass.
+template <typename TV, int RB, int R>
 __global__ __launch_bounds__(KTPB) void k_gm_update(TV *x, const TV *V, int64_t n, int64_t ld, const Ctl *ctl) {
   const int LD = MAXR + 1;
   __shared__ double coef[RB];
@@ -982,44 +990,65 @@ __global__ __launch_bounds__(KTPB) void k_gm_update(TV *x, const TV *V, int64_t 
   __shared__ double gs[RB];
   __shared__ int s_m;
   __shared__ double vsh[RB];
-  if (threadIdx.x == 0) {
+  const int t = threadIdx.x;
+  if (t == 0) {
     const int st = ctl->state, je = ctl->jend;
     s_m = (st == ST_RUN) ? je : -1;
   }
   // stage the whole triangle, right-hand side and scales at once (unused entries are
   // never read)
-  for (int e = threadIdx.x; e < RB * RB; e += blockDim.x) {
+  for (int e = t; e < RB * RB; e += blockDim.x) {
     const int i = e % RB, l = e / RB;
     Rs[i + l * RB] = (i <= l) ? ctl->R[i + l * LD] : 0.0;
   }
-  if (threadIdx.x < RB) {
-    gs[threadIdx.x] = ctl->gam[threadIdx.x];
-    vsh[threadIdx.x] = ctl->vs[threadIdx.x];
+  if (t < RB) {
+    gs[t] = ctl->gam[t];
+    vsh[t] = ctl->vs[t];
   }
   __syncthreads();
   const int m = s_m;
-  if (m < 0) return;
+  if (m <= 0) return;
+  const int64_t stride = (int64_t)gridDim.x * (R * KTPB);
+  int64_t r0 = (int64_t)blockIdx.x * (R * KTPB);
+  TV vl[R][RB], xv[R];
+  auto load_pass = [&](int64_t rb) {
+#pragma unroll
+    for (int u = 0; u < R; ++u) {
+      const int64_t i = rb + (int64_t)u * KTPB + t;
+      const int64_t ic = i < n ? i : n - 1;
+#pragma unroll
+      for (int l = 0; l < RB; ++l) vl[u][l] = slot_load(V, ld, ic, l, m);
+      xv[u] = x[ic];
+    }
+  };
+  load_pass(r0);
   // R y = gam by columns on one wave: lane l keeps the right-hand side entry l
-  if (threadIdx.x < WAVE) {
-    const int l = threadIdx.x;
+  if (t < WAVE) {
+    const int l = t;
     double g = (l < m) ? gs[l] : 0.0;
     for (int i = m - 1; i >= 0; --i) {
-      const double yi = __shfl(g, i, WAVE) / Rs[i + i * RB];
+      const double yi = lane_bcast(g, i) / Rs[i + i * RB];
       if (l < i) g -= Rs[l + i * RB] * yi;
       if (l == i) coef[i] = yi * vsh[i];
     }
     if (l >= m && l < RB) coef[l] = 0.0;
   }
   __syncthreads();
-  if (m == 0) return;
-  KROWS(i, n) {
-    double s = (double)x[i];
+#pragma unroll 1
+  for (; r0 < n;) {
 #pragma unroll
-    for (int l = 0; l < RB; ++l) {
-      const double v = (double)V[(size_t)(l < m ? l : m - 1) * ld + i];
-      s += (l < m) ? coef[l] * v : 0.0;
+    for (int u = 0; u < R; ++u) {
+      const int64_t i = r0 + (int64_t)u * KTPB + t;
+      if (i < n) {
+        double s = (double)xv[u];
+#pragma unroll
+        for (int l = 0; l < RB; ++l) s += coef[l] * (double)vl[u][l];
+        x[i] = (TV)s;
+      }
     }
-    x[i] = (TV)s;
+    r0 += stride;
+    if (r0 >= n) break;
+    load_pass(r0);
   }
 }
 
@@ -1119,15 +1148,23 @@ hipError_t launch_gm_finish(const CsrView &A, TV *V, TV *T, int64_t ld, int m, d
   return hipGetLastError();
 }
 
+template <typename TV, int RB>
+static void gm_update_rb(TV *x, const TV *V, int64_t n, int64_t ld, Ctl *ctl, hipStream_t st) {
+  const int nb = kblocks(n);
+  if (gm_two_rows(n))
+    hipLaunchKernelGGL((k_gm_update<TV, RB, 2>), dim3(nb), dim3(KTPB), 0, st, x, V, n, ld, ctl);
+  else
+    hipLaunchKernelGGL((k_gm_update<TV, RB, 1>), dim3(nb), dim3(KTPB), 0, st, x, V, n, ld, ctl);
+}
+
 template <typename TV>
 hipError_t launch_gm_update(TV *x, const TV *V, int64_t n, int64_t ld, int restart, Ctl *ctl, hipStream_t st) {
-  const int nb = kblocks(n);
   if (restart <= 8)
-    hipLaunchKernelGGL((k_gm_update<TV, 8>), dim3(nb), dim3(KTPB), 0, st, x, V, n, ld, ctl);
+    gm_update_rb<TV, 8>(x, V, n, ld, ctl, st);
   else if (restart <= 16)
-    hipLaunchKernelGGL((k_gm_update<TV, 16>), dim3(nb), dim3(KTPB), 0, st, x, V, n, ld, ctl);
+    gm_update_rb<TV, 16>(x, V, n, ld, ctl, st);
   else
-    hipLaunchKernelGGL((k_gm_update<TV, 32>), dim3(nb), dim3(KTPB), 0, st, x, V, n, ld, ctl);
+    gm_update_rb<TV, 32>(x, V, n, ld, ctl, st);
   return hipGetLastError();
 }
 
