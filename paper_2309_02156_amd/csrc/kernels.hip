@@ -136,63 +136,32 @@ hipError_t launch_push(const double *x, TX *X, double *SX, int64_t n, int64_t ld
 // One workgroup.  Householder QR with column pivoting (largest remaining column norm,
 // recomputed exactly at every step; ties pick the lowest index) of Y = SX[:, 0:cnt],
 // diag(R) >= 0, rank k = leading count of |R_jj| > tau |R_11|, T1 = P R11^-1.
-// Finish of the push (the sketch of the newest column from the push blocks' partial
-// rows) and the QR with column pivoting of the sketched history.  One block of TPB
-// threads: the partial rows are reduced by all waves in one trip to memory (each wave
-// owns every NWAVE-th sketch row, each lane a strided set of push blocks, then a
-// fixed-order wave reduction); the factorization runs on wave 0 alone (no block
-// barriers): lane l owns rows l, l + 64, ..., column norms and Householder products of
-// all remaining columns are reduced together (wave_sum_multi), pivots are the largest
-// remaining exact column norm, lowest index on ties.
-template <int MC>
 __global__ __launch_bounds__(TPB) void k_qrcp(double *SX, int s, int cnt, int newest, double tau,
                                               const double *partials, int nbx, Ctl *ctl) {
   extern __shared__ double sh[];
-  double *Y = sh;                     // s x cnt, ld s
+  double *Y = sh;                  // s x cnt, ld s
   double *Ri = sh + (size_t)s * cnt;  // cnt x cnt inverse, ld cnt
-  __shared__ double nrm[MAXM], dsh[MAXM];
+  __shared__ double nrm[MAXM];
   __shared__ double v[MAXS];
+  __shared__ double scratch[TPB];
   __shared__ int perm[MAXM];
-  __shared__ int s_bad, s_newest_bad;
+  __shared__ int s_piv, s_bad, s_newest_bad, s_k;
+  __shared__ double s_tauh;
   const int tid = threadIdx.x, lane = tid % WAVE, wid = tid / WAVE;
-  constexpr int STEP = WAVE / MC;  // lanes per reduced entry
   if (tid == 0) {
     s_bad = 0;
     s_newest_bad = 0;
   }
-  // ---- finish the push: v[r] = sum over push blocks of the sketch partials
-  {
-    constexpr int PK = MC > 32 ? 32 : MC;     // entries reduced together
-    constexpr int PSTEP = WAVE / PK;
-    const int per = (s + NWAVE - 1) / NWAVE;  // sketch rows of this wave: r = wid + NWAVE e
-    for (int e0 = 0; e0 < per; e0 += PK) {
-      double a[PK];
-#pragma unroll
-      for (int e = 0; e < PK; ++e) a[e] = 0.0;
-      // one slice of 64 push blocks at a time, the loads of all entries issued together
-      for (int b = lane; b - lane < nbx; b += WAVE) {
-        double t[PK];
-#pragma unroll
-        for (int e = 0; e < PK; ++e) {
-          const int r = wid + NWAVE * (e0 + e);
-          const int rc = r < s ? r : s - 1;
-          const int bc = b < nbx ? b : nbx - 1;
-          t[e] = partials[((size_t)(rc / SKETCH_RG) * nbx + bc) * SKETCH_RG + rc % SKETCH_RG];
-        }
-#pragma unroll
-        for (int e = 0; e < PK; ++e) {
-          const int r = wid + NWAVE * (e0 + e);
-          if (r < s && b < nbx) a[e] += t[e];
-        }
-      }
-      wave_sum_multi<PK>(a);
-      const int e = lane / PSTEP, r = wid + NWAVE * (e0 + e);
-      if (lane % PSTEP == 0 && r < s) v[r] = a[0];
-    }
+  // finish the push: SX[:, newest] = (sum over push blocks of the sketch partials) / sqrt(s)
+  const int ng = (s + SKETCH_RG - 1) / SKETCH_RG;
+  for (int g = 0; g < ng; ++g) {
+    const int r0 = g * SKETCH_RG;
+    const int rc = (s - r0) < SKETCH_RG ? (s - r0) : SKETCH_RG;
+    final_sum(partials + (size_t)g * nbx * SKETCH_RG, nbx, SKETCH_RG, rc, v + r0, scratch);
   }
-  __syncthreads();
   const double inv = 1.0 / sqrt((double)s);
   for (int r = tid; r < s; r += blockDim.x) SX[(size_t)newest * s + r] = v[r] * inv;
+  __syncthreads();
   for (int e = tid; e < s * cnt; e += blockDim.x) {
     double y = (e / s == newest) ? v[e % s] * inv : SX[e];
     Y[e] = y;
@@ -214,105 +183,94 @@ __global__ __launch_bounds__(TPB) void k_qrcp(double *SX, int s, int cnt, int ne
     }
     return;
   }
-  if (wid != 0) return;
-  // ---- QR with column pivoting on wave 0 (from here on no block barrier)
-  const int l = lane;
   int jj = 0;
   for (; jj < cnt; ++jj) {
     // exact column norms over rows jj..s-1 of the remaining columns
-    double a[MC];
-#pragma unroll
-    for (int c = 0; c < MC; ++c) {
-      double acc = 0.0;
-      if (c >= jj && c < cnt)
-        for (int r = l; r < s; r += WAVE)
-          if (r >= jj) {
-            const double y = Y[(size_t)c * s + r];
-            acc += y * y;
-          }
-      a[c] = acc;
+    for (int c = jj + wid; c < cnt; c += NWAVE) {
+      double a = 0.0;
+      for (int r = jj + lane; r < s; r += WAVE) {
+        double y = Y[(size_t)c * s + r];
+        a += y * y;
+      }
+      a = wave_sum(a);
+      if (lane == 0) nrm[c] = a;
     }
-    wave_sum_multi<MC>(a);
-    if (l % STEP == 0 && l / STEP < cnt) nrm[l / STEP] = a[0];
-    __builtin_amdgcn_wave_barrier();
-    int p = jj;
-    for (int c = jj + 1; c < cnt; ++c)
-      if (nrm[c] > nrm[p]) p = c;
-    if (l == 0 && p != jj) {
-      const int t = perm[jj];
+    __syncthreads();
+    if (tid == 0) {
+      int p = jj;
+      for (int c = jj + 1; c < cnt; ++c)
+        if (nrm[c] > nrm[p]) p = c;
+      s_piv = p;
+      int t = perm[jj];
       perm[jj] = perm[p];
       perm[p] = t;
     }
+    __syncthreads();
+    const int p = s_piv;
     if (p != jj)
-      for (int r = l; r < s; r += WAVE) {
-        const double t = Y[(size_t)jj * s + r];
+      for (int r = tid; r < s; r += blockDim.x) {
+        double t = Y[(size_t)jj * s + r];
         Y[(size_t)jj * s + r] = Y[(size_t)p * s + r];
         Y[(size_t)p * s + r] = t;
       }
-    __builtin_amdgcn_wave_barrier();
+    __syncthreads();
     const double alpha = sqrt(nrm[p]);
     const double x0 = Y[(size_t)jj * s + jj];
     if (alpha == 0.0) {
       // the rest is zero: R_jj = 0 onward
-      for (int c = jj + l; c < cnt; c += WAVE) Y[(size_t)c * s + c] = 0.0;
-      __builtin_amdgcn_wave_barrier();
+      for (int c = jj + tid; c < cnt; c += blockDim.x) Y[(size_t)c * s + c] = 0.0;
+      __syncthreads();
       break;
     }
     const double beta = x0 >= 0.0 ? -alpha : alpha;  // R_jj (sign fixed below)
     const double v0 = x0 - beta;
-    const double tauh = 2.0 / (v0 * v0 + (alpha * alpha - x0 * x0));
-    for (int r = l; r < s; r += WAVE)
-      if (r >= jj) v[r] = (r == jj) ? v0 : Y[(size_t)jj * s + r];
-    __builtin_amdgcn_wave_barrier();
-    // d_c = tauh v^T Y[:, c] for the columns right of jj, then Y[:, c] -= d_c v
-#pragma unroll
-    for (int c = 0; c < MC; ++c) {
-      double acc = 0.0;
-      if (c > jj && c < cnt)
-        for (int r = l; r < s; r += WAVE)
-          if (r >= jj) acc += v[r] * Y[(size_t)c * s + r];
-      a[c] = acc;
+    for (int r = jj + tid; r < s; r += blockDim.x) v[r] = (r == jj) ? v0 : Y[(size_t)jj * s + r];
+    if (tid == 0) s_tauh = 2.0 / (v0 * v0 + (alpha * alpha - x0 * x0));
+    __syncthreads();
+    const double tauh = s_tauh;
+    for (int c = jj + 1 + wid; c < cnt; c += NWAVE) {
+      double d = 0.0;
+      for (int r = jj + lane; r < s; r += WAVE) d += v[r] * Y[(size_t)c * s + r];
+      d = wave_sum(d) * tauh;
+      for (int r = jj + lane; r < s; r += WAVE) Y[(size_t)c * s + r] -= d * v[r];
     }
-    wave_sum_multi<MC>(a);
-    if (l % STEP == 0 && l / STEP < cnt) dsh[l / STEP] = a[0] * tauh;
-    __builtin_amdgcn_wave_barrier();
-    for (int c = jj + 1; c < cnt; ++c) {
-      const double d = dsh[c];
-      for (int r = l; r < s; r += WAVE)
-        if (r >= jj) Y[(size_t)c * s + r] -= d * v[r];
-    }
-    if (l == 0) Y[(size_t)jj * s + jj] = beta;
-    __builtin_amdgcn_wave_barrier();
+    if (tid == 0) Y[(size_t)jj * s + jj] = beta;
+    __syncthreads();
   }
   // sign convention diag(R) >= 0: negate rows with a negative diagonal
-  for (int r = 0; r < cnt; ++r) {
+  for (int r = wid; r < cnt; r += NWAVE) {
     const bool neg = Y[(size_t)r * s + r] < 0.0;
-    __builtin_amdgcn_wave_barrier();
     if (neg)
-      for (int c = r + l; c < cnt; c += WAVE) Y[(size_t)c * s + r] = -Y[(size_t)c * s + r];
-    __builtin_amdgcn_wave_barrier();
+      for (int c = r + lane; c < cnt; c += WAVE) Y[(size_t)c * s + r] = -Y[(size_t)c * s + r];
   }
-  const double r00 = fabs(Y[0]);
-  int k = 0;
-  if (r00 > 0.0)
-    while (k < cnt && fabs(Y[(size_t)k * s + k]) > tau * r00) ++k;
-  // R11^-1, one column per lane (upper triangular back substitution)
-  for (int c = l; c < k; c += WAVE) {
+  __syncthreads();
+  if (tid == 0) {
+    const double r00 = fabs(Y[0]);
+    int k = 0;
+    if (r00 > 0.0)
+      while (k < cnt && fabs(Y[(size_t)k * s + k]) > tau * r00) ++k;
+    s_k = k;
+  }
+  __syncthreads();
+  const int k = s_k;
+  // R11^-1, one column per thread (upper triangular back substitution)
+  for (int c = tid; c < k; c += blockDim.x) {
     for (int i = 0; i < k; ++i) Ri[i + c * k] = 0.0;
     Ri[c + c * k] = 1.0 / Y[(size_t)c * s + c];
     for (int i = c - 1; i >= 0; --i) {
       double acc = 0.0;
-      for (int m2 = i + 1; m2 <= c; ++m2) acc += Y[(size_t)m2 * s + i] * Ri[m2 + c * k];
+      for (int l = i + 1; l <= c; ++l) acc += Y[(size_t)l * s + i] * Ri[l + c * k];
       Ri[i + c * k] = -acc / Y[(size_t)i * s + i];
     }
   }
-  __builtin_amdgcn_wave_barrier();
-  for (int e = l; e < MAXM * MAXM; e += WAVE) ctl->T1[e] = 0.0;
-  for (int e = l; e < k * k; e += WAVE) {
+  __syncthreads();
+  for (int e = tid; e < MAXM * MAXM; e += blockDim.x) ctl->T1[e] = 0.0;
+  __syncthreads();
+  for (int e = tid; e < k * k; e += blockDim.x) {
     const int i = e % k, c = e / k;
     if (i <= c) ctl->T1[perm[i] + c * MAXM] = Ri[i + c * k];
   }
-  if (l == 0) {
+  if (tid == 0) {
     ctl->k = k;
     ctl->nonfinite = 0;
   }
@@ -321,13 +279,8 @@ __global__ __launch_bounds__(TPB) void k_qrcp(double *SX, int s, int cnt, int ne
 hipError_t launch_qrcp(double *SX, int s, int cnt, int newest, double tau, const double *partials, int64_t n,
                        Ctl *ctl, hipStream_t st) {
   size_t lds = ((size_t)s * cnt + (size_t)cnt * cnt) * sizeof(double);
-  const int nbx = push_blocks_x(n, s);
-  if (cnt <= 16)
-    hipLaunchKernelGGL(k_qrcp<16>, dim3(1), dim3(TPB), lds, st, SX, s, cnt, newest, tau, partials, nbx, ctl);
-  else if (cnt <= 32)
-    hipLaunchKernelGGL(k_qrcp<32>, dim3(1), dim3(TPB), lds, st, SX, s, cnt, newest, tau, partials, nbx, ctl);
-  else
-    hipLaunchKernelGGL(k_qrcp<64>, dim3(1), dim3(TPB), lds, st, SX, s, cnt, newest, tau, partials, nbx, ctl);
+  hipLaunchKernelGGL(k_qrcp, dim3(1), dim3(TPB), lds, st, SX, s, cnt, newest, tau, partials, push_blocks_x(n, s),
+                     ctl);
   return hipGetLastError();
 }
 
@@ -401,13 +354,42 @@ __global__ __launch_bounds__(GRAM_TPB) void k_spmm_gram(const int *rowptr, const
 #pragma unroll
     for (int c = 0; c < MC; ++c) w[c] = 0.0;
     if (i < n) {
+      // nonzeros in groups of NZ (their columns and values loaded together), the basis
+      // columns in chunks of CC: every gather of a chunk is issued before the first is
+      // used (slots past the row's nonzeros or past k re-read a live entry, weight 0)
+      constexpr int NZ = 6, CC = 4;
       const int p0 = rowptr[i], p1 = rowptr[i + 1];
-      for (int p = p0; p < p1; ++p) {
-        const double av = (double)val[p];
-        const int64_t jc = col[p];
+      for (int pb = p0; pb < p1; pb += NZ) {
+        int cj[NZ];
+        double av[NZ];
 #pragma unroll
-        for (int c = 0; c < MC; ++c)
-          if (c < k) w[c] += av * (double)Q1[(size_t)c * ld + jc];
+        for (int u = 0; u < NZ; ++u) {
+          const int p = pb + u;
+          const int pc = p < p1 ? p : p1 - 1;
+          cj[u] = col[pc];
+          const double a = (double)val[pc];
+          av[u] = p < p1 ? a : 0.0;
+        }
+#pragma unroll
+        for (int c0 = 0; c0 < MC; c0 += CC) {
+          if (c0 < k) {
+            double gq[NZ][CC];
+#pragma unroll
+            for (int u = 0; u < NZ; ++u)
+#pragma unroll
+              for (int cc = 0; cc < CC; ++cc) {
+                const int c = c0 + cc < k ? c0 + cc : k - 1;
+                gq[u][cc] = (double)Q1[(size_t)c * ld + cj[u]];
+              }
+#pragma unroll
+            for (int cc = 0; cc < CC; ++cc) {
+              double acc = 0.0;
+#pragma unroll
+              for (int u = 0; u < NZ; ++u) acc += av[u] * gq[u][cc];
+              if (c0 + cc < k) w[c0 + cc] += acc;
+            }
+          }
+        }
       }
     }
 #pragma unroll
