@@ -55,10 +55,7 @@ def run_sequence(sacc, torch, A, vals_d, rhs_d, method, steps, warmup, guess="pr
 
     def step(i):
         A.val.copy_(vals_d[i])
-        b = rhs_d[i]
-        seq.initial_guess(A, b, x, info=False)
-        _, inf = seq.solve(A, b, x)
-        seq.push(x)
+        _, inf = seq.step(A, rhs_d[i], x)
         return inf
 
     for i in range(warmup):

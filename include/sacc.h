@@ -145,8 +145,8 @@ int sa_init_sequence(const sa_config *cfg, void *dev_ws, size_t ws_bytes, void *
 int sa_push_solution(sa_seq *q, const void *x_dev, void *stream);
 
 /* Initial guess of Alg. 1 for the system (A, b): basis Q of span(history) from the
- * sketched QR (Alg. 1 (basis), Section 2.2), reduced problem (Alg. 1 (reduced problem); Galerkin
- * or minimum residual per the config) and x0 = Q y.  Empty history gives x0 = 0.
+ * sketched QR (the basis of Alg. 1, Section 2.2), reduced problem (the reduced problem
+ * of Alg. 1; Galerkin or minimum residual per the config) and x0 = Q y.  Empty history gives x0 = 0.
  * b_dev, x0_dev: float64, length n.  Asynchronous; if info is non-NULL the call waits
  * for the stream and fills k_eff, k_sketch, history, used_fallback, ms_guess.
  * Errors: SA_EINVAL (shape mismatch), SA_EHIP. */
@@ -165,6 +165,14 @@ int sa_initial_guess(sa_seq *q, const sa_csr *A, const void *b_dev, void *x0_dev
  * relres0, relres, status, ms_solve).  Returns SA_OK, SA_NOTCONV or an error code. */
 int sa_solve(sa_seq *q, const sa_csr *A, const void *b_dev, void *x_dev, sa_info *info,
              void *stream);
+
+/* One step of Alg. 1 for the system (A, b): initial guess into x_dev, solve from it,
+ * push of the solution, in one call (the same work as sa_initial_guess, sa_solve and
+ * sa_push_solution in turn, without waiting for the stream between them).  x_dev:
+ * float64, length n, out = x.  Fills info if non-NULL (the fields of both calls).
+ * The solution is pushed also when the solve reports SA_NOTCONV or SA_EBREAKDOWN.
+ * Returns the solve's status, or the first error. */
+int sa_step(sa_seq *q, const sa_csr *A, const void *b_dev, void *x_dev, sa_info *info, void *stream);
 
 /* Release the sequence's host state and control blocks (not the workspace). */
 int sa_destroy_sequence(sa_seq *q);

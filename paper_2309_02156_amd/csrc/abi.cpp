@@ -54,7 +54,9 @@ struct sa_seq {
   long long *srht_rows = nullptr;
   Ctl *ctl = nullptr;     // device control block (projection + outer solve)
   Ctl *ctl_in = nullptr;  // device control block of the inner solves (mixed)
-  int *hbuf = nullptr;    // pinned host mirror of solver state
+  int *hbuf = nullptr;    // pinned host mirror of solver state (128 ints; from int 64 on the
+                          // snapshot of the last poll: norms, then the state words)
+  const Ctl *snap_ctl = nullptr;  // control block of that snapshot
   unsigned long long *mir[2] = {nullptr, nullptr};  // progress words of ctl and ctl_in (pinned)
   long long pushes = 0;
   int64_t ld = 0;  // leading dimension of X, Q1 and the Krylov vectors
@@ -200,10 +202,17 @@ CsrView view(const sa_csr *A) {
 
 inline int count(const sa_seq *q) { return (int)(q->pushes < q->cfg.M ? q->pushes : q->cfg.M); }
 
-// solver state mirror of a control block: state, iters, restarts, maxit, active, jend
+// solver state of a control block, read after all enqueued work: one copy of the norms
+// (bnorm, relres0, relres, tol) and the state words that follow them (state, iters,
+// restarts, maxit, active, jend, restart, pad0); the state words land in hbuf[0..7]
+static_assert(offsetof(Ctl, state) == offsetof(Ctl, bnorm) + 4 * sizeof(double), "norms then state words");
+inline double *snapshot(sa_seq *q) { return (double *)(q->hbuf + 64); }
 int poll(sa_seq *q, Ctl *ctl, hipStream_t st) {
-  HIP_TRY(hipMemcpyAsync(q->hbuf, &ctl->state, 8 * sizeof(int), hipMemcpyDeviceToHost, st));
+  double *snap = snapshot(q);
+  HIP_TRY(hipMemcpyAsync(snap, &ctl->bnorm, 4 * sizeof(double) + 8 * sizeof(int), hipMemcpyDeviceToHost, st));
   HIP_TRY(hipStreamSynchronize(st));
+  memcpy(q->hbuf, snap + 4, 8 * sizeof(int));
+  q->snap_ctl = ctl;
   return SA_OK;
 }
 
@@ -544,7 +553,7 @@ int sa_init_sequence(const sa_config *cfg, void *dev_ws, size_t ws_bytes, void *
     q->r32 = (float *)(q->ws + L.r32);
     q->d32 = (float *)(q->ws + L.d32);
   }
-  bool ok = hipHostMalloc((void **)&q->hbuf, 64 * sizeof(int), hipHostMallocDefault) == hipSuccess;
+  bool ok = hipHostMalloc((void **)&q->hbuf, 128 * sizeof(int), hipHostMallocDefault) == hipSuccess;
   for (int e = 0; ok && e < 4; ++e) ok = hipEventCreate(&q->ev[e]) == hipSuccess;
   if (ok) ok = init_ctl(&q->ctl, &q->mir[0], cfg->tol, cfg->maxit, cfg->restart, 0, st) == SA_OK;
   if (ok && q->mixed)
@@ -596,16 +605,23 @@ int sa_push_solution(sa_seq *q, const void *x_dev, void *stream) {
   return SA_OK;
 }
 
-int sa_initial_guess(sa_seq *q, const sa_csr *A, const void *b_dev, void *x0_dev, sa_info *info, void *stream) {
-  if (!q || !q->alive) return SA_ESTATE;
+}  // extern "C"
+
+namespace {
+
+// Enqueues the initial guess of the next step into x0; with `want_info` also its timing
+// events and copies of the basis ranks and the learned decision into hbuf[16..20]
+// (read by guess_info after the stream has synchronized).  *cnt = history columns used.
+int guess_enqueue(sa_seq *q, const sa_csr *A, const void *b_dev, void *x0_dev, bool want_info, hipStream_t st,
+                  int *cnt_out) {
   int rc = check_csr(q, A);
   if (rc != SA_OK) return rc;
   if (!b_dev || !x0_dev) return SA_EINVAL;
-  hipStream_t st = (hipStream_t)stream;
   const sa_config &c = q->cfg;
   const int cnt = count(q);
+  *cnt_out = cnt;
   const size_t nb = (size_t)c.n * sizeof(double);
-  if (info) HIP_TRY(hipEventRecord(q->ev[0], st));
+  if (want_info) HIP_TRY(hipEventRecord(q->ev[0], st));
   const int newest = cnt > 0 ? (int)((q->pushes - 1) % c.M) : -1;
   if (cnt == 0 || c.guess == SA_GUESS_ZERO) {
     HIP_TRY(hipMemsetAsync(x0_dev, 0, nb, st));
@@ -623,25 +639,41 @@ int sa_initial_guess(sa_seq *q, const sa_csr *A, const void *b_dev, void *x0_dev
       SA_TRY(guess_projection<double>(q, v, (const double *)b_dev, (double *)x0_dev, cnt, st));
     if (q->mlp && q->ltargets >= q->lhist) SA_TRY(guess_learned(q, v, (const double *)b_dev, (double *)x0_dev, cnt, st));
   }
-  if (info) {
+  if (want_info) {
     HIP_TRY(hipEventRecord(q->ev[1], st));
     HIP_TRY(hipMemcpyAsync(q->hbuf + 16, &q->ctl->k, 4 * sizeof(int), hipMemcpyDeviceToHost, st));
+    HIP_TRY(hipMemcpyAsync(q->hbuf + 20, &q->ctl->learned_used, sizeof(int), hipMemcpyDeviceToHost, st));
+  }
+  return SA_OK;
+}
+
+// the guess fields of info, after the stream has synchronized past guess_enqueue
+int guess_info(sa_seq *q, int cnt, sa_info *info) {
+  const sa_config &c = q->cfg;
+  float ms = 0.f;
+  HIP_TRY(hipEventElapsedTime(&ms, q->ev[0], q->ev[1]));
+  const bool proj = cnt > 0 && c.guess == SA_GUESS_PROJECTION;
+  info->k_sketch = proj ? q->hbuf[16] : 0;
+  info->k_eff = proj ? q->hbuf[17] : 0;
+  info->used_fallback = proj ? q->hbuf[18] : 0;
+  info->history = cnt;
+  info->used_learned = (q->mlp && proj && q->ltargets >= q->lhist) ? q->hbuf[20] : 0;
+  info->ms_guess = ms;
+  return SA_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int sa_initial_guess(sa_seq *q, const sa_csr *A, const void *b_dev, void *x0_dev, sa_info *info, void *stream) {
+  if (!q || !q->alive) return SA_ESTATE;
+  hipStream_t st = (hipStream_t)stream;
+  int cnt = 0;
+  SA_TRY(guess_enqueue(q, A, b_dev, x0_dev, info != nullptr, st, &cnt));
+  if (info) {
     HIP_TRY(hipStreamSynchronize(st));
-    float ms = 0.f;
-    HIP_TRY(hipEventElapsedTime(&ms, q->ev[0], q->ev[1]));
-    const bool proj = cnt > 0 && c.guess == SA_GUESS_PROJECTION;
-    info->k_sketch = proj ? q->hbuf[16] : 0;
-    info->k_eff = proj ? q->hbuf[17] : 0;
-    info->used_fallback = proj ? q->hbuf[18] : 0;
-    info->history = cnt;
-    info->used_learned = 0;
-    if (q->mlp && proj && q->ltargets >= q->lhist) {
-      int used = 0;
-      HIP_TRY(hipMemcpyAsync(&used, &q->ctl->learned_used, sizeof(int), hipMemcpyDeviceToHost, st));
-      HIP_TRY(hipStreamSynchronize(st));
-      info->used_learned = used;
-    }
-    info->ms_guess = ms;
+    SA_TRY(guess_info(q, cnt, info));
   }
   return SA_OK;
 }
@@ -704,6 +736,7 @@ int sa_solve(sa_seq *q, const sa_csr *A, const void *b_dev, void *x_dev, sa_info
   double *x = (double *)x_dev;
   if (info) HIP_TRY(hipEventRecord(q->ev[2], st));
   int *hs = q->hbuf;
+  q->snap_ctl = nullptr;
   int iters = 0, restarts = 0, sweeps = 0;
   if (q->mixed) {
     SA_TRY(solve_mixed(q, v, b, x, &iters, &restarts, &sweeps, st));
@@ -719,7 +752,13 @@ int sa_solve(sa_seq *q, const sa_csr *A, const void *b_dev, void *x_dev, sa_info
   if (info) {
     HIP_TRY(hipEventRecord(q->ev[3], st));
     double d[4];  // bnorm, relres0, relres, tol
-    SA_TRY(read_norms(q, q->ctl, d, st));
+    if (q->snap_ctl == q->ctl) {
+      // the solve ended with a poll of this control block: its norms are final
+      memcpy(d, snapshot(q), sizeof(d));
+      HIP_TRY(hipEventSynchronize(q->ev[3]));
+    } else {
+      SA_TRY(read_norms(q, q->ctl, d, st));
+    }
     float ms = 0.f;
     HIP_TRY(hipEventElapsedTime(&ms, q->ev[2], q->ev[3]));
     info->iters = iters;
@@ -731,6 +770,19 @@ int sa_solve(sa_seq *q, const sa_csr *A, const void *b_dev, void *x_dev, sa_info
     info->ms_solve = ms;
   }
   return ret;
+}
+
+int sa_step(sa_seq *q, const sa_csr *A, const void *b_dev, void *x_dev, sa_info *info, void *stream) {
+  if (!q || !q->alive) return SA_ESTATE;
+  hipStream_t st = (hipStream_t)stream;
+  int cnt = 0;
+  SA_TRY(guess_enqueue(q, A, b_dev, x_dev, info != nullptr, st, &cnt));
+  // with info the solve returns with the stream synchronized, past the guess's copies
+  const int rs = sa_solve(q, A, b_dev, x_dev, info, st);
+  if (rs != SA_OK && rs != SA_NOTCONV && rs != SA_EBREAKDOWN) return rs;
+  if (info) SA_TRY(guess_info(q, cnt, info));
+  SA_TRY(sa_push_solution(q, x_dev, st));
+  return rs;
 }
 
 int sa_destroy_sequence(sa_seq *q) {

@@ -21,7 +21,7 @@ SA_SKETCH_GAUSSIAN, SA_SKETCH_SRHT = 0, 1
 SA_GUESS_PROJECTION, SA_GUESS_ZERO, SA_GUESS_PREVIOUS = 0, 1, 2
 
 EXPORTS = ("sa_workspace_bytes", "sa_init_sequence", "sa_push_solution", "sa_initial_guess",
-           "sa_solve", "sa_destroy_sequence", "sa_status_string", "sa_spmv", "sa_copy_state",
+           "sa_solve", "sa_step", "sa_destroy_sequence", "sa_status_string", "sa_spmv", "sa_copy_state",
            "sa_profile_enable", "sa_profile_read", "sa_mlp_create", "sa_mlp_destroy", "sa_mlp_set_scaling",
            "sa_mlp_forward", "sa_mlp_train_step", "sa_mlp_get", "sa_learned_attach", "sa_set_time",
            "sa_batch_create", "sa_batch_destroy", "sa_batch_step", "sa_batch_plan")
@@ -95,6 +95,7 @@ def lib() -> ctypes.CDLL:
     L.sa_push_solution.argtypes = [vp, vp, vp]
     L.sa_initial_guess.argtypes = [vp, P(SaCsr), vp, vp, P(SaInfo), vp]
     L.sa_solve.argtypes = [vp, P(SaCsr), vp, vp, P(SaInfo), vp]
+    L.sa_step.argtypes = [vp, P(SaCsr), vp, vp, P(SaInfo), vp]
     L.sa_destroy_sequence.argtypes = [vp]
     L.sa_status_string.argtypes = [i32]
     L.sa_status_string.restype = ctypes.c_char_p

@@ -136,14 +136,19 @@ class Sequence:
         d["rc"] = rc
         return x, d
 
-    def step(self, A: DeviceCSR, b: torch.Tensor, x: Optional[torch.Tensor] = None):
-        """initial guess -> solve -> push; returns (x, merged info)."""
-        x, g = self.initial_guess(A, b, x)
-        x, s = self.solve(A, b, x)
-        self.push(x)
-        for key in ("k_eff", "k_sketch", "used_fallback", "history", "ms_guess", "used_learned"):
-            s[key] = g[key]
-        return x, s
+    def step(self, A: DeviceCSR, b: torch.Tensor, x: Optional[torch.Tensor] = None, info: bool = True,
+             allow=(nv.SA_OK, nv.SA_NOTCONV, nv.SA_EBREAKDOWN)):
+        """initial guess -> solve -> push in one library call (sa_step); returns (x, info)."""
+        if x is None:
+            x = torch.empty_like(b)
+        inf = nv.SaInfo()
+        s = A.c_struct()
+        rc = nv.lib().sa_step(self._h, ctypes.byref(s), _ptr(b), _ptr(x), ctypes.byref(inf) if info else None,
+                              _stream(self.stream))
+        nv.check(rc, "sa_step", allow)
+        d = inf.as_dict() if info else {}
+        d["rc"] = rc
+        return x, d
 
     # ------------------------------------------------------------------ learned guess
     def learned_attach(self, mlp: "MLP", n_hist: int = 8):

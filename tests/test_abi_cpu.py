@@ -70,6 +70,7 @@ def test_null_handles_and_status_strings(nv):
     assert L.sa_push_solution(None, None, None) == nv.SA_ESTATE
     assert L.sa_initial_guess(None, None, None, None, None, None) == nv.SA_ESTATE
     assert L.sa_solve(None, None, None, None, None, None) == nv.SA_ESTATE
+    assert L.sa_step(None, None, None, None, None, None) == nv.SA_ESTATE
     assert L.sa_spmv(None, None, None, None) == nv.SA_EINVAL
     assert L.sa_copy_state(None, 0, None, 0, None) == nv.SA_ESTATE
     for code in (0, 1, -1, -2, -3, -4, -5):
