@@ -90,6 +90,23 @@ inline int stream_blocks(int64_t n) {
 #define GRID_ROWS(i, n) \
   for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < (n); i += (int64_t)gridDim.x * blockDim.x)
 
+// ---------------------------------------------------------------- control-block reads
+// Reads of control-block fields through the vector memory path: the index is a register
+// the compiler cannot prove uniform, so the read is a global load counted with the other
+// vector loads.  A scalar load shares its wait counter with the kernel-argument and LDS
+// traffic, so the first wait for an argument or an LDS result after it would also wait
+// for a control-block read still on its way from memory (one more trip before the
+// kernel's main loads go out).
+__device__ inline int vzero() {
+  int z;
+  asm volatile("v_mov_b32 %0, 0" : "=v"(z));
+  return z;
+}
+template <typename T>
+__device__ inline T vread(const T *p, int z) {
+  return p[z];
+}
+
 // ---------------------------------------------------------------- reductions
 // Cross-lane exchanges without the LDS unit: v_permlane32_swap / v_permlane16_swap
 // (gfx950) for partners 32 and 16 lanes apart, DPP row controls inside a row of 16
@@ -213,39 +230,16 @@ __device__ inline void block_sum_store(double (&v)[K], int kc, double *red, doub
 //
 // Sums over nblk rows of partials[nblk][W] for entries e < kc, in a fixed order
 // (per-thread sums over a strided set of rows, all loads of a thread issued
-// together, then a fixed tree), into LDS out[0..kc).  `scratch` is LDS of blockDim.x
-// doubles; blockDim.x must be a power of two.
+// together, then the fixed tree of final_tree), into LDS out[0..kc), 64 entries at a
+// time.  `scratch` is LDS of blockDim.x doubles; blockDim.x must be a multiple of 64.
+template <int U = 32>
+__device__ inline double final_part(const double *partials, int nblk, int W, int kc);
+__device__ inline void final_tree(double s, int kc, double *out, double *scratch);
 __device__ inline void final_sum(const double *partials, int nblk, int W, int kc, double *out,
                                  double *scratch) {
-  constexpr int U = 32;
   for (int e0 = 0; e0 < kc; e0 += WAVE) {
     const int ec = kc - e0 < WAVE ? kc - e0 : WAVE;
-    int ep = 1;
-    while (ep < ec) ep <<= 1;
-    const int ngrp = blockDim.x / ep;
-    const int e = threadIdx.x % ep, grp = threadIdx.x / ep;
-    double s = 0.0;
-    if (e < ec) {
-      for (int b0 = grp; b0 < nblk; b0 += U * ngrp) {
-        double t[U];
-#pragma unroll
-        for (int u = 0; u < U; ++u) {
-          const int b = b0 + u * ngrp;
-          const double x = partials[(size_t)(b < nblk ? b : nblk - 1) * W + e0 + e];
-          t[u] = b < nblk ? x : 0.0;
-        }
-#pragma unroll
-        for (int u = 0; u < U; ++u) s += t[u];
-      }
-    }
-    scratch[threadIdx.x] = s;
-    __syncthreads();
-    for (int off = ngrp / 2; off > 0; off >>= 1) {
-      if (grp < off) scratch[threadIdx.x] += scratch[threadIdx.x + off * ep];
-      __syncthreads();
-    }
-    if (threadIdx.x < ec) out[e0 + threadIdx.x] = scratch[threadIdx.x];
-    __syncthreads();
+    final_tree(final_part(partials + e0, nblk, W, ec), ec, out + e0, scratch);
   }
 }
 
@@ -254,8 +248,8 @@ __device__ inline void final_sum(const double *partials, int nblk, int W, int kc
 // reads: one trip to memory instead of two).  final_part: this thread's sum over its
 // rows (the same rows and order as final_sum); final_tree: the fixed tree into LDS
 // out[0..kc), identical results to final_sum.
+template <int U>
 __device__ inline double final_part(const double *partials, int nblk, int W, int kc) {
-  constexpr int U = 32;
   int ep = 1;
   while (ep < kc) ep <<= 1;
   const int ngrp = blockDim.x / ep;
@@ -277,18 +271,72 @@ __device__ inline double final_part(const double *partials, int nblk, int W, int
   return s;
 }
 
-__device__ inline void final_tree(double s, int kc, double *out, double *scratch) {
+// final_part in two halves, so that the loads of the partial rows go out with a
+// kernel's other first-trip loads and the sum runs after a barrier: final_part_load
+// issues U rows per thread (every thread, no branch around the loads: entries and rows
+// past the valid ranges re-read valid ones), final_part_sum adds them (masked) and any
+// further rows, in final_part's order and with its result.  U is chosen by the caller
+// from the entry count it expects (nblk <= U * blockDim.x / ep rows in one round).
+template <int U>
+__device__ inline void final_part_load(const double *partials, int nblk, int W, int kc, double (&t)[U]) {
   int ep = 1;
   while (ep < kc) ep <<= 1;
   const int ngrp = blockDim.x / ep;
-  const int grp = threadIdx.x / ep;
-  scratch[threadIdx.x] = s;
-  __syncthreads();
-  for (int off = ngrp / 2; off > 0; off >>= 1) {
-    if (grp < off) scratch[threadIdx.x] += scratch[threadIdx.x + off * ep];
-    __syncthreads();
+  const int e = threadIdx.x % ep, grp = threadIdx.x / ep;
+  const int ec = e < kc ? e : kc - 1;
+#pragma unroll
+  for (int u = 0; u < U; ++u) {
+    const int b = grp + u * ngrp;
+    t[u] = partials[(size_t)(b < nblk ? b : nblk - 1) * W + ec];
   }
-  if (threadIdx.x < kc) out[threadIdx.x] = scratch[threadIdx.x];
+}
+
+template <int U>
+__device__ inline double final_part_sum(const double *partials, int nblk, int W, int kc, const double (&t)[U]) {
+  int ep = 1;
+  while (ep < kc) ep <<= 1;
+  const int ngrp = blockDim.x / ep;
+  const int e = threadIdx.x % ep, grp = threadIdx.x / ep;
+  double s = 0.0;
+  if (e < kc) {
+#pragma unroll
+    for (int u = 0; u < U; ++u) s += (grp + u * ngrp < nblk) ? t[u] : 0.0;
+    for (int b = grp + U * ngrp; b < nblk; b += ngrp) s += partials[(size_t)b * W + e];
+  }
+  return s;
+}
+
+// One folding step of final_tree: v plus the value of the lane D apart in the same
+// entry (lane % ep), for D = 32, 16 (permlane swaps) and 8, 4, 2, 1 (DPP row_ror:D,
+// rotation inside rows of 16).  Applied from D = 32 down to ep, every lane ends with
+// the sum over the lanes of its wave that hold its entry, the same value in each.
+template <int D>
+__device__ inline double tree_fold(double v) {
+  if constexpr (D == 32) return swap_sum<32>(v, v);
+  else if constexpr (D == 16) return swap_sum<16>(v, v);
+  else return v + dpp_partner<0x120 + D>(v);
+}
+
+// Fixed tree over the threads' sums s of entry threadIdx.x % ep (ep = kc rounded up to
+// a power of two, kc <= 64): folded inside each wave, then the waves' sums added in
+// wave order, into LDS out[0..kc).  Called by every thread of the block.
+__device__ inline void final_tree(double s, int kc, double *out, double *scratch) {
+  int ep = 1;
+  while (ep < kc) ep <<= 1;
+  if (ep <= 32) s = tree_fold<32>(s);
+  if (ep <= 16) s = tree_fold<16>(s);
+  if (ep <= 8) s = tree_fold<8>(s);
+  if (ep <= 4) s = tree_fold<4>(s);
+  if (ep <= 2) s = tree_fold<2>(s);
+  if (ep <= 1) s = tree_fold<1>(s);
+  const int lane = threadIdx.x % WAVE, wid = threadIdx.x / WAVE, nw = blockDim.x / WAVE;
+  if (lane < ep) scratch[wid * ep + lane] = s;
+  __syncthreads();
+  if (threadIdx.x < kc) {
+    double a = 0.0;
+    for (int w = 0; w < nw; ++w) a += scratch[w * ep + threadIdx.x];
+    out[threadIdx.x] = a;
+  }
   __syncthreads();
 }
 

@@ -84,20 +84,33 @@ __device__ inline bool block_running(const Ctl *ctl, bool need_active) {
 // accept: the recursive estimate already met the tolerance and the control block
 // trusts it (inner solves of the mixed mode), so the solve ends converged.  Returns
 // the new state; `persist` writes it (one thread of one block).
-__device__ inline int residual_decide(double rho, double bb, int mode, Ctl *ctl, bool persist, bool accept = false) {
-  const int k = mode == 0 ? 0 : ctl->iters;
-  const double bn = mode == 0 ? sqrt(bb) : ctl->bnorm;
+// The control-block fields the decision reads, loaded by the caller (with its other
+// first-trip loads, or by decide_in).
+struct DecideIn {
+  double bnorm, tol;
+  int iters, maxit, restarts;
+};
+
+__device__ inline DecideIn decide_in(const Ctl *ctl, int z) {
+  return DecideIn{vread(&ctl->bnorm, z), vread(&ctl->tol, z), vread(&ctl->iters, z), vread(&ctl->maxit, z),
+                  vread(&ctl->restarts, z)};
+}
+
+__device__ inline int residual_decide(double rho, double bb, int mode, const DecideIn &in, Ctl *ctl, bool persist,
+                                      bool accept = false) {
+  const int k = mode == 0 ? 0 : in.iters;
+  const double bn = mode == 0 ? sqrt(bb) : in.bnorm;
   const double nr = sqrt(rho);
   const double rel = bn > 0.0 ? nr / bn : 0.0;
   int st;
   if (bn == 0.0)
     st = ST_ZERO_RHS;
-  else if (nr <= ctl->tol * bn)
+  else if (nr <= in.tol * bn)
     st = ST_CONV;
   else if (!isfinite(nr))
     st = ST_BREAK;
   else
-    st = (k >= ctl->maxit) ? ST_MAXIT : ST_RUN;
+    st = (k >= in.maxit) ? ST_MAXIT : ST_RUN;
   if (accept && mode == 1 && (st == ST_RUN || st == ST_MAXIT)) st = ST_CONV;
   if (persist) {
     if (mode == 0) {
@@ -108,9 +121,13 @@ __device__ inline int residual_decide(double rho, double bb, int mode, Ctl *ctl,
     }
     ctl->relres = rel;
     if (mode != 2) ctl->state = st;
-    if (mode == 1 && st == ST_RUN) ctl->restarts += 1;
+    if (mode == 1 && st == ST_RUN) ctl->restarts = in.restarts + 1;
   }
   return st;
+}
+
+__device__ inline int residual_decide(double rho, double bb, int mode, Ctl *ctl, bool persist, bool accept = false) {
+  return residual_decide(rho, bb, mode, decide_in(ctl, vzero()), ctl, persist, accept);
 }
 
 // entry e (0..3) of a 4-entry register array without dynamic indexing
@@ -205,7 +222,7 @@ __global__ __launch_bounds__(KTPB) void k_cg_p(const int *rowptr, const int *col
   __shared__ double s_beta, s_tolb, s_rho2;
   // r^T r of the previous iteration (unused when the direction restarts), loaded
   // together with the control block
-  const double part = final_part(Pin, nblk, KW, 1);
+  const double part = final_part<1>(Pin, nblk, KW, 1);
   if (threadIdx.x == 0) {
     // every control-block read of the kernel, issued together
     const int st = ctl->state, it = ctl->iters, fa = ctl->fresh_at, mx = ctl->maxit;
@@ -290,7 +307,7 @@ __global__ __launch_bounds__(KTPB) void k_cg_xr(TV *x, TV *r, const TV *P0, cons
   __shared__ double scratch[KTPB];
   __shared__ int s_k, s_go, s_st;
   __shared__ double s_rho;
-  const double part = final_part(Pin, nblk, KW, 1);  // p^T q, loaded with the control block
+  const double part = final_part<1>(Pin, nblk, KW, 1);  // p^T q, loaded with the control block
   if (threadIdx.x == 0) {
     const int st = ctl->state, k = ctl->kcur;
     double r4[4];
@@ -472,9 +489,10 @@ __device__ inline void close_stage(int j, const Ctl *ctl, CloseIn *ci) {
     ci->cs[t] = ctl->cs[t];
     ci->sn[t] = ctl->sn[t];
   }
+  const int z = vzero();
+  const double gj = vread(&ctl->gnext[j], z), tol = vread(&ctl->tol, z), bn = vread(&ctl->bnorm, z);
+  const int maxit = vread(&ctl->maxit, z), restart = vread(&ctl->restart, z), trust = vread(&ctl->trust_est, z);
   if (t == WAVE) {
-    const double gj = ctl->gnext[j], tol = ctl->tol, bn = ctl->bnorm;
-    const int maxit = ctl->maxit, restart = ctl->restart, trust = ctl->trust_est;
     ci->gj = gj;
     ci->tolb = tol * bn;
     ci->maxit = maxit;
@@ -483,21 +501,30 @@ __device__ inline void close_stage(int j, const Ctl *ctl, CloseIn *ci) {
   }
 }
 
+// lane i's value of v, in every lane (i uniform)
+__device__ inline double lane_bcast(double v, int i) {
+  const int lo = __builtin_amdgcn_readlane((int)dlo(v), i), hi = __builtin_amdgcn_readlane((int)dhi(v), i);
+  return dmake((unsigned)lo, (unsigned)hi);
+}
+
 // Close Arnoldi step j given hn = ||w''_{j+1}|| from the staged inputs: rotate the raw
 // column j, new Givens rotation, rotated right-hand side, cycle-end test.  `it` =
-// global iteration number of step j (1-based).  The scalar recurrence runs on one
-// thread with the carried entry in a register; the rotated column is left in ci->col.
+// global iteration number of step j (1-based).  Run by a whole wave, every lane
+// computing the same scalars: lane l holds entry l of the column and rotation l, and
+// the scalar recurrence reads them with v_readlane (no LDS round trip per rotation).
 // Every block computes the same result; only `persist` (block 0) writes the control
-// block (the rotated column itself is written by the caller).  Returns the cycle-end
-// flag.
-__device__ inline bool gm_close_scalar(int j, double hn, int it, CloseIn *ci, Ctl *ctl, bool persist) {
-  double *col = ci->col;
-  col[j + 1] = hn;
-  double cur = col[0];
+// block, the rotated column included (lanes 0..j; j < 64).  Returns the cycle-end flag.
+__device__ inline bool gm_close_wave(int j, double hn, int it, const CloseIn *ci, Ctl *ctl, bool persist) {
+  const int LD = MAXR + 1;
+  const int lane = threadIdx.x % WAVE;
+  double cv = ci->col[lane <= j ? lane : 0];
+  const double cl = ci->cs[lane < j ? lane : 0], sl = ci->sn[lane < j ? lane : 0];
+  double cur = lane_bcast(cv, 0);
   for (int l = 0; l < j; ++l) {
-    const double nxt = col[l + 1], c = ci->cs[l], s = ci->sn[l];
-    col[l] = c * cur + s * nxt;
+    const double nxt = lane_bcast(cv, l + 1), c = lane_bcast(cl, l), s = lane_bcast(sl, l);
+    const double nl = c * cur + s * nxt;
     cur = -s * cur + c * nxt;
+    cv = lane == l ? nl : cv;
   }
   const double a = cur;
   const double rr = hypot(a, hn);
@@ -506,35 +533,37 @@ __device__ inline bool gm_close_scalar(int j, double hn, int it, CloseIn *ci, Ct
     c = a / rr;
     s = hn / rr;
   }
-  col[j] = rr;
+  cv = lane == j ? rr : cv;
   const double gj = ci->gj;
   const double gam_j = c * gj, gnext = -s * gj;
   const bool est_conv = fabs(gnext) <= ci->tolb;
   const bool end = est_conv || hn == 0.0 || it >= ci->maxit || j + 1 >= ci->restart || !isfinite(gnext);
   if (persist) {
-    ctl->cs[j] = c;
-    ctl->sn[j] = s;
-    ctl->gam[j] = gam_j;
-    ctl->gnext[j + 1] = gnext;
-    ctl->vs[j + 1] = hn > 0.0 ? 1.0 / hn : 0.0;
-    ctl->iters = it;
-    ctl->jend = j + 1;
-    if (end) ctl->active = 0;
-    if (est_conv && ci->trust) ctl->conv_pending = 1;
+    if (lane <= j) ctl->R[lane + j * LD] = cv;
+    if (lane == 0) {
+      ctl->cs[j] = c;
+      ctl->sn[j] = s;
+      ctl->gam[j] = gam_j;
+      ctl->gnext[j + 1] = gnext;
+      ctl->vs[j + 1] = hn > 0.0 ? 1.0 / hn : 0.0;
+      ctl->iters = it;
+      ctl->jend = j + 1;
+      if (end) ctl->active = 0;
+      if (est_conv && ci->trust) ctl->conv_pending = 1;
+    }
   }
   return end;
 }
 
-// gm_close_scalar for a whole block (after close_stage and a barrier): thread 0 runs
-// the recurrence, then the block persists the rotated column.  Returns the cycle-end
-// flag to every thread.
+// gm_close_wave for a whole block (after close_stage and a barrier): wave 0 runs it and
+// persists the rotated column.  Returns the cycle-end flag to every thread.
 __device__ inline bool gm_close_block(int j, double hn, int it, CloseIn *ci, Ctl *ctl, bool persist) {
-  const int LD = MAXR + 1;
   __shared__ int s_endf;
-  if (threadIdx.x == 0) s_endf = gm_close_scalar(j, hn, it, ci, ctl, persist) ? 1 : 0;
+  if (threadIdx.x < WAVE) {
+    const bool end = gm_close_wave(j, hn, it, ci, ctl, persist);
+    if (threadIdx.x == 0) s_endf = end ? 1 : 0;
+  }
   __syncthreads();
-  if (persist)
-    for (int l = threadIdx.x; l <= j; l += blockDim.x) ctl->R[l + j * LD] = ci->col[l];
   return s_endf != 0;
 }
 
@@ -547,12 +576,13 @@ struct PassRows {
 };
 
 template <int R>
-__device__ inline PassRows<R> pass_rows(const int *__restrict__ rowptr, int64_t n, int64_t r0) {
+__device__ inline PassRows<R> pass_rows(const int *__restrict__ rowptr, int64_t n, int64_t r0, int z) {
   const int64_t rs = r0 < n ? r0 : n;
   const int64_t re = r0 + (int64_t)R * KTPB < n ? r0 + (int64_t)R * KTPB : n;
   PassRows<R> pr;
-  pr.p0 = rowptr[rs];
-  pr.p1 = rowptr[re];
+  // vector loads (z = vzero()): see vread; made uniform where the pass uses them
+  pr.p0 = rowptr[rs + z];
+  pr.p1 = rowptr[re + z];
 #pragma unroll
   for (int u = 0; u < R; ++u) {
     const int64_t i = r0 + (int64_t)u * KTPB + threadIdx.x;
@@ -652,8 +682,11 @@ __global__ __launch_bounds__(KTPB) void k_gm_f(const int *rowptr, const int *col
   int64_t r0 = (int64_t)blockIdx.x * NR;
 
   // ---- one trip: first pass's row pointers, control block, partial rows
-  PassRows<R> pr = pass_rows<R>(rowptr, n, r0);
-  const int st = ctl->state, act = ctl->active;
+  const int z = vzero();
+  PassRows<R> pr = pass_rows<R>(rowptr, n, r0, z);
+  const int st = vread(&ctl->state, z), act = vread(&ctl->active, z);
+  const DecideIn din = decide_in(ctl, z);
+  const int trust = vread(&ctl->trust_est, z), pend = vread(&ctl->conv_pending, z);
   const int hcnt = j > 1 ? (j - 1) * LD : 0;
   const int jm = j > 0 ? j - 1 : 0;
   double hreg[HPT];
@@ -663,7 +696,10 @@ __global__ __launch_bounds__(KTPB) void k_gm_f(const int *rowptr, const int *col
     hreg[u] = ctl->Hraw[e < hcnt ? e : 0];
   }
   const double vs_t = ctl->vs[t < jm ? t : jm], h1_t = ctl->h1[t < jm ? t : jm];
-  const double part = final_part(Pin, nblk, KW, j == 0 ? 2 : j);
+  const int kp = j == 0 ? 2 : j;
+  // partial rows a thread needs: nblk <= KMAXBLK rows of kp <= RB entries
+  double pt[RB / 2 > 0 ? RB / 2 : 1];
+  final_part_load(Pin, nblk, KW, kp, pt);
   if (t == 0) s_go = j == 0 ? ((mode == 0) || st == ST_RUN) : ((st == ST_RUN) && act);
 #pragma unroll
   for (int u = 0; u < HPT; ++u) {
@@ -676,20 +712,21 @@ __global__ __launch_bounds__(KTPB) void k_gm_f(const int *rowptr, const int *col
   }
   __syncthreads();
   if (!s_go) return;
+  // (summed here: holding the loaded rows past the column loads below would spill)
+  const double part = final_part_sum(Pin, nblk, KW, kp, pt);
   if (j == 0) {
     // open the cycle from the start kernel's partials
     final_tree(part, 2, outv, scratch);
     if (t == 0) {
       const bool persist = blockIdx.x == 0;
-      const int trust = ctl->trust_est, pend = ctl->conv_pending;
       const bool accept = mode != 0 && trust && pend;
-      const int sd = residual_decide(outv[0], outv[1], mode == 0 ? 0 : 1, ctl, persist, accept);
+      const int sd = residual_decide(outv[0], outv[1], mode == 0 ? 0 : 1, din, ctl, persist, accept);
       if (persist && sd == ST_RUN) {
         ctl->conv_pending = 0;
         const double beta = sqrt(outv[0]);
         ctl->active = 1;
         ctl->jend = 0;
-        ctl->ibase = mode == 0 ? 0 : ctl->iters;
+        ctl->ibase = mode == 0 ? 0 : din.iters;
         ctl->gnext[0] = beta;
         ctl->vs[0] = 1.0 / beta;
       }
@@ -711,11 +748,12 @@ __global__ __launch_bounds__(KTPB) void k_gm_f(const int *rowptr, const int *col
   bool first = true;
   for (; r0 < n; r0 += stride) {
     const bool spmv = mode != 2;
-    const bool staged = spmv && pr.p1 > pr.p0 && pr.p1 - pr.p0 <= CAP;
+    const int p0 = __builtin_amdgcn_readfirstlane(pr.p0), p1 = __builtin_amdgcn_readfirstlane(pr.p1);
+    const bool staged = spmv && p1 > p0 && p1 - p0 <= CAP;
     // SpMV round 1: columns and values (issued unconditionally: a branch around them
     // would make the column loads below wait for them)
     StageRound<C> sr;
-    stage_load<C>(sr, col, val, pr.p0, pr.p1);
+    stage_load<C>(sr, col, val, p0, p1);
     // with 16 or more slots the gathers go out before the column stream too (their LDS
     // write and the row sums then overlap the stream; measured faster there, slower at 8)
     constexpr bool gathers_first = RB >= 16;
@@ -769,11 +807,11 @@ __global__ __launch_bounds__(KTPB) void k_gm_f(const int *rowptr, const int *col
     if (spmv) {
       if (staged) {
         if constexpr (!gathers_first) stage_gather<C>(sr, gx);
-        stage_write<C>(sr, pr.p0, pr.p0, pr.p1, prod);
-        for (int base = pr.p0 + C * KTPB; base < pr.p1; base += C * KTPB) {
-          stage_load<C>(sr, col, val, base, pr.p1);
+        stage_write<C>(sr, p0, p0, p1, prod);
+        for (int base = p0 + C * KTPB; base < p1; base += C * KTPB) {
+          stage_load<C>(sr, col, val, base, p1);
           stage_gather<C>(sr, gx);
-          stage_write<C>(sr, base, pr.p0, pr.p1, prod);
+          stage_write<C>(sr, base, p0, p1, prod);
         }
       }
       __syncthreads();
@@ -781,7 +819,7 @@ __global__ __launch_bounds__(KTPB) void k_gm_f(const int *rowptr, const int *col
       for (int u = 0; u < R; ++u) {
         double a = 0.0;
         if (staged) {
-          for (int p = pr.a[u]; p < pr.b[u]; ++p) a += prod[p - pr.p0];
+          for (int p = pr.a[u]; p < pr.b[u]; ++p) a += prod[p - p0];
         } else {
           for (int p = pr.a[u]; p < pr.b[u]; ++p) a += (double)val[p] * gx(col[p]);
         }
@@ -790,7 +828,7 @@ __global__ __launch_bounds__(KTPB) void k_gm_f(const int *rowptr, const int *col
     }
     __syncthreads();  // fco / cco visible; prod free for the next pass
     // the next pass's row pointers, requested before this pass's arithmetic
-    if (r0 + stride < n) pr = pass_rows<R>(rowptr, n, r0 + stride);
+    if (r0 + stride < n) pr = pass_rows<R>(rowptr, n, r0 + stride, z);
     const double cj = cco[j < RB ? j : RB];
 #pragma unroll
     for (int u = 0; u < R; ++u) {
@@ -843,15 +881,19 @@ __global__ __launch_bounds__(KTPB) void k_gm_g(const TV *V, TV *T, int64_t n, in
   __shared__ CloseIn ci;
   const int t = threadIdx.x;
   // ---- one trip: control block (run flag, close inputs, column scales), partial rows
-  const int st = ctl->state, act = ctl->active, ib = ctl->ibase;
-  unsigned long long *const mir = ctl->mirror;
+  const int z = vzero();
+  const int st = vread(&ctl->state, z), act = vread(&ctl->active, z), ib = vread(&ctl->ibase, z);
+  unsigned long long *const mir = vread(&ctl->mirror, z);
   const int jc = j > 0 ? j - 1 : 0;  // step closed here
   const double col_t = ctl->Hraw[(t <= jc ? t : jc) + jc * LD];
   const double cs_t = ctl->cs[t < jc ? t : 0], sn_t = ctl->sn[t < jc ? t : 0];
-  const double gj = ctl->gnext[jc], tol = ctl->tol, bn = ctl->bnorm;
-  const int maxit = ctl->maxit, restart = ctl->restart, trust = ctl->trust_est;
+  const double gj = vread(&ctl->gnext[jc], z), tol = vread(&ctl->tol, z), bn = vread(&ctl->bnorm, z);
+  const int maxit = vread(&ctl->maxit, z), restart = vread(&ctl->restart, z), trust = vread(&ctl->trust_est, z);
   const double vs_t = ctl->vs[t <= j ? t : j];
-  const double part = final_part(Pin, nblk, KW, j + 2);
+  // partial rows a thread needs: nblk <= KMAXBLK rows of j + 2 <= 32 entries (more are
+  // summed by final_part_sum)
+  double pt[RB < 16 ? RB : 16];
+  final_part_load(Pin, nblk, KW, j + 2, pt);
   if (t == 0) {
     s_go = (st == ST_RUN) && act;
     s_ibase = ib;
@@ -892,6 +934,10 @@ __global__ __launch_bounds__(KTPB) void k_gm_g(const TV *V, TV *T, int64_t n, in
       yv[u] = ycol[ic];
     }
   };
+  // the partial rows came with the control block; summed before the column loads go
+  // out (a wait for them behind the column loads, which sit in uniform branches, would
+  // be counted as a wait for those too)
+  const double part = final_part_sum(Pin, nblk, KW, j + 2, pt);
   load_pass(r0);
   final_tree(part, j + 2, outv, scratch);
   // scale of v_j: 1 / ||w''_j|| (the close of step j - 1 records the same), or vs[0]
@@ -916,12 +962,8 @@ __global__ __launch_bounds__(KTPB) void k_gm_g(const TV *V, TV *T, int64_t n, in
   // outputs (every later kernel of the cycle checks `active`)
   if (j > 0 && t < WAVE) {
     const bool persist = blockIdx.x == 0;
-    if (t == 0) {
-      const bool end = gm_close_scalar(j - 1, hn, s_ibase + j, &ci, ctl, persist);
-      if (persist) mirror_report(mir, serial, end ? MIR_CYCLE_END : 0u);
-    }
-    if (persist)
-      for (int l = t; l <= j - 1; l += WAVE) ctl->R[l + (j - 1) * LD] = ci.col[l];
+    const bool end = gm_close_wave(j - 1, hn, s_ibase + j, &ci, ctl, persist);
+    if (persist && t == 0) mirror_report(mir, serial, end ? MIR_CYCLE_END : 0u);
   } else if (j == 0 && blockIdx.x == 0 && t == 0) {
     mirror_report(mir, serial, 0u);
   }
@@ -960,22 +1002,20 @@ __global__ __launch_bounds__(KTPB) void k_gm_close(const double *Pin, int nblk, 
   __shared__ double scratch[KTPB];
   __shared__ int s_go, s_ibase;
   __shared__ CloseIn ci;
+  // one trip: control block and F(m)'s partial rows
+  const int z = vzero();
+  const int st = vread(&ctl->state, z), act = vread(&ctl->active, z), ib = vread(&ctl->ibase, z);
+  close_stage(j, ctl, &ci);
+  double pt[1];
+  final_part_load(Pin, nblk, KW, 1, pt);
   if (threadIdx.x == 0) {
-    const int st = ctl->state, act = ctl->active, ib = ctl->ibase;
     s_go = (st == ST_RUN) && act;
     s_ibase = ib;
   }
-  close_stage(j, ctl, &ci);
   __syncthreads();
   if (!s_go) return;
-  final_sum(Pin, nblk, KW, 1, outv, scratch);
+  final_tree(final_part_sum(Pin, nblk, KW, 1, pt), 1, outv, scratch);
   gm_close_block(j, sqrt(outv[0]), s_ibase + j + 1, &ci, ctl, true);
-}
-
-// lane i's value of v, in every lane (i uniform)
-__device__ inline double lane_bcast(double v, int i) {
-  const int lo = __builtin_amdgcn_readlane((int)dlo(v), i), hi = __builtin_amdgcn_readlane((int)dhi(v), i);
-  return dmake((unsigned)lo, (unsigned)hi);
 }
 
 // End of a cycle: every block solves R y = gam (m x m upper triangular, staged in
