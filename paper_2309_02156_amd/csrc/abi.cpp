@@ -57,11 +57,13 @@ struct sa_seq {
   int *hbuf = nullptr;    // pinned host mirror of solver state (128 ints; from int 64 on the
                           // snapshot of the last poll: norms, then the state words)
   const Ctl *snap_ctl = nullptr;  // control block of that snapshot
+  const Ctl *poll_ctl = nullptr;  // control block of the snapshot copy in flight (ev_poll)
   unsigned long long *mir[2] = {nullptr, nullptr};  // progress words of ctl and ctl_in (pinned)
   long long pushes = 0;
   int64_t ld = 0;  // leading dimension of X, Q1 and the Krylov vectors
   double tau_s = 1e-12, tau_c = 1e-12;
   hipEvent_t ev[4] = {nullptr, nullptr, nullptr, nullptr};
+  hipEvent_t ev_poll = nullptr;  // completion of the last snapshot copy
   KernelProfile prof;
   sa_mlp *mlp = nullptr;  // learned guess (sa_learned_attach)
   int lhist = 0;          // targets per MLP input
@@ -207,13 +209,24 @@ inline int count(const sa_seq *q) { return (int)(q->pushes < q->cfg.M ? q->pushe
 // restarts, maxit, active, jend, restart, pad0); the state words land in hbuf[0..7]
 static_assert(offsetof(Ctl, state) == offsetof(Ctl, bnorm) + 4 * sizeof(double), "norms then state words");
 inline double *snapshot(sa_seq *q) { return (double *)(q->hbuf + 64); }
-int poll(sa_seq *q, Ctl *ctl, hipStream_t st) {
-  double *snap = snapshot(q);
-  HIP_TRY(hipMemcpyAsync(snap, &ctl->bnorm, 4 * sizeof(double) + 8 * sizeof(int), hipMemcpyDeviceToHost, st));
-  HIP_TRY(hipStreamSynchronize(st));
-  memcpy(q->hbuf, snap + 4, 8 * sizeof(int));
-  q->snap_ctl = ctl;
+// poll = poll_enqueue (the copy, then an event) + poll_wait (the host waits for that event
+// only, so work enqueued after the copy keeps the device busy meanwhile)
+int poll_enqueue(sa_seq *q, Ctl *ctl, hipStream_t st) {
+  HIP_TRY(hipMemcpyAsync(snapshot(q), &ctl->bnorm, 4 * sizeof(double) + 8 * sizeof(int), hipMemcpyDeviceToHost,
+                         st));
+  HIP_TRY(hipEventRecord(q->ev_poll, st));
+  q->poll_ctl = ctl;
   return SA_OK;
+}
+int poll_wait(sa_seq *q) {
+  HIP_TRY(hipEventSynchronize(q->ev_poll));
+  memcpy(q->hbuf, snapshot(q) + 4, 8 * sizeof(int));
+  q->snap_ctl = q->poll_ctl;
+  return SA_OK;
+}
+int poll(sa_seq *q, Ctl *ctl, hipStream_t st) {
+  SA_TRY(poll_enqueue(q, ctl, st));
+  return poll_wait(q);
 }
 
 // control block in device memory, with its progress word in pinned host memory
@@ -235,6 +248,7 @@ int init_ctl(Ctl **out, unsigned long long **mir_out, double tol, int maxit, int
   }
   memset((void *)h, 0, sizeof(Ctl));
   h->mirror = md;
+  h->hinfo = (int *)(md + 2);  // same pinned block, bytes 16..47
   h->tol = tol;
   h->maxit = maxit;
   h->restart = restart;
@@ -415,7 +429,8 @@ int run_cg(sa_seq *q, const CsrView &v, Ctl *ctl, const TV *b, TV *x, int maxit,
 
 // GMRES(m) to the tolerance (or maxit); final state words in q->hbuf[0..7].
 template <typename TV>
-int run_gmres(sa_seq *q, const CsrView &v, Ctl *ctl, const TV *b, TV *x, int maxit, hipStream_t st) {
+int run_gmres(sa_seq *q, const CsrView &v, Ctl *ctl, const TV *b, TV *x, int maxit, hipStream_t st,
+              bool defer = false) {
   const sa_config &c = q->cfg;
   TV *V = (TV *)q->kry;
   TV *T = V + (size_t)(c.restart + 1) * q->ld;
@@ -427,19 +442,29 @@ int run_gmres(sa_seq *q, const CsrView &v, Ctl *ctl, const TV *b, TV *x, int max
   const int ahead = c.poll > MIR_EVERY ? c.poll : MIR_EVERY;  // progress arrives every MIR_EVERY steps
   HIP_TRY(launch_gm_start<TV>(v, b, x, V, 0, q->partials, ctl, st));
   bool stop = false;
+  bool est_end = false;  // the last cycle ended on its residual estimate
   // every cycle either adds an iteration or ends the solve in its first step
   for (long long cycle = 0; !stop; ++cycle) {
     if (cycle > (long long)maxit + 4) return SA_EHIP;
     const int first = pg.serial + 1;
+    bool cut = false;  // the cycle ended before its last step: its last close ran in G
     for (int j = 0; j < c.restart; ++j) {
       int seen;
       unsigned fl;
-      SA_TRY(progress_wait(q, ctl, pg, pg.serial - ahead, first, MIR_STOPPED | MIR_CYCLE_END, st, &seen, &fl));
+      // after a cycle that ended on its estimate, the restart's decision (reported by
+      // its first step) is awaited before more steps go out: most likely it ends the solve
+      const int target = (est_end && j == 1) ? pg.serial : pg.serial - ahead;
+      SA_TRY(progress_wait(q, ctl, pg, target, first, MIR_STOPPED | MIR_CYCLE_END, st, &seen, &fl));
       if (fl & MIR_STOPPED) {
         stop = true;
         break;
       }
-      if ((fl & MIR_CYCLE_END) && seen >= first) break;  // the rest of this cycle would be no-ops
+      if ((fl & MIR_CYCLE_END) && seen >= first) {  // the rest of this cycle would be no-ops
+        cut = true;
+        est_end = (fl & MIR_EST_CONV) != 0;
+        break;
+      }
+      if (j == 1) est_end = false;
       KTiming tm;
       const KTiming *tp = nullptr;
       if (q->prof.on) {
@@ -450,13 +475,18 @@ int run_gmres(sa_seq *q, const CsrView &v, Ctl *ctl, const TV *b, TV *x, int max
                                  ", " + std::to_string(gm_f_rows_per_thread(v.n, rb)) + ">";
         tp = prof_slot(q, name, bytes, &tm);
       }
-      HIP_TRY(launch_gm_step<TV>(v, V, T, q->ld, j, cycle > 0 ? 1 : 0, q->partials, ctl, st, tp, pg.next()));
+      // (the restart's first step reports in any case when the host will wait for it)
+      const int serial = pg.next() | ((est_end && j == 0) ? MIR_REPORT : 0);
+      HIP_TRY(launch_gm_step<TV>(v, V, T, q->ld, j, cycle > 0 ? 1 : 0, q->partials, ctl, st, tp, serial));
     }
     if (stop) break;
-    HIP_TRY(launch_gm_finish<TV>(v, V, T, q->ld, c.restart, q->partials, ctl, st));
+    if (!cut) HIP_TRY(launch_gm_finish<TV>(v, V, T, q->ld, c.restart, q->partials, ctl, st));
     HIP_TRY(launch_gm_update<TV>(x, V, v.n, q->ld, c.restart, ctl, st));
     HIP_TRY(launch_gm_start<TV>(v, b, x, V, 1, q->partials, ctl, st));
   }
+  // defer: only enqueue the final read of the state (poll_wait reads it); the GMRES
+  // state needs no action after it
+  if (defer && !q->prof.on) return poll_enqueue(q, ctl, st);
   SA_TRY(poll(q, ctl, st));
   return prof_end(q, ctl, st);
 }
@@ -555,6 +585,7 @@ int sa_init_sequence(const sa_config *cfg, void *dev_ws, size_t ws_bytes, void *
   }
   bool ok = hipHostMalloc((void **)&q->hbuf, 128 * sizeof(int), hipHostMallocDefault) == hipSuccess;
   for (int e = 0; ok && e < 4; ++e) ok = hipEventCreate(&q->ev[e]) == hipSuccess;
+  if (ok) ok = hipEventCreateWithFlags(&q->ev_poll, hipEventDisableTiming) == hipSuccess;
   if (ok) ok = init_ctl(&q->ctl, &q->mir[0], cfg->tol, cfg->maxit, cfg->restart, 0, st) == SA_OK;
   if (ok && q->mixed)
     ok = init_ctl(&q->ctl_in, &q->mir[1], cfg->inner_tol, cfg->maxit, cfg->restart, 1, st) == SA_OK;
@@ -579,18 +610,20 @@ int sa_init_sequence(const sa_config *cfg, void *dev_ws, size_t ws_bytes, void *
   return SA_OK;
 }
 
-int sa_push_solution(sa_seq *q, const void *x_dev, void *stream) {
-  if (!q || !q->alive) return SA_ESTATE;
-  if (!x_dev) return SA_EINVAL;
-  hipStream_t st = (hipStream_t)stream;
+}  // extern "C"
+
+namespace {
+
+// push x into the history; zero_rhs: push zero if the last solve ended with b = 0
+int push_enqueue(sa_seq *q, const void *x_dev, int zero_rhs, hipStream_t st) {
   const sa_config &c = q->cfg;
   const int slot = (int)(q->pushes % c.M);
   if (q->x32)
     HIP_TRY(launch_push<float>((const double *)x_dev, (float *)q->X, q->SX, c.n, q->ld, slot, c.s, c.sketch, c.seed,
-                               q->srht_rows, q->partials, q->ctl, st));
+                               q->srht_rows, q->partials, q->ctl, zero_rhs, st));
   else
     HIP_TRY(launch_push<double>((const double *)x_dev, (double *)q->X, q->SX, c.n, q->ld, slot, c.s, c.sketch,
-                                c.seed, q->srht_rows, q->partials, q->ctl, st));
+                                c.seed, q->srht_rows, q->partials, q->ctl, zero_rhs, st));
   if (q->mlp) {
     // target of the step whose solution this is: its sketched least-squares
     // coordinates in that step's history (before this push changes SX and T1)
@@ -605,13 +638,24 @@ int sa_push_solution(sa_seq *q, const void *x_dev, void *stream) {
   return SA_OK;
 }
 
+}  // namespace
+
+extern "C" {
+
+int sa_push_solution(sa_seq *q, const void *x_dev, void *stream) {
+  if (!q || !q->alive) return SA_ESTATE;
+  if (!x_dev) return SA_EINVAL;
+  return push_enqueue(q, x_dev, 0, (hipStream_t)stream);
+}
+
 }  // extern "C"
 
 namespace {
 
 // Enqueues the initial guess of the next step into x0; with `want_info` also its timing
-// events and copies of the basis ranks and the learned decision into hbuf[16..20]
-// (read by guess_info after the stream has synchronized).  *cnt = history columns used.
+// events (the reduced solve and the learned choice write their ranks and decision into
+// the pinned guess record, read by guess_info after the stream has passed them).
+// *cnt = history columns used.
 int guess_enqueue(sa_seq *q, const sa_csr *A, const void *b_dev, void *x0_dev, bool want_info, hipStream_t st,
                   int *cnt_out) {
   int rc = check_csr(q, A);
@@ -639,11 +683,7 @@ int guess_enqueue(sa_seq *q, const sa_csr *A, const void *b_dev, void *x0_dev, b
       SA_TRY(guess_projection<double>(q, v, (const double *)b_dev, (double *)x0_dev, cnt, st));
     if (q->mlp && q->ltargets >= q->lhist) SA_TRY(guess_learned(q, v, (const double *)b_dev, (double *)x0_dev, cnt, st));
   }
-  if (want_info) {
-    HIP_TRY(hipEventRecord(q->ev[1], st));
-    HIP_TRY(hipMemcpyAsync(q->hbuf + 16, &q->ctl->k, 4 * sizeof(int), hipMemcpyDeviceToHost, st));
-    HIP_TRY(hipMemcpyAsync(q->hbuf + 20, &q->ctl->learned_used, sizeof(int), hipMemcpyDeviceToHost, st));
-  }
+  if (want_info) HIP_TRY(hipEventRecord(q->ev[1], st));
   return SA_OK;
 }
 
@@ -653,11 +693,12 @@ int guess_info(sa_seq *q, int cnt, sa_info *info) {
   float ms = 0.f;
   HIP_TRY(hipEventElapsedTime(&ms, q->ev[0], q->ev[1]));
   const bool proj = cnt > 0 && c.guess == SA_GUESS_PROJECTION;
-  info->k_sketch = proj ? q->hbuf[16] : 0;
-  info->k_eff = proj ? q->hbuf[17] : 0;
-  info->used_fallback = proj ? q->hbuf[18] : 0;
+  const volatile int *rec = (const volatile int *)(q->mir[0] + 2);  // the pinned guess record
+  info->k_sketch = proj ? rec[0] : 0;
+  info->k_eff = proj ? rec[1] : 0;
+  info->used_fallback = proj ? rec[2] : 0;
   info->history = cnt;
-  info->used_learned = (q->mlp && proj && q->ltargets >= q->lhist) ? q->hbuf[20] : 0;
+  info->used_learned = (q->mlp && proj && q->ltargets >= q->lhist) ? rec[4] : 0;
   info->ms_guess = ms;
   return SA_OK;
 }
@@ -775,14 +816,47 @@ int sa_solve(sa_seq *q, const sa_csr *A, const void *b_dev, void *x_dev, sa_info
 int sa_step(sa_seq *q, const sa_csr *A, const void *b_dev, void *x_dev, sa_info *info, void *stream) {
   if (!q || !q->alive) return SA_ESTATE;
   hipStream_t st = (hipStream_t)stream;
+  const sa_config &c = q->cfg;
   int cnt = 0;
   SA_TRY(guess_enqueue(q, A, b_dev, x_dev, info != nullptr, st, &cnt));
-  // with info the solve returns with the stream synchronized, past the guess's copies
-  const int rs = sa_solve(q, A, b_dev, x_dev, info, st);
-  if (rs != SA_OK && rs != SA_NOTCONV && rs != SA_EBREAKDOWN) return rs;
-  if (info) SA_TRY(guess_info(q, cnt, info));
-  SA_TRY(sa_push_solution(q, x_dev, st));
-  return rs;
+  if (q->mixed || c.solver != SA_GMRES || q->prof.on) {
+    // with info the solve returns with the stream synchronized, past the guess
+    const int rs = sa_solve(q, A, b_dev, x_dev, info, st);
+    if (rs != SA_OK && rs != SA_NOTCONV && rs != SA_EBREAKDOWN) return rs;
+    if (info) SA_TRY(guess_info(q, cnt, info));
+    SA_TRY(push_enqueue(q, x_dev, 0, st));
+    return rs;
+  }
+  // GMRES: the solve, the read of its final state and the push are all enqueued before
+  // the host waits, for the read only, so the push runs while the host takes the result
+  // and enqueues the next step.  (A solve that ended with b = 0 pushes zero: its x is
+  // zeroed below, after the push in stream order.)
+  if (info) HIP_TRY(hipEventRecord(q->ev[2], st));
+  q->snap_ctl = nullptr;
+  SA_TRY(run_gmres<double>(q, view(A), q->ctl, (const double *)b_dev, (double *)x_dev, c.maxit, st, true));
+  if (info) HIP_TRY(hipEventRecord(q->ev[3], st));
+  SA_TRY(push_enqueue(q, x_dev, 1, st));
+  SA_TRY(poll_wait(q));
+  const int state = q->hbuf[0];
+  if (state < ST_RUN || state > ST_ZERO_RHS) return SA_EHIP;
+  if (state == ST_ZERO_RHS) HIP_TRY(hipMemsetAsync(x_dev, 0, (size_t)c.n * sizeof(double), st));
+  const int ret = status_of(state);
+  if (info) {
+    HIP_TRY(hipEventSynchronize(q->ev[3]));
+    double d[4];  // bnorm, relres0, relres, tol
+    memcpy(d, snapshot(q), sizeof(d));
+    float ms = 0.f;
+    HIP_TRY(hipEventElapsedTime(&ms, q->ev[2], q->ev[3]));
+    info->iters = q->hbuf[1];
+    info->restarts = q->hbuf[2];
+    info->refinements = 0;
+    info->relres0 = d[1];
+    info->relres = state == ST_ZERO_RHS ? 0.0 : d[2];
+    info->status = ret;
+    info->ms_solve = ms;
+    SA_TRY(guess_info(q, cnt, info));
+  }
+  return ret;
 }
 
 int sa_destroy_sequence(sa_seq *q) {
@@ -795,6 +869,7 @@ int sa_destroy_sequence(sa_seq *q) {
     if (m) (void)hipHostFree(m);
   for (int e = 0; e < 4; ++e)
     if (q->ev[e]) (void)hipEventDestroy(q->ev[e]);
+  if (q->ev_poll) (void)hipEventDestroy(q->ev_poll);
   for (auto &e : q->prof.ev)
     if (e) (void)hipEventDestroy(e);
   delete q;

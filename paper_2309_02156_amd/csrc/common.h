@@ -44,6 +44,8 @@ struct Ctl {
   int pad2;
   double rho[4];                // CG: r^T r after iteration k in slot k & 3
   unsigned long long *mirror;   // host-visible progress word (pinned host memory), or null
+  int *hinfo;                   // host-visible guess record (pinned host memory), or null:
+                                // [0] k, [1] k2, [2] fallback (reduced solve), [4] learned used
   double h1[MAXR + 1];          // GMRES: first Gram-Schmidt pass of the current step
   double cs[MAXR], sn[MAXR];    // Givens rotations
   double gam[MAXR + 1];         // rotated right-hand side (final entries)
@@ -71,11 +73,18 @@ struct Ctl {
 // host gave the last step kernel that ran, and what that kernel saw.  A kernel cannot
 // complete before its store to host memory is acknowledged, so steps without news
 // report only every MIR_EVERY serials; any flag is reported at once.
-enum : unsigned { MIR_STOPPED = 1u, MIR_CYCLE_END = 2u, MIR_CHECK = 4u };
+// MIR_EST_CONV comes with MIR_CYCLE_END when the cycle ended on its residual estimate
+// (the restart's true residual will most likely end the solve).
+enum : unsigned { MIR_STOPPED = 1u, MIR_CYCLE_END = 2u, MIR_CHECK = 4u, MIR_EST_CONV = 8u };
 constexpr int MIR_EVERY = 8;
 
+// A serial with MIR_REPORT set asks for a report even without news (the host waits for it).
+constexpr int MIR_REPORT = 1 << 30;
+
 __device__ inline void mirror_report(unsigned long long *m, int serial, unsigned flags) {
-  if (m && serial > 0 && (flags != 0u || serial % MIR_EVERY == 0))
+  const bool force = (serial & MIR_REPORT) != 0;
+  serial &= ~MIR_REPORT;
+  if (m && serial > 0 && (force || flags != 0u || serial % MIR_EVERY == 0))
     *(volatile unsigned long long *)m = ((unsigned long long)(unsigned)serial << 32) | flags;
 }
 

@@ -62,11 +62,13 @@ hipError_t launch_spmv(const CsrView &A, const double *x, double *y, hipStream_t
 
 // ============================================================================ push + sketch
 // Grid (nbx, ceil(s / SKETCH_RG)): block row-group g accumulates rows [16 g, 16 g + 16)
-// of S x; group 0 also copies x into the history slot.  The last block reduces.
+// of S x; group 0 also copies x into the history slot.  The next kernel reduces.
+// zero_rhs: the pushed column is zero when the solve just ended in the zero right-hand
+// side state (its solution is x = 0, written after the push was enqueued).
 template <int SK, typename TX>
 __global__ __launch_bounds__(TPB) void k_push(const double *x, TX *X, double *SX, int64_t n, int64_t ld, int slot,
                                               int s, uint64_t seed, const long long *rows,
-                                              double *partials, Ctl *ctl) {
+                                              double *partials, const Ctl *ctl, int zero_rhs) {
   __shared__ double red[NWAVE * SKETCH_RG];
   __shared__ double outv[MAXS];
   __shared__ double scratch[TPB];
@@ -80,9 +82,10 @@ __global__ __launch_bounds__(TPB) void k_push(const double *x, TX *X, double *SX
 #pragma unroll
     for (int r = 0; r < SKETCH_RG; ++r) myrows[r] = (r < rc) ? rows[r0 + r] : 0;
   }
+  const bool zero = zero_rhs && ctl->state == ST_ZERO_RHS;
   GRID_ROWS(j, n) {
     // the stored (possibly FP32-rounded) column is what gets sketched
-    const TX xs = (TX)x[j];
+    const TX xs = zero ? (TX)0 : (TX)x[j];
     const double xj = (double)xs;
     if (g == 0) X[(size_t)slot * ld + j] = xs;
     if (SK == 0) {
@@ -106,7 +109,6 @@ __global__ __launch_bounds__(TPB) void k_push(const double *x, TX *X, double *SX
   (void)outv;
   (void)scratch;
   (void)SX;
-  (void)ctl;
   // per-block partial sums; the QRCP kernel that follows reduces them into SX[:, slot]
   block_sum_store<SKETCH_RG>(acc, rc, red, partials + (size_t)blk * SKETCH_RG);
 }
@@ -120,15 +122,16 @@ int push_blocks_x(int64_t n, int s) {
 
 template <typename TX>
 hipError_t launch_push(const double *x, TX *X, double *SX, int64_t n, int64_t ld, int slot, int s, int sketch,
-                       uint64_t seed, const long long *srht_rows, double *partials, Ctl *ctl, hipStream_t st) {
+                       uint64_t seed, const long long *srht_rows, double *partials, const Ctl *ctl, int zero_rhs,
+                       hipStream_t st) {
   const int ng = (s + SKETCH_RG - 1) / SKETCH_RG;
   const int nbx = push_blocks_x(n, s);
   if (sketch == 0)
     hipLaunchKernelGGL((k_push<0, TX>), dim3(nbx, ng), dim3(TPB), 0, st, x, X, SX, n, ld, slot, s, seed,
-                       srht_rows, partials, ctl);
+                       srht_rows, partials, ctl, zero_rhs);
   else
     hipLaunchKernelGGL((k_push<1, TX>), dim3(nbx, ng), dim3(TPB), 0, st, x, X, SX, n, ld, slot, s, seed,
-                       srht_rows, partials, ctl);
+                       srht_rows, partials, ctl, zero_rhs);
   return hipGetLastError();
 }
 
@@ -531,8 +534,14 @@ __global__ __launch_bounds__(TPB) void k_small_solve(int cnt, int spd, double ta
       ctl->cX[c] = 0.0;
     }
     if (tid == 0) {
+      const int fb = ctl->nonfinite;
       ctl->k2 = 0;
-      ctl->fallback = ctl->nonfinite;
+      ctl->fallback = fb;
+      if (int *hi = ctl->hinfo) {
+        ((volatile int *)hi)[0] = 0;
+        ((volatile int *)hi)[1] = 0;
+        ((volatile int *)hi)[2] = fb;
+      }
     }
     return;
   }
@@ -740,6 +749,12 @@ __global__ __launch_bounds__(TPB) void k_small_solve(int cnt, int spd, double ta
   if (tid == 0) {
     ctl->k2 = k2;
     ctl->fallback = s_fail;
+    // the ranks and the decision of this guess, for the host (read after the solve)
+    if (int *hi = ctl->hinfo) {
+      ((volatile int *)hi)[0] = k;
+      ((volatile int *)hi)[1] = k2;
+      ((volatile int *)hi)[2] = s_fail;
+    }
   }
 }
 
@@ -862,7 +877,7 @@ hipError_t launch_ir_update(double *x, const float *d, int64_t n, hipStream_t st
 
 #define SACC_INSTANTIATE_PROJ(TX)                                                                              \
   template hipError_t launch_push<TX>(const double *, TX *, double *, int64_t, int64_t, int, int, int, uint64_t, \
-                                      const long long *, double *, Ctl *, hipStream_t);                        \
+                                      const long long *, double *, const Ctl *, int, hipStream_t);             \
   template hipError_t launch_basis<TX>(const TX *, TX *, int64_t, int64_t, int, Ctl *, hipStream_t);           \
   template hipError_t launch_spmm_gram<TX>(const CsrView &, const TX *, int64_t, const double *, int, int,    \
                                            double *, int *, Ctl *, hipStream_t);                               \

@@ -513,8 +513,10 @@ __device__ inline double lane_bcast(double v, int i) {
 // computing the same scalars: lane l holds entry l of the column and rotation l, and
 // the scalar recurrence reads them with v_readlane (no LDS round trip per rotation).
 // Every block computes the same result; only `persist` (block 0) writes the control
-// block, the rotated column included (lanes 0..j; j < 64).  Returns the cycle-end flag.
-__device__ inline bool gm_close_wave(int j, double hn, int it, const CloseIn *ci, Ctl *ctl, bool persist) {
+// block, the rotated column included (lanes 0..j; j < 64).  Returns CLOSE_END when the
+// cycle ends, with CLOSE_EST when it ends on the residual estimate.
+enum : int { CLOSE_END = 1, CLOSE_EST = 2 };
+__device__ inline int gm_close_wave(int j, double hn, int it, const CloseIn *ci, Ctl *ctl, bool persist) {
   const int LD = MAXR + 1;
   const int lane = threadIdx.x % WAVE;
   double cv = ci->col[lane <= j ? lane : 0];
@@ -552,7 +554,7 @@ __device__ inline bool gm_close_wave(int j, double hn, int it, const CloseIn *ci
       if (est_conv && ci->trust) ctl->conv_pending = 1;
     }
   }
-  return end;
+  return end ? (CLOSE_END | (est_conv ? CLOSE_EST : 0)) : 0;
 }
 
 // gm_close_wave for a whole block (after close_stage and a barrier): wave 0 runs it and
@@ -560,8 +562,8 @@ __device__ inline bool gm_close_wave(int j, double hn, int it, const CloseIn *ci
 __device__ inline bool gm_close_block(int j, double hn, int it, CloseIn *ci, Ctl *ctl, bool persist) {
   __shared__ int s_endf;
   if (threadIdx.x < WAVE) {
-    const bool end = gm_close_wave(j, hn, it, ci, ctl, persist);
-    if (threadIdx.x == 0) s_endf = end ? 1 : 0;
+    const int cl = gm_close_wave(j, hn, it, ci, ctl, persist);
+    if (threadIdx.x == 0) s_endf = cl & CLOSE_END;
   }
   __syncthreads();
   return s_endf != 0;
@@ -962,8 +964,9 @@ __global__ __launch_bounds__(KTPB) void k_gm_g(const TV *V, TV *T, int64_t n, in
   // outputs (every later kernel of the cycle checks `active`)
   if (j > 0 && t < WAVE) {
     const bool persist = blockIdx.x == 0;
-    const bool end = gm_close_wave(j - 1, hn, s_ibase + j, &ci, ctl, persist);
-    if (persist && t == 0) mirror_report(mir, serial, end ? MIR_CYCLE_END : 0u);
+    const int cl = gm_close_wave(j - 1, hn, s_ibase + j, &ci, ctl, persist);
+    if (persist && t == 0)
+      mirror_report(mir, serial, (cl & CLOSE_END) ? (MIR_CYCLE_END | ((cl & CLOSE_EST) ? MIR_EST_CONV : 0u)) : 0u);
   } else if (j == 0 && blockIdx.x == 0 && t == 0) {
     mirror_report(mir, serial, 0u);
   }

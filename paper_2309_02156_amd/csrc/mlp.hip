@@ -348,6 +348,7 @@ __global__ __launch_bounds__(TPB) void k_learn_choose(const double *partials, in
   const bool take = isfinite(outv[1]) && outv[1] < outv[0];
   if (blockIdx.x == 0 && threadIdx.x == 0) {
     ctl->learned_used = take ? 1 : 0;
+    if (int *hi = ctl->hinfo) ((volatile int *)hi)[4] = take ? 1 : 0;
     ctl->learned_r2[0] = outv[0];
     ctl->learned_r2[1] = outv[1];
   }
