@@ -126,6 +126,12 @@ __device__ inline unsigned dlo(double v) { return (unsigned)__double2loint(v); }
 __device__ inline unsigned dhi(double v) { return (unsigned)__double2hiint(v); }
 __device__ inline double dmake(unsigned lo, unsigned hi) { return __hiloint2double((int)hi, (int)lo); }
 
+// lane i's value of v, in every lane (i uniform)
+__device__ inline double lane_bcast(double v, int i) {
+  const int lo = __builtin_amdgcn_readlane((int)dlo(v), i), hi = __builtin_amdgcn_readlane((int)dhi(v), i);
+  return dmake((unsigned)lo, (unsigned)hi);
+}
+
 // x' + y' after exchanging the upper half of x's lane group with the lower half of
 // y's: lanes in a lower half get the pair sum of x, lanes in an upper half the pair
 // sum of y.  W = 32 (halves of the wave) or 16 (rows).

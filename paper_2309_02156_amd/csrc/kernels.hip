@@ -139,17 +139,24 @@ hipError_t launch_push(const double *x, TX *X, double *SX, int64_t n, int64_t ld
 // One workgroup.  Householder QR with column pivoting (largest remaining column norm,
 // recomputed exactly at every step; ties pick the lowest index) of Y = SX[:, 0:cnt],
 // diag(R) >= 0, rank k = leading count of |R_jj| > tau |R_11|, T1 = P R11^-1.
+//
+// Wave w owns the columns c = w (mod NWAVE).  A pivot step: every wave forms the norms of
+// its remaining columns (all their LDS reads issued together, one multi-value wave
+// reduction: each norm is the same lane-order sum and tree as a one-column reduction),
+// every wave finds the pivot on its own (no serial scan, no barrier for it), the columns
+// swap, and every wave applies the reflector to its columns (the dots batched the same
+// way).  Three barriers a step.  MC = columns a wave owns at most, RW = 64-row chunks.
+template <int MC, int RW>
 __global__ __launch_bounds__(TPB) void k_qrcp(double *SX, int s, int cnt, int newest, double tau,
                                               const double *partials, int nbx, Ctl *ctl) {
   extern __shared__ double sh[];
-  double *Y = sh;                  // s x cnt, ld s
+  double *Y = sh;                     // s x cnt, ld s
   double *Ri = sh + (size_t)s * cnt;  // cnt x cnt inverse, ld cnt
   __shared__ double nrm[MAXM];
   __shared__ double v[MAXS];
   __shared__ double scratch[TPB];
-  __shared__ int perm[MAXM];
-  __shared__ int s_piv, s_bad, s_newest_bad, s_k;
-  __shared__ double s_tauh;
+  __shared__ int perm[MAXM], iperm[MAXM];
+  __shared__ int s_bad, s_newest_bad;
   const int tid = threadIdx.x, lane = tid % WAVE, wid = tid / WAVE;
   if (tid == 0) {
     s_bad = 0;
@@ -188,35 +195,57 @@ __global__ __launch_bounds__(TPB) void k_qrcp(double *SX, int s, int cnt, int ne
   }
   int jj = 0;
   for (; jj < cnt; ++jj) {
-    // exact column norms over rows jj..s-1 of the remaining columns
-    for (int c = jj + wid; c < cnt; c += NWAVE) {
-      double a = 0.0;
-      for (int r = jj + lane; r < s; r += WAVE) {
-        double y = Y[(size_t)c * s + r];
-        a += y * y;
+    // exact column norms over rows jj..s-1 of this wave's remaining columns
+    {
+      double a[MC];
+#pragma unroll
+      for (int u = 0; u < MC; ++u) {
+        const int c = jj + wid + NWAVE * u;
+        const int cc = c < cnt ? c : cnt - 1;
+        double acc = 0.0;
+#pragma unroll
+        for (int w = 0; w < RW; ++w) {
+          const int r = jj + lane + WAVE * w;
+          const double y = Y[(size_t)cc * s + (r < s ? r : s - 1)];
+          if (r < s) acc += y * y;
+        }
+        a[u] = acc;
       }
-      a = wave_sum(a);
-      if (lane == 0) nrm[c] = a;
+      wave_sum_multi<MC>(a);
+      constexpr int LPE = WAVE / MC;  // lanes per entry after the reduction
+      const int c = jj + wid + NWAVE * (lane / LPE);
+      if (lane % LPE == 0 && c < cnt) nrm[c] = a[0];
     }
     __syncthreads();
+    // pivot: largest norm, lowest index among equal ones (each wave, the same result)
+    int p;
+    {
+      double bv = (jj + lane < cnt) ? nrm[jj + lane] : -1.0;
+      int bi = jj + lane;
+#pragma unroll
+      for (int d = WAVE / 2; d > 0; d >>= 1) {
+        const double ov = __shfl_xor(bv, d);
+        const int oi = __shfl_xor(bi, d);
+        if (ov > bv || (ov == bv && oi < bi)) {
+          bv = ov;
+          bi = oi;
+        }
+      }
+      p = __builtin_amdgcn_readfirstlane(bi);
+    }
     if (tid == 0) {
-      int p = jj;
-      for (int c = jj + 1; c < cnt; ++c)
-        if (nrm[c] > nrm[p]) p = c;
-      s_piv = p;
-      int t = perm[jj];
+      const int t = perm[jj];
       perm[jj] = perm[p];
       perm[p] = t;
     }
-    __syncthreads();
-    const int p = s_piv;
-    if (p != jj)
+    if (p != jj) {
       for (int r = tid; r < s; r += blockDim.x) {
-        double t = Y[(size_t)jj * s + r];
+        const double t = Y[(size_t)jj * s + r];
         Y[(size_t)jj * s + r] = Y[(size_t)p * s + r];
         Y[(size_t)p * s + r] = t;
       }
-    __syncthreads();
+      __syncthreads();
+    }
     const double alpha = sqrt(nrm[p]);
     const double x0 = Y[(size_t)jj * s + jj];
     if (alpha == 0.0) {
@@ -227,15 +256,47 @@ __global__ __launch_bounds__(TPB) void k_qrcp(double *SX, int s, int cnt, int ne
     }
     const double beta = x0 >= 0.0 ? -alpha : alpha;  // R_jj (sign fixed below)
     const double v0 = x0 - beta;
-    for (int r = jj + tid; r < s; r += blockDim.x) v[r] = (r == jj) ? v0 : Y[(size_t)jj * s + r];
-    if (tid == 0) s_tauh = 2.0 / (v0 * v0 + (alpha * alpha - x0 * x0));
-    __syncthreads();
-    const double tauh = s_tauh;
-    for (int c = jj + 1 + wid; c < cnt; c += NWAVE) {
-      double d = 0.0;
-      for (int r = jj + lane; r < s; r += WAVE) d += v[r] * Y[(size_t)c * s + r];
-      d = wave_sum(d) * tauh;
-      for (int r = jj + lane; r < s; r += WAVE) Y[(size_t)c * s + r] -= d * v[r];
+    const double tauh = 2.0 / (v0 * v0 + (alpha * alpha - x0 * x0));
+    // reflector v = (v0, Y[jj+1.., jj]) applied to this wave's columns c > jj
+    {
+      double vr[RW];
+#pragma unroll
+      for (int w = 0; w < RW; ++w) {
+        const int r = jj + lane + WAVE * w;
+        const double y = Y[(size_t)jj * s + (r < s ? r : s - 1)];
+        vr[w] = r == jj ? v0 : y;
+      }
+      double yc[MC][RW], d[MC];
+#pragma unroll
+      for (int u = 0; u < MC; ++u) {
+        const int c = jj + 1 + wid + NWAVE * u;
+        const int cc = c < cnt ? c : cnt - 1;
+        double acc = 0.0;
+#pragma unroll
+        for (int w = 0; w < RW; ++w) {
+          const int r = jj + lane + WAVE * w;
+          yc[u][w] = Y[(size_t)cc * s + (r < s ? r : s - 1)];
+          if (r < s) acc += vr[w] * yc[u][w];
+        }
+        d[u] = acc;
+      }
+      double dr[MC];
+#pragma unroll
+      for (int u = 0; u < MC; ++u) dr[u] = d[u];
+      wave_sum_multi<MC>(dr);
+      constexpr int LPE = WAVE / MC;
+#pragma unroll
+      for (int u = 0; u < MC; ++u) {
+        const int c = jj + 1 + wid + NWAVE * u;
+        const double du = lane_bcast(dr[0], u * LPE) * tauh;
+        if (c < cnt) {
+#pragma unroll
+          for (int w = 0; w < RW; ++w) {
+            const int r = jj + lane + WAVE * w;
+            if (r < s) Y[(size_t)c * s + r] = yc[u][w] - du * vr[w];
+          }
+        }
+      }
     }
     if (tid == 0) Y[(size_t)jj * s + jj] = beta;
     __syncthreads();
@@ -247,31 +308,39 @@ __global__ __launch_bounds__(TPB) void k_qrcp(double *SX, int s, int cnt, int ne
       for (int c = r + lane; c < cnt; c += WAVE) Y[(size_t)c * s + r] = -Y[(size_t)c * s + r];
   }
   __syncthreads();
-  if (tid == 0) {
-    const double r00 = fabs(Y[0]);
-    int k = 0;
-    if (r00 > 0.0)
-      while (k < cnt && fabs(Y[(size_t)k * s + k]) > tau * r00) ++k;
-    s_k = k;
-  }
-  __syncthreads();
-  const int k = s_k;
-  // R11^-1, one column per thread (upper triangular back substitution)
-  for (int c = tid; c < k; c += blockDim.x) {
-    for (int i = 0; i < k; ++i) Ri[i + c * k] = 0.0;
-    Ri[c + c * k] = 1.0 / Y[(size_t)c * s + c];
-    for (int i = c - 1; i >= 0; --i) {
-      double acc = 0.0;
-      for (int l = i + 1; l <= c; ++l) acc += Y[(size_t)l * s + i] * Ri[l + c * k];
-      Ri[i + c * k] = -acc / Y[(size_t)i * s + i];
+  // rank: leading count of |R_jj| > tau |R_11| (every thread, from LDS)
+  const double r00 = fabs(Y[0]);
+  int k = 0;
+  if (r00 > 0.0)
+    while (k < cnt && fabs(Y[(size_t)k * s + k]) > tau * r00) ++k;
+  // R11^-1 on wave 0, lane c = column c, row by row from the bottom (each entry the same
+  // ascending sum as a per-column back substitution)
+  if (wid == 0) {
+    const int c = lane;
+    if (c < k) {
+      for (int i = 0; i < k; ++i) Ri[i + c * k] = 0.0;
+      Ri[c + c * k] = 1.0 / Y[(size_t)c * s + c];
+    }
+    for (int i = k - 2; i >= 0; --i) {
+      if (c > i && c < k) {
+        double acc = 0.0;
+#pragma unroll 4
+        for (int l = i + 1; l <= c; ++l) acc += Y[(size_t)l * s + i] * Ri[l + c * k];
+        Ri[i + c * k] = -acc / Y[(size_t)i * s + i];
+      }
     }
   }
+  for (int i = tid; i < cnt; i += blockDim.x) iperm[perm[i]] = i;
   __syncthreads();
-  for (int e = tid; e < MAXM * MAXM; e += blockDim.x) ctl->T1[e] = 0.0;
-  __syncthreads();
-  for (int e = tid; e < k * k; e += blockDim.x) {
-    const int i = e % k, c = e / k;
-    if (i <= c) ctl->T1[perm[i] + c * MAXM] = Ri[i + c * k];
+  // T1 = P R11^-1 (zero elsewhere), every entry written once
+  for (int e = tid; e < MAXM * MAXM; e += blockDim.x) {
+    const int row = e % MAXM, c = e / MAXM;
+    double t = 0.0;
+    if (c < k && row < cnt) {
+      const int i = iperm[row];
+      if (i <= c) t = Ri[i + c * k];
+    }
+    ctl->T1[e] = t;
   }
   if (tid == 0) {
     ctl->k = k;
@@ -282,8 +351,12 @@ __global__ __launch_bounds__(TPB) void k_qrcp(double *SX, int s, int cnt, int ne
 hipError_t launch_qrcp(double *SX, int s, int cnt, int newest, double tau, const double *partials, int64_t n,
                        Ctl *ctl, hipStream_t st) {
   size_t lds = ((size_t)s * cnt + (size_t)cnt * cnt) * sizeof(double);
-  hipLaunchKernelGGL(k_qrcp, dim3(1), dim3(TPB), lds, st, SX, s, cnt, newest, tau, partials, push_blocks_x(n, s),
-                     ctl);
+  if (cnt <= 2 * NWAVE * 4 && s <= 2 * WAVE)
+    hipLaunchKernelGGL((k_qrcp<8, 2>), dim3(1), dim3(TPB), lds, st, SX, s, cnt, newest, tau, partials,
+                       push_blocks_x(n, s), ctl);
+  else
+    hipLaunchKernelGGL((k_qrcp<MAXM / NWAVE, MAXS / WAVE>), dim3(1), dim3(TPB), lds, st, SX, s, cnt, newest, tau,
+                       partials, push_blocks_x(n, s), ctl);
   return hipGetLastError();
 }
 

@@ -501,12 +501,6 @@ __device__ inline void close_stage(int j, const Ctl *ctl, CloseIn *ci) {
   }
 }
 
-// lane i's value of v, in every lane (i uniform)
-__device__ inline double lane_bcast(double v, int i) {
-  const int lo = __builtin_amdgcn_readlane((int)dlo(v), i), hi = __builtin_amdgcn_readlane((int)dhi(v), i);
-  return dmake((unsigned)lo, (unsigned)hi);
-}
-
 // Close Arnoldi step j given hn = ||w''_{j+1}|| from the staged inputs: rotate the raw
 // column j, new Givens rotation, rotated right-hand side, cycle-end test.  `it` =
 // global iteration number of step j (1-based).  Run by a whole wave, every lane
