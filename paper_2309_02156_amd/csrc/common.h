@@ -157,6 +157,52 @@ __device__ inline double dpp_partner(double v) {
   return dmake(lo, hi);
 }
 
+// Largest value over the wave's lanes and its index, the lowest index among equal values
+// (values not NaN); every lane returns the index.  Exchanges: permlane32 / permlane16
+// swaps, then DPP row rotations by 8, 4, 2, 1 (a total order, so every lane ends with
+// the same pair).
+__device__ inline void argmax_take(double &v, int &i, double ov, int oi) {
+  if (ov > v || (ov == v && oi < i)) {
+    v = ov;
+    i = oi;
+  }
+}
+template <int W>
+__device__ inline void argmax_swap_step(double &v, int &i) {
+  const bool up = (threadIdx.x & W) != 0;
+  unsigned lo0, lo1, hi0, hi1, i0, i1;
+  if constexpr (W == 32) {
+    const auto lo = __builtin_amdgcn_permlane32_swap(dlo(v), dlo(v), false, false);
+    const auto hi = __builtin_amdgcn_permlane32_swap(dhi(v), dhi(v), false, false);
+    const auto ix = __builtin_amdgcn_permlane32_swap((unsigned)i, (unsigned)i, false, false);
+    lo0 = lo[0]; lo1 = lo[1]; hi0 = hi[0]; hi1 = hi[1]; i0 = ix[0]; i1 = ix[1];
+  } else {
+    const auto lo = __builtin_amdgcn_permlane16_swap(dlo(v), dlo(v), false, false);
+    const auto hi = __builtin_amdgcn_permlane16_swap(dhi(v), dhi(v), false, false);
+    const auto ix = __builtin_amdgcn_permlane16_swap((unsigned)i, (unsigned)i, false, false);
+    lo0 = lo[0]; lo1 = lo[1]; hi0 = hi[0]; hi1 = hi[1]; i0 = ix[0]; i1 = ix[1];
+  }
+  // lower lanes find the partner's value in the second result, upper lanes in the first
+  const double ov = up ? dmake(lo0, hi0) : dmake(lo1, hi1);
+  const int oi = (int)(up ? i0 : i1);
+  argmax_take(v, i, ov, oi);
+}
+template <int D>
+__device__ inline void argmax_ror_step(double &v, int &i) {
+  const double ov = dpp_partner<0x120 + D>(v);
+  const int oi = __builtin_amdgcn_update_dpp(0, i, 0x120 + D, 0xF, 0xF, true);
+  argmax_take(v, i, ov, oi);
+}
+__device__ inline int wave_argmax(double v, int i) {
+  argmax_swap_step<32>(v, i);
+  argmax_swap_step<16>(v, i);
+  argmax_ror_step<8>(v, i);
+  argmax_ror_step<4>(v, i);
+  argmax_ror_step<2>(v, i);
+  argmax_ror_step<1>(v, i);
+  return __builtin_amdgcn_readfirstlane(i);
+}
+
 // Level L = 0..5 of the wave reduction splits lane groups of 64 >> L at lane bit
 // 32 >> L: partners by permlane32 / permlane16 swaps, then row_mirror (lane i <-> 15 - i),
 // row_half_mirror (i <-> 7 - i), quad permutations [3,2,1,0] and [1,0,3,2].

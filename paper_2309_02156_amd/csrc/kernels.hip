@@ -162,12 +162,28 @@ __global__ __launch_bounds__(TPB) void k_qrcp(double *SX, int s, int cnt, int ne
     s_bad = 0;
     s_newest_bad = 0;
   }
-  // finish the push: SX[:, newest] = (sum over push blocks of the sketch partials) / sqrt(s)
-  const int ng = (s + SKETCH_RG - 1) / SKETCH_RG;
-  for (int g = 0; g < ng; ++g) {
-    const int r0 = g * SKETCH_RG;
-    const int rc = (s - r0) < SKETCH_RG ? (s - r0) : SKETCH_RG;
-    final_sum(partials + (size_t)g * nbx * SKETCH_RG, nbx, SKETCH_RG, rc, v + r0, scratch);
+  // finish the push: SX[:, newest] = (sum over push blocks of the sketch partials) / sqrt(s).
+  // Sketch row r sits in row group r / SKETCH_RG, entry r % SKETCH_RG of each push block's
+  // partial row; `parts` threads per sketch row sum every parts-th block, then one adds
+  // the parts in order.
+  {
+    static_assert(MAXS <= TPB, "one thread at least per sketch row");
+    const int parts = (int)blockDim.x / s;
+    const int r = tid % s, part = tid / s;
+    if (part < parts) {
+      const double *pr = partials + ((size_t)(r / SKETCH_RG) * nbx) * SKETCH_RG + r % SKETCH_RG;
+      double acc = 0.0;
+#pragma unroll 8
+      for (int b = part; b < nbx; b += parts) acc += pr[(size_t)b * SKETCH_RG];
+      scratch[tid] = acc;
+    }
+    __syncthreads();
+    if (tid < s) {
+      double a = 0.0;
+      for (int q = 0; q < parts; ++q) a += scratch[q * s + tid];
+      v[tid] = a;
+    }
+    __syncthreads();
   }
   const double inv = 1.0 / sqrt((double)s);
   for (int r = tid; r < s; r += blockDim.x) SX[(size_t)newest * s + r] = v[r] * inv;
@@ -218,21 +234,7 @@ __global__ __launch_bounds__(TPB) void k_qrcp(double *SX, int s, int cnt, int ne
     }
     __syncthreads();
     // pivot: largest norm, lowest index among equal ones (each wave, the same result)
-    int p;
-    {
-      double bv = (jj + lane < cnt) ? nrm[jj + lane] : -1.0;
-      int bi = jj + lane;
-#pragma unroll
-      for (int d = WAVE / 2; d > 0; d >>= 1) {
-        const double ov = __shfl_xor(bv, d);
-        const int oi = __shfl_xor(bi, d);
-        if (ov > bv || (ov == bv && oi < bi)) {
-          bv = ov;
-          bi = oi;
-        }
-      }
-      p = __builtin_amdgcn_readfirstlane(bi);
-    }
+    const int p = wave_argmax((jj + lane < cnt) ? nrm[jj + lane] : -1.0, jj + lane);
     if (tid == 0) {
       const int t = perm[jj];
       perm[jj] = perm[p];
@@ -589,11 +591,10 @@ hipError_t launch_colsum(const double *partials, int nblk, int W, Ctl *ctl, hipS
 __global__ __launch_bounds__(TPB) void k_small_solve(int cnt, int spd, double tau_c, Ctl *ctl) {
   extern __shared__ double sh[];
   const int k = ctl->k;
-  const int tid = threadIdx.x;
+  const int tid = threadIdx.x, lane = tid % WAVE, wid = tid / WAVE;
   __shared__ int perm[MAXM];
-  __shared__ int ipiv[MAXM];
   __shared__ double gv[MAXM], yv[MAXM], cv[MAXM];
-  __shared__ int s_k2, s_stop, s_fail, s_p;
+  __shared__ int s_k2, s_fail;
   __shared__ double s_dmax;
   double *Gm = sh;                  // k x k, ld k  (-> R2 in its leading k2 x k2, upper part)
   double *Ri = sh + (size_t)k * k;  // k2 x k2, ld k
@@ -625,32 +626,28 @@ __global__ __launch_bounds__(TPB) void k_small_solve(int cnt, int spd, double ta
   for (int a = tid; a < k; a += blockDim.x) perm[a] = a;
   if (tid == 0) {
     s_fail = 0;
-    s_stop = 0;
     double dm = 0.0;
     for (int a = 0; a < k; ++a) dm = fmax(dm, P[a + a * cnt]);
     s_dmax = dm;
     s_k2 = k;
   }
   __syncthreads();
-  // pivoted Cholesky, outer-product form, in place on the full symmetric matrix
+  // pivoted Cholesky, outer-product form, in place on the full symmetric matrix; the
+  // pivot (largest remaining diagonal, lowest index among equal ones) found by every
+  // wave on its own
   for (int j = 0; j < k; ++j) {
-    if (tid == 0) {
-      int p = j;
-      for (int a = j + 1; a < k; ++a)
-        if (Gm[a + a * k] > Gm[p + p * k]) p = a;
-      s_p = p;
-      if (!(Gm[p + p * k] > tau_c * s_dmax)) {
-        s_stop = 1;
-        s_k2 = j;
-      } else if (p != j) {
-        int t = perm[j];
-        perm[j] = perm[p];
-        perm[p] = t;
-      }
+    const int p = wave_argmax((j + lane < k) ? Gm[(j + lane) * (k + 1)] : -INFINITY, j + lane);
+    const bool stop = !(Gm[p * (k + 1)] > tau_c * s_dmax);
+    __syncthreads();  // every wave has read the diagonal before the swaps below
+    if (stop) {
+      if (tid == 0) s_k2 = j;
+      break;
     }
-    __syncthreads();
-    if (s_stop) break;
-    const int p = s_p;
+    if (tid == 0 && p != j) {
+      int t = perm[j];
+      perm[j] = perm[p];
+      perm[p] = t;
+    }
     if (p != j) {
       for (int a = tid; a < k; a += blockDim.x) {  // swap rows j, p
         double t = Gm[j + a * k];
@@ -676,15 +673,23 @@ __global__ __launch_bounds__(TPB) void k_small_solve(int cnt, int spd, double ta
     }
     __syncthreads();
   }
+  __syncthreads();
   const int k2 = s_k2;
-  // Ri = R2^-1 (upper triangular, ld k)
-  for (int c = tid; c < k2; c += blockDim.x) {
-    for (int i = 0; i < k2; ++i) Ri[i + c * k] = 0.0;
-    Ri[c + c * k] = 1.0 / Gm[c + c * k];
-    for (int i = c - 1; i >= 0; --i) {
-      double acc = 0.0;
-      for (int l = i + 1; l <= c; ++l) acc += Gm[i + l * k] * Ri[l + c * k];
-      Ri[i + c * k] = -acc / Gm[i + i * k];
+  // Ri = R2^-1 (upper triangular, ld k) on wave 0, lane c = column c, row by row from the
+  // bottom (each entry the same ascending sum as a per-column back substitution)
+  if (wid == 0) {
+    const int c = lane;
+    if (c < k2) {
+      for (int i = 0; i < k2; ++i) Ri[i + c * k] = 0.0;
+      Ri[c + c * k] = 1.0 / Gm[c + c * k];
+    }
+    for (int i = k2 - 2; i >= 0; --i) {
+      if (c > i && c < k2) {
+        double acc = 0.0;
+#pragma unroll 4
+        for (int l = i + 1; l <= c; ++l) acc += Gm[i + l * k] * Ri[l + c * k];
+        Ri[i + c * k] = -acc / Gm[i + i * k];
+      }
     }
   }
   __syncthreads();
@@ -736,36 +741,42 @@ __global__ __launch_bounds__(TPB) void k_small_solve(int cnt, int spd, double ta
       }
       __syncthreads();
     }
-    if (tid == 0 && !s_fail) {
-      for (int a = 0; a < k2; ++a) {
-        double acc = gv[a];
-        for (int l = 0; l < a; ++l) acc -= Gm[a + l * k] * yv[l];
-        yv[a] = acc / Gm[a + a * k];
+    __syncthreads();
+    // L L^T y = g on wave 0 by columns, lane a = entry a: forward (terms in ascending
+    // order), then backward from the last entry
+    if (wid == 0 && !s_fail) {
+      const int a = lane;
+      double acc = a < k2 ? gv[a] : 0.0;
+      for (int l = 0; l < k2; ++l) {
+        if (a == l) acc = acc / Gm[a + a * k];
+        const double yl = lane_bcast(acc, l);
+        if (a > l && a < k2) acc -= Gm[a + l * k] * yl;
       }
-      for (int a = k2 - 1; a >= 0; --a) {
-        double acc = yv[a];
-        for (int l = a + 1; l < k2; ++l) acc -= Gm[l + a * k] * yv[l];
-        yv[a] = acc / Gm[a + a * k];
+      for (int l = k2 - 1; l >= 0; --l) {
+        if (a == l) acc = acc / Gm[a + a * k];
+        const double yl = lane_bcast(acc, l);
+        if (a < l) acc -= Gm[l + a * k] * yl;
       }
+      if (a < k2) yv[a] = acc;
     }
   } else {
     // LU with partial pivoting, row interchanges applied to the whole rows
     for (int j = 0; j < k2; ++j) {
-      if (tid == 0) {
-        int p = j;
-        for (int a = j + 1; a < k2; ++a)
-          if (fabs(Gm[a + j * k]) > fabs(Gm[p + j * k])) p = a;
-        ipiv[j] = p;
-        if (!(Gm[p + j * k] != 0.0) || !isfinite(Gm[p + j * k])) s_fail = 1;
-        if (p != j) {
-          double t = gv[j];
-          gv[j] = gv[p];
-          gv[p] = t;
-        }
+      // pivot: largest |entry| of column j at or below the diagonal, lowest index among
+      // equal ones (every wave on its own)
+      const int p = wave_argmax((j + lane < k2) ? fabs(Gm[j + lane + j * k]) : -1.0, j + lane);
+      const double gp = Gm[p + j * k];
+      const bool fail = !(gp != 0.0) || !isfinite(gp);
+      __syncthreads();  // every wave has read column j before the swap below
+      if (fail) {
+        if (tid == 0) s_fail = 1;
+        break;
       }
-      __syncthreads();
-      if (s_fail) break;
-      const int p = ipiv[j];
+      if (tid == 0 && p != j) {
+        double t = gv[j];
+        gv[j] = gv[p];
+        gv[p] = t;
+      }
       if (p != j)
         for (int b = tid; b < k2; b += blockDim.x) {
           double t = Gm[j + b * k];
@@ -782,17 +793,22 @@ __global__ __launch_bounds__(TPB) void k_small_solve(int cnt, int spd, double ta
       }
       __syncthreads();
     }
-    if (tid == 0 && !s_fail) {
-      for (int a = 0; a < k2; ++a) {
-        double acc = gv[a];
-        for (int l = 0; l < a; ++l) acc -= Gm[a + l * k] * yv[l];
-        yv[a] = acc;
+    __syncthreads();
+    // L U y = g on wave 0 by columns, lane a = entry a: forward (unit lower, terms in
+    // ascending order), then backward from the last entry
+    if (wid == 0 && !s_fail) {
+      const int a = lane;
+      double acc = a < k2 ? gv[a] : 0.0;
+      for (int l = 0; l < k2; ++l) {
+        const double yl = lane_bcast(acc, l);
+        if (a > l && a < k2) acc -= Gm[a + l * k] * yl;
       }
-      for (int a = k2 - 1; a >= 0; --a) {
-        double acc = yv[a];
-        for (int l = a + 1; l < k2; ++l) acc -= Gm[a + l * k] * yv[l];
-        yv[a] = acc / Gm[a + a * k];
+      for (int l = k2 - 1; l >= 0; --l) {
+        if (a == l) acc = acc / Gm[a + a * k];
+        const double yl = lane_bcast(acc, l);
+        if (a < l) acc -= Gm[a + l * k] * yl;
       }
+      if (a < k2) yv[a] = acc;
     }
   }
   __syncthreads();
