@@ -52,6 +52,7 @@ struct sa_seq {
   void *kry = nullptr;               // Krylov vectors (double, or float for inner solves)
   float *r32 = nullptr, *d32 = nullptr;  // mixed: inner right-hand side and correction
   long long *srht_rows = nullptr;
+  unsigned long long *srht_signs = nullptr;  // SRHT sign words (one bit per row of x)
   Ctl *ctl = nullptr;     // device control block (projection + outer solve)
   Ctl *ctl_in = nullptr;  // device control block of the inner solves (mixed)
   int *hbuf = nullptr;    // pinned host mirror of solver state (128 ints; from int 64 on the
@@ -117,7 +118,7 @@ void srht_rows_host(int64_t n, int s, uint64_t seed, std::vector<long long> &out
 }
 
 struct Layout {
-  size_t X, SX, Q1, kry, partials, rows, r32, d32, total;
+  size_t X, SX, Q1, kry, partials, rows, signs, r32, d32, total;
 };
 
 int validate(const sa_config *c) {
@@ -161,6 +162,8 @@ Layout layout(const sa_config *c) {
   off += up(partials_doubles(c->n, c->M, c->s) * sizeof(double));
   L.rows = off;
   off += up((size_t)c->s * sizeof(long long));
+  L.signs = off;
+  off += up((size_t)(c->n + 63) / 64 * sizeof(unsigned long long));
   L.r32 = L.d32 = 0;
   if (mixed) {
     L.r32 = off;
@@ -579,6 +582,7 @@ int sa_init_sequence(const sa_config *cfg, void *dev_ws, size_t ws_bytes, void *
   q->kry = q->ws + L.kry;
   q->partials = (double *)(q->ws + L.partials);
   q->srht_rows = (long long *)(q->ws + L.rows);
+  q->srht_signs = (unsigned long long *)(q->ws + L.signs);
   if (q->mixed) {
     q->r32 = (float *)(q->ws + L.r32);
     q->d32 = (float *)(q->ws + L.d32);
@@ -598,6 +602,7 @@ int sa_init_sequence(const sa_config *cfg, void *dev_ws, size_t ws_bytes, void *
   hipError_t e = hipSuccess;
   if (!rows.empty())
     e = hipMemcpyAsync(q->srht_rows, rows.data(), rows.size() * sizeof(long long), hipMemcpyHostToDevice, st);
+  if (e == hipSuccess && cfg->sketch == SA_SKETCH_SRHT) e = launch_srht_signs(q->srht_signs, cfg->n, cfg->seed, st);
   const size_t w = q->x32 ? sizeof(float) : sizeof(double);
   if (e == hipSuccess) e = hipMemsetAsync(q->X, 0, (size_t)q->ld * cfg->M * w, st);
   if (e == hipSuccess) e = hipMemsetAsync(q->SX, 0, (size_t)cfg->s * cfg->M * sizeof(double), st);
@@ -620,10 +625,10 @@ int push_enqueue(sa_seq *q, const void *x_dev, int zero_rhs, hipStream_t st) {
   const int slot = (int)(q->pushes % c.M);
   if (q->x32)
     HIP_TRY(launch_push<float>((const double *)x_dev, (float *)q->X, q->SX, c.n, q->ld, slot, c.s, c.sketch, c.seed,
-                               q->srht_rows, q->partials, q->ctl, zero_rhs, st));
+                               q->srht_rows, q->srht_signs, q->partials, q->ctl, zero_rhs, st));
   else
     HIP_TRY(launch_push<double>((const double *)x_dev, (double *)q->X, q->SX, c.n, q->ld, slot, c.s, c.sketch,
-                                c.seed, q->srht_rows, q->partials, q->ctl, zero_rhs, st));
+                                c.seed, q->srht_rows, q->srht_signs, q->partials, q->ctl, zero_rhs, st));
   if (q->mlp) {
     // target of the step whose solution this is: its sketched least-squares
     // coordinates in that step's history (before this push changes SX and T1)

@@ -621,4 +621,14 @@ __device__ inline double srht_sign(uint64_t j, uint64_t seed) {
   return ((word >> (j & 63)) & 1ull) ? -1.0 : 1.0;
 }
 
+// The bit words srht_sign draws from, word w = bits of entries 64 w .. 64 w + 63 (bit set:
+// sign -1); a sequence stores them once, so a push reads one word per 64 entries instead
+// of evaluating the generator.
+__device__ inline unsigned long long srht_sign_word(uint64_t w, uint64_t seed) {
+  return philox4x64(w >> 2, 0, STREAM_SRHT_SIGNS, 0, seed, 0).v[w & 3];
+}
+__device__ inline bool srht_negative(const unsigned long long *words, uint64_t j) {
+  return ((words[j >> 6] >> (j & 63)) & 1ull) != 0;
+}
+
 }  // namespace sacc

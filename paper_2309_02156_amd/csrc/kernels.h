@@ -22,10 +22,14 @@ hipError_t launch_spmv(const CsrView &A, const double *x, double *y, hipStream_t
 // TX = storage type of the history X and basis Q1 (double, or float in the mixed mode)
 // zero_rhs != 0: push zero instead of x when ctl's solve ended in the zero right-hand side
 // state (for a push enqueued before the host has read that state)
+// srht_signs: the sign words of launch_srht_signs (SRHT sketch only)
 template <typename TX>
 hipError_t launch_push(const double *x, TX *X, double *SX, int64_t n, int64_t ld, int slot, int s, int sketch,
-                       uint64_t seed, const long long *srht_rows, double *partials, const Ctl *ctl, int zero_rhs,
-                       hipStream_t st);
+                       uint64_t seed, const long long *srht_rows, const unsigned long long *srht_signs,
+                       double *partials, const Ctl *ctl, int zero_rhs, hipStream_t st);
+
+// the SRHT sign words of a sequence (ceil(n / 64) words), once at creation
+hipError_t launch_srht_signs(unsigned long long *words, int64_t n, uint64_t seed, hipStream_t st);
 
 // blocks along n of the push kernel (its partial rows per row group)
 int push_blocks_x(int64_t n, int s);

@@ -68,7 +68,8 @@ hipError_t launch_spmv(const CsrView &A, const double *x, double *y, hipStream_t
 template <int SK, typename TX>
 __global__ __launch_bounds__(TPB) void k_push(const double *x, TX *X, double *SX, int64_t n, int64_t ld, int slot,
                                               int s, uint64_t seed, const long long *rows,
-                                              double *partials, const Ctl *ctl, int zero_rhs) {
+                                              const unsigned long long *signs, double *partials,
+                                              const Ctl *ctl, int zero_rhs) {
   __shared__ double red[NWAVE * SKETCH_RG];
   __shared__ double outv[MAXS];
   __shared__ double scratch[TPB];
@@ -99,7 +100,7 @@ __global__ __launch_bounds__(TPB) void k_push(const double *x, TX *X, double *SX
         }
       }
     } else {
-      const double d = srht_sign((uint64_t)j, seed) * xj;
+      const double d = srht_negative(signs, (uint64_t)j) ? -xj : xj;
 #pragma unroll
       for (int r = 0; r < SKETCH_RG; ++r)
         acc[r] += (__popcll((unsigned long long)myrows[r] & (unsigned long long)j) & 1) ? -d : d;
@@ -113,6 +114,16 @@ __global__ __launch_bounds__(TPB) void k_push(const double *x, TX *X, double *SX
   block_sum_store<SKETCH_RG>(acc, rc, red, partials + (size_t)blk * SKETCH_RG);
 }
 
+__global__ __launch_bounds__(TPB) void k_srht_signs(unsigned long long *words, int64_t nw, uint64_t seed) {
+  GRID_ROWS(w, nw) words[w] = srht_sign_word((uint64_t)w, seed);
+}
+
+hipError_t launch_srht_signs(unsigned long long *words, int64_t n, uint64_t seed, hipStream_t st) {
+  const int64_t nw = (n + 63) / 64;
+  hipLaunchKernelGGL(k_srht_signs, dim3(stream_blocks(nw)), dim3(TPB), 0, st, words, nw, seed);
+  return hipGetLastError();
+}
+
 int push_blocks_x(int64_t n, int s) {
   const int ng = (s + SKETCH_RG - 1) / SKETCH_RG;
   int nbx = stream_blocks(n);
@@ -122,16 +133,16 @@ int push_blocks_x(int64_t n, int s) {
 
 template <typename TX>
 hipError_t launch_push(const double *x, TX *X, double *SX, int64_t n, int64_t ld, int slot, int s, int sketch,
-                       uint64_t seed, const long long *srht_rows, double *partials, const Ctl *ctl, int zero_rhs,
-                       hipStream_t st) {
+                       uint64_t seed, const long long *srht_rows, const unsigned long long *srht_signs,
+                       double *partials, const Ctl *ctl, int zero_rhs, hipStream_t st) {
   const int ng = (s + SKETCH_RG - 1) / SKETCH_RG;
   const int nbx = push_blocks_x(n, s);
   if (sketch == 0)
     hipLaunchKernelGGL((k_push<0, TX>), dim3(nbx, ng), dim3(TPB), 0, st, x, X, SX, n, ld, slot, s, seed,
-                       srht_rows, partials, ctl, zero_rhs);
+                       srht_rows, srht_signs, partials, ctl, zero_rhs);
   else
     hipLaunchKernelGGL((k_push<1, TX>), dim3(nbx, ng), dim3(TPB), 0, st, x, X, SX, n, ld, slot, s, seed,
-                       srht_rows, partials, ctl, zero_rhs);
+                       srht_rows, srht_signs, partials, ctl, zero_rhs);
   return hipGetLastError();
 }
 
@@ -966,7 +977,8 @@ hipError_t launch_ir_update(double *x, const float *d, int64_t n, hipStream_t st
 
 #define SACC_INSTANTIATE_PROJ(TX)                                                                              \
   template hipError_t launch_push<TX>(const double *, TX *, double *, int64_t, int64_t, int, int, int, uint64_t, \
-                                      const long long *, double *, const Ctl *, int, hipStream_t);             \
+                                      const long long *, const unsigned long long *, double *, const Ctl *, int, \
+                                      hipStream_t);                                                            \
   template hipError_t launch_basis<TX>(const TX *, TX *, int64_t, int64_t, int, Ctl *, hipStream_t);           \
   template hipError_t launch_spmm_gram<TX>(const CsrView &, const TX *, int64_t, const double *, int, int,    \
                                            double *, int *, Ctl *, hipStream_t);                               \
