@@ -483,8 +483,9 @@ int run_gmres(sa_seq *q, const CsrView &v, Ctl *ctl, const TV *b, TV *x, int max
       HIP_TRY(launch_gm_step<TV>(v, V, T, q->ld, j, cycle > 0 ? 1 : 0, q->partials, ctl, st, tp, serial));
     }
     if (stop) break;
-    if (!cut) HIP_TRY(launch_gm_finish<TV>(v, V, T, q->ld, c.restart, q->partials, ctl, st));
-    HIP_TRY(launch_gm_update<TV>(x, V, v.n, q->ld, c.restart, ctl, st));
+    // a full cycle: F(m), then the update closes step m - 1 itself
+    if (!cut) HIP_TRY(launch_gm_finish<TV>(v, V, T, q->ld, c.restart, q->partials, ctl, st, false));
+    HIP_TRY(launch_gm_update<TV>(x, V, v.n, q->ld, c.restart, ctl, st, q->partials, !cut));
     HIP_TRY(launch_gm_start<TV>(v, b, x, V, 1, q->partials, ctl, st));
   }
   // defer: only enqueue the final read of the state (poll_wait reads it); the GMRES

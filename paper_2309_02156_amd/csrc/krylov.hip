@@ -510,7 +510,11 @@ __device__ inline void close_stage(int j, const Ctl *ctl, CloseIn *ci) {
 // block, the rotated column included (lanes 0..j; j < 64).  Returns CLOSE_END when the
 // cycle ends, with CLOSE_EST when it ends on the residual estimate.
 enum : int { CLOSE_END = 1, CLOSE_EST = 2 };
-__device__ inline int gm_close_wave(int j, double hn, int it, const CloseIn *ci, Ctl *ctl, bool persist) {
+// With col_out / gam_out the rotated column (rows 0..j) and gam_j also go to those (LDS)
+// locations in every block; keep_active leaves ctl->active as it is (for a kernel whose
+// other blocks read it).
+__device__ inline int gm_close_wave(int j, double hn, int it, const CloseIn *ci, Ctl *ctl, bool persist,
+                                   double *col_out = nullptr, double *gam_out = nullptr, bool keep_active = false) {
   const int LD = MAXR + 1;
   const int lane = threadIdx.x % WAVE;
   double cv = ci->col[lane <= j ? lane : 0];
@@ -544,10 +548,12 @@ __device__ inline int gm_close_wave(int j, double hn, int it, const CloseIn *ci,
       ctl->vs[j + 1] = hn > 0.0 ? 1.0 / hn : 0.0;
       ctl->iters = it;
       ctl->jend = j + 1;
-      if (end) ctl->active = 0;
+      if (end && !keep_active) ctl->active = 0;
       if (est_conv && ci->trust) ctl->conv_pending = 1;
     }
   }
+  if (col_out && lane <= j) col_out[lane] = cv;
+  if (gam_out && lane == 0) *gam_out = gam_j;
   return end ? (CLOSE_END | (est_conv ? CLOSE_EST : 0)) : 0;
 }
 
@@ -1018,19 +1024,37 @@ __global__ __launch_bounds__(KTPB) void k_gm_close(const double *Pin, int nblk, 
 // End of a cycle: every block solves R y = gam (m x m upper triangular, staged in
 // LDS) and adds x += sum_l y_l v_l for its rows.  The block's column values are
 // requested before the triangular solve, which runs while they arrive; R = row tiles
-// per pass.
+// per pass.  jclose >= 0 (a cycle that ran all its steps): every block first closes step
+// jclose = m - 1 itself from the finalise-only F(m)'s partial rows (Pin, nblk), the work
+// of k_gm_close, and takes the rotated column and gam from that close; block 0 persists
+// it (not `active`, which the other blocks read here; the restart sets it).  When the
+// cycle had already ended (active = 0: its last close ran in G) the staged values serve.
 template <typename TV, int RB, int R>
-__global__ __launch_bounds__(KTPB) void k_gm_update(TV *x, const TV *V, int64_t n, int64_t ld, const Ctl *ctl) {
+__global__ __launch_bounds__(KTPB) void k_gm_update(TV *x, const TV *V, int64_t n, int64_t ld, Ctl *ctl,
+                                                    const double *Pin, int nblk, int jclose) {
   const int LD = MAXR + 1;
   __shared__ double coef[RB];
   __shared__ double Rs[RB * RB];
   __shared__ double gs[RB];
-  __shared__ int s_m;
+  __shared__ int s_m, s_close, s_ibase;
   __shared__ double vsh[RB];
+  __shared__ double outv[1];
+  __shared__ double scratch[KTPB];
+  __shared__ CloseIn ci;
   const int t = threadIdx.x;
+  const int z = vzero();
+  const int st = vread(&ctl->state, z), je = vread(&ctl->jend, z), act = vread(&ctl->active, z);
+  const int ib = vread(&ctl->ibase, z);
+  double pt[1];
+  if (jclose >= 0) {
+    close_stage(jclose, ctl, &ci);
+    final_part_load(Pin, nblk, KW, 1, pt);
+  }
   if (t == 0) {
-    const int st = ctl->state, je = ctl->jend;
-    s_m = (st == ST_RUN) ? je : -1;
+    const bool close = jclose >= 0 && st == ST_RUN && act;
+    s_close = close ? 1 : 0;
+    s_m = (st == ST_RUN) ? (close ? jclose + 1 : je) : -1;
+    s_ibase = ib;
   }
   // stage the whole triangle, right-hand side and scales at once (unused entries are
   // never read)
@@ -1045,6 +1069,14 @@ __global__ __launch_bounds__(KTPB) void k_gm_update(TV *x, const TV *V, int64_t 
   __syncthreads();
   const int m = s_m;
   if (m <= 0) return;
+  if (s_close) {
+    // hn = ||w''_m|| from F(m)'s partial rows; the close of step m - 1 on wave 0
+    final_tree(final_part_sum(Pin, nblk, KW, 1, pt), 1, outv, scratch);
+    if (t < WAVE)
+      gm_close_wave(jclose, sqrt(outv[0]), s_ibase + jclose + 1, &ci, ctl, blockIdx.x == 0, Rs + jclose * RB,
+                    gs + jclose, true);
+    __syncthreads();
+  }
   const int64_t stride = (int64_t)gridDim.x * (R * KTPB);
   int64_t r0 = (int64_t)blockIdx.x * (R * KTPB);
   TV vl[R][RB], xv[R];
@@ -1170,10 +1202,10 @@ hipError_t launch_gm_step(const CsrView &A, TV *V, TV *T, int64_t ld, int j, int
   return hipGetLastError();
 }
 
-// end of a cycle of m steps: F(m) finalise-only, close of step m - 1
+// end of a cycle of m steps: F(m) finalise-only, then (close) the close of step m - 1
 template <typename TV>
 hipError_t launch_gm_finish(const CsrView &A, TV *V, TV *T, int64_t ld, int m, double *partials, Ctl *ctl,
-                            hipStream_t st) {
+                            hipStream_t st, bool close) {
   const int nb = kblocks(A.n);
   if (m <= 8)
     gm_f_rb<TV, 8>(A, V, T, ld, m, 2, partials, ctl, st);
@@ -1181,27 +1213,31 @@ hipError_t launch_gm_finish(const CsrView &A, TV *V, TV *T, int64_t ld, int m, d
     gm_f_rb<TV, 16>(A, V, T, ld, m, 2, partials, ctl, st);
   else
     gm_f_rb<TV, 32>(A, V, T, ld, m, 2, partials, ctl, st);
-  hipLaunchKernelGGL(k_gm_close, dim3(1), dim3(KTPB), 0, st, PB(partials), nb, m - 1, ctl);
+  if (close) hipLaunchKernelGGL(k_gm_close, dim3(1), dim3(KTPB), 0, st, PB(partials), nb, m - 1, ctl);
   return hipGetLastError();
 }
 
 template <typename TV, int RB>
-static void gm_update_rb(TV *x, const TV *V, int64_t n, int64_t ld, Ctl *ctl, hipStream_t st) {
+static void gm_update_rb(TV *x, const TV *V, int64_t n, int64_t ld, Ctl *ctl, const double *Pin, int jclose,
+                         hipStream_t st) {
   const int nb = kblocks(n);
   if (gm_two_rows(n))
-    hipLaunchKernelGGL((k_gm_update<TV, RB, 2>), dim3(nb), dim3(KTPB), 0, st, x, V, n, ld, ctl);
+    hipLaunchKernelGGL((k_gm_update<TV, RB, 2>), dim3(nb), dim3(KTPB), 0, st, x, V, n, ld, ctl, Pin, nb, jclose);
   else
-    hipLaunchKernelGGL((k_gm_update<TV, RB, 1>), dim3(nb), dim3(KTPB), 0, st, x, V, n, ld, ctl);
+    hipLaunchKernelGGL((k_gm_update<TV, RB, 1>), dim3(nb), dim3(KTPB), 0, st, x, V, n, ld, ctl, Pin, nb, jclose);
 }
 
 template <typename TV>
-hipError_t launch_gm_update(TV *x, const TV *V, int64_t n, int64_t ld, int restart, Ctl *ctl, hipStream_t st) {
+hipError_t launch_gm_update(TV *x, const TV *V, int64_t n, int64_t ld, int restart, Ctl *ctl, hipStream_t st,
+                            double *partials, bool close_last) {
+  const double *Pin = partials ? PB(partials) : nullptr;
+  const int jclose = close_last ? restart - 1 : -1;
   if (restart <= 8)
-    gm_update_rb<TV, 8>(x, V, n, ld, ctl, st);
+    gm_update_rb<TV, 8>(x, V, n, ld, ctl, Pin, jclose, st);
   else if (restart <= 16)
-    gm_update_rb<TV, 16>(x, V, n, ld, ctl, st);
+    gm_update_rb<TV, 16>(x, V, n, ld, ctl, Pin, jclose, st);
   else
-    gm_update_rb<TV, 32>(x, V, n, ld, ctl, st);
+    gm_update_rb<TV, 32>(x, V, n, ld, ctl, Pin, jclose, st);
   return hipGetLastError();
 }
 
@@ -1215,8 +1251,9 @@ hipError_t launch_gm_update(TV *x, const TV *V, int64_t n, int64_t ld, int resta
   template hipError_t launch_gm_step<TV>(const CsrView &, TV *, TV *, int64_t, int, int, double *, Ctl *,        \
                                          hipStream_t, const KTiming *, int);                                     \
   template hipError_t launch_gm_finish<TV>(const CsrView &, TV *, TV *, int64_t, int, double *, Ctl *,           \
-                                           hipStream_t);                                                         \
-  template hipError_t launch_gm_update<TV>(TV *, const TV *, int64_t, int64_t, int, Ctl *, hipStream_t);
+                                           hipStream_t, bool);                                                   \
+  template hipError_t launch_gm_update<TV>(TV *, const TV *, int64_t, int64_t, int, Ctl *, hipStream_t, double *, \
+                                           bool);
 
 SACC_INSTANTIATE_KRYLOV(double)
 SACC_INSTANTIATE_KRYLOV(float)
