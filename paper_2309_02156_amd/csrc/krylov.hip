@@ -1171,12 +1171,20 @@ static void gm_f_rb(const CsrView &A, TV *V, TV *T, int64_t ld, int j, int mode,
   gm_f_launch<TV, RB, 1>(A, V, T, ld, j, mode, partials, ctl, st, tm);
 }
 
-// G takes one row tile per pass (measured faster than two for every column count: the
-// lower register count lets the first pass's loads overlap the close better)
+// G takes two row tiles per pass up to 8 columns on grids with two tiles per block, one
+// tile otherwise (measured: two tiles 6.2 against 6.4 us at 8 slots, equal at 16, slower
+// at 32 where the column values of two tiles take most of the registers)
 template <typename TV, int RB>
 static void gm_g_rb(const CsrView &A, TV *V, TV *T, int64_t ld, int j, double *partials, Ctl *ctl, hipStream_t st,
                     int serial) {
   const int nb = kblocks(A.n);
+  if constexpr (RB <= 8) {
+    if (gm_two_rows(A.n)) {
+      hipLaunchKernelGGL((k_gm_g<TV, RB, 2>), dim3(nb), dim3(KTPB), 0, st, V, T, A.n, ld, j, PB(partials), nb,
+                         PA(partials), ctl, serial);
+      return;
+    }
+  }
   hipLaunchKernelGGL((k_gm_g<TV, RB, 1>), dim3(nb), dim3(KTPB), 0, st, V, T, A.n, ld, j, PB(partials), nb,
                      PA(partials), ctl, serial);
 }

@@ -275,6 +275,30 @@ def test_zero_rhs_maxit_breakdown(sacc):
     assert info["rc"] == -5
 
 
+def test_step_gmres_zero_rhs_pushes_zero(sacc):
+    """sa_step with GMRES enqueues the push before it reads the final state: a step with
+    b = 0 still returns x = 0 and pushes a zero column (slot = pushes mod M).  The guess
+    is the previous solution, so the iterate the solve starts from is not zero."""
+    rng = np.random.default_rng(9)
+    n = 300
+    S = _spd_small(n, rng)
+    Ad = _dcsr(sacc, S)
+    seq = sacc.Sequence(n, 3, s=6, solver="gmres", tol=1e-10, restart=20, guess="previous")
+    for _ in range(2):
+        _, info = seq.step(Ad, dev(rng.standard_normal(n)))
+        assert info["rc"] == 0 and info["relres"] <= 1e-10
+    x, info = seq.step(Ad, dev(np.zeros(n)), dev(np.ones(n)))
+    assert info["rc"] == 0 and info["iters"] == 0 and info["relres"] == 0.0
+    assert np.all(host(x) == 0)
+    X, SX = seq.copy_state("X"), seq.copy_state("SX")
+    assert np.all(X[:, 2] == 0) and np.all(SX[:, 2] == 0)
+    assert np.all(np.any(X[:, :2] != 0, axis=0))
+    b = rng.standard_normal(n)
+    x, info = seq.step(Ad, dev(b))
+    assert info["rc"] == 0 and info["relres"] <= 1e-10
+    assert np.linalg.norm(b - S @ host(x)) <= 1e-10 * np.linalg.norm(b) * (1 + 1e-6)
+
+
 def test_history_edge_cases(sacc):
     rng = np.random.default_rng(6)
     n = 500
