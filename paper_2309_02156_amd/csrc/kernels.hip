@@ -446,7 +446,7 @@ __global__ __launch_bounds__(GRAM_TPB) void k_spmm_gram(const int *rowptr, const
       // nonzeros in groups of NZ (their columns and values loaded together), the basis
       // columns in chunks of CC: every gather of a chunk is issued before the first is
       // used (slots past the row's nonzeros or past k re-read a live entry, weight 0)
-      constexpr int NZ = 6, CC = 4;
+      constexpr int NZ = 5, CC = 4;
       const int p0 = rowptr[i], p1 = rowptr[i + 1];
       for (int pb = p0; pb < p1; pb += NZ) {
         int cj[NZ];
@@ -577,7 +577,9 @@ __global__ __launch_bounds__(TPB) void k_colsum(const double *partials, int nblk
   __shared__ double sc[TPB];
   const int e = blockIdx.x * 16 + threadIdx.x % 16, grp = threadIdx.x / 16;
   double s = 0.0;
+  // (unrolled so that a thread's row loads go out together: 18.8 -> 6.7 us over 768 rows)
   if (e < W)
+#pragma unroll 16
     for (int b = grp; b < nblk; b += 16) s += partials[(size_t)b * W + e];
   sc[threadIdx.x] = s;
   __syncthreads();
