@@ -172,8 +172,9 @@ int sa_solve(sa_seq *q, const sa_csr *A, const void *b_dev, void *x_dev, sa_info
  * float64, length n, out = x.  Fills info if non-NULL (the fields of both calls).
  * The solution is pushed also when the solve reports SA_NOTCONV or SA_EBREAKDOWN.  With
  * GMRES in float64 the push is enqueued before the host reads the solve's final state
- * and the call returns once that state has been read: the push (and the sketched QR
- * that follows it) may still be running on the stream.  Returns the solve's status, or
+ * and the call returns once that state has been read: the push, the sketched QR that
+ * follows it and the next step's basis Q1 = X T1 (projection guess; it depends on the
+ * history only) may still be running on the stream, and the next guess skips the basis.  Returns the solve's status, or
  * the first error (an error the host detects only from the final state, SA_EHIP, then
  * comes after the push). */
 int sa_step(sa_seq *q, const sa_csr *A, const void *b_dev, void *x_dev, sa_info *info, void *stream);

@@ -61,6 +61,7 @@ struct sa_seq {
   const Ctl *poll_ctl = nullptr;  // control block of the snapshot copy in flight (ev_poll)
   unsigned long long *mir[2] = {nullptr, nullptr};  // progress words of ctl and ctl_in (pinned)
   long long pushes = 0;
+  long long basis_for = -1;  // Q1 holds X T1 of the history after this many pushes
   int64_t ld = 0;  // leading dimension of X, Q1 and the Krylov vectors
   double tau_s = 1e-12, tau_c = 1e-12;
   hipEvent_t ev[4] = {nullptr, nullptr, nullptr, nullptr};
@@ -518,7 +519,10 @@ template <typename TX>
 int guess_projection(sa_seq *q, const CsrView &v, const double *b, double *x0, int cnt, hipStream_t st) {
   const sa_config &c = q->cfg;
   int nblk = 0;
-  HIP_TRY(launch_basis<TX>((const TX *)q->X, (TX *)q->Q1, c.n, q->ld, cnt, q->ctl, st));
+  if (q->basis_for != q->pushes) {
+    HIP_TRY(launch_basis<TX>((const TX *)q->X, (TX *)q->Q1, c.n, q->ld, cnt, q->ctl, st));
+    q->basis_for = q->pushes;
+  }
   HIP_TRY(launch_spmm_gram<TX>(v, (const TX *)q->Q1, q->ld, b, cnt, 0, q->partials, &nblk, q->ctl, st));
   HIP_TRY(launch_colsum(q->partials, nblk, cnt * (2 * cnt + 1), q->ctl, st));
   HIP_TRY(launch_small_solve(cnt, 0, c.solver == SA_CG ? 1 : 0, q->tau_c, q->ctl, st));
@@ -693,6 +697,20 @@ int guess_enqueue(sa_seq *q, const sa_csr *A, const void *b_dev, void *x0_dev, b
   return SA_OK;
 }
 
+// After a step's push: the next projection guess's basis Q1 = X T1 depends on the history
+// only, so it is enqueued at once (it runs while the host returns and prepares the next
+// system); guess_projection then skips it.
+int basis_ahead(sa_seq *q, hipStream_t st) {
+  const int cnt = count(q);
+  if (cnt == 0 || q->cfg.guess != SA_GUESS_PROJECTION) return SA_OK;
+  if (q->x32)
+    HIP_TRY(launch_basis<float>((const float *)q->X, (float *)q->Q1, q->cfg.n, q->ld, cnt, q->ctl, st));
+  else
+    HIP_TRY(launch_basis<double>((const double *)q->X, (double *)q->Q1, q->cfg.n, q->ld, cnt, q->ctl, st));
+  q->basis_for = q->pushes;
+  return SA_OK;
+}
+
 // the guess fields of info, after the stream has synchronized past guess_enqueue
 int guess_info(sa_seq *q, int cnt, sa_info *info) {
   const sa_config &c = q->cfg;
@@ -831,6 +849,7 @@ int sa_step(sa_seq *q, const sa_csr *A, const void *b_dev, void *x_dev, sa_info 
     if (rs != SA_OK && rs != SA_NOTCONV && rs != SA_EBREAKDOWN) return rs;
     if (info) SA_TRY(guess_info(q, cnt, info));
     SA_TRY(push_enqueue(q, x_dev, 0, st));
+    SA_TRY(basis_ahead(q, st));
     return rs;
   }
   // GMRES: the solve, the read of its final state and the push are all enqueued before
@@ -842,6 +861,7 @@ int sa_step(sa_seq *q, const sa_csr *A, const void *b_dev, void *x_dev, sa_info 
   SA_TRY(run_gmres<double>(q, view(A), q->ctl, (const double *)b_dev, (double *)x_dev, c.maxit, st, true));
   if (info) HIP_TRY(hipEventRecord(q->ev[3], st));
   SA_TRY(push_enqueue(q, x_dev, 1, st));
+  SA_TRY(basis_ahead(q, st));
   SA_TRY(poll_wait(q));
   const int state = q->hbuf[0];
   if (state < ST_RUN || state > ST_ZERO_RHS) return SA_EHIP;
