@@ -748,14 +748,22 @@ __global__ __launch_bounds__(KTPB) void k_gm_f(const int *rowptr, const int *col
 #pragma unroll
   for (int l = 0; l < RB; ++l) acc[l] = 0.0;
   bool first = true;
+  // SpMV round 1 of a pass: columns and values (issued unconditionally: a branch around
+  // them would make the column loads below wait for them).  With one row tile per pass
+  // the next pass's round 1 is requested before this pass's arithmetic (its row pointers
+  // with this pass's first loads), so a later pass starts with its gathers.
+  StageRound<C> sr;
+  if constexpr (R == 1)
+    stage_load<C>(sr, col, val, __builtin_amdgcn_readfirstlane(pr.p0), __builtin_amdgcn_readfirstlane(pr.p1));
   for (; r0 < n; r0 += stride) {
     const bool spmv = mode != 2;
     const int p0 = __builtin_amdgcn_readfirstlane(pr.p0), p1 = __builtin_amdgcn_readfirstlane(pr.p1);
     const bool staged = spmv && p1 > p0 && p1 - p0 <= CAP;
-    // SpMV round 1: columns and values (issued unconditionally: a branch around them
-    // would make the column loads below wait for them)
-    StageRound<C> sr;
-    stage_load<C>(sr, col, val, p0, p1);
+    PassRows<R> prn;
+    if constexpr (R == 1)
+      prn = pass_rows<R>(rowptr, n, r0 + stride, z);  // in bounds past the last pass
+    else
+      stage_load<C>(sr, col, val, p0, p1);
     // with 16 or more slots the gathers go out before the column stream too (their LDS
     // write and the row sums then overlap the stream; measured faster there, slower at 8)
     constexpr bool gathers_first = RB >= 16;
@@ -829,8 +837,14 @@ __global__ __launch_bounds__(KTPB) void k_gm_f(const int *rowptr, const int *col
       }
     }
     __syncthreads();  // fco / cco visible; prod free for the next pass
-    // the next pass's row pointers, requested before this pass's arithmetic
-    if (r0 + stride < n) pr = pass_rows<R>(rowptr, n, r0 + stride, z);
+    if constexpr (R == 1) {
+      // the next pass's round 1 (past the last pass: in-bounds loads nobody uses)
+      pr = prn;
+      stage_load<C>(sr, col, val, __builtin_amdgcn_readfirstlane(pr.p0), __builtin_amdgcn_readfirstlane(pr.p1));
+    } else {
+      // the next pass's row pointers, requested before this pass's arithmetic
+      if (r0 + stride < n) pr = pass_rows<R>(rowptr, n, r0 + stride, z);
+    }
     const double cj = cco[j < RB ? j : RB];
 #pragma unroll
     for (int u = 0; u < R; ++u) {
