@@ -1171,12 +1171,14 @@ static void gm_f_launch(const CsrView &A, TV *V, TV *T, int64_t ld, int j, int m
                           (const double *)valp, V, T, A.n, ld, j, mode, PA(partials), nb, PB(partials), ctl, lidx);
 }
 
-// F takes two row tiles per pass only up to 16 columns (at 32 the column values, the
-// dots and a staging round no longer fit in the registers of two waves per SIMD)
+// F takes two row tiles per pass only at 8 slots on grids with two tiles per block
+// (measured 9.5 against 9.8 us); from 16 slots one tile per pass with the next pass's
+// SpMV round requested ahead is faster (12.9 against 13.8 us at j = 12), and at 32 two
+// tiles would not fit in the registers of two waves per SIMD
 template <typename TV, int RB>
 static void gm_f_rb(const CsrView &A, TV *V, TV *T, int64_t ld, int j, int mode, double *partials, Ctl *ctl,
                     hipStream_t st, const KTiming *tm = nullptr) {
-  if constexpr (RB <= 16) {
+  if constexpr (RB <= 8) {
     if (gm_two_rows(A.n)) {
       gm_f_launch<TV, RB, 2>(A, V, T, ld, j, mode, partials, ctl, st, tm);
       return;
@@ -1287,7 +1289,7 @@ int64_t padded_ld(int64_t n) { return (n + 511) / 512 * 512 + 576; }
 
 size_t krylov_partials_doubles() { return (size_t)2 * KMAXBLK * KW; }
 
-int gm_f_rows_per_thread(int64_t n, int rb) { return rb <= 16 && gm_two_rows(n) ? 2 : 1; }
+int gm_f_rows_per_thread(int64_t n, int rb) { return rb <= 8 && gm_two_rows(n) ? 2 : 1; }
 
 int cg_rows_per_thread(int64_t n) { return cg_rows(n); }
 
