@@ -8,11 +8,13 @@
 //   small     pivoted Cholesky of G = Q1^T Q1 (Cholesky-QR finish), reduced Galerkin
 //             system R2^-T (Q1^T A Q1) R2^-1 y = R2^-T Q1^T b, c = R2^-1 y
 //   x0        x0 = Q1 c
-//   Krylov    CG (3 kernels / iteration) or GMRES with classical Gram-Schmidt applied
-//             twice (3 kernels / Arnoldi step), device-side scalars and stopping tests.
+//   Krylov    CG (2 kernels / iteration) or GMRES with classical Gram-Schmidt applied
+//             twice (2 kernels / Arnoldi step), device-side scalars and stopping tests
+//             (krylov.hip).
 //
-// Reductions are deterministic: per-block partial sums in fixed order, reduced by the
-// last block to arrive (or a column-sum kernel), never by floating-point atomics.
+// Reductions are deterministic: per-block partial sums in fixed order, reduced in a
+// fixed order by the kernel that follows (or a column-sum kernel), never by
+// floating-point atomics.
 #include <math.h>
 
 #include "common.h"

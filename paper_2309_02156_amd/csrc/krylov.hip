@@ -438,8 +438,10 @@ hipError_t launch_cg_iter(const CsrView &A, TV *x, TV *r, TV *p2, TV *q, double 
 //         end-of-cycle test); h1 = V_j^T A v_j; w'_{j+1} = A v_j - V h1 into T;
 //         partial dots V[:, k]^T w'_{j+1} (the second pass of step j).
 // F(0) instead reduces the start kernel's partials (||r||^2, ||b||^2) and opens the
-// cycle.  After G(m-1): F(m) in finalise-only mode and a one-block close of step m-1;
-// then the update x += V y.  The pair (F, G) reads V twice per step, the same as
+// cycle.  After G(m-1): F(m) in finalise-only mode, then the update x += V y, whose
+// blocks first close step m - 1 themselves (a cycle cut short by its close in G goes
+// to the update directly; the one-block close kernel k_gm_close remains for callers
+// of launch_gm_finish with close).  The pair (F, G) reads V twice per step, the same as
 // CGS2 needs for its two projections, and the second projection of step j shares
 // the pass of the SpMV of step j + 1.
 //
