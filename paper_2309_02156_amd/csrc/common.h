@@ -512,22 +512,40 @@ __device__ inline TileRowsR<R> tile_spmv_stage_r(const int *__restrict__ rowptr,
     tr.direct = 1;
     return tr;
   }
-  for (int base = p0; base < p1; base += C * NT) {
-    int cc[C];
-    double vv[C], xx[C];
+  // rounds of C nonzeros per thread, software-pipelined: a round's gathers and the next
+  // round's column / value loads are in flight together, so a round costs one trip to
+  // memory instead of two (loads past the range re-read an in-bounds entry)
+  int cc[C];
+  double vv[C];
 #pragma unroll
-    for (int u = 0; u < C; ++u) {
-      const int p = base + t + u * NT;
-      const int pc = p < p1 ? p : p1 - 1;
-      cc[u] = col[pc];
-      vv[u] = (double)val[pc];
-    }
+  for (int u = 0; u < C; ++u) {
+    const int p = p0 + t + u * NT;
+    const int pc = p < p1 ? p : (p1 > 0 ? p1 - 1 : 0);
+    cc[u] = col[pc];
+    vv[u] = (double)val[pc];
+  }
+  for (int base = p0; base < p1; base += C * NT) {
+    double xx[C];
 #pragma unroll
     for (int u = 0; u < C; ++u) xx[u] = gx(cc[u]);
+    int cn[C];
+    double vn[C];
+#pragma unroll
+    for (int u = 0; u < C; ++u) {
+      const int p = base + C * NT + t + u * NT;
+      const int pc = p < p1 ? p : p1 - 1;
+      cn[u] = col[pc];
+      vn[u] = (double)val[pc];
+    }
 #pragma unroll
     for (int u = 0; u < C; ++u) {
       const int p = base + t + u * NT;
       if (p < p1) prod[p - p0] = vv[u] * xx[u];
+    }
+#pragma unroll
+    for (int u = 0; u < C; ++u) {
+      cc[u] = cn[u];
+      vv[u] = vn[u];
     }
   }
   return tr;
