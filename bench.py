@@ -354,7 +354,7 @@ def main():
                     help="also run the float32-operator comparator on the 512 x 512 GMRES sequence")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(f"bench.py: this build runs on one GPU; --gpus {args.gpus} is not supported "
+        print(f"bench.py: the benchmark runs on one GPU; --gpus {args.gpus} is not supported "
               "(independent sequences would shard across GPUs with no communication).", file=sys.stderr)
         sys.exit(2)
 
