@@ -346,6 +346,8 @@ def main():
     ap.add_argument("--batch-warmup", type=int, default=31)
     ap.add_argument("--batch-steps", type=int, default=10)
     ap.add_argument("--only-batch", action="store_true", help="run only the batched workload")
+    ap.add_argument("--only-mixed", action="store_true",
+                    help="run only the 128^3 CG mixed-precision comparator (fp64, mixed, mixed_krylov)")
     ap.add_argument("--learned-train", type=int, default=200)
     ap.add_argument("--learned-eval", type=int, default=100)
     ap.add_argument("--mixed-warmup", type=int, default=32)
@@ -366,6 +368,9 @@ def main():
 
     if args.only_batch:
         print(json.dumps({"batch64": batch_cmp(sacc, torch, np, args.batch_warmup, args.batch_steps)}), flush=True)
+        return
+    if args.only_mixed:
+        print(json.dumps({"mixed_3d": mixed_3d(sacc, torch, np, args.mixed_warmup, args.mixed_steps)}), flush=True)
         return
 
     p, method = config(1)
