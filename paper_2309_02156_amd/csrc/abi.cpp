@@ -447,6 +447,7 @@ int run_gmres(sa_seq *q, const CsrView &v, Ctl *ctl, const TV *b, TV *x, int max
   HIP_TRY(launch_gm_start<TV>(v, b, x, V, 0, q->partials, ctl, st));
   bool stop = false;
   bool est_end = false;  // the last cycle ended on its residual estimate
+  const bool from_g = gm_norm_in_g(c.restart);  // G(m - 1) records ||w'_m||^2 (no F(m))
   // every cycle either adds an iteration or ends the solve in its first step
   for (long long cycle = 0; !stop; ++cycle) {
     if (cycle > (long long)maxit + 4) return SA_EHIP;
@@ -481,12 +482,14 @@ int run_gmres(sa_seq *q, const CsrView &v, Ctl *ctl, const TV *b, TV *x, int max
       }
       // (the restart's first step reports in any case when the host will wait for it)
       const int serial = pg.next() | ((est_end && j == 0) ? MIR_REPORT : 0);
-      HIP_TRY(launch_gm_step<TV>(v, V, T, q->ld, j, cycle > 0 ? 1 : 0, q->partials, ctl, st, tp, serial));
+      HIP_TRY(launch_gm_step<TV>(v, V, T, q->ld, j, cycle > 0 ? 1 : 0, q->partials, ctl, st, tp, serial,
+                                 from_g && j + 1 == c.restart));
     }
     if (stop) break;
-    // a full cycle: F(m), then the update closes step m - 1 itself
-    if (!cut) HIP_TRY(launch_gm_finish<TV>(v, V, T, q->ld, c.restart, q->partials, ctl, st, false));
-    HIP_TRY(launch_gm_update<TV>(x, V, v.n, q->ld, c.restart, ctl, st, q->partials, !cut));
+    // a full cycle: the update closes step m - 1 itself, from G(m - 1)'s partial rows
+    // (||w''_m|| from ||w'_m|| and the second-pass coefficients) or after a finalise F(m)
+    if (!cut && !from_g) HIP_TRY(launch_gm_finish<TV>(v, V, T, q->ld, c.restart, q->partials, ctl, st, false));
+    HIP_TRY(launch_gm_update<TV>(x, V, v.n, q->ld, c.restart, ctl, st, q->partials, !cut, from_g));
     HIP_TRY(launch_gm_start<TV>(v, b, x, V, 1, q->partials, ctl, st));
   }
   // defer: only enqueue the final read of the state (poll_wait reads it); the GMRES

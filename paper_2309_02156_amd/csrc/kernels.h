@@ -100,16 +100,19 @@ hipError_t launch_gm_start(const CsrView &A, const TV *b, const TV *x, TV *V, in
 // tm (may be null) times the step's first kernel (SpMV, finalisation, first dots)
 template <typename TV>
 hipError_t launch_gm_step(const CsrView &A, TV *V, TV *T, int64_t ld, int j, int first_mode, double *partials,
-                          Ctl *ctl, hipStream_t st, const KTiming *tm = nullptr, int serial = 0);
+                          Ctl *ctl, hipStream_t st, const KTiming *tm = nullptr, int serial = 0,
+                          bool norm_w = false);
 // end of a full cycle: F(m) finalise-only, and with close the one-block close of step m - 1
 template <typename TV>
 hipError_t launch_gm_finish(const CsrView &A, TV *V, TV *T, int64_t ld, int m, double *partials, Ctl *ctl,
                             hipStream_t st, bool close = true);
-// x += V y at the end of a cycle; close_last: close step m - 1 first from F(m)'s partial
-// rows (in every block, instead of the finish's one-block close)
+// x += V y at the end of a cycle; close_last: close step m - 1 first (in every block,
+// instead of the finish's one-block close) from F(m)'s partial rows, or with from_g from
+// G(m - 1)'s (no F(m) needed; only when gm_norm_in_g(m))
 template <typename TV>
 hipError_t launch_gm_update(TV *x, const TV *V, int64_t n, int64_t ld, int restart, Ctl *ctl, hipStream_t st,
-                            double *partials = nullptr, bool close_last = false);
+                            double *partials = nullptr, bool close_last = false, bool from_g = false);
+bool gm_norm_in_g(int m);
 size_t krylov_partials_doubles();
 // row tiles per pass of the GMRES kernel F (1 or 2) for n rows and rb column slots
 int gm_f_rows_per_thread(int64_t n, int rb);

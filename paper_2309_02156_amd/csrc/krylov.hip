@@ -446,7 +446,7 @@ hipError_t launch_cg_iter(const CsrView &A, TV *x, TV *r, TV *p2, TV *q, double 
 // the pass of the SpMV of step j + 1.
 //
 // Partial rows: start [||r||^2, ||b||^2] -> PA; F: [||w''_j||^2, V_j^T y, V_{0..j-1}^T y]
-// -> PB; G: [V_{0..j}^T w'] -> PA.
+// -> PB; G: [V_{0..j}^T w' (, ||w'||^2 at the last step of a full cycle)] -> PA.
 
 template <typename VT, typename TV>
 __global__ __launch_bounds__(KTPB) void k_gm_start(const int *rowptr, const int *col, const VT *val,
@@ -884,8 +884,10 @@ __global__ __launch_bounds__(KTPB) void k_gm_f(const int *rowptr, const int *col
 
 // G(j); R = row tiles of KTPB rows each block takes per pass.  One trip for the
 // control block and F(j)'s partial rows; then the first pass's columns are requested
-// before the reduction and the close of step j - 1 run, which they overlap.
-template <typename TV, int RB, int R>
+// before the reduction and the close of step j - 1 run, which they overlap.  NW (the
+// last step of a full cycle, j + 1 < RB): ||w'||^2 also goes to the partial rows, in
+// slot j + 1, for the close of step j at the cycle end.
+template <typename TV, int RB, int R, bool NW>
 __global__ __launch_bounds__(KTPB) void k_gm_g(const TV *V, TV *T, int64_t n, int64_t ld, int j, const double *Pin,
                                                int nblk, double *Pout, Ctl *ctl, int serial) {
   const int LD = MAXR + 1;
@@ -986,7 +988,7 @@ __global__ __launch_bounds__(KTPB) void k_gm_g(const TV *V, TV *T, int64_t n, in
   } else if (j == 0 && blockIdx.x == 0 && t == 0) {
     mirror_report(mir, serial, 0u);
   }
-  double acc[RB];
+  double acc[RB], ww = 0.0;
 #pragma unroll
   for (int l = 0; l < RB; ++l) acc[l] = 0.0;
 #pragma unroll 1
@@ -1006,13 +1008,20 @@ __global__ __launch_bounds__(KTPB) void k_gm_g(const TV *V, TV *T, int64_t n, in
         const double wd = (double)ws;
 #pragma unroll
         for (int k = 0; k < RB; ++k) acc[k] += (double)vl[u][k] * wd;
+        if constexpr (NW) ww += wd * wd;
       }
     }
     r0 += stride;
     if (r0 >= n) break;
     load_pass(r0);
   }
-  kstore<RB>(acc, j + 1, red, Pout + (size_t)blockIdx.x * KW);
+  if constexpr (NW) {
+    // ||w'||^2 in slot j + 1 (a column past the live ones)
+#pragma unroll
+    for (int k = 0; k < RB; ++k)
+      if (k == j + 1) acc[k] = ww;
+  }
+  kstore<RB>(acc, NW ? j + 2 : j + 1, red, Pout + (size_t)blockIdx.x * KW);
 }
 
 // close of the last step of a cycle (after the finalise-only F(m))
@@ -1041,30 +1050,38 @@ __global__ __launch_bounds__(KTPB) void k_gm_close(const double *Pin, int nblk, 
 // LDS) and adds x += sum_l y_l v_l for its rows.  The block's column values are
 // requested before the triangular solve, which runs while they arrive; R = row tiles
 // per pass.  jclose >= 0 (a cycle that ran all its steps): every block first closes step
-// jclose = m - 1 itself from the finalise-only F(m)'s partial rows (Pin, nblk), the work
-// of k_gm_close, and takes the rotated column and gam from that close; block 0 persists
-// it (not `active`, which the other blocks read here; the restart sets it).  When the
-// cycle had already ended (active = 0: its last close ran in G) the staged values serve.
+// jclose = m - 1 itself, the work of k_gm_close, and takes the rotated column and gam
+// from that close; block 0 persists it (not `active`, which the other blocks read here;
+// the restart sets it).  The close's inputs come from the finalise-only F(m)'s partial
+// rows (Pin = ||w''_m||^2), or with pyth from G(m - 1)'s (Pin = V^T w'_m and ||w'_m||^2):
+// the second-pass coefficients g, column m - 1 of H = h1 + g, and ||w''_m||^2 =
+// ||w'_m||^2 - ||g||^2 (w''_m = w'_m - V g with V orthonormal; g is the small second
+// correction, so there is no cancellation), which saves F(m).  When the cycle had
+// already ended (active = 0: its last close ran in G) the staged values serve.
 template <typename TV, int RB, int R>
 __global__ __launch_bounds__(KTPB) void k_gm_update(TV *x, const TV *V, int64_t n, int64_t ld, Ctl *ctl,
-                                                    const double *Pin, int nblk, int jclose) {
+                                                    const double *Pin, int nblk, int jclose, int pyth) {
   const int LD = MAXR + 1;
   __shared__ double coef[RB];
   __shared__ double Rs[RB * RB];
   __shared__ double gs[RB];
   __shared__ int s_m, s_close, s_ibase;
   __shared__ double vsh[RB];
-  __shared__ double outv[1];
+  __shared__ double outv[RB + 2];
   __shared__ double scratch[KTPB];
+  __shared__ double gsq[RB];
   __shared__ CloseIn ci;
   const int t = threadIdx.x;
   const int z = vzero();
   const int st = vread(&ctl->state, z), je = vread(&ctl->jend, z), act = vread(&ctl->active, z);
   const int ib = vread(&ctl->ibase, z);
-  double pt[1];
+  // partial entries: 1 (F(m)'s ||w''||^2) or m + 1 (G(m - 1)'s dots and ||w'||^2)
+  const int kc = pyth ? jclose + 2 : 1;
+  double pt[RB / 2];
+  const double h1_t = ctl->h1[t <= jclose ? t : 0];
   if (jclose >= 0) {
     close_stage(jclose, ctl, &ci);
-    final_part_load(Pin, nblk, KW, 1, pt);
+    final_part_load(Pin, nblk, KW, kc, pt);
   }
   if (t == 0) {
     const bool close = jclose >= 0 && st == ST_RUN && act;
@@ -1086,11 +1103,28 @@ __global__ __launch_bounds__(KTPB) void k_gm_update(TV *x, const TV *V, int64_t 
   const int m = s_m;
   if (m <= 0) return;
   if (s_close) {
-    // hn = ||w''_m|| from F(m)'s partial rows; the close of step m - 1 on wave 0
-    final_tree(final_part_sum(Pin, nblk, KW, 1, pt), 1, outv, scratch);
+    // hn = ||w''_m||; the close of step m - 1 on wave 0
+    final_tree(final_part_sum(Pin, nblk, KW, kc, pt), kc, outv, scratch);
+    double hn;
+    if (pyth) {
+      // column m - 1 of H and ||g||^2 (every block, the same fixed order)
+      if (t <= jclose) {
+        const double g = outv[t] * vsh[t];
+        ci.col[t] = h1_t + g;
+        gsq[t] = g * g;
+        if (blockIdx.x == 0) ctl->Hraw[t + jclose * LD] = h1_t + g;
+      }
+      __syncthreads();
+      double gg = 0.0;
+      for (int l = 0; l <= jclose; ++l) gg += gsq[l];
+      const double hh = outv[jclose + 1] - gg;
+      hn = hh > 0.0 ? sqrt(hh) : 0.0;
+    } else {
+      hn = sqrt(outv[0]);
+    }
     if (t < WAVE)
-      gm_close_wave(jclose, sqrt(outv[0]), s_ibase + jclose + 1, &ci, ctl, blockIdx.x == 0, Rs + jclose * RB,
-                    gs + jclose, true);
+      gm_close_wave(jclose, hn, s_ibase + jclose + 1, &ci, ctl, blockIdx.x == 0, Rs + jclose * RB, gs + jclose,
+                    true);
     __syncthreads();
   }
   const int64_t stride = (int64_t)gridDim.x * (R * KTPB);
@@ -1192,26 +1226,35 @@ static void gm_f_rb(const CsrView &A, TV *V, TV *T, int64_t ld, int j, int mode,
 // G takes two row tiles per pass up to 8 columns on grids with two tiles per block, one
 // tile otherwise (measured: two tiles 6.2 against 6.4 us at 8 slots, equal at 16, slower
 // at 32 where the column values of two tiles take most of the registers)
-template <typename TV, int RB>
-static void gm_g_rb(const CsrView &A, TV *V, TV *T, int64_t ld, int j, double *partials, Ctl *ctl, hipStream_t st,
-                    int serial) {
+template <typename TV, int RB, bool NW>
+static void gm_g_rb_nw(const CsrView &A, TV *V, TV *T, int64_t ld, int j, double *partials, Ctl *ctl, hipStream_t st,
+                       int serial) {
   const int nb = kblocks(A.n);
   if constexpr (RB <= 8) {
     if (gm_two_rows(A.n)) {
-      hipLaunchKernelGGL((k_gm_g<TV, RB, 2>), dim3(nb), dim3(KTPB), 0, st, V, T, A.n, ld, j, PB(partials), nb,
+      hipLaunchKernelGGL((k_gm_g<TV, RB, 2, NW>), dim3(nb), dim3(KTPB), 0, st, V, T, A.n, ld, j, PB(partials), nb,
                          PA(partials), ctl, serial);
       return;
     }
   }
-  hipLaunchKernelGGL((k_gm_g<TV, RB, 1>), dim3(nb), dim3(KTPB), 0, st, V, T, A.n, ld, j, PB(partials), nb,
+  hipLaunchKernelGGL((k_gm_g<TV, RB, 1, NW>), dim3(nb), dim3(KTPB), 0, st, V, T, A.n, ld, j, PB(partials), nb,
                      PA(partials), ctl, serial);
 }
 
+template <typename TV, int RB>
+static void gm_g_rb(const CsrView &A, TV *V, TV *T, int64_t ld, int j, double *partials, Ctl *ctl, hipStream_t st,
+                    int serial, bool nw) {
+  if (nw && j + 1 < RB)
+    gm_g_rb_nw<TV, RB, true>(A, V, T, ld, j, partials, ctl, st, serial);
+  else
+    gm_g_rb_nw<TV, RB, false>(A, V, T, ld, j, partials, ctl, st, serial);
+}
+
 // Arnoldi step j of a cycle: F(j), G(j).  first_mode: 0 first cycle, 1 restart
-// (used at j = 0).
+// (used at j = 0); norm_w: G(j) also records ||w'||^2 (see k_gm_g).
 template <typename TV>
 hipError_t launch_gm_step(const CsrView &A, TV *V, TV *T, int64_t ld, int j, int first_mode, double *partials,
-                          Ctl *ctl, hipStream_t st, const KTiming *tm, int serial) {
+                          Ctl *ctl, hipStream_t st, const KTiming *tm, int serial, bool norm_w) {
   const int mode = j == 0 ? first_mode : 0;
   if (j <= 8)
     gm_f_rb<TV, 8>(A, V, T, ld, j, mode, partials, ctl, st, tm);
@@ -1220,11 +1263,11 @@ hipError_t launch_gm_step(const CsrView &A, TV *V, TV *T, int64_t ld, int j, int
   else
     gm_f_rb<TV, 32>(A, V, T, ld, j, mode, partials, ctl, st, tm);
   if (j < 8)
-    gm_g_rb<TV, 8>(A, V, T, ld, j, partials, ctl, st, serial);
+    gm_g_rb<TV, 8>(A, V, T, ld, j, partials, ctl, st, serial, norm_w);
   else if (j < 16)
-    gm_g_rb<TV, 16>(A, V, T, ld, j, partials, ctl, st, serial);
+    gm_g_rb<TV, 16>(A, V, T, ld, j, partials, ctl, st, serial, norm_w);
   else
-    gm_g_rb<TV, 32>(A, V, T, ld, j, partials, ctl, st, serial);
+    gm_g_rb<TV, 32>(A, V, T, ld, j, partials, ctl, st, serial, norm_w);
   return hipGetLastError();
 }
 
@@ -1245,25 +1288,32 @@ hipError_t launch_gm_finish(const CsrView &A, TV *V, TV *T, int64_t ld, int m, d
 
 template <typename TV, int RB>
 static void gm_update_rb(TV *x, const TV *V, int64_t n, int64_t ld, Ctl *ctl, const double *Pin, int jclose,
-                         hipStream_t st) {
+                         int pyth, hipStream_t st) {
   const int nb = kblocks(n);
   if (gm_two_rows(n))
-    hipLaunchKernelGGL((k_gm_update<TV, RB, 2>), dim3(nb), dim3(KTPB), 0, st, x, V, n, ld, ctl, Pin, nb, jclose);
+    hipLaunchKernelGGL((k_gm_update<TV, RB, 2>), dim3(nb), dim3(KTPB), 0, st, x, V, n, ld, ctl, Pin, nb, jclose,
+                       pyth);
   else
-    hipLaunchKernelGGL((k_gm_update<TV, RB, 1>), dim3(nb), dim3(KTPB), 0, st, x, V, n, ld, ctl, Pin, nb, jclose);
+    hipLaunchKernelGGL((k_gm_update<TV, RB, 1>), dim3(nb), dim3(KTPB), 0, st, x, V, n, ld, ctl, Pin, nb, jclose,
+                       pyth);
 }
+
+// whether G(m - 1) stores ||w'_m||^2 (a spare slot past its live columns): then a full
+// cycle of m steps needs no finalise step F(m)
+bool gm_norm_in_g(int m) { return m >= 1 && m < 32 && m != 8 && m != 16; }
 
 template <typename TV>
 hipError_t launch_gm_update(TV *x, const TV *V, int64_t n, int64_t ld, int restart, Ctl *ctl, hipStream_t st,
-                            double *partials, bool close_last) {
-  const double *Pin = partials ? PB(partials) : nullptr;
+                            double *partials, bool close_last, bool from_g) {
+  const int pyth = close_last && from_g ? 1 : 0;
+  const double *Pin = partials ? (pyth ? PA(partials) : PB(partials)) : nullptr;
   const int jclose = close_last ? restart - 1 : -1;
   if (restart <= 8)
-    gm_update_rb<TV, 8>(x, V, n, ld, ctl, Pin, jclose, st);
+    gm_update_rb<TV, 8>(x, V, n, ld, ctl, Pin, jclose, pyth, st);
   else if (restart <= 16)
-    gm_update_rb<TV, 16>(x, V, n, ld, ctl, Pin, jclose, st);
+    gm_update_rb<TV, 16>(x, V, n, ld, ctl, Pin, jclose, pyth, st);
   else
-    gm_update_rb<TV, 32>(x, V, n, ld, ctl, Pin, jclose, st);
+    gm_update_rb<TV, 32>(x, V, n, ld, ctl, Pin, jclose, pyth, st);
   return hipGetLastError();
 }
 
@@ -1275,11 +1325,11 @@ hipError_t launch_gm_update(TV *x, const TV *V, int64_t n, int64_t ld, int resta
   template hipError_t launch_gm_start<TV>(const CsrView &, const TV *, const TV *, TV *, int, double *, Ctl *,   \
                                           hipStream_t);                                                          \
   template hipError_t launch_gm_step<TV>(const CsrView &, TV *, TV *, int64_t, int, int, double *, Ctl *,        \
-                                         hipStream_t, const KTiming *, int);                                     \
+                                         hipStream_t, const KTiming *, int, bool);                               \
   template hipError_t launch_gm_finish<TV>(const CsrView &, TV *, TV *, int64_t, int, double *, Ctl *,           \
                                            hipStream_t, bool);                                                   \
   template hipError_t launch_gm_update<TV>(TV *, const TV *, int64_t, int64_t, int, Ctl *, hipStream_t, double *, \
-                                           bool);
+                                           bool, bool);
 
 SACC_INSTANTIATE_KRYLOV(double)
 SACC_INSTANTIATE_KRYLOV(float)
