@@ -1102,9 +1102,27 @@ __global__ __launch_bounds__(KTPB) void k_gm_update(TV *x, const TV *V, int64_t 
   __syncthreads();
   const int m = s_m;
   if (m <= 0) return;
+  const int64_t stride = (int64_t)gridDim.x * (R * KTPB);
+  int64_t r0 = (int64_t)blockIdx.x * (R * KTPB);
+  TV vl[R][RB], xv[R];
+  auto load_pass = [&](int64_t rb) {
+#pragma unroll
+    for (int u = 0; u < R; ++u) {
+      const int64_t i = rb + (int64_t)u * KTPB + t;
+      const int64_t ic = i < n ? i : n - 1;
+#pragma unroll
+      for (int l = 0; l < RB; ++l) vl[u][l] = slot_load(V, ld, ic, l, m);
+      xv[u] = x[ic];
+    }
+  };
+  // the partial rows are summed before the column loads go out (a wait for them behind
+  // loads in uniform branches would wait for those too); the columns then arrive while
+  // the close and the triangular solve run
+  const double part = s_close ? final_part_sum(Pin, nblk, KW, kc, pt) : 0.0;
+  load_pass(r0);
   if (s_close) {
     // hn = ||w''_m||; the close of step m - 1 on wave 0
-    final_tree(final_part_sum(Pin, nblk, KW, kc, pt), kc, outv, scratch);
+    final_tree(part, kc, outv, scratch);
     double hn;
     if (pyth) {
       // column m - 1 of H and ||g||^2 (every block, the same fixed order)
@@ -1127,20 +1145,6 @@ __global__ __launch_bounds__(KTPB) void k_gm_update(TV *x, const TV *V, int64_t 
                     true);
     __syncthreads();
   }
-  const int64_t stride = (int64_t)gridDim.x * (R * KTPB);
-  int64_t r0 = (int64_t)blockIdx.x * (R * KTPB);
-  TV vl[R][RB], xv[R];
-  auto load_pass = [&](int64_t rb) {
-#pragma unroll
-    for (int u = 0; u < R; ++u) {
-      const int64_t i = rb + (int64_t)u * KTPB + t;
-      const int64_t ic = i < n ? i : n - 1;
-#pragma unroll
-      for (int l = 0; l < RB; ++l) vl[u][l] = slot_load(V, ld, ic, l, m);
-      xv[u] = x[ic];
-    }
-  };
-  load_pass(r0);
   // R y = gam by columns on one wave: lane l keeps the right-hand side entry l
   if (t < WAVE) {
     const int l = t;
