@@ -438,10 +438,11 @@ hipError_t launch_cg_iter(const CsrView &A, TV *x, TV *r, TV *p2, TV *q, double 
 //         end-of-cycle test); h1 = V_j^T A v_j; w'_{j+1} = A v_j - V h1 into T;
 //         partial dots V[:, k]^T w'_{j+1} (the second pass of step j).
 // F(0) instead reduces the start kernel's partials (||r||^2, ||b||^2) and opens the
-// cycle.  After G(m-1): F(m) in finalise-only mode, then the update x += V y, whose
-// blocks first close step m - 1 themselves (a cycle cut short by its close in G goes
-// to the update directly; the one-block close kernel k_gm_close remains for callers
-// of launch_gm_finish with close).  The pair (F, G) reads V twice per step, the same as
+// cycle.  After G(m-1) of a full cycle: the update x += V y, whose blocks first close
+// step m - 1 themselves from G(m-1)'s partial rows (with F(m) in finalise-only mode
+// before it where m fills its column tier: 8, 16, 32); a cycle cut short by its close
+// in G goes to the update directly; the one-block close kernel k_gm_close remains for
+// callers of launch_gm_finish with close.  The pair (F, G) reads V twice per step, the same as
 // CGS2 needs for its two projections, and the second projection of step j shares
 // the pass of the SpMV of step j + 1.
 //
@@ -452,25 +453,46 @@ template <typename VT, typename TV>
 __global__ __launch_bounds__(KTPB) void k_gm_start(const int *rowptr, const int *col, const VT *val,
                                                    const TV *b, const TV *x, TV *V, int64_t n, int restart_mode,
                                                    double *Pout, const Ctl *ctl) {
+  // two row tiles per pass (one pass over n = 2^18 rows with the full grid): their
+  // row-pointer, column / value and gather trips are shared
+  constexpr int R = 2;
   __shared__ double red[KNW * 2];
-  __shared__ double prod[SPMV_CAP];
-  __shared__ int s_go;
-  if (threadIdx.x == 0) s_go = !restart_mode || ctl->state == ST_RUN;
-  __syncthreads();
-  if (!s_go) return;
+  __shared__ double prod[SPMV_CAP * R];
+  const int t = threadIdx.x;
+  // the run state is read with the first loads; a stopped solve returns after the
+  // stage (block-uniform)
+  const int z = vzero();
+  const int st = vread(&ctl->state, z);
+  const Gather1<TV> gx{x};
   double acc[2] = {0.0, 0.0};
-  KTILES(r0, n) {
-    const double ax = tile_spmv<KTPB>(rowptr, col, val, x, n, r0, prod);
-    const int64_t i = r0 + threadIdx.x;
-    if (i < n) {
-      const double bi = (double)b[i];
-      const TV rs = (TV)(bi - ax);
-      V[i] = rs;
-      const double ri = (double)rs;
-      acc[0] += ri * ri;
-      acc[1] += bi * bi;
+  const int64_t stride = (int64_t)gridDim.x * (R * KTPB);
+  for (int64_t r0 = (int64_t)blockIdx.x * (R * KTPB); r0 < n; r0 += stride) {
+    TV bv[R];
+#pragma unroll
+    for (int u = 0; u < R; ++u) {
+      const int64_t i = r0 + (int64_t)u * KTPB + t;
+      bv[u] = b[i < n ? i : n - 1];
+    }
+    const TileRowsR<R> tr = tile_spmv_stage_r<KTPB, R, SPMV_CAP * R>(rowptr, col, val, gx, n, r0, prod);
+    __syncthreads();
+    double ax[R];
+    tile_spmv_sum_r(tr, col, val, gx, prod, ax);
+    __syncthreads();
+    if (restart_mode && st != ST_RUN) return;
+#pragma unroll
+    for (int u = 0; u < R; ++u) {
+      const int64_t i = r0 + (int64_t)u * KTPB + t;
+      if (i < n) {
+        const double bi = (double)bv[u];
+        const TV rs = (TV)(bi - ax[u]);
+        V[i] = rs;
+        const double ri = (double)rs;
+        acc[0] += ri * ri;
+        acc[1] += bi * bi;
+      }
     }
   }
+  if (restart_mode && st != ST_RUN) return;
   kstore<2>(acc, 2, red, Pout + (size_t)blockIdx.x * KW);
 }
 
