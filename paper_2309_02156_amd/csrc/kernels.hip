@@ -186,7 +186,9 @@ __global__ __launch_bounds__(TPB) void k_qrcp(double *SX, int s, int cnt, int ne
     if (part < parts) {
       const double *pr = partials + ((size_t)(r / SKETCH_RG) * nbx) * SKETCH_RG + r % SKETCH_RG;
       double acc = 0.0;
-#pragma unroll 8
+      // (unrolled so that a thread's loads go out together: a loop over ~85 blocks with
+      // 8 loads per round made 11 dependent trips to memory)
+#pragma unroll 32
       for (int b = part; b < nbx; b += parts) acc += pr[(size_t)b * SKETCH_RG];
       scratch[tid] = acc;
     }
@@ -201,12 +203,25 @@ __global__ __launch_bounds__(TPB) void k_qrcp(double *SX, int s, int cnt, int ne
   const double inv = 1.0 / sqrt((double)s);
   for (int r = tid; r < s; r += blockDim.x) SX[(size_t)newest * s + r] = v[r] * inv;
   __syncthreads();
-  for (int e = tid; e < s * cnt; e += blockDim.x) {
-    double y = (e / s == newest) ? v[e % s] * inv : SX[e];
-    Y[e] = y;
-    if (!isfinite(y)) {
-      s_bad = 1;
-      if (e / s == newest) s_newest_bad = 1;
+  // the stored sketch columns, 8 entries per thread and round requested together
+  for (int e0 = 0; e0 < s * cnt; e0 += 8 * (int)blockDim.x) {
+    double sv[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      const int e = e0 + u * (int)blockDim.x + tid;
+      sv[u] = SX[e < s * cnt ? e : s * cnt - 1];
+    }
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      const int e = e0 + u * (int)blockDim.x + tid;
+      if (e < s * cnt) {
+        const double y = (e / s == newest) ? v[e % s] * inv : sv[u];
+        Y[e] = y;
+        if (!isfinite(y)) {
+          s_bad = 1;
+          if (e / s == newest) s_newest_bad = 1;
+        }
+      }
     }
   }
   for (int c = tid; c < cnt; c += blockDim.x) perm[c] = c;
@@ -615,7 +630,23 @@ __global__ __launch_bounds__(TPB) void k_small_solve(int cnt, int spd, double ta
   double *Ri = sh + (size_t)k * k;  // k2 x k2, ld k
   double *Hm = sh + (size_t)2 * k * k;  // k x k, ld k
   double *P = sh + (size_t)3 * cnt * cnt;  // LDS copy of the reduced Gram block (ld cnt)
-  for (int e = tid; e < cnt * (2 * cnt + 1); e += blockDim.x) P[e] = ctl->gram[e];
+  {
+    // the reduced Gram block, 16 entries per thread and round requested together
+    const int tot = cnt * (2 * cnt + 1);
+    for (int e0 = 0; e0 < tot; e0 += 16 * (int)blockDim.x) {
+      double v[16];
+#pragma unroll
+      for (int u = 0; u < 16; ++u) {
+        const int e = e0 + u * (int)blockDim.x + tid;
+        v[u] = ctl->gram[e < tot ? e : tot - 1];
+      }
+#pragma unroll
+      for (int u = 0; u < 16; ++u) {
+        const int e = e0 + u * (int)blockDim.x + tid;
+        if (e < tot) P[e] = v[u];
+      }
+    }
+  }
   __syncthreads();
   if (k == 0) {
     for (int c = tid; c < MAXM; c += blockDim.x) {
@@ -847,7 +878,16 @@ __global__ __launch_bounds__(TPB) void k_small_solve(int cnt, int spd, double ta
   for (int l = tid; l < MAXM; l += blockDim.x) {
     double acc = 0.0;
     if (!s_fail && l < cnt)
-      for (int c = 0; c < k; ++c) acc += ctl->T1[l + c * MAXM] * cv[c];
+      // T1's row l in rounds of 16 entries requested together (one load at a time would
+      // wait for each in turn); the terms are added in column order
+      for (int c0 = 0; c0 < k; c0 += 16) {
+        double tv[16];
+#pragma unroll
+        for (int u = 0; u < 16; ++u) tv[u] = ctl->T1[l + (c0 + u < k ? c0 + u : k - 1) * MAXM];
+#pragma unroll
+        for (int u = 0; u < 16; ++u)
+          if (c0 + u < k) acc += tv[u] * cv[c0 + u];
+      }
     ctl->cX[l] = acc;
   }
   if (tid == 0) {
