@@ -1094,32 +1094,65 @@ __global__ __launch_bounds__(KTPB) void k_gm_update(TV *x, const TV *V, int64_t 
   __shared__ double gsq[RB];
   __shared__ CloseIn ci;
   const int t = threadIdx.x;
+  // ---- one trip: every input of the prologue is requested before any is used (loads
+  // at clamped indices, outside branches: a load whose value is stored under a branch
+  // waits before the next one goes out)
   const int z = vzero();
   const int st = vread(&ctl->state, z), je = vread(&ctl->jend, z), act = vread(&ctl->active, z);
   const int ib = vread(&ctl->ibase, z);
+  const int jc = jclose >= 0 ? jclose : 0;
   // partial entries: 1 (F(m)'s ||w''||^2) or m + 1 (G(m - 1)'s dots and ||w'||^2)
   const int kc = pyth ? jclose + 2 : 1;
-  double pt[RB / 2];
-  const double h1_t = ctl->h1[t <= jclose ? t : 0];
-  if (jclose >= 0) {
-    close_stage(jclose, ctl, &ci);
-    final_part_load(Pin, nblk, KW, kc, pt);
+  const double h1_t = ctl->h1[t <= jc ? t : 0];
+  // inputs of the close of step jclose (as close_stage stages them)
+  const double col_t = ctl->Hraw[(t <= jc ? t : jc) + jc * LD];
+  const double cs_t = ctl->cs[t < jc ? t : 0], sn_t = ctl->sn[t < jc ? t : 0];
+  const double gj = vread(&ctl->gnext[jc], z), tol = vread(&ctl->tol, z), bn = vread(&ctl->bnorm, z);
+  const int maxit = vread(&ctl->maxit, z), restart = vread(&ctl->restart, z), trust = vread(&ctl->trust_est, z);
+  // the triangle, right-hand side and scales
+  constexpr int RPT = (RB * RB + KTPB - 1) / KTPB;
+  double rv[RPT];
+#pragma unroll
+  for (int u = 0; u < RPT; ++u) {
+    const int e = t + u * KTPB;
+    const int ec = e < RB * RB ? e : 0;
+    rv[u] = ctl->R[ec % RB + (ec / RB) * LD];
   }
+  const double gs_t = ctl->gam[t < RB ? t : 0], vs_t = ctl->vs[t < RB ? t : 0];
+  double pt[RB / 2];
+  if (jclose >= 0) final_part_load(Pin, nblk, KW, kc, pt);
   if (t == 0) {
     const bool close = jclose >= 0 && st == ST_RUN && act;
     s_close = close ? 1 : 0;
     s_m = (st == ST_RUN) ? (close ? jclose + 1 : je) : -1;
     s_ibase = ib;
   }
-  // stage the whole triangle, right-hand side and scales at once (unused entries are
-  // never read)
-  for (int e = t; e < RB * RB; e += blockDim.x) {
-    const int i = e % RB, l = e / RB;
-    Rs[i + l * RB] = (i <= l) ? ctl->R[i + l * LD] : 0.0;
+  if (jclose >= 0) {
+    if (t <= jclose) ci.col[t] = col_t;
+    if (t < jclose) {
+      ci.cs[t] = cs_t;
+      ci.sn[t] = sn_t;
+    }
+    if (t == WAVE) {
+      ci.gj = gj;
+      ci.tolb = tol * bn;
+      ci.maxit = maxit;
+      ci.restart = restart;
+      ci.trust = trust;
+    }
+  }
+  // (unused entries are never read)
+#pragma unroll
+  for (int u = 0; u < RPT; ++u) {
+    const int e = t + u * KTPB;
+    if (e < RB * RB) {
+      const int i = e % RB, l = e / RB;
+      Rs[i + l * RB] = (i <= l) ? rv[u] : 0.0;
+    }
   }
   if (t < RB) {
-    gs[t] = ctl->gam[t];
-    vsh[t] = ctl->vs[t];
+    gs[t] = gs_t;
+    vsh[t] = vs_t;
   }
   __syncthreads();
   const int m = s_m;
