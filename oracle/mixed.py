@@ -11,9 +11,9 @@ since float32 storage can keep the inner residual above the inner tolerance), an
 updates x += d in FP64.  The iteration count is the sum of the inner iterations; the
 refinement count is the number of sweeps that ran an inner solve.
 
-Parity: the rounding points follow the description above; the iteration counts are
-checked against the HIP path within one per step and the final residual against the
-tolerance.
+Parity: the rounding points follow the description above; the GPU tests compare the
+iteration counts with the HIP path's under the bar stated in tests/test_gpu_mixed.py and
+check the final residual against the tolerance.
 """
 
 from __future__ import annotations
