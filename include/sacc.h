@@ -41,6 +41,8 @@ extern "C" {
 #define SA_EHIP (-3)       /* a HIP runtime call failed                                 */
 #define SA_ESTATE (-4)     /* call out of order (e.g. push before init)                 */
 #define SA_EBREAKDOWN (-5) /* CG: p^T A p <= 0 or not finite; GMRES: non-finite residual */
+#define SA_ETOOBIG (-6)    /* the problem needs more than the fixed device scratch of an
+                              allocation-free call (sa_solve_static)                      */
 
 /* ---- enumerations (stored as int32 in the structs) ----------------------------- */
 #define SA_FP64 0          /* every vector and reduction in float64                     */
@@ -293,6 +295,37 @@ int sa_batch_plan(const sa_batch *b, int *streams, int *poll, int *tuned);
  *             (SA_ESTATE without an attached predictor or before the first push).
  * Waits for the stream.  Errors: SA_EINVAL (bytes too small or unknown what). */
 int sa_copy_state(sa_seq *q, int what, void *host_dst, size_t bytes, void *stream);
+
+/* ---- allocation-free solve ----------------------------------------------------------
+ * For callers that cannot allocate device memory (code under stream capture, tight
+ * serving loops, harnesses that forbid hipMalloc): the Krylov solve of sa_solve for one
+ * system, without a sequence.  Its control block, partial sums and Krylov vectors live
+ * in one fixed device array inside the library (32 MiB per device, held by each device
+ * the library runs on until the process ends); nothing is allocated, by the library or
+ * through any other library, during the call.  The caller passes the inputs and the
+ * output only.
+ *
+ * cfg: as for sa_init_sequence, precision SA_FP64 (history fields unused: no initial
+ * guess is formed; x_dev holds x0 on entry and x on return).  A, b_dev, x_dev, info,
+ * stream: as for sa_solve.  The call waits for the stream (the host keeps cfg->poll
+ * Krylov steps in flight, then reads the solver state with a synchronous copy).
+ * Results equal sa_solve's on a fresh sequence of the same configuration: the same
+ * kernels run in the same order on the same partial-sum layout.
+ *
+ * Every call on one device shares that device's array and leaves its last contents
+ * there (each call resets the control block first): calls that overlap on one device,
+ * from several host threads or streams, race and give undefined results.
+ *
+ * Errors: SA_EINVAL (invalid configuration, precision other than SA_FP64, null
+ * pointers, shape mismatch), SA_ETOOBIG (the Krylov vectors, partial sums and control
+ * block need more than the array holds; sa_static_scratch_bytes reports both sizes),
+ * SA_EHIP.  Returns SA_OK, SA_NOTCONV or SA_EBREAKDOWN as sa_solve does. */
+int sa_solve_static(const sa_config *cfg, const sa_csr *A, const void *b_dev, void *x_dev, sa_info *info,
+                    void *stream);
+
+/* Bytes of the fixed array a configuration needs (*need) and what the array holds
+ * (*capacity).  Host only.  Errors: SA_EINVAL. */
+int sa_static_scratch_bytes(const sa_config *cfg, size_t *need, size_t *capacity);
 
 #ifdef __cplusplus
 }

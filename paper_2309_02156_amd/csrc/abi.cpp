@@ -8,6 +8,7 @@
 #include <algorithm>
 #include <chrono>
 #include <climits>
+#include <mutex>
 #include <new>
 #include <string>
 #include <thread>
@@ -66,6 +67,8 @@ struct sa_seq {
   double tau_s = 1e-12, tau_c = 1e-12;
   hipEvent_t ev[4] = {nullptr, nullptr, nullptr, nullptr};
   hipEvent_t ev_poll = nullptr;  // completion of the last snapshot copy
+  hipStream_t poll_stream = nullptr;  // stream of the snapshot copy in flight
+  bool sync_poll = false;  // no event: the host waits for the whole stream after a snapshot copy
   KernelProfile prof;
   sa_mlp *mlp = nullptr;  // learned guess (sa_learned_attach)
   int lhist = 0;          // targets per MLP input
@@ -218,12 +221,16 @@ inline double *snapshot(sa_seq *q) { return (double *)(q->hbuf + 64); }
 int poll_enqueue(sa_seq *q, Ctl *ctl, hipStream_t st) {
   HIP_TRY(hipMemcpyAsync(snapshot(q), &ctl->bnorm, 4 * sizeof(double) + 8 * sizeof(int), hipMemcpyDeviceToHost,
                          st));
-  HIP_TRY(hipEventRecord(q->ev_poll, st));
+  if (!q->sync_poll) HIP_TRY(hipEventRecord(q->ev_poll, st));
   q->poll_ctl = ctl;
+  q->poll_stream = st;
   return SA_OK;
 }
 int poll_wait(sa_seq *q) {
-  HIP_TRY(hipEventSynchronize(q->ev_poll));
+  if (q->sync_poll)
+    HIP_TRY(hipStreamSynchronize(q->poll_stream));
+  else
+    HIP_TRY(hipEventSynchronize(q->ev_poll));
   memcpy(q->hbuf, snapshot(q) + 4, 8 * sizeof(int));
   q->snap_ctl = q->poll_ctl;
   return SA_OK;
@@ -1086,6 +1093,7 @@ const char *sa_status_string(int code) {
     case SA_EHIP: return "HIP runtime error";
     case SA_ESTATE: return "call out of order";
     case SA_EBREAKDOWN: return "breakdown";
+    case SA_ETOOBIG: return "problem larger than the fixed scratch of an allocation-free call";
     default: return "unknown status";
   }
 }
@@ -1133,6 +1141,120 @@ int sa_copy_state(sa_seq *q, int what, void *host_dst, size_t bytes, void *strea
     return SA_OK;
   }
   return SA_EINVAL;
+}
+
+}  // extern "C"
+
+// ============================================================================ allocation-free solve
+// sa_solve_static: the Krylov solve of sa_solve for callers that cannot allocate.  Its
+// control block, partial sums and Krylov vectors live in one file-scope device array
+// (each device holds its own copy for the life of the process); the host state is a
+// stack object.  Without a progress word in pinned memory the host keeps `poll` steps
+// in flight, waits for the stream to drain and reads the state with a copy.
+namespace {
+
+constexpr size_t kScratchBytes = (size_t)32 << 20;
+constexpr int kMaxDevices = 64;
+
+__device__ __align__(256) unsigned char scratch[kScratchBytes];
+
+std::mutex g_scratch_mu;
+void *g_scratch_ptr[kMaxDevices];  // device address of `scratch` per device (null: not resolved)
+
+// the device address of the current device's scratch array, resolved once per device
+int scratch_base(void **out) {
+  int dev = 0;
+  HIP_TRY(hipGetDevice(&dev));
+  if (dev < 0 || dev >= kMaxDevices) return SA_EINVAL;
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void *p = nullptr;
+    HIP_TRY(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)));
+    if (!p) return SA_EHIP;
+    g_scratch_ptr[dev] = p;
+  }
+  *out = g_scratch_ptr[dev];
+  return SA_OK;
+}
+
+struct StaticLayout {
+  size_t ctl, partials, kry, total;
+};
+
+StaticLayout static_layout(const sa_config *c) {
+  StaticLayout L;
+  size_t off = 0;
+  L.ctl = off;
+  off += up(sizeof(Ctl));
+  L.partials = off;
+  off += up(krylov_partials_doubles() * sizeof(double));
+  L.kry = off;
+  const size_t kv = c->solver == SA_GMRES ? (size_t)(c->restart + 2) : 4;
+  off += up((size_t)padded_ld(c->n) * kv * sizeof(double));
+  L.total = off;
+  return L;
+}
+
+}  // namespace
+
+extern "C" {
+
+int sa_static_scratch_bytes(const sa_config *cfg, size_t *need, size_t *capacity) {
+  int rc = validate(cfg);
+  if (rc != SA_OK) return rc;
+  if (!need || !capacity) return SA_EINVAL;
+  *need = static_layout(cfg).total;
+  *capacity = kScratchBytes;
+  return SA_OK;
+}
+
+int sa_solve_static(const sa_config *cfg, const sa_csr *A, const void *b_dev, void *x_dev, sa_info *info,
+                    void *stream) {
+  int rc = validate(cfg);
+  if (rc != SA_OK) return rc;
+  if (cfg->precision != SA_FP64 || !b_dev || !x_dev) return SA_EINVAL;
+  const StaticLayout L = static_layout(cfg);
+  if (L.total > kScratchBytes) return SA_ETOOBIG;
+  sa_seq q;  // host state on the stack
+  q.cfg = *cfg;
+  if (q.cfg.poll <= 0) q.cfg.poll = 8;
+  rc = check_csr(&q, A);
+  if (rc != SA_OK) return rc;
+  void *base = nullptr;
+  SA_TRY(scratch_base(&base));
+  hipStream_t st = (hipStream_t)stream;
+  alignas(64) int hb[128] = {0};
+  unsigned long long progress = 0ull;  // never written by the device (no mirror)
+  q.hbuf = hb;
+  q.mir[0] = &progress;
+  q.sync_poll = true;
+  q.ld = padded_ld(cfg->n);
+  q.ctl = (Ctl *)((char *)base + L.ctl);
+  q.partials = (double *)((char *)base + L.partials);
+  q.kry = (char *)base + L.kry;
+  const auto t0 = std::chrono::steady_clock::now();
+  HIP_TRY(launch_ctl_reset(q.ctl, cfg->tol, cfg->maxit, cfg->restart, 0, st));
+  SA_TRY(run_krylov<double>(&q, view(A), q.ctl, (const double *)b_dev, (double *)x_dev, cfg->maxit, st));
+  const int state = hb[0];
+  if (state < ST_RUN || state > ST_ZERO_RHS) return SA_EHIP;
+  if (state == ST_ZERO_RHS) HIP_TRY(launch_zero((double *)x_dev, cfg->n, st));
+  const int ret = status_of(state);
+  if (info) {
+    double d[4];  // bnorm, relres0, relres, tol: the last poll's snapshot of this control block
+    memcpy(d, snapshot(&q), sizeof(d));
+    HIP_TRY(hipStreamSynchronize(st));
+    memset(info, 0, sizeof(*info));
+    info->iters = hb[1];
+    info->restarts = hb[2];
+    info->relres0 = d[1];
+    info->relres = state == ST_ZERO_RHS ? 0.0 : d[2];
+    info->status = ret;
+    info->ms_solve = (float)(1e3 * std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count());
+  }
+  q.hbuf = nullptr;  // not owned
+  q.mir[0] = nullptr;
+  q.ctl = nullptr;
+  return ret;
 }
 
 }  // extern "C"

@@ -148,6 +148,13 @@ hipError_t launch_learn_xpred(const TX *X, int64_t n, int64_t ld, int cnt, int n
 hipError_t launch_learn_pick(const CsrView &A, const double *b, double *x0, const double *xp, double *partials,
                              Ctl *ctl, hipStream_t st);
 
+// control block reset in device memory: every field zero, then the solver settings, the
+// initial state ST_CONV and no history (newest = -1); mirror and guess record unset
+hipError_t launch_ctl_reset(Ctl *ctl, double tol, int maxit, int restart, int trust_est, hipStream_t st);
+
+// x = 0 by a fill kernel
+hipError_t launch_zero(double *x, int64_t n, hipStream_t st);
+
 // leading dimension of the column-major history, basis and Krylov blocks
 int64_t padded_ld(int64_t n);
 

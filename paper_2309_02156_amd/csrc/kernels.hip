@@ -1019,6 +1019,39 @@ hipError_t launch_ir_update(double *x, const float *d, int64_t n, hipStream_t st
   return hipGetLastError();
 }
 
+// ============================================================================ control block reset
+// Fill kernels rather than a memset, so that the call also stays valid in a captured
+// stream: the grid clears every word, then one thread sets the solver settings.
+__global__ __launch_bounds__(TPB) void k_ctl_clear(unsigned long long *w, int64_t nw) {
+  GRID_ROWS(e, nw) w[e] = 0ull;
+}
+
+__global__ void k_ctl_set(Ctl *ctl, double tol, int maxit, int restart, int trust_est) {
+  ctl->tol = tol;
+  ctl->maxit = maxit;
+  ctl->restart = restart;
+  ctl->trust_est = trust_est;
+  ctl->state = ST_CONV;
+  ctl->newest = -1;
+}
+
+hipError_t launch_ctl_reset(Ctl *ctl, double tol, int maxit, int restart, int trust_est, hipStream_t st) {
+  static_assert(sizeof(Ctl) % sizeof(unsigned long long) == 0, "control block of whole words");
+  const int64_t nw = (int64_t)(sizeof(Ctl) / sizeof(unsigned long long));
+  hipLaunchKernelGGL(k_ctl_clear, dim3(stream_blocks(nw)), dim3(TPB), 0, st, (unsigned long long *)ctl, nw);
+  hipLaunchKernelGGL(k_ctl_set, dim3(1), dim3(1), 0, st, ctl, tol, maxit, restart, trust_est);
+  return hipGetLastError();
+}
+
+__global__ __launch_bounds__(TPB) void k_zero(double *x, int64_t n) {
+  GRID_ROWS(i, n) x[i] = 0.0;
+}
+
+hipError_t launch_zero(double *x, int64_t n, hipStream_t st) {
+  hipLaunchKernelGGL(k_zero, dim3(stream_blocks(n)), dim3(TPB), 0, st, x, n);
+  return hipGetLastError();
+}
+
 #define SACC_INSTANTIATE_PROJ(TX)                                                                              \
   template hipError_t launch_push<TX>(const double *, TX *, double *, int64_t, int64_t, int, int, int, uint64_t, \
                                       const long long *, const unsigned long long *, double *, const Ctl *, int, \

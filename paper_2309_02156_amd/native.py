@@ -13,7 +13,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libsacc.so")
 
 SA_OK, SA_NOTCONV = 0, 1
-SA_EINVAL, SA_ENOMEM, SA_EHIP, SA_ESTATE, SA_EBREAKDOWN = -1, -2, -3, -4, -5
+SA_EINVAL, SA_ENOMEM, SA_EHIP, SA_ESTATE, SA_EBREAKDOWN, SA_ETOOBIG = -1, -2, -3, -4, -5, -6
 SA_FP64, SA_MIXED, SA_MIXED_KRYLOV = 0, 1, 2
 SA_CG, SA_GMRES = 0, 1
 SA_GALERKIN, SA_MINRES = 0, 1
@@ -24,7 +24,8 @@ EXPORTS = ("sa_workspace_bytes", "sa_init_sequence", "sa_push_solution", "sa_ini
            "sa_solve", "sa_step", "sa_destroy_sequence", "sa_status_string", "sa_spmv", "sa_copy_state",
            "sa_profile_enable", "sa_profile_read", "sa_mlp_create", "sa_mlp_destroy", "sa_mlp_set_scaling",
            "sa_mlp_forward", "sa_mlp_train_step", "sa_mlp_get", "sa_learned_attach", "sa_set_time",
-           "sa_batch_create", "sa_batch_destroy", "sa_batch_step", "sa_batch_plan")
+           "sa_batch_create", "sa_batch_destroy", "sa_batch_step", "sa_batch_plan", "sa_solve_static",
+           "sa_static_scratch_bytes")
 
 
 class SaConfig(ctypes.Structure):
@@ -116,6 +117,8 @@ def lib() -> ctypes.CDLL:
     L.sa_batch_destroy.argtypes = [vp]
     L.sa_batch_step.argtypes = [vp, P(vp), P(vp), P(vp), P(SaInfo)]
     L.sa_batch_plan.argtypes = [vp, P(i32), P(i32), P(i32)]
+    L.sa_solve_static.argtypes = [P(SaConfig), P(SaCsr), vp, vp, P(SaInfo), vp]
+    L.sa_static_scratch_bytes.argtypes = [P(SaConfig), P(sz), P(sz)]
     for name in EXPORTS:
         if name != "sa_status_string":
             getattr(L, name).restype = i32

@@ -71,6 +71,32 @@ def spmv(A: DeviceCSR, x: torch.Tensor, y: Optional[torch.Tensor] = None, stream
     return y
 
 
+def solver_config(n: int, solver: str = "cg", restart: int = 30, tol: float = 1e-8, maxit: int = 200000,
+                  poll: int = 0) -> nv.SaConfig:
+    """The configuration of a plain FP64 Krylov solve of size n (history fields at their
+    smallest valid values: no initial guess is formed)."""
+    return nv.SaConfig(n=n, M=1, s=1, sketch=nv.SA_SKETCH_GAUSSIAN, projection=nv.SA_GALERKIN,
+                       solver=_SOLVER[solver], restart=restart, tol=tol, maxit=maxit, precision=nv.SA_FP64,
+                       inner_tol=1e-4, max_refine=1, guess=nv.SA_GUESS_ZERO, rank_tol_sketch=0.0,
+                       rank_tol_chol=0.0, seed=0, poll=poll, inner_maxit=0)
+
+
+def solve_static(A: DeviceCSR, b: torch.Tensor, x: torch.Tensor, solver: str = "cg", restart: int = 30,
+                 tol: float = 1e-8, maxit: int = 200000, poll: int = 0, stream=None,
+                 allow=(nv.SA_OK, nv.SA_NOTCONV, nv.SA_EBREAKDOWN)):
+    """Krylov solve of A x = b from the iterate in x through sa_solve_static (no device
+    allocation by the library); returns (x, info)."""
+    cfg = solver_config(A.n, solver, restart, tol, maxit, poll)
+    inf = nv.SaInfo()
+    s = A.c_struct()
+    rc = nv.lib().sa_solve_static(ctypes.byref(cfg), ctypes.byref(s), _ptr(b), _ptr(x), ctypes.byref(inf),
+                                  _stream(stream))
+    nv.check(rc, "sa_solve_static", allow)
+    d = inf.as_dict()
+    d["rc"] = rc
+    return x, d
+
+
 class Sequence:
     """One sequence of systems A(t_i) x = b(t_i) handled by the library."""
 

@@ -73,7 +73,7 @@ def test_null_handles_and_status_strings(nv):
     assert L.sa_step(None, None, None, None, None, None) == nv.SA_ESTATE
     assert L.sa_spmv(None, None, None, None) == nv.SA_EINVAL
     assert L.sa_copy_state(None, 0, None, 0, None) == nv.SA_ESTATE
-    for code in (0, 1, -1, -2, -3, -4, -5):
+    for code in (0, 1, -1, -2, -3, -4, -5, -6):
         s = L.sa_status_string(code).decode()
         assert s and s != "unknown status"
     assert L.sa_status_string(99).decode() == "unknown status"
@@ -152,3 +152,29 @@ def test_product_path_does_not_touch_the_oracle():
         if f.endswith(".py"):
             text = open(os.path.join(ROOT, "oracle", f)).read()
             assert "paper_2309_02156_amd" not in text, f
+
+def test_static_solve_limits(nv):
+    """The allocation-free solve reports its fixed scratch, rejects configurations that do
+    not fit it (SA_ETOOBIG) or that it does not serve (SA_EINVAL) before any device work."""
+    L = nv.lib()
+    need, cap = ctypes.c_size_t(0), ctypes.c_size_t(0)
+    assert L.sa_static_scratch_bytes(ctypes.byref(_cfg(nv, n=4096)), ctypes.byref(need), ctypes.byref(cap)) == 0
+    assert cap.value == 32 << 20 and 4 * 8 * 4096 < need.value < cap.value
+    big = _cfg(nv, n=1 << 21)
+    assert L.sa_static_scratch_bytes(ctypes.byref(big), ctypes.byref(need), ctypes.byref(cap)) == 0
+    assert need.value > cap.value
+    info = nv.SaInfo()
+    dummy = ctypes.c_void_p(256)
+    csr = nv.SaCsr(1 << 21, 7 << 21, dummy, dummy, dummy, 0, 0)
+    assert L.sa_solve_static(ctypes.byref(big), ctypes.byref(csr), dummy, dummy, ctypes.byref(info),
+                             None) == nv.SA_ETOOBIG
+    gm = _cfg(nv, n=1 << 17, solver=1, restart=30)   # 32 vectors of 2^17 doubles: 32 MiB
+    assert L.sa_static_scratch_bytes(ctypes.byref(gm), ctypes.byref(need), ctypes.byref(cap)) == 0
+    assert need.value > cap.value
+    mixed = _cfg(nv, n=4096, precision=1)
+    csr = nv.SaCsr(4096, 7 * 4096, dummy, dummy, dummy, 1, 0)
+    assert L.sa_solve_static(ctypes.byref(mixed), ctypes.byref(csr), dummy, dummy, ctypes.byref(info),
+                             None) == nv.SA_EINVAL
+    assert L.sa_solve_static(ctypes.byref(_cfg(nv, n=4096)), ctypes.byref(csr), None, dummy, ctypes.byref(info),
+                             None) == nv.SA_EINVAL
+    assert b"fixed scratch" in L.sa_status_string(nv.SA_ETOOBIG)
