@@ -255,6 +255,48 @@ def range_finder_z(M: int, m: int, seed: int, epoch: int, row0: int = 0) -> np.n
     return g.reshape(M, -1)[:, :m]
 
 
+def range_finder_rows(rows, m: int, seed: int, epoch: int) -> np.ndarray:
+    """The stream rows `rows` (any order) of epoch `epoch`, as a len(rows) x m matrix."""
+    rows = np.asarray(rows, dtype=np.uint64)
+    q = np.arange((m + 3) // 4, dtype=np.uint64)
+    g = px.normals4(rows[:, None], (np.uint64(epoch) << np.uint64(16)) | q[None, :],
+                    px.STREAM_RANGE_Z, seed)          # (len, nq, 4)
+    return g.reshape(len(rows), -1)[:, :m]
+
+
+class RangeFinderRows:
+    """Which row of the Gaussian range-finder stream each history column carries
+    (Alg. 3): the first full window and every `refresh` pushes after it draw a new epoch
+    and give the window's columns rows 0..M-1 in lag order (lines 2-4); otherwise the
+    oldest column leaves with its row and the new column takes the next unused row of
+    the epoch (lines 6-9).  While the window fills, every push starts a new epoch."""
+
+    def __init__(self, M: int, refresh: int = 50):
+        self.M, self.refresh = M, refresh
+        self.rows: list[int] = []
+        self.epoch = 0
+        self.since = 0
+        self.drawn = 0
+
+    def _scratch(self, cnt: int):
+        self.epoch += 1
+        self.rows = list(range(cnt))
+        self.drawn = cnt
+        self.since = 0
+
+    def push(self):
+        if len(self.rows) < self.M:
+            self._scratch(len(self.rows) + 1)
+            return
+        self.rows.pop(0)
+        self.since += 1
+        if self.since >= self.refresh:
+            self._scratch(self.M)
+            return
+        self.rows.append(self.drawn)
+        self.drawn += 1
+
+
 class ProgressiveSketch:
     """Omega = X Z kept up to date by rank-one updates (Alg. 3 (rank-one updates of Omega)).
 

@@ -33,7 +33,8 @@ class Sequence:
                  seed: int = 0, solver: str = "cg", restart: int = 30, tol: float = 1e-8,
                  maxit: int = 200000, projection: str = "galerkin", tau_s: float = 1e-12,
                  tau_c: float = 1e-12, m: int | None = None, guess: str = "projection",
-                 precision: str = "fp64", inner_tol: float = 1e-4, max_refine: int = 10):
+                 precision: str = "fp64", inner_tol: float = 1e-4, max_refine: int = 10,
+                 refresh: int = 50):
         self.n, self.M = n, M
         self.m = M if m is None else m
         self.s = 2 * M if s is None else s
@@ -47,7 +48,10 @@ class Sequence:
         self.S = Sketch(sketch, n, self.s, seed)
         self.cols: list[np.ndarray] = []
         self.scols: list[np.ndarray] = []
-        self.Z = None if self.m == self.M else bs.range_finder_z(M, self.m, seed, 0)
+        # m < M: the range finder's Z follows Alg. 3 (each column keeps the Gaussian row it
+        # was given, a new Z every `refresh` pushes); Omega = X Z is never formed (its span
+        # is folded into the small factor of the sketched QR)
+        self.zrows = bs.RangeFinderRows(M, refresh) if self.m < self.M else None
 
     # ------------------------------------------------------------------ history
     def push(self, x: np.ndarray):
@@ -59,6 +63,8 @@ class Sequence:
         if len(self.cols) > self.M:
             self.cols.pop(0)
             self.scols.pop(0)
+        if self.zrows is not None:
+            self.zrows.push()
 
     def history(self):
         """(X, SX) with columns oldest first."""
@@ -77,8 +83,8 @@ class Sequence:
             cX[-1] = 1.0
             return bs.Guess(X[:, -1].copy(), 0, 0, np.zeros(0), cX, False)
         Z = None
-        if self.Z is not None:
-            Z = self.Z[self.M - k_h:, :] if k_h < self.M else self.Z
+        if self.zrows is not None:
+            Z = bs.range_finder_rows(self.zrows.rows, self.m, self.seed, self.zrows.epoch)
         return bs.initial_guess(A, b, X, SX, Z, self.projection, self.solver == "cg",
                                 self.tau_s, self.tau_c, self.store)
 

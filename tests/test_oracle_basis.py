@@ -246,3 +246,25 @@ def test_range_finder_z_rows_shift_consistently():
     Z = bs.range_finder_z(10, 5, seed=1, epoch=2)
     Z2 = bs.range_finder_z(4, 5, seed=1, epoch=2, row0=6)
     assert np.array_equal(Z[6:], Z2)
+
+
+def test_sequence_z_matches_alg3_progressive():
+    """The sequence's m < M mode uses, at every step, the Z that Alg. 3 carries (the
+    progressive sketch's): rows travel with their columns, a new epoch every 50 pushes.
+    Its basis therefore spans the progressive Omega's range (Section 2.2: the updates
+    equal the from-scratch sketch in exact arithmetic)."""
+    from oracle.sequence import Sequence
+
+    rng = np.random.default_rng(16)
+    n, M, m = 200, 6, 3
+    seq = Sequence(n, M, "gaussian", 12, seed=5, m=m, refresh=7)
+    ps = bs.ProgressiveSketch(n, M, m, seed=5, refresh=7)
+    path = np.cumsum(rng.standard_normal((30, n)), 0)
+    for x in path:
+        seq.push(x)
+        ps.push(x)
+        Zs = bs.range_finder_rows(seq.zrows.rows, m, 5, seq.zrows.epoch)
+        assert seq.zrows.epoch == ps.epoch
+        assert np.array_equal(Zs, ps.Z)
+        X, _ = seq.history()
+        assert np.linalg.norm(X @ Zs - ps.Omega) <= 1e-10 * np.linalg.norm(ps.Omega)
