@@ -235,14 +235,17 @@ class SeqProblem:
         return CSR(self.n, rowptr, col, val.astype(np.float32) if want32 else val)
 
     def value_basis(self):
-        """2-D workloads: CSR values of A(t) as sum_k coef_k(t) B[k] (B: 7 x nnz).
+        """CSR values of A(t) as sum_k coef_k(t) B[k]; 3-D: see ``_value_basis_3d``.
+
+        2-D workloads (B: 7 x nnz):
 
         A(t) = D0 + cos(t + phi3) D1 + c(t) I + |v_x| / h I + v_x+ / h (-W) + v_x- / h E
         + |v_y| / h I + v_y+ / h (-S) + v_y- / h N, with D0, D1 the diffusion part split by
         k = 1 + cos(t + phi3) K(x, y) and W, E, S, N the indicator of each stencil slot;
         `value_coefs(i)` gives the 7 coefficients.  Equal to `matrix(i)` up to rounding.
         """
-        assert self.dim == 2, "the affine value basis is defined for the 2-D workloads"
+        if self.dim == 3:
+            return self._value_basis_3d()
         self.pattern()
         mask = self._pattern[2]
         h = self.h
@@ -269,9 +272,45 @@ class SeqProblem:
         E[4][:, 4] = 1.0
         return np.stack([D0[mask], D1[mask], E[0][mask], E[1][mask], E[2][mask], E[3][mask], E[4][mask]])
 
+    def _value_basis_3d(self):
+        """3-D workload (B: 4 x nnz): with sin(2 pi x + t) = sin(2 pi x) cos t + cos(2 pi x) sin t
+        the face coefficients are K0 + cos t K1 + sin t K2, so
+        A(t) = D(K0) + cos t D(K1) + sin t D(K2) + c(t) I, D(K) the diffusion part of K."""
+        assert self.advection == 0.0, "the 3-D workloads carry no advection"
+        self.pattern()
+        mask = self._pattern[2]
+        h = self.h
+        inv_h2 = 1.0 / (h * h)
+        ln = self._ln_nodes() if self.lognormal != 0.0 else None
+        g1 = np.arange(1, self.N + 1, dtype=np.float64)
+        n, nst, centre = self.n, 7, 3
+        D = [np.zeros((n, nst)) for _ in range(3)]
+        off_slots = [0, 1, 2, 4, 5, 6]
+        for slot, d in zip(off_slots, [(0, 0, -1), (0, -1, 0), (-1, 0, 0), (1, 0, 0), (0, 1, 0), (0, 0, 1)]):
+            xa = TWO_PI * ((g1 + 0.5 * d[0]) * h)
+            sb = np.sin(TWO_PI * ((g1 + 0.5 * d[1]) * h))
+            sc = np.sin(TWO_PI * ((g1 + 0.5 * d[2]) * h))
+            yz = (sb[None, :, None] * sc[:, None, None])
+            K1 = (0.5 * np.sin(xa)[None, None, :] * yz).reshape(-1)
+            K2 = (0.5 * np.cos(xa)[None, None, :] * yz).reshape(-1)
+            K0 = np.ones(n)
+            if ln is not None:
+                cen = ln[1:-1, 1:-1, 1:-1]
+                nb = ln[1 + d[2]:ln.shape[0] - 1 + d[2], 1 + d[1]:ln.shape[1] - 1 + d[1],
+                        1 + d[0]:ln.shape[2] - 1 + d[0]]
+                K0 = K0 + self.lognormal * 0.5 * (cen + nb).reshape(-1)
+            for Dk, K in zip(D, (K0, K1, K2)):
+                Dk[:, slot] = -K * inv_h2
+                Dk[:, centre] += K * inv_h2
+        E = np.zeros((n, nst))
+        E[:, centre] = 1.0
+        return np.stack([D[0][mask], D[1][mask], D[2][mask], E[mask]])
+
     def value_coefs(self, i: int) -> np.ndarray:
         """Coefficients of `value_basis` at t_i."""
         t = self.t(i)
+        if self.dim == 3:
+            return np.array([1.0, math.cos(t), math.sin(t), self.ccoef(t)])
         h = self.h
         vx, vy = self.velocity(t)
         diag = self.ccoef(t) + (abs(vx) + abs(vy)) / h

@@ -58,10 +58,14 @@ extern "C" {
 #define SA_GMRES 1         /* restarted GMRES(restart), classical Gram-Schmidt twice    */
 
 #define SA_GALERKIN 0      /* reduced problem Q^T A Q y = Q^T b                         */
-#define SA_MINRES 1        /* reduced problem min ||A Q y - b||_2 (Section 2)           */
+#define SA_MINRES 1        /* reduced problem min ||A Q y - b||_2 (Section 2): normal
+                              equations (A Q)^T (A Q) y = (A Q)^T b from the same SpMM
+                              pass, solved by Cholesky                                  */
 
 #define SA_SKETCH_GAUSSIAN 0 /* S[r, j] Gaussian from Philox4x64-10 + Box-Muller      */
 #define SA_SKETCH_SRHT 1     /* S = s^-1/2 R H D, n a power of two                     */
+
+#define SA_BASIS_SKETCHED_QR 0 /* QR with column pivoting of the sketch S X (Z), Cholesky finish */
 
 #define SA_GUESS_PROJECTION 0 /* the method: x0 = Q y                                  */
 #define SA_GUESS_ZERO 1       /* x0 = 0                                                 */
@@ -73,9 +77,9 @@ typedef struct {
   int32_t M;              /* history length (number of previous solutions kept), 1..32 */
   int32_t s;              /* sketch rows, M <= s <= 256, s*M <= 8192; SRHT: s <= n     */
   int32_t sketch;         /* SA_SKETCH_*                                               */
-  int32_t projection;     /* SA_GALERKIN (SA_MINRES is rejected with SA_EINVAL)        */
+  int32_t projection;     /* SA_GALERKIN or SA_MINRES                                   */
   int32_t solver;         /* SA_CG or SA_GMRES                                         */
-  int32_t restart;        /* GMRES restart length, 1..64                               */
+  int32_t restart;        /* GMRES restart length, 1..32                               */
   double tol;             /* stop when ||b - A x||_2 <= tol ||b||_2                   */
   int32_t maxit;          /* iteration cap (A-products for CG, Arnoldi steps GMRES)    */
   int32_t precision;      /* SA_FP64, SA_MIXED or SA_MIXED_KRYLOV                      */
@@ -89,6 +93,13 @@ typedef struct {
   int32_t poll;           /* Krylov steps the host may enqueue ahead of the device (<= 0: default 8) */
   int32_t inner_maxit;    /* mixed: iteration cap of one inner solve (<= 0: 10 GMRES
                              cycles, or 1000 CG iterations)                          */
+  int32_t m;              /* range finder (Section 2.2, Alg. 3): 1 <= m < M multiplies the
+                             history by an M x m Gaussian Z (each column keeps the row of Z
+                             it was given, Alg. 3), so the basis spans X Z; 0 or M: Z = I */
+  int32_t refresh;        /* with 1 <= m < M: a new Z every `refresh` pushes once the
+                             window is full (<= 0: 50, Section 4)                        */
+  int32_t basis;          /* SA_BASIS_SKETCHED_QR                                       */
+  int32_t reserved2;
 } sa_config;
 
 typedef struct {
@@ -295,6 +306,27 @@ int sa_batch_plan(const sa_batch *b, int *streams, int *poll, int *tuned);
  *             (SA_ESTATE without an attached predictor or before the first push).
  * Waits for the stream.  Errors: SA_EINVAL (bytes too small or unknown what). */
 int sa_copy_state(sa_seq *q, int what, void *host_dst, size_t bytes, void *stream);
+
+/* ---- checkpoint / resume -------------------------------------------------------------
+ * The state a sequence carries between steps (Section 2: the window of the M most recent
+ * solutions; the sketch S X and the sketched QR of the window; the learned predictor's
+ * recent targets), so that a run can stop and resume: after sa_import_state a fresh
+ * sequence of the same configuration computes bit for bit the guesses and solves the
+ * exporting one would have.  The image is host memory in this library's own layout: a
+ * header (a magic word, the configuration, the push count), X (n x M in ring-slot
+ * order, float32 for SA_MIXED, else float64), S X (s x M float64), the projection part
+ * of the control block.  The predictor's weights are not part of it (sa_mlp_get).
+ *
+ * sa_state_bytes: size of the image.  Errors: SA_ESTATE, SA_EINVAL.
+ * sa_export_state: writes the image to host_dst (>= sa_state_bytes); waits for the
+ *   stream.  Errors: SA_ESTATE, SA_EINVAL (too small), SA_EHIP.
+ * sa_import_state: loads an image into q, which must have the configuration the image
+ *   was exported with (n, M, s, sketch, precision and seed equal; solver settings may
+ *   differ); waits for the stream.  Errors: SA_ESTATE, SA_EINVAL (not an image of this
+ *   library, another configuration, too small), SA_EHIP. */
+int sa_state_bytes(const sa_seq *q, size_t *bytes);
+int sa_export_state(sa_seq *q, void *host_dst, size_t bytes, void *stream);
+int sa_import_state(sa_seq *q, const void *host_src, size_t bytes, void *stream);
 
 /* ---- allocation-free solve ----------------------------------------------------------
  * For callers that cannot allocate device memory (code under stream capture, tight

@@ -74,6 +74,10 @@ struct sa_seq {
   int lhist = 0;          // targets per MLP input
   long long ltargets = 0; // targets written (one per push while attached)
   double t_now = 0.0;     // time of the next system (sa_set_time)
+  // range finder (1 <= m < M): the Gaussian row each history column carries, in lag
+  // order (oldest first), the stream's epoch, pushes since its draw and its next row
+  std::vector<int> zrows;
+  int z_epoch = 0, z_since = 0, z_drawn = 0;
   bool alive = true;
 };
 
@@ -133,7 +137,7 @@ int validate(const sa_config *c) {
   if (c->sketch != SA_SKETCH_GAUSSIAN && c->sketch != SA_SKETCH_SRHT) return SA_EINVAL;
   if (c->sketch == SA_SKETCH_SRHT && (c->n & (c->n - 1)) != 0) return SA_EINVAL;
   if (c->sketch == SA_SKETCH_SRHT && c->s > c->n) return SA_EINVAL;
-  if (c->projection != SA_GALERKIN) return SA_EINVAL;
+  if (c->projection != SA_GALERKIN && c->projection != SA_MINRES) return SA_EINVAL;
   if (c->solver != SA_CG && c->solver != SA_GMRES) return SA_EINVAL;
   if (c->solver == SA_GMRES && (c->restart < 1 || c->restart > MAXR)) return SA_EINVAL;
   if (!(c->tol > 0.0) || c->maxit < 0) return SA_EINVAL;
@@ -141,6 +145,9 @@ int validate(const sa_config *c) {
   if (c->precision != SA_FP64 && (!(c->inner_tol > 0.0) || !(c->inner_tol < 1.0) || c->max_refine < 1))
     return SA_EINVAL;
   if (c->guess < SA_GUESS_PROJECTION || c->guess > SA_GUESS_PREVIOUS) return SA_EINVAL;
+  if (c->m < 0 || c->m > c->M) return SA_EINVAL;
+  if (c->m > 0 && c->m < c->M && (int64_t)c->s * (c->M + 2 * c->m) + (int64_t)c->m * c->m > 12288) return SA_EINVAL;
+  if (c->basis != SA_BASIS_SKETCHED_QR) return SA_EINVAL;
   return SA_OK;
 }
 
@@ -403,7 +410,7 @@ int run_cg(sa_seq *q, const CsrView &v, Ctl *ctl, const TV *b, TV *x, int maxit,
   const size_t w = sizeof(TV), wv = v.fp32 ? 4 : 8;
   const double csr = 4.0 * (v.n + 1) + (4.0 + wv) * v.nnz;
   const std::string pname =
-      std::string("k_cg_p<") + tname(wv) + ", " + tname(w) + ", " + std::to_string(cg_rows_per_thread(v.n)) + ">";
+      std::string("k_cg_p<") + tname(wv) + ", " + tname(w) + ", " + std::to_string(cg_tile_chunk(v.n, v.nnz)) + ">";
   Progress pg = progress_of(q, ctl);
   pg.reset();
   const int ahead = c.poll > MIR_EVERY ? c.poll : MIR_EVERY;  // progress arrives every MIR_EVERY steps
@@ -533,9 +540,10 @@ int guess_projection(sa_seq *q, const CsrView &v, const double *b, double *x0, i
     HIP_TRY(launch_basis<TX>((const TX *)q->X, (TX *)q->Q1, c.n, q->ld, cnt, q->ctl, st));
     q->basis_for = q->pushes;
   }
-  HIP_TRY(launch_spmm_gram<TX>(v, (const TX *)q->Q1, q->ld, b, cnt, 0, q->partials, &nblk, q->ctl, st));
-  HIP_TRY(launch_colsum(q->partials, nblk, cnt * (2 * cnt + 1), q->ctl, st));
-  HIP_TRY(launch_small_solve(cnt, 0, c.solver == SA_CG ? 1 : 0, q->tau_c, q->ctl, st));
+  const int mr = c.projection == SA_MINRES ? 1 : 0;
+  HIP_TRY(launch_spmm_gram<TX>(v, (const TX *)q->Q1, q->ld, b, cnt, mr, q->partials, &nblk, q->ctl, st));
+  HIP_TRY(launch_colsum(q->partials, nblk, gram_width(cnt, mr), q->ctl, st));
+  HIP_TRY(launch_small_solve(cnt, mr, c.solver == SA_CG ? 1 : 0, q->tau_c, q->ctl, st));
   HIP_TRY(launch_x0<TX>((const TX *)q->Q1, (const TX *)q->X, x0, c.n, q->ld, q->ctl, st));
   return SA_OK;
 }
@@ -634,6 +642,42 @@ int sa_init_sequence(const sa_config *cfg, void *dev_ws, size_t ws_bytes, void *
 
 namespace {
 
+// The range finder's rows after a push (q->pushes already counts it), in ring-slot
+// order for the QR kernel (Alg. 3): while the window fills and every `refresh` pushes
+// after, a new epoch gives the window's columns rows 0..cnt-1 in lag order; otherwise
+// the oldest column leaves with its row and the new column takes the epoch's next row.
+ZRows zrows_push(sa_seq *q) {
+  const sa_config &c = q->cfg;
+  ZRows z;
+  memset(&z, 0, sizeof(z));
+  if (!(c.m > 0 && c.m < c.M)) return z;
+  const int cnt = count(q);
+  const int refresh = c.refresh > 0 ? c.refresh : 50;
+  auto scratch = [&](int k) {
+    q->z_epoch += 1;
+    q->zrows.resize(k);
+    for (int l = 0; l < k; ++l) q->zrows[l] = l;
+    q->z_drawn = k;
+    q->z_since = 0;
+  };
+  if ((int)q->zrows.size() < c.M) {
+    scratch((int)q->zrows.size() + 1);
+  } else {
+    q->zrows.erase(q->zrows.begin());
+    q->z_since += 1;
+    if (q->z_since >= refresh) {
+      scratch(c.M);
+    } else {
+      q->zrows.push_back(q->z_drawn);
+      q->z_drawn += 1;
+    }
+  }
+  for (int l = 0; l < cnt; ++l) z.row[(q->pushes - cnt + l) % c.M] = q->zrows[l];
+  z.m = c.m;
+  z.epoch = (unsigned)q->z_epoch;
+  return z;
+}
+
 // push x into the history; zero_rhs: push zero if the last solve ended with b = 0
 int push_enqueue(sa_seq *q, const void *x_dev, int zero_rhs, hipStream_t st) {
   const sa_config &c = q->cfg;
@@ -654,7 +698,7 @@ int push_enqueue(sa_seq *q, const void *x_dev, int zero_rhs, hipStream_t st) {
     q->ltargets += 1;
   }
   q->pushes += 1;
-  HIP_TRY(launch_qrcp(q->SX, c.s, count(q), slot, q->tau_s, q->partials, c.n, q->ctl, st));
+  HIP_TRY(launch_qrcp(q->SX, c.s, count(q), slot, q->tau_s, q->partials, c.n, q->ctl, zrows_push(q), c.seed, st));
   return SA_OK;
 }
 
@@ -1141,6 +1185,123 @@ int sa_copy_state(sa_seq *q, int what, void *host_dst, size_t bytes, void *strea
     return SA_OK;
   }
   return SA_EINVAL;
+}
+
+}  // extern "C"
+
+// ============================================================================ checkpoint / resume
+// The state a sequence carries from one step to the next: the history X (n x M in ring
+// slots), its sketch S X, the push count (which fixes the ring order), the sketched QR
+// of the history (T1, rank, newest slot and its finiteness) and the learned predictor's
+// target ring.  Everything else (Krylov vectors, partial sums, the basis Q1) is rebuilt
+// by the next step, and the sketch's random entries follow from the configuration.
+namespace {
+
+constexpr uint64_t kStateMagic = 0x3130746174734153ull;  // "SAstat01"
+
+struct StateHeader {
+  uint64_t magic;
+  sa_config cfg;
+  int64_t pushes, ltargets;
+  double t_now;
+  uint64_t x_bytes, sx_bytes, ctl_bytes;
+  int32_t z_epoch, z_since, z_drawn, z_count;
+  int32_t zrows[MAXM];
+};
+
+// the control-block fields of the projection state, one contiguous range
+constexpr size_t kCtlLo = offsetof(Ctl, k);
+constexpr size_t kCtlHi = offsetof(Ctl, c);
+static_assert(offsetof(Ctl, T1) > kCtlLo && offsetof(Ctl, T1) < kCtlHi, "T1 inside the saved range");
+
+size_t state_bytes(const sa_seq *q) {
+  const size_t w = q->x32 ? sizeof(float) : sizeof(double);
+  return sizeof(StateHeader) + (size_t)q->cfg.n * q->cfg.M * w + (size_t)q->cfg.s * q->cfg.M * sizeof(double) +
+         (kCtlHi - kCtlLo) + sizeof(((Ctl *)0)->lhist);
+}
+
+bool same_method(const sa_config &a, const sa_config &b) {
+  return a.n == b.n && a.M == b.M && a.s == b.s && a.sketch == b.sketch && a.precision == b.precision &&
+         a.seed == b.seed && a.m == b.m && a.refresh == b.refresh && a.basis == b.basis;
+}
+
+}  // namespace
+
+extern "C" {
+
+int sa_state_bytes(const sa_seq *q, size_t *bytes) {
+  if (!q || !q->alive) return SA_ESTATE;
+  if (!bytes) return SA_EINVAL;
+  *bytes = state_bytes(q);
+  return SA_OK;
+}
+
+int sa_export_state(sa_seq *q, void *host_dst, size_t bytes, void *stream) {
+  if (!q || !q->alive) return SA_ESTATE;
+  if (!host_dst || bytes < state_bytes(q)) return SA_EINVAL;
+  hipStream_t st = (hipStream_t)stream;
+  const sa_config &c = q->cfg;
+  const size_t w = q->x32 ? sizeof(float) : sizeof(double);
+  StateHeader h;
+  memset(&h, 0, sizeof(h));
+  h.magic = kStateMagic;
+  h.cfg = c;
+  h.pushes = q->pushes;
+  h.ltargets = q->ltargets;
+  h.t_now = q->t_now;
+  h.x_bytes = (uint64_t)c.n * c.M * w;
+  h.sx_bytes = (uint64_t)c.s * c.M * sizeof(double);
+  h.ctl_bytes = (uint64_t)(kCtlHi - kCtlLo) + sizeof(((Ctl *)0)->lhist);
+  h.z_epoch = q->z_epoch;
+  h.z_since = q->z_since;
+  h.z_drawn = q->z_drawn;
+  h.z_count = (int32_t)q->zrows.size();
+  for (int l = 0; l < h.z_count && l < MAXM; ++l) h.zrows[l] = q->zrows[l];
+  char *o = (char *)host_dst;
+  memcpy(o, &h, sizeof(h));
+  o += sizeof(h);
+  HIP_TRY(hipMemcpy2DAsync(o, (size_t)c.n * w, q->X, (size_t)q->ld * w, (size_t)c.n * w, (size_t)c.M,
+                           hipMemcpyDeviceToHost, st));
+  o += h.x_bytes;
+  HIP_TRY(hipMemcpyAsync(o, q->SX, h.sx_bytes, hipMemcpyDeviceToHost, st));
+  o += h.sx_bytes;
+  HIP_TRY(hipMemcpyAsync(o, (const char *)q->ctl + kCtlLo, kCtlHi - kCtlLo, hipMemcpyDeviceToHost, st));
+  o += kCtlHi - kCtlLo;
+  HIP_TRY(hipMemcpyAsync(o, q->ctl->lhist, sizeof(((Ctl *)0)->lhist), hipMemcpyDeviceToHost, st));
+  HIP_TRY(hipStreamSynchronize(st));
+  return SA_OK;
+}
+
+int sa_import_state(sa_seq *q, const void *host_src, size_t bytes, void *stream) {
+  if (!q || !q->alive) return SA_ESTATE;
+  if (!host_src || bytes < sizeof(StateHeader)) return SA_EINVAL;
+  StateHeader h;
+  memcpy(&h, host_src, sizeof(h));
+  if (h.magic != kStateMagic || !same_method(h.cfg, q->cfg) || bytes < state_bytes(q) || h.pushes < 0 ||
+      h.z_count < 0 || h.z_count > MAXM)
+    return SA_EINVAL;
+  hipStream_t st = (hipStream_t)stream;
+  const sa_config &c = q->cfg;
+  const size_t w = q->x32 ? sizeof(float) : sizeof(double);
+  const char *in = (const char *)host_src + sizeof(h);
+  HIP_TRY(hipMemcpy2DAsync(q->X, (size_t)q->ld * w, in, (size_t)c.n * w, (size_t)c.n * w, (size_t)c.M,
+                           hipMemcpyHostToDevice, st));
+  in += h.x_bytes;
+  HIP_TRY(hipMemcpyAsync(q->SX, in, h.sx_bytes, hipMemcpyHostToDevice, st));
+  in += h.sx_bytes;
+  HIP_TRY(hipMemcpyAsync((char *)q->ctl + kCtlLo, in, kCtlHi - kCtlLo, hipMemcpyHostToDevice, st));
+  in += kCtlHi - kCtlLo;
+  HIP_TRY(hipMemcpyAsync(q->ctl->lhist, in, sizeof(((Ctl *)0)->lhist), hipMemcpyHostToDevice, st));
+  HIP_TRY(hipStreamSynchronize(st));
+  q->pushes = h.pushes;
+  q->z_epoch = h.z_epoch;
+  q->z_since = h.z_since;
+  q->z_drawn = h.z_drawn;
+  q->zrows.assign(h.zrows, h.zrows + h.z_count);
+  q->ltargets = q->mlp ? h.ltargets : 0;
+  q->t_now = h.t_now;
+  q->basis_for = -1;
+  return SA_OK;
 }
 
 }  // extern "C"

@@ -580,6 +580,212 @@ __device__ inline double tile_spmv(const int *__restrict__ rowptr, const int *__
   return tile_spmv_g<NT>(rowptr, col, val, Gather1<TX>{x}, n, r0, prod);
 }
 
+// ---------------------------------------------------------------- wave-tile CSR SpMV
+// A wave owns a tile of 64 consecutive rows (lane l: row r0 + l) and works on it alone:
+// no block barrier, so the waves of a block (and the several blocks a compute unit
+// holds) overlap each other's memory trips.  Stage: the tile's nonzeros [p0, p1) are
+// read with consecutive lanes on consecutive nonzeros (coalesced), C per lane per round,
+// all issued before the first is used (slots past the tile re-read its last entry and
+// are dropped); then the gathers; the products go to the wave's own LDS slice.  Sum:
+// each lane adds its row's products in column order.  Tiles with more than WT_CAP
+// nonzeros read their rows directly.  `gx(c)` returns the source vector's entry c.
+constexpr int WT_CAP = 512;  // nonzeros of one wave tile staged in LDS (4 KB)
+constexpr int NXCD = 8;      // accelerator complex dies (each with its own L2) of the MI355X
+
+__device__ inline void wave_lds_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// (A x)_{r0 + lane} for the wave's tile (0 for rows >= n); prod: the wave's LDS slice
+// of WT_CAP doubles.  Every lane of the wave must call it with the same r0 < n.
+template <int C, typename VT, typename G>
+__device__ inline double wave_tile_spmv(const int *__restrict__ rowptr, const int *__restrict__ col,
+                                        const VT *__restrict__ val, const G &gx, int64_t n, int64_t r0,
+                                        double *prod) {
+  const int lane = threadIdx.x % WAVE;
+  const int64_t i = r0 + lane;
+  const int last = (int)((n - r0 < WAVE ? n - r0 : WAVE) - 1);  // last lane with a row
+  const int64_t ic = i < n ? i : n - 1;
+  const int a = rowptr[ic], b = rowptr[ic + 1];
+  const int p0 = __builtin_amdgcn_readfirstlane(a);
+  const int p1 = __builtin_amdgcn_readlane(b, last);
+  double s = 0.0;
+  if (p1 - p0 <= WT_CAP) {
+    for (int base = p0; base < p1; base += C * WAVE) {
+      int cc[C];
+      double vv[C], xx[C];
+#pragma unroll
+      for (int u = 0; u < C; ++u) {
+        const int p = base + u * WAVE + lane;
+        const int pc = p < p1 ? p : p1 - 1;
+        cc[u] = col[pc];
+        vv[u] = (double)val[pc];
+      }
+#pragma unroll
+      for (int u = 0; u < C; ++u) xx[u] = gx(cc[u]);
+#pragma unroll
+      for (int u = 0; u < C; ++u) {
+        const int p = base + u * WAVE + lane;
+        if (p < p1) prod[p - p0] = vv[u] * xx[u];
+      }
+    }
+    wave_lds_sync();
+    if (i < n)
+      for (int p = a; p < b; ++p) s += prod[p - p0];
+    wave_lds_sync();  // the slice is rewritten by the wave's next tile
+  } else if (i < n) {
+    for (int p = a; p < b; ++p) s += (double)val[p] * gx(col[p]);
+  }
+  return i < n ? s : 0.0;
+}
+
+// A wave's loop over its tiles with the index loads of the next tile in flight while
+// the current tile's gathers are outstanding: per tile the row pointers of the next tile
+// go out first, then this tile's gathers and `pre` (a load of the row's own entries),
+// then the next tile's first round of columns / values (its row pointers have arrived by
+// then); the products of this tile go to LDS and `epi(i, pre value, (A x)_i)` runs for
+// every row i < n of the tile.  The loads of the last tile's successor re-read the last
+// tile (no branch around loads).  Tiles past WT_CAP nonzeros read their rows directly;
+// rounds after the first of a long tile load inline.  Same sums, in the same order, as
+// wave_tile_spmv.
+template <int C, typename VT, typename G, typename PRE, typename EPI>
+__device__ inline void wave_tiles_spmv_pipelined(const int *__restrict__ rowptr, const int *__restrict__ col,
+                                                 const VT *__restrict__ val, const G &gx, int64_t n, int64_t t,
+                                                 int64_t end, int64_t step, double *prod, const PRE &pre,
+                                                 const EPI &epi) {
+  const int lane = threadIdx.x % WAVE;
+  if (t >= end) return;
+  int a, b, p0, p1, cc[C];
+  double vv[C];
+  auto load_rows = [&](int64_t tt, int &ra, int &rb) {
+    const int64_t i = tt * WAVE + lane;
+    const int64_t ic = i < n ? i : n - 1;
+    ra = rowptr[ic];
+    rb = rowptr[ic + 1];
+  };
+  auto tile_range = [&](int64_t tt, int ra, int rb, int &q0, int &q1) {
+    const int64_t r0 = tt * WAVE;
+    const int last = (int)((n - r0 < WAVE ? n - r0 : WAVE) - 1);
+    q0 = __builtin_amdgcn_readfirstlane(ra);
+    q1 = __builtin_amdgcn_readlane(rb, last);
+  };
+  // (q1 == 0: no nonzero up to this tile, possibly none at all: nothing is read)
+  auto load_round = [&](int base, int q1, int (&c)[C], double (&v)[C]) {
+#pragma unroll
+    for (int u = 0; u < C; ++u) {
+      c[u] = 0;
+      v[u] = 0.0;
+    }
+    if (q1 > 0) {
+#pragma unroll
+      for (int u = 0; u < C; ++u) {
+        const int pp = base + u * WAVE + lane;
+        const int pc = pp < q1 ? pp : q1 - 1;
+        c[u] = col[pc];
+        v[u] = (double)val[pc];
+      }
+    }
+  };
+  load_rows(t, a, b);
+  tile_range(t, a, b, p0, p1);
+  load_round(p0, p1, cc, vv);
+  for (;;) {
+    const int64_t r0 = t * WAVE, i = r0 + lane;
+    const int64_t tn = t + step;
+    const bool more = tn < end;
+    int an, bn;
+    load_rows(more ? tn : t, an, bn);
+    double xx[C];
+#pragma unroll
+    for (int u = 0; u < C; ++u) xx[u] = gx(cc[u]);
+    const double own = pre(i < n ? i : n - 1);
+    int p0n, p1n, ccn[C];
+    double vvn[C];
+    tile_range(more ? tn : t, an, bn, p0n, p1n);
+    load_round(p0n, p1n, ccn, vvn);
+    double s = 0.0;
+    if (p1 - p0 <= WT_CAP) {
+#pragma unroll
+      for (int u = 0; u < C; ++u) {
+        const int pp = p0 + u * WAVE + lane;
+        if (pp < p1) prod[pp - p0] = vv[u] * xx[u];
+      }
+      for (int base = p0 + C * WAVE; base < p1; base += C * WAVE) {
+        int c2[C];
+        double v2[C], x2[C];
+        load_round(base, p1, c2, v2);
+#pragma unroll
+        for (int u = 0; u < C; ++u) x2[u] = gx(c2[u]);
+#pragma unroll
+        for (int u = 0; u < C; ++u) {
+          const int pp = base + u * WAVE + lane;
+          if (pp < p1) prod[pp - p0] = v2[u] * x2[u];
+        }
+      }
+      wave_lds_sync();
+      if (i < n)
+        for (int pp = a; pp < b; ++pp) s += prod[pp - p0];
+      wave_lds_sync();  // the slice is rewritten by the wave's next tile
+    } else if (i < n) {
+      for (int pp = a; pp < b; ++pp) s += (double)val[pp] * gx(col[pp]);
+    }
+    if (i < n) epi(i, own, s);
+    if (!more) break;
+    t = tn;
+    a = an;
+    b = bn;
+    p0 = p0n;
+    p1 = p1n;
+#pragma unroll
+    for (int u = 0; u < C; ++u) {
+      cc[u] = ccn[u];
+      vv[u] = vvn[u];
+    }
+  }
+}
+
+// The wave tiles of a launch in an XCD-aware order.  Blocks are dispatched to the dies
+// round robin by block index, so blocks with equal blockIdx.x % 8 share an L2; each
+// such group takes one contiguous eighth of the tiles (a stencil's neighbour rows are
+// then mostly in the same L2) and its waves take those tiles round robin.  The grid is
+// a multiple of 8 blocks, or fewer than 8 (one group).
+struct WaveTiles {
+  int64_t t, end, step;
+};
+__device__ inline WaveTiles wave_tiles(int64_t n) {
+  const int nw = blockDim.x / WAVE, wid = threadIdx.x / WAVE;
+  const int64_t T = (n + WAVE - 1) / WAVE;
+  const int groups = gridDim.x >= NXCD ? NXCD : 1;
+  const int g = blockIdx.x % groups;
+  const int64_t per = (T + groups - 1) / groups;
+  const int64_t lo = g * per;
+  const int64_t hi = lo + per < T ? lo + per : T;
+  const int64_t idx = (int64_t)(blockIdx.x / groups) * nw + wid;
+  return WaveTiles{lo + idx, hi, (int64_t)(gridDim.x / groups) * nw};
+}
+
+// grid of a wave-tile launch: enough blocks of `threads` for one tile per wave, at most
+// maxblk, rounded to a multiple of NXCD once it reaches NXCD
+inline int wave_tile_blocks(int64_t n, int threads, int maxblk) {
+  const int64_t T = (n + WAVE - 1) / WAVE;
+  const int64_t nw = threads / WAVE;
+  int64_t b = (T + nw - 1) / nw;
+  if (b > maxblk) b = maxblk;
+  if (b < 1) b = 1;
+  if (b >= NXCD) b = (b + NXCD - 1) / NXCD * NXCD;
+  if (b > maxblk) b = maxblk / NXCD * NXCD;
+  return (int)b;
+}
+
+// gathers per lane and round of a wave tile (5, 7 or 9): the matrix's average row
+// length rounded up, so that one round covers an average tile
+inline int wave_tile_chunk(int64_t n, int64_t nnz) {
+  const int64_t c = n > 0 ? (nnz + n - 1) / n : 1;
+  return c <= 5 ? 5 : (c <= 7 ? 7 : 9);
+}
+
 // ---------------------------------------------------------------- Philox4x64-10
 // Salmon, Moraes, Dror, Shaw, "Parallel random numbers: as easy as 1, 2, 3", SC'11.
 struct U64x4 {
@@ -617,7 +823,7 @@ __device__ inline double unit_open(uint64_t w) {
   return ((double)(w >> 12) + 0.5) * 0x1p-52;
 }
 
-enum : uint64_t { STREAM_GAUSS_SKETCH = 1, STREAM_SRHT_SIGNS = 2, STREAM_SRHT_ROWS = 3 };
+enum : uint64_t { STREAM_GAUSS_SKETCH = 1, STREAM_SRHT_SIGNS = 2, STREAM_SRHT_ROWS = 3, STREAM_RANGE_Z = 4 };
 
 // Four Box-Muller normals of block (c0, c1, stream): (cos0, sin0, cos1, sin1).
 __device__ inline void normals4(uint64_t c0, uint64_t c1, uint64_t stream, uint64_t seed, double g[4]) {

@@ -34,10 +34,18 @@ hipError_t launch_srht_signs(unsigned long long *words, int64_t n, uint64_t seed
 // blocks along n of the push kernel (its partial rows per row group)
 int push_blocks_x(int64_t n, int s);
 
+// Rows of the range finder's Gaussian stream carried by the history columns (ring-slot
+// order) and the stream's epoch; m = 0: no range finder (Z = I)
+struct ZRows {
+  int row[MAXM];
+  int m;
+  unsigned epoch;
+};
+
 // finish the push (reduce the sketch partials into SX[:, newest]), then QR with column
-// pivoting of SX[:, 0:cnt] -> k, T1 (in ctl)
+// pivoting of SX[:, 0:cnt] (or of SX[:, 0:cnt] Z with the range finder) -> k, T1 (in ctl)
 hipError_t launch_qrcp(double *SX, int s, int cnt, int newest, double tau, const double *partials, int64_t n,
-                       Ctl *ctl, hipStream_t st);
+                       Ctl *ctl, const ZRows &zr, uint64_t seed, hipStream_t st);
 
 // Q1 = X T1 (first ctl->k columns)
 template <typename TX>
@@ -47,6 +55,9 @@ hipError_t launch_basis(const TX *X, TX *Q1, int64_t n, int64_t ld, int cnt, Ctl
 template <typename TX>
 hipError_t launch_spmm_gram(const CsrView &A, const TX *Q1, int64_t ld, const double *b, int cnt, int minres,
                             double *partials, int *nblk_out, Ctl *ctl, hipStream_t st);
+
+// entries of one partial row of launch_spmm_gram (Galerkin block, then the minimum-residual one)
+int gram_width(int cnt, int minres);
 
 // column sums of partials[nblk][W] -> ctl->gram
 hipError_t launch_colsum(const double *partials, int nblk, int W, Ctl *ctl, hipStream_t st);
@@ -116,8 +127,8 @@ bool gm_norm_in_g(int m);
 size_t krylov_partials_doubles();
 // row tiles per pass of the GMRES kernel F (1 or 2) for n rows and rb column slots
 int gm_f_rows_per_thread(int64_t n, int rb);
-// row tiles each block of the CG iteration kernels takes at once (1, 2 or 4)
-int cg_rows_per_thread(int64_t n);
+// gathers per lane and round of the CG kernels' wave-tile SpMV (their template argument)
+int cg_tile_chunk(int64_t n, int64_t nnz);
 
 // ---- learned coefficient predictor (MLP) and the learned initial guess
 constexpr int MLP_MAXL = 8;  // linear layers at most

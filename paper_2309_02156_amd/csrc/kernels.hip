@@ -161,10 +161,16 @@ hipError_t launch_push(const double *x, TX *X, double *SX, int64_t n, int64_t ld
 // way).  Three barriers a step.  MC = columns a wave owns at most, RW = 64-row chunks.
 template <int MC, int RW>
 __global__ __launch_bounds__(TPB) void k_qrcp(double *SX, int s, int cnt, int newest, double tau,
-                                              const double *partials, int nbx, Ctl *ctl) {
+                                              const double *partials, int nbx, Ctl *ctl, ZRows zr,
+                                              uint64_t seed) {
   extern __shared__ double sh[];
-  double *Y = sh;                     // s x cnt, ld s
-  double *Ri = sh + (size_t)s * cnt;  // cnt x cnt inverse, ld cnt
+  // zr.m > 0: the range finder's Z (cnt x m) multiplies S X first (Alg. 3: the sketch of
+  // Omega = X Z), and the QR runs over the m columns of Y = (S X) Z
+  const int nq = zr.m > 0 ? zr.m : cnt;  // columns of the factorised matrix
+  double *Y = sh;                     // s x cnt, ld s (then s x nq)
+  double *Ri = sh + (size_t)s * cnt;  // nq x nq inverse, ld nq
+  double *Zm = Ri + (size_t)nq * nq;  // cnt x m, ld cnt
+  double *Yz = Zm + (size_t)cnt * (zr.m > 0 ? zr.m : 0);  // s x m, ld s
   __shared__ double nrm[MAXM];
   __shared__ double v[MAXS];
   __shared__ double scratch[TPB];
@@ -224,7 +230,6 @@ __global__ __launch_bounds__(TPB) void k_qrcp(double *SX, int s, int cnt, int ne
       }
     }
   }
-  for (int c = tid; c < cnt; c += blockDim.x) perm[c] = c;
   __syncthreads();
   if (tid == 0) {
     ctl->newest = newest;
@@ -237,15 +242,39 @@ __global__ __launch_bounds__(TPB) void k_qrcp(double *SX, int s, int cnt, int ne
     }
     return;
   }
+  if (zr.m > 0) {
+    // Z[l][c] = Gaussian entry (row zr.row[l], column c) of the epoch's stream: normal
+    // lane c & 3 of Philox block (row, (epoch << 16) | (c >> 2), STREAM_RANGE_Z)
+    const int nq4 = (zr.m + 3) / 4;
+    for (int e = tid; e < cnt * nq4; e += blockDim.x) {
+      const int l = e % cnt, q4 = e / cnt;
+      double g[4];
+      normals4((uint64_t)zr.row[l], ((uint64_t)zr.epoch << 16) | (uint64_t)q4, STREAM_RANGE_Z, seed, g);
+#pragma unroll
+      for (int u = 0; u < 4; ++u)
+        if (4 * q4 + u < zr.m) Zm[l + (size_t)(4 * q4 + u) * cnt] = g[u];
+    }
+    __syncthreads();
+    for (int e = tid; e < s * zr.m; e += blockDim.x) {
+      const int r = e % s, c = e / s;
+      double acc = 0.0;
+      for (int l = 0; l < cnt; ++l) acc += Y[r + (size_t)l * s] * Zm[l + (size_t)c * cnt];
+      Yz[e] = acc;
+    }
+    __syncthreads();
+    Y = Yz;
+  }
+  for (int c = tid; c < nq; c += blockDim.x) perm[c] = c;
+  __syncthreads();
   int jj = 0;
-  for (; jj < cnt; ++jj) {
+  for (; jj < nq; ++jj) {
     // exact column norms over rows jj..s-1 of this wave's remaining columns
     {
       double a[MC];
 #pragma unroll
       for (int u = 0; u < MC; ++u) {
         const int c = jj + wid + NWAVE * u;
-        const int cc = c < cnt ? c : cnt - 1;
+        const int cc = c < nq ? c : nq - 1;
         double acc = 0.0;
 #pragma unroll
         for (int w = 0; w < RW; ++w) {
@@ -258,11 +287,11 @@ __global__ __launch_bounds__(TPB) void k_qrcp(double *SX, int s, int cnt, int ne
       wave_sum_multi<MC>(a);
       constexpr int LPE = WAVE / MC;  // lanes per entry after the reduction
       const int c = jj + wid + NWAVE * (lane / LPE);
-      if (lane % LPE == 0 && c < cnt) nrm[c] = a[0];
+      if (lane % LPE == 0 && c < nq) nrm[c] = a[0];
     }
     __syncthreads();
     // pivot: largest norm, lowest index among equal ones (each wave, the same result)
-    const int p = wave_argmax((jj + lane < cnt) ? nrm[jj + lane] : -1.0, jj + lane);
+    const int p = wave_argmax((jj + lane < nq) ? nrm[jj + lane] : -1.0, jj + lane);
     if (tid == 0) {
       const int t = perm[jj];
       perm[jj] = perm[p];
@@ -280,7 +309,7 @@ __global__ __launch_bounds__(TPB) void k_qrcp(double *SX, int s, int cnt, int ne
     const double x0 = Y[(size_t)jj * s + jj];
     if (alpha == 0.0) {
       // the rest is zero: R_jj = 0 onward
-      for (int c = jj + tid; c < cnt; c += blockDim.x) Y[(size_t)c * s + c] = 0.0;
+      for (int c = jj + tid; c < nq; c += blockDim.x) Y[(size_t)c * s + c] = 0.0;
       __syncthreads();
       break;
     }
@@ -300,7 +329,7 @@ __global__ __launch_bounds__(TPB) void k_qrcp(double *SX, int s, int cnt, int ne
 #pragma unroll
       for (int u = 0; u < MC; ++u) {
         const int c = jj + 1 + wid + NWAVE * u;
-        const int cc = c < cnt ? c : cnt - 1;
+        const int cc = c < nq ? c : nq - 1;
         double acc = 0.0;
 #pragma unroll
         for (int w = 0; w < RW; ++w) {
@@ -319,7 +348,7 @@ __global__ __launch_bounds__(TPB) void k_qrcp(double *SX, int s, int cnt, int ne
       for (int u = 0; u < MC; ++u) {
         const int c = jj + 1 + wid + NWAVE * u;
         const double du = lane_bcast(dr[0], u * LPE) * tauh;
-        if (c < cnt) {
+        if (c < nq) {
 #pragma unroll
           for (int w = 0; w < RW; ++w) {
             const int r = jj + lane + WAVE * w;
@@ -332,17 +361,17 @@ __global__ __launch_bounds__(TPB) void k_qrcp(double *SX, int s, int cnt, int ne
     __syncthreads();
   }
   // sign convention diag(R) >= 0: negate rows with a negative diagonal
-  for (int r = wid; r < cnt; r += NWAVE) {
+  for (int r = wid; r < nq && r < s; r += NWAVE) {
     const bool neg = Y[(size_t)r * s + r] < 0.0;
     if (neg)
-      for (int c = r + lane; c < cnt; c += WAVE) Y[(size_t)c * s + r] = -Y[(size_t)c * s + r];
+      for (int c = r + lane; c < nq; c += WAVE) Y[(size_t)c * s + r] = -Y[(size_t)c * s + r];
   }
   __syncthreads();
   // rank: leading count of |R_jj| > tau |R_11| (every thread, from LDS)
   const double r00 = fabs(Y[0]);
   int k = 0;
   if (r00 > 0.0)
-    while (k < cnt && fabs(Y[(size_t)k * s + k]) > tau * r00) ++k;
+    while (k < nq && k < s && fabs(Y[(size_t)k * s + k]) > tau * r00) ++k;
   // R11^-1 on wave 0, lane c = column c, row by row from the bottom (each entry the same
   // ascending sum as a per-column back substitution)
   if (wid == 0) {
@@ -360,15 +389,20 @@ __global__ __launch_bounds__(TPB) void k_qrcp(double *SX, int s, int cnt, int ne
       }
     }
   }
-  for (int i = tid; i < cnt; i += blockDim.x) iperm[perm[i]] = i;
+  for (int i = tid; i < nq; i += blockDim.x) iperm[perm[i]] = i;
   __syncthreads();
-  // T1 = P R11^-1 (zero elsewhere), every entry written once
+  // T1 = P R11^-1, or Z P R11^-1 with the range finder (zero elsewhere), every entry
+  // written once
   for (int e = tid; e < MAXM * MAXM; e += blockDim.x) {
     const int row = e % MAXM, c = e / MAXM;
     double t = 0.0;
     if (c < k && row < cnt) {
-      const int i = iperm[row];
-      if (i <= c) t = Ri[i + c * k];
+      if (zr.m > 0) {
+        for (int i = 0; i <= c; ++i) t += Zm[row + (size_t)perm[i] * cnt] * Ri[i + c * k];
+      } else {
+        const int i = iperm[row];
+        if (i <= c) t = Ri[i + c * k];
+      }
     }
     ctl->T1[e] = t;
   }
@@ -379,14 +413,16 @@ __global__ __launch_bounds__(TPB) void k_qrcp(double *SX, int s, int cnt, int ne
 }
 
 hipError_t launch_qrcp(double *SX, int s, int cnt, int newest, double tau, const double *partials, int64_t n,
-                       Ctl *ctl, hipStream_t st) {
-  size_t lds = ((size_t)s * cnt + (size_t)cnt * cnt) * sizeof(double);
-  if (cnt <= 2 * NWAVE * 4 && s <= 2 * WAVE)
+                       Ctl *ctl, const ZRows &zr, uint64_t seed, hipStream_t st) {
+  const int nq = zr.m > 0 ? zr.m : cnt;
+  size_t lds = ((size_t)s * cnt + (size_t)nq * nq) * sizeof(double);
+  if (zr.m > 0) lds += ((size_t)cnt * zr.m + (size_t)s * zr.m) * sizeof(double);
+  if (nq <= 2 * NWAVE * 4 && s <= 2 * WAVE)
     hipLaunchKernelGGL((k_qrcp<8, 2>), dim3(1), dim3(TPB), lds, st, SX, s, cnt, newest, tau, partials,
-                       push_blocks_x(n, s), ctl);
+                       push_blocks_x(n, s), ctl, zr, seed);
   else
     hipLaunchKernelGGL((k_qrcp<MAXM / NWAVE, MAXS / WAVE>), dim3(1), dim3(TPB), lds, st, SX, s, cnt, newest, tau,
-                       partials, push_blocks_x(n, s), ctl);
+                       partials, push_blocks_x(n, s), ctl, zr, seed);
   return hipGetLastError();
 }
 
@@ -425,168 +461,265 @@ hipError_t launch_basis(const TX *X, TX *Q1, int64_t n, int64_t ld, int cnt, Ctl
 }
 
 // ============================================================================ SpMM + Gram (MFMA)
-// Each wave owns 64-row tiles.  Lane = row: w = (A Q1)_row in registers.  The tile
-// [Q1 | W | b] (64 rows x (2 cnt + 1) columns) is staged in the wave's LDS and
-// Q1_tile^T [Q1 | W | b]_tile is accumulated with v_mfma_f64_16x16x4f64 over 16 steps
-// of 4 rows.  Columns >= k of the Q1 and W blocks are zero.  Operand layout of the
-// 16x16x4 f64 instruction: A[i][kq] from lane i + 16 kq, B[kq][j] from lane j + 16 kq,
-// D[lane / 16 + 4 v][lane % 16] in accumulator element v.
-constexpr int GRAM_TPB = 128;
+// A wave owns tiles of 16 rows (XCD-aware order); lane l works on row rr = l % 16 of the
+// tile and on the basis columns [CPL q, CPL q + CPL) with q = l / 16, CPL = KB / 4.
+// SpMM: w = (A Q1)_{row, cols} accumulated in registers; the row's nonzeros in rounds
+// of NZ (their columns and values loaded together), the CPL gathers of every nonzero of
+// a round issued together (consecutive rows of a column sit side by side, so each load
+// instruction touches four short runs of a column).
+// Gram: the tile's W, with b as column k, goes to the wave's LDS slice, and
+// v_mfma_f64_16x16x4f64 accumulates over the tile's four row quads
+//   G += Q1^T Q1 (blocks on and above the diagonal), H += Q1^T [W | b],
+//   and for the minimum-residual problem K += W^T [W | b];
+// the Q1 operands are read straight from memory (the tile's 16 rows of a column share
+// one cache line), the W operands from LDS.  Operand layout of the instruction:
+// A[i][kq] from lane i + 16 kq, B[kq][j] from lane j + 16 kq, D[lane / 16 + 4 v][lane % 16]
+// in accumulator element v.  Columns >= k of Q1 and W are zero.
+// The waves' accumulators are added in wave order in LDS and the block writes one row
+// of partial sums: P[a + col cnt] for a < cnt, col < 2 cnt + 1 (Q1^T Q1 | Q1^T W | Q1^T b),
+// then for the minimum residual K[a + col cnt], col < cnt + 1 (W^T W | W^T b).
+constexpr int GRAM_TPB = 256;
 constexpr int GRAM_NW = GRAM_TPB / WAVE;
-constexpr int GRAM_LDT = WAVE + 1;
-constexpr int GRAM_MAXBLK = 768;
+constexpr int GRAM_ROWS = 16;
+constexpr int GRAM_MAXBLK = 1024;
 
-template <typename VT, int MC, typename TX>
+template <int KB, bool MR>
+struct GramShape {
+  static constexpr int NA = KB / 16;                       // 16-column blocks of Q1
+  static constexpr int NWB = KB / 16 + 1;                  // 16-column blocks of [W | b]
+  static constexpr int LDW = NWB * 16 + 1;                 // LDS row stride of the W tile
+  static constexpr int NG = NA * (NA + 1) / 2;             // G blocks kept
+  static constexpr int NBLK = NG + NA * NWB + (MR ? NA * NWB : 0);
+  static constexpr int TILE = GRAM_NW * GRAM_ROWS * LDW;   // doubles of the W tiles
+  static constexpr int COMB = NBLK * 256;                  // doubles of the combined blocks
+  static constexpr int LDS = TILE > COMB ? TILE : COMB;
+};
+
+__device__ inline int gram_gidx(int a, int bq, int na) {  // index of G block (a <= bq)
+  return a * na - a * (a - 1) / 2 + (bq - a);
+}
+
+template <typename VT, int KB, typename TX, bool MR>
 __global__ __launch_bounds__(GRAM_TPB) void k_spmm_gram(const int *rowptr, const int *col, const VT *val,
                                                         const TX *Q1, const double *b, int64_t n, int64_t ld,
                                                         int cnt, double *partials, const Ctl *ctl) {
-  extern __shared__ double lds[];
-  constexpr int NA = MC / 16;
-  constexpr int NB = (2 * MC + 1 + 15) / 16;
+  using S = GramShape<KB, MR>;
+  constexpr int CPL = KB / 4, NA = S::NA, NWB = S::NWB, LDW = S::LDW, NZ = KB == 32 ? 2 : 4;
+  __shared__ double lds[S::LDS];
   const int k = ctl->k;
-  const int nbc = 2 * cnt + 1;
   const int lane = threadIdx.x % WAVE, wid = threadIdx.x / WAVE;
-  double *T = lds + (size_t)wid * nbc * GRAM_LDT;
-  const int na = (k + 15) / 16, nb = (nbc + 15) / 16;
-  d4 acc[NA][NB];
+  const int rr = lane % 16, q = lane / 16;
+  const int na = (k + 15) / 16, nwb = (k + 1 + 15) / 16;
+  double *Wl = lds + (size_t)wid * GRAM_ROWS * LDW;
+  d4 accG[S::NG], accH[NA][NWB], accK[MR ? NA : 1][MR ? NWB : 1];
+#pragma unroll
+  for (int e = 0; e < S::NG; ++e) accG[e] = (d4){0.0, 0.0, 0.0, 0.0};
 #pragma unroll
   for (int a = 0; a < NA; ++a)
 #pragma unroll
-    for (int bq = 0; bq < NB; ++bq) acc[a][bq] = (d4){0.0, 0.0, 0.0, 0.0};
-  const int64_t ntiles = (n + WAVE - 1) / WAVE;
-  for (int64_t t = (int64_t)blockIdx.x * GRAM_NW + wid; t < ntiles; t += (int64_t)gridDim.x * GRAM_NW) {
-    const int64_t i = t * WAVE + lane;
-    double w[MC];
+    for (int bw = 0; bw < NWB; ++bw) {
+      accH[a][bw] = (d4){0.0, 0.0, 0.0, 0.0};
+      if constexpr (MR) accK[a][bw] = (d4){0.0, 0.0, 0.0, 0.0};
+    }
+  const int64_t T = (n + GRAM_ROWS - 1) / GRAM_ROWS;
+  const int groups = gridDim.x >= NXCD ? NXCD : 1;
+  const int64_t per = (T + groups - 1) / groups;
+  const int64_t tlo = (int64_t)(blockIdx.x % groups) * per;
+  const int64_t thi = tlo + per < T ? tlo + per : T;
+  const int64_t tstep = (int64_t)(gridDim.x / groups) * GRAM_NW;
+  for (int64_t t = tlo + (int64_t)(blockIdx.x / groups) * GRAM_NW + wid; k > 0 && t < thi; t += tstep) {
+    const int64_t r0 = t * GRAM_ROWS, row = r0 + rr;
+    const bool valid = row < n;
+    const int64_t rc = valid ? row : n - 1;
+    const int pa = rowptr[rc], pb = valid ? rowptr[rc + 1] : pa;
+    double w[CPL];
 #pragma unroll
-    for (int c = 0; c < MC; ++c) w[c] = 0.0;
-    if (i < n) {
-      // nonzeros in groups of NZ (their columns and values loaded together), the basis
-      // columns in chunks of CC: every gather of a chunk is issued before the first is
-      // used (slots past the row's nonzeros or past k re-read a live entry, weight 0)
-      constexpr int NZ = 5, CC = 4;
-      const int p0 = rowptr[i], p1 = rowptr[i + 1];
-      for (int pb = p0; pb < p1; pb += NZ) {
-        int cj[NZ];
-        double av[NZ];
+    for (int u = 0; u < CPL; ++u) w[u] = 0.0;
+    for (int p = pa; p < pb; p += NZ) {
+      int cj[NZ];
+      double av[NZ];
 #pragma unroll
-        for (int u = 0; u < NZ; ++u) {
-          const int p = pb + u;
-          const int pc = p < p1 ? p : p1 - 1;
-          cj[u] = col[pc];
-          const double a = (double)val[pc];
-          av[u] = p < p1 ? a : 0.0;
+      for (int z = 0; z < NZ; ++z) {
+        const int pp = p + z;
+        const int pc = pp < pb ? pp : pb - 1;
+        cj[z] = col[pc];
+        const double a = (double)val[pc];
+        av[z] = pp < pb ? a : 0.0;
+      }
+      double g[NZ][CPL];
+#pragma unroll
+      for (int z = 0; z < NZ; ++z)
+#pragma unroll
+        for (int u = 0; u < CPL; ++u) {
+          const int c = q * CPL + u;
+          g[z][u] = (double)Q1[(size_t)(c < k ? c : k - 1) * ld + cj[z]];
         }
 #pragma unroll
-        for (int c0 = 0; c0 < MC; c0 += CC) {
-          if (c0 < k) {
-            double gq[NZ][CC];
+      for (int u = 0; u < CPL; ++u) {
+        double acc = 0.0;
 #pragma unroll
-            for (int u = 0; u < NZ; ++u)
-#pragma unroll
-              for (int cc = 0; cc < CC; ++cc) {
-                const int c = c0 + cc < k ? c0 + cc : k - 1;
-                gq[u][cc] = (double)Q1[(size_t)c * ld + cj[u]];
-              }
-#pragma unroll
-            for (int cc = 0; cc < CC; ++cc) {
-              double acc = 0.0;
-#pragma unroll
-              for (int u = 0; u < NZ; ++u) acc += av[u] * gq[u][cc];
-              if (c0 + cc < k) w[c0 + cc] += acc;
-            }
-          }
-        }
+        for (int z = 0; z < NZ; ++z) acc += av[z] * g[z][u];
+        w[u] += acc;
       }
     }
+    // the tile's [W | b] into the wave's slice: W, zero columns past k, then b in column k
 #pragma unroll
-    for (int c = 0; c < MC; ++c) {
-      if (c < cnt) {
-        const bool ok = (c < k) && (i < n);
-        T[c * GRAM_LDT + lane] = ok ? (double)Q1[(size_t)c * ld + i] : 0.0;
-        T[(cnt + c) * GRAM_LDT + lane] = ok ? w[c] : 0.0;
-      }
+    for (int u = 0; u < CPL; ++u) {
+      const int c = q * CPL + u;
+      Wl[rr * LDW + c] = (c < k && valid) ? w[u] : 0.0;
     }
-    T[(2 * cnt) * GRAM_LDT + lane] = (i < n) ? b[i] : 0.0;
-    wave_sync();
-    const int li = lane % 16, kq = lane / 16;
-#pragma unroll 4
-    for (int ks = 0; ks < WAVE / 4; ++ks) {
-      const int r = ks * 4 + kq;
-      double av[NA], bv[NB];
+#pragma unroll
+    for (int u = 0; u < (NWB * 16 - KB) / 4; ++u) Wl[rr * LDW + KB + q * ((NWB * 16 - KB) / 4) + u] = 0.0;
+    wave_lds_sync();
+    if (q == 0) Wl[rr * LDW + k] = valid ? b[row] : 0.0;
+    wave_lds_sync();
+    const int i16 = lane % 16, kq = lane / 16;
+#pragma unroll
+    for (int s4 = 0; s4 < GRAM_ROWS / 4; ++s4) {
+      const int lr = 4 * s4 + kq;
+      const int64_t rowk = r0 + lr;
+      double aq[NA], wv[NWB];
 #pragma unroll
       for (int a = 0; a < NA; ++a) {
-        const int c = a * 16 + li;
-        av[a] = (a < na && c < k) ? T[c * GRAM_LDT + r] : 0.0;
+        const int ca = a * 16 + i16;
+        const int64_t rq = rowk < n ? rowk : n - 1;
+        const double v = (double)Q1[(size_t)(ca < k ? ca : k - 1) * ld + rq];
+        aq[a] = (ca < k && rowk < n) ? v : 0.0;
       }
 #pragma unroll
-      for (int bq = 0; bq < NB; ++bq) {
-        const int c = bq * 16 + li;
-        bv[bq] = (bq < nb && c < nbc) ? T[c * GRAM_LDT + r] : 0.0;
+      for (int bw = 0; bw < NWB; ++bw) wv[bw] = Wl[lr * LDW + bw * 16 + i16];
+#pragma unroll
+      for (int a = 0; a < NA; ++a) {
+        if (a < na) {
+#pragma unroll
+          for (int bq = a; bq < NA; ++bq)
+            if (bq < na)
+              accG[gram_gidx(a, bq, NA)] =
+                  __builtin_amdgcn_mfma_f64_16x16x4f64(aq[a], aq[bq], accG[gram_gidx(a, bq, NA)], 0, 0, 0);
+#pragma unroll
+          for (int bw = 0; bw < NWB; ++bw)
+            if (bw < nwb) {
+              accH[a][bw] = __builtin_amdgcn_mfma_f64_16x16x4f64(aq[a], wv[bw], accH[a][bw], 0, 0, 0);
+              if constexpr (MR) accK[a][bw] = __builtin_amdgcn_mfma_f64_16x16x4f64(wv[a], wv[bw], accK[a][bw], 0, 0, 0);
+            }
+        }
       }
+    }
+    wave_lds_sync();  // the slice is rewritten by the wave's next tile
+  }
+  // the waves' blocks added in wave order: D element v of a block sits at row
+  // lane / 16 + 4 v, column lane % 16 (row-major 16 x 16)
+  __syncthreads();
+  for (int wv = 0; wv < GRAM_NW; ++wv) {
+    if (wid == wv) {
+      int blk = 0;
+      auto put = [&](const d4 &acc) {
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+          double *dst = lds + (size_t)blk * 256 + (lane / 16 + 4 * v) * 16 + lane % 16;
+          *dst = wv == 0 ? acc[v] : *dst + acc[v];
+        }
+        ++blk;
+      };
+#pragma unroll
+      for (int e = 0; e < S::NG; ++e) put(accG[e]);
 #pragma unroll
       for (int a = 0; a < NA; ++a)
 #pragma unroll
-        for (int bq = 0; bq < NB; ++bq)
-          if (a < na && bq < nb) acc[a][bq] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[a], bv[bq], acc[a][bq], 0, 0, 0);
-    }
-    wave_sync();
-  }
-  // combine the waves of the block, then write this block's partial P[a + col * cnt]
-  __syncthreads();
-  double *P = lds;  // reuse: GRAM_NW x (NA*16) x (NB*16)
-  constexpr int PA = NA * 16, PB = NB * 16;
+        for (int bw = 0; bw < NWB; ++bw) put(accH[a][bw]);
+      if constexpr (MR) {
 #pragma unroll
-  for (int a = 0; a < NA; ++a)
+        for (int a = 0; a < NA; ++a)
 #pragma unroll
-    for (int bq = 0; bq < NB; ++bq)
-#pragma unroll
-      for (int vv = 0; vv < 4; ++vv) {
-        const int row = a * 16 + lane / 16 + 4 * vv, colx = bq * 16 + lane % 16;
-        P[(size_t)wid * PA * PB + row + colx * PA] = acc[a][bq][vv];
+          for (int bw = 0; bw < NWB; ++bw) put(accK[a][bw]);
       }
-  __syncthreads();
-  const int W = cnt * nbc;
-  double *out = partials + (size_t)blockIdx.x * W;
-  for (int e = threadIdx.x; e < W; e += blockDim.x) {
-    const int a = e % cnt, colx = e / cnt;
-    double sum = 0.0;
-    if (a < k && a < PA && colx < PB)
-      for (int ww = 0; ww < GRAM_NW; ++ww) sum += P[(size_t)ww * PA * PB + a + colx * PA];
-    out[e] = sum;
+    }
+    __syncthreads();
   }
+  const int Wg = cnt * (2 * cnt + 1), Wout = MR ? Wg + cnt * (cnt + 1) : Wg;
+  double *out = partials + (size_t)blockIdx.x * Wout;
+  const double *comb = lds;
+  const int hbase = S::NG, kbase = S::NG + NA * NWB;
+  for (int e = threadIdx.x; e < Wout; e += blockDim.x) {
+    double v = 0.0;
+    if (e < Wg) {
+      const int a = e % cnt, cx = e / cnt;
+      if (a < k) {
+        if (cx < cnt) {  // G, from the block on or above the diagonal
+          if (cx < k) {
+            const int r = a <= cx ? a : cx, c = a <= cx ? cx : a;
+            if (r / 16 == c / 16 || r / 16 < c / 16)
+              v = comb[(size_t)gram_gidx(r / 16, c / 16, NA) * 256 + (r % 16) * 16 + c % 16];
+          }
+        } else if (cx < 2 * cnt) {  // Q1^T W
+          const int c = cx - cnt;
+          if (c < k) v = comb[(size_t)(hbase + (a / 16) * NWB + c / 16) * 256 + (a % 16) * 16 + c % 16];
+        } else {  // Q1^T b (column k of the W tile)
+          v = comb[(size_t)(hbase + (a / 16) * NWB + k / 16) * 256 + (a % 16) * 16 + k % 16];
+        }
+      }
+    } else {
+      const int e2 = e - Wg, a = e2 % cnt, cx = e2 / cnt;
+      if (a < k) {
+        const int c = cx < cnt ? cx : k;  // W^T W column, or W^T b (column k)
+        if (cx == cnt || c < k) v = comb[(size_t)(kbase + (a / 16) * NWB + c / 16) * 256 + (a % 16) * 16 + c % 16];
+      }
+    }
+    out[e] = v;
+  }
+}
+
+template <typename VT, int KB, typename TX, bool MR>
+static int gram_grid(int64_t n) {
+  static int resident = 0;  // blocks of this instantiation the device holds at once
+  const int64_t T = (n + GRAM_ROWS - 1) / GRAM_ROWS;
+  int64_t want = (T + GRAM_NW - 1) / GRAM_NW;
+  if (resident == 0) {
+    int dev = 0, ncu = 0, per = 0;
+    if (hipGetDevice(&dev) == hipSuccess &&
+        hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess &&
+        hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, k_spmm_gram<VT, KB, TX, MR>, GRAM_TPB, 0) ==
+            hipSuccess &&
+        per >= 1) {
+      const int r = per * ncu / NXCD * NXCD;
+      resident = r < NXCD ? NXCD : (r > GRAM_MAXBLK ? GRAM_MAXBLK : r);
+    } else {
+      resident = 256;
+    }
+  }
+  if (want > resident) want = resident;
+  if (want >= NXCD) want = want / NXCD * NXCD;
+  return (int)(want < 1 ? 1 : want);
+}
+
+template <typename VT, int KB, typename TX, bool MR>
+static int gram_launch(const CsrView &A, const TX *Q1, int64_t ld, const double *b, int cnt, double *partials,
+                       const Ctl *ctl, hipStream_t st) {
+  const int nb = gram_grid<VT, KB, TX, MR>(A.n);
+  hipLaunchKernelGGL((k_spmm_gram<VT, KB, TX, MR>), dim3(nb), dim3(GRAM_TPB), 0, st, A.rowptr, A.col,
+                     (const VT *)A.val, Q1, b, A.n, ld, cnt, partials, ctl);
+  return nb;
+}
+
+template <typename VT, typename TX>
+static int gram_launch_vt(const CsrView &A, const TX *Q1, int64_t ld, const double *b, int cnt, int minres,
+                          double *partials, const Ctl *ctl, hipStream_t st) {
+  if (cnt <= 16)
+    return minres ? gram_launch<VT, 16, TX, true>(A, Q1, ld, b, cnt, partials, ctl, st)
+                  : gram_launch<VT, 16, TX, false>(A, Q1, ld, b, cnt, partials, ctl, st);
+  return minres ? gram_launch<VT, 32, TX, true>(A, Q1, ld, b, cnt, partials, ctl, st)
+                : gram_launch<VT, 32, TX, false>(A, Q1, ld, b, cnt, partials, ctl, st);
 }
 
 template <typename TX>
 hipError_t launch_spmm_gram(const CsrView &A, const TX *Q1, int64_t ld, const double *b, int cnt, int minres,
                             double *partials, int *nblk_out, Ctl *ctl, hipStream_t st) {
-  (void)minres;
-  const int64_t ntiles = (A.n + WAVE - 1) / WAVE;
-  int64_t nb = (ntiles + GRAM_NW - 1) / GRAM_NW;
-  if (nb > GRAM_MAXBLK) nb = GRAM_MAXBLK;
-  if (nb < 1) nb = 1;
-  const int nbc = 2 * cnt + 1;
-  const int mc = cnt <= 16 ? 16 : 32;
-  const size_t tile = (size_t)GRAM_NW * nbc * GRAM_LDT;
-  const size_t comb = (size_t)GRAM_NW * (mc) * (((2 * mc + 1 + 15) / 16) * 16);
-  const size_t lds = (tile > comb ? tile : comb) * sizeof(double);
-  *nblk_out = (int)nb;
-  if (A.fp32) {
-    if (mc == 16)
-      hipLaunchKernelGGL((k_spmm_gram<float, 16, TX>), dim3(nb), dim3(GRAM_TPB), lds, st, A.rowptr, A.col,
-                         (const float *)A.val, Q1, b, A.n, ld, cnt, partials, ctl);
-    else
-      hipLaunchKernelGGL((k_spmm_gram<float, 32, TX>), dim3(nb), dim3(GRAM_TPB), lds, st, A.rowptr, A.col,
-                         (const float *)A.val, Q1, b, A.n, ld, cnt, partials, ctl);
-  } else {
-    if (mc == 16)
-      hipLaunchKernelGGL((k_spmm_gram<double, 16, TX>), dim3(nb), dim3(GRAM_TPB), lds, st, A.rowptr, A.col,
-                         (const double *)A.val, Q1, b, A.n, ld, cnt, partials, ctl);
-    else
-      hipLaunchKernelGGL((k_spmm_gram<double, 32, TX>), dim3(nb), dim3(GRAM_TPB), lds, st, A.rowptr, A.col,
-                         (const double *)A.val, Q1, b, A.n, ld, cnt, partials, ctl);
-  }
+  *nblk_out = A.fp32 ? gram_launch_vt<float, TX>(A, Q1, ld, b, cnt, minres, partials, ctl, st)
+                     : gram_launch_vt<double, TX>(A, Q1, ld, b, cnt, minres, partials, ctl, st);
   return hipGetLastError();
 }
+
+int gram_width(int cnt, int minres) { return cnt * (2 * cnt + 1) + (minres ? cnt * (cnt + 1) : 0); }
 
 // ---------------------------------------------------------------------------- column sums
 // gram[e] = sum_b partials[b][e]; block = 16 entries x 16 block-groups.
@@ -614,11 +747,13 @@ hipError_t launch_colsum(const double *partials, int nblk, int W, Ctl *ctl, hipS
 
 // ============================================================================ small reduced solve
 // One workgroup.  gram holds P = Q1^T [Q1 | W | b] with ld cnt: G = P[:, 0:k],
-// Ht = P[:, cnt:cnt+k], gt = P[:, 2 cnt].  Pivoted Cholesky of G with threshold
+// Ht = P[:, cnt:cnt+k], gt = P[:, 2 cnt]; for the minimum residual it is followed by
+// K = W^T [W | b] (ld cnt), and Ht, gt are taken from K instead: K[:, 0:k], K[:, cnt]
+// (the normal equations of min ||A Q y - b||).  Pivoted Cholesky of G with threshold
 // tau_c max(diag G) gives R2 (k2 x k2) and perm2; H = R2^-T Ht_pp R2^-1,
-// g = R2^-T gt_p; H y = g by Cholesky (SPD path) or LU with partial pivoting;
-// c[perm2[i]] = (R2^-1 y)_i, cX = T1 c.
-__global__ __launch_bounds__(TPB) void k_small_solve(int cnt, int spd, double tau_c, Ctl *ctl) {
+// g = R2^-T gt_p; H y = g by Cholesky (SPD path, and always for the minimum residual)
+// or LU with partial pivoting; c[perm2[i]] = (R2^-1 y)_i, cX = T1 c.
+__global__ __launch_bounds__(TPB) void k_small_solve(int cnt, int minres, int spd, double tau_c, Ctl *ctl) {
   extern __shared__ double sh[];
   const int k = ctl->k;
   const int tid = threadIdx.x, lane = tid % WAVE, wid = tid / WAVE;
@@ -630,9 +765,12 @@ __global__ __launch_bounds__(TPB) void k_small_solve(int cnt, int spd, double ta
   double *Ri = sh + (size_t)k * k;  // k2 x k2, ld k
   double *Hm = sh + (size_t)2 * k * k;  // k x k, ld k
   double *P = sh + (size_t)3 * cnt * cnt;  // LDS copy of the reduced Gram block (ld cnt)
+  // column 0 of the reduced matrix and the column of its right-hand side inside P
+  const int hoff = minres ? cnt * (2 * cnt + 1) : cnt * cnt;
+  const int goff = minres ? cnt * (2 * cnt + 1) + cnt * cnt : 2 * cnt * cnt;
   {
     // the reduced Gram block, 16 entries per thread and round requested together
-    const int tot = cnt * (2 * cnt + 1);
+    const int tot = cnt * (2 * cnt + 1) + (minres ? cnt * (cnt + 1) : 0);
     for (int e0 = 0; e0 < tot; e0 += 16 * (int)blockDim.x) {
       double v[16];
 #pragma unroll
@@ -743,12 +881,12 @@ __global__ __launch_bounds__(TPB) void k_small_solve(int cnt, int spd, double ta
   for (int e = tid; e < k2 * k2; e += blockDim.x) {
     const int a = e % k2, b = e / k2;
     double acc = 0.0;
-    for (int l = 0; l <= b; ++l) acc += P[perm[a] + (cnt + perm[l]) * cnt] * Ri[l + b * k];
+    for (int l = 0; l <= b; ++l) acc += P[hoff + perm[a] + perm[l] * cnt] * Ri[l + b * k];
     Hm[a + b * k] = acc;
   }
   for (int a = tid; a < k2; a += blockDim.x) {
     double acc = 0.0;
-    for (int l = 0; l <= a; ++l) acc += Ri[l + a * k] * P[perm[l] + (2 * cnt) * cnt];
+    for (int l = 0; l <= a; ++l) acc += Ri[l + a * k] * P[goff + perm[l]];
     gv[a] = acc;
   }
   __syncthreads();
@@ -903,10 +1041,9 @@ __global__ __launch_bounds__(TPB) void k_small_solve(int cnt, int spd, double ta
 }
 
 hipError_t launch_small_solve(int cnt, int minres, int spd, double tau_c, Ctl *ctl, hipStream_t st) {
-  (void)minres;
-  size_t lds = ((size_t)3 * cnt * cnt + (size_t)cnt * (2 * cnt + 1)) * sizeof(double);
+  size_t lds = ((size_t)3 * cnt * cnt + (size_t)gram_width(cnt, minres)) * sizeof(double);
   if (lds == 0) lds = sizeof(double);
-  hipLaunchKernelGGL(k_small_solve, dim3(1), dim3(TPB), lds, st, cnt, spd, tau_c, ctl);
+  hipLaunchKernelGGL(k_small_solve, dim3(1), dim3(TPB), lds, st, cnt, minres, minres ? 1 : spd, tau_c, ctl);
   return hipGetLastError();
 }
 
@@ -1069,7 +1206,7 @@ size_t partials_doubles(int64_t n, int M, int s) {
   (void)n;
   size_t a = krylov_partials_doubles();                                 // Krylov dots
   size_t b = (size_t)MAXBLK * SKETCH_RG;                                // sketch
-  size_t c = (size_t)GRAM_MAXBLK * M * (2 * M + 1);                     // Gram
+  size_t c = (size_t)GRAM_MAXBLK * M * (3 * M + 2);                     // Gram (minimum residual)
   (void)s;
   size_t m = a > b ? a : b;
   return m > c ? m : c;

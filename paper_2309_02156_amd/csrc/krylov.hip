@@ -28,14 +28,19 @@ constexpr int KTPB = 512;
 constexpr int KNW = KTPB / WAVE;
 constexpr int KMAXBLK = 256;
 constexpr int KW = 64;  // stride of a partial row
+// CG kernels: wave tiles, up to four blocks of KTPB threads per compute unit (each
+// block's LDS is its waves' product slices), so up to 1024 partial rows
+constexpr int CG_MAXBLK = 1024;
+constexpr int PROWS = CG_MAXBLK > KMAXBLK ? CG_MAXBLK : KMAXBLK;  // rows of each partial buffer
 
 static inline int kblocks(int64_t n) {
   int64_t b = (n + KTPB - 1) / KTPB;
   if (b < 1) b = 1;
   return (int)(b > KMAXBLK ? KMAXBLK : b);
 }
+static inline int cgblocks(int64_t n) { return wave_tile_blocks(n, KTPB, CG_MAXBLK); }
 static inline double *PA(double *P) { return P; }
-static inline double *PB(double *P) { return P + (size_t)KMAXBLK * KW; }
+static inline double *PB(double *P) { return P + (size_t)PROWS * KW; }
 
 #define KROWS(i, n) \
   for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < (n); i += (int64_t)gridDim.x * blockDim.x)
@@ -146,29 +151,31 @@ __device__ inline double pick4(const double (&r)[4], int e) {
 // recursive-residual stop (state CHECK) the host's batch-end confirmation recomputes
 // the true residual; if it fails the direction restarts (p = r).
 
-template <typename VT, typename TV>
+template <typename VT, typename TV, int C>
 __global__ __launch_bounds__(KTPB) void k_cg_start(const int *rowptr, const int *col, const VT *val,
                                                    const TV *b, const TV *x, TV *r, int64_t n, int mode,
                                                    double *Pout, const Ctl *ctl) {
   __shared__ double red[KNW * 2];
-  __shared__ double prod[SPMV_CAP];
+  __shared__ double prod[KNW * WT_CAP];
   __shared__ int s_go;
   if (threadIdx.x == 0) s_go = (mode != 1) || (ctl->state == ST_CHECK);
   __syncthreads();
   if (!s_go) return;
+  const int lane = threadIdx.x % WAVE, wid = threadIdx.x / WAVE;
+  double *pw = prod + (size_t)wid * WT_CAP;
+  (void)lane;
+  const Gather1<TV> gx{x};
   double acc[2] = {0.0, 0.0};
-  KTILES(r0, n) {
-    const double ax = tile_spmv<KTPB>(rowptr, col, val, x, n, r0, prod);
-    const int64_t i = r0 + threadIdx.x;
-    if (i < n) {
-      const double bi = (double)b[i];
-      const TV rs = (TV)(bi - ax);
-      if (mode != 2) r[i] = rs;
-      const double ri = (double)rs;
-      acc[0] += ri * ri;
-      acc[1] += bi * bi;
-    }
-  }
+  const WaveTiles wt = wave_tiles(n);
+  wave_tiles_spmv_pipelined<C>(
+      rowptr, col, val, gx, n, wt.t, wt.end, wt.step, pw, [&](int64_t i) { return (double)b[i]; },
+      [&](int64_t i, double bi, double ax) {
+        const TV rs = (TV)(bi - ax);
+        if (mode != 2) r[i] = rs;
+        const double ri = (double)rs;
+        acc[0] += ri * ri;
+        acc[1] += bi * bi;
+      });
   kstore<2>(acc, 2, red, Pout + (size_t)blockIdx.x * KW);
 }
 
@@ -203,26 +210,31 @@ struct GatherDir {
   const TV *__restrict__ p;
   double beta;
   int fresh;
-  // the direction entry as it is stored (rounded to TV), so q = A p uses the same p
+  // the direction entry as it is stored (rounded to TV), so q = A p uses the same p.
+  // Both entries are loaded unconditionally: with the load of p[c] under the branch on
+  // `fresh` the compiler waited for each gather before issuing the next one.
   __device__ double operator()(int c) const {
-    return fresh ? (double)r[c] : (double)(TV)((double)r[c] + beta * (double)p[c]);
+    const double rv = (double)r[c];
+    const double pv = (double)p[c];
+    const double d = (double)(TV)(rv + beta * pv);
+    return fresh ? rv : d;
   }
 };
 
-// R = row tiles of KTPB rows each block takes at once
-template <typename VT, typename TV, int R>
+// C = gathers per lane and round of a wave tile
+template <typename VT, typename TV, int C>
 __global__ __launch_bounds__(KTPB) void k_cg_p(const int *rowptr, const int *col, const VT *val, const TV *r,
                                                TV *P0, TV *P1, TV *q, int64_t n, const double *Pin, int nblk,
                                                double *Pout, Ctl *ctl, int lidx) {
   __shared__ double red[KNW];
   __shared__ double outv[1];
   __shared__ double scratch[KTPB];
-  __shared__ double prod[SPMV_CAP * R];
+  __shared__ double prod[KNW * WT_CAP];
   __shared__ int s_k, s_fresh, s_go, s_cont, s_maxit;
   __shared__ double s_beta, s_tolb, s_rho2;
   // r^T r of the previous iteration (unused when the direction restarts), loaded
   // together with the control block
-  const double part = final_part<1>(Pin, nblk, KW, 1);
+  const double part = final_part<2>(Pin, nblk, KW, 1);
   if (threadIdx.x == 0) {
     // every control-block read of the kernel, issued together
     const int st = ctl->state, it = ctl->iters, fa = ctl->fresh_at, mx = ctl->maxit;
@@ -269,32 +281,22 @@ __global__ __launch_bounds__(KTPB) void k_cg_p(const int *rowptr, const int *col
   const TV *pin = (k & 1) ? P0 : P1;
   TV *pout = (k & 1) ? P1 : P0;
   const GatherDir<TV> gx{r, pin, beta, fresh};
+  const int lane = threadIdx.x % WAVE, wid = threadIdx.x / WAVE;
+  double *pw = prod + (size_t)wid * WT_CAP;
+  (void)lane;
   double acc[1] = {0.0};
-  for (int64_t r0 = (int64_t)blockIdx.x * (R * KTPB); r0 < n; r0 += (int64_t)gridDim.x * (R * KTPB)) {
-    // the rows' own direction entries, requested before the SpMV (exact: gx rounds to TV)
-    double pv[R];
-#pragma unroll
-    for (int u = 0; u < R; ++u) {
-      const int64_t i = r0 + (int64_t)u * KTPB + threadIdx.x;
-      pv[u] = gx((int)(i < n ? i : n - 1));
-    }
-    const TileRowsR<R> tr = tile_spmv_stage_r<KTPB, R, SPMV_CAP * R>(rowptr, col, val, gx, n, r0, prod);
-    __syncthreads();
-    double qi[R];
-    tile_spmv_sum_r<R>(tr, col, val, gx, prod, qi);
-    __syncthreads();
-#pragma unroll
-    for (int u = 0; u < R; ++u) {
-      const int64_t i = r0 + (int64_t)u * KTPB + threadIdx.x;
-      if (i < n) {
-        const TV ps = (TV)pv[u];
+  const WaveTiles wt = wave_tiles(n);
+  // the row's own direction entry is requested with the tile's gathers (exact: gx rounds
+  // to TV); the next tile's index loads overlap this tile's gathers
+  wave_tiles_spmv_pipelined<C>(
+      rowptr, col, val, gx, n, wt.t, wt.end, wt.step, pw, [&](int64_t i) { return gx((int)i); },
+      [&](int64_t i, double pv, double qi) {
+        const TV ps = (TV)pv;
         pout[i] = ps;
-        const TV qs = (TV)qi[u];
+        const TV qs = (TV)qi;
         q[i] = qs;
         acc[0] += (double)ps * (double)qs;
-      }
-    }
-  }
+      });
   kstore<1>(acc, 1, red, Pout + (size_t)blockIdx.x * KW);
 }
 
@@ -307,7 +309,7 @@ __global__ __launch_bounds__(KTPB) void k_cg_xr(TV *x, TV *r, const TV *P0, cons
   __shared__ double scratch[KTPB];
   __shared__ int s_k, s_go, s_st;
   __shared__ double s_rho;
-  const double part = final_part<1>(Pin, nblk, KW, 1);  // p^T q, loaded with the control block
+  const double part = final_part<2>(Pin, nblk, KW, 1);  // p^T q, loaded with the control block
   if (threadIdx.x == 0) {
     const int st = ctl->state, k = ctl->kcur;
     double r4[4];
@@ -367,49 +369,94 @@ __global__ __launch_bounds__(KTPB) void k_cg_xr(TV *x, TV *r, const TV *P0, cons
   }
 }
 
-template <typename TV>
-hipError_t launch_cg_start_k(const CsrView &A, const TV *b, const TV *x, TV *r, int mode, double *partials, Ctl *ctl,
-                             hipStream_t st, int serial) {
-  const int nb = kblocks(A.n);
-  if (A.fp32)
-    hipLaunchKernelGGL((k_cg_start<float, TV>), dim3(nb), dim3(KTPB), 0, st, A.rowptr, A.col,
-                       (const float *)A.val, b, x, r, A.n, mode, PA(partials), ctl);
-  else
-    hipLaunchKernelGGL((k_cg_start<double, TV>), dim3(nb), dim3(KTPB), 0, st, A.rowptr, A.col,
-                       (const double *)A.val, b, x, r, A.n, mode, PA(partials), ctl);
-  hipLaunchKernelGGL(k_cg_start_close, dim3(1), dim3(KTPB), 0, st, PA(partials), nb, mode, ctl, serial);
-  return hipGetLastError();
+// Grid of the CG iteration kernels: one wave tile per wave, at most the blocks the device
+// holds at once (every block of the grid-stride loop resident, so no tail of late
+// blocks), a multiple of NXCD.  The p / q kernel's registers decide the occupancy.
+template <typename VT, typename TV, int C>
+static int cg_grid(int64_t n) {
+  static int resident = 0;  // blocks of k_cg_p<VT, TV, C> the device holds at once
+  if (resident == 0) {
+    int dev = 0, ncu = 0, per = 0;
+    if (hipGetDevice(&dev) != hipSuccess ||
+        hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
+        hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, k_cg_p<VT, TV, C>, KTPB, 0) != hipSuccess || per < 1)
+      return cgblocks(n);
+    const int r = per * ncu / NXCD * NXCD;
+    resident = r < NXCD ? NXCD : (r > CG_MAXBLK ? CG_MAXBLK : r);
+  }
+  const int nb = cgblocks(n);
+  return nb < resident ? nb : resident;
 }
 
-// row tiles per block pass of the CG kernels: as many as every block has (1, 2 or 4)
-static inline int cg_rows(int64_t n) {
-  const int64_t passes = (n + (int64_t)KTPB * KMAXBLK - 1) / ((int64_t)KTPB * KMAXBLK);
-  return passes >= 4 ? 4 : (passes >= 2 ? 2 : 1);
+// rows each thread of the x / r kernel takes per pass (all its loads issued first)
+static inline int cg_rows(int64_t n, int nb) {
+  const int64_t threads = (int64_t)KTPB * nb;
+  const int64_t per = (n + threads - 1) / threads;
+  return per >= 4 ? 4 : (per >= 2 ? 2 : 1);
 }
 
-template <typename VT, typename TV, int R>
+template <typename VT, typename TV, int C, int U>
 static void cg_iter_launch(const CsrView &A, TV *x, TV *r, TV *P0, TV *P1, TV *q, double *partials, Ctl *ctl,
-                           hipStream_t st, const KTiming *tm, int serial) {
-  const int nb = kblocks(A.n);
+                           hipStream_t st, const KTiming *tm, int serial, int nb) {
   // timed launches record their start/stop events in the kernel's own dispatch
   hipEvent_t e0 = tm ? tm->e0 : nullptr, e1 = tm ? tm->e1 : nullptr;
   const int lidx = tm ? tm->lidx : -1;
-  hipExtLaunchKernelGGL((k_cg_p<VT, TV, R>), dim3(nb), dim3(KTPB), 0, st, e0, e1, 0, A.rowptr, A.col,
+  hipExtLaunchKernelGGL((k_cg_p<VT, TV, C>), dim3(nb), dim3(KTPB), 0, st, e0, e1, 0, A.rowptr, A.col,
                         (const VT *)A.val, r, P0, P1, q, A.n, PA(partials), nb, PB(partials), ctl, lidx);
-  hipLaunchKernelGGL((k_cg_xr<TV, R>), dim3(nb), dim3(KTPB), 0, st, x, r, P0, P1, q, A.n, PB(partials), nb,
+  hipLaunchKernelGGL((k_cg_xr<TV, U>), dim3(nb), dim3(KTPB), 0, st, x, r, P0, P1, q, A.n, PB(partials), nb,
                      PA(partials), ctl, serial);
+}
+
+template <typename VT, typename TV, int C>
+static void cg_iter_u(const CsrView &A, TV *x, TV *r, TV *P0, TV *P1, TV *q, double *partials, Ctl *ctl,
+                      hipStream_t st, const KTiming *tm, int serial) {
+  const int nb = cg_grid<VT, TV, C>(A.n);
+  const int U = cg_rows(A.n, nb);
+  if (U == 4)
+    cg_iter_launch<VT, TV, C, 4>(A, x, r, P0, P1, q, partials, ctl, st, tm, serial, nb);
+  else if (U == 2)
+    cg_iter_launch<VT, TV, C, 2>(A, x, r, P0, P1, q, partials, ctl, st, tm, serial, nb);
+  else
+    cg_iter_launch<VT, TV, C, 1>(A, x, r, P0, P1, q, partials, ctl, st, tm, serial, nb);
+}
+
+template <typename VT, typename TV, int C>
+static int cg_start_c(const CsrView &A, const TV *b, const TV *x, TV *r, int mode, double *partials, const Ctl *ctl,
+                      hipStream_t st) {
+  const int nb = cg_grid<VT, TV, C>(A.n);
+  hipLaunchKernelGGL((k_cg_start<VT, TV, C>), dim3(nb), dim3(KTPB), 0, st, A.rowptr, A.col, (const VT *)A.val, b,
+                     x, r, A.n, mode, PA(partials), ctl);
+  return nb;
+}
+
+template <typename VT, typename TV>
+static int cg_start_launch(const CsrView &A, const TV *b, const TV *x, TV *r, int mode, double *partials,
+                           const Ctl *ctl, hipStream_t st) {
+  const int C = wave_tile_chunk(A.n, A.nnz);
+  if (C <= 5) return cg_start_c<VT, TV, 5>(A, b, x, r, mode, partials, ctl, st);
+  if (C <= 7) return cg_start_c<VT, TV, 7>(A, b, x, r, mode, partials, ctl, st);
+  return cg_start_c<VT, TV, 9>(A, b, x, r, mode, partials, ctl, st);
+}
+
+template <typename TV>
+hipError_t launch_cg_start_k(const CsrView &A, const TV *b, const TV *x, TV *r, int mode, double *partials, Ctl *ctl,
+                             hipStream_t st, int serial) {
+  const int nb = A.fp32 ? cg_start_launch<float, TV>(A, b, x, r, mode, partials, ctl, st)
+                        : cg_start_launch<double, TV>(A, b, x, r, mode, partials, ctl, st);
+  hipLaunchKernelGGL(k_cg_start_close, dim3(1), dim3(KTPB), 0, st, PA(partials), nb, mode, ctl, serial);
+  return hipGetLastError();
 }
 
 template <typename VT, typename TV>
 static void cg_iter_vt(const CsrView &A, TV *x, TV *r, TV *P0, TV *P1, TV *q, double *partials, Ctl *ctl,
                        hipStream_t st, const KTiming *tm, int serial) {
-  const int R = cg_rows(A.n);
-  if (R == 4)
-    cg_iter_launch<VT, TV, 4>(A, x, r, P0, P1, q, partials, ctl, st, tm, serial);
-  else if (R == 2)
-    cg_iter_launch<VT, TV, 2>(A, x, r, P0, P1, q, partials, ctl, st, tm, serial);
+  const int C = wave_tile_chunk(A.n, A.nnz);
+  if (C <= 5)
+    cg_iter_u<VT, TV, 5>(A, x, r, P0, P1, q, partials, ctl, st, tm, serial);
+  else if (C <= 7)
+    cg_iter_u<VT, TV, 7>(A, x, r, P0, P1, q, partials, ctl, st, tm, serial);
   else
-    cg_iter_launch<VT, TV, 1>(A, x, r, P0, P1, q, partials, ctl, st, tm, serial);
+    cg_iter_u<VT, TV, 9>(A, x, r, P0, P1, q, partials, ctl, st, tm, serial);
 }
 
 template <typename TV>
@@ -1398,10 +1445,10 @@ SACC_INSTANTIATE_KRYLOV(float)
 // power of two apart map onto the same memory channels)
 int64_t padded_ld(int64_t n) { return (n + 511) / 512 * 512 + 576; }
 
-size_t krylov_partials_doubles() { return (size_t)2 * KMAXBLK * KW; }
+size_t krylov_partials_doubles() { return (size_t)2 * PROWS * KW; }
 
 int gm_f_rows_per_thread(int64_t n, int rb) { return rb <= 8 && gm_two_rows(n) ? 2 : 1; }
 
-int cg_rows_per_thread(int64_t n) { return cg_rows(n); }
+int cg_tile_chunk(int64_t n, int64_t nnz) { return wave_tile_chunk(n, nnz); }
 
 }  // namespace sacc

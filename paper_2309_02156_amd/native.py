@@ -19,13 +19,14 @@ SA_CG, SA_GMRES = 0, 1
 SA_GALERKIN, SA_MINRES = 0, 1
 SA_SKETCH_GAUSSIAN, SA_SKETCH_SRHT = 0, 1
 SA_GUESS_PROJECTION, SA_GUESS_ZERO, SA_GUESS_PREVIOUS = 0, 1, 2
+SA_BASIS_SKETCHED_QR = 0
 
 EXPORTS = ("sa_workspace_bytes", "sa_init_sequence", "sa_push_solution", "sa_initial_guess",
            "sa_solve", "sa_step", "sa_destroy_sequence", "sa_status_string", "sa_spmv", "sa_copy_state",
            "sa_profile_enable", "sa_profile_read", "sa_mlp_create", "sa_mlp_destroy", "sa_mlp_set_scaling",
            "sa_mlp_forward", "sa_mlp_train_step", "sa_mlp_get", "sa_learned_attach", "sa_set_time",
            "sa_batch_create", "sa_batch_destroy", "sa_batch_step", "sa_batch_plan", "sa_solve_static",
-           "sa_static_scratch_bytes")
+           "sa_static_scratch_bytes", "sa_state_bytes", "sa_export_state", "sa_import_state")
 
 
 class SaConfig(ctypes.Structure):
@@ -37,6 +38,8 @@ class SaConfig(ctypes.Structure):
         ("max_refine", ctypes.c_int32), ("guess", ctypes.c_int32),
         ("rank_tol_sketch", ctypes.c_double), ("rank_tol_chol", ctypes.c_double),
         ("seed", ctypes.c_uint64), ("poll", ctypes.c_int32), ("inner_maxit", ctypes.c_int32),
+        ("m", ctypes.c_int32), ("refresh", ctypes.c_int32), ("basis", ctypes.c_int32),
+        ("reserved2", ctypes.c_int32),
     ]
 
 
@@ -119,6 +122,9 @@ def lib() -> ctypes.CDLL:
     L.sa_batch_plan.argtypes = [vp, P(i32), P(i32), P(i32)]
     L.sa_solve_static.argtypes = [P(SaConfig), P(SaCsr), vp, vp, P(SaInfo), vp]
     L.sa_static_scratch_bytes.argtypes = [P(SaConfig), P(sz), P(sz)]
+    L.sa_state_bytes.argtypes = [vp, P(sz)]
+    L.sa_export_state.argtypes = [vp, vp, sz, vp]
+    L.sa_import_state.argtypes = [vp, vp, sz, vp]
     for name in EXPORTS:
         if name != "sa_status_string":
             getattr(L, name).restype = i32

@@ -18,6 +18,7 @@ _SKETCH = {"gaussian": nv.SA_SKETCH_GAUSSIAN, "srht": nv.SA_SKETCH_SRHT}
 _SOLVER = {"cg": nv.SA_CG, "gmres": nv.SA_GMRES}
 _PREC = {"fp64": nv.SA_FP64, "mixed": nv.SA_MIXED, "mixed_krylov": nv.SA_MIXED_KRYLOV}
 _PROJ = {"galerkin": nv.SA_GALERKIN, "minres": nv.SA_MINRES}
+_BASIS = {"sketched_qr": nv.SA_BASIS_SKETCHED_QR}
 _GUESS = {"projection": nv.SA_GUESS_PROJECTION, "zero": nv.SA_GUESS_ZERO,
           "previous": nv.SA_GUESS_PREVIOUS}
 
@@ -78,7 +79,8 @@ def solver_config(n: int, solver: str = "cg", restart: int = 30, tol: float = 1e
     return nv.SaConfig(n=n, M=1, s=1, sketch=nv.SA_SKETCH_GAUSSIAN, projection=nv.SA_GALERKIN,
                        solver=_SOLVER[solver], restart=restart, tol=tol, maxit=maxit, precision=nv.SA_FP64,
                        inner_tol=1e-4, max_refine=1, guess=nv.SA_GUESS_ZERO, rank_tol_sketch=0.0,
-                       rank_tol_chol=0.0, seed=0, poll=poll, inner_maxit=0)
+                       rank_tol_chol=0.0, seed=0, poll=poll, inner_maxit=0, m=0, refresh=0,
+                       basis=nv.SA_BASIS_SKETCHED_QR, reserved2=0)
 
 
 def solve_static(A: DeviceCSR, b: torch.Tensor, x: torch.Tensor, solver: str = "cg", restart: int = 30,
@@ -104,8 +106,8 @@ class Sequence:
                  solver: str = "cg", restart: int = 30, tol: float = 1e-8, maxit: int = 200000,
                  precision: str = "fp64", projection: str = "galerkin", guess: str = "projection",
                  seed: int = 0, rank_tol_sketch: float = 0.0, rank_tol_chol: float = 0.0,
-                 inner_tol: float = 1e-4, max_refine: int = 10, inner_maxit: int = 0, poll: int = 0, device="cuda",
-                 stream=None):
+                 inner_tol: float = 1e-4, max_refine: int = 10, inner_maxit: int = 0, poll: int = 0,
+                 m: int = 0, refresh: int = 0, basis: str = "sketched_qr", device="cuda", stream=None):
         self.n, self.M = n, M
         self.s = 2 * M if s is None else s
         self.precision = precision
@@ -114,7 +116,8 @@ class Sequence:
             solver=_SOLVER[solver], restart=restart, tol=tol, maxit=maxit,
             precision=_PREC[precision], inner_tol=inner_tol, max_refine=max_refine,
             guess=_GUESS[guess], rank_tol_sketch=rank_tol_sketch, rank_tol_chol=rank_tol_chol,
-            seed=seed, poll=poll, inner_maxit=inner_maxit)
+            seed=seed, poll=poll, inner_maxit=inner_maxit, m=m, refresh=refresh, basis=_BASIS[basis],
+            reserved2=0)
         L = nv.lib()
         nbytes = ctypes.c_size_t(0)
         nv.check(L.sa_workspace_bytes(ctypes.byref(self.cfg), ctypes.byref(nbytes)), "sa_workspace_bytes")
@@ -189,6 +192,21 @@ class Sequence:
     def last_target(self) -> np.ndarray:
         """The learned target written by the last push (M coefficients, lag order)."""
         return self.copy_state("target")
+
+    # ------------------------------------------------------------------ checkpoint
+    def export_state(self) -> bytes:
+        """The sequence's carried state (history, sketch, sketched QR) as bytes."""
+        L = nv.lib()
+        nb = ctypes.c_size_t(0)
+        nv.check(L.sa_state_bytes(self._h, ctypes.byref(nb)), "sa_state_bytes")
+        buf = ctypes.create_string_buffer(nb.value)
+        nv.check(L.sa_export_state(self._h, buf, nb.value, _stream(self.stream)), "sa_export_state")
+        return buf.raw
+
+    def import_state(self, image: bytes):
+        """Resume from export_state's bytes (a fresh sequence of the same configuration)."""
+        buf = ctypes.create_string_buffer(image, len(image))
+        nv.check(nv.lib().sa_import_state(self._h, buf, len(image), _stream(self.stream)), "sa_import_state")
 
     # ------------------------------------------------------------------ inspection
     def profile_enable(self, enable: bool = True):

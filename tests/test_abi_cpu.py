@@ -58,7 +58,7 @@ def test_workspace_sizes_and_validation(nv):
     assert b.value > small   # GMRES(30) basis is larger than CG's three vectors
     bad = [dict(M=0), dict(M=33), dict(s=5), dict(s=300), dict(sketch=1, n=1000), dict(sketch=1, n=16, s=20, M=4),
            dict(solver=1, restart=0), dict(solver=1, restart=65), dict(tol=0.0), dict(tol=-1.0),
-           dict(maxit=-1), dict(guess=7), dict(n=0), dict(sketch=5), dict(projection=3), dict(precision=4)]
+           dict(maxit=-1), dict(guess=7), dict(n=0), dict(sketch=5), dict(projection=3), dict(projection=2), dict(precision=4)]
     for over in bad:
         assert L.sa_workspace_bytes(ctypes.byref(_cfg(nv, **over)), ctypes.byref(b)) == nv.SA_EINVAL, over
     assert L.sa_workspace_bytes(None, ctypes.byref(b)) == nv.SA_EINVAL
@@ -73,6 +73,10 @@ def test_null_handles_and_status_strings(nv):
     assert L.sa_step(None, None, None, None, None, None) == nv.SA_ESTATE
     assert L.sa_spmv(None, None, None, None) == nv.SA_EINVAL
     assert L.sa_copy_state(None, 0, None, 0, None) == nv.SA_ESTATE
+    nb = ctypes.c_size_t(0)
+    assert L.sa_state_bytes(None, ctypes.byref(nb)) == nv.SA_ESTATE
+    assert L.sa_export_state(None, None, 0, None) == nv.SA_ESTATE
+    assert L.sa_import_state(None, None, 0, None) == nv.SA_ESTATE
     for code in (0, 1, -1, -2, -3, -4, -5, -6):
         s = L.sa_status_string(code).decode()
         assert s and s != "unknown status"
@@ -152,6 +156,7 @@ def test_product_path_does_not_touch_the_oracle():
         if f.endswith(".py"):
             text = open(os.path.join(ROOT, "oracle", f)).read()
             assert "paper_2309_02156_amd" not in text, f
+
 
 def test_static_solve_limits(nv):
     """The allocation-free solve reports its fixed scratch, rejects configurations that do

@@ -131,7 +131,8 @@ def test_affine_value_basis_reproduces_assembly():
     to stage long runs on the device equals the direct assembly to rounding."""
     from gen import batch_problems
 
-    cases = [config(0, N=20)[0], config(1, N=32)[0]] + [p for p, _ in batch_problems(nseq=3, lo=16, hi=40)]
+    cases = [config(0, N=20)[0], config(1, N=32)[0], config(2, N=12)[0]] + \
+        [p for p, _ in batch_problems(nseq=3, lo=16, hi=40)]
     for p in cases:
         B = p.value_basis()
         for i in (0, 7, 33):

@@ -56,3 +56,66 @@ def test_batch_equals_sequential_and_tunes(sacc):
     plan = batch.plan()
     print_case("plan", plan)
     assert plan["tuned"] and 1 <= plan["streams"] <= 4
+
+
+def test_batch_matches_oracle(sacc):
+    """Each sequence of a batch, stepped by the batch driver in its own configuration
+    (float32 operator and Krylov vectors, FP64 history and refinement, up to 100 sweeps),
+    against the oracle on the same history: before every step the oracle's history holds
+    exactly the solutions the GPU pushed.  Equal kept ranks; both meet the tolerance; per
+    step the iteration counts within twice the oracle's own change under a rounding-only
+    perturbation (reversed summation order of A x, or its start perturbed by 1e-15
+    relative), at least one per refinement sweep and 10 % (each side starts from its own
+    guess, and the float32 inner solves of the first steps' two sweeps move by several
+    iterations under such perturbations); the totals over all steps within 3 %."""
+    import math
+
+    import torch
+
+    from oracle.sequence import Sequence as OSeq
+    from tests.gpu_helpers import reversed_order
+
+    probs = batch_problems(seed=4, nseq=5, lo=16, hi=36, steps=40)
+    steps = 20
+    print_case("batch vs oracle", [(p.N, m["M"], m["solver"]) for p, m in probs], steps)
+    seqs = [_seq(sacc, p, m) for p, m in probs]
+    batch = sacc.Batch(seqs, max_streams=4, tune_warmup=4)
+    oseqs = [OSeq(p.n, m["M"], m["sketch"], m["s"], m["method_seed"], m["solver"], m["restart"], m["tol"],
+                  precision=m["prec"], max_refine=m["max_refine"]) for p, m in probs]
+    rows = []
+    rng = np.random.default_rng(11)
+    tot_g = tot_o = 0
+    for i in range(steps):
+        As = [sacc.DeviceCSR.from_csr(p.matrix(i)) for p, _ in probs]
+        bs = [dev(p.rhs(i)) for p, _ in probs]
+        xb = [torch.empty(p.n, dtype=torch.float64, device="cuda") for p, _ in probs]
+        ref = []
+        for j, (p, m) in enumerate(probs):
+            Asc = p.matrix(i).to_scipy().astype(np.float64)
+            b = p.rhs(i)
+            g = oseqs[j].initial_guess(Asc, b)
+            xo, oinfo = oseqs[j].solve(Asc, b, g.x0)
+            ref.append((Asc, b, g, oinfo))
+        infos = batch.step(As, bs, xb)
+        for j, (p, m) in enumerate(probs):
+            Asc, b, g, oinfo = ref[j]
+            gi = infos[j]
+            xg = host(xb[j])
+            rel = np.linalg.norm(b - Asc @ xg) / np.linalg.norm(b)
+            assert rel <= m["tol"] * (1 + 1e-6) and oinfo["relres"] <= m["tol"], (i, j, rel, oinfo["relres"])
+            assert gi["k_sketch"] == g.k and gi["k_eff"] == g.k2, (i, j, gi["k_sketch"], gi["k_eff"], g.k, g.k2)
+            # each side starts from its own guess (equal up to rounding); the allowance
+            # is calibrated by the oracle's own change when its start or its A x is
+            # perturbed at rounding level, floored at one per sweep and 10 %
+            sweeps = max(gi["refinements"], oinfo["refinements"], 1)
+            _, o2 = oseqs[j].solve(reversed_order(Asc), b, g.x0)
+            _, o3 = oseqs[j].solve(Asc, b, g.x0 * (1.0 + 1e-15 * rng.standard_normal(p.n)))
+            spread = max(abs(o2["iters"] - oinfo["iters"]), abs(o3["iters"] - oinfo["iters"]))
+            allowed = max(sweeps, 2 * spread + 1, math.ceil(0.1 * oinfo["iters"]))
+            assert abs(gi["iters"] - oinfo["iters"]) <= allowed, (i, j, gi["iters"], oinfo["iters"], allowed)
+            rows.append((i, j, gi["iters"], oinfo["iters"], spread, gi["k_eff"]))
+            tot_g += gi["iters"]
+            tot_o += oinfo["iters"]
+            oseqs[j].push(xg)   # the oracle's history follows the GPU's
+    print_case("(step, seq, iters gpu, iters oracle, oracle spread, k)", rows)
+    assert abs(tot_g - tot_o) <= 0.03 * tot_o, (tot_g, tot_o)

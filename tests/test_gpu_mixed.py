@@ -2,10 +2,10 @@
 emulation of it (``oracle.mixed``, ``oracle.sequence`` with precision="mixed").
 
 Bar: both sides reach the FP64 tolerance against the float32-valued operator after
-refinement; per step the iteration counts agree within one per refinement sweep (the
-two sides round their float32-stored inner vectors at slightly different points), or,
-for long restarted solves, within 2% or twice the oracle's own change under a
-rounding-only perturbation;
+refinement; per step the iteration counts agree within one per refinement sweep for CG;
+for float32 GMRES(30), whose count moves by tens of iterations under a rounding-only
+change on the oracle side alone, within 2% or twice the oracle's own change under a
+rounding-only perturbation (reversed summation order in A x);
 the guesses agree far below the tolerance unless the float32 rounding of the basis
 flips a last bit, so their difference is bounded by 1e-2 tol ||b|| plus 1e-3 of the
 oracle guess's own residual.  The difference of the final solutions is printed per step.
@@ -80,11 +80,18 @@ def test_mixed_stepwise(sacc, k, N, steps, prec):
         assert oinfo["relres"] <= m["tol"]
         sweeps = max(sinfo["refinements"], oinfo["refinements"], 1)
         assert abs(sinfo["refinements"] - oinfo["refinements"]) <= 1, (i, sinfo, oinfo)
-        # the oracle's own sensitivity to a rounding-only change (reversed summation
-        # order in A x) calibrates the allowance for long restarted float32 solves
-        _, oinfo2 = oseq.solve(reversed_order(As), b, g.x0)
-        spread = abs(oinfo2["iters"] - oinfo["iters"])
-        allowed = max(sweeps, 2 * spread + 1, math.ceil(0.02 * oinfo["iters"]))
+        if m["solver"] == "cg":
+            # one iteration per refinement sweep: both sides start every sweep from the
+            # same FP64 residual up to rounding
+            allowed = sweeps
+            spread = 0
+        else:
+            # float32 GMRES(30) with capped cycles: the oracle's own count moves by tens
+            # of iterations under a rounding-only change (reversed summation order in
+            # A x), so the allowance is calibrated by that change
+            _, oinfo2 = oseq.solve(reversed_order(As), b, g.x0)
+            spread = abs(oinfo2["iters"] - oinfo["iters"])
+            allowed = max(sweeps, 2 * spread + 1, math.ceil(0.02 * oinfo["iters"]))
         assert abs(sinfo["iters"] - oinfo["iters"]) <= allowed, (i, sinfo["iters"], oinfo["iters"], spread)
         rows.append((i, sinfo["iters"], oinfo["iters"], sinfo["refinements"], oinfo["refinements"],
                      float(np.linalg.norm(xg - xo) / max(np.linalg.norm(xo), 1e-300))))
