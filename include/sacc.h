@@ -66,6 +66,14 @@ extern "C" {
 #define SA_SKETCH_SRHT 1     /* S = s^-1/2 R H D, n a power of two                     */
 
 #define SA_BASIS_SKETCHED_QR 0 /* QR with column pivoting of the sketch S X (Z), Cholesky finish */
+#define SA_PRECOND_NONE 0   /* unpreconditioned Krylov solve                          */
+#define SA_PRECOND_JACOBI 1 /* D = diag(A) (zero or missing entries taken as 1): CG on
+                               z = D^-1 r, GMRES right-preconditioned on A D^-1, so the
+                               stopping test stays on the true residual ||b - A x||   */
+#define SA_BASIS_POD 1         /* Alg. 2: the m leading left singular vectors of X, from the
+                                  eigen-decomposition of X^T X (FP64); singular values below
+                                  1e-7 of the largest are dropped (not resolved through the
+                                  Gram); the same Cholesky finish                          */
 
 #define SA_GUESS_PROJECTION 0 /* the method: x0 = Q y                                  */
 #define SA_GUESS_ZERO 1       /* x0 = 0                                                 */
@@ -98,8 +106,10 @@ typedef struct {
                              it was given, Alg. 3), so the basis spans X Z; 0 or M: Z = I */
   int32_t refresh;        /* with 1 <= m < M: a new Z every `refresh` pushes once the
                              window is full (<= 0: 50, Section 4)                        */
-  int32_t basis;          /* SA_BASIS_SKETCHED_QR                                       */
-  int32_t reserved2;
+  int32_t basis;          /* SA_BASIS_SKETCHED_QR, or SA_BASIS_POD (m: the POD dimension,
+                             0 = M)                                                      */
+  int32_t precond;        /* SA_PRECOND_NONE or SA_PRECOND_JACOBI (mixed modes: from the
+                             FP32 operator, stored in FP32)                          */
 } sa_config;
 
 typedef struct {

@@ -183,7 +183,7 @@ def reduced_solve(A, b: np.ndarray, B: Basis, projection: str = "galerkin",
 
 
 def initial_guess(A, b, X, SX, Z=None, projection="galerkin", spd=True,
-                  tau_s=1e-12, tau_c=1e-12, store=None) -> Guess:
+                  tau_s=1e-12, tau_c=1e-12, store=None, pod_m: int | None = None) -> Guess:
     """x0 of Alg. 1 from a history X (n x M, any column order) and its sketch SX.
 
     Empty or rank-zero history gives x0 = 0.  A non-finite sketch or reduced solution
@@ -195,7 +195,8 @@ def initial_guess(A, b, X, SX, Z=None, projection="galerkin", spd=True,
     if M == 0:
         return Guess(np.zeros(n), 0, 0, np.zeros(0), np.zeros(0), False)
     if np.all(np.isfinite(SX)):
-        B = sketched_basis(X, SX, Z, tau_s, tau_c, store)
+        B = (pod_basis_from_gram(X, pod_m, tau_c, store) if pod_m is not None
+             else sketched_basis(X, SX, Z, tau_s, tau_c, store))
         c = reduced_solve(A, b, B, projection, spd) if np.all(np.isfinite(B.Q1)) else None
         x0 = B.Q1 @ c if c is not None else None
         if x0 is not None and np.all(np.isfinite(x0)):
@@ -238,6 +239,42 @@ def pod_basis(X: np.ndarray, m: int) -> np.ndarray:
     """First m left singular vectors of X (Alg. 2)."""
     U, _, _ = np.linalg.svd(X, full_matrices=False)
     return U[:, :m]
+
+
+POD_TAU = 1e-14  # eigenvalues of X^T X kept above POD_TAU times the largest (sigma ratio 1e-7)
+
+
+def pod_gram_factor(X: np.ndarray, m: int, tau: float = POD_TAU):
+    """Alg. 2 through the Gram matrix: X^T X = V diag(lam) V^T (eigenvalues descending),
+    the POD basis U_m = X V_m diag(lam_m)^(-1/2) = X T1.  Returns (T1, k) with
+    k = min(m, #{lam_j > tau lam_1}); the squared singular values below tau lam_1 are
+    not resolved in FP64 and are dropped.  Pinned against the SVD definition."""
+    M = X.shape[1]
+    if M == 0:
+        return np.zeros((0, 0)), 0
+    G = X.T @ X
+    lam, V = np.linalg.eigh(0.5 * (G + G.T))
+    order = np.argsort(-lam, kind="stable")
+    lam, V = lam[order], V[:, order]
+    if not lam[0] > 0.0:
+        return np.zeros((M, 0)), 0
+    k = int(min(m, np.sum(lam > tau * lam[0])))
+    return V[:, :k] / np.sqrt(lam[:k]), k
+
+
+def pod_basis_from_gram(X: np.ndarray, m: int, tau_c: float = 1e-12, store=None) -> "Basis":
+    """The POD basis (Alg. 2) in the form the guess uses: Q1 = X T1 with T1 from
+    ``pod_gram_factor``, then the same pivoted-Cholesky finish as the sketched basis."""
+    M = X.shape[1]
+    T1, k = pod_gram_factor(X, m)
+    if k == 0:
+        T1 = np.zeros((M, 0))
+    Q1 = X @ T1
+    if store is not None:
+        Q1 = store(Q1)
+    G = Q1.T @ Q1
+    R2, perm2, k2 = pivoted_cholesky(G, tau_c)
+    return Basis(T1, Q1, k, R2, perm2, k2)
 
 
 # ---------------------------------------------------------------------------- Alg. 3 literal

@@ -21,6 +21,14 @@ tolerance, without the true-residual check.
 and a round trip through float32 for the inner solves of the mixed mode (all
 arithmetic stays in float64 between stores).
 
+``dinv`` (optional) applies the Jacobi preconditioner M^-1 = diag(dinv), dinv = 1 / diag(A)
+(``jacobi_dinv``): CG becomes preconditioned CG (z = M^-1 r, beta = r^T z / r_old^T z_old,
+the stopping rule still on ||r||); GMRES is right-preconditioned (Arnoldi on A M^-1, the
+cycle's correction M^-1 V y), so its residual estimate is the true residual's.  The
+paper preconditions every solve (ILU in Section 4, algebraic multigrid in Section 5);
+the diagonal is the simplest such M.  In the mixed mode dinv is stored in float32 like
+the other vectors.
+
 Both return (x, info) with info = dict(iters, restarts, relres, relres0, status),
 status 0 converged, 1 not converged within maxit, -5 breakdown (CG p^T A p <= 0 or
 not finite).  A zero right-hand side returns x = 0 with zero iterations.
@@ -41,8 +49,17 @@ def _identity(v):
     return v
 
 
-def cg(A, b, x0, tol: float, maxit: int = 100000, store=None, confirm: bool = True):
-    """Hestenes-Stiefel conjugate gradients from x0."""
+def jacobi_dinv(A) -> np.ndarray:
+    """1 / diag(A) (an entry 1 where the diagonal is zero or missing)."""
+    d = np.asarray(A.diagonal(), dtype=np.float64)
+    out = np.ones_like(d)
+    nz = d != 0.0
+    out[nz] = 1.0 / d[nz]
+    return out
+
+
+def cg(A, b, x0, tol: float, maxit: int = 100000, store=None, confirm: bool = True, dinv=None):
+    """Hestenes-Stiefel conjugate gradients from x0 (preconditioned with diag(dinv))."""
     st = _identity if store is None else store
     b = np.asarray(b, dtype=np.float64)
     x = st(np.array(x0, dtype=np.float64, copy=True))
@@ -50,14 +67,16 @@ def cg(A, b, x0, tol: float, maxit: int = 100000, store=None, confirm: bool = Tr
     if bnorm == 0.0:
         return np.zeros_like(b), dict(iters=0, restarts=0, relres=0.0, relres0=0.0, status=CONVERGED)
     thresh = tol * bnorm
+    pre = (lambda v: v) if dinv is None else (lambda v: st(dinv) * v)
     r = st(b - A @ x)
-    rho = float(np.dot(r, r))
-    relres0 = np.sqrt(rho) / bnorm
+    rr = float(np.dot(r, r))
+    relres0 = np.sqrt(rr) / bnorm
     it = 0
     restarts = 0
-    if np.sqrt(rho) <= thresh:
+    if np.sqrt(rr) <= thresh:
         return x, dict(iters=0, restarts=0, relres=relres0, relres0=relres0, status=CONVERGED)
-    p = r.copy()
+    p = st(pre(r))
+    rho = float(np.dot(r, pre(r)))
     status = NOTCONV
     while it < maxit:
         q = st(A @ p)
@@ -68,23 +87,25 @@ def cg(A, b, x0, tol: float, maxit: int = 100000, store=None, confirm: bool = Tr
         alpha = rho / pq
         x = st(x + alpha * p)
         r = st(r - alpha * q)
-        rho_new = float(np.dot(r, r))
+        rr_new = float(np.dot(r, r))
         it += 1
-        if np.sqrt(rho_new) <= thresh:
+        if np.sqrt(rr_new) <= thresh:
             if not confirm:
                 status = CONVERGED
                 break
             r = st(b - A @ x)
-            rho = float(np.dot(r, r))
-            if np.sqrt(rho) <= thresh:
+            rr = float(np.dot(r, r))
+            if np.sqrt(rr) <= thresh:
                 status = CONVERGED
                 break
             restarts += 1
-            p = r.copy()
+            p = st(pre(r))
+            rho = float(np.dot(r, pre(r)))
             continue
+        rho_new = float(np.dot(r, pre(r)))
         beta = rho_new / rho
         rho = rho_new
-        p = st(r + beta * p)
+        p = st(pre(r) + beta * p)
     rt = b - A @ x
     return x, dict(iters=it, restarts=restarts, relres=_norm(rt) / bnorm, relres0=relres0,
                    status=status)
@@ -99,9 +120,11 @@ def givens(a: float, b: float):
 
 
 def gmres(A, b, x0, tol: float, restart: int = 30, maxit: int = 100000, store=None,
-          confirm: bool = True):
-    """Restarted GMRES(restart) with modified Gram-Schmidt Arnoldi and Givens rotations."""
+          confirm: bool = True, dinv=None):
+    """Restarted GMRES(restart) with modified Gram-Schmidt Arnoldi and Givens rotations
+    (right-preconditioned with diag(dinv): Arnoldi on A diag(dinv))."""
     st = _identity if store is None else store
+    pre = (lambda v: v) if dinv is None else (lambda v: st(dinv) * v)
     b = np.asarray(b, dtype=np.float64)
     x = st(np.array(x0, dtype=np.float64, copy=True))
     n = b.shape[0]
@@ -126,7 +149,7 @@ def gmres(A, b, x0, tol: float, restart: int = 30, maxit: int = 100000, store=No
         g[0] = beta
         jend = 0
         for j in range(m):
-            w = st(A @ V[:, j])
+            w = st(A @ pre(V[:, j]))
             for l in range(j + 1):
                 H[l, j] = float(np.dot(V[:, l], w))
                 w -= H[l, j] * V[:, l]
@@ -149,7 +172,7 @@ def gmres(A, b, x0, tol: float, restart: int = 30, maxit: int = 100000, store=No
         y = np.zeros(jend)
         for i in range(jend - 1, -1, -1):
             y[i] = (g[i] - np.dot(H[i, i + 1:jend], y[i + 1:jend])) / H[i, i]
-        x = st(x + V[:, :jend] @ y)
+        x = st(x + pre(V[:, :jend] @ y))
         r = st(b - A @ x)
         beta = _norm(r)
         cycles += 1

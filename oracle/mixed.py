@@ -36,9 +36,10 @@ def inner_cap(solver: str, restart: int, inner_maxit: int = 0) -> int:
 
 def solve_ir(A32, b, x0, tol: float, solver: str = "cg", restart: int = 30,
              inner_tol: float = 1e-4, max_refine: int = 10, maxit: int = 100000,
-             inner_maxit: int = 0):
+             inner_maxit: int = 0, precond: str = "none"):
     b = np.asarray(b, dtype=np.float64)
     x = np.array(x0, dtype=np.float64, copy=True)
+    dinv = kr.jacobi_dinv(A32) if precond == "jacobi" else None
     bnorm = float(np.linalg.norm(b))
     if bnorm == 0.0:
         return np.zeros_like(b), dict(iters=0, restarts=0, refinements=0, relres=0.0, relres0=0.0,
@@ -64,10 +65,10 @@ def solve_ir(A32, b, x0, tol: float, solver: str = "cg", restart: int = 30,
         r32 = fl32(r)
         cap = min(maxit - iters, inner_cap(solver, restart, inner_maxit))
         if solver == "cg":
-            d, info = kr.cg(A32, r32, np.zeros_like(b), inner_tol, cap, store=fl32, confirm=False)
+            d, info = kr.cg(A32, r32, np.zeros_like(b), inner_tol, cap, store=fl32, confirm=False, dinv=dinv)
         else:
             d, info = kr.gmres(A32, r32, np.zeros_like(b), inner_tol, restart, cap, store=fl32,
-                               confirm=False)
+                               confirm=False, dinv=dinv)
         iters += info["iters"]
         restarts += info["restarts"]
         if info["status"] == kr.BREAKDOWN:

@@ -34,7 +34,7 @@ class Sequence:
                  maxit: int = 200000, projection: str = "galerkin", tau_s: float = 1e-12,
                  tau_c: float = 1e-12, m: int | None = None, guess: str = "projection",
                  precision: str = "fp64", inner_tol: float = 1e-4, max_refine: int = 10,
-                 refresh: int = 50):
+                 refresh: int = 50, basis: str = "sketched_qr", precond: str = "none"):
         self.n, self.M = n, M
         self.m = M if m is None else m
         self.s = 2 * M if s is None else s
@@ -51,7 +51,13 @@ class Sequence:
         # m < M: the range finder's Z follows Alg. 3 (each column keeps the Gaussian row it
         # was given, a new Z every `refresh` pushes); Omega = X Z is never formed (its span
         # is folded into the small factor of the sketched QR)
-        self.zrows = bs.RangeFinderRows(M, refresh) if self.m < self.M else None
+        if basis not in ("sketched_qr", "pod"):
+            raise ValueError(basis)
+        self.basis = basis   # "pod": Alg. 2's basis (m leading left singular vectors of X)
+        if precond not in ("none", "jacobi"):
+            raise ValueError(precond)
+        self.precond = precond
+        self.zrows = bs.RangeFinderRows(M, refresh) if (self.m < self.M and basis == "sketched_qr") else None
 
     # ------------------------------------------------------------------ history
     def push(self, x: np.ndarray):
@@ -86,16 +92,18 @@ class Sequence:
         if self.zrows is not None:
             Z = bs.range_finder_rows(self.zrows.rows, self.m, self.seed, self.zrows.epoch)
         return bs.initial_guess(A, b, X, SX, Z, self.projection, self.solver == "cg",
-                                self.tau_s, self.tau_c, self.store)
+                                self.tau_s, self.tau_c, self.store,
+                                pod_m=self.m if self.basis == "pod" else None)
 
     def solve(self, A, b, x0):
         """Krylov solve from x0; in the mixed mode A must carry float32 values."""
         if self.precision != "fp64":
             return mx.solve_ir(A, b, x0, self.tol, self.solver, self.restart, self.inner_tol,
-                               self.max_refine, self.maxit)
+                               self.max_refine, self.maxit, precond=self.precond)
+        dinv = kr.jacobi_dinv(A) if self.precond == "jacobi" else None
         if self.solver == "cg":
-            return kr.cg(A, b, x0, self.tol, self.maxit)
-        return kr.gmres(A, b, x0, self.tol, self.restart, self.maxit)
+            return kr.cg(A, b, x0, self.tol, self.maxit, dinv=dinv)
+        return kr.gmres(A, b, x0, self.tol, self.restart, self.maxit, dinv=dinv)
 
     def step(self, A, b):
         t0 = time.perf_counter()

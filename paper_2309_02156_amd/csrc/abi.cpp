@@ -84,6 +84,7 @@ struct sa_seq {
 namespace {
 
 constexpr size_t ALIGN = 256;
+constexpr double kPodTau = 1e-14;  // POD: eigenvalues of X^T X kept above this times the largest
 inline size_t up(size_t v) { return (v + ALIGN - 1) / ALIGN * ALIGN; }
 
 // Host Philox4x64-10 (Salmon et al., SC'11): used for the SRHT row sample only.
@@ -147,8 +148,16 @@ int validate(const sa_config *c) {
   if (c->guess < SA_GUESS_PROJECTION || c->guess > SA_GUESS_PREVIOUS) return SA_EINVAL;
   if (c->m < 0 || c->m > c->M) return SA_EINVAL;
   if (c->m > 0 && c->m < c->M && (int64_t)c->s * (c->M + 2 * c->m) + (int64_t)c->m * c->m > 12288) return SA_EINVAL;
-  if (c->basis != SA_BASIS_SKETCHED_QR) return SA_EINVAL;
+  if (c->basis != SA_BASIS_SKETCHED_QR && c->basis != SA_BASIS_POD) return SA_EINVAL;
+  if (c->precond != SA_PRECOND_NONE && c->precond != SA_PRECOND_JACOBI) return SA_EINVAL;
   return SA_OK;
+}
+
+// columns of ld rows in the Krylov block: GMRES V (restart + 1 columns) and a scratch
+// column, CG r, two p and q; then D^-1 with the Jacobi preconditioner
+size_t krylov_columns(const sa_config *c) {
+  const size_t kv = c->solver == SA_GMRES ? (size_t)(c->restart + 2) : 4;
+  return kv + (c->precond == SA_PRECOND_JACOBI ? 1 : 0);
 }
 
 Layout layout(const sa_config *c) {
@@ -166,9 +175,7 @@ Layout layout(const sa_config *c) {
   L.Q1 = off;
   off += up(ld * M * wx);
   L.kry = off;
-  // GMRES: V (restart + 1 columns) and a scratch column; CG: r, two p, q
-  const size_t kv = c->solver == SA_GMRES ? (size_t)(c->restart + 2) : 4;
-  off += up(ld * kv * wk);
+  off += up(ld * krylov_columns(c) * wk);
   L.partials = off;
   off += up(partials_doubles(c->n, c->M, c->s) * sizeof(double));
   L.rows = off;
@@ -402,7 +409,7 @@ int progress_wait(sa_seq *q, Ctl *ctl, const Progress &pg, int target, int cycle
 
 // CG to the tolerance (or maxit); final state words in q->hbuf[0..7].
 template <typename TV>
-int run_cg(sa_seq *q, const CsrView &v, Ctl *ctl, const TV *b, TV *x, int maxit, hipStream_t st) {
+int run_cg(sa_seq *q, const CsrView &v, Ctl *ctl, const TV *b, TV *x, int maxit, hipStream_t st, const TV *dinv) {
   const sa_config &c = q->cfg;
   int *hs = q->hbuf;
   TV *r = (TV *)q->kry, *p2 = r + q->ld, *qq = r + 3 * q->ld;
@@ -414,7 +421,7 @@ int run_cg(sa_seq *q, const CsrView &v, Ctl *ctl, const TV *b, TV *x, int maxit,
   Progress pg = progress_of(q, ctl);
   pg.reset();
   const int ahead = c.poll > MIR_EVERY ? c.poll : MIR_EVERY;  // progress arrives every MIR_EVERY steps
-  HIP_TRY(launch_cg_start_k<TV>(v, b, x, r, 0, q->partials, ctl, st, pg.next()));
+  HIP_TRY(launch_cg_start_k<TV>(v, b, x, r, 0, q->partials, ctl, st, pg.next(), dinv));
   // every launched iteration is productive, or a no-op while a check or the end of the
   // solve is on its way to the host (at most `poll` of them each time)
   const long long cap = 2LL * maxit + 64LL * c.poll + 1024;
@@ -427,19 +434,19 @@ int run_cg(sa_seq *q, const CsrView &v, Ctl *ctl, const TV *b, TV *x, int maxit,
     if (fl & MIR_CHECK) {
       // the recursive residual met the tolerance: confirm with the true residual and
       // wait for the decision
-      HIP_TRY(launch_cg_start_k<TV>(v, b, x, r, 1, q->partials, ctl, st, pg.next()));
+      HIP_TRY(launch_cg_start_k<TV>(v, b, x, r, 1, q->partials, ctl, st, pg.next(), dinv));
       SA_TRY(progress_wait(q, ctl, pg, pg.serial, INT_MAX, MIR_STOPPED, st, &seen, &fl));
       if (fl & MIR_STOPPED) break;
       continue;
     }
     KTiming tm;
     // gathers r and p, writes p and q
-    const KTiming *tp = prof_slot(q, pname, csr + 4.0 * w * v.n, &tm);
-    HIP_TRY(launch_cg_iter<TV>(v, x, r, p2, qq, q->partials, ctl, st, tp, pg.next()));
+    const KTiming *tp = prof_slot(q, pname, csr + (dinv ? 5.0 : 4.0) * w * v.n, &tm);
+    HIP_TRY(launch_cg_iter<TV>(v, x, r, p2, qq, q->partials, ctl, st, tp, pg.next(), dinv));
   }
   SA_TRY(poll(q, ctl, st));
   if (hs[0] == ST_MAXIT || hs[0] == ST_BREAK) {
-    HIP_TRY(launch_cg_start_k<TV>(v, b, x, r, 2, q->partials, ctl, st));
+    HIP_TRY(launch_cg_start_k<TV>(v, b, x, r, 2, q->partials, ctl, st, 0, dinv));
     SA_TRY(poll(q, ctl, st));
   }
   return prof_end(q, ctl, st);
@@ -447,7 +454,7 @@ int run_cg(sa_seq *q, const CsrView &v, Ctl *ctl, const TV *b, TV *x, int maxit,
 
 // GMRES(m) to the tolerance (or maxit); final state words in q->hbuf[0..7].
 template <typename TV>
-int run_gmres(sa_seq *q, const CsrView &v, Ctl *ctl, const TV *b, TV *x, int maxit, hipStream_t st,
+int run_gmres(sa_seq *q, const CsrView &v, Ctl *ctl, const TV *b, TV *x, int maxit, hipStream_t st, const TV *dinv,
               bool defer = false) {
   const sa_config &c = q->cfg;
   TV *V = (TV *)q->kry;
@@ -489,7 +496,7 @@ int run_gmres(sa_seq *q, const CsrView &v, Ctl *ctl, const TV *b, TV *x, int max
       if (q->prof.on) {
         // SpMV of the source column, columns 0..j-1, the finalised column and y
         const int rb = j <= 8 ? 8 : (j <= 16 ? 16 : 32);
-        const double bytes = csr + (j == 0 ? 2.0 : (double)(j + 3)) * w * v.n;
+        const double bytes = csr + ((j == 0 ? 2.0 : (double)(j + 3)) + (dinv ? 1.0 : 0.0)) * w * v.n;
         const std::string name = std::string("k_gm_f<") + tname(wv) + ", " + tname(w) + ", " + std::to_string(rb) +
                                  ", " + std::to_string(gm_f_rows_per_thread(v.n, rb)) + ">";
         tp = prof_slot(q, name, bytes, &tm);
@@ -497,13 +504,13 @@ int run_gmres(sa_seq *q, const CsrView &v, Ctl *ctl, const TV *b, TV *x, int max
       // (the restart's first step reports in any case when the host will wait for it)
       const int serial = pg.next() | ((est_end && j == 0) ? MIR_REPORT : 0);
       HIP_TRY(launch_gm_step<TV>(v, V, T, q->ld, j, cycle > 0 ? 1 : 0, q->partials, ctl, st, tp, serial,
-                                 from_g && j + 1 == c.restart));
+                                 from_g && j + 1 == c.restart, dinv));
     }
     if (stop) break;
     // a full cycle: the update closes step m - 1 itself, from G(m - 1)'s partial rows
     // (||w''_m|| from ||w'_m|| and the second-pass coefficients) or after a finalise F(m)
     if (!cut && !from_g) HIP_TRY(launch_gm_finish<TV>(v, V, T, q->ld, c.restart, q->partials, ctl, st, false));
-    HIP_TRY(launch_gm_update<TV>(x, V, v.n, q->ld, c.restart, ctl, st, q->partials, !cut, from_g));
+    HIP_TRY(launch_gm_update<TV>(x, V, v.n, q->ld, c.restart, ctl, st, q->partials, !cut, from_g, dinv));
     HIP_TRY(launch_gm_start<TV>(v, b, x, V, 1, q->partials, ctl, st));
   }
   // defer: only enqueue the final read of the state (poll_wait reads it); the GMRES
@@ -513,9 +520,24 @@ int run_gmres(sa_seq *q, const CsrView &v, Ctl *ctl, const TV *b, TV *x, int max
   return prof_end(q, ctl, st);
 }
 
+// Jacobi preconditioner of the operator of a solve: D^-1 in the last Krylov column
+// (null without a preconditioner)
+template <typename TV>
+int jacobi_setup(sa_seq *q, const CsrView &v, hipStream_t st, const TV **dinv) {
+  *dinv = nullptr;
+  if (q->cfg.precond != SA_PRECOND_JACOBI) return SA_OK;
+  TV *d = (TV *)q->kry + (krylov_columns(&q->cfg) - 1) * (size_t)q->ld;
+  HIP_TRY(launch_jacobi_dinv<TV>(v, d, st));
+  *dinv = d;
+  return SA_OK;
+}
+
 template <typename TV>
 int run_krylov(sa_seq *q, const CsrView &v, Ctl *ctl, const TV *b, TV *x, int maxit, hipStream_t st) {
-  return q->cfg.solver == SA_CG ? run_cg<TV>(q, v, ctl, b, x, maxit, st) : run_gmres<TV>(q, v, ctl, b, x, maxit, st);
+  const TV *dinv;
+  SA_TRY(jacobi_setup<TV>(q, v, st, &dinv));
+  return q->cfg.solver == SA_CG ? run_cg<TV>(q, v, ctl, b, x, maxit, st, dinv)
+                                : run_gmres<TV>(q, v, ctl, b, x, maxit, st, dinv);
 }
 
 // read (bnorm, relres0, relres) of a control block
@@ -531,15 +553,28 @@ int status_of(int state) {
   return SA_OK;
 }
 
+// The basis Q1 = X T1 of the current history: T1 from the sketched QR of the last push,
+// or for POD (Alg. 2) from the eigen-decomposition of X^T X formed here.
+template <typename TX>
+int basis_enqueue(sa_seq *q, int cnt, hipStream_t st) {
+  const sa_config &c = q->cfg;
+  if (c.basis == SA_BASIS_POD) {
+    int nb = 0;
+    HIP_TRY(launch_gram_x<TX>((const TX *)q->X, c.n, q->ld, cnt, q->partials, &nb, st));
+    HIP_TRY(launch_colsum(q->partials, nb, cnt * cnt, q->ctl, st));
+    HIP_TRY(launch_pod_eig(cnt, c.m > 0 ? c.m : c.M, kPodTau, q->ctl, st));
+  }
+  HIP_TRY(launch_basis<TX>((const TX *)q->X, (TX *)q->Q1, c.n, q->ld, cnt, q->ctl, st));
+  q->basis_for = q->pushes;
+  return SA_OK;
+}
+
 // Alg. 1 (basis and reduced problem) on the device: Q1 = X T1, SpMM + Gram, reduced solve, x0 = Q1 c.
 template <typename TX>
 int guess_projection(sa_seq *q, const CsrView &v, const double *b, double *x0, int cnt, hipStream_t st) {
   const sa_config &c = q->cfg;
   int nblk = 0;
-  if (q->basis_for != q->pushes) {
-    HIP_TRY(launch_basis<TX>((const TX *)q->X, (TX *)q->Q1, c.n, q->ld, cnt, q->ctl, st));
-    q->basis_for = q->pushes;
-  }
+  if (q->basis_for != q->pushes) SA_TRY(basis_enqueue<TX>(q, cnt, st));
   const int mr = c.projection == SA_MINRES ? 1 : 0;
   HIP_TRY(launch_spmm_gram<TX>(v, (const TX *)q->Q1, q->ld, b, cnt, mr, q->partials, &nblk, q->ctl, st));
   HIP_TRY(launch_colsum(q->partials, nblk, gram_width(cnt, mr), q->ctl, st));
@@ -650,7 +685,7 @@ ZRows zrows_push(sa_seq *q) {
   const sa_config &c = q->cfg;
   ZRows z;
   memset(&z, 0, sizeof(z));
-  if (!(c.m > 0 && c.m < c.M)) return z;
+  if (!(c.m > 0 && c.m < c.M) || c.basis != SA_BASIS_SKETCHED_QR) return z;
   const int cnt = count(q);
   const int refresh = c.refresh > 0 ? c.refresh : 50;
   auto scratch = [&](int k) {
@@ -757,12 +792,7 @@ int guess_enqueue(sa_seq *q, const sa_csr *A, const void *b_dev, void *x0_dev, b
 int basis_ahead(sa_seq *q, hipStream_t st) {
   const int cnt = count(q);
   if (cnt == 0 || q->cfg.guess != SA_GUESS_PROJECTION) return SA_OK;
-  if (q->x32)
-    HIP_TRY(launch_basis<float>((const float *)q->X, (float *)q->Q1, q->cfg.n, q->ld, cnt, q->ctl, st));
-  else
-    HIP_TRY(launch_basis<double>((const double *)q->X, (double *)q->Q1, q->cfg.n, q->ld, cnt, q->ctl, st));
-  q->basis_for = q->pushes;
-  return SA_OK;
+  return q->x32 ? basis_enqueue<float>(q, cnt, st) : basis_enqueue<double>(q, cnt, st);
 }
 
 // the guess fields of info, after the stream has synchronized past guess_enqueue
@@ -912,7 +942,9 @@ int sa_step(sa_seq *q, const sa_csr *A, const void *b_dev, void *x_dev, sa_info 
   // zeroed below, after the push in stream order.)
   if (info) HIP_TRY(hipEventRecord(q->ev[2], st));
   q->snap_ctl = nullptr;
-  SA_TRY(run_gmres<double>(q, view(A), q->ctl, (const double *)b_dev, (double *)x_dev, c.maxit, st, true));
+  const double *dinv;
+  SA_TRY(jacobi_setup<double>(q, view(A), st, &dinv));
+  SA_TRY(run_gmres<double>(q, view(A), q->ctl, (const double *)b_dev, (double *)x_dev, c.maxit, st, dinv, true));
   if (info) HIP_TRY(hipEventRecord(q->ev[3], st));
   SA_TRY(push_enqueue(q, x_dev, 1, st));
   SA_TRY(basis_ahead(q, st));
@@ -1350,8 +1382,7 @@ StaticLayout static_layout(const sa_config *c) {
   L.partials = off;
   off += up(krylov_partials_doubles() * sizeof(double));
   L.kry = off;
-  const size_t kv = c->solver == SA_GMRES ? (size_t)(c->restart + 2) : 4;
-  off += up((size_t)padded_ld(c->n) * kv * sizeof(double));
+  off += up((size_t)padded_ld(c->n) * krylov_columns(c) * sizeof(double));
   L.total = off;
   return L;
 }

@@ -585,11 +585,14 @@ __device__ inline double tile_spmv(const int *__restrict__ rowptr, const int *__
 // no block barrier, so the waves of a block (and the several blocks a compute unit
 // holds) overlap each other's memory trips.  Stage: the tile's nonzeros [p0, p1) are
 // read with consecutive lanes on consecutive nonzeros (coalesced), C per lane per round,
-// all issued before the first is used (slots past the tile re-read its last entry and
-// are dropped); then the gathers; the products go to the wave's own LDS slice.  Sum:
-// each lane adds its row's products in column order.  Tiles with more than WT_CAP
-// nonzeros read their rows directly.  `gx(c)` returns the source vector's entry c.
-constexpr int WT_CAP = 512;  // nonzeros of one wave tile staged in LDS (4 KB)
+// and the column indices and values go to the wave's own LDS slices.  Gather: each lane
+// then walks its own row, C entries at a time, all gathers of a step issued together,
+// so that lane l's k-th gather sits next to lane l+1's whenever neighbouring rows have
+// neighbouring columns (a stencil): a gather instruction then touches two or three
+// cache lines instead of one per row it crosses.  Each lane adds its row's products in
+// column order.  Tiles with more than WT_CAP nonzeros read their rows directly.
+// `gx(c)` returns the source vector's entry c (double, or the vector's own type).
+constexpr int WT_CAP = 512;  // nonzeros of one wave tile staged in LDS
 constexpr int NXCD = 8;      // accelerator complex dies (each with its own L2) of the MI355X
 
 __device__ inline void wave_lds_sync() {
@@ -598,67 +601,27 @@ __device__ inline void wave_lds_sync() {
   __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
-// (A x)_{r0 + lane} for the wave's tile (0 for rows >= n); prod: the wave's LDS slice
-// of WT_CAP doubles.  Every lane of the wave must call it with the same r0 < n.
-template <int C, typename VT, typename G>
-__device__ inline double wave_tile_spmv(const int *__restrict__ rowptr, const int *__restrict__ col,
-                                        const VT *__restrict__ val, const G &gx, int64_t n, int64_t r0,
-                                        double *prod) {
-  const int lane = threadIdx.x % WAVE;
-  const int64_t i = r0 + lane;
-  const int last = (int)((n - r0 < WAVE ? n - r0 : WAVE) - 1);  // last lane with a row
-  const int64_t ic = i < n ? i : n - 1;
-  const int a = rowptr[ic], b = rowptr[ic + 1];
-  const int p0 = __builtin_amdgcn_readfirstlane(a);
-  const int p1 = __builtin_amdgcn_readlane(b, last);
-  double s = 0.0;
-  if (p1 - p0 <= WT_CAP) {
-    for (int base = p0; base < p1; base += C * WAVE) {
-      int cc[C];
-      double vv[C], xx[C];
-#pragma unroll
-      for (int u = 0; u < C; ++u) {
-        const int p = base + u * WAVE + lane;
-        const int pc = p < p1 ? p : p1 - 1;
-        cc[u] = col[pc];
-        vv[u] = (double)val[pc];
-      }
-#pragma unroll
-      for (int u = 0; u < C; ++u) xx[u] = gx(cc[u]);
-#pragma unroll
-      for (int u = 0; u < C; ++u) {
-        const int p = base + u * WAVE + lane;
-        if (p < p1) prod[p - p0] = vv[u] * xx[u];
-      }
-    }
-    wave_lds_sync();
-    if (i < n)
-      for (int p = a; p < b; ++p) s += prod[p - p0];
-    wave_lds_sync();  // the slice is rewritten by the wave's next tile
-  } else if (i < n) {
-    for (int p = a; p < b; ++p) s += (double)val[p] * gx(col[p]);
-  }
-  return i < n ? s : 0.0;
-}
-
-// A wave's loop over its tiles with the index loads of the next tile in flight while
-// the current tile's gathers are outstanding: per tile the row pointers of the next tile
-// go out first, then this tile's gathers and `pre` (a load of the row's own entries),
-// then the next tile's first round of columns / values (its row pointers have arrived by
-// then); the products of this tile go to LDS and `epi(i, pre value, (A x)_i)` runs for
-// every row i < n of the tile.  The loads of the last tile's successor re-read the last
-// tile (no branch around loads).  Tiles past WT_CAP nonzeros read their rows directly;
-// rounds after the first of a long tile load inline.  Same sums, in the same order, as
-// wave_tile_spmv.
+// A wave's loop over its tiles t, t + step, ... < end.  Per tile: the next tile's row
+// pointers go out first; this tile's first round of columns / values (requested while
+// the previous tile was summed) goes to LDS, later rounds of a long tile load inline;
+// then the next tile's first round is requested, then this tile's gathers and `pre`
+// (a load of the row's own entries), so the next tile's index stream overlaps this
+// tile's gathers.  `epi(i, pre value, (A x)_i)` runs for every row i < n.  Loads are
+// unconditional (a load under a branch makes the compiler count the memory queue as if
+// it had not gone out, so its later waits drain the queue): slots past a tile re-read
+// its last entry, a tile with no nonzero up to it re-reads entry 0, so col and val must
+// hold at least one entry even for a matrix without nonzeros (callers pass stand-ins),
+// and the loads of the last tile's successor re-read the last tile.  lcol / lval: the
+// wave's LDS slices of WT_CAP entries.
 template <int C, typename VT, typename G, typename PRE, typename EPI>
-__device__ inline void wave_tiles_spmv_pipelined(const int *__restrict__ rowptr, const int *__restrict__ col,
-                                                 const VT *__restrict__ val, const G &gx, int64_t n, int64_t t,
-                                                 int64_t end, int64_t step, double *prod, const PRE &pre,
-                                                 const EPI &epi) {
+__device__ inline void wave_tiles_spmv(const int *__restrict__ rowptr, const int *__restrict__ col,
+                                       const VT *__restrict__ val, const G &gx, int64_t n, int64_t t, int64_t end,
+                                       int64_t step, int *lcol, VT *lval, const PRE &pre, const EPI &epi) {
+  using XT = decltype(gx(0));
   const int lane = threadIdx.x % WAVE;
   if (t >= end) return;
   int a, b, p0, p1, cc[C];
-  double vv[C];
+  VT vv[C];
   auto load_rows = [&](int64_t tt, int &ra, int &rb) {
     const int64_t i = tt * WAVE + lane;
     const int64_t ic = i < n ? i : n - 1;
@@ -671,20 +634,22 @@ __device__ inline void wave_tiles_spmv_pipelined(const int *__restrict__ rowptr,
     q0 = __builtin_amdgcn_readfirstlane(ra);
     q1 = __builtin_amdgcn_readlane(rb, last);
   };
-  // (q1 == 0: no nonzero up to this tile, possibly none at all: nothing is read)
-  auto load_round = [&](int base, int q1, int (&c)[C], double (&v)[C]) {
+  auto load_round = [&](int base, int q1, int (&c)[C], VT (&v)[C]) {
 #pragma unroll
     for (int u = 0; u < C; ++u) {
-      c[u] = 0;
-      v[u] = 0.0;
+      const int pp = base + u * WAVE + lane;
+      const int pc = pp < q1 ? pp : (q1 > 0 ? q1 - 1 : 0);
+      c[u] = col[(unsigned)pc];
+      v[u] = val[(unsigned)pc];
     }
-    if (q1 > 0) {
+  };
+  auto stage = [&](int base, int q0, int q1, const int (&c)[C], const VT (&v)[C]) {
 #pragma unroll
-      for (int u = 0; u < C; ++u) {
-        const int pp = base + u * WAVE + lane;
-        const int pc = pp < q1 ? pp : q1 - 1;
-        c[u] = col[pc];
-        v[u] = (double)val[pc];
+    for (int u = 0; u < C; ++u) {
+      const int pp = base + u * WAVE + lane;
+      if (pp < q1) {
+        lcol[pp - q0] = c[u];
+        lval[pp - q0] = v[u];
       }
     }
   };
@@ -692,44 +657,53 @@ __device__ inline void wave_tiles_spmv_pipelined(const int *__restrict__ rowptr,
   tile_range(t, a, b, p0, p1);
   load_round(p0, p1, cc, vv);
   for (;;) {
-    const int64_t r0 = t * WAVE, i = r0 + lane;
+    const int64_t i = t * WAVE + lane;
+    const int64_t ic = i < n ? i : n - 1;
     const int64_t tn = t + step;
     const bool more = tn < end;
     int an, bn;
     load_rows(more ? tn : t, an, bn);
-    double xx[C];
-#pragma unroll
-    for (int u = 0; u < C; ++u) xx[u] = gx(cc[u]);
-    const double own = pre(i < n ? i : n - 1);
-    int p0n, p1n, ccn[C];
-    double vvn[C];
-    tile_range(more ? tn : t, an, bn, p0n, p1n);
-    load_round(p0n, p1n, ccn, vvn);
-    double s = 0.0;
-    if (p1 - p0 <= WT_CAP) {
-#pragma unroll
-      for (int u = 0; u < C; ++u) {
-        const int pp = p0 + u * WAVE + lane;
-        if (pp < p1) prod[pp - p0] = vv[u] * xx[u];
-      }
+    // the row pointers go out ahead of this tile's remaining loads
+    __builtin_amdgcn_sched_barrier(0);
+    const bool staged = p1 - p0 <= WT_CAP;
+    if (staged) {
+      stage(p0, p0, p1, cc, vv);
       for (int base = p0 + C * WAVE; base < p1; base += C * WAVE) {
         int c2[C];
-        double v2[C], x2[C];
+        VT v2[C];
         load_round(base, p1, c2, v2);
-#pragma unroll
-        for (int u = 0; u < C; ++u) x2[u] = gx(c2[u]);
-#pragma unroll
-        for (int u = 0; u < C; ++u) {
-          const int pp = base + u * WAVE + lane;
-          if (pp < p1) prod[pp - p0] = v2[u] * x2[u];
-        }
+        stage(base, p0, p1, c2, v2);
       }
       wave_lds_sync();
-      if (i < n)
-        for (int pp = a; pp < b; ++pp) s += prod[pp - p0];
-      wave_lds_sync();  // the slice is rewritten by the wave's next tile
-    } else if (i < n) {
-      for (int pp = a; pp < b; ++pp) s += (double)val[pp] * gx(col[pp]);
+    }
+    int p0n, p1n;
+    tile_range(more ? tn : t, an, bn, p0n, p1n);
+    load_round(p0n, p1n, cc, vv);
+    const int len = i < n ? b - a : 0;
+    const int off = a - p0;
+    const double own = pre(ic);
+    double s = 0.0;
+    if (staged) {
+      for (int k0 = 0; __any(k0 < len); k0 += C) {
+        int c[C];
+        VT v[C];
+        XT x[C];
+#pragma unroll
+        for (int u = 0; u < C; ++u) {
+          const int k = k0 + u;
+          const int idx = k < len ? off + k : 0;
+          c[u] = k < len ? lcol[idx] : (int)ic;
+          v[u] = lval[idx];
+        }
+#pragma unroll
+        for (int u = 0; u < C; ++u) x[u] = gx(c[u]);
+#pragma unroll
+        for (int u = 0; u < C; ++u)
+          if (k0 + u < len) s += (double)v[u] * (double)x[u];
+      }
+      wave_lds_sync();  // the slices are rewritten by the wave's next tile
+    } else {
+      for (int pp = a; pp < a + len; ++pp) s += (double)val[pp] * (double)gx(col[pp]);
     }
     if (i < n) epi(i, own, s);
     if (!more) break;
@@ -738,11 +712,6 @@ __device__ inline void wave_tiles_spmv_pipelined(const int *__restrict__ rowptr,
     b = bn;
     p0 = p0n;
     p1 = p1n;
-#pragma unroll
-    for (int u = 0; u < C; ++u) {
-      cc[u] = ccn[u];
-      vv[u] = vvn[u];
-    }
   }
 }
 

@@ -59,6 +59,14 @@ hipError_t launch_spmm_gram(const CsrView &A, const TX *Q1, int64_t ld, const do
 // entries of one partial row of launch_spmm_gram (Galerkin block, then the minimum-residual one)
 int gram_width(int cnt, int minres);
 
+// POD (Alg. 2): partial rows of G = X^T X (cnt x cnt), then, after k_colsum, the
+// eigen-decomposition of G and T1 = V_k diag(lam_k)^(-1/2) for the k <= m leading
+// eigenvalues above tau lam_1 (in ctl)
+template <typename TX>
+hipError_t launch_gram_x(const TX *X, int64_t n, int64_t ld, int cnt, double *partials, int *nblk_out,
+                         hipStream_t st);
+hipError_t launch_pod_eig(int cnt, int m, double tau, Ctl *ctl, hipStream_t st);
+
 // column sums of partials[nblk][W] -> ctl->gram
 hipError_t launch_colsum(const double *partials, int nblk, int W, Ctl *ctl, hipStream_t st);
 
@@ -95,12 +103,17 @@ struct KTiming {
 // p2 holds the two alternating direction vectors (p2 and p2 + padded_ld(n)).
 template <typename TV>
 hipError_t launch_cg_start_k(const CsrView &A, const TV *b, const TV *x, TV *r, int mode, double *partials,
-                             Ctl *ctl, hipStream_t st, int serial = 0);
+                             Ctl *ctl, hipStream_t st, int serial = 0, const TV *dinv = nullptr);
 // tm (may be null) times the direction/SpMV kernel of the iteration.  serial > 0: the
-// step's kernel reports serial and what it saw in the control block's progress word
+// step's kernel reports serial and what it saw in the control block's progress word.
+// dinv (may be null): Jacobi preconditioning, z = dinv * r (the start kernel then also
+// forms r^T z); the stopping test stays on ||r||.
 template <typename TV>
 hipError_t launch_cg_iter(const CsrView &A, TV *x, TV *r, TV *p2, TV *q, double *partials, Ctl *ctl,
-                          hipStream_t st, const KTiming *tm = nullptr, int serial = 0);
+                          hipStream_t st, const KTiming *tm = nullptr, int serial = 0, const TV *dinv = nullptr);
+// dinv[i] = 1 / (sum of row i's entries in column i), 1 where that sum is zero
+template <typename TV>
+hipError_t launch_jacobi_dinv(const CsrView &A, TV *dinv, hipStream_t st);
 
 // GMRES(m), classical Gram-Schmidt applied twice.  A cycle: start (residual into
 // V[:, 0]), steps j = 0..m-1 (first_mode 0 for the first cycle of a solve, 1 for a
@@ -108,21 +121,24 @@ hipError_t launch_cg_iter(const CsrView &A, TV *x, TV *r, TV *p2, TV *q, double 
 template <typename TV>
 hipError_t launch_gm_start(const CsrView &A, const TV *b, const TV *x, TV *V, int restart_mode, double *partials,
                            Ctl *ctl, hipStream_t st);
-// tm (may be null) times the step's first kernel (SpMV, finalisation, first dots)
+// tm (may be null) times the step's first kernel (SpMV, finalisation, first dots).
+// dinv (may be null): right preconditioning, the step's product is A (dinv * v_j)
 template <typename TV>
 hipError_t launch_gm_step(const CsrView &A, TV *V, TV *T, int64_t ld, int j, int first_mode, double *partials,
                           Ctl *ctl, hipStream_t st, const KTiming *tm = nullptr, int serial = 0,
-                          bool norm_w = false);
+                          bool norm_w = false, const TV *dinv = nullptr);
 // end of a full cycle: F(m) finalise-only, and with close the one-block close of step m - 1
 template <typename TV>
 hipError_t launch_gm_finish(const CsrView &A, TV *V, TV *T, int64_t ld, int m, double *partials, Ctl *ctl,
                             hipStream_t st, bool close = true);
 // x += V y at the end of a cycle; close_last: close step m - 1 first (in every block,
 // instead of the finish's one-block close) from F(m)'s partial rows, or with from_g from
-// G(m - 1)'s (no F(m) needed; only when gm_norm_in_g(m))
+// G(m - 1)'s (no F(m) needed; only when gm_norm_in_g(m)).  dinv (may be null): right
+// preconditioning, x += dinv * (V y)
 template <typename TV>
 hipError_t launch_gm_update(TV *x, const TV *V, int64_t n, int64_t ld, int restart, Ctl *ctl, hipStream_t st,
-                            double *partials = nullptr, bool close_last = false, bool from_g = false);
+                            double *partials = nullptr, bool close_last = false, bool from_g = false,
+                            const TV *dinv = nullptr);
 bool gm_norm_in_g(int m);
 size_t krylov_partials_doubles();
 // row tiles per pass of the GMRES kernel F (1 or 2) for n rows and rb column slots

@@ -721,6 +721,242 @@ hipError_t launch_spmm_gram(const CsrView &A, const TX *Q1, int64_t ld, const do
 
 int gram_width(int cnt, int minres) { return cnt * (2 * cnt + 1) + (minres ? cnt * (cnt + 1) : 0); }
 
+// ============================================================================ POD (Alg. 2)
+// The POD basis is formed from the Gram matrix of the history: G = X^T X (this kernel,
+// partial rows reduced by k_colsum), G = V diag(lam) V^T by cyclic Jacobi rotations on one
+// workgroup (k_pod_eig), T1 = V_k diag(lam_k)^(-1/2) for the k leading eigenvalues, so
+// Q1 = X T1 holds the k leading left singular vectors of X.
+//
+// Gram: a wave owns tiles of 16 rows; v_mfma_f64_16x16x4f64 accumulates the blocks on and
+// above the diagonal over the tile's four row quads, the operands read straight from X
+// (A[i][kq] from lane i + 16 kq, B[kq][j] from lane j + 16 kq); the waves' blocks are added
+// in wave order and the block writes its partial row P[a + c cnt], a, c < cnt.
+template <int KB, typename TX>
+__global__ __launch_bounds__(GRAM_TPB) void k_gram_x(const TX *X, int64_t n, int64_t ld, int cnt,
+                                                     double *partials) {
+  constexpr int NA = KB / 16, NG = NA * (NA + 1) / 2;
+  __shared__ double comb[NG * 256];
+  const int lane = threadIdx.x % WAVE, wid = threadIdx.x / WAVE;
+  const int i16 = lane % 16, kq = lane / 16;
+  const int na = (cnt + 15) / 16;
+  d4 acc[NG];
+#pragma unroll
+  for (int e = 0; e < NG; ++e) acc[e] = (d4){0.0, 0.0, 0.0, 0.0};
+  const int64_t T = (n + GRAM_ROWS - 1) / GRAM_ROWS;
+  const int groups = gridDim.x >= NXCD ? NXCD : 1;
+  const int64_t per = (T + groups - 1) / groups;
+  const int64_t tlo = (int64_t)(blockIdx.x % groups) * per;
+  const int64_t thi = tlo + per < T ? tlo + per : T;
+  const int64_t tstep = (int64_t)(gridDim.x / groups) * GRAM_NW;
+  for (int64_t t = tlo + (int64_t)(blockIdx.x / groups) * GRAM_NW + wid; t < thi; t += tstep) {
+    double xv[GRAM_ROWS / 4][NA];
+#pragma unroll
+    for (int s4 = 0; s4 < GRAM_ROWS / 4; ++s4) {
+      const int64_t row = t * GRAM_ROWS + 4 * s4 + kq;
+      const int64_t rq = row < n ? row : n - 1;
+#pragma unroll
+      for (int a = 0; a < NA; ++a) {
+        const int c = a * 16 + i16;
+        const double v = (double)X[(size_t)(c < cnt ? c : cnt - 1) * ld + rq];
+        xv[s4][a] = (c < cnt && row < n) ? v : 0.0;
+      }
+    }
+#pragma unroll
+    for (int s4 = 0; s4 < GRAM_ROWS / 4; ++s4)
+#pragma unroll
+      for (int a = 0; a < NA; ++a)
+        if (a < na)
+#pragma unroll
+          for (int bq = a; bq < NA; ++bq)
+            if (bq < na)
+              acc[gram_gidx(a, bq, NA)] =
+                  __builtin_amdgcn_mfma_f64_16x16x4f64(xv[s4][a], xv[s4][bq], acc[gram_gidx(a, bq, NA)], 0, 0, 0);
+  }
+  for (int wv = 0; wv < GRAM_NW; ++wv) {
+    if (wid == wv)
+#pragma unroll
+      for (int e = 0; e < NG; ++e)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+          double *dst = comb + (size_t)e * 256 + (lane / 16 + 4 * v) * 16 + lane % 16;
+          *dst = wv == 0 ? acc[e][v] : *dst + acc[e][v];
+        }
+    __syncthreads();
+  }
+  double *out = partials + (size_t)blockIdx.x * cnt * cnt;
+  for (int e = threadIdx.x; e < cnt * cnt; e += blockDim.x) {
+    const int a = e % cnt, c = e / cnt;
+    const int r = a <= c ? a : c, q = a <= c ? c : a;
+    out[e] = comb[(size_t)gram_gidx(r / 16, q / 16, NA) * 256 + (r % 16) * 16 + q % 16];
+  }
+}
+
+template <int KB, typename TX>
+static int gram_x_launch(const TX *X, int64_t n, int64_t ld, int cnt, double *partials, hipStream_t st) {
+  const int64_t T = (n + GRAM_ROWS - 1) / GRAM_ROWS;
+  int64_t nb = (T + GRAM_NW - 1) / GRAM_NW;
+  if (nb > 512) nb = 512;
+  if (nb >= NXCD) nb = nb / NXCD * NXCD;
+  if (nb < 1) nb = 1;
+  hipLaunchKernelGGL((k_gram_x<KB, TX>), dim3(nb), dim3(GRAM_TPB), 0, st, X, n, ld, cnt, partials);
+  return (int)nb;
+}
+
+template <typename TX>
+hipError_t launch_gram_x(const TX *X, int64_t n, int64_t ld, int cnt, double *partials, int *nblk_out,
+                         hipStream_t st) {
+  *nblk_out = cnt <= 16 ? gram_x_launch<16, TX>(X, n, ld, cnt, partials, st)
+                        : gram_x_launch<32, TX>(X, n, ld, cnt, partials, st);
+  return hipGetLastError();
+}
+
+// One workgroup: eigen-decomposition of the Gram matrix in ctl->gram (cnt x cnt) by cyclic
+// Jacobi rotations, the round-robin ordering giving cnt / 2 disjoint pairs per round (all
+// pairs' rotations from the same matrix, then the rows, then the columns and V); sweeps
+// until the off-diagonal norm is at most 1e-15 of the Frobenius norm, at most 30.  The
+// eigenvalues in descending order (lowest index first among equal ones); k = the leading
+// count with lam_j > tau lam_1, at most m; T1[:, c] = V[:, c] / sqrt(lam_c).
+__global__ __launch_bounds__(TPB) void k_pod_eig(int cnt, int m, double tau, Ctl *ctl) {
+  constexpr int N = MAXM;  // padded order (even)
+  __shared__ double A[N][N + 1], V[N][N + 1];
+  __shared__ double cs[N / 2], sn[N / 2];
+  __shared__ int pp[N / 2], qq[N / 2];
+  __shared__ double lam[N];
+  __shared__ int order[N];
+  __shared__ int s_bad, s_done;
+  __shared__ double s_red[TPB / WAVE];
+  const int tid = threadIdx.x, lane = tid % WAVE, wid = tid / WAVE;
+  const int np = cnt + (cnt & 1);  // even order for the tournament (a zero row and column added)
+  for (int e = tid; e < N * N; e += blockDim.x) {
+    const int a = e % N, b = e / N;
+    double g = 0.0;
+    if (a < cnt && b < cnt) g = 0.5 * (ctl->gram[a + b * cnt] + ctl->gram[b + a * cnt]);
+    A[a][b] = g;
+    V[a][b] = a == b ? 1.0 : 0.0;
+  }
+  if (tid == 0) s_bad = 0;
+  __syncthreads();
+  for (int e = tid; e < cnt * cnt; e += blockDim.x)
+    if (!isfinite(A[e % cnt][e / cnt])) s_bad = 1;
+  __syncthreads();
+  if (s_bad || cnt == 0) {
+    for (int e = tid; e < MAXM * MAXM; e += blockDim.x) ctl->T1[e] = 0.0;
+    if (tid == 0) {
+      ctl->k = 0;
+      ctl->nonfinite = s_bad;
+    }
+    return;
+  }
+  // Frobenius norm (fixed order: each wave sums its rows, waves in order)
+  double fro2 = 0.0;
+  {
+    double part = 0.0;
+    for (int e = tid; e < np * np; e += blockDim.x) part += A[e % np][e / np] * A[e % np][e / np];
+    part = wave_sum(part);
+    if (lane == 0) s_red[wid] = part;
+    __syncthreads();
+    for (int w = 0; w < (int)blockDim.x / WAVE; ++w) fro2 += s_red[w];
+    __syncthreads();
+  }
+  for (int sweep = 0; sweep < 30 && np > 1; ++sweep) {
+    for (int r = 0; r < np - 1; ++r) {
+      if (tid < np / 2) {
+        const int i = tid;
+        int p = i == 0 ? r % (np - 1) : (r + i) % (np - 1);
+        int q = i == 0 ? np - 1 : (r - i + np - 1) % (np - 1);
+        if (p > q) {
+          const int t = p;
+          p = q;
+          q = t;
+        }
+        const double apq = A[p][q];
+        double c = 1.0, sv = 0.0;
+        if (apq != 0.0) {
+          const double th = (A[q][q] - A[p][p]) / (2.0 * apq);
+          const double t = (th >= 0.0 ? 1.0 : -1.0) / (fabs(th) + sqrt(th * th + 1.0));
+          c = 1.0 / sqrt(t * t + 1.0);
+          sv = t * c;
+        }
+        pp[i] = p;
+        qq[i] = q;
+        cs[i] = c;
+        sn[i] = sv;
+      }
+      __syncthreads();
+      // rows p, q of every pair: row_p <- c row_p - s row_q, row_q <- s row_p + c row_q
+      for (int e = tid; e < (np / 2) * np; e += blockDim.x) {
+        const int i = e / np, j = e % np;
+        const int p = pp[i], q = qq[i];
+        const double c = cs[i], sv = sn[i], ap = A[p][j], aq = A[q][j];
+        A[p][j] = c * ap - sv * aq;
+        A[q][j] = sv * ap + c * aq;
+      }
+      __syncthreads();
+      // columns p, q of every pair, and of V
+      for (int e = tid; e < (np / 2) * np; e += blockDim.x) {
+        const int i = e / np, j = e % np;
+        const int p = pp[i], q = qq[i];
+        const double c = cs[i], sv = sn[i];
+        const double ap = A[j][p], aq = A[j][q];
+        A[j][p] = c * ap - sv * aq;
+        A[j][q] = sv * ap + c * aq;
+        const double vp = V[j][p], vq = V[j][q];
+        V[j][p] = c * vp - sv * vq;
+        V[j][q] = sv * vp + c * vq;
+      }
+      __syncthreads();
+    }
+    // off-diagonal norm after the sweep
+    double part = 0.0;
+    for (int e = tid; e < np * np; e += blockDim.x) {
+      const int a = e % np, b = e / np;
+      if (a != b) part += A[a][b] * A[a][b];
+    }
+    part = wave_sum(part);
+    if (lane == 0) s_red[wid] = part;
+    __syncthreads();
+    if (tid == 0) {
+      double off = 0.0;
+      for (int w = 0; w < (int)blockDim.x / WAVE; ++w) off += s_red[w];
+      s_done = off <= 1e-30 * fro2;
+    }
+    __syncthreads();
+    if (s_done) break;
+  }
+  // eigenvalues of the cnt real columns, descending (selection by the wave argmax,
+  // lowest index among equal values), on wave 0
+  if (wid == 0) {
+    double v = lane < cnt ? A[lane][lane] : -INFINITY;
+    for (int j = 0; j < cnt; ++j) {
+      const int imax = wave_argmax(v, lane);
+      if (lane == 0) {
+        order[j] = imax;
+        lam[j] = A[imax][imax];
+      }
+      if (lane == imax) v = -INFINITY;
+    }
+  }
+  __syncthreads();
+  int k = 0;
+  if (lam[0] > 0.0)
+    while (k < cnt && k < m && lam[k] > tau * lam[0]) ++k;
+  for (int e = tid; e < MAXM * MAXM; e += blockDim.x) {
+    const int row = e % MAXM, c = e / MAXM;
+    double t = 0.0;
+    if (c < k && row < cnt) t = V[row][order[c]] / sqrt(lam[c]);
+    ctl->T1[e] = t;
+  }
+  if (tid == 0) {
+    ctl->k = k;
+    ctl->nonfinite = 0;
+  }
+}
+
+hipError_t launch_pod_eig(int cnt, int m, double tau, Ctl *ctl, hipStream_t st) {
+  hipLaunchKernelGGL(k_pod_eig, dim3(1), dim3(TPB), 0, st, cnt, m, tau, ctl);
+  return hipGetLastError();
+}
+
 // ---------------------------------------------------------------------------- column sums
 // gram[e] = sum_b partials[b][e]; block = 16 entries x 16 block-groups.
 __global__ __launch_bounds__(TPB) void k_colsum(const double *partials, int nblk, int W, Ctl *ctl) {
@@ -1197,6 +1433,7 @@ hipError_t launch_zero(double *x, int64_t n, hipStream_t st) {
   template hipError_t launch_spmm_gram<TX>(const CsrView &, const TX *, int64_t, const double *, int, int,    \
                                            double *, int *, Ctl *, hipStream_t);                               \
   template hipError_t launch_x0<TX>(const TX *, const TX *, double *, int64_t, int64_t, Ctl *, hipStream_t);   \
+  template hipError_t launch_gram_x<TX>(const TX *, int64_t, int64_t, int, double *, int *, hipStream_t);     \
   template hipError_t launch_to_double<TX>(const TX *, double *, int64_t, hipStream_t);
 
 SACC_INSTANTIATE_PROJ(double)

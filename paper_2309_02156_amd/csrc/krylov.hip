@@ -19,6 +19,8 @@
 #include <hip/hip_ext.h>
 #include <math.h>
 
+#include <type_traits>
+
 #include "common.h"
 #include "kernels.h"
 
@@ -151,37 +153,43 @@ __device__ inline double pick4(const double (&r)[4], int e) {
 // recursive-residual stop (state CHECK) the host's batch-end confirmation recomputes
 // the true residual; if it fails the direction restarts (p = r).
 
-template <typename VT, typename TV, int C>
+template <typename VT, typename TV, int C, bool PC>
 __global__ __launch_bounds__(KTPB) void k_cg_start(const int *rowptr, const int *col, const VT *val,
                                                    const TV *b, const TV *x, TV *r, int64_t n, int mode,
-                                                   double *Pout, const Ctl *ctl) {
-  __shared__ double red[KNW * 2];
-  __shared__ double prod[KNW * WT_CAP];
+                                                   double *Pout, const Ctl *ctl, const TV *dinv) {
+  __shared__ double red[KNW * 4];
+  __shared__ int lcol[KNW * WT_CAP];
+  __shared__ VT lval[KNW * WT_CAP];
   __shared__ int s_go;
   if (threadIdx.x == 0) s_go = (mode != 1) || (ctl->state == ST_CHECK);
   __syncthreads();
   if (!s_go) return;
   const int lane = threadIdx.x % WAVE, wid = threadIdx.x / WAVE;
-  double *pw = prod + (size_t)wid * WT_CAP;
+  int *lc = lcol + (size_t)wid * WT_CAP;
+  VT *lv = lval + (size_t)wid * WT_CAP;
   (void)lane;
   const Gather1<TV> gx{x};
-  double acc[2] = {0.0, 0.0};
+  // ||r||^2, ||b||^2 and (preconditioned) r^T z with z = D^-1 r
+  constexpr int K = PC ? 4 : 2;
+  double acc[K] = {};
   const WaveTiles wt = wave_tiles(n);
-  wave_tiles_spmv_pipelined<C>(
-      rowptr, col, val, gx, n, wt.t, wt.end, wt.step, pw, [&](int64_t i) { return (double)b[i]; },
+  wave_tiles_spmv<C>(
+      rowptr, col, val, gx, n, wt.t, wt.end, wt.step, lc, lv,
+      [&](int64_t i) { return (double)b[i]; },
       [&](int64_t i, double bi, double ax) {
         const TV rs = (TV)(bi - ax);
         if (mode != 2) r[i] = rs;
         const double ri = (double)rs;
         acc[0] += ri * ri;
         acc[1] += bi * bi;
+        if constexpr (PC) acc[K - 2] += ri * ((double)dinv[i] * ri);
       });
-  kstore<2>(acc, 2, red, Pout + (size_t)blockIdx.x * KW);
+  kstore<K>(acc, PC ? 3 : 2, red, Pout + (size_t)blockIdx.x * KW);
 }
 
 __global__ __launch_bounds__(KTPB) void k_cg_start_close(const double *Pin, int nblk, int mode, Ctl *ctl,
-                                                         int serial) {
-  __shared__ double outv[2];
+                                                         int serial, int pc) {
+  __shared__ double outv[3];
   __shared__ double scratch[KTPB];
   __shared__ int s_go, s_st;
   if (threadIdx.x == 0) {
@@ -193,48 +201,55 @@ __global__ __launch_bounds__(KTPB) void k_cg_start_close(const double *Pin, int 
     if (threadIdx.x == 0) mirror_report(ctl->mirror, serial, s_st == ST_RUN ? 0u : MIR_STOPPED);
     return;
   }
-  final_sum(Pin, nblk, KW, 2, outv, scratch);
+  final_sum(Pin, nblk, KW, pc ? 3 : 2, outv, scratch);
   if (threadIdx.x != 0) return;
   const int st = residual_decide(outv[0], outv[1], mode, ctl, true, ctl->trust_est != 0);
   if (mode != 2 && st == ST_RUN) {
     const int k = ctl->iters;
-    ctl->rho[k & 3] = outv[0];
+    ctl->rho[k & 3] = pc ? outv[2] : outv[0];  // r^T z (z = r without the preconditioner)
     ctl->fresh_at = k + 1;
   }
   if (mode != 2) mirror_report(ctl->mirror, serial, st == ST_RUN ? 0u : MIR_STOPPED);
 }
 
-template <typename TV>
+template <typename TV, bool PC>
 struct GatherDir {
   const TV *__restrict__ r;
   const TV *__restrict__ p;
+  const TV *__restrict__ dinv;  // Jacobi: z = D^-1 r (PC)
   double beta;
   int fresh;
-  // the direction entry as it is stored (rounded to TV), so q = A p uses the same p.
-  // Both entries are loaded unconditionally: with the load of p[c] under the branch on
-  // `fresh` the compiler waited for each gather before issuing the next one.
-  __device__ double operator()(int c) const {
-    const double rv = (double)r[c];
-    const double pv = (double)p[c];
-    const double d = (double)(TV)(rv + beta * pv);
-    return fresh ? rv : d;
+  // the direction entry as it is stored (rounded to TV), so q = A p uses the same p:
+  // p = z + beta p_old, or p = z when the direction restarts.  Every entry is loaded
+  // unconditionally: with the load of p[c] under the branch on `fresh` the compiler
+  // waited for each gather before issuing the next one.
+  // (returned in TV: the value is a TV in any case)
+  __device__ TV operator()(int c) const {
+    const unsigned u = (unsigned)c;
+    const double rv = (double)r[u];
+    const double pv = (double)p[u];
+    double zv = rv;
+    if constexpr (PC) zv = (double)dinv[u] * rv;
+    const TV d = (TV)(zv + beta * pv);
+    return fresh ? (TV)zv : d;
   }
 };
 
 // C = gathers per lane and round of a wave tile
-template <typename VT, typename TV, int C>
+template <typename VT, typename TV, int C, bool PC>
 __global__ __launch_bounds__(KTPB) void k_cg_p(const int *rowptr, const int *col, const VT *val, const TV *r,
                                                TV *P0, TV *P1, TV *q, int64_t n, const double *Pin, int nblk,
-                                               double *Pout, Ctl *ctl, int lidx) {
+                                               double *Pout, Ctl *ctl, int lidx, const TV *dinv) {
   __shared__ double red[KNW];
-  __shared__ double outv[1];
+  __shared__ double outv[2];
   __shared__ double scratch[KTPB];
-  __shared__ double prod[KNW * WT_CAP];
+  __shared__ int lcol[KNW * WT_CAP];
+  __shared__ VT lval[KNW * WT_CAP];
   __shared__ int s_k, s_fresh, s_go, s_cont, s_maxit;
   __shared__ double s_beta, s_tolb, s_rho2;
-  // r^T r of the previous iteration (unused when the direction restarts), loaded
-  // together with the control block
-  const double part = final_part<2>(Pin, nblk, KW, 1);
+  // r^T r (and r^T z) of the previous iteration (unused when the direction restarts),
+  // loaded together with the control block
+  const double part = final_part<2>(Pin, nblk, KW, PC ? 2 : 1);
   if (threadIdx.x == 0) {
     // every control-block read of the kernel, issued together
     const int st = ctl->state, it = ctl->iters, fa = ctl->fresh_at, mx = ctl->maxit;
@@ -252,15 +267,15 @@ __global__ __launch_bounds__(KTPB) void k_cg_p(const int *rowptr, const int *col
   __syncthreads();
   if (!s_go) return;
   const int k = s_k, fresh = s_fresh;
-  if (!fresh) final_tree(part, 1, outv, scratch);
+  if (!fresh) final_tree(part, PC ? 2 : 1, outv, scratch);
   if (threadIdx.x == 0) {
     int st = ST_RUN;
     double beta = 0.0;
     if (!fresh) {
-      const double rho = outv[0];
-      if (sqrt(rho) <= s_tolb)
+      const double rr = outv[0], rho = PC ? outv[1] : outv[0];  // ||r||^2 decides; r^T z gives beta
+      if (sqrt(rr) <= s_tolb)
         st = ST_CHECK;
-      else if (!isfinite(rho))
+      else if (!isfinite(rr) || !isfinite(rho))
         st = ST_BREAK;
       else
         beta = rho / s_rho2;
@@ -280,16 +295,17 @@ __global__ __launch_bounds__(KTPB) void k_cg_p(const int *rowptr, const int *col
   const double beta = s_beta;
   const TV *pin = (k & 1) ? P0 : P1;
   TV *pout = (k & 1) ? P1 : P0;
-  const GatherDir<TV> gx{r, pin, beta, fresh};
+  const GatherDir<TV, PC> gx{r, pin, dinv, beta, fresh};
   const int lane = threadIdx.x % WAVE, wid = threadIdx.x / WAVE;
-  double *pw = prod + (size_t)wid * WT_CAP;
+  int *lc = lcol + (size_t)wid * WT_CAP;
+  VT *lv = lval + (size_t)wid * WT_CAP;
   (void)lane;
   double acc[1] = {0.0};
   const WaveTiles wt = wave_tiles(n);
   // the row's own direction entry is requested with the tile's gathers (exact: gx rounds
   // to TV); the next tile's index loads overlap this tile's gathers
-  wave_tiles_spmv_pipelined<C>(
-      rowptr, col, val, gx, n, wt.t, wt.end, wt.step, pw, [&](int64_t i) { return gx((int)i); },
+  wave_tiles_spmv<C>(
+      rowptr, col, val, gx, n, wt.t, wt.end, wt.step, lc, lv, [&](int64_t i) { return gx((int)i); },
       [&](int64_t i, double pv, double qi) {
         const TV ps = (TV)pv;
         pout[i] = ps;
@@ -301,10 +317,11 @@ __global__ __launch_bounds__(KTPB) void k_cg_p(const int *rowptr, const int *col
 }
 
 // U = rows each thread takes per pass (all their loads issued before the first use)
-template <typename TV, int U>
+template <typename TV, int U, bool PC>
 __global__ __launch_bounds__(KTPB) void k_cg_xr(TV *x, TV *r, const TV *P0, const TV *P1, const TV *q, int64_t n,
-                                                const double *Pin, int nblk, double *Pout, Ctl *ctl, int serial) {
-  __shared__ double red[KNW];
+                                                const double *Pin, int nblk, double *Pout, Ctl *ctl, int serial,
+                                                const TV *dinv) {
+  __shared__ double red[KNW * 2];
   __shared__ double outv[1];
   __shared__ double scratch[KTPB];
   __shared__ int s_k, s_go, s_st;
@@ -338,9 +355,11 @@ __global__ __launch_bounds__(KTPB) void k_cg_xr(TV *x, TV *r, const TV *P0, cons
   }
   const double alpha = s_rho / pq;
   const TV *p = (k & 1) ? P1 : P0;
-  double acc[1] = {0.0};
+  // ||r||^2 and (preconditioned) r^T z of the new residual
+  constexpr int K = PC ? 2 : 1;
+  double acc[K] = {};
   for (int64_t r0 = (int64_t)blockIdx.x * (U * KTPB); r0 < n; r0 += (int64_t)gridDim.x * (U * KTPB)) {
-    double xv[U], pv[U], rv[U], qv[U];
+    double xv[U], pv[U], rv[U], qv[U], dv[U];
 #pragma unroll
     for (int u = 0; u < U; ++u) {
       const int64_t i = r0 + (int64_t)u * KTPB + threadIdx.x;
@@ -349,6 +368,7 @@ __global__ __launch_bounds__(KTPB) void k_cg_xr(TV *x, TV *r, const TV *P0, cons
       pv[u] = (double)p[ic];
       rv[u] = (double)r[ic];
       qv[u] = (double)q[ic];
+      if constexpr (PC) dv[u] = (double)dinv[ic];
     }
 #pragma unroll
     for (int u = 0; u < U; ++u) {
@@ -359,10 +379,11 @@ __global__ __launch_bounds__(KTPB) void k_cg_xr(TV *x, TV *r, const TV *P0, cons
         r[i] = rs;
         const double ri = (double)rs;
         acc[0] += ri * ri;
+        if constexpr (PC) acc[K - 1] += ri * (dv[u] * ri);
       }
     }
   }
-  kstore<1>(acc, 1, red, Pout + (size_t)blockIdx.x * KW);
+  kstore<K>(acc, K, red, Pout + (size_t)blockIdx.x * KW);
   if (blockIdx.x == 0 && threadIdx.x == 0) {
     ctl->iters = k;
     mirror_report(ctl->mirror, serial, 0u);
@@ -372,14 +393,15 @@ __global__ __launch_bounds__(KTPB) void k_cg_xr(TV *x, TV *r, const TV *P0, cons
 // Grid of the CG iteration kernels: one wave tile per wave, at most the blocks the device
 // holds at once (every block of the grid-stride loop resident, so no tail of late
 // blocks), a multiple of NXCD.  The p / q kernel's registers decide the occupancy.
-template <typename VT, typename TV, int C>
+template <typename VT, typename TV, int C, bool PC>
 static int cg_grid(int64_t n) {
-  static int resident = 0;  // blocks of k_cg_p<VT, TV, C> the device holds at once
+  static int resident = 0;  // blocks of k_cg_p<VT, TV, C, PC> the device holds at once
   if (resident == 0) {
     int dev = 0, ncu = 0, per = 0;
     if (hipGetDevice(&dev) != hipSuccess ||
         hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
-        hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, k_cg_p<VT, TV, C>, KTPB, 0) != hipSuccess || per < 1)
+        hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, k_cg_p<VT, TV, C, PC>, KTPB, 0) != hipSuccess ||
+        per < 1)
       return cgblocks(n);
     const int r = per * ncu / NXCD * NXCD;
     resident = r < NXCD ? NXCD : (r > CG_MAXBLK ? CG_MAXBLK : r);
@@ -395,79 +417,99 @@ static inline int cg_rows(int64_t n, int nb) {
   return per >= 4 ? 4 : (per >= 2 ? 2 : 1);
 }
 
-template <typename VT, typename TV, int C, int U>
+template <typename VT, typename TV, int C, int U, bool PC>
 static void cg_iter_launch(const CsrView &A, TV *x, TV *r, TV *P0, TV *P1, TV *q, double *partials, Ctl *ctl,
-                           hipStream_t st, const KTiming *tm, int serial, int nb) {
+                           hipStream_t st, const KTiming *tm, int serial, int nb, const TV *dinv) {
   // timed launches record their start/stop events in the kernel's own dispatch
   hipEvent_t e0 = tm ? tm->e0 : nullptr, e1 = tm ? tm->e1 : nullptr;
   const int lidx = tm ? tm->lidx : -1;
-  hipExtLaunchKernelGGL((k_cg_p<VT, TV, C>), dim3(nb), dim3(KTPB), 0, st, e0, e1, 0, A.rowptr, A.col,
-                        (const VT *)A.val, r, P0, P1, q, A.n, PA(partials), nb, PB(partials), ctl, lidx);
-  hipLaunchKernelGGL((k_cg_xr<TV, U>), dim3(nb), dim3(KTPB), 0, st, x, r, P0, P1, q, A.n, PB(partials), nb,
-                     PA(partials), ctl, serial);
+  // the SpMV reads one column / value entry even without nonzeros: stand-in arrays then
+  // (the row pointers and the workspace's residual, never used in a product)
+  const int *colp = A.nnz > 0 ? A.col : A.rowptr;
+  const VT *valp = A.nnz > 0 ? (const VT *)A.val : (const VT *)r;
+  hipExtLaunchKernelGGL((k_cg_p<VT, TV, C, PC>), dim3(nb), dim3(KTPB), 0, st, e0, e1, 0, A.rowptr, colp, valp, r,
+                        P0, P1, q, A.n, PA(partials), nb, PB(partials), ctl, lidx, dinv);
+  hipLaunchKernelGGL((k_cg_xr<TV, U, PC>), dim3(nb), dim3(KTPB), 0, st, x, r, P0, P1, q, A.n, PB(partials), nb,
+                     PA(partials), ctl, serial, dinv);
 }
 
-template <typename VT, typename TV, int C>
+template <typename VT, typename TV, int C, bool PC>
 static void cg_iter_u(const CsrView &A, TV *x, TV *r, TV *P0, TV *P1, TV *q, double *partials, Ctl *ctl,
-                      hipStream_t st, const KTiming *tm, int serial) {
-  const int nb = cg_grid<VT, TV, C>(A.n);
+                      hipStream_t st, const KTiming *tm, int serial, const TV *dinv) {
+  const int nb = cg_grid<VT, TV, C, PC>(A.n);
   const int U = cg_rows(A.n, nb);
   if (U == 4)
-    cg_iter_launch<VT, TV, C, 4>(A, x, r, P0, P1, q, partials, ctl, st, tm, serial, nb);
+    cg_iter_launch<VT, TV, C, 4, PC>(A, x, r, P0, P1, q, partials, ctl, st, tm, serial, nb, dinv);
   else if (U == 2)
-    cg_iter_launch<VT, TV, C, 2>(A, x, r, P0, P1, q, partials, ctl, st, tm, serial, nb);
+    cg_iter_launch<VT, TV, C, 2, PC>(A, x, r, P0, P1, q, partials, ctl, st, tm, serial, nb, dinv);
   else
-    cg_iter_launch<VT, TV, C, 1>(A, x, r, P0, P1, q, partials, ctl, st, tm, serial, nb);
+    cg_iter_launch<VT, TV, C, 1, PC>(A, x, r, P0, P1, q, partials, ctl, st, tm, serial, nb, dinv);
 }
 
-template <typename VT, typename TV, int C>
+template <typename VT, typename TV, int C, bool PC>
 static int cg_start_c(const CsrView &A, const TV *b, const TV *x, TV *r, int mode, double *partials, const Ctl *ctl,
-                      hipStream_t st) {
-  const int nb = cg_grid<VT, TV, C>(A.n);
-  hipLaunchKernelGGL((k_cg_start<VT, TV, C>), dim3(nb), dim3(KTPB), 0, st, A.rowptr, A.col, (const VT *)A.val, b,
-                     x, r, A.n, mode, PA(partials), ctl);
+                      hipStream_t st, const TV *dinv) {
+  const int nb = cg_grid<VT, TV, C, PC>(A.n);
+  // stand-ins without nonzeros, as for the iteration kernel (r: workspace of >= 576 entries)
+  const int *colp = A.nnz > 0 ? A.col : A.rowptr;
+  const VT *valp = A.nnz > 0 ? (const VT *)A.val : (const VT *)r;
+  hipLaunchKernelGGL((k_cg_start<VT, TV, C, PC>), dim3(nb), dim3(KTPB), 0, st, A.rowptr, colp, valp, b, x, r, A.n,
+                     mode, PA(partials), ctl, dinv);
   return nb;
 }
 
-template <typename VT, typename TV>
+template <typename VT, typename TV, bool PC>
 static int cg_start_launch(const CsrView &A, const TV *b, const TV *x, TV *r, int mode, double *partials,
-                           const Ctl *ctl, hipStream_t st) {
+                           const Ctl *ctl, hipStream_t st, const TV *dinv) {
   const int C = wave_tile_chunk(A.n, A.nnz);
-  if (C <= 5) return cg_start_c<VT, TV, 5>(A, b, x, r, mode, partials, ctl, st);
-  if (C <= 7) return cg_start_c<VT, TV, 7>(A, b, x, r, mode, partials, ctl, st);
-  return cg_start_c<VT, TV, 9>(A, b, x, r, mode, partials, ctl, st);
+  if (C <= 5) return cg_start_c<VT, TV, 5, PC>(A, b, x, r, mode, partials, ctl, st, dinv);
+  if (C <= 7) return cg_start_c<VT, TV, 7, PC>(A, b, x, r, mode, partials, ctl, st, dinv);
+  return cg_start_c<VT, TV, 9, PC>(A, b, x, r, mode, partials, ctl, st, dinv);
 }
 
 template <typename TV>
 hipError_t launch_cg_start_k(const CsrView &A, const TV *b, const TV *x, TV *r, int mode, double *partials, Ctl *ctl,
-                             hipStream_t st, int serial) {
-  const int nb = A.fp32 ? cg_start_launch<float, TV>(A, b, x, r, mode, partials, ctl, st)
-                        : cg_start_launch<double, TV>(A, b, x, r, mode, partials, ctl, st);
-  hipLaunchKernelGGL(k_cg_start_close, dim3(1), dim3(KTPB), 0, st, PA(partials), nb, mode, ctl, serial);
+                             hipStream_t st, int serial, const TV *dinv) {
+  int nb;
+  if (dinv)
+    nb = A.fp32 ? cg_start_launch<float, TV, true>(A, b, x, r, mode, partials, ctl, st, dinv)
+                : cg_start_launch<double, TV, true>(A, b, x, r, mode, partials, ctl, st, dinv);
+  else
+    nb = A.fp32 ? cg_start_launch<float, TV, false>(A, b, x, r, mode, partials, ctl, st, dinv)
+                : cg_start_launch<double, TV, false>(A, b, x, r, mode, partials, ctl, st, dinv);
+  hipLaunchKernelGGL(k_cg_start_close, dim3(1), dim3(KTPB), 0, st, PA(partials), nb, mode, ctl, serial,
+                     dinv ? 1 : 0);
   return hipGetLastError();
 }
 
-template <typename VT, typename TV>
+template <typename VT, typename TV, bool PC>
 static void cg_iter_vt(const CsrView &A, TV *x, TV *r, TV *P0, TV *P1, TV *q, double *partials, Ctl *ctl,
-                       hipStream_t st, const KTiming *tm, int serial) {
+                       hipStream_t st, const KTiming *tm, int serial, const TV *dinv) {
   const int C = wave_tile_chunk(A.n, A.nnz);
   if (C <= 5)
-    cg_iter_u<VT, TV, 5>(A, x, r, P0, P1, q, partials, ctl, st, tm, serial);
+    cg_iter_u<VT, TV, 5, PC>(A, x, r, P0, P1, q, partials, ctl, st, tm, serial, dinv);
   else if (C <= 7)
-    cg_iter_u<VT, TV, 7>(A, x, r, P0, P1, q, partials, ctl, st, tm, serial);
+    cg_iter_u<VT, TV, 7, PC>(A, x, r, P0, P1, q, partials, ctl, st, tm, serial, dinv);
   else
-    cg_iter_u<VT, TV, 9>(A, x, r, P0, P1, q, partials, ctl, st, tm, serial);
+    cg_iter_u<VT, TV, 9, PC>(A, x, r, P0, P1, q, partials, ctl, st, tm, serial, dinv);
 }
 
 template <typename TV>
 hipError_t launch_cg_iter(const CsrView &A, TV *x, TV *r, TV *p2, TV *q, double *partials, Ctl *ctl,
-                          hipStream_t st, const KTiming *tm, int serial) {
+                          hipStream_t st, const KTiming *tm, int serial, const TV *dinv) {
   const int64_t ld = padded_ld(A.n);
   TV *P0 = p2, *P1 = p2 + ld;
-  if (A.fp32)
-    cg_iter_vt<float, TV>(A, x, r, P0, P1, q, partials, ctl, st, tm, serial);
-  else
-    cg_iter_vt<double, TV>(A, x, r, P0, P1, q, partials, ctl, st, tm, serial);
+  if (dinv) {
+    if (A.fp32)
+      cg_iter_vt<float, TV, true>(A, x, r, P0, P1, q, partials, ctl, st, tm, serial, dinv);
+    else
+      cg_iter_vt<double, TV, true>(A, x, r, P0, P1, q, partials, ctl, st, tm, serial, dinv);
+  } else {
+    if (A.fp32)
+      cg_iter_vt<float, TV, false>(A, x, r, P0, P1, q, partials, ctl, st, tm, serial, dinv);
+    else
+      cg_iter_vt<double, TV, false>(A, x, r, P0, P1, q, partials, ctl, st, tm, serial, dinv);
+  }
   return hipGetLastError();
 }
 
@@ -720,8 +762,16 @@ __device__ inline TV slot_load(const TV *V, int64_t ld, int64_t i, int k, int li
   }
 }
 
+// Right-preconditioned operand of the Arnoldi product: A (D^-1 v) gathers d_c^-1 v_c
+template <typename TV>
+struct GatherScaled {
+  const TV *__restrict__ x;
+  const TV *__restrict__ dinv;
+  __device__ double operator()(int c) const { return (double)dinv[c] * (double)x[c]; }
+};
+
 // F(j); mode 0: first cycle, 1: restart cycle (both only matter for j = 0), 2: the
-// finalise-only step j = m.  R = row tiles of KTPB rows each block takes per pass.
+// finalise-only step j = m.  PC: Jacobi right preconditioning, w = A D^-1 v.  R = row tiles of KTPB rows each block takes per pass.
 //
 // Order of the memory traffic (the first pass): one trip for the control block, the
 // previous kernel's partial rows and the pass's row pointers; then the SpMV's column /
@@ -729,10 +779,10 @@ __device__ inline TV slot_load(const TV *V, int64_t ld, int64_t i, int k, int li
 // before the column values), so the column stream overlaps the SpMV's dependent trips
 // and the LDS work of the prologue.  The gathers read in bounds for any pass: column
 // indices come from clamped in-range loads.
-template <typename VT, typename TV, int RB, int R>
+template <typename VT, typename TV, int RB, int R, bool PC>
 __global__ __launch_bounds__(KTPB) void k_gm_f(const int *rowptr, const int *col, const VT *val, TV *V, TV *T,
                                                int64_t n, int64_t ld, int j, int mode, const double *Pin, int nblk,
-                                               double *Pout, Ctl *ctl, int lidx) {
+                                               double *Pout, Ctl *ctl, int lidx, const TV *dinv) {
   const int LD = MAXR + 1;
   constexpr int NR = R * KTPB;
   constexpr int CAP = SPMV_CAP * R;
@@ -750,7 +800,12 @@ __global__ __launch_bounds__(KTPB) void k_gm_f(const int *rowptr, const int *col
   const TV *src = (j == 0) ? V : T;
   TV *wcol = V + (size_t)j * ld;
   TV *ycol = V + (size_t)(j + 1) * ld;
-  const Gather1<TV> gx{src};
+  using Gx = std::conditional_t<PC, GatherScaled<TV>, Gather1<TV>>;
+  Gx gx;
+  if constexpr (PC)
+    gx = Gx{src, dinv};
+  else
+    gx = Gx{src};
   const int64_t stride = (int64_t)gridDim.x * NR;
   int64_t r0 = (int64_t)blockIdx.x * NR;
 
@@ -1127,9 +1182,10 @@ __global__ __launch_bounds__(KTPB) void k_gm_close(const double *Pin, int nblk, 
 // ||w'_m||^2 - ||g||^2 (w''_m = w'_m - V g with V orthonormal; g is the small second
 // correction, so there is no cancellation), which saves F(m).  When the cycle had
 // already ended (active = 0: its last close ran in G) the staged values serve.
-template <typename TV, int RB, int R>
+template <typename TV, int RB, int R, bool PC>
 __global__ __launch_bounds__(KTPB) void k_gm_update(TV *x, const TV *V, int64_t n, int64_t ld, Ctl *ctl,
-                                                    const double *Pin, int nblk, int jclose, int pyth) {
+                                                    const double *Pin, int nblk, int jclose, int pyth,
+                                                    const TV *dinv) {
   const int LD = MAXR + 1;
   __shared__ double coef[RB];
   __shared__ double Rs[RB * RB];
@@ -1206,7 +1262,7 @@ __global__ __launch_bounds__(KTPB) void k_gm_update(TV *x, const TV *V, int64_t 
   if (m <= 0) return;
   const int64_t stride = (int64_t)gridDim.x * (R * KTPB);
   int64_t r0 = (int64_t)blockIdx.x * (R * KTPB);
-  TV vl[R][RB], xv[R];
+  TV vl[R][RB], xv[R], dv[R];
   auto load_pass = [&](int64_t rb) {
 #pragma unroll
     for (int u = 0; u < R; ++u) {
@@ -1215,6 +1271,7 @@ __global__ __launch_bounds__(KTPB) void k_gm_update(TV *x, const TV *V, int64_t 
 #pragma unroll
       for (int l = 0; l < RB; ++l) vl[u][l] = slot_load(V, ld, ic, l, m);
       xv[u] = x[ic];
+      if constexpr (PC) dv[u] = dinv[ic];
     }
   };
   // the partial rows are summed before the column loads go out (a wait for them behind
@@ -1265,10 +1322,18 @@ __global__ __launch_bounds__(KTPB) void k_gm_update(TV *x, const TV *V, int64_t 
     for (int u = 0; u < R; ++u) {
       const int64_t i = r0 + (int64_t)u * KTPB + t;
       if (i < n) {
-        double s = (double)xv[u];
+        if constexpr (PC) {
+          // right preconditioning: x += D^-1 (V y)
+          double s = 0.0;
 #pragma unroll
-        for (int l = 0; l < RB; ++l) s += coef[l] * (double)vl[u][l];
-        x[i] = (TV)s;
+          for (int l = 0; l < RB; ++l) s += coef[l] * (double)vl[u][l];
+          x[i] = (TV)((double)xv[u] + (double)dv[u] * s);
+        } else {
+          double s = (double)xv[u];
+#pragma unroll
+          for (int l = 0; l < RB; ++l) s += coef[l] * (double)vl[u][l];
+          x[i] = (TV)s;
+        }
       }
     }
     r0 += stride;
@@ -1294,9 +1359,9 @@ hipError_t launch_gm_start(const CsrView &A, const TV *b, const TV *x, TV *V, in
 // has at least two (the grid is capped at KMAXBLK blocks)
 static inline bool gm_two_rows(int64_t n) { return n >= (int64_t)2 * KTPB * KMAXBLK; }
 
-template <typename TV, int RB, int R>
-static void gm_f_launch(const CsrView &A, TV *V, TV *T, int64_t ld, int j, int mode, double *partials, Ctl *ctl,
-                        hipStream_t st, const KTiming *tm) {
+template <typename TV, int RB, int R, bool PC>
+static void gm_f_launch_pc(const CsrView &A, TV *V, TV *T, int64_t ld, int j, int mode, double *partials, Ctl *ctl,
+                           hipStream_t st, const KTiming *tm, const TV *dinv) {
   const int nb = kblocks(A.n);
   // timed launches record their start/stop events in the kernel's own dispatch
   hipEvent_t e0 = tm ? tm->e0 : nullptr, e1 = tm ? tm->e1 : nullptr;
@@ -1306,11 +1371,22 @@ static void gm_f_launch(const CsrView &A, TV *V, TV *T, int64_t ld, int j, int m
   const int *colp = A.nnz > 0 ? A.col : A.rowptr;
   const void *valp = A.nnz > 0 ? A.val : (const void *)V;
   if (A.fp32)
-    hipExtLaunchKernelGGL((k_gm_f<float, TV, RB, R>), dim3(nb), dim3(KTPB), 0, st, e0, e1, 0, A.rowptr, colp,
-                          (const float *)valp, V, T, A.n, ld, j, mode, PA(partials), nb, PB(partials), ctl, lidx);
+    hipExtLaunchKernelGGL((k_gm_f<float, TV, RB, R, PC>), dim3(nb), dim3(KTPB), 0, st, e0, e1, 0, A.rowptr, colp,
+                          (const float *)valp, V, T, A.n, ld, j, mode, PA(partials), nb, PB(partials), ctl, lidx,
+                          dinv);
   else
-    hipExtLaunchKernelGGL((k_gm_f<double, TV, RB, R>), dim3(nb), dim3(KTPB), 0, st, e0, e1, 0, A.rowptr, colp,
-                          (const double *)valp, V, T, A.n, ld, j, mode, PA(partials), nb, PB(partials), ctl, lidx);
+    hipExtLaunchKernelGGL((k_gm_f<double, TV, RB, R, PC>), dim3(nb), dim3(KTPB), 0, st, e0, e1, 0, A.rowptr,
+                          colp, (const double *)valp, V, T, A.n, ld, j, mode, PA(partials), nb, PB(partials), ctl,
+                          lidx, dinv);
+}
+
+template <typename TV, int RB, int R>
+static void gm_f_launch(const CsrView &A, TV *V, TV *T, int64_t ld, int j, int mode, double *partials, Ctl *ctl,
+                        hipStream_t st, const KTiming *tm, const TV *dinv) {
+  if (dinv)
+    gm_f_launch_pc<TV, RB, R, true>(A, V, T, ld, j, mode, partials, ctl, st, tm, dinv);
+  else
+    gm_f_launch_pc<TV, RB, R, false>(A, V, T, ld, j, mode, partials, ctl, st, tm, dinv);
 }
 
 // F takes two row tiles per pass only at 8 slots on grids with two tiles per block
@@ -1319,14 +1395,14 @@ static void gm_f_launch(const CsrView &A, TV *V, TV *T, int64_t ld, int j, int m
 // tiles would not fit in the registers of two waves per SIMD
 template <typename TV, int RB>
 static void gm_f_rb(const CsrView &A, TV *V, TV *T, int64_t ld, int j, int mode, double *partials, Ctl *ctl,
-                    hipStream_t st, const KTiming *tm = nullptr) {
+                    hipStream_t st, const KTiming *tm, const TV *dinv) {
   if constexpr (RB <= 8) {
     if (gm_two_rows(A.n)) {
-      gm_f_launch<TV, RB, 2>(A, V, T, ld, j, mode, partials, ctl, st, tm);
+      gm_f_launch<TV, RB, 2>(A, V, T, ld, j, mode, partials, ctl, st, tm, dinv);
       return;
     }
   }
-  gm_f_launch<TV, RB, 1>(A, V, T, ld, j, mode, partials, ctl, st, tm);
+  gm_f_launch<TV, RB, 1>(A, V, T, ld, j, mode, partials, ctl, st, tm, dinv);
 }
 
 // G takes two row tiles per pass up to 8 columns on grids with two tiles per block, one
@@ -1360,14 +1436,14 @@ static void gm_g_rb(const CsrView &A, TV *V, TV *T, int64_t ld, int j, double *p
 // (used at j = 0); norm_w: G(j) also records ||w'||^2 (see k_gm_g).
 template <typename TV>
 hipError_t launch_gm_step(const CsrView &A, TV *V, TV *T, int64_t ld, int j, int first_mode, double *partials,
-                          Ctl *ctl, hipStream_t st, const KTiming *tm, int serial, bool norm_w) {
+                          Ctl *ctl, hipStream_t st, const KTiming *tm, int serial, bool norm_w, const TV *dinv) {
   const int mode = j == 0 ? first_mode : 0;
   if (j <= 8)
-    gm_f_rb<TV, 8>(A, V, T, ld, j, mode, partials, ctl, st, tm);
+    gm_f_rb<TV, 8>(A, V, T, ld, j, mode, partials, ctl, st, tm, dinv);
   else if (j <= 16)
-    gm_f_rb<TV, 16>(A, V, T, ld, j, mode, partials, ctl, st, tm);
+    gm_f_rb<TV, 16>(A, V, T, ld, j, mode, partials, ctl, st, tm, dinv);
   else
-    gm_f_rb<TV, 32>(A, V, T, ld, j, mode, partials, ctl, st, tm);
+    gm_f_rb<TV, 32>(A, V, T, ld, j, mode, partials, ctl, st, tm, dinv);
   if (j < 8)
     gm_g_rb<TV, 8>(A, V, T, ld, j, partials, ctl, st, serial, norm_w);
   else if (j < 16)
@@ -1381,27 +1457,37 @@ hipError_t launch_gm_step(const CsrView &A, TV *V, TV *T, int64_t ld, int j, int
 template <typename TV>
 hipError_t launch_gm_finish(const CsrView &A, TV *V, TV *T, int64_t ld, int m, double *partials, Ctl *ctl,
                             hipStream_t st, bool close) {
+  // the finalise-only step F(m) forms no product: the operand scaling does not matter
   const int nb = kblocks(A.n);
   if (m <= 8)
-    gm_f_rb<TV, 8>(A, V, T, ld, m, 2, partials, ctl, st);
+    gm_f_rb<TV, 8>(A, V, T, ld, m, 2, partials, ctl, st, nullptr, nullptr);
   else if (m <= 16)
-    gm_f_rb<TV, 16>(A, V, T, ld, m, 2, partials, ctl, st);
+    gm_f_rb<TV, 16>(A, V, T, ld, m, 2, partials, ctl, st, nullptr, nullptr);
   else
-    gm_f_rb<TV, 32>(A, V, T, ld, m, 2, partials, ctl, st);
+    gm_f_rb<TV, 32>(A, V, T, ld, m, 2, partials, ctl, st, nullptr, nullptr);
   if (close) hipLaunchKernelGGL(k_gm_close, dim3(1), dim3(KTPB), 0, st, PB(partials), nb, m - 1, ctl);
   return hipGetLastError();
 }
 
-template <typename TV, int RB>
-static void gm_update_rb(TV *x, const TV *V, int64_t n, int64_t ld, Ctl *ctl, const double *Pin, int jclose,
-                         int pyth, hipStream_t st) {
+template <typename TV, int RB, bool PC>
+static void gm_update_pc(TV *x, const TV *V, int64_t n, int64_t ld, Ctl *ctl, const double *Pin, int jclose,
+                         int pyth, hipStream_t st, const TV *dinv) {
   const int nb = kblocks(n);
   if (gm_two_rows(n))
-    hipLaunchKernelGGL((k_gm_update<TV, RB, 2>), dim3(nb), dim3(KTPB), 0, st, x, V, n, ld, ctl, Pin, nb, jclose,
-                       pyth);
+    hipLaunchKernelGGL((k_gm_update<TV, RB, 2, PC>), dim3(nb), dim3(KTPB), 0, st, x, V, n, ld, ctl, Pin, nb,
+                       jclose, pyth, dinv);
   else
-    hipLaunchKernelGGL((k_gm_update<TV, RB, 1>), dim3(nb), dim3(KTPB), 0, st, x, V, n, ld, ctl, Pin, nb, jclose,
-                       pyth);
+    hipLaunchKernelGGL((k_gm_update<TV, RB, 1, PC>), dim3(nb), dim3(KTPB), 0, st, x, V, n, ld, ctl, Pin, nb,
+                       jclose, pyth, dinv);
+}
+
+template <typename TV, int RB>
+static void gm_update_rb(TV *x, const TV *V, int64_t n, int64_t ld, Ctl *ctl, const double *Pin, int jclose,
+                         int pyth, hipStream_t st, const TV *dinv) {
+  if (dinv)
+    gm_update_pc<TV, RB, true>(x, V, n, ld, ctl, Pin, jclose, pyth, st, dinv);
+  else
+    gm_update_pc<TV, RB, false>(x, V, n, ld, ctl, Pin, jclose, pyth, st, dinv);
 }
 
 // whether G(m - 1) stores ||w'_m||^2 (a spare slot past its live columns): then a full
@@ -1410,32 +1496,57 @@ bool gm_norm_in_g(int m) { return m >= 1 && m < 32 && m != 8 && m != 16; }
 
 template <typename TV>
 hipError_t launch_gm_update(TV *x, const TV *V, int64_t n, int64_t ld, int restart, Ctl *ctl, hipStream_t st,
-                            double *partials, bool close_last, bool from_g) {
+                            double *partials, bool close_last, bool from_g, const TV *dinv) {
   const int pyth = close_last && from_g ? 1 : 0;
   const double *Pin = partials ? (pyth ? PA(partials) : PB(partials)) : nullptr;
   const int jclose = close_last ? restart - 1 : -1;
   if (restart <= 8)
-    gm_update_rb<TV, 8>(x, V, n, ld, ctl, Pin, jclose, pyth, st);
+    gm_update_rb<TV, 8>(x, V, n, ld, ctl, Pin, jclose, pyth, st, dinv);
   else if (restart <= 16)
-    gm_update_rb<TV, 16>(x, V, n, ld, ctl, Pin, jclose, pyth, st);
+    gm_update_rb<TV, 16>(x, V, n, ld, ctl, Pin, jclose, pyth, st, dinv);
   else
-    gm_update_rb<TV, 32>(x, V, n, ld, ctl, Pin, jclose, pyth, st);
+    gm_update_rb<TV, 32>(x, V, n, ld, ctl, Pin, jclose, pyth, st, dinv);
+  return hipGetLastError();
+}
+
+// Jacobi: one thread per row sums the row's entries in the diagonal column
+template <typename VT, typename TV>
+__global__ __launch_bounds__(KTPB) void k_jacobi_dinv(const int *rowptr, const int *col, const VT *val, TV *dinv,
+                                                      int64_t n) {
+  for (int64_t i = (int64_t)blockIdx.x * KTPB + threadIdx.x; i < n; i += (int64_t)gridDim.x * KTPB) {
+    double d = 0.0;
+    for (int k = rowptr[i], e = rowptr[i + 1]; k < e; ++k)
+      if (col[k] == (int)i) d += (double)val[k];
+    dinv[i] = (TV)(d != 0.0 ? 1.0 / d : 1.0);
+  }
+}
+
+template <typename TV>
+hipError_t launch_jacobi_dinv(const CsrView &A, TV *dinv, hipStream_t st) {
+  const int nb = kblocks(A.n);
+  if (A.fp32)
+    hipLaunchKernelGGL((k_jacobi_dinv<float, TV>), dim3(nb), dim3(KTPB), 0, st, A.rowptr, A.col,
+                       (const float *)A.val, dinv, A.n);
+  else
+    hipLaunchKernelGGL((k_jacobi_dinv<double, TV>), dim3(nb), dim3(KTPB), 0, st, A.rowptr, A.col,
+                       (const double *)A.val, dinv, A.n);
   return hipGetLastError();
 }
 
 #define SACC_INSTANTIATE_KRYLOV(TV)                                                                              \
   template hipError_t launch_cg_start_k<TV>(const CsrView &, const TV *, const TV *, TV *, int, double *, Ctl *, \
-                                            hipStream_t, int);                                                   \
+                                            hipStream_t, int, const TV *);                                       \
   template hipError_t launch_cg_iter<TV>(const CsrView &, TV *, TV *, TV *, TV *, double *, Ctl *, hipStream_t,  \
-                                         const KTiming *, int);                                                  \
+                                         const KTiming *, int, const TV *);                                      \
   template hipError_t launch_gm_start<TV>(const CsrView &, const TV *, const TV *, TV *, int, double *, Ctl *,   \
                                           hipStream_t);                                                          \
   template hipError_t launch_gm_step<TV>(const CsrView &, TV *, TV *, int64_t, int, int, double *, Ctl *,        \
-                                         hipStream_t, const KTiming *, int, bool);                               \
+                                         hipStream_t, const KTiming *, int, bool, const TV *);                   \
   template hipError_t launch_gm_finish<TV>(const CsrView &, TV *, TV *, int64_t, int, double *, Ctl *,           \
                                            hipStream_t, bool);                                                   \
   template hipError_t launch_gm_update<TV>(TV *, const TV *, int64_t, int64_t, int, Ctl *, hipStream_t, double *, \
-                                           bool, bool);
+                                           bool, bool, const TV *);                                              \
+  template hipError_t launch_jacobi_dinv<TV>(const CsrView &, TV *, hipStream_t);
 
 SACC_INSTANTIATE_KRYLOV(double)
 SACC_INSTANTIATE_KRYLOV(float)

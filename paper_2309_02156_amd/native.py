@@ -19,7 +19,8 @@ SA_CG, SA_GMRES = 0, 1
 SA_GALERKIN, SA_MINRES = 0, 1
 SA_SKETCH_GAUSSIAN, SA_SKETCH_SRHT = 0, 1
 SA_GUESS_PROJECTION, SA_GUESS_ZERO, SA_GUESS_PREVIOUS = 0, 1, 2
-SA_BASIS_SKETCHED_QR = 0
+SA_BASIS_SKETCHED_QR, SA_BASIS_POD = 0, 1
+SA_PRECOND_NONE, SA_PRECOND_JACOBI = 0, 1
 
 EXPORTS = ("sa_workspace_bytes", "sa_init_sequence", "sa_push_solution", "sa_initial_guess",
            "sa_solve", "sa_step", "sa_destroy_sequence", "sa_status_string", "sa_spmv", "sa_copy_state",
@@ -39,7 +40,7 @@ class SaConfig(ctypes.Structure):
         ("rank_tol_sketch", ctypes.c_double), ("rank_tol_chol", ctypes.c_double),
         ("seed", ctypes.c_uint64), ("poll", ctypes.c_int32), ("inner_maxit", ctypes.c_int32),
         ("m", ctypes.c_int32), ("refresh", ctypes.c_int32), ("basis", ctypes.c_int32),
-        ("reserved2", ctypes.c_int32),
+        ("precond", ctypes.c_int32),
     ]
 
 

@@ -18,7 +18,8 @@ _SKETCH = {"gaussian": nv.SA_SKETCH_GAUSSIAN, "srht": nv.SA_SKETCH_SRHT}
 _SOLVER = {"cg": nv.SA_CG, "gmres": nv.SA_GMRES}
 _PREC = {"fp64": nv.SA_FP64, "mixed": nv.SA_MIXED, "mixed_krylov": nv.SA_MIXED_KRYLOV}
 _PROJ = {"galerkin": nv.SA_GALERKIN, "minres": nv.SA_MINRES}
-_BASIS = {"sketched_qr": nv.SA_BASIS_SKETCHED_QR}
+_BASIS = {"sketched_qr": nv.SA_BASIS_SKETCHED_QR, "pod": nv.SA_BASIS_POD}
+_PRECOND = {"none": nv.SA_PRECOND_NONE, "jacobi": nv.SA_PRECOND_JACOBI}
 _GUESS = {"projection": nv.SA_GUESS_PROJECTION, "zero": nv.SA_GUESS_ZERO,
           "previous": nv.SA_GUESS_PREVIOUS}
 
@@ -73,22 +74,22 @@ def spmv(A: DeviceCSR, x: torch.Tensor, y: Optional[torch.Tensor] = None, stream
 
 
 def solver_config(n: int, solver: str = "cg", restart: int = 30, tol: float = 1e-8, maxit: int = 200000,
-                  poll: int = 0) -> nv.SaConfig:
+                  poll: int = 0, precond: str = "none") -> nv.SaConfig:
     """The configuration of a plain FP64 Krylov solve of size n (history fields at their
     smallest valid values: no initial guess is formed)."""
     return nv.SaConfig(n=n, M=1, s=1, sketch=nv.SA_SKETCH_GAUSSIAN, projection=nv.SA_GALERKIN,
                        solver=_SOLVER[solver], restart=restart, tol=tol, maxit=maxit, precision=nv.SA_FP64,
                        inner_tol=1e-4, max_refine=1, guess=nv.SA_GUESS_ZERO, rank_tol_sketch=0.0,
                        rank_tol_chol=0.0, seed=0, poll=poll, inner_maxit=0, m=0, refresh=0,
-                       basis=nv.SA_BASIS_SKETCHED_QR, reserved2=0)
+                       basis=nv.SA_BASIS_SKETCHED_QR, precond=_PRECOND[precond])
 
 
 def solve_static(A: DeviceCSR, b: torch.Tensor, x: torch.Tensor, solver: str = "cg", restart: int = 30,
                  tol: float = 1e-8, maxit: int = 200000, poll: int = 0, stream=None,
-                 allow=(nv.SA_OK, nv.SA_NOTCONV, nv.SA_EBREAKDOWN)):
+                 allow=(nv.SA_OK, nv.SA_NOTCONV, nv.SA_EBREAKDOWN), precond: str = "none"):
     """Krylov solve of A x = b from the iterate in x through sa_solve_static (no device
     allocation by the library); returns (x, info)."""
-    cfg = solver_config(A.n, solver, restart, tol, maxit, poll)
+    cfg = solver_config(A.n, solver, restart, tol, maxit, poll, precond)
     inf = nv.SaInfo()
     s = A.c_struct()
     rc = nv.lib().sa_solve_static(ctypes.byref(cfg), ctypes.byref(s), _ptr(b), _ptr(x), ctypes.byref(inf),
@@ -107,7 +108,8 @@ class Sequence:
                  precision: str = "fp64", projection: str = "galerkin", guess: str = "projection",
                  seed: int = 0, rank_tol_sketch: float = 0.0, rank_tol_chol: float = 0.0,
                  inner_tol: float = 1e-4, max_refine: int = 10, inner_maxit: int = 0, poll: int = 0,
-                 m: int = 0, refresh: int = 0, basis: str = "sketched_qr", device="cuda", stream=None):
+                 m: int = 0, refresh: int = 0, basis: str = "sketched_qr", precond: str = "none",
+                 device="cuda", stream=None):
         self.n, self.M = n, M
         self.s = 2 * M if s is None else s
         self.precision = precision
@@ -117,7 +119,7 @@ class Sequence:
             precision=_PREC[precision], inner_tol=inner_tol, max_refine=max_refine,
             guess=_GUESS[guess], rank_tol_sketch=rank_tol_sketch, rank_tol_chol=rank_tol_chol,
             seed=seed, poll=poll, inner_maxit=inner_maxit, m=m, refresh=refresh, basis=_BASIS[basis],
-            reserved2=0)
+            precond=_PRECOND[precond])
         L = nv.lib()
         nbytes = ctypes.c_size_t(0)
         nv.check(L.sa_workspace_bytes(ctypes.byref(self.cfg), ctypes.byref(nbytes)), "sa_workspace_bytes")

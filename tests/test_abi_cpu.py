@@ -58,7 +58,8 @@ def test_workspace_sizes_and_validation(nv):
     assert b.value > small   # GMRES(30) basis is larger than CG's three vectors
     bad = [dict(M=0), dict(M=33), dict(s=5), dict(s=300), dict(sketch=1, n=1000), dict(sketch=1, n=16, s=20, M=4),
            dict(solver=1, restart=0), dict(solver=1, restart=65), dict(tol=0.0), dict(tol=-1.0),
-           dict(maxit=-1), dict(guess=7), dict(n=0), dict(sketch=5), dict(projection=3), dict(projection=2), dict(precision=4)]
+           dict(maxit=-1), dict(guess=7), dict(n=0), dict(sketch=5), dict(projection=3), dict(projection=2), dict(precision=4),
+           dict(precond=2), dict(precond=-1)]
     for over in bad:
         assert L.sa_workspace_bytes(ctypes.byref(_cfg(nv, **over)), ctypes.byref(b)) == nv.SA_EINVAL, over
     assert L.sa_workspace_bytes(None, ctypes.byref(b)) == nv.SA_EINVAL

@@ -633,3 +633,58 @@ def test_range_finder_compression(sacc, k, N, steps, m):
         oseq.push(sols[i])
         gseq.push(dev(sols[i]))
     print_case("range finder worst max |dx0| / max |x0|", worst)
+
+
+# ---------------------------------------------------------------------------- POD basis (Alg. 2)
+
+@pytest.mark.parametrize("k,N,steps,m", [(0, 64, 16, 5), (1, 64, 24, 10)])
+def test_pod_guess_stepwise(sacc, k, N, steps, m):
+    """Alg. 2's basis (the m leading left singular vectors of X, through the FP64 Gram
+    X^T X and its Jacobi eigen-decomposition) from the same injected history: equal
+    ranks; x0 element by element within 1e-8 of its largest entry (the Gram squares the
+    singular values, so the trailing kept directions, near 1e-7 of the largest singular
+    value, are determined only to about 1e-9: the oracle's own guess moves by up to 7e-11
+    of its largest entry under a 1e-16 relative perturbation of X)."""
+    print_case("pod", k, N, steps, m)
+    p, meth = config(k, N)
+    sols = _oracle_history(p, meth, steps)
+    gseq = sacc.Sequence(p.n, **method_kwargs(meth, m=m, basis="pod"))
+    oseq = OSeq(p.n, meth["M"], meth["sketch"], meth["s"], meth["method_seed"], meth["solver"], meth["restart"],
+                meth["tol"], m=m, basis="pod")
+    worst = 0.0
+    for i in range(steps):
+        A = p.matrix(i)
+        As = A.to_scipy()
+        b = p.rhs(i)
+        g = oseq.initial_guess(As, b)
+        x0d, gi = gseq.initial_guess(sacc.DeviceCSR.from_csr(A), dev(b))
+        x0 = host(x0d)
+        assert (gi["k_sketch"], gi["k_eff"]) == (g.k, g.k2), (i, gi, g.k, g.k2)
+        if i > 0:
+            ew = float(np.max(np.abs(x0 - g.x0)) / np.max(np.abs(g.x0)))
+            worst = max(worst, ew)
+            assert ew <= 1e-8, (i, ew)
+        oseq.push(sols[i])
+        gseq.push(dev(sols[i]))
+    print_case("pod worst max |dx0| / max |x0|", worst)
+
+
+def test_pod_plain_definition(sacc):
+    """Separated singular values: the POD guess is the Galerkin projection on the span of
+    the m leading left singular vectors of X (numpy's SVD)."""
+    rng = np.random.default_rng(41)
+    n, M, m = 1500, 12, 5
+    U0, _ = np.linalg.qr(rng.standard_normal((n, M)))
+    V0, _ = np.linalg.qr(rng.standard_normal((M, M)))
+    X = U0 @ np.diag(np.geomspace(1.0, 1e-3, M)) @ V0.T
+    S = _spd_small(n, rng)
+    b = rng.standard_normal(n)
+    seq = sacc.Sequence(n, M, s=2 * M, solver="cg", m=m, basis="pod")
+    for j in range(M):
+        seq.push(dev(X[:, j]))
+    x0, info = seq.initial_guess(_dcsr(sacc, S), dev(b))
+    Um = obs.pod_basis(X, m)
+    ref = Um @ np.linalg.solve(Um.T @ (S @ Um), Um.T @ b)
+    err = np.linalg.norm(host(x0) - ref) / np.linalg.norm(ref)
+    print_case("pod plain: k, rel err", info["k_eff"], err)
+    assert info["k_sketch"] == m and err <= 1e-9

@@ -268,3 +268,35 @@ def test_sequence_z_matches_alg3_progressive():
         assert np.array_equal(Zs, ps.Z)
         X, _ = seq.history()
         assert np.linalg.norm(X @ Zs - ps.Omega) <= 1e-10 * np.linalg.norm(ps.Omega)
+
+
+def test_pod_from_gram_equals_svd_definition():
+    """Alg. 2 through X^T X: the basis X T1 spans the m leading left singular vectors of
+    X (the SVD definition) when the singular values are separated, is orthonormal, and
+    the guess built on it equals the Galerkin projection on span(U_m)."""
+    rng = np.random.default_rng(31)
+    n, M, m = 400, 10, 4
+    U0, _ = np.linalg.qr(rng.standard_normal((n, M)))
+    V0, _ = np.linalg.qr(rng.standard_normal((M, M)))
+    sv = np.geomspace(1.0, 1e-4, M)
+    X = U0 @ np.diag(sv) @ V0.T
+    T1, k = bs.pod_gram_factor(X, m)
+    assert k == m
+    Q1 = X @ T1
+    assert np.linalg.norm(Q1.T @ Q1 - np.eye(m)) <= 1e-10
+    Um = bs.pod_basis(X, m)
+    # principal angles between the two subspaces
+    cosines = np.linalg.svd(Um.T @ Q1, compute_uv=False)
+    assert np.all(cosines >= 1 - 1e-10)
+    # the guess on this basis is the Galerkin projection on span(U_m)
+    main = 4.0 + rng.uniform(0, 1, n)
+    A = np.diag(main) - np.diag(np.ones(n - 1), 1) - np.diag(np.ones(n - 1), -1)
+    b = rng.standard_normal(n)
+    g = bs.initial_guess(A, b, X, np.zeros((2 * M, M)), pod_m=m, spd=True)
+    H = Um.T @ A @ Um
+    ref = Um @ np.linalg.solve(H, Um.T @ b)
+    assert g.k == m and np.linalg.norm(g.x0 - ref) <= 1e-9 * np.linalg.norm(ref)
+    # singular values below 1e-7 of the largest are not resolved through the Gram: dropped
+    X2 = U0 @ np.diag(np.r_[1.0, 0.5, 1e-9, 1e-10, np.zeros(M - 4)]) @ V0.T
+    _, k2 = bs.pod_gram_factor(X2, m)
+    assert k2 == 2

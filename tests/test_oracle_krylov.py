@@ -133,3 +133,45 @@ def test_maxit_reports_not_converged(solver):
 def test_givens_rotation():
     c, s, r = kr.givens(3.0, 4.0)
     assert np.isclose(r, 5.0) and np.allclose([c * 3 + s * 4, -s * 3 + c * 4], [5.0, 0.0])
+
+
+def test_jacobi_preconditioned_solvers():
+    """Diagonal preconditioning: PCG equals CG on the symmetrically scaled system
+    D^-1/2 A D^-1/2 (the same iterates mapped back, x = D^-1/2 y); right-preconditioned
+    GMRES's first step minimises ||b - A D^-1 (c b)|| over c (closed form); both reach
+    the tolerance; with an identity diagonal they reduce to the plain solvers."""
+    import scipy.sparse as sp
+
+    from oracle import krylov as kr
+
+    rng = np.random.default_rng(51)
+    n = 120
+    d = rng.uniform(1.0, 50.0, n)
+    off = -np.ones(n - 1)
+    A = sp.diags([off, d + 2.5, off], [-1, 0, 1]).tocsr()
+    b = rng.standard_normal(n)
+    dinv = kr.jacobi_dinv(A)
+    assert np.allclose(dinv, 1.0 / (d + 2.5))
+    for it in (1, 3, 7):
+        xp, ip = kr.cg(A, b, np.zeros(n), 1e-14, maxit=it, dinv=dinv)
+        s = np.sqrt(dinv)
+        As = sp.diags(s) @ A @ sp.diags(s)
+        ys, _ = kr.cg(As, s * b, np.zeros(n), 1e-14, maxit=it)
+        assert ip["iters"] == it
+        assert np.linalg.norm(xp - s * ys) <= 1e-12 * np.linalg.norm(xp)
+    x, info = kr.cg(A, b, np.zeros(n), 1e-10, dinv=dinv)
+    assert info["status"] == 0 and np.linalg.norm(b - A @ x) <= 1e-10 * np.linalg.norm(b)
+    x0, i0 = kr.cg(A, b, np.zeros(n), 1e-10)
+    assert info["iters"] < i0["iters"]     # the diagonal spread 1..50 is what Jacobi removes
+    N = sp.diags([off * 1.4, d + 2.5, off * 0.6], [-1, 0, 1]).tocsr()
+    x1, i1 = kr.gmres(N, b, np.zeros(n), 1e-14, 30, maxit=1, dinv=dinv)
+    w = N @ (dinv * b)
+    c = (w @ b) / (w @ w)
+    assert np.linalg.norm(x1 - c * dinv * b) <= 1e-12 * np.linalg.norm(x1)
+    x2, i2 = kr.gmres(N, b, np.zeros(n), 1e-10, 30, dinv=dinv)
+    assert i2["status"] == 0 and np.linalg.norm(b - N @ x2) <= 1e-10 * np.linalg.norm(b)
+    for f in (kr.cg, kr.gmres):
+        xa, _ = f(A, b, np.zeros(n), 1e-14, maxit=5, dinv=np.ones(n)) if f is kr.cg else \
+            f(A, b, np.zeros(n), 1e-14, 30, maxit=5, dinv=np.ones(n))
+        xb, _ = f(A, b, np.zeros(n), 1e-14, maxit=5) if f is kr.cg else f(A, b, np.zeros(n), 1e-14, 30, maxit=5)
+        assert np.array_equal(xa, xb)
