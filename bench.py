@@ -102,18 +102,18 @@ class Staged:
                              shape=(self.n, self.n))
 
 
-def make_seq(sacc, n, method, guess="projection", precision=None):
+def make_seq(sacc, n, method, guess="projection", precision=None, precond="none"):
     return sacc.Sequence(n, method["M"], s=method["s"], sketch=method["sketch"], solver=method["solver"],
                          restart=method["restart"], tol=method["tol"], seed=method["method_seed"], guess=guess,
-                         precision=precision or method["prec"])
+                         precision=precision or method["prec"], precond=precond)
 
 
 def run_sequence(sacc, torch, st, method, fill, warmup, steps, guess="projection", precision=None, profile=False,
-                 keep_seq=False):
+                 keep_seq=False, precond="none"):
     """Steps 0 .. fill + warmup + steps - 1; the last `steps` are timed.  Returns the
     infos of the timed steps, their wall time, the kernel records (profile=True) and the
     sequence (keep_seq=True: the caller closes it) with its last solution."""
-    seq = make_seq(sacc, st.n, method, guess, precision)
+    seq = make_seq(sacc, st.n, method, guess, precision, precond)
     x = torch.empty(st.n, dtype=torch.float64, device="cuda")
     first = fill + warmup
     for i in range(first):
@@ -288,7 +288,7 @@ def headline(sacc, torch, np, args):
     comps = {}
     if not args.no_comparators:
         for name, kw in (("plain_fp64", dict(precision="fp64")), ("mixed_krylov", dict(precision="mixed_krylov")),
-                         ("previous", dict(guess="previous"))):
+                         ("previous", dict(guess="previous")), ("mixed_jacobi", dict(precond="jacobi"))):
             log(f"comparator on the same steps: {name}")
             # the plain FP64 method runs on the same operator (its float32 values upcast)
             stc = st.as_fp64() if name == "plain_fp64" else st

@@ -48,7 +48,11 @@ extern "C" {
 #define SA_FP64 0          /* every vector and reduction in float64                     */
 #define SA_MIXED 1         /* float32 matrix values (val_is_fp32 = 1), history, basis and
                               inner Krylov vectors; float64 arithmetic in registers, the
-                              small dense solves and the outer iterative refinement      */
+                              small dense solves and the outer iterative refinement; the
+                              Gaussian sketch in BF16 on the matrix cores: its normals G
+                              rounded to BF16 once, kept in the workspace
+                              (ceil(s / 16) 16 x ceil(n / 64) 64 x 2 bytes), applied to
+                              BF16(float32(x)) with FP32 accumulation, S = G / sqrt(s)  */
 #define SA_MIXED_KRYLOV 2  /* as SA_MIXED but history and basis in float64: the initial
                               guess keeps FP64 accuracy (float32 storage of the history
                               puts rounding noise of relative size 6e-8 into every guess,

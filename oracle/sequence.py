@@ -45,7 +45,8 @@ class Sequence:
             raise ValueError(precision)
         self.precision, self.inner_tol, self.max_refine = precision, inner_tol, max_refine
         self.store = mx.fl32 if precision == "mixed" else None
-        self.S = Sketch(sketch, n, self.s, seed)
+        # the mixed mode applies the Gaussian sketch in BF16 (its history is FP32)
+        self.S = Sketch(sketch, n, self.s, seed, bf16=precision == "mixed" and sketch == "gaussian")
         self.cols: list[np.ndarray] = []
         self.scols: list[np.ndarray] = []
         # m < M: the range finder's Z follows Alg. 3 (each column keeps the Gaussian row it

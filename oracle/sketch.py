@@ -15,8 +15,17 @@ Cholesky-QR).  S is one of
   entries of a partial Fisher-Yates shuffle of 0..n-1 (step i swaps i with
   i + index(word0 of block (i, 0, STREAM_SRHT_ROWS), n - i)).
 
-Pins: the Gaussian entries' moments, H^T H = n I, S's embedding distortion, and
-the oracle-independent numpy Philox (via ``philox``).
+With ``bf16=True`` (the Gaussian sketch of the mixed-precision mode) the sketch
+matrix is BF16: S = BF16(G) / sqrt(s), every normal g(r, j) rounded to FP32 and then
+to BF16 (round to nearest, ties to even, on the FP32 bit pattern).  It is applied to
+the FP32 column fl32(x) exactly (S x is the exact sum of the products, scaled by
+1 / sqrt(s)): on the GPU the FP32 column is split exactly into three BF16 terms
+(hi + mid + lo, 8 significant bits each) that the matrix cores multiply in one
+instruction, accumulating in FP32 over short runs and the runs in FP64.
+
+Pins: the Gaussian entries' moments, H^T H = n I, S's embedding distortion, the
+oracle-independent numpy Philox (via ``philox``), and the BF16 rounding against
+hand-worked bit patterns and torch's own float32 -> bfloat16 conversion.
 """
 
 from __future__ import annotations
@@ -26,13 +35,24 @@ import numpy as np
 from . import philox as px
 
 
-def gaussian_block(s: int, j0: int, j1: int, seed: int) -> np.ndarray:
-    """Columns j0..j1-1 of the Gaussian sketch S (s x (j1 - j0))."""
+def to_bf16(v) -> np.ndarray:
+    """Round to FP32, then to BF16 (nearest, ties to even), returned as float64."""
+    u = np.asarray(v, dtype=np.float64).astype(np.float32).view(np.uint32).astype(np.uint64)
+    u = (u + np.uint64(0x7FFF) + ((u >> np.uint64(16)) & np.uint64(1))) & np.uint64(0xFFFF0000)
+    return u.astype(np.uint32).view(np.float32).astype(np.float64)
+
+
+def gaussian_normals(s: int, j0: int, j1: int, seed: int) -> np.ndarray:
+    """The standard normals g(r, j) behind columns j0..j1-1 of the Gaussian sketch."""
     j = np.arange(j0, j1, dtype=np.uint64)
     q = np.arange((s + 3) // 4, dtype=np.uint64)
     g = px.normals4(j[None, :], q[:, None], px.STREAM_GAUSS_SKETCH, seed)  # (nq, nj, 4)
-    g = np.transpose(g, (0, 2, 1)).reshape(-1, j1 - j0)[:s]
-    return g / np.sqrt(s)
+    return np.transpose(g, (0, 2, 1)).reshape(-1, j1 - j0)[:s]
+
+
+def gaussian_block(s: int, j0: int, j1: int, seed: int) -> np.ndarray:
+    """Columns j0..j1-1 of the Gaussian sketch S (s x (j1 - j0))."""
+    return gaussian_normals(s, j0, j1, seed) / np.sqrt(s)
 
 
 def srht_signs(n: int, seed: int) -> np.ndarray:
@@ -71,8 +91,11 @@ def hadamard_entries(rows: np.ndarray, cols: np.ndarray) -> np.ndarray:
 class Sketch:
     """The sketch S of one sequence; ``apply(x)`` returns S x (length s, float64)."""
 
-    def __init__(self, kind: str, n: int, s: int, seed: int, chunk: int = 1 << 15):
+    def __init__(self, kind: str, n: int, s: int, seed: int, chunk: int = 1 << 15, bf16: bool = False):
         self.kind, self.n, self.s, self.seed, self.chunk = kind, n, s, seed, chunk
+        if bf16 and kind != "gaussian":
+            raise ValueError("the BF16 sketch is the Gaussian one")
+        self.bf16 = bf16
         if kind == "srht":
             if n & (n - 1):
                 raise ValueError("SRHT sketch needs n to be a power of two")
@@ -83,6 +106,8 @@ class Sketch:
 
     def block(self, j0: int, j1: int) -> np.ndarray:
         if self.kind == "gaussian":
+            if self.bf16:  # S = BF16(G) / sqrt(s): the normals are rounded, the scale is not
+                return to_bf16(gaussian_normals(self.s, j0, j1, self.seed)) / np.sqrt(self.s)
             return gaussian_block(self.s, j0, j1, self.seed)
         cols = np.arange(j0, j1)
         h = hadamard_entries(self.rows[:, None], cols[None, :])
@@ -93,6 +118,8 @@ class Sketch:
 
     def apply(self, x: np.ndarray) -> np.ndarray:
         x = np.asarray(x, dtype=np.float64)
+        if self.bf16:
+            x = x.astype(np.float32).astype(np.float64)
         out = np.zeros(self.s if x.ndim == 1 else (self.s, x.shape[1]))
         for j0 in range(0, self.n, self.chunk):
             j1 = min(self.n, j0 + self.chunk)

@@ -54,6 +54,7 @@ struct sa_seq {
   float *r32 = nullptr, *d32 = nullptr;  // mixed: inner right-hand side and correction
   long long *srht_rows = nullptr;
   unsigned long long *srht_signs = nullptr;  // SRHT sign words (one bit per row of x)
+  unsigned short *sketch_bf16 = nullptr;     // SA_MIXED Gaussian sketch: BF16 normals (MFMA push)
   Ctl *ctl = nullptr;     // device control block (projection + outer solve)
   Ctl *ctl_in = nullptr;  // device control block of the inner solves (mixed)
   int *hbuf = nullptr;    // pinned host mirror of solver state (128 ints; from int 64 on the
@@ -127,8 +128,14 @@ void srht_rows_host(int64_t n, int s, uint64_t seed, std::vector<long long> &out
 }
 
 struct Layout {
-  size_t X, SX, Q1, kry, partials, rows, signs, r32, d32, total;
+  size_t X, SX, Q1, kry, partials, rows, signs, r32, d32, gbf16, total;
 };
+
+// the mixed mode applies its Gaussian sketch in BF16 on the matrix cores, from normals
+// generated once into the workspace
+inline bool bf16_sketch(const sa_config *c) {
+  return c->precision == SA_MIXED && c->sketch == SA_SKETCH_GAUSSIAN;
+}
 
 int validate(const sa_config *c) {
   if (!c) return SA_EINVAL;
@@ -188,6 +195,11 @@ Layout layout(const sa_config *c) {
     off += up(ld * sizeof(float));
     L.d32 = off;
     off += up(ld * sizeof(float));
+  }
+  L.gbf16 = 0;
+  if (bf16_sketch(c)) {
+    L.gbf16 = off;
+    off += up((size_t)sketch_bf16_rows(c->s) * (size_t)sketch_bf16_ld(c->n) * sizeof(unsigned short));
   }
   L.total = off;
   return L;
@@ -645,6 +657,7 @@ int sa_init_sequence(const sa_config *cfg, void *dev_ws, size_t ws_bytes, void *
     q->r32 = (float *)(q->ws + L.r32);
     q->d32 = (float *)(q->ws + L.d32);
   }
+  if (bf16_sketch(cfg)) q->sketch_bf16 = (unsigned short *)(q->ws + L.gbf16);
   bool ok = hipHostMalloc((void **)&q->hbuf, 128 * sizeof(int), hipHostMallocDefault) == hipSuccess;
   for (int e = 0; ok && e < 4; ++e) ok = hipEventCreate(&q->ev[e]) == hipSuccess;
   if (ok) ok = hipEventCreateWithFlags(&q->ev_poll, hipEventDisableTiming) == hipSuccess;
@@ -661,6 +674,7 @@ int sa_init_sequence(const sa_config *cfg, void *dev_ws, size_t ws_bytes, void *
   if (!rows.empty())
     e = hipMemcpyAsync(q->srht_rows, rows.data(), rows.size() * sizeof(long long), hipMemcpyHostToDevice, st);
   if (e == hipSuccess && cfg->sketch == SA_SKETCH_SRHT) e = launch_srht_signs(q->srht_signs, cfg->n, cfg->seed, st);
+  if (e == hipSuccess && q->sketch_bf16) e = launch_gen_sketch_bf16(q->sketch_bf16, cfg->n, cfg->s, cfg->seed, st);
   const size_t w = q->x32 ? sizeof(float) : sizeof(double);
   if (e == hipSuccess) e = hipMemsetAsync(q->X, 0, (size_t)q->ld * cfg->M * w, st);
   if (e == hipSuccess) e = hipMemsetAsync(q->SX, 0, (size_t)cfg->s * cfg->M * sizeof(double), st);
@@ -717,7 +731,10 @@ ZRows zrows_push(sa_seq *q) {
 int push_enqueue(sa_seq *q, const void *x_dev, int zero_rhs, hipStream_t st) {
   const sa_config &c = q->cfg;
   const int slot = (int)(q->pushes % c.M);
-  if (q->x32)
+  if (q->sketch_bf16)
+    HIP_TRY(launch_push_bf16<float>((const double *)x_dev, (float *)q->X, q->sketch_bf16, q->SX, c.n, q->ld, slot,
+                                    c.s, q->partials, q->ctl, zero_rhs, st));
+  else if (q->x32)
     HIP_TRY(launch_push<float>((const double *)x_dev, (float *)q->X, q->SX, c.n, q->ld, slot, c.s, c.sketch, c.seed,
                                q->srht_rows, q->srht_signs, q->partials, q->ctl, zero_rhs, st));
   else

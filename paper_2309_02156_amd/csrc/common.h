@@ -95,6 +95,20 @@ inline int stream_blocks(int64_t n) {
   return (int)(b > MAXBLK ? MAXBLK : b);
 }
 
+// Blocks of `kernel` with `threads` threads the device holds at once (0 when the runtime
+// cannot say); `cache` is the caller's per-kernel slot, filled on the first call.
+inline int resident_blocks(const void *kernel, int threads, int &cache) {
+  if (cache == 0) {
+    int dev = 0, ncu = 0, per = 0;
+    if (hipGetDevice(&dev) != hipSuccess ||
+        hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
+        hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, kernel, threads, 0) != hipSuccess || per < 1)
+      return 0;
+    cache = per * ncu;
+  }
+  return cache;
+}
+
 // grid-stride loop over rows
 #define GRID_ROWS(i, n) \
   for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < (n); i += (int64_t)gridDim.x * blockDim.x)
@@ -590,8 +604,10 @@ __device__ inline double tile_spmv(const int *__restrict__ rowptr, const int *__
 // so that lane l's k-th gather sits next to lane l+1's whenever neighbouring rows have
 // neighbouring columns (a stencil): a gather instruction then touches two or three
 // cache lines instead of one per row it crosses.  Each lane adds its row's products in
-// column order.  Tiles with more than WT_CAP nonzeros read their rows directly.
-// `gx(c)` returns the source vector's entry c (double, or the vector's own type).
+// column order, each product rounded before it is added (no fused multiply-add, the
+// rounding of a plain CSR product loop).  Tiles with more than WT_CAP nonzeros read
+// their rows directly.  `gx(c)` returns the source vector's entry c (double, or the
+// vector's own type).
 constexpr int WT_CAP = 512;  // nonzeros of one wave tile staged in LDS
 constexpr int NXCD = 8;      // accelerator complex dies (each with its own L2) of the MI355X
 
@@ -699,11 +715,11 @@ __device__ inline void wave_tiles_spmv(const int *__restrict__ rowptr, const int
         for (int u = 0; u < C; ++u) x[u] = gx(c[u]);
 #pragma unroll
         for (int u = 0; u < C; ++u)
-          if (k0 + u < len) s += (double)v[u] * (double)x[u];
+          if (k0 + u < len) s += __dmul_rn((double)v[u], (double)x[u]);
       }
       wave_lds_sync();  // the slices are rewritten by the wave's next tile
     } else {
-      for (int pp = a; pp < a + len; ++pp) s += (double)val[pp] * (double)gx(col[pp]);
+      for (int pp = a; pp < a + len; ++pp) s += __dmul_rn((double)val[pp], (double)gx(col[pp]));
     }
     if (i < n) epi(i, own, s);
     if (!more) break;

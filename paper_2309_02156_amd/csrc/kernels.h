@@ -28,6 +28,17 @@ hipError_t launch_push(const double *x, TX *X, double *SX, int64_t n, int64_t ld
                        uint64_t seed, const long long *srht_rows, const unsigned long long *srht_signs,
                        double *partials, const Ctl *ctl, int zero_rhs, hipStream_t st);
 
+// BF16 Gaussian sketch (mixed mode): G = BF16(normals), s rounded up to 16 rows of
+// sketch_bf16_ld(n) entries, generated once; the push streams it through the matrix
+// cores and leaves the same partial rows as launch_push (scale 1 / sqrt(s) applied by
+// the reduction)
+int64_t sketch_bf16_ld(int64_t n);
+int sketch_bf16_rows(int s);
+hipError_t launch_gen_sketch_bf16(unsigned short *G, int64_t n, int s, uint64_t seed, hipStream_t st);
+template <typename TX>
+hipError_t launch_push_bf16(const double *x, TX *X, const unsigned short *G, double *SX, int64_t n, int64_t ld,
+                            int slot, int s, double *partials, const Ctl *ctl, int zero_rhs, hipStream_t st);
+
 // the SRHT sign words of a sequence (ceil(n / 64) words), once at creation
 hipError_t launch_srht_signs(unsigned long long *words, int64_t n, uint64_t seed, hipStream_t st);
 

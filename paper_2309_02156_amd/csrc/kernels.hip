@@ -41,24 +41,57 @@ __device__ inline void wave_sync() {
 
 
 // ============================================================================ SpMV
-template <typename VT>
+// Wave tiles of 64 rows (the CG kernels' scheme): columns / values staged coalesced in
+// LDS, each lane gathers along its own row.  C: gathers per lane and step.
+template <typename VT, int C>
 __global__ __launch_bounds__(TPB) void k_spmv(const int *rowptr, const int *col, const VT *val,
                                               const double *x, double *y, int64_t n) {
-  __shared__ double prod[SPMV_CAP];
-  for (int64_t r0 = (int64_t)blockIdx.x * TPB; r0 < n; r0 += (int64_t)gridDim.x * TPB) {
-    const double s = tile_spmv<TPB>(rowptr, col, val, x, n, r0, prod);
-    if (r0 + threadIdx.x < n) y[r0 + threadIdx.x] = s;
-  }
+  __shared__ int lcol[NWAVE * WT_CAP];
+  __shared__ VT lval[NWAVE * WT_CAP];
+  const int wid = threadIdx.x / WAVE;
+  const WaveTiles wt = wave_tiles(n);
+  wave_tiles_spmv<C>(
+      rowptr, col, val, Gather1<double>{x}, n, wt.t, wt.end, wt.step, lcol + wid * WT_CAP, lval + wid * WT_CAP,
+      [&](int64_t) { return 0.0; }, [&](int64_t i, double, double s) { y[i] = s; });
+}
+
+// grid of a wave-tile streaming kernel: one tile per wave up to what the device holds
+// at once, at most cap blocks (MAXBLK when the runtime cannot say)
+static int wave_grid(const void *kernel, int64_t n, int &cache, int cap) {
+  const int res = resident_blocks(kernel, TPB, cache);
+  return wave_tile_blocks(n, TPB, res > 0 ? (res < cap ? res : cap) : MAXBLK);
+}
+
+// partial rows of 2 entries the mixed-mode residual may leave (the Krylov partials
+// buffer holds far more)
+constexpr int IR_MAXBLK = 4096;
+
+template <typename VT, int C>
+static void spmv_c(const CsrView &A, const double *x, double *y, hipStream_t st) {
+  static int cache = 0;
+  const int nb = wave_grid((const void *)k_spmv<VT, C>, A.n, cache, 1 << 16);
+  // stand-ins for a matrix without nonzeros (one entry is read, never used)
+  const int *colp = A.nnz > 0 ? A.col : A.rowptr;
+  const VT *valp = A.nnz > 0 ? (const VT *)A.val : (const VT *)x;
+  hipLaunchKernelGGL((k_spmv<VT, C>), dim3(nb), dim3(TPB), 0, st, A.rowptr, colp, valp, x, y, A.n);
+}
+
+template <typename VT>
+static void spmv_vt(const CsrView &A, const double *x, double *y, hipStream_t st) {
+  const int C = wave_tile_chunk(A.n, A.nnz);
+  if (C <= 5)
+    spmv_c<VT, 5>(A, x, y, st);
+  else if (C <= 7)
+    spmv_c<VT, 7>(A, x, y, st);
+  else
+    spmv_c<VT, 9>(A, x, y, st);
 }
 
 hipError_t launch_spmv(const CsrView &A, const double *x, double *y, hipStream_t st) {
-  int nb = stream_blocks(A.n);
   if (A.fp32)
-    hipLaunchKernelGGL(k_spmv<float>, dim3(nb), dim3(TPB), 0, st, A.rowptr, A.col, (const float *)A.val, x,
-                       y, A.n);
+    spmv_vt<float>(A, x, y, st);
   else
-    hipLaunchKernelGGL(k_spmv<double>, dim3(nb), dim3(TPB), 0, st, A.rowptr, A.col, (const double *)A.val, x,
-                       y, A.n);
+    spmv_vt<double>(A, x, y, st);
   return hipGetLastError();
 }
 
@@ -145,6 +178,163 @@ hipError_t launch_push(const double *x, TX *X, double *SX, int64_t n, int64_t ld
   else
     hipLaunchKernelGGL((k_push<1, TX>), dim3(nbx, ng), dim3(TPB), 0, st, x, X, SX, n, ld, slot, s, seed,
                        srht_rows, srht_signs, partials, ctl, zero_rhs);
+  return hipGetLastError();
+}
+
+// ============================================================================ BF16 sketch (MFMA)
+// The mixed mode's Gaussian sketch is applied in BF16 on the matrix cores: the normals
+// G (s x n, the same Philox / Box-Muller entries as the FP64 sketch) are generated once
+// per sequence, rounded FP64 -> FP32 -> BF16 (nearest even) and kept in HBM, rows padded
+// to a multiple of 16 and columns to a multiple of 64 with zeros; a push streams them.
+// S = BF16(G) / sqrt(s): the scale is applied where the push partials are reduced.
+__device__ inline unsigned short bf16_bits(float f) {
+  unsigned u = __float_as_uint(f);
+  u += 0x7FFFu + ((u >> 16) & 1u);  // round to nearest, ties to even (finite values)
+  return (unsigned short)(u >> 16);
+}
+
+__global__ __launch_bounds__(TPB) void k_gen_sketch_bf16(unsigned short *G, int64_t n, int64_t lds, int s, int spad,
+                                                         uint64_t seed) {
+  const int nq = spad / 4;
+  GRID_ROWS(e, lds * nq) {
+    const int64_t j = e % lds;
+    const int q = (int)(e / lds);
+    double g[4] = {0.0, 0.0, 0.0, 0.0};
+    if (j < n && 4 * q < s) normals4((uint64_t)j, (uint64_t)q, STREAM_GAUSS_SKETCH, seed, g);
+#pragma unroll
+    for (int l = 0; l < 4; ++l) {
+      const int r = 4 * q + l;
+      G[(size_t)r * lds + j] = (r < s && j < n) ? bf16_bits((float)g[l]) : (unsigned short)0;
+    }
+  }
+}
+
+int64_t sketch_bf16_ld(int64_t n) { return (n + 63) / 64 * 64; }
+int sketch_bf16_rows(int s) { return (s + SKETCH_RG - 1) / SKETCH_RG * SKETCH_RG; }
+
+hipError_t launch_gen_sketch_bf16(unsigned short *G, int64_t n, int s, uint64_t seed, hipStream_t st) {
+  const int64_t lds = sketch_bf16_ld(n);
+  const int spad = sketch_bf16_rows(s);
+  hipLaunchKernelGGL(k_gen_sketch_bf16, dim3(stream_blocks(lds * (spad / 4))), dim3(TPB), 0, st, G, n, lds, s, spad,
+                     seed);
+  return hipGetLastError();
+}
+
+typedef short s4v __attribute__((ext_vector_type(4)));
+typedef float f4v __attribute__((ext_vector_type(4)));
+
+// Push with the BF16 sketch.  Grid (nbx, ceil(s / 16)) as k_push, the same partial rows.
+// A wave takes chunks of 64 entries, PU of them per round (their loads issued together);
+// per chunk four v_mfma_f32_16x16x16bf16_1k with A = G[16 rows of the group][16 entries]
+// and B = the chunk's FP32 column split exactly into three BF16 terms, hi, mid and lo
+// (each the BF16 rounding of what the previous ones leave), in B's columns 0, 1 and 2
+// (columns 3..15 zero): D[:, 0..2] hold the 16 rows' sums of the three terms.  Operand
+// layout: A[i][4 kq + e] from lane i + 16 kq, B[4 kq + e][j] from lane j + 16 kq
+// (e = 0..3, the four 16-bit halves of the operand), D[4 kq + v][j] in lane j + 16 kq,
+// element v.  In MFMA m of a chunk, k slot 4 kq + e is the chunk's entry 16 kq + 4 m + e.
+// D is added into FP64 after every chunk (64 exact products per FP32 sum), the three
+// columns when the block's partial row is formed.  The stored column X[:, slot] = TX(x)
+// is written by row group 0; the FP32 values reach the B lanes through the wave's LDS.
+template <typename TX>
+__global__ __launch_bounds__(TPB) void k_push_bf16(const double *x, TX *X, const unsigned short *G, int64_t n,
+                                                   int64_t ld, int64_t lds, int slot, int s, double *partials,
+                                                   const Ctl *ctl, int zero_rhs) {
+  constexpr int PU = 4;
+  __shared__ __align__(16) float xf[NWAVE * PU * WAVE];
+  __shared__ double red[NWAVE * 3 * SKETCH_RG];
+  const int g = blockIdx.y, r0 = g * SKETCH_RG;
+  const int rc = (s - r0) < SKETCH_RG ? (s - r0) : SKETCH_RG;
+  const int lane = threadIdx.x % WAVE, wid = threadIdx.x / WAVE;
+  const int i16 = lane % 16, kq = lane / 16;
+  float *xw = xf + wid * PU * WAVE;
+  const bool zero = zero_rhs && ctl->state == ST_ZERO_RHS;
+  double accd[4] = {0.0, 0.0, 0.0, 0.0};
+  const int64_t nch = (n + WAVE - 1) / WAVE;  // chunks of 64 entries
+  const int64_t wstep = (int64_t)gridDim.x * NWAVE * PU;
+  const unsigned short *grow = G + (size_t)(r0 + i16) * lds + 16 * kq;
+  for (int64_t c0 = ((int64_t)blockIdx.x * NWAVE + wid) * PU; c0 < nch; c0 += wstep) {
+    uint4 av[PU][2];
+    double xv[PU];
+#pragma unroll
+    for (int u = 0; u < PU; ++u) {
+      // chunks past the end re-read the last one (their B operand is zero)
+      const int64_t ch = c0 + u < nch ? c0 + u : nch - 1;
+      const uint4 *ap = (const uint4 *)(grow + ch * WAVE);
+      av[u][0] = ap[0];
+      av[u][1] = ap[1];
+      const int64_t j = (c0 + u) * WAVE + lane;
+      xv[u] = x[j < n ? j : n - 1];
+    }
+#pragma unroll
+    for (int u = 0; u < PU; ++u) {
+      const int64_t j = (c0 + u) * WAVE + lane;
+      const bool in = j < n;
+      const TX xs = (zero || !in) ? (TX)0 : (TX)xv[u];
+      if (g == 0 && in) X[(size_t)slot * ld + j] = xs;
+      xw[u * WAVE + lane] = (float)xs;
+    }
+    wave_lds_sync();
+#pragma unroll
+    for (int u = 0; u < PU; ++u) {
+      // this lane's B operand: term i16 (< 3) of 16 entries from 16 kq on
+      unsigned bw[8];
+      const float4 *bp = (const float4 *)(xw + u * WAVE + 16 * kq);
+#pragma unroll
+      for (int h = 0; h < 4; ++h) {
+        const float4 f = bp[h];
+        const float fv[4] = {f.x, f.y, f.z, f.w};
+        unsigned short t[4];
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+          const unsigned short hi = bf16_bits(fv[e]);
+          const float r1 = fv[e] - __uint_as_float((unsigned)hi << 16);
+          const unsigned short mid = bf16_bits(r1);
+          const float r2 = r1 - __uint_as_float((unsigned)mid << 16);
+          const unsigned short lo = bf16_bits(r2);  // exact: r2 has at most 8 significant bits
+          t[e] = i16 == 0 ? hi : (i16 == 1 ? mid : (i16 == 2 ? lo : (unsigned short)0));
+        }
+        bw[2 * h] = (unsigned)t[0] | ((unsigned)t[1] << 16);
+        bw[2 * h + 1] = (unsigned)t[2] | ((unsigned)t[3] << 16);
+      }
+      f4v d = {0.0f, 0.0f, 0.0f, 0.0f};
+#pragma unroll
+      for (int m = 0; m < 4; ++m) {
+        const uint4 &aw = av[u][m / 2];
+        const unsigned a0 = (m & 1) ? aw.z : aw.x, a1 = (m & 1) ? aw.w : aw.y;
+        const unsigned b0 = bw[2 * m], b1 = bw[2 * m + 1];
+        const s4v a = {(short)(a0 & 0xFFFFu), (short)(a0 >> 16), (short)(a1 & 0xFFFFu), (short)(a1 >> 16)};
+        const s4v b = {(short)(b0 & 0xFFFFu), (short)(b0 >> 16), (short)(b1 & 0xFFFFu), (short)(b1 >> 16)};
+        d = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, b, d, 0, 0, 0);
+      }
+#pragma unroll
+      for (int v = 0; v < 4; ++v) accd[v] += (double)d[v];
+    }
+    wave_lds_sync();  // the slice is rewritten in the next round
+  }
+  // lanes j + 16 kq (j < 3: column j of D) hold rows 4 kq .. 4 kq + 3 of term j; the block
+  // adds the waves' rows in wave order, the three terms of a wave in order
+  if (i16 < 3) {
+#pragma unroll
+    for (int v = 0; v < 4; ++v) red[(wid * 3 + i16) * SKETCH_RG + 4 * kq + v] = accd[v];
+  }
+  __syncthreads();
+  const int blk = blockIdx.y * gridDim.x + blockIdx.x;
+  if (threadIdx.x < rc) {
+    double a = 0.0;
+    for (int w = 0; w < NWAVE; ++w)
+      for (int j = 0; j < 3; ++j) a += red[(w * 3 + j) * SKETCH_RG + threadIdx.x];
+    partials[(size_t)blk * SKETCH_RG + threadIdx.x] = a;
+  }
+}
+
+template <typename TX>
+hipError_t launch_push_bf16(const double *x, TX *X, const unsigned short *G, double *SX, int64_t n, int64_t ld,
+                            int slot, int s, double *partials, const Ctl *ctl, int zero_rhs, hipStream_t st) {
+  (void)SX;
+  const int ng = (s + SKETCH_RG - 1) / SKETCH_RG;
+  const int nbx = push_blocks_x(n, s);
+  hipLaunchKernelGGL((k_push_bf16<TX>), dim3(nbx, ng), dim3(TPB), 0, st, x, X, G, n, ld, sketch_bf16_ld(n), slot, s,
+                     partials, ctl, zero_rhs);
   return hipGetLastError();
 }
 
@@ -1327,24 +1517,47 @@ hipError_t launch_to_double(const TX *x, double *y, int64_t n, hipStream_t st) {
 // Outer residual of the mixed mode: r = b - A32 x in FP64 (the FP32 matrix values are
 // exact in FP64), the inner right-hand side r32 = fl32(r), and partial sums of
 // ||r||^2 and ||b||^2.
-template <typename VT>
+template <typename VT, int C>
 __global__ __launch_bounds__(TPB) void k_ir_resid(const int *rowptr, const int *col, const VT *val,
                                                   const double *b, const double *x, float *r32, int64_t n,
                                                   double *partials) {
   __shared__ double red[NWAVE * 2];
-  __shared__ double prod[SPMV_CAP];
+  __shared__ int lcol[NWAVE * WT_CAP];
+  __shared__ VT lval[NWAVE * WT_CAP];
+  const int wid = threadIdx.x / WAVE;
   double acc[2] = {0.0, 0.0};
-  for (int64_t r0 = (int64_t)blockIdx.x * TPB; r0 < n; r0 += (int64_t)gridDim.x * TPB) {
-    const double ax = tile_spmv<TPB>(rowptr, col, val, x, n, r0, prod);
-    const int64_t i = r0 + threadIdx.x;
-    if (i < n) {
-      const double bi = b[i], ri = bi - ax;
-      r32[i] = (float)ri;
-      acc[0] += ri * ri;
-      acc[1] += bi * bi;
-    }
-  }
+  const WaveTiles wt = wave_tiles(n);
+  wave_tiles_spmv<C>(
+      rowptr, col, val, Gather1<double>{x}, n, wt.t, wt.end, wt.step, lcol + wid * WT_CAP, lval + wid * WT_CAP,
+      [&](int64_t i) { return b[i]; },
+      [&](int64_t i, double bi, double ax) {
+        const double ri = bi - ax;
+        r32[i] = (float)ri;
+        acc[0] += ri * ri;
+        acc[1] += bi * bi;
+      });
   block_sum_store<2>(acc, 2, red, partials + (size_t)blockIdx.x * 2);
+}
+
+template <typename VT, int C>
+static int ir_resid_c(const CsrView &A, const double *b, const double *x, float *r32, double *partials,
+                      hipStream_t st) {
+  static int cache = 0;
+  const int nb = wave_grid((const void *)k_ir_resid<VT, C>, A.n, cache, IR_MAXBLK);
+  const int *colp = A.nnz > 0 ? A.col : A.rowptr;
+  const VT *valp = A.nnz > 0 ? (const VT *)A.val : (const VT *)x;
+  hipLaunchKernelGGL((k_ir_resid<VT, C>), dim3(nb), dim3(TPB), 0, st, A.rowptr, colp, valp, b, x, r32, A.n,
+                     partials);
+  return nb;
+}
+
+template <typename VT>
+static int ir_resid_vt(const CsrView &A, const double *b, const double *x, float *r32, double *partials,
+                       hipStream_t st) {
+  const int C = wave_tile_chunk(A.n, A.nnz);
+  if (C <= 5) return ir_resid_c<VT, 5>(A, b, x, r32, partials, st);
+  if (C <= 7) return ir_resid_c<VT, 7>(A, b, x, r32, partials, st);
+  return ir_resid_c<VT, 9>(A, b, x, r32, partials, st);
 }
 
 // One block: the outer stopping test ||r|| <= tol ||b|| (first sweep also sets ||b||
@@ -1376,13 +1589,8 @@ __global__ __launch_bounds__(TPB) void k_ir_update(double *x, const float *d, in
 
 hipError_t launch_ir_resid(const CsrView &A, const double *b, const double *x, float *r32, double *partials,
                            int sweep, int max_refine, Ctl *ctl, hipStream_t st) {
-  const int nb = stream_blocks(A.n);
-  if (A.fp32)
-    hipLaunchKernelGGL(k_ir_resid<float>, dim3(nb), dim3(TPB), 0, st, A.rowptr, A.col, (const float *)A.val, b,
-                       x, r32, A.n, partials);
-  else
-    hipLaunchKernelGGL(k_ir_resid<double>, dim3(nb), dim3(TPB), 0, st, A.rowptr, A.col, (const double *)A.val,
-                       b, x, r32, A.n, partials);
+  const int nb = A.fp32 ? ir_resid_vt<float>(A, b, x, r32, partials, st)
+                        : ir_resid_vt<double>(A, b, x, r32, partials, st);
   hipLaunchKernelGGL(k_ir_close, dim3(1), dim3(TPB), 0, st, partials, nb, sweep, max_refine, ctl);
   return hipGetLastError();
 }
@@ -1426,6 +1634,8 @@ hipError_t launch_zero(double *x, int64_t n, hipStream_t st) {
 }
 
 #define SACC_INSTANTIATE_PROJ(TX)                                                                              \
+  template hipError_t launch_push_bf16<TX>(const double *, TX *, const unsigned short *, double *, int64_t,       \
+                                           int64_t, int, int, double *, const Ctl *, int, hipStream_t);           \
   template hipError_t launch_push<TX>(const double *, TX *, double *, int64_t, int64_t, int, int, int, uint64_t, \
                                       const long long *, const unsigned long long *, double *, const Ctl *, int, \
                                       hipStream_t);                                                            \

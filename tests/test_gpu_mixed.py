@@ -2,13 +2,18 @@
 emulation of it (``oracle.mixed``, ``oracle.sequence`` with precision="mixed").
 
 Bar: both sides reach the FP64 tolerance against the float32-valued operator after
-refinement; per step the iteration counts agree within one per refinement sweep for CG;
+refinement; per step the iteration counts agree within one per refinement sweep for CG
+(within twice the oracle's own change under a rounding-only perturbation where that
+change is not zero);
 for float32 GMRES(30), whose count moves by tens of iterations under a rounding-only
 change on the oracle side alone, within 2% or twice the oracle's own change under a
 rounding-only perturbation (reversed summation order in A x);
 the guesses agree far below the tolerance unless the float32 rounding of the basis
 flips a last bit, so their difference is bounded by 1e-2 tol ||b|| plus 1e-3 of the
-oracle guess's own residual.  The difference of the final solutions is printed per step.
+oracle guess's own residual; with the BF16 sketch (the "mixed" mode's Gaussian sketch)
+the two sides' S X differ by FP32 accumulation and their float32 bases round apart, so
+10 times the oracle guess's change under a relative 1e-7 perturbation of its S X is
+added.  The difference of the final solutions is printed per step.
 """
 
 import math
@@ -71,7 +76,18 @@ def test_mixed_stepwise(sacc, k, N, steps, prec):
         ores0 = np.linalg.norm(b - As @ g.x0) / bn
         dres = np.linalg.norm(As @ (x0 - g.x0)) / bn
         assert ginfo["k_sketch"] == g.k and ginfo["k_eff"] == g.k2, (i, ginfo, g.k, g.k2)
-        assert dres <= 1e-2 * m["tol"] + 1e-3 * ores0, (i, dres, ores0)
+        gspread = 0.0
+        if prec == "mixed" and m["sketch"] == "gaussian" and g.k > 0:
+            # BF16 sketch: the GPU's S X is the oracle's up to FP32 accumulation (relative
+            # 2e-7 seen), so the two sides' float32 bases round apart; the oracle's own
+            # guess under a relative 1e-7 perturbation of its S X calibrates that
+            Xo_, SXo_ = oseq.history()
+            rng = np.random.default_rng(100 + i)
+            SXp = SXo_ * (1.0 + 1e-7 * rng.standard_normal(SXo_.shape))
+            gp = obs.initial_guess(As, b, Xo_, SXp, None, oseq.projection, oseq.solver == "cg", oseq.tau_s,
+                                   oseq.tau_c, oseq.store)
+            gspread = float(np.linalg.norm(As @ (gp.x0 - g.x0)) / bn)
+        assert dres <= 1e-2 * m["tol"] + 1e-3 * ores0 + 10 * gspread, (i, dres, ores0, gspread)
         xo, oinfo = oseq.solve(As, b, g.x0)
         xd, sinfo = gseq.solve(Ad, dev(b), dev(g.x0))
         xg = host(xd)
@@ -80,17 +96,20 @@ def test_mixed_stepwise(sacc, k, N, steps, prec):
         assert oinfo["relres"] <= m["tol"]
         sweeps = max(sinfo["refinements"], oinfo["refinements"], 1)
         assert abs(sinfo["refinements"] - oinfo["refinements"]) <= 1, (i, sinfo, oinfo)
+        # the oracle's own count under a rounding-only change (reversed summation order
+        # in A x) calibrates the allowance where it moves
+        _, oinfo2 = oseq.solve(reversed_order(As), b, g.x0)
+        spread = abs(oinfo2["iters"] - oinfo["iters"])
         if m["solver"] == "cg":
             # one iteration per refinement sweep: both sides start every sweep from the
-            # same FP64 residual up to rounding
-            allowed = sweeps
-            spread = 0
+            # same FP64 residual up to rounding; where the oracle itself moves (an inner
+            # solve ending next to the tolerance: 229 against 212 iterations at step 2 of
+            # the 48 x 48 sequence), twice that change
+            allowed = max(sweeps, 2 * spread + 1) if spread > 0 else sweeps
         else:
             # float32 GMRES(30) with capped cycles: the oracle's own count moves by tens
-            # of iterations under a rounding-only change (reversed summation order in
-            # A x), so the allowance is calibrated by that change
-            _, oinfo2 = oseq.solve(reversed_order(As), b, g.x0)
-            spread = abs(oinfo2["iters"] - oinfo["iters"])
+            # of iterations under a rounding-only change, so the allowance is calibrated by
+            # that change
             allowed = max(sweeps, 2 * spread + 1, math.ceil(0.02 * oinfo["iters"]))
         assert abs(sinfo["iters"] - oinfo["iters"]) <= allowed, (i, sinfo["iters"], oinfo["iters"], spread)
         rows.append((i, sinfo["iters"], oinfo["iters"], sinfo["refinements"], oinfo["refinements"],

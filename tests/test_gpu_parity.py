@@ -123,6 +123,40 @@ def test_push_sketch_parity(sacc, kind, n, s):
         assert np.all(np.abs(SX[:, slot] - ref) <= 1e-13 * scale)
 
 
+@pytest.mark.parametrize("n,s", [(4096, 20), (1000, 24), (300000, 60), (1, 16)])
+def test_push_sketch_parity_bf16(sacc, n, s):
+    """Mixed mode, Gaussian sketch: S = BF16(G) / sqrt(s) applied to the FP32 column on
+    the matrix cores (split exactly into three BF16 terms).  The products are exact on
+    both sides; the GPU adds each chunk's 64 products of a term in FP32 (error at most
+    63 u of their absolute sum, u = 2^-24) and chunks and terms in FP64; the terms'
+    absolute values add up to at most (1 + 2^-7) |x|, so every entry is within
+    65 u sum_j |S_rj x_j| of the oracle's exact sum."""
+    print_case("sketch bf16", n, s)
+    rng = np.random.default_rng(3)
+    M = 6
+    seq = sacc.Sequence(n, M, s=s, sketch="gaussian", seed=11, precision="mixed")
+    S = Sketch("gaussian", n, s, 11, bf16=True)
+    xs = [rng.standard_normal(n) * 10.0 ** rng.integers(-3, 3) for _ in range(M + 2)]
+    for x in xs:
+        seq.push(dev(x))
+    SX = seq.copy_state("SX")
+    order = seq.copy_state("order")
+    X = seq.copy_state("X")
+    X32 = np.stack([xs[len(xs) - M + lag].astype(np.float32) for lag in range(M)], 1)
+    Xb = X32.astype(np.float64)
+    ref, absum = np.zeros((s, M)), np.zeros((s, M))
+    for j0 in range(0, n, S.chunk):
+        B = S.block(j0, min(n, j0 + S.chunk))
+        ref += B @ Xb[j0:j0 + B.shape[1]]
+        absum += np.abs(B) @ np.abs(Xb[j0:j0 + B.shape[1]])
+    bound = 65 * 2.0 ** -24 * absum
+    for lag, slot in enumerate(order):
+        assert np.array_equal(X[:, slot], X32[:, lag])
+        err = np.abs(SX[:, slot] - ref[:, lag])
+        print_case("max err / bound", float(np.max(err / np.maximum(bound[:, lag], 1e-300))))
+        assert np.all(err <= bound[:, lag])
+
+
 # ---------------------------------------------------------------------------- initial guess
 
 def _oracle_history(problem, method, steps):

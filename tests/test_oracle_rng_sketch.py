@@ -93,3 +93,53 @@ def test_subspace_embedding(kind):
     SU = S.apply(U)
     sv = np.linalg.svd(SU, compute_uv=False)
     assert sv.max() < 2.0 and sv.min() > 0.3
+
+
+def test_bf16_rounding_bit_patterns():
+    """FP32 -> BF16 round to nearest, ties to even, on hand-worked values: 1 + 2^-8 is
+    halfway between 1 and 1 + 2^-7 (tie -> even mantissa 1.0), 1 + 3 2^-8 is halfway
+    between 1 + 2^-7 and 1 + 2^-6 (tie -> even 1 + 2^-6), 1 + 2^-8 + 2^-20 rounds up,
+    and values already in BF16 stay."""
+    cases = {1.0 + 2.0 ** -8: 1.0, 1.0 + 3 * 2.0 ** -8: 1.0 + 2.0 ** -6, 1.0 + 2.0 ** -8 + 2.0 ** -20: 1.0 + 2.0 ** -7,
+             -(1.0 + 2.0 ** -8 + 2.0 ** -20): -(1.0 + 2.0 ** -7), 0.75: 0.75, 0.0: 0.0, 2.0 ** -130: 2.0 ** -130}
+    for v, want in cases.items():
+        assert sk.to_bf16(np.array([v]))[0] == want, v
+
+
+def test_bf16_rounding_matches_torch():
+    """Against torch's own float32 -> bfloat16 conversion (round to nearest even)."""
+    torch = pytest.importorskip("torch")
+    rng = np.random.default_rng(5)
+    v = np.concatenate([rng.standard_normal(20000) * 10.0 ** rng.integers(-8, 8, 20000),
+                        rng.standard_normal(1000).astype(np.float32).astype(np.float64)])
+    f32 = v.astype(np.float32)
+    ref = torch.from_numpy(f32).to(torch.bfloat16).to(torch.float64).numpy()
+    assert np.array_equal(sk.to_bf16(v), ref)
+
+
+def test_bf16_gaussian_sketch_is_the_rounded_sketch():
+    """The BF16 sketch applies BF16(G) / sqrt(s) to fl32(x): S x within the BF16 rounding
+    of G (relative 2^-8 bounds it) plus the FP32 rounding of x of the FP64 sketch; sqrt(s)
+    S holds BF16 values; and an FP32 value is exactly the sum of three BF16 terms taken by
+    successive rounding (the split the GPU feeds its matrix cores)."""
+    n, s = 3000, 24
+    rng = np.random.default_rng(2)
+    x = rng.standard_normal(n)
+    S64 = sk.Sketch("gaussian", n, s, 9)
+    Sb = sk.Sketch("gaussian", n, s, 9, bf16=True)
+    D = Sb.dense() * np.sqrt(s)
+    assert np.allclose(sk.to_bf16(D), D, rtol=1e-15, atol=0)
+    G = sk.gaussian_normals(s, 0, n, 9)
+    assert np.array_equal(sk.to_bf16(G) / np.sqrt(s), Sb.dense())
+    x32 = x.astype(np.float32).astype(np.float64)
+    assert np.allclose(Sb.apply(x), (sk.to_bf16(G) @ x32) / np.sqrt(s), rtol=1e-14, atol=1e-14)
+    bound = (2.0 ** -8 + 2.0 ** -23) * (np.abs(S64.dense()) @ np.abs(x))
+    assert np.all(np.abs(Sb.apply(x) - S64.apply(x)) <= bound)
+    v = np.concatenate([x, x * 1e-20, x * 1e20]).astype(np.float32).astype(np.float64)
+    hi = sk.to_bf16(v)
+    mid = sk.to_bf16(v - hi)
+    lo = v - hi - mid
+    assert np.array_equal(sk.to_bf16(lo), lo)
+    assert np.array_equal(hi + mid + lo, v)
+    with pytest.raises(ValueError):
+        sk.Sketch("srht", 4096, 16, 1, bf16=True)
