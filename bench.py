@@ -102,18 +102,18 @@ class Staged:
                              shape=(self.n, self.n))
 
 
-def make_seq(sacc, n, method, guess="projection", precision=None, precond="none"):
+def make_seq(sacc, n, method, guess="projection", precision=None, precond="none", **extra):
     return sacc.Sequence(n, method["M"], s=method["s"], sketch=method["sketch"], solver=method["solver"],
                          restart=method["restart"], tol=method["tol"], seed=method["method_seed"], guess=guess,
-                         precision=precision or method["prec"], precond=precond)
+                         precision=precision or method["prec"], precond=precond, **extra)
 
 
 def run_sequence(sacc, torch, st, method, fill, warmup, steps, guess="projection", precision=None, profile=False,
-                 keep_seq=False, precond="none"):
+                 keep_seq=False, precond="none", **extra):
     """Steps 0 .. fill + warmup + steps - 1; the last `steps` are timed.  Returns the
     infos of the timed steps, their wall time, the kernel records (profile=True) and the
     sequence (keep_seq=True: the caller closes it) with its last solution."""
-    seq = make_seq(sacc, st.n, method, guess, precision, precond)
+    seq = make_seq(sacc, st.n, method, guess, precision, precond, **extra)
     x = torch.empty(st.n, dtype=torch.float64, device="cuda")
     first = fill + warmup
     for i in range(first):
@@ -353,9 +353,38 @@ def paper4_cmp(sacc, torch, np):
             rec["previous"]["iters_per_step"] / max(rec["projection"]["iters_per_step"], 1e-9), 3)
         rec["time_ratio_previous_over_projection"] = round(
             rec["previous"]["ms_per_step"] / rec["projection"]["ms_per_step"], 3)
+        if dt >= 1e-3:
+            rec["table1"] = table1_sweep(sacc, torch, st, m, p.steps)
         out[f"dt={dt:g}"] = rec
         del st
     return out
+
+
+# the (M, m) pairs of the paper's Table 1
+TABLE1 = ((15, 6), (15, 8), (15, 10), (20, 10), (20, 15), (30, 8), (30, 12), (30, 15))
+
+
+def table1_sweep(sacc, torch, st, m, steps):
+    """Table 1's quantities for its (M, m) pairs on the Section 4 sequence: time and GMRES
+    iterations per step of the range-finder guess (Gaussian Z, redrawn every 50 pushes;
+    the paper's minimum-residual reduced problem; s = 2M) against the Baseline guess
+    x0 = x(t_{i-1}), all over the same steps 30..steps-1."""
+    fill = max(M for M, _ in TABLE1)
+    n_t = steps - fill
+    log(f"table1: {len(TABLE1)} (M, m) pairs on steps {fill}..{steps - 1}")
+    bi, bw, _ = run_sequence(sacc, torch, st, m, fill, 0, n_t, guess="previous")
+    base = summary(bi, bw, n_t)
+    rows = []
+    for M, mm in TABLE1:
+        meth = dict(m, M=M, s=2 * M)
+        ci, cw, _ = run_sequence(sacc, torch, st, meth, fill, 0, n_t, m=mm, projection="minres")
+        r = summary(ci, cw, n_t)
+        rows.append(dict(M=M, m=mm, ms_per_step=r["ms_per_step"], iters_per_step=r["iters_per_step"],
+                         time_speedup=round(base["ms_per_step"] / r["ms_per_step"], 3),
+                         iters_speedup=round(base["iters_per_step"] / max(r["iters_per_step"], 1e-9), 3),
+                         relres_max=r["relres_max"], k_eff=r["k_eff"]))
+    return dict(steps_timed=f"{fill}..{steps - 1}", baseline=dict(ms_per_step=base["ms_per_step"],
+                iters_per_step=base["iters_per_step"]), rows=rows)
 
 
 def learned_cmp(sacc, torch, np, n_train, n_eval, epochs=60, batch=32, n_hist=8):

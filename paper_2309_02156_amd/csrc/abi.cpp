@@ -864,8 +864,7 @@ static int solve_mixed(sa_seq *q, const CsrView &v, const double *b, double *x, 
     if (outer < ST_RUN || outer > ST_ZERO_RHS) return SA_EHIP;
     if (outer != ST_RUN || *iters >= c.maxit) {
       if (outer == ST_RUN) {  // iteration budget spent: report as not converged
-        const int st_maxit = ST_MAXIT;
-        HIP_TRY(hipMemcpyAsync(&q->ctl->state, &st_maxit, sizeof(int), hipMemcpyHostToDevice, st));
+        HIP_TRY(launch_set_int(&q->ctl->state, ST_MAXIT, st));
         HIP_TRY(hipStreamSynchronize(st));
         hs[0] = ST_MAXIT;
       }
@@ -873,7 +872,7 @@ static int solve_mixed(sa_seq *q, const CsrView &v, const double *b, double *x, 
     }
     // inner solve from d = 0 with the remaining iteration budget, at most inner_maxit
     hs[40] = c.maxit - *iters < inner_cap(c) ? c.maxit - *iters : inner_cap(c);
-    HIP_TRY(hipMemcpyAsync(&q->ctl_in->maxit, hs + 40, sizeof(int), hipMemcpyHostToDevice, st));
+    HIP_TRY(launch_set_int(&q->ctl_in->maxit, hs[40], st));
     HIP_TRY(hipMemsetAsync(q->d32, 0, (size_t)c.n * sizeof(float), st));
     SA_TRY(run_krylov<float>(q, v, q->ctl_in, q->r32, q->d32, hs[40], st));
     const int inner_state = hs[0];

@@ -189,6 +189,8 @@ hipError_t launch_learn_pick(const CsrView &A, const double *b, double *x0, cons
 // control block reset in device memory: every field zero, then the solver settings, the
 // initial state ST_CONV and no history (newest = -1); mirror and guess record unset
 hipError_t launch_ctl_reset(Ctl *ctl, double tol, int maxit, int restart, int trust_est, hipStream_t st);
+// *p = v in stream order, from a kernel (no host-side copy)
+hipError_t launch_set_int(int *p, int v, hipStream_t st);
 
 // x = 0 by a fill kernel
 hipError_t launch_zero(double *x, int64_t n, hipStream_t st);

@@ -1624,6 +1624,16 @@ hipError_t launch_ctl_reset(Ctl *ctl, double tol, int maxit, int restart, int tr
   return hipGetLastError();
 }
 
+// one word of device state set by a kernel (instead of a small host-to-device copy)
+__global__ void k_set_int(int *p, int v) {
+  if (threadIdx.x == 0) *p = v;
+}
+
+hipError_t launch_set_int(int *p, int v, hipStream_t st) {
+  hipLaunchKernelGGL(k_set_int, dim3(1), dim3(64), 0, st, p, v);
+  return hipGetLastError();
+}
+
 __global__ __launch_bounds__(TPB) void k_zero(double *x, int64_t n) {
   GRID_ROWS(i, n) x[i] = 0.0;
 }

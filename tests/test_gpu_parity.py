@@ -635,21 +635,24 @@ def test_export_import_resumes_bitwise(sacc, k, N, prec):
 
 # ---------------------------------------------------------------------------- range finder m < M
 
-@pytest.mark.parametrize("k,N,steps,m", [(0, 64, 16, 5), (1, 64, 24, 10)])
-def test_range_finder_compression(sacc, k, N, steps, m):
+@pytest.mark.parametrize("k,N,steps,m,proj", [(0, 64, 16, 5, "galerkin"), (1, 64, 24, 10, "galerkin"),
+                                              (1, 64, 24, 10, "minres")])
+def test_range_finder_compression(sacc, k, N, steps, m, proj):
     """The paper's randomized range finder with m < M (Section 2.2, Alg. 3): the basis
     spans X Z with the Gaussian Z whose rows travel with the history columns and a new Z
     every `refresh` pushes (7 here, so the run crosses several refreshes).  Same injected
     history on both sides: equal ranks; x0 element by element within 1e-12 of its largest
     entry (the oracle's own guess moves by at most 4.7e-14 of it when X, S X and Z are
     perturbed by 1e-16 relative: the Gaussian entries may differ in the last bits between
-    the device's and the host's log, sqrt and sincospi)."""
-    print_case("range finder", k, N, steps, m)
+    the device's and the host's log, sqrt and sincospi); with the minimum-residual
+    reduced problem (the Table 1 runs) within 1e-11, the bar of its own stepwise test."""
+    print_case("range finder", k, N, steps, m, proj)
     p, meth = config(k, N)
     sols = _oracle_history(p, meth, steps)
-    gseq = sacc.Sequence(p.n, **method_kwargs(meth, m=m, refresh=7))
+    gseq = sacc.Sequence(p.n, **method_kwargs(meth, m=m, refresh=7, projection=proj))
     oseq = OSeq(p.n, meth["M"], meth["sketch"], meth["s"], meth["method_seed"], meth["solver"], meth["restart"],
-                meth["tol"], m=m, refresh=7)
+                meth["tol"], m=m, refresh=7, projection=proj)
+    bar = X0_ELEMENTWISE if proj == "galerkin" else 1e-11
     worst = 0.0
     for i in range(steps):
         A = p.matrix(i)
@@ -663,7 +666,7 @@ def test_range_finder_compression(sacc, k, N, steps, m):
         if i > 0:
             ew = float(np.max(np.abs(x0 - g.x0)) / np.max(np.abs(g.x0)))
             worst = max(worst, ew)
-            assert ew <= X0_ELEMENTWISE, (i, ew)
+            assert ew <= bar, (i, ew)
         oseq.push(sols[i])
         gseq.push(dev(sols[i]))
     print_case("range finder worst max |dx0| / max |x0|", worst)
