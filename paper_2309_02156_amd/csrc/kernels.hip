@@ -239,7 +239,7 @@ template <typename TX>
 __global__ __launch_bounds__(TPB) void k_push_bf16(const double *x, TX *X, const unsigned short *G, int64_t n,
                                                    int64_t ld, int64_t lds, int slot, int s, double *partials,
                                                    const Ctl *ctl, int zero_rhs) {
-  constexpr int PU = 4;
+  constexpr int PU = 8;
   __shared__ __align__(16) float xf[NWAVE * PU * WAVE];
   __shared__ double red[NWAVE * 3 * SKETCH_RG];
   const int g = blockIdx.y, r0 = g * SKETCH_RG;
@@ -617,36 +617,76 @@ hipError_t launch_qrcp(double *SX, int s, int cnt, int newest, double tau, const
 }
 
 // ============================================================================ basis Q1 = X T1
+// A tall-skinny dense product on the matrix cores, formed transposed so that the stores
+// run along rows: Q1^T = T1^T X^T with v_mfma_f64_16x16x4f64, A = T1^T[16 basis columns]
+// [4 history columns] (lane i + 16 kq: basis column i, history column kq of the chunk;
+// read once per wave and kept in registers), B = X^T[4 history columns][16 rows]
+// (lane j + 16 kq: row j), D[kq + 4 v][j] (basis column kq + 4 v, row j) in lane
+// j + 16 kq: each store instruction writes 16 consecutive rows of four columns.
+// A wave takes RB blocks of 16 rows per round, all their X loads issued together.
+// Columns past cnt of X and past k of T1 are zero; Q1 is written for columns < k.
 template <int MC, typename TX>
 __global__ __launch_bounds__(TPB) void k_basis(const TX *X, TX *Q1, int64_t n, int64_t ld, int cnt,
                                                const Ctl *ctl) {
-  __shared__ double T[MC * MC];
+  constexpr int NL = MC / 4, NC = MC / 16, RB = 4;
   const int k = ctl->k;
-  for (int e = threadIdx.x; e < MC * MC; e += blockDim.x) {
-    const int l = e % MC, c = e / MC;
-    T[e] = (l < cnt && c < k) ? ctl->T1[l + c * MAXM] : 0.0;
-  }
-  __syncthreads();
-  GRID_ROWS(i, n) {
-    double xr[MC];
+  const int lane = threadIdx.x % WAVE, wid = threadIdx.x / WAVE;
+  const int i16 = lane % 16, kq = lane / 16;
+  double bop[NL][NC];
 #pragma unroll
-    for (int l = 0; l < MC; ++l) xr[l] = (l < cnt) ? (double)X[(size_t)l * ld + i] : 0.0;
-    for (int c = 0; c < k; ++c) {
-      double q = 0.0;
+  for (int lc = 0; lc < NL; ++lc)
 #pragma unroll
-      for (int l = 0; l < MC; ++l) q += xr[l] * T[l + c * MC];
-      Q1[(size_t)c * ld + i] = (TX)q;
+    for (int cb = 0; cb < NC; ++cb) {
+      const int l = 4 * lc + kq, c = 16 * cb + i16;
+      bop[lc][cb] = (l < cnt && c < k) ? ctl->T1[l + c * MAXM] : 0.0;
+    }
+  const int64_t nblk = (n + 15) / 16;
+  const int64_t step = (int64_t)gridDim.x * NWAVE * RB;
+  for (int64_t b0 = ((int64_t)blockIdx.x * NWAVE + wid) * RB; b0 < nblk; b0 += step) {
+    double aop[RB][NL];
+#pragma unroll
+    for (int r = 0; r < RB; ++r) {
+      const int64_t row = (b0 + r) * 16 + i16;
+      const int64_t rc = row < n ? row : n - 1;
+#pragma unroll
+      for (int lc = 0; lc < NL; ++lc) {
+        const int l = 4 * lc + kq;
+        const double v = (double)X[(size_t)(l < cnt ? l : 0) * ld + rc];
+        aop[r][lc] = (l < cnt && row < n) ? v : 0.0;
+      }
+    }
+#pragma unroll
+    for (int r = 0; r < RB; ++r) {
+#pragma unroll
+      for (int cb = 0; cb < NC; ++cb) {
+        d4 acc = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+        for (int lc = 0; lc < NL; ++lc) acc = __builtin_amdgcn_mfma_f64_16x16x4f64(bop[lc][cb], aop[r][lc], acc, 0, 0, 0);
+        const int64_t row = (b0 + r) * 16 + i16;
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+          const int c = 16 * cb + kq + 4 * v;
+          if (c < k && row < n) Q1[(size_t)c * ld + row] = (TX)acc[v];
+        }
+      }
     }
   }
 }
 
 template <typename TX>
 hipError_t launch_basis(const TX *X, TX *Q1, int64_t n, int64_t ld, int cnt, Ctl *ctl, hipStream_t st) {
-  const int nb = stream_blocks(n);
-  if (cnt <= 16)
-    hipLaunchKernelGGL((k_basis<16, TX>), dim3(nb), dim3(TPB), 0, st, X, Q1, n, ld, cnt, ctl);
-  else
-    hipLaunchKernelGGL((k_basis<32, TX>), dim3(nb), dim3(TPB), 0, st, X, Q1, n, ld, cnt, ctl);
+  static int cache16 = 0, cache32 = 0;
+  const int64_t waves = ((n + 15) / 16 + 3) / 4;  // rounds of 4 row blocks
+  int64_t want = (waves + NWAVE - 1) / NWAVE;
+  if (cnt <= 16) {
+    const int res = resident_blocks((const void *)k_basis<16, TX>, TPB, cache16);
+    if (res > 0 && want > res) want = res;
+    hipLaunchKernelGGL((k_basis<16, TX>), dim3(want < 1 ? 1 : want), dim3(TPB), 0, st, X, Q1, n, ld, cnt, ctl);
+  } else {
+    const int res = resident_blocks((const void *)k_basis<32, TX>, TPB, cache32);
+    if (res > 0 && want > res) want = res;
+    hipLaunchKernelGGL((k_basis<32, TX>), dim3(want < 1 ? 1 : want), dim3(TPB), 0, st, X, Q1, n, ld, cnt, ctl);
+  }
   return hipGetLastError();
 }
 
@@ -672,6 +712,8 @@ constexpr int GRAM_TPB = 256;
 constexpr int GRAM_NW = GRAM_TPB / WAVE;
 constexpr int GRAM_ROWS = 16;
 constexpr int GRAM_MAXBLK = 1024;
+constexpr int GRAM_STAGE = 128;  // nonzeros of a 16-row tile staged in LDS (longer tiles read directly)
+
 
 template <int KB, bool MR>
 struct GramShape {
@@ -694,13 +736,19 @@ __global__ __launch_bounds__(GRAM_TPB) void k_spmm_gram(const int *rowptr, const
                                                         const TX *Q1, const double *b, int64_t n, int64_t ld,
                                                         int cnt, double *partials, const Ctl *ctl) {
   using S = GramShape<KB, MR>;
-  constexpr int CPL = KB / 4, NA = S::NA, NWB = S::NWB, LDW = S::LDW, NZ = KB == 32 ? 2 : 4;
+  constexpr int CPL = KB / 4, NA = S::NA, NWB = S::NWB, LDW = S::LDW;
+  constexpr int SU = GRAM_STAGE / WAVE;  // staged nonzeros per lane
+  constexpr int GRAM_NZ = sizeof(TX) == 4 ? 4 : 2;  // nonzeros of a row whose gathers go out together
   __shared__ double lds[S::LDS];
+  __shared__ int scol[GRAM_NW * GRAM_STAGE];
+  __shared__ VT sval[GRAM_NW * GRAM_STAGE];
   const int k = ctl->k;
   const int lane = threadIdx.x % WAVE, wid = threadIdx.x / WAVE;
   const int rr = lane % 16, q = lane / 16;
   const int na = (k + 15) / 16, nwb = (k + 1 + 15) / 16;
   double *Wl = lds + (size_t)wid * GRAM_ROWS * LDW;
+  int *lc = scol + wid * GRAM_STAGE;
+  VT *lv = sval + wid * GRAM_STAGE;
   d4 accG[S::NG], accH[NA][NWB], accK[MR ? NA : 1][MR ? NWB : 1];
 #pragma unroll
   for (int e = 0; e < S::NG; ++e) accG[e] = (d4){0.0, 0.0, 0.0, 0.0};
@@ -717,41 +765,106 @@ __global__ __launch_bounds__(GRAM_TPB) void k_spmm_gram(const int *rowptr, const
   const int64_t tlo = (int64_t)(blockIdx.x % groups) * per;
   const int64_t thi = tlo + per < T ? tlo + per : T;
   const int64_t tstep = (int64_t)(gridDim.x / groups) * GRAM_NW;
-  for (int64_t t = tlo + (int64_t)(blockIdx.x / groups) * GRAM_NW + wid; k > 0 && t < thi; t += tstep) {
+  // Tile prefetch: the row pointers and the first GRAM_STAGE nonzeros (columns, values)
+  // of a tile, requested while the previous tile's Gram products run.  Loads are
+  // unconditional and in bounds (col / val hold at least one entry).
+  struct Pre {
+    int pa, pb, p0, p1;
+    int c[SU];
+    VT v[SU];
+  };
+  auto prefetch = [&](int64_t tt, Pre &f) {
+    const int64_t r0 = tt * GRAM_ROWS, row = r0 + rr;
+    const int64_t rc = row < n ? row : n - 1;
+    const int64_t rl = r0 + GRAM_ROWS < n ? r0 + GRAM_ROWS : n;
+    f.pa = rowptr[rc];
+    f.pb = rowptr[rc + 1];
+    f.p0 = rowptr[r0 < n ? r0 : n - 1];
+    f.p1 = rowptr[rl];
+    __builtin_amdgcn_sched_barrier(0);
+    const int p0 = __builtin_amdgcn_readfirstlane(f.p0), p1 = __builtin_amdgcn_readfirstlane(f.p1);
+#pragma unroll
+    for (int u = 0; u < SU; ++u) {
+      const int pp = p0 + u * WAVE + lane;
+      const int pc = pp < p1 ? pp : (p1 > 0 ? p1 - 1 : 0);
+      f.c[u] = col[(unsigned)pc];
+      f.v[u] = val[(unsigned)pc];
+    }
+  };
+  int64_t t = tlo + (int64_t)(blockIdx.x / groups) * GRAM_NW + wid;
+  Pre cur;
+  if (k > 0 && t < thi) prefetch(t, cur);
+  for (; k > 0 && t < thi; t += tstep) {
     const int64_t r0 = t * GRAM_ROWS, row = r0 + rr;
     const bool valid = row < n;
-    const int64_t rc = valid ? row : n - 1;
-    const int pa = rowptr[rc], pb = valid ? rowptr[rc + 1] : pa;
+    const int p0 = __builtin_amdgcn_readfirstlane(cur.p0), p1 = __builtin_amdgcn_readfirstlane(cur.p1);
+    const int pa = valid ? cur.pa : 0, len = valid ? cur.pb - cur.pa : 0;
+    const bool staged = p1 - p0 <= GRAM_STAGE;
+    // this tile's nonzeros into the wave's staging slice
+#pragma unroll
+    for (int u = 0; u < SU; ++u) {
+      const int pp = p0 + u * WAVE + lane;
+      if (pp < p1 && pp - p0 < GRAM_STAGE) {
+        lc[pp - p0] = cur.c[u];
+        lv[pp - p0] = cur.v[u];
+      }
+    }
+    wave_lds_sync();
+    // the Gram operands of the tile's rows (independent of the SpMM): requested first
+    const int i16 = lane % 16, kq = lane / 16;
+    TX aqr[GRAM_ROWS / 4][NA];
+#pragma unroll
+    for (int s4 = 0; s4 < GRAM_ROWS / 4; ++s4) {
+      const int64_t rowk = r0 + 4 * s4 + kq;
+      const int64_t rq = rowk < n ? rowk : n - 1;
+#pragma unroll
+      for (int a = 0; a < NA; ++a) {
+        const int ca = a * 16 + i16;
+        aqr[s4][a] = Q1[(size_t)(ca < k ? ca : k - 1) * ld + rq];
+      }
+    }
+    // SpMM: w = (A Q1)_{row, cols}, the row's nonzeros NZ at a time from the staging
+    // slice (the gathers of a round issued together)
     double w[CPL];
 #pragma unroll
     for (int u = 0; u < CPL; ++u) w[u] = 0.0;
-    for (int p = pa; p < pb; p += NZ) {
-      int cj[NZ];
-      double av[NZ];
+    const int off = pa - p0;
+    for (int z0 = 0; __any(z0 < len); z0 += GRAM_NZ) {
+      int cj[GRAM_NZ];
+      double av[GRAM_NZ];
 #pragma unroll
-      for (int z = 0; z < NZ; ++z) {
-        const int pp = p + z;
-        const int pc = pp < pb ? pp : pb - 1;
-        cj[z] = col[pc];
-        const double a = (double)val[pc];
-        av[z] = pp < pb ? a : 0.0;
+      for (int z = 0; z < GRAM_NZ; ++z) {
+        const bool on = z0 + z < len;
+        if (staged) {
+          const int idx = on ? off + z0 + z : 0;
+          cj[z] = on ? lc[idx] : (int)(valid ? row : n - 1);
+          av[z] = on ? (double)lv[idx] : 0.0;
+        } else {
+          const int pp = on ? pa + z0 + z : 0;
+          cj[z] = on ? col[(unsigned)pp] : (int)(valid ? row : n - 1);
+          av[z] = on ? (double)val[(unsigned)pp] : 0.0;
+        }
       }
-      double g[NZ][CPL];
+      TX g[GRAM_NZ][CPL];
 #pragma unroll
-      for (int z = 0; z < NZ; ++z)
+      for (int z = 0; z < GRAM_NZ; ++z)
 #pragma unroll
         for (int u = 0; u < CPL; ++u) {
           const int c = q * CPL + u;
-          g[z][u] = (double)Q1[(size_t)(c < k ? c : k - 1) * ld + cj[z]];
+          g[z][u] = Q1[(size_t)(c < k ? c : k - 1) * ld + (unsigned)cj[z]];
         }
 #pragma unroll
       for (int u = 0; u < CPL; ++u) {
         double acc = 0.0;
 #pragma unroll
-        for (int z = 0; z < NZ; ++z) acc += av[z] * g[z][u];
+        for (int z = 0; z < GRAM_NZ; ++z) acc += av[z] * (double)g[z][u];
         w[u] += acc;
       }
     }
+    // the next tile's row pointers and first nonzeros, in flight during the products
+    const int64_t tn = t + tstep < thi ? t + tstep : t;
+    Pre nxt;
+    prefetch(tn, nxt);
     // the tile's [W | b] into the wave's slice: W, zero columns past k, then b in column k
 #pragma unroll
     for (int u = 0; u < CPL; ++u) {
@@ -763,7 +876,6 @@ __global__ __launch_bounds__(GRAM_TPB) void k_spmm_gram(const int *rowptr, const
     wave_lds_sync();
     if (q == 0) Wl[rr * LDW + k] = valid ? b[row] : 0.0;
     wave_lds_sync();
-    const int i16 = lane % 16, kq = lane / 16;
 #pragma unroll
     for (int s4 = 0; s4 < GRAM_ROWS / 4; ++s4) {
       const int lr = 4 * s4 + kq;
@@ -772,9 +884,7 @@ __global__ __launch_bounds__(GRAM_TPB) void k_spmm_gram(const int *rowptr, const
 #pragma unroll
       for (int a = 0; a < NA; ++a) {
         const int ca = a * 16 + i16;
-        const int64_t rq = rowk < n ? rowk : n - 1;
-        const double v = (double)Q1[(size_t)(ca < k ? ca : k - 1) * ld + rq];
-        aq[a] = (ca < k && rowk < n) ? v : 0.0;
+        aq[a] = (ca < k && rowk < n) ? (double)aqr[s4][a] : 0.0;
       }
 #pragma unroll
       for (int bw = 0; bw < NWB; ++bw) wv[bw] = Wl[lr * LDW + bw * 16 + i16];
@@ -795,7 +905,8 @@ __global__ __launch_bounds__(GRAM_TPB) void k_spmm_gram(const int *rowptr, const
         }
       }
     }
-    wave_lds_sync();  // the slice is rewritten by the wave's next tile
+    wave_lds_sync();  // the slices are rewritten by the wave's next tile
+    cur = nxt;
   }
   // the waves' blocks added in wave order: D element v of a block sits at row
   // lane / 16 + 4 v, column lane % 16 (row-major 16 x 16)
