@@ -531,6 +531,8 @@ def main():
     ap.add_argument("--batch-steps", type=int, default=4)
     ap.add_argument("--no-batch", action="store_true")
     ap.add_argument("--only-batch", action="store_true", help="run only the batched workload")
+    ap.add_argument("--only-advdiff", action="store_true",
+                    help="run only the 512 x 512 GMRES comparator (for profiling its kernels)")
     ap.add_argument("--learned-train", type=int, default=200)
     ap.add_argument("--learned-eval", type=int, default=100)
     ap.add_argument("--no-learned", action="store_true")
@@ -549,6 +551,17 @@ def main():
 
     if args.only_batch:
         print(json.dumps({"batch64": batch_cmp(sacc, torch, np, args.batch_warmup, args.batch_steps)}), flush=True)
+        return
+    if args.only_advdiff:
+        if args.copy_calibration:
+            src = torch.empty(32 << 20, dtype=torch.float64, device="cuda").fill_(1.0)
+            dst = torch.empty_like(src)
+            for _ in range(3):
+                dst.copy_(src)
+            torch.cuda.synchronize()
+            log("copy calibration: 3 copies of 268435456 bytes")
+            del src, dst
+        print(json.dumps({"advdiff512": advdiff_cmp(sacc, torch, np, args.warmup, args.steps)}), flush=True)
         return
 
     p, method, res, roof, comps, cpu, err, extra, spmv = headline(sacc, torch, np, args)
