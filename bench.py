@@ -349,6 +349,10 @@ def paper4_cmp(sacc, torch, np):
         for name in ("projection", "previous"):
             ci, cw, _ = run_sequence(sacc, torch, st, m, M, 0, p.steps - M, guess=name)
             rec[name] = summary(ci, cw, p.steps - M)
+        # the paper's figures are for a preconditioned GMRES (ILU there); Jacobi here
+        for name in ("projection", "previous"):
+            ci, cw, _ = run_sequence(sacc, torch, st, m, M, 0, p.steps - M, guess=name, precond="jacobi")
+            rec[name + "_jacobi"] = summary(ci, cw, p.steps - M)
         rec["iters_ratio_previous_over_projection"] = round(
             rec["previous"]["iters_per_step"] / max(rec["projection"]["iters_per_step"], 1e-9), 3)
         rec["time_ratio_previous_over_projection"] = round(

@@ -55,6 +55,7 @@ struct sa_seq {
   long long *srht_rows = nullptr;
   unsigned long long *srht_signs = nullptr;  // SRHT sign words (one bit per row of x)
   unsigned short *sketch_bf16 = nullptr;     // SA_MIXED Gaussian sketch: BF16 normals (MFMA push)
+  bool tune = true;  // the CG kernels' tile autotuner may run (not in the allocation-free solve)
   Ctl *ctl = nullptr;     // device control block (projection + outer solve)
   Ctl *ctl_in = nullptr;  // device control block of the inner solves (mixed)
   int *hbuf = nullptr;    // pinned host mirror of solver state (128 ints; from int 64 on the
@@ -428,12 +429,14 @@ int run_cg(sa_seq *q, const CsrView &v, Ctl *ctl, const TV *b, TV *x, int maxit,
   SA_TRY(prof_begin(q, ctl, st));
   const size_t w = sizeof(TV), wv = v.fp32 ? 4 : 8;
   const double csr = 4.0 * (v.n + 1) + (4.0 + wv) * v.nnz;
+  // wave-tile shape of the CG kernels: tuned on first use of this operator shape
+  const int chunk = q->tune ? cg_tile_tune<TV>(v, b, x, r, q->partials, ctl, st) : cg_tile_chunk(v.n, v.nnz);
   const std::string pname =
-      std::string("k_cg_p<") + tname(wv) + ", " + tname(w) + ", " + std::to_string(cg_tile_chunk(v.n, v.nnz)) + ">";
+      std::string("k_cg_p<") + tname(wv) + ", " + tname(w) + ", " + std::to_string(chunk) + ">";
   Progress pg = progress_of(q, ctl);
   pg.reset();
   const int ahead = c.poll > MIR_EVERY ? c.poll : MIR_EVERY;  // progress arrives every MIR_EVERY steps
-  HIP_TRY(launch_cg_start_k<TV>(v, b, x, r, 0, q->partials, ctl, st, pg.next(), dinv));
+  HIP_TRY(launch_cg_start_k<TV>(v, b, x, r, 0, q->partials, ctl, st, pg.next(), dinv, chunk));
   // every launched iteration is productive, or a no-op while a check or the end of the
   // solve is on its way to the host (at most `poll` of them each time)
   const long long cap = 2LL * maxit + 64LL * c.poll + 1024;
@@ -446,7 +449,7 @@ int run_cg(sa_seq *q, const CsrView &v, Ctl *ctl, const TV *b, TV *x, int maxit,
     if (fl & MIR_CHECK) {
       // the recursive residual met the tolerance: confirm with the true residual and
       // wait for the decision
-      HIP_TRY(launch_cg_start_k<TV>(v, b, x, r, 1, q->partials, ctl, st, pg.next(), dinv));
+      HIP_TRY(launch_cg_start_k<TV>(v, b, x, r, 1, q->partials, ctl, st, pg.next(), dinv, chunk));
       SA_TRY(progress_wait(q, ctl, pg, pg.serial, INT_MAX, MIR_STOPPED, st, &seen, &fl));
       if (fl & MIR_STOPPED) break;
       continue;
@@ -454,11 +457,11 @@ int run_cg(sa_seq *q, const CsrView &v, Ctl *ctl, const TV *b, TV *x, int maxit,
     KTiming tm;
     // gathers r and p, writes p and q
     const KTiming *tp = prof_slot(q, pname, csr + (dinv ? 5.0 : 4.0) * w * v.n, &tm);
-    HIP_TRY(launch_cg_iter<TV>(v, x, r, p2, qq, q->partials, ctl, st, tp, pg.next(), dinv));
+    HIP_TRY(launch_cg_iter<TV>(v, x, r, p2, qq, q->partials, ctl, st, tp, pg.next(), dinv, chunk));
   }
   SA_TRY(poll(q, ctl, st));
   if (hs[0] == ST_MAXIT || hs[0] == ST_BREAK) {
-    HIP_TRY(launch_cg_start_k<TV>(v, b, x, r, 2, q->partials, ctl, st, 0, dinv));
+    HIP_TRY(launch_cg_start_k<TV>(v, b, x, r, 2, q->partials, ctl, st, 0, dinv, chunk));
     SA_TRY(poll(q, ctl, st));
   }
   return prof_end(q, ctl, st);
@@ -1436,6 +1439,7 @@ int sa_solve_static(const sa_config *cfg, const sa_csr *A, const void *b_dev, vo
   q.hbuf = hb;
   q.mir[0] = &progress;
   q.sync_poll = true;
+  q.tune = false;  // the autotuner creates events
   q.ld = padded_ld(cfg->n);
   q.ctl = (Ctl *)((char *)base + L.ctl);
   q.partials = (double *)((char *)base + L.partials);

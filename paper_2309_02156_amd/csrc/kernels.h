@@ -114,14 +114,22 @@ struct KTiming {
 // p2 holds the two alternating direction vectors (p2 and p2 + padded_ld(n)).
 template <typename TV>
 hipError_t launch_cg_start_k(const CsrView &A, const TV *b, const TV *x, TV *r, int mode, double *partials,
-                             Ctl *ctl, hipStream_t st, int serial = 0, const TV *dinv = nullptr);
+                             Ctl *ctl, hipStream_t st, int serial = 0, const TV *dinv = nullptr, int chunk = 0);
 // tm (may be null) times the direction/SpMV kernel of the iteration.  serial > 0: the
 // step's kernel reports serial and what it saw in the control block's progress word.
 // dinv (may be null): Jacobi preconditioning, z = dinv * r (the start kernel then also
 // forms r^T z); the stopping test stays on ||r||.
 template <typename TV>
 hipError_t launch_cg_iter(const CsrView &A, TV *x, TV *r, TV *p2, TV *q, double *partials, Ctl *ctl,
-                          hipStream_t st, const KTiming *tm = nullptr, int serial = 0, const TV *dinv = nullptr);
+                          hipStream_t st, const KTiming *tm = nullptr, int serial = 0, const TV *dinv = nullptr,
+                          int chunk = 0);
+// chunk: gathers per lane and step of the wave tiles (5, 7 or 9; 0: the heuristic
+// cg_tile_chunk).  cg_tile_tune picks it for an operator by timing the start kernel's
+// SpMV (mode 2, only partial rows written: b and x are read, r is not written) for each
+// value, cached per (n, nnz, value type, vector type); the first call for a shape waits
+// for its timing launches.
+template <typename TV>
+int cg_tile_tune(const CsrView &A, const TV *b, const TV *x, TV *r, double *partials, Ctl *ctl, hipStream_t st);
 // dinv[i] = 1 / (sum of row i's entries in column i), 1 where that sum is zero
 template <typename TV>
 hipError_t launch_jacobi_dinv(const CsrView &A, TV *dinv, hipStream_t st);

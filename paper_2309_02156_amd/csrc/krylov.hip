@@ -19,6 +19,9 @@
 #include <hip/hip_ext.h>
 #include <math.h>
 
+#include <map>
+#include <mutex>
+#include <tuple>
 #include <type_traits>
 
 #include "common.h"
@@ -460,8 +463,8 @@ static int cg_start_c(const CsrView &A, const TV *b, const TV *x, TV *r, int mod
 
 template <typename VT, typename TV, bool PC>
 static int cg_start_launch(const CsrView &A, const TV *b, const TV *x, TV *r, int mode, double *partials,
-                           const Ctl *ctl, hipStream_t st, const TV *dinv) {
-  const int C = wave_tile_chunk(A.n, A.nnz);
+                           const Ctl *ctl, hipStream_t st, const TV *dinv, int chunk) {
+  const int C = chunk > 0 ? chunk : wave_tile_chunk(A.n, A.nnz);
   if (C <= 5) return cg_start_c<VT, TV, 5, PC>(A, b, x, r, mode, partials, ctl, st, dinv);
   if (C <= 7) return cg_start_c<VT, TV, 7, PC>(A, b, x, r, mode, partials, ctl, st, dinv);
   return cg_start_c<VT, TV, 9, PC>(A, b, x, r, mode, partials, ctl, st, dinv);
@@ -469,14 +472,14 @@ static int cg_start_launch(const CsrView &A, const TV *b, const TV *x, TV *r, in
 
 template <typename TV>
 hipError_t launch_cg_start_k(const CsrView &A, const TV *b, const TV *x, TV *r, int mode, double *partials, Ctl *ctl,
-                             hipStream_t st, int serial, const TV *dinv) {
+                             hipStream_t st, int serial, const TV *dinv, int chunk) {
   int nb;
   if (dinv)
-    nb = A.fp32 ? cg_start_launch<float, TV, true>(A, b, x, r, mode, partials, ctl, st, dinv)
-                : cg_start_launch<double, TV, true>(A, b, x, r, mode, partials, ctl, st, dinv);
+    nb = A.fp32 ? cg_start_launch<float, TV, true>(A, b, x, r, mode, partials, ctl, st, dinv, chunk)
+                : cg_start_launch<double, TV, true>(A, b, x, r, mode, partials, ctl, st, dinv, chunk);
   else
-    nb = A.fp32 ? cg_start_launch<float, TV, false>(A, b, x, r, mode, partials, ctl, st, dinv)
-                : cg_start_launch<double, TV, false>(A, b, x, r, mode, partials, ctl, st, dinv);
+    nb = A.fp32 ? cg_start_launch<float, TV, false>(A, b, x, r, mode, partials, ctl, st, dinv, chunk)
+                : cg_start_launch<double, TV, false>(A, b, x, r, mode, partials, ctl, st, dinv, chunk);
   hipLaunchKernelGGL(k_cg_start_close, dim3(1), dim3(KTPB), 0, st, PA(partials), nb, mode, ctl, serial,
                      dinv ? 1 : 0);
   return hipGetLastError();
@@ -484,8 +487,8 @@ hipError_t launch_cg_start_k(const CsrView &A, const TV *b, const TV *x, TV *r, 
 
 template <typename VT, typename TV, bool PC>
 static void cg_iter_vt(const CsrView &A, TV *x, TV *r, TV *P0, TV *P1, TV *q, double *partials, Ctl *ctl,
-                       hipStream_t st, const KTiming *tm, int serial, const TV *dinv) {
-  const int C = wave_tile_chunk(A.n, A.nnz);
+                       hipStream_t st, const KTiming *tm, int serial, const TV *dinv, int chunk) {
+  const int C = chunk > 0 ? chunk : wave_tile_chunk(A.n, A.nnz);
   if (C <= 5)
     cg_iter_u<VT, TV, 5, PC>(A, x, r, P0, P1, q, partials, ctl, st, tm, serial, dinv);
   else if (C <= 7)
@@ -496,21 +499,72 @@ static void cg_iter_vt(const CsrView &A, TV *x, TV *r, TV *P0, TV *P1, TV *q, do
 
 template <typename TV>
 hipError_t launch_cg_iter(const CsrView &A, TV *x, TV *r, TV *p2, TV *q, double *partials, Ctl *ctl,
-                          hipStream_t st, const KTiming *tm, int serial, const TV *dinv) {
+                          hipStream_t st, const KTiming *tm, int serial, const TV *dinv, int chunk) {
   const int64_t ld = padded_ld(A.n);
   TV *P0 = p2, *P1 = p2 + ld;
   if (dinv) {
     if (A.fp32)
-      cg_iter_vt<float, TV, true>(A, x, r, P0, P1, q, partials, ctl, st, tm, serial, dinv);
+      cg_iter_vt<float, TV, true>(A, x, r, P0, P1, q, partials, ctl, st, tm, serial, dinv, chunk);
     else
-      cg_iter_vt<double, TV, true>(A, x, r, P0, P1, q, partials, ctl, st, tm, serial, dinv);
+      cg_iter_vt<double, TV, true>(A, x, r, P0, P1, q, partials, ctl, st, tm, serial, dinv, chunk);
   } else {
     if (A.fp32)
-      cg_iter_vt<float, TV, false>(A, x, r, P0, P1, q, partials, ctl, st, tm, serial, dinv);
+      cg_iter_vt<float, TV, false>(A, x, r, P0, P1, q, partials, ctl, st, tm, serial, dinv, chunk);
     else
-      cg_iter_vt<double, TV, false>(A, x, r, P0, P1, q, partials, ctl, st, tm, serial, dinv);
+      cg_iter_vt<double, TV, false>(A, x, r, P0, P1, q, partials, ctl, st, tm, serial, dinv, chunk);
   }
   return hipGetLastError();
+}
+
+// Tile autotuner of the CG kernels: the gathers per lane and step (C = 5, 7 or 9) of
+// their wave tiles, chosen by timing the start kernel's SpMV (mode 2: it writes only its
+// partial rows) for each C on the operator at hand, three launches each, the fastest
+// median kept.  Cached per (n, nnz, value type, vector type) for the process; the first
+// solve of a new shape pays about 20 launches and one wait.
+template <typename TV>
+int cg_tile_tune(const CsrView &A, const TV *b, const TV *x, TV *r, double *partials, Ctl *ctl, hipStream_t st) {
+  using Key = std::tuple<int64_t, int64_t, int, int>;
+  static std::map<Key, int> cache;
+  static std::mutex mu;
+  const Key key{A.n, A.nnz, A.fp32, (int)sizeof(TV)};
+  {
+    std::lock_guard<std::mutex> lk(mu);
+    auto it = cache.find(key);
+    if (it != cache.end()) return it->second;
+  }
+  const int heuristic = wave_tile_chunk(A.n, A.nnz);
+  if (A.nnz == 0) return heuristic;
+  hipEvent_t ev[4];
+  for (int e = 0; e < 4; ++e)
+    if (hipEventCreate(&ev[e]) != hipSuccess) return heuristic;
+  const int cands[3] = {5, 7, 9};
+  float best = 0.0f;
+  int pick = heuristic;
+  bool ok = true;
+  for (int ci = 0; ci < 3 && ok; ++ci) {
+    const int C = cands[ci];
+    float t[3];
+    // one untimed launch, then three timed
+    ok = launch_cg_start_k<TV>(A, b, x, r, 2, partials, ctl, st, 0, nullptr, C) == hipSuccess;
+    for (int rep = 0; rep < 3 && ok; ++rep) {
+      ok = hipEventRecord(ev[0], st) == hipSuccess &&
+           launch_cg_start_k<TV>(A, b, x, r, 2, partials, ctl, st, 0, nullptr, C) == hipSuccess &&
+           hipEventRecord(ev[1], st) == hipSuccess && hipEventSynchronize(ev[1]) == hipSuccess &&
+           hipEventElapsedTime(&t[rep], ev[0], ev[1]) == hipSuccess;
+    }
+    if (!ok) break;
+    const float med = t[0] < t[1] ? (t[1] < t[2] ? t[1] : (t[0] < t[2] ? t[2] : t[0]))
+                                  : (t[0] < t[2] ? t[0] : (t[1] < t[2] ? t[2] : t[1]));
+    if (ci == 0 || med < best) {
+      best = med;
+      pick = C;
+    }
+  }
+  for (int e = 0; e < 4; ++e) (void)hipEventDestroy(ev[e]);
+  if (!ok) return heuristic;
+  std::lock_guard<std::mutex> lk(mu);
+  cache[key] = pick;
+  return pick;
 }
 
 // ============================================================================ GMRES
@@ -1535,9 +1589,10 @@ hipError_t launch_jacobi_dinv(const CsrView &A, TV *dinv, hipStream_t st) {
 
 #define SACC_INSTANTIATE_KRYLOV(TV)                                                                              \
   template hipError_t launch_cg_start_k<TV>(const CsrView &, const TV *, const TV *, TV *, int, double *, Ctl *, \
-                                            hipStream_t, int, const TV *);                                       \
+                                            hipStream_t, int, const TV *, int);                                  \
   template hipError_t launch_cg_iter<TV>(const CsrView &, TV *, TV *, TV *, TV *, double *, Ctl *, hipStream_t,  \
-                                         const KTiming *, int, const TV *);                                      \
+                                         const KTiming *, int, const TV *, int);                                 \
+  template int cg_tile_tune<TV>(const CsrView &, const TV *, const TV *, TV *, double *, Ctl *, hipStream_t);    \
   template hipError_t launch_gm_start<TV>(const CsrView &, const TV *, const TV *, TV *, int, double *, Ctl *,   \
                                           hipStream_t);                                                          \
   template hipError_t launch_gm_step<TV>(const CsrView &, TV *, TV *, int64_t, int, int, double *, Ctl *,        \

@@ -725,3 +725,26 @@ def test_pod_plain_definition(sacc):
     err = np.linalg.norm(host(x0) - ref) / np.linalg.norm(ref)
     print_case("pod plain: k, rel err", info["k_eff"], err)
     assert info["k_sketch"] == m and err <= 1e-9
+
+
+def test_cg_tile_tuner(sacc):
+    """The CG kernels' wave-tile shape is tuned on first use of an operator shape (one
+    of 5, 7, 9 gathers per lane and step; the tuning launches write only partial rows):
+    the solve that tunes and a later one on a fresh sequence (cached shape) give the same
+    bits, and both match the oracle's iteration count within one."""
+    p, m = config(2, 16)
+    A = p.matrix(3, fp32=False)
+    As = A.to_scipy()
+    b = p.rhs(3)
+    xo, oinfo = okr.cg(As, b, np.zeros(p.n), 1e-10)
+    out = []
+    for _ in range(2):
+        seq = sacc.Sequence(p.n, 2, s=4, solver="cg", tol=1e-10)
+        seq.profile_enable(True)
+        xd, info = seq.solve(sacc.DeviceCSR.from_csr(A), dev(b), dev(np.zeros(p.n)))
+        names = [r["name"] for r in seq.profile_read() if r["name"].startswith("k_cg_p<")]
+        assert names and all(nm.rstrip(">").split(", ")[-1] in ("5", "7", "9") for nm in names), names
+        out.append((host(xd), info["iters"], names))
+    print_case("tuned tile", out[0][2])
+    assert np.array_equal(out[0][0], out[1][0]) and out[0][2] == out[1][2]
+    assert abs(out[0][1] - oinfo["iters"]) <= 1
