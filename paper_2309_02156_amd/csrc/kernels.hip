@@ -765,15 +765,18 @@ __global__ __launch_bounds__(GRAM_TPB) void k_spmm_gram(const int *rowptr, const
   const int64_t tlo = (int64_t)(blockIdx.x % groups) * per;
   const int64_t thi = tlo + per < T ? tlo + per : T;
   const int64_t tstep = (int64_t)(gridDim.x / groups) * GRAM_NW;
-  // Tile prefetch: the row pointers and the first GRAM_STAGE nonzeros (columns, values)
-  // of a tile, requested while the previous tile's Gram products run.  Loads are
-  // unconditional and in bounds (col / val hold at least one entry).
-  struct Pre {
+  // Two-stage tile prefetch: a tile's row pointers are requested two tiles ahead and
+  // its first GRAM_STAGE nonzeros (columns, values) one tile ahead, both with the current
+  // tile's gathers, so a tile waits for one trip to memory.  Loads are unconditional and
+  // in bounds (col / val hold at least one entry); past the last tile they re-read it.
+  struct Rows {
     int pa, pb, p0, p1;
+  };
+  struct Nz {
     int c[SU];
     VT v[SU];
   };
-  auto prefetch = [&](int64_t tt, Pre &f) {
+  auto load_rows = [&](int64_t tt, Rows &f) {
     const int64_t r0 = tt * GRAM_ROWS, row = r0 + rr;
     const int64_t rc = row < n ? row : n - 1;
     const int64_t rl = r0 + GRAM_ROWS < n ? r0 + GRAM_ROWS : n;
@@ -781,32 +784,47 @@ __global__ __launch_bounds__(GRAM_TPB) void k_spmm_gram(const int *rowptr, const
     f.pb = rowptr[rc + 1];
     f.p0 = rowptr[r0 < n ? r0 : n - 1];
     f.p1 = rowptr[rl];
-    __builtin_amdgcn_sched_barrier(0);
+  };
+  auto load_nz = [&](const Rows &f, Nz &z) {
     const int p0 = __builtin_amdgcn_readfirstlane(f.p0), p1 = __builtin_amdgcn_readfirstlane(f.p1);
 #pragma unroll
     for (int u = 0; u < SU; ++u) {
       const int pp = p0 + u * WAVE + lane;
       const int pc = pp < p1 ? pp : (p1 > 0 ? p1 - 1 : 0);
-      f.c[u] = col[(unsigned)pc];
-      f.v[u] = val[(unsigned)pc];
+      z.c[u] = col[(unsigned)pc];
+      z.v[u] = val[(unsigned)pc];
     }
   };
   int64_t t = tlo + (int64_t)(blockIdx.x / groups) * GRAM_NW + wid;
-  Pre cur;
-  if (k > 0 && t < thi) prefetch(t, cur);
+  auto clampt = [&](int64_t tt) { return tt < thi ? tt : (t < thi ? thi - 1 : t); };
+  Rows cur, nr;
+  Nz cz;
+  if (k > 0 && t < thi) {
+    load_rows(t, cur);
+    load_rows(clampt(t + tstep), nr);
+    load_nz(cur, cz);
+  }
   for (; k > 0 && t < thi; t += tstep) {
     const int64_t r0 = t * GRAM_ROWS, row = r0 + rr;
     const bool valid = row < n;
     const int p0 = __builtin_amdgcn_readfirstlane(cur.p0), p1 = __builtin_amdgcn_readfirstlane(cur.p1);
     const int pa = valid ? cur.pa : 0, len = valid ? cur.pb - cur.pa : 0;
     const bool staged = p1 - p0 <= GRAM_STAGE;
+    // the next tile's nonzeros (its row pointers arrived during this tile's predecessor)
+    // and the row pointers of the tile after it
+    Nz nz;
+    Rows nr2;
+    load_nz(nr, nz);
+    load_rows(clampt(t + 2 * tstep), nr2);
+    __builtin_amdgcn_sched_barrier(0);
+    const Nz &cc = cz;
     // this tile's nonzeros into the wave's staging slice
 #pragma unroll
     for (int u = 0; u < SU; ++u) {
       const int pp = p0 + u * WAVE + lane;
       if (pp < p1 && pp - p0 < GRAM_STAGE) {
-        lc[pp - p0] = cur.c[u];
-        lv[pp - p0] = cur.v[u];
+        lc[pp - p0] = cc.c[u];
+        lv[pp - p0] = cc.v[u];
       }
     }
     wave_lds_sync();
@@ -861,10 +879,6 @@ __global__ __launch_bounds__(GRAM_TPB) void k_spmm_gram(const int *rowptr, const
         w[u] += acc;
       }
     }
-    // the next tile's row pointers and first nonzeros, in flight during the products
-    const int64_t tn = t + tstep < thi ? t + tstep : t;
-    Pre nxt;
-    prefetch(tn, nxt);
     // the tile's [W | b] into the wave's slice: W, zero columns past k, then b in column k
 #pragma unroll
     for (int u = 0; u < CPL; ++u) {
@@ -906,7 +920,9 @@ __global__ __launch_bounds__(GRAM_TPB) void k_spmm_gram(const int *rowptr, const
       }
     }
     wave_lds_sync();  // the slices are rewritten by the wave's next tile
-    cur = nxt;
+    cur = nr;
+    nr = nr2;
+    cz = nz;
   }
   // the waves' blocks added in wave order: D element v of a block sits at row
   // lane / 16 + 4 v, column lane % 16 (row-major 16 x 16)
