@@ -501,13 +501,21 @@ def batch_cmp(sacc, torch, np, warmup, steps, max_streams=4, seed=4, nseq=64, pr
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     its, rel, stat = 0, 0.0, []
+    by_solver = {"cg": 0, "gmres": 0}
+    longest = 0
+    per_seq = [0] * len(probs)
     for i in range(fill + warmup, total):
         infos = run(i)
         its += sum(d["iters"] for d in infos)
+        for j, d in enumerate(infos):
+            by_solver[probs[j][1]["solver"]] += d["iters"]
+            per_seq[j] += d["iters"]
+        longest += max(d["iters"] for d in infos)
         rel = max(rel, max(d["relres"] for d in infos))
         stat += [d["status"] for d in infos]
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
+    top = sorted(range(len(probs)), key=lambda j: -per_seq[j])[:5]
     plan = batch.plan()
     batch.close()
     for s in seqs:
@@ -518,6 +526,10 @@ def batch_cmp(sacc, torch, np, warmup, steps, max_streams=4, seed=4, nseq=64, pr
                          f"{probs[0][1]['max_refine']} sweeps), relres 1e-8",
                 steps_timed=f"{fill + warmup}..{total - 1}", ms_per_step=round(1e3 * wall / steps, 3),
                 krylov_iters_per_step=its / steps, relres_max=rel,
+                iters_per_step_by_solver={k: v / steps for k, v in by_solver.items()},
+                longest_sequence_iters_per_step=longest / steps,
+                heaviest_sequences=[dict(n=probs[j][0].n, solver=probs[j][1]["solver"],
+                                         iters_per_step=per_seq[j] / steps) for j in top],
                 not_converged=int(sum(1 for s_ in stat if s_ != 0)), plan=plan)
 
 
