@@ -449,6 +449,7 @@ int run_cg(sa_seq *q, const CsrView &v, Ctl *ctl, const TV *b, TV *x, int maxit,
     if (fl & MIR_CHECK) {
       // the recursive residual met the tolerance: confirm with the true residual and
       // wait for the decision
+      HIP_TRY(launch_cg_xfix<TV>(v, x, p2, ctl, st));
       HIP_TRY(launch_cg_start_k<TV>(v, b, x, r, 1, q->partials, ctl, st, pg.next(), dinv, chunk));
       SA_TRY(progress_wait(q, ctl, pg, pg.serial, INT_MAX, MIR_STOPPED, st, &seen, &fl));
       if (fl & MIR_STOPPED) break;
@@ -456,9 +457,13 @@ int run_cg(sa_seq *q, const CsrView &v, Ctl *ctl, const TV *b, TV *x, int maxit,
     }
     KTiming tm;
     // gathers r and p, writes p and q
-    const KTiming *tp = prof_slot(q, pname, csr + (dinv ? 5.0 : 4.0) * w * v.n, &tm);
+    // r and p gathered, p and q written, x read and written (the previous iteration's
+    // x += alpha p)
+    const KTiming *tp = prof_slot(q, pname, csr + (dinv ? 7.0 : 6.0) * w * v.n, &tm);
     HIP_TRY(launch_cg_iter<TV>(v, x, r, p2, qq, q->partials, ctl, st, tp, pg.next(), dinv, chunk));
   }
+  // the last x += alpha p (no-op when the check before the stop applied it)
+  HIP_TRY(launch_cg_xfix<TV>(v, x, p2, ctl, st));
   SA_TRY(poll(q, ctl, st));
   if (hs[0] == ST_MAXIT || hs[0] == ST_BREAK) {
     HIP_TRY(launch_cg_start_k<TV>(v, b, x, r, 2, q->partials, ctl, st, 0, dinv, chunk));

@@ -43,6 +43,9 @@ struct Ctl {
   int conv_pending;             // GMRES: the last cycle ended on the estimate (trust_est)
   int pad2;
   double rho[4];                // CG: r^T r after iteration k in slot k & 3
+  double cg_alpha;              // CG: alpha of iteration cg_xk, whose x += alpha p is pending
+  int cg_xk, cg_xdone;          // CG: iteration of the pending x update; last one applied by
+                                // the fix-up kernel (the next p / q kernel applies it otherwise)
   unsigned long long *mirror;   // host-visible progress word (pinned host memory), or null
   int *hinfo;                   // host-visible guess record (pinned host memory), or null:
                                 // [0] k, [1] k2, [2] fallback (reduced solve), [4] learned used

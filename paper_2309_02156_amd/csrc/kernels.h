@@ -123,6 +123,11 @@ template <typename TV>
 hipError_t launch_cg_iter(const CsrView &A, TV *x, TV *r, TV *p2, TV *q, double *partials, Ctl *ctl,
                           hipStream_t st, const KTiming *tm = nullptr, int serial = 0, const TV *dinv = nullptr,
                           int chunk = 0);
+// The x / r kernel leaves x += alpha p pending (the next p / q kernel applies it for its
+// rows); launch_cg_xfix applies it on its own and must precede a true-residual start
+// (mode 1 or 2) and the end of a solve.  p2: the two direction buffers.
+template <typename TV>
+hipError_t launch_cg_xfix(const CsrView &A, TV *x, TV *p2, Ctl *ctl, hipStream_t st);
 // chunk: gathers per lane and step of the wave tiles (5, 7 or 9; 0: the heuristic
 // cg_tile_chunk).  cg_tile_tune picks it for an operator by timing the start kernel's
 // SpMV (mode 2, only partial rows written: b and x are read, r is not written) for each

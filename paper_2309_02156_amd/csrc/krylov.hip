@@ -159,12 +159,17 @@ __device__ inline double pick4(const double (&r)[4], int e) {
 template <typename VT, typename TV, int C, bool PC>
 __global__ __launch_bounds__(KTPB) void k_cg_start(const int *rowptr, const int *col, const VT *val,
                                                    const TV *b, const TV *x, TV *r, int64_t n, int mode,
-                                                   double *Pout, const Ctl *ctl, const TV *dinv) {
+                                                   double *Pout, Ctl *ctl, const TV *dinv) {
   __shared__ double red[KNW * 4];
   __shared__ int lcol[KNW * WT_CAP];
   __shared__ VT lval[KNW * WT_CAP];
   __shared__ int s_go;
-  if (threadIdx.x == 0) s_go = (mode != 1) || (ctl->state == ST_CHECK);
+  if (threadIdx.x == 0) {
+    s_go = (mode != 1) || (ctl->state == ST_CHECK);
+    // modes 1 and 2 follow the fix-up kernel: the pending x update is in x now (no other
+    // block of this launch reads the mark)
+    if (blockIdx.x == 0 && mode != 0) ctl->cg_xdone = ctl->cg_xk;
+  }
   __syncthreads();
   if (!s_go) return;
   const int lane = threadIdx.x % WAVE, wid = threadIdx.x / WAVE;
@@ -207,6 +212,7 @@ __global__ __launch_bounds__(KTPB) void k_cg_start_close(const double *Pin, int 
   final_sum(Pin, nblk, KW, pc ? 3 : 2, outv, scratch);
   if (threadIdx.x != 0) return;
   const int st = residual_decide(outv[0], outv[1], mode, ctl, true, ctl->trust_est != 0);
+  if (mode == 0) ctl->cg_xk = ctl->cg_xdone = 0;  // a new solve: no x update pending
   if (mode != 2 && st == ST_RUN) {
     const int k = ctl->iters;
     ctl->rho[k & 3] = pc ? outv[2] : outv[0];  // r^T z (z = r without the preconditioner)
@@ -239,24 +245,29 @@ struct GatherDir {
 };
 
 // C = gathers per lane and round of a wave tile
+// Also applies the x update of the previous iteration, x += alpha_{k-1} p_{k-1}, for its
+// own rows (the x / r kernel leaves it pending: p_{k-1} is this kernel's input direction).
 template <typename VT, typename TV, int C, bool PC>
 __global__ __launch_bounds__(KTPB) void k_cg_p(const int *rowptr, const int *col, const VT *val, const TV *r,
                                                TV *P0, TV *P1, TV *q, int64_t n, const double *Pin, int nblk,
-                                               double *Pout, Ctl *ctl, int lidx, const TV *dinv) {
+                                               double *Pout, Ctl *ctl, int lidx, const TV *dinv, TV *x) {
   __shared__ double red[KNW];
   __shared__ double outv[2];
   __shared__ double scratch[KTPB];
   __shared__ int lcol[KNW * WT_CAP];
   __shared__ VT lval[KNW * WT_CAP];
-  __shared__ int s_k, s_fresh, s_go, s_cont, s_maxit;
-  __shared__ double s_beta, s_tolb, s_rho2;
+  __shared__ int s_k, s_fresh, s_go, s_cont, s_maxit, s_xpend;
+  __shared__ double s_beta, s_tolb, s_rho2, s_alpha;
   // r^T r (and r^T z) of the previous iteration (unused when the direction restarts),
   // loaded together with the control block
   const double part = final_part<2>(Pin, nblk, KW, PC ? 2 : 1);
   if (threadIdx.x == 0) {
     // every control-block read of the kernel, issued together
     const int st = ctl->state, it = ctl->iters, fa = ctl->fresh_at, mx = ctl->maxit;
-    const double tol = ctl->tol, bn = ctl->bnorm;
+    const int xk = ctl->cg_xk, xd = ctl->cg_xdone;
+    const double tol = ctl->tol, bn = ctl->bnorm, al = ctl->cg_alpha;
+    s_xpend = xk == it && xk > xd;  // the previous iteration's x update, not yet applied
+    s_alpha = al;
     double r4[4];
 #pragma unroll
     for (int e = 0; e < 4; ++e) r4[e] = ctl->rho[e];
@@ -295,7 +306,8 @@ __global__ __launch_bounds__(KTPB) void k_cg_p(const int *rowptr, const int *col
   __syncthreads();
   if (!s_cont) return;
   if (lidx >= 0 && blockIdx.x == 0 && threadIdx.x == 0) ctl->work_log[lidx] = 1;
-  const double beta = s_beta;
+  const double beta = s_beta, alpha = s_alpha;
+  const int xpend = s_xpend;
   const TV *pin = (k & 1) ? P0 : P1;
   TV *pout = (k & 1) ? P1 : P0;
   const GatherDir<TV, PC> gx{r, pin, dinv, beta, fresh};
@@ -315,8 +327,30 @@ __global__ __launch_bounds__(KTPB) void k_cg_p(const int *rowptr, const int *col
         const TV qs = (TV)qi;
         q[i] = qs;
         acc[0] += (double)ps * (double)qs;
+        if (xpend) x[i] = (TV)((double)x[i] + alpha * (double)pin[i]);
       });
   kstore<1>(acc, 1, red, Pout + (size_t)blockIdx.x * KW);
+}
+
+// The pending x update, applied on its own (before a true-residual check and at the end
+// of a solve): x += alpha p of iteration cg_xk unless that was applied already.  The
+// start kernel that follows (modes 1 and 2) marks it applied: a mark written here could
+// reach blocks of this same launch that have not read the state yet.
+template <typename TV>
+__global__ __launch_bounds__(KTPB) void k_cg_xfix(TV *x, const TV *P0, const TV *P1, int64_t n, const Ctl *ctl) {
+  __shared__ int s_go, s_k;
+  __shared__ double s_alpha;
+  if (threadIdx.x == 0) {
+    const int xk = ctl->cg_xk, xd = ctl->cg_xdone;
+    s_go = xk > xd;
+    s_k = xk;
+    s_alpha = ctl->cg_alpha;
+  }
+  __syncthreads();
+  if (!s_go) return;
+  const TV *p = (s_k & 1) ? P1 : P0;
+  const double alpha = s_alpha;
+  GRID_ROWS(i, n) x[i] = (TV)((double)x[i] + alpha * (double)p[i]);
 }
 
 // U = rows each thread takes per pass (all their loads issued before the first use)
@@ -352,23 +386,26 @@ __global__ __launch_bounds__(KTPB) void k_cg_xr(TV *x, TV *r, const TV *P0, cons
   if (!(pq > 0.0) || !isfinite(pq)) {
     if (blockIdx.x == 0 && threadIdx.x == 0) {
       ctl->state = ST_BREAK;
+      // the p / q kernel of this iteration applied the previous x update
+      ctl->cg_xdone = ctl->cg_xk;
       mirror_report(ctl->mirror, serial, MIR_STOPPED);
     }
     return;
   }
   const double alpha = s_rho / pq;
-  const TV *p = (k & 1) ? P1 : P0;
-  // ||r||^2 and (preconditioned) r^T z of the new residual
+  (void)x;
+  (void)P0;
+  (void)P1;
+  // ||r||^2 and (preconditioned) r^T z of the new residual; x += alpha p is left to the
+  // next p / q kernel (or the fix-up kernel)
   constexpr int K = PC ? 2 : 1;
   double acc[K] = {};
   for (int64_t r0 = (int64_t)blockIdx.x * (U * KTPB); r0 < n; r0 += (int64_t)gridDim.x * (U * KTPB)) {
-    double xv[U], pv[U], rv[U], qv[U], dv[U];
+    double rv[U], qv[U], dv[U];
 #pragma unroll
     for (int u = 0; u < U; ++u) {
       const int64_t i = r0 + (int64_t)u * KTPB + threadIdx.x;
       const int64_t ic = i < n ? i : n - 1;
-      xv[u] = (double)x[ic];
-      pv[u] = (double)p[ic];
       rv[u] = (double)r[ic];
       qv[u] = (double)q[ic];
       if constexpr (PC) dv[u] = (double)dinv[ic];
@@ -377,7 +414,6 @@ __global__ __launch_bounds__(KTPB) void k_cg_xr(TV *x, TV *r, const TV *P0, cons
     for (int u = 0; u < U; ++u) {
       const int64_t i = r0 + (int64_t)u * KTPB + threadIdx.x;
       if (i < n) {
-        x[i] = (TV)(xv[u] + alpha * pv[u]);
         const TV rs = (TV)(rv[u] - alpha * qv[u]);
         r[i] = rs;
         const double ri = (double)rs;
@@ -389,6 +425,8 @@ __global__ __launch_bounds__(KTPB) void k_cg_xr(TV *x, TV *r, const TV *P0, cons
   kstore<K>(acc, K, red, Pout + (size_t)blockIdx.x * KW);
   if (blockIdx.x == 0 && threadIdx.x == 0) {
     ctl->iters = k;
+    ctl->cg_alpha = alpha;
+    ctl->cg_xk = k;
     mirror_report(ctl->mirror, serial, 0u);
   }
 }
@@ -431,7 +469,7 @@ static void cg_iter_launch(const CsrView &A, TV *x, TV *r, TV *P0, TV *P1, TV *q
   const int *colp = A.nnz > 0 ? A.col : A.rowptr;
   const VT *valp = A.nnz > 0 ? (const VT *)A.val : (const VT *)r;
   hipExtLaunchKernelGGL((k_cg_p<VT, TV, C, PC>), dim3(nb), dim3(KTPB), 0, st, e0, e1, 0, A.rowptr, colp, valp, r,
-                        P0, P1, q, A.n, PA(partials), nb, PB(partials), ctl, lidx, dinv);
+                        P0, P1, q, A.n, PA(partials), nb, PB(partials), ctl, lidx, dinv, x);
   hipLaunchKernelGGL((k_cg_xr<TV, U, PC>), dim3(nb), dim3(KTPB), 0, st, x, r, P0, P1, q, A.n, PB(partials), nb,
                      PA(partials), ctl, serial, dinv);
 }
@@ -450,7 +488,7 @@ static void cg_iter_u(const CsrView &A, TV *x, TV *r, TV *P0, TV *P1, TV *q, dou
 }
 
 template <typename VT, typename TV, int C, bool PC>
-static int cg_start_c(const CsrView &A, const TV *b, const TV *x, TV *r, int mode, double *partials, const Ctl *ctl,
+static int cg_start_c(const CsrView &A, const TV *b, const TV *x, TV *r, int mode, double *partials, Ctl *ctl,
                       hipStream_t st, const TV *dinv) {
   const int nb = cg_grid<VT, TV, C, PC>(A.n);
   // stand-ins without nonzeros, as for the iteration kernel (r: workspace of >= 576 entries)
@@ -463,7 +501,7 @@ static int cg_start_c(const CsrView &A, const TV *b, const TV *x, TV *r, int mod
 
 template <typename VT, typename TV, bool PC>
 static int cg_start_launch(const CsrView &A, const TV *b, const TV *x, TV *r, int mode, double *partials,
-                           const Ctl *ctl, hipStream_t st, const TV *dinv, int chunk) {
+                           Ctl *ctl, hipStream_t st, const TV *dinv, int chunk) {
   const int C = chunk > 0 ? chunk : wave_tile_chunk(A.n, A.nnz);
   if (C <= 5) return cg_start_c<VT, TV, 5, PC>(A, b, x, r, mode, partials, ctl, st, dinv);
   if (C <= 7) return cg_start_c<VT, TV, 7, PC>(A, b, x, r, mode, partials, ctl, st, dinv);
@@ -513,6 +551,13 @@ hipError_t launch_cg_iter(const CsrView &A, TV *x, TV *r, TV *p2, TV *q, double 
     else
       cg_iter_vt<double, TV, false>(A, x, r, P0, P1, q, partials, ctl, st, tm, serial, dinv, chunk);
   }
+  return hipGetLastError();
+}
+
+template <typename TV>
+hipError_t launch_cg_xfix(const CsrView &A, TV *x, TV *p2, Ctl *ctl, hipStream_t st) {
+  const int64_t ld = padded_ld(A.n);
+  hipLaunchKernelGGL((k_cg_xfix<TV>), dim3(kblocks(A.n)), dim3(KTPB), 0, st, x, p2, p2 + ld, A.n, ctl);
   return hipGetLastError();
 }
 
@@ -1593,6 +1638,7 @@ hipError_t launch_jacobi_dinv(const CsrView &A, TV *dinv, hipStream_t st) {
   template hipError_t launch_cg_iter<TV>(const CsrView &, TV *, TV *, TV *, TV *, double *, Ctl *, hipStream_t,  \
                                          const KTiming *, int, const TV *, int);                                 \
   template int cg_tile_tune<TV>(const CsrView &, const TV *, const TV *, TV *, double *, Ctl *, hipStream_t);    \
+  template hipError_t launch_cg_xfix<TV>(const CsrView &, TV *, TV *, Ctl *, hipStream_t);                       \
   template hipError_t launch_gm_start<TV>(const CsrView &, const TV *, const TV *, TV *, int, double *, Ctl *,   \
                                           hipStream_t);                                                          \
   template hipError_t launch_gm_step<TV>(const CsrView &, TV *, TV *, int64_t, int, int, double *, Ctl *,        \
