@@ -223,6 +223,9 @@ hipError_t launch_gen_sketch_bf16(unsigned short *G, int64_t n, int s, uint64_t 
 typedef short s4v __attribute__((ext_vector_type(4)));
 typedef float f4v __attribute__((ext_vector_type(4)));
 
+constexpr int PUSH_TPB = 512;  // eight waves per block: four per SIMD with the push grid's block count
+constexpr int PUSH_NW = PUSH_TPB / WAVE;
+
 // Push with the BF16 sketch.  Grid (nbx, ceil(s / 16)) as k_push, the same partial rows.
 // A wave takes chunks of 64 entries, PU of them per round (their loads issued together);
 // per chunk four v_mfma_f32_16x16x16bf16_1k with A = G[16 rows of the group][16 entries]
@@ -236,12 +239,12 @@ typedef float f4v __attribute__((ext_vector_type(4)));
 // columns when the block's partial row is formed.  The stored column X[:, slot] = TX(x)
 // is written by row group 0; the FP32 values reach the B lanes through the wave's LDS.
 template <typename TX>
-__global__ __launch_bounds__(TPB) void k_push_bf16(const double *x, TX *X, const unsigned short *G, int64_t n,
+__global__ __launch_bounds__(PUSH_TPB) void k_push_bf16(const double *x, TX *X, const unsigned short *G, int64_t n,
                                                    int64_t ld, int64_t lds, int slot, int s, double *partials,
                                                    const Ctl *ctl, int zero_rhs) {
   constexpr int PU = 8;
-  __shared__ __align__(16) float xf[NWAVE * PU * WAVE];
-  __shared__ double red[NWAVE * 3 * SKETCH_RG];
+  __shared__ __align__(16) float xf[PUSH_NW * PU * WAVE];
+  __shared__ double red[PUSH_NW * 3 * SKETCH_RG];
   const int g = blockIdx.y, r0 = g * SKETCH_RG;
   const int rc = (s - r0) < SKETCH_RG ? (s - r0) : SKETCH_RG;
   const int lane = threadIdx.x % WAVE, wid = threadIdx.x / WAVE;
@@ -250,9 +253,9 @@ __global__ __launch_bounds__(TPB) void k_push_bf16(const double *x, TX *X, const
   const bool zero = zero_rhs && ctl->state == ST_ZERO_RHS;
   double accd[4] = {0.0, 0.0, 0.0, 0.0};
   const int64_t nch = (n + WAVE - 1) / WAVE;  // chunks of 64 entries
-  const int64_t wstep = (int64_t)gridDim.x * NWAVE * PU;
+  const int64_t wstep = (int64_t)gridDim.x * PUSH_NW * PU;
   const unsigned short *grow = G + (size_t)(r0 + i16) * lds + 16 * kq;
-  for (int64_t c0 = ((int64_t)blockIdx.x * NWAVE + wid) * PU; c0 < nch; c0 += wstep) {
+  for (int64_t c0 = ((int64_t)blockIdx.x * PUSH_NW + wid) * PU; c0 < nch; c0 += wstep) {
     uint4 av[PU][2];
     double xv[PU];
 #pragma unroll
@@ -321,7 +324,7 @@ __global__ __launch_bounds__(TPB) void k_push_bf16(const double *x, TX *X, const
   const int blk = blockIdx.y * gridDim.x + blockIdx.x;
   if (threadIdx.x < rc) {
     double a = 0.0;
-    for (int w = 0; w < NWAVE; ++w)
+    for (int w = 0; w < PUSH_NW; ++w)
       for (int j = 0; j < 3; ++j) a += red[(w * 3 + j) * SKETCH_RG + threadIdx.x];
     partials[(size_t)blk * SKETCH_RG + threadIdx.x] = a;
   }
@@ -333,7 +336,7 @@ hipError_t launch_push_bf16(const double *x, TX *X, const unsigned short *G, dou
   (void)SX;
   const int ng = (s + SKETCH_RG - 1) / SKETCH_RG;
   const int nbx = push_blocks_x(n, s);
-  hipLaunchKernelGGL((k_push_bf16<TX>), dim3(nbx, ng), dim3(TPB), 0, st, x, X, G, n, ld, sketch_bf16_ld(n), slot, s,
+  hipLaunchKernelGGL((k_push_bf16<TX>), dim3(nbx, ng), dim3(PUSH_TPB), 0, st, x, X, G, n, ld, sketch_bf16_ld(n), slot, s,
                      partials, ctl, zero_rhs);
   return hipGetLastError();
 }
@@ -628,7 +631,7 @@ hipError_t launch_qrcp(double *SX, int s, int cnt, int newest, double tau, const
 template <int MC, typename TX>
 __global__ __launch_bounds__(TPB) void k_basis(const TX *X, TX *Q1, int64_t n, int64_t ld, int cnt,
                                                const Ctl *ctl) {
-  constexpr int NL = MC / 4, NC = MC / 16, RB = 4;
+  constexpr int NL = MC / 4, NC = MC / 16, RB = 2;
   const int k = ctl->k;
   const int lane = threadIdx.x % WAVE, wid = threadIdx.x / WAVE;
   const int i16 = lane % 16, kq = lane / 16;
@@ -676,7 +679,7 @@ __global__ __launch_bounds__(TPB) void k_basis(const TX *X, TX *Q1, int64_t n, i
 template <typename TX>
 hipError_t launch_basis(const TX *X, TX *Q1, int64_t n, int64_t ld, int cnt, Ctl *ctl, hipStream_t st) {
   static int cache16 = 0, cache32 = 0;
-  const int64_t waves = ((n + 15) / 16 + 3) / 4;  // rounds of 4 row blocks
+  const int64_t waves = ((n + 15) / 16 + 1) / 2;  // rounds of 2 row blocks
   int64_t want = (waves + NWAVE - 1) / NWAVE;
   if (cnt <= 16) {
     const int res = resident_blocks((const void *)k_basis<16, TX>, TPB, cache16);
