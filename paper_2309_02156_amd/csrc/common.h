@@ -632,10 +632,22 @@ __device__ inline void wave_lds_sync() {
 // hold at least one entry even for a matrix without nonzeros (callers pass stand-ins),
 // and the loads of the last tile's successor re-read the last tile.  lcol / lval: the
 // wave's LDS slices of WT_CAP entries.
+// The row pointers of a wave's first tile, for a caller that requests them before its
+// own prologue (wave_tiles_spmv's `first` argument); in bounds for any t.
+struct TileRows0 {
+  int a, b;
+};
+__device__ inline TileRows0 wave_tile_first_rows(const int *__restrict__ rowptr, int64_t n, int64_t t) {
+  const int64_t i = t * WAVE + threadIdx.x % WAVE;
+  const int64_t ic = i < n ? i : n - 1;
+  return TileRows0{rowptr[ic], rowptr[ic + 1]};
+}
+
 template <int C, typename VT, typename G, typename PRE, typename EPI>
 __device__ inline void wave_tiles_spmv(const int *__restrict__ rowptr, const int *__restrict__ col,
                                        const VT *__restrict__ val, const G &gx, int64_t n, int64_t t, int64_t end,
-                                       int64_t step, int *lcol, VT *lval, const PRE &pre, const EPI &epi) {
+                                       int64_t step, int *lcol, VT *lval, const PRE &pre, const EPI &epi,
+                                       const TileRows0 *first = nullptr) {
   using XT = decltype(gx(0));
   const int lane = threadIdx.x % WAVE;
   if (t >= end) return;
@@ -672,7 +684,12 @@ __device__ inline void wave_tiles_spmv(const int *__restrict__ rowptr, const int
       }
     }
   };
-  load_rows(t, a, b);
+  if (first) {
+    a = first->a;
+    b = first->b;
+  } else {
+    load_rows(t, a, b);
+  }
   tile_range(t, a, b, p0, p1);
   load_round(p0, p1, cc, vv);
   for (;;) {

@@ -259,8 +259,11 @@ __global__ __launch_bounds__(KTPB) void k_cg_p(const int *rowptr, const int *col
   __shared__ int s_k, s_fresh, s_go, s_cont, s_maxit, s_xpend;
   __shared__ double s_beta, s_tolb, s_rho2, s_alpha;
   // r^T r (and r^T z) of the previous iteration (unused when the direction restarts),
-  // loaded together with the control block
+  // loaded together with the control block, and the row pointers of this wave's first
+  // tile (they arrive during the prologue)
   const double part = final_part<2>(Pin, nblk, KW, PC ? 2 : 1);
+  const WaveTiles wt = wave_tiles(n);
+  const TileRows0 first = wave_tile_first_rows(rowptr, n, wt.t < wt.end ? wt.t : 0);
   if (threadIdx.x == 0) {
     // every control-block read of the kernel, issued together
     const int st = ctl->state, it = ctl->iters, fa = ctl->fresh_at, mx = ctl->maxit;
@@ -316,7 +319,6 @@ __global__ __launch_bounds__(KTPB) void k_cg_p(const int *rowptr, const int *col
   VT *lv = lval + (size_t)wid * WT_CAP;
   (void)lane;
   double acc[1] = {0.0};
-  const WaveTiles wt = wave_tiles(n);
   // the row's own direction entry is requested with the tile's gathers (exact: gx rounds
   // to TV); the next tile's index loads overlap this tile's gathers
   wave_tiles_spmv<C>(
@@ -328,7 +330,8 @@ __global__ __launch_bounds__(KTPB) void k_cg_p(const int *rowptr, const int *col
         q[i] = qs;
         acc[0] += (double)ps * (double)qs;
         if (xpend) x[i] = (TV)((double)x[i] + alpha * (double)pin[i]);
-      });
+      },
+      &first);
   kstore<1>(acc, 1, red, Pout + (size_t)blockIdx.x * KW);
 }
 
@@ -364,6 +367,18 @@ __global__ __launch_bounds__(KTPB) void k_cg_xr(TV *x, TV *r, const TV *P0, cons
   __shared__ int s_k, s_go, s_st;
   __shared__ double s_rho;
   const double part = final_part<2>(Pin, nblk, KW, 1);  // p^T q, loaded with the control block
+  // the first pass's r and q (they do not depend on alpha) go out before the reduction
+  // (loads at clamped indices, unconditional; unused when the solve has stopped)
+  TV r1[U], q1[U], d1[U];
+  const int64_t rfirst = (int64_t)blockIdx.x * (U * KTPB);
+#pragma unroll
+  for (int u = 0; u < U; ++u) {
+    const int64_t i = rfirst + (int64_t)u * KTPB + threadIdx.x;
+    const int64_t ic = i < n ? i : n - 1;
+    r1[u] = r[ic];
+    q1[u] = q[ic];
+    if constexpr (PC) d1[u] = dinv[ic];
+  }
   if (threadIdx.x == 0) {
     const int st = ctl->state, k = ctl->kcur;
     double r4[4];
@@ -400,15 +415,16 @@ __global__ __launch_bounds__(KTPB) void k_cg_xr(TV *x, TV *r, const TV *P0, cons
   // next p / q kernel (or the fix-up kernel)
   constexpr int K = PC ? 2 : 1;
   double acc[K] = {};
-  for (int64_t r0 = (int64_t)blockIdx.x * (U * KTPB); r0 < n; r0 += (int64_t)gridDim.x * (U * KTPB)) {
+  for (int64_t r0 = rfirst; r0 < n; r0 += (int64_t)gridDim.x * (U * KTPB)) {
     double rv[U], qv[U], dv[U];
 #pragma unroll
     for (int u = 0; u < U; ++u) {
       const int64_t i = r0 + (int64_t)u * KTPB + threadIdx.x;
       const int64_t ic = i < n ? i : n - 1;
-      rv[u] = (double)r[ic];
-      qv[u] = (double)q[ic];
-      if constexpr (PC) dv[u] = (double)dinv[ic];
+      const bool pre = r0 == rfirst;
+      rv[u] = (double)(pre ? r1[u] : r[ic]);
+      qv[u] = (double)(pre ? q1[u] : q[ic]);
+      if constexpr (PC) dv[u] = (double)(pre ? d1[u] : dinv[ic]);
     }
 #pragma unroll
     for (int u = 0; u < U; ++u) {
