@@ -188,6 +188,9 @@ int sa_initial_guess(sa_seq *q, const sa_csr *A, const void *b_dev, void *x0_dev
  * vectors until the solver's own residual estimate is below inner_tol ||fl32(r)|| (no
  * true-residual confirmation: the next sweep's residual checks the result) or
  * inner_maxit iterations, and updates x += d (iters sums the inner iterations).
+ * CG tunes its SpMV tile shape on the first solve of an operator shape (n, nnz, value
+ * and vector types) by timing a few launches that change no solver state (cached for
+ * the process; the environment variable SACC_CG_CHUNK = 5, 7 or 9 pins it).
  * Waits for the stream; fills info if non-NULL (iters, restarts, refinements,
  * relres0, relres, status, ms_solve).  Returns SA_OK, SA_NOTCONV or an error code. */
 int sa_solve(sa_seq *q, const sa_csr *A, const void *b_dev, void *x_dev, sa_info *info,
