@@ -466,7 +466,7 @@ def learned_cmp(sacc, torch, np, n_train, n_eval, epochs=60, batch=32, n_hist=8)
     return out
 
 
-def batch_cmp(sacc, torch, np, warmup, steps, max_streams=4, seed=4, nseq=64, precision=None):
+def batch_cmp(sacc, torch, np, warmup, steps, max_streams=8, seed=4, nseq=64, precision=None):
     """The batched workload: 64 independent 2-D sequences (sides U{96..768}, M in
     {8, 16, 24}, half advective with GMRES(30), the rest CG), float32 values with FP64
     refinement to 1e-8, stepped together by the library's batch driver on up to
@@ -543,7 +543,8 @@ def main():
     ap.add_argument("--only-headline", action="store_true", help="the headline workload only (no other workloads)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="run 3 plain 256 MiB device copies first (reference for HBM byte counters)")
-    ap.add_argument("--batch-warmup", type=int, default=2)
+    ap.add_argument("--batch-warmup", type=int, default=9,
+                    help="batch steps after the histories fill, before timing (the plan tuner times 9 candidates)")
     ap.add_argument("--batch-steps", type=int, default=4)
     ap.add_argument("--no-batch", action="store_true")
     ap.add_argument("--only-batch", action="store_true", help="run only the batched workload")

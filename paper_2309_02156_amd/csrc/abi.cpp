@@ -8,6 +8,8 @@
 #include <algorithm>
 #include <chrono>
 #include <climits>
+#include <condition_variable>
+#include <functional>
 #include <mutex>
 #include <new>
 #include <string>
@@ -1491,7 +1493,7 @@ struct Plan {
 };
 
 // candidates the autotuner times, one step each (after the history is full)
-const Plan kCandidates[] = {{1, 8}, {2, 8}, {4, 8}, {4, 4}, {4, 16}, {4, 30}, {2, 16}};
+const Plan kCandidates[] = {{1, 8}, {2, 8}, {4, 8}, {4, 4}, {4, 16}, {4, 30}, {2, 16}, {8, 8}, {8, 16}};
 constexpr int kNumCandidates = sizeof(kCandidates) / sizeof(kCandidates[0]);
 
 }  // namespace batchplan
@@ -1500,9 +1502,22 @@ using batchplan::Plan;
 using batchplan::kCandidates;
 using batchplan::kNumCandidates;
 
+// The batch's host threads: one per stream beyond the caller's, created with the batch
+// and kept; a step hands each of them its list through a generation counter.
+struct BatchPool {
+  std::vector<std::thread> th;
+  std::mutex mu;
+  std::condition_variable go, done;
+  long long gen = 0;
+  int active = 0, pending = 0;
+  bool stop = false;
+  std::function<void(int)> job;
+};
+
 struct sa_batch {
   std::vector<sa_seq *> seqs;
   std::vector<hipStream_t> streams;
+  BatchPool pool;
   std::vector<double> cost;  // estimated cost of a sequence's step (nnz x (iterations + 10))
   Plan plan{4, 8};
   int tune_next = 0;        // next candidate to time; kNumCandidates when tuned
@@ -1533,12 +1548,36 @@ int sa_batch_create(sa_seq *const *seqs, int nseq, int max_streams, int tune_war
   b->plan = Plan{max_streams, 8};
   b->tune_warm = tune_warmup;
   b->tune_next = 0;
+  BatchPool &P = b->pool;
+  for (int s = 1; s < max_streams; ++s)
+    P.th.emplace_back([&P, s] {
+      long long seen = 0;
+      for (;;) {
+        std::unique_lock<std::mutex> lk(P.mu);
+        P.go.wait(lk, [&] { return P.stop || P.gen != seen; });
+        if (P.stop) return;
+        seen = P.gen;
+        const bool mine = s < P.active;
+        lk.unlock();
+        if (mine) {
+          P.job(s);
+          std::lock_guard<std::mutex> g(P.mu);
+          if (--P.pending == 0) P.done.notify_one();
+        }
+      }
+    });
   *out = b;
   return SA_OK;
 }
 
 int sa_batch_destroy(sa_batch *b) {
   if (!b) return SA_EINVAL;
+  {
+    std::lock_guard<std::mutex> lk(b->pool.mu);
+    b->pool.stop = true;
+  }
+  b->pool.go.notify_all();
+  for (auto &t : b->pool.th) t.join();
   for (auto &s : b->streams)
     if (s) (void)hipStreamDestroy(s);
   delete b;
@@ -1604,10 +1643,21 @@ int sa_batch_step(sa_batch *b, const sa_csr *const *A, const void *const *rhs, v
     }
   };
   const auto t0 = std::chrono::steady_clock::now();
-  std::vector<std::thread> th;
-  for (int s = 1; s < plan.streams; ++s) th.emplace_back(worker, s);
+  BatchPool &P = b->pool;
+  {
+    std::lock_guard<std::mutex> lk(P.mu);
+    P.job = worker;
+    P.active = plan.streams;
+    P.pending = plan.streams - 1;
+    P.gen += 1;
+  }
+  P.go.notify_all();
   worker(0);
-  for (auto &t : th) t.join();
+  {
+    std::unique_lock<std::mutex> lk(P.mu);
+    P.done.wait(lk, [&] { return P.pending == 0; });
+    P.job = nullptr;
+  }
   const double sec = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
   for (int s = 0; s < plan.streams; ++s)
     if (rc[s] != SA_OK) return rc[s];
