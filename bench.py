@@ -476,7 +476,8 @@ def batch_cmp(sacc, torch, np, warmup, steps, max_streams=8, seed=4, nseq=64, pr
 
     probs = batch_problems(seed=seed, nseq=nseq, steps=100)
     fill = max(m["M"] for _, m in probs)
-    total = fill + warmup + steps
+    extra = 2  # steps of each fixed mode after the tuned ones
+    total = fill + warmup + steps + 2 * extra
     log(f"batch: staging {total} steps of {nseq} sequences")
     sts, seqs, xs = [], [], []
     nnz_tot, n_tot = 0, 0
@@ -504,7 +505,7 @@ def batch_cmp(sacc, torch, np, warmup, steps, max_streams=8, seed=4, nseq=64, pr
     by_solver = {"cg": 0, "gmres": 0}
     longest = 0
     per_seq = [0] * len(probs)
-    for i in range(fill + warmup, total):
+    for i in range(fill + warmup, fill + warmup + steps):
         infos = run(i)
         its += sum(d["iters"] for d in infos)
         for j, d in enumerate(infos):
@@ -517,6 +518,21 @@ def batch_cmp(sacc, torch, np, warmup, steps, max_streams=8, seed=4, nseq=64, pr
     wall = time.perf_counter() - t0
     top = sorted(range(len(probs)), key=lambda j: -per_seq[j])[:5]
     plan = batch.plan()
+    # the next steps in each fixed mode: every solve on its own stream, then all solves
+    # in the segmented engine (graph replays)
+    fixed = {}
+    k = fill + warmup + steps
+    for mode in ("streams", "segmented"):
+        batch.set_mode(mode)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        its_m = 0
+        for _ in range(extra):
+            its_m += sum(d["iters"] for d in run(k))
+            k += 1
+        torch.cuda.synchronize()
+        fixed[mode] = dict(ms_per_step=round(1e3 * (time.perf_counter() - t1) / extra, 3),
+                           krylov_iters_per_step=its_m / extra, steps=f"{k - extra}..{k - 1}")
     batch.close()
     for s in seqs:
         s.close()
@@ -524,13 +540,13 @@ def batch_cmp(sacc, torch, np, warmup, steps, max_streams=8, seed=4, nseq=64, pr
                          f"M in {{8,16,24}}, half GMRES(30) / half CG, float32 operator and Krylov vectors + FP64 "
                          f"refinement ({precision or probs[0][1]['prec']}, at most "
                          f"{probs[0][1]['max_refine']} sweeps), relres 1e-8",
-                steps_timed=f"{fill + warmup}..{total - 1}", ms_per_step=round(1e3 * wall / steps, 3),
+                steps_timed=f"{fill + warmup}..{fill + warmup + steps - 1}", ms_per_step=round(1e3 * wall / steps, 3),
                 krylov_iters_per_step=its / steps, relres_max=rel,
                 iters_per_step_by_solver={k: v / steps for k, v in by_solver.items()},
                 longest_sequence_iters_per_step=longest / steps,
                 heaviest_sequences=[dict(n=probs[j][0].n, solver=probs[j][1]["solver"],
                                          iters_per_step=per_seq[j] / steps) for j in top],
-                not_converged=int(sum(1 for s_ in stat if s_ != 0)), plan=plan)
+                not_converged=int(sum(1 for s_ in stat if s_ != 0)), plan=plan, fixed_modes=fixed)
 
 
 def main():
@@ -543,8 +559,8 @@ def main():
     ap.add_argument("--only-headline", action="store_true", help="the headline workload only (no other workloads)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="run 3 plain 256 MiB device copies first (reference for HBM byte counters)")
-    ap.add_argument("--batch-warmup", type=int, default=9,
-                    help="batch steps after the histories fill, before timing (the plan tuner times 9 candidates)")
+    ap.add_argument("--batch-warmup", type=int, default=11,
+                    help="batch steps after the histories fill, before timing (the plan tuner times 11 candidates)")
     ap.add_argument("--batch-steps", type=int, default=4)
     ap.add_argument("--no-batch", action="store_true")
     ap.add_argument("--only-batch", action="store_true", help="run only the batched workload")

@@ -309,8 +309,33 @@ int sa_batch_destroy(sa_batch *b);
 int sa_batch_step(sa_batch *b, const sa_csr *const *A, const void *const *rhs, void *const *x,
                   sa_info *info);
 
-/* The plan in use and whether tuning has finished. */
-int sa_batch_plan(const sa_batch *b, int *streams, int *poll, int *tuned);
+/* The plan in use, whether tuning has finished (always, in a fixed mode) and whether the
+ * solves run in the segmented engine. */
+int sa_batch_plan(const sa_batch *b, int *streams, int *poll, int *tuned, int *segmented);
+
+/* Execution of a batch's solves.
+ *   SA_BATCH_AUTO: the tuner times the stream plans and, where every sequence is
+ *     SA_MIXED or SA_MIXED_KRYLOV without a preconditioner, the segmented ones, and
+ *     keeps the fastest (the default);
+ *   SA_BATCH_STREAMS: every sequence's solve on its own stream (max_streams threads);
+ *   SA_BATCH_SEGMENTED: the solves of all sequences advanced together by the
+ *     segmented engine: per engine step one launch over the rows of every unfinished
+ *     system and one launch with a block per system that reduces its partial sums and
+ *     picks its next phase (residual, CG or GMRES inner step, update), the systems'
+ *     phases and scalars kept in device memory; the host replays a captured hipGraph of
+ *     16 engine steps until every system has stopped.  Same method, stopping rules and
+ *     counts as sa_solve's mixed mode (GMRES with classical Gram-Schmidt twice), with
+ *     its own reduction order;
+ *   SA_BATCH_SEGMENTED_EAGER: the same launches without the graph (bitwise the same
+ *     results).
+ * The guesses and pushes of a segmented step run on the batch's streams.  A step whose
+ * matrices include one without nonzeros runs on streams.  Errors: SA_EINVAL (segmented
+ * modes for a batch with an FP64 or preconditioned sequence). */
+#define SA_BATCH_AUTO 0
+#define SA_BATCH_STREAMS 1
+#define SA_BATCH_SEGMENTED 2
+#define SA_BATCH_SEGMENTED_EAGER 3
+int sa_batch_set_mode(sa_batch *b, int mode);
 
 /* Copy internal state to host memory for inspection:
  *   what = 0: SX, s x M float64 column-major, columns in ring-slot order;

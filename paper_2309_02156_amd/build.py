@@ -11,7 +11,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libsacc.so")
-SOURCES = ["kernels.hip", "krylov.hip", "mlp.hip", "abi.cpp"]
+SOURCES = ["kernels.hip", "krylov.hip", "segmented.hip", "mlp.hip", "abi.cpp"]
 
 # -packed-fp32-ops: keep the compiler from forming packed FP32 instructions.
 FLAGS = [

@@ -1488,12 +1488,17 @@ int sa_solve_static(const sa_config *cfg, const sa_csr *A, const void *b_dev, vo
 
 namespace batchplan {
 
+// streams: host threads / streams in use; poll: Krylov steps enqueued ahead (stream
+// plans); seg: the solves run in the segmented engine (the streams then carry the
+// guesses and pushes)
 struct Plan {
-  int streams, poll;
+  int streams, poll, seg;
 };
 
-// candidates the autotuner times, one step each (after the history is full)
-const Plan kCandidates[] = {{1, 8}, {2, 8}, {4, 8}, {4, 4}, {4, 16}, {4, 30}, {2, 16}, {8, 8}, {8, 16}};
+// candidates the autotuner times, one step each (after the history is full); the
+// segmented ones only where every sequence can use the engine
+const Plan kCandidates[] = {{1, 8, 0}, {2, 8, 0}, {4, 8, 0}, {4, 4, 0},  {4, 16, 0}, {4, 30, 0},
+                            {2, 16, 0}, {8, 8, 0}, {8, 16, 0}, {4, 8, 1}, {8, 8, 1}};
 constexpr int kNumCandidates = sizeof(kCandidates) / sizeof(kCandidates[0]);
 
 }  // namespace batchplan
@@ -1519,13 +1524,138 @@ struct sa_batch {
   std::vector<hipStream_t> streams;
   BatchPool pool;
   std::vector<double> cost;  // estimated cost of a sequence's step (nnz x (iterations + 10))
-  Plan plan{4, 8};
+  Plan plan{4, 8, 0};
   int tune_next = 0;        // next candidate to time; kNumCandidates when tuned
   int tune_warm = 0;        // steps before timing starts (history filling)
   double tune_best = 1e300;
-  Plan tune_best_plan{4, 8};
+  Plan tune_best_plan{4, 8, 0};
   long long steps = 0;
+  int mode = SA_BATCH_AUTO;
+  bool seg_ok = false;        // every sequence is mixed-precision without a preconditioner
+  SegEngine *seg = nullptr;   // created on first segmented step
 };
+
+namespace {
+
+// job(s) for s in [0, nthreads) on the batch's threads (job(0) on the caller's)
+void pool_run(sa_batch *b, int nthreads, const std::function<void(int)> &job) {
+  BatchPool &P = b->pool;
+  {
+    std::lock_guard<std::mutex> lk(P.mu);
+    P.job = job;
+    P.active = nthreads;
+    P.pending = nthreads - 1;
+    P.gen += 1;
+  }
+  P.go.notify_all();
+  job(0);
+  std::unique_lock<std::mutex> lk(P.mu);
+  P.done.wait(lk, [&] { return P.pending == 0; });
+  P.job = nullptr;
+}
+
+void guess_into(sa_info &dst, const sa_info &g) {
+  dst.k_eff = g.k_eff;
+  dst.k_sketch = g.k_sketch;
+  dst.used_fallback = g.used_fallback;
+  dst.history = g.history;
+  dst.ms_guess = g.ms_guess;
+}
+
+// One step with the solves in the segmented engine: the guesses on the plan's streams
+// (each stream waits for its own), the solves of all sequences together on stream 0,
+// then the pushes on the plan's streams.
+int batch_step_seg(sa_batch *b, const Plan &plan, const std::vector<std::vector<int>> &lists, const sa_csr *const *A,
+                   const void *const *rhs, void *const *x, std::vector<sa_info> &inf, bool graph) {
+  const int nseq = (int)b->seqs.size();
+  std::vector<int> rc(plan.streams, SA_OK);
+  pool_run(b, plan.streams, [&](int s) {
+    hipStream_t st = b->streams[s];
+    for (int i : lists[s]) {
+      memset(&inf[i], 0, sizeof(sa_info));
+      sa_info g;
+      memset(&g, 0, sizeof(g));
+      int r = sa_initial_guess(b->seqs[i], A[i], rhs[i], x[i], &g, st);
+      if (r == SA_OK) r = hipStreamSynchronize(st) == hipSuccess ? SA_OK : SA_EHIP;
+      guess_into(inf[i], g);
+      if (r != SA_OK) {
+        rc[s] = r;
+        return;
+      }
+    }
+  });
+  for (int r : rc)
+    if (r != SA_OK) return r;
+  if (!b->seg) {
+    std::vector<int64_t> ns(nseq);
+    int64_t tn = 0, tnnz = 0;
+    for (int i = 0; i < nseq; ++i) {
+      ns[i] = b->seqs[i]->cfg.n;
+      tn += A[i]->n;
+      tnnz += A[i]->nnz;
+    }
+    if (seg_engine_create(ns.data(), nseq, wave_tile_chunk(tn, tnnz), &b->seg) != 0) return SA_ENOMEM;
+  }
+  std::vector<SegDesc> desc(nseq);
+  for (int i = 0; i < nseq; ++i) {
+    const sa_seq *q = b->seqs[i];
+    const sa_config &c = q->cfg;
+    SegDesc &d = desc[i];
+    memset(&d, 0, sizeof(d));
+    d.rowptr = A[i]->rowptr_dev;
+    d.col = A[i]->col_dev;
+    d.val = (const float *)A[i]->val_dev;
+    d.b = (const double *)rhs[i];
+    d.x = (double *)x[i];
+    d.kry = (float *)q->kry;
+    d.r32 = q->r32;
+    d.d32 = q->d32;
+    d.n = c.n;
+    d.ld = q->ld;
+    d.solver = c.solver;
+    d.m = c.solver == SA_GMRES ? c.restart : 0;
+    d.max_refine = c.max_refine;
+    d.maxit = c.maxit;
+    d.icap = inner_cap(c);
+    d.tol = c.tol;
+    d.itol = c.inner_tol;
+  }
+  hipStream_t st = b->streams[0];
+  std::vector<SegResult> res(nseq);
+  const auto t0 = std::chrono::steady_clock::now();
+  if (seg_engine_solve(b->seg, desc.data(), graph, st, res.data()) != hipSuccess) return SA_EHIP;
+  for (int i = 0; i < nseq; ++i)
+    if (res[i].state == ST_ZERO_RHS) HIP_TRY(hipMemsetAsync(x[i], 0, (size_t)desc[i].n * sizeof(double), st));
+  HIP_TRY(hipStreamSynchronize(st));
+  const float ms = (float)(1e3 * std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count());
+  for (int i = 0; i < nseq; ++i) {
+    const SegResult &r = res[i];
+    if (r.state < ST_RUN || r.state > ST_ZERO_RHS) return SA_EHIP;
+    inf[i].iters = r.iters;
+    inf[i].restarts = r.restarts;
+    inf[i].refinements = r.sweeps;
+    inf[i].relres0 = r.relres0;
+    inf[i].relres = r.state == ST_ZERO_RHS ? 0.0 : r.relres;
+    inf[i].status = status_of(r.state);
+    inf[i].ms_solve = ms;
+  }
+  pool_run(b, plan.streams, [&](int s) {
+    hipStream_t sp = b->streams[s];
+    for (int i : lists[s]) {
+      int r = sa_push_solution(b->seqs[i], x[i], sp);
+      if (r == SA_OK) r = hipStreamSynchronize(sp) == hipSuccess ? SA_OK : SA_EHIP;
+      if (r != SA_OK) {
+        rc[s] = r;
+        return;
+      }
+    }
+  });
+  for (int r : rc)
+    if (r != SA_OK) return r;
+  return SA_OK;
+}
+
+}  // namespace
 
 extern "C" {
 
@@ -1545,7 +1675,10 @@ int sa_batch_create(sa_seq *const *seqs, int nseq, int max_streams, int tune_war
       delete b;
       return SA_EHIP;
     }
-  b->plan = Plan{max_streams, 8};
+  b->plan = Plan{max_streams, 8, 0};
+  b->seg_ok = true;
+  for (int i = 0; i < nseq; ++i)
+    b->seg_ok = b->seg_ok && seqs[i]->mixed && seqs[i]->cfg.precond == SA_PRECOND_NONE;
   b->tune_warm = tune_warmup;
   b->tune_next = 0;
   BatchPool &P = b->pool;
@@ -1578,17 +1711,27 @@ int sa_batch_destroy(sa_batch *b) {
   }
   b->pool.go.notify_all();
   for (auto &t : b->pool.th) t.join();
+  if (b->seg) seg_engine_destroy(b->seg);
   for (auto &s : b->streams)
     if (s) (void)hipStreamDestroy(s);
   delete b;
   return SA_OK;
 }
 
-int sa_batch_plan(const sa_batch *b, int *streams, int *poll, int *tuned) {
-  if (!b || !streams || !poll || !tuned) return SA_EINVAL;
+int sa_batch_plan(const sa_batch *b, int *streams, int *poll, int *tuned, int *segmented) {
+  if (!b || !streams || !poll || !tuned || !segmented) return SA_EINVAL;
   *streams = b->plan.streams;
   *poll = b->plan.poll;
-  *tuned = b->tune_next >= kNumCandidates ? 1 : 0;
+  *tuned = (b->mode != SA_BATCH_AUTO || b->tune_next >= kNumCandidates) ? 1 : 0;
+  *segmented = b->plan.seg;
+  return SA_OK;
+}
+
+int sa_batch_set_mode(sa_batch *b, int mode) {
+  if (!b || mode < SA_BATCH_AUTO || mode > SA_BATCH_SEGMENTED_EAGER) return SA_EINVAL;
+  if ((mode == SA_BATCH_SEGMENTED || mode == SA_BATCH_SEGMENTED_EAGER) && !b->seg_ok) return SA_EINVAL;
+  b->mode = mode;
+  if (mode != SA_BATCH_AUTO) b->plan = Plan{(int)b->streams.size(), 8, mode == SA_BATCH_STREAMS ? 0 : 1};
   return SA_OK;
 }
 
@@ -1597,11 +1740,17 @@ int sa_batch_step(sa_batch *b, const sa_csr *const *A, const void *const *rhs, v
   const int nseq = (int)b->seqs.size();
   for (int i = 0; i < nseq; ++i)
     if (!A[i] || !rhs[i] || !x[i]) return SA_EINVAL;
-  // plan of this step: a candidate while tuning, else the chosen one
-  const bool timing = b->steps >= b->tune_warm && b->tune_next < kNumCandidates;
+  // plan of this step: a candidate while tuning, else the chosen one (segmented
+  // candidates are skipped for a batch the engine cannot take)
+  if (b->mode == SA_BATCH_AUTO && !b->seg_ok)
+    while (b->tune_next < kNumCandidates && kCandidates[b->tune_next].seg) ++b->tune_next;
+  const bool timing = b->mode == SA_BATCH_AUTO && b->steps >= b->tune_warm && b->tune_next < kNumCandidates;
   Plan plan = b->plan;
   if (timing) plan = kCandidates[b->tune_next];
   if (plan.streams > (int)b->streams.size()) plan.streams = (int)b->streams.size();
+  // the engine needs at least one nonzero per matrix (its SpMV tiles read entry 0)
+  bool seg = plan.seg != 0 && b->seg_ok;
+  for (int i = 0; i < nseq && seg; ++i) seg = A[i]->nnz > 0 && A[i]->val_is_fp32 && A[i]->n == b->seqs[i]->cfg.n;
   // longest processing time first: sequences by decreasing cost to the least loaded stream
   std::vector<int> order(nseq);
   for (int i = 0; i < nseq; ++i) order[i] = i;
@@ -1624,6 +1773,7 @@ int sa_batch_step(sa_batch *b, const sa_csr *const *A, const void *const *rhs, v
       q->cfg.poll = plan.poll;
       memset(&inf[i], 0, sizeof(sa_info));
       sa_info g;
+      memset(&g, 0, sizeof(g));
       int r = sa_initial_guess(q, A[i], rhs[i], x[i], &g, st);
       if (r == SA_OK) {
         r = sa_solve(q, A[i], rhs[i], x[i], &inf[i], st);
@@ -1631,11 +1781,7 @@ int sa_batch_step(sa_batch *b, const sa_csr *const *A, const void *const *rhs, v
       }
       if (r == SA_OK) r = sa_push_solution(q, x[i], st);
       if (r == SA_OK) r = hipStreamSynchronize(st) == hipSuccess ? SA_OK : SA_EHIP;
-      inf[i].k_eff = g.k_eff;
-      inf[i].k_sketch = g.k_sketch;
-      inf[i].used_fallback = g.used_fallback;
-      inf[i].history = g.history;
-      inf[i].ms_guess = g.ms_guess;
+      guess_into(inf[i], g);
       if (r != SA_OK) {
         rc[s] = r;
         return;
@@ -1643,20 +1789,11 @@ int sa_batch_step(sa_batch *b, const sa_csr *const *A, const void *const *rhs, v
     }
   };
   const auto t0 = std::chrono::steady_clock::now();
-  BatchPool &P = b->pool;
-  {
-    std::lock_guard<std::mutex> lk(P.mu);
-    P.job = worker;
-    P.active = plan.streams;
-    P.pending = plan.streams - 1;
-    P.gen += 1;
-  }
-  P.go.notify_all();
-  worker(0);
-  {
-    std::unique_lock<std::mutex> lk(P.mu);
-    P.done.wait(lk, [&] { return P.pending == 0; });
-    P.job = nullptr;
+  if (seg) {
+    const int r = batch_step_seg(b, plan, lists, A, rhs, x, inf, b->mode != SA_BATCH_SEGMENTED_EAGER);
+    if (r != SA_OK) return r;
+  } else {
+    pool_run(b, plan.streams, worker);
   }
   const double sec = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
   for (int s = 0; s < plan.streams; ++s)

@@ -214,4 +214,39 @@ int64_t padded_ld(int64_t n);
 // partial-buffer size (doubles) the launchers above need for a problem of size n
 size_t partials_doubles(int64_t n, int M, int s);
 
+
+// ---- segmented solve of many independent mixed-precision systems (batched step)
+// FP64 refinement around float32 CG / GMRES(m) inner solves for every system of a
+// batch in lockstep: one data launch over all systems' rows and one close launch (a
+// block per system) per engine step; per-system phase and scalars live in device
+// memory.  Each system uses its sequence's own float32 work vectors: kry holds
+// max(4, m + 2) columns of ld entries (CG: r, p, p', q; GMRES: V_0..V_m, w), r32 and
+// d32 one column each.
+struct SegDesc {
+  const int *rowptr, *col;
+  const float *val;   // float32 operator values (at least one nonzero)
+  const double *b;
+  double *x;          // in: the initial guess; out: the solution
+  float *kry, *r32, *d32;
+  double *part;       // set by the engine
+  int64_t n, ld;
+  int nblk;           // set by the engine
+  int solver, m, max_refine, maxit, icap;
+  double tol, itol;
+};
+// state: ST_CONV / ST_MAXIT / ST_BREAK / ST_ZERO_RHS (x is left to the caller to zero)
+struct SegResult {
+  int state, iters, restarts, sweeps;
+  double relres0, relres;
+};
+struct SegEngine;
+// an engine for systems of sizes n[0..nseg); chunk: gathers per lane of its SpMV tiles
+// (5, 7 or 9).  Returns 0, or -1 when device or pinned memory is short.
+int seg_engine_create(const int64_t *n, int nseg, int chunk, SegEngine **out);
+void seg_engine_destroy(SegEngine *e);
+// Solves every system (desc[i].n must equal the engine's n[i]) on stream st, eager
+// launches or replays of one captured hipGraph per chunk of steps; synchronous.
+hipError_t seg_engine_solve(SegEngine *e, const SegDesc *desc, bool graph, hipStream_t st, SegResult *res);
+int seg_rows_per_block();
+
 }  // namespace sacc

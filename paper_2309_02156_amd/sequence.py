@@ -353,7 +353,14 @@ class Batch:
         nv.check(nv.lib().sa_batch_step(self._h, Aarr, barr, xarr, infos), "sa_batch_step")
         return [i.as_dict() for i in infos]
 
+    MODES = {"auto": 0, "streams": 1, "segmented": 2, "segmented_eager": 3}
+
+    def set_mode(self, mode: str):
+        """"auto" (tuned), "streams", "segmented" (graph replays) or "segmented_eager"."""
+        nv.check(nv.lib().sa_batch_set_mode(self._h, self.MODES[mode]), "sa_batch_set_mode")
+
     def plan(self):
-        s, p, t = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32()
-        nv.check(nv.lib().sa_batch_plan(self._h, ctypes.byref(s), ctypes.byref(p), ctypes.byref(t)), "sa_batch_plan")
-        return dict(streams=s.value, poll=p.value, tuned=bool(t.value))
+        s, p, t, g = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32()
+        nv.check(nv.lib().sa_batch_plan(self._h, ctypes.byref(s), ctypes.byref(p), ctypes.byref(t), ctypes.byref(g)),
+                 "sa_batch_plan")
+        return dict(streams=s.value, poll=p.value, tuned=bool(t.value), segmented=bool(g.value))

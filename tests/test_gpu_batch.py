@@ -1,9 +1,11 @@
 """GPU tests of the batched execution of independent sequences (sa_batch_*).
 
-The batch runs the same kernels as one sequence at a time, only on several streams at
+On streams the batch runs the same kernels as one sequence at a time, only several at
 once, so its solutions and iteration counts must equal those of the sequences stepped
-one by one (bit for bit); every solve meets the FP64 tolerance against its float32
-operator; the plan autotuner ends with a tuned plan.
+one by one (bit for bit).  The segmented engine (all solves in lockstep launches) is
+checked against the oracle per sequence like the stream plan, and its graph replays
+against its eager launches bit for bit.  Every solve meets the FP64 tolerance against
+its float32 operator; the plan autotuner ends with a tuned plan.
 """
 
 import numpy as np
@@ -31,7 +33,7 @@ def _seq(sacc, p, m):
                          max_refine=m["max_refine"])
 
 
-def test_batch_equals_sequential_and_tunes(sacc):
+def test_batch_streams_equals_sequential(sacc):
     import torch
 
     probs = batch_problems(seed=4, nseq=6, lo=16, hi=40, steps=40)
@@ -40,6 +42,7 @@ def test_batch_equals_sequential_and_tunes(sacc):
     seqs_b = [_seq(sacc, p, m) for p, m in probs]
     seqs_s = [_seq(sacc, p, m) for p, m in probs]
     batch = sacc.Batch(seqs_b, max_streams=4, tune_warmup=8)
+    batch.set_mode("streams")
     for i in range(steps):
         As = [sacc.DeviceCSR.from_csr(p.matrix(i)) for p, _ in probs]
         bs = [dev(p.rhs(i)) for p, _ in probs]
@@ -55,10 +58,71 @@ def test_batch_equals_sequential_and_tunes(sacc):
             assert rel <= m["tol"] * (1 + 1e-6), (i, j, rel)
     plan = batch.plan()
     print_case("plan", plan)
-    assert plan["tuned"] and 1 <= plan["streams"] <= 4
+    assert plan["tuned"] and not plan["segmented"] and plan["streams"] == 4
 
 
-def test_batch_matches_oracle(sacc):
+def test_batch_auto_tunes(sacc):
+    """The tuner times every stream plan and both segmented plans, one step each after
+    the warm-up, and keeps one; every step meets the tolerance whichever plan ran it."""
+    import torch
+
+    probs = batch_problems(seed=5, nseq=5, lo=16, hi=32, steps=40)
+    warm, steps = 3, 16
+    seqs = [_seq(sacc, p, m) for p, m in probs]
+    batch = sacc.Batch(seqs, max_streams=8, tune_warmup=warm)
+    seen_seg = False
+    for i in range(steps):
+        As = [sacc.DeviceCSR.from_csr(p.matrix(i)) for p, _ in probs]
+        bs = [dev(p.rhs(i)) for p, _ in probs]
+        xb = [torch.empty(p.n, dtype=torch.float64, device="cuda") for p, _ in probs]
+        infos = batch.step(As, bs, xb)
+        seen_seg = seen_seg or batch.plan()["segmented"]
+        for j, (p, m) in enumerate(probs):
+            Asc = p.matrix(i).to_scipy().astype(np.float64)
+            b = p.rhs(i)
+            rel = np.linalg.norm(b - Asc @ host(xb[j])) / np.linalg.norm(b)
+            assert rel <= m["tol"] * (1 + 1e-6) and infos[j]["status"] == 0, (i, j, rel)
+    plan = batch.plan()
+    print_case("plan", plan)
+    assert plan["tuned"] and 1 <= plan["streams"] <= 8
+
+
+def test_batch_segmented_graph_equals_eager(sacc):
+    """The segmented engine replaying its captured hipGraph of 16 steps (many replays per
+    solve, the guesses' eager launches and host waits between solves) gives bitwise the
+    solutions and counts of the same engine launched eagerly, step after step; every
+    solve meets the tolerance."""
+    import torch
+
+    probs = batch_problems(seed=6, nseq=6, lo=12, hi=40, steps=40)
+    steps = 14
+    print_case("segmented graph / eager", [(p.N, m["M"], m["solver"]) for p, m in probs], steps)
+    ga = sacc.Batch([_seq(sacc, p, m) for p, m in probs], max_streams=2)
+    ea = sacc.Batch([_seq(sacc, p, m) for p, m in probs], max_streams=2)
+    ga.set_mode("segmented")
+    ea.set_mode("segmented_eager")
+    for i in range(steps):
+        As = [sacc.DeviceCSR.from_csr(p.matrix(i)) for p, _ in probs]
+        bs = [dev(p.rhs(i)) for p, _ in probs]
+        xg = [torch.empty(p.n, dtype=torch.float64, device="cuda") for p, _ in probs]
+        xe = [torch.empty(p.n, dtype=torch.float64, device="cuda") for p, _ in probs]
+        ig = ga.step(As, bs, xg)
+        ie = ea.step(As, bs, xe)
+        for j, (p, m) in enumerate(probs):
+            assert np.array_equal(host(xg[j]), host(xe[j])), (i, j)
+            for key in ("iters", "restarts", "refinements", "status", "k_eff"):
+                assert ig[j][key] == ie[j][key], (i, j, key, ig[j][key], ie[j][key])
+            assert ig[j]["relres"] == ie[j]["relres"]
+            Asc = p.matrix(i).to_scipy().astype(np.float64)
+            b = p.rhs(i)
+            rel = np.linalg.norm(b - Asc @ host(xg[j])) / np.linalg.norm(b)
+            assert rel <= m["tol"] * (1 + 1e-6), (i, j, rel)
+            assert abs(ig[j]["relres"] - rel) <= 1e-6 * rel + 1e-15, (i, j, ig[j]["relres"], rel)
+    assert ga.plan()["segmented"] and ea.plan()["segmented"]
+
+
+@pytest.mark.parametrize("mode", ["streams", "segmented"])
+def test_batch_matches_oracle(sacc, mode):
     """Each sequence of a batch, stepped by the batch driver in its own configuration
     (float32 operator and Krylov vectors, FP64 history and refinement, up to 100 sweeps),
     against the oracle on the same history: before every step the oracle's history holds
@@ -80,6 +144,7 @@ def test_batch_matches_oracle(sacc):
     print_case("batch vs oracle", [(p.N, m["M"], m["solver"]) for p, m in probs], steps)
     seqs = [_seq(sacc, p, m) for p, m in probs]
     batch = sacc.Batch(seqs, max_streams=4, tune_warmup=4)
+    batch.set_mode(mode)
     oseqs = [OSeq(p.n, m["M"], m["sketch"], m["s"], m["method_seed"], m["solver"], m["restart"], m["tol"],
                   precision=m["prec"], max_refine=m["max_refine"]) for p, m in probs]
     rows = []
