@@ -466,7 +466,7 @@ def learned_cmp(sacc, torch, np, n_train, n_eval, epochs=60, batch=32, n_hist=8)
     return out
 
 
-def batch_cmp(sacc, torch, np, warmup, steps, max_streams=8, seed=4, nseq=64, precision=None):
+def batch_cmp(sacc, torch, np, warmup, steps, max_streams=8, seed=4, nseq=64, precision=None, lo=96, hi=768):
     """The batched workload: 64 independent 2-D sequences (sides U{96..768}, M in
     {8, 16, 24}, half advective with GMRES(30), the rest CG), float32 values with FP64
     refinement to 1e-8, stepped together by the library's batch driver on up to
@@ -474,7 +474,7 @@ def batch_cmp(sacc, torch, np, warmup, steps, max_streams=8, seed=4, nseq=64, pr
     Timing starts after the longest history (24) is full and `warmup` more steps."""
     from gen import batch_problems
 
-    probs = batch_problems(seed=seed, nseq=nseq, steps=100)
+    probs = batch_problems(seed=seed, nseq=nseq, lo=lo, hi=hi, steps=100)
     fill = max(m["M"] for _, m in probs)
     extra = 2  # steps of each fixed mode after the tuned ones
     total = fill + warmup + steps + 2 * extra
@@ -536,7 +536,7 @@ def batch_cmp(sacc, torch, np, warmup, steps, max_streams=8, seed=4, nseq=64, pr
     batch.close()
     for s in seqs:
         s.close()
-    return dict(workload=f"{nseq} sequences, sides U{{96..768}} (seed {seed}), n total {n_tot}, nnz total {nnz_tot}, "
+    return dict(workload=f"{nseq} sequences, sides U{{{lo}..{hi}}} (seed {seed}), n total {n_tot}, nnz total {nnz_tot}, "
                          f"M in {{8,16,24}}, half GMRES(30) / half CG, float32 operator and Krylov vectors + FP64 "
                          f"refinement ({precision or probs[0][1]['prec']}, at most "
                          f"{probs[0][1]['max_refine']} sweeps), relres 1e-8",
@@ -583,7 +583,9 @@ def main():
     import paper_2309_02156_amd as sacc
 
     if args.only_batch:
-        print(json.dumps({"batch64": batch_cmp(sacc, torch, np, args.batch_warmup, args.batch_steps)}), flush=True)
+        print(json.dumps({"batch64": batch_cmp(sacc, torch, np, args.batch_warmup, args.batch_steps),
+                          "batch64_small": batch_cmp(sacc, torch, np, args.batch_warmup, args.batch_steps, lo=32,
+                                                     hi=128)}), flush=True)
         return
     if args.only_advdiff:
         if args.copy_calibration:
@@ -608,6 +610,8 @@ def main():
             others["learned"] = learned_cmp(sacc, torch, np, args.learned_train, args.learned_eval)
         if not args.no_batch:
             others["batch64"] = batch_cmp(sacc, torch, np, args.batch_warmup, args.batch_steps)
+            # many small sequences: per-sequence kernels are launch-latency bound there
+            others["batch64_small"] = batch_cmp(sacc, torch, np, args.batch_warmup, args.batch_steps, lo=32, hi=128)
     comps.update(others)
     out = {
         "metric": METRIC,

@@ -20,18 +20,23 @@
 //         (converged, breakdown, sweeps or iterations spent) or start an inner solve
 //   CG:   CGQ  p = fl32(r + beta p) (p = r first), q = fl32(A p), p^T q -> alpha
 //         CGU  d = fl32(d + alpha p), r = fl32(r - alpha q), r^T r -> stop or beta
-//   GMRES (classical Gram-Schmidt twice):
-//         V0   v_0 = fl32(w / beta)
-//         A1   w = fl32(A v_j), h = V_j^T w
-//         A2   w' = fl32(w - V h), h2 = V_j^T w', ||w'||^2 -> column j of H = h + h2,
-//              ||w''|| = sqrt(||w'||^2 - ||h2||^2), Givens rotation, residual estimate
-//         A3   v_{j+1} = fl32((w' - V h2) / ||w''||)
+//   GMRES (classical Gram-Schmidt twice, two passes over V per Arnoldi step):
+//         F(j) v_j = fl32((u - V_{<j} h2) / s), with u the once-orthogonalised vector of
+//              step j - 1 (the residual and s = beta at j = 0) and s = ||w''_{j-1}||;
+//              w_j = A v_j = fl32((A u - sum_{l<j} h2_l A v_l) / s), the SpMV taken of
+//              the stored u and each A v_l = V H[:, l] by the Arnoldi relation, so the
+//              correction is a combination sum_k c_k v_k of the columns the pass reads
+//              anyway; h = V_{<=j}^T w_j
+//         G(j) w' = fl32(w_j - V h), h2 = V_{<=j}^T w', ||w'||^2 -> column j of H =
+//              h + h2, ||w''_j|| = sqrt(||w'||^2 - ||h2||^2), Givens rotation, residual
+//              estimate, end of cycle or F(j + 1)
 //         UPD  d = fl32(d + V y)          (end of a cycle)
-//         GRES w = fl32(r32 - A d), ||w|| -> restart or stop
+//         GRES u = fl32(r32 - A d), ||u|| -> restart or stop
 //   XUPD  x += d (FP64), next sweep
 #include <hip/hip_runtime.h>
 #include <math.h>
 #include <stdint.h>
+#include <stdlib.h>
 #include <string.h>
 
 #include <algorithm>
@@ -53,7 +58,7 @@ constexpr int SG_EW = SG_ROWS / SG_TPB;        // rows per thread in the element
 constexpr int SG_R = MAXR;                     // longest GMRES cycle
 constexpr int SG_PW = SG_R + 2;                // doubles per partial row
 
-enum SegPhase : int { SP_RES, SP_XUPD, SP_CGQ, SP_CGU, SP_V0, SP_A1, SP_A2, SP_A3, SP_UPD, SP_GRES, SP_DONE };
+enum SegPhase : int { SP_RES, SP_XUPD, SP_CGQ, SP_CGU, SP_F, SP_G, SP_UPD, SP_GRES, SP_DONE };
 
 // State of one segment.  The summary (ints and the norms) comes first: the host copies
 // only that part back.
@@ -62,8 +67,9 @@ struct SegState {
   int inner_it, icap_cur, j, jend, cycles, par, first, pad;
   double bnorm, relres0, relres;
   double ith, rho, alpha, beta, hn;
-  double h[SG_R + 1], h2[SG_R + 1], g[SG_R + 1], cs[SG_R], sn[SG_R], y[SG_R];
-  double H[SG_R * (SG_R + 1)];  // column j at H[j * (SG_R + 1)]
+  double h[SG_R + 1], h2[SG_R + 1], c[SG_R + 1], g[SG_R + 1], cs[SG_R], sn[SG_R], y[SG_R];
+  double Hraw[SG_R * (SG_R + 1)];  // Hessenberg columns as built: column j at Hraw[j * (SG_R + 1)]
+  double H[SG_R * (SG_R + 1)];     // the same after the Givens rotations
 };
 constexpr size_t SG_SUMMARY = offsetof(SegState, ith);
 
@@ -72,13 +78,16 @@ __host__ __device__ inline int phase_cols(int phase, int j) {
   switch (phase) {
     case SP_RES: return 3;
     case SP_CGQ: case SP_CGU: case SP_GRES: return 1;
-    case SP_A1: return j + 1;
-    case SP_A2: return j + 2;
+    case SP_F: return j + 1;
+    case SP_G: return j + 2;
     default: return 0;
   }
 }
 
 __device__ inline float *kcol(const SegDesc &d, int c) { return d.kry + (size_t)c * (size_t)d.ld; }
+// GMRES work columns: F(j) reads xcol(d, j + 1) and writes xcol(d, j), which G(j)
+// rewrites in place (columns m and m + 1: V_m itself is never formed)
+__device__ inline float *xcol(const SegDesc &d, int j) { return kcol(d, d.m + (j & 1)); }
 
 // ---------------------------------------------------------------------------- data kernel
 // Column dots of a wave's tile through LDS: the tile's rows of V[:, 0..jc) are staged
@@ -112,26 +121,15 @@ __device__ inline void col_sums_store(double acc, int kc, double *red, double *o
   }
 }
 
+// The row work of one work item (a segment's block of SG_ROWS rows) in the segment's
+// current phase; leaves the item's partial row.
 template <int C>
-__global__ __launch_bounds__(SG_TPB) void k_seg_data(const SegDesc *__restrict__ D, const SegState *__restrict__ S,
-                                                    const int *__restrict__ blkseg, const int *__restrict__ blk0) {
-  // LDS: the SpMV tiles' column / value slices, or the staged V columns of the dots
-  constexpr int SPMV_B = SG_NW * WT_CAP * (int)(sizeof(int) + sizeof(float));
-  constexpr int DOTS_B = SG_NW * ((SG_R + 1) * SG_LDV + WAVE) * (int)sizeof(float);
-  __shared__ __align__(16) char lds[SPMV_B > DOTS_B ? SPMV_B : DOTS_B];
+__device__ inline void seg_item(const SegDesc &d, const SegState &st, int phase, int lb, char *lds, double *red,
+                                double *red1, double *coef, double *coef2) {
   int(*lcol)[WT_CAP] = (int(*)[WT_CAP])lds;
   float(*lval)[WT_CAP] = (float(*)[WT_CAP])(lds + SG_NW * WT_CAP * sizeof(int));
   float *sV = (float *)lds + (threadIdx.x / WAVE) * ((SG_R + 1) * SG_LDV + WAVE);
   float *sy = sV + (SG_R + 1) * SG_LDV;
-  __shared__ double red[SG_NW * 32];
-  __shared__ double red1[SG_NW];
-  __shared__ double coef[SG_R + 1];
-  const int s = blkseg[blockIdx.x];
-  const SegState &st = S[s];
-  const int phase = st.phase;
-  if (phase == SP_DONE) return;
-  const SegDesc d = D[s];
-  const int lb = (int)blockIdx.x - blk0[s];
   const int tid = threadIdx.x, wid = tid / WAVE;
   const int64_t n = d.n;
   const int64_t T = (n + WAVE - 1) / WAVE;
@@ -222,35 +220,47 @@ __global__ __launch_bounds__(SG_TPB) void k_seg_data(const SegDesc *__restrict__
       block_sum_store<1>(acc, 1, red, out);
       break;
     }
-    case SP_V0: {
-      const double beta = st.beta;
-      const float *__restrict__ W = kcol(d, m + 1);
-      float *__restrict__ V0 = kcol(d, 0);
-#pragma unroll
-      for (int k = 0; k < SG_EW; ++k) {
-        const int64_t i = row0 + k * SG_TPB + tid;
-        if (i < n) V0[i] = (float)((double)W[i] / beta);
-      }
-      break;
-    }
-    case SP_A1: {
+    case SP_F: {
       const int j = st.j;
-      const float *__restrict__ Vj = kcol(d, j);
-      float *__restrict__ W = kcol(d, m + 1);
+      const double sc = st.hn;
+      if (tid < j) coef[tid] = st.h2[tid];
+      if (tid <= j) coef2[tid] = st.c[tid];
+      __syncthreads();
+      const float *__restrict__ U = xcol(d, j + 1);
+      float *__restrict__ Wn = xcol(d, j);
+      float *__restrict__ Vj = kcol(d, j);
       const float *__restrict__ V = d.kry;
       const size_t ld = (size_t)d.ld;
       wave_tiles_spmv<C>(
-          d.rowptr, d.col, d.val, [&](int c) { return Vj[c]; }, n, t0 + wid, tend, SG_NW, lcol[wid], lval[wid],
-          [&](int64_t) { return 0.0; }, [&](int64_t i, double, double av) { W[i] = (float)av; });
+          d.rowptr, d.col, d.val, [&](int c) { return U[c]; }, n, t0 + wid, tend, SG_NW, lcol[wid], lval[wid],
+          [&](int64_t ic) { return (double)U[ic]; },
+          [&](int64_t i, double u, double au) {
+            double v = u, a = au;
+            for (int l0 = 0; l0 < j; l0 += 8) {
+              float v8[8];
+#pragma unroll
+              for (int e = 0; e < 8; ++e) v8[e] = l0 + e < j ? V[(l0 + e) * ld + i] : 0.0f;
+#pragma unroll
+              for (int e = 0; e < 8; ++e)
+                if (l0 + e < j) {
+                  v = __dadd_rn(v, -__dmul_rn(coef[l0 + e], (double)v8[e]));
+                  a = __dadd_rn(a, -__dmul_rn(coef2[l0 + e], (double)v8[e]));
+                }
+            }
+            const float vj = (float)(v / sc);
+            Vj[i] = vj;
+            a = __dadd_rn(a, -__dmul_rn(coef2[j], (double)vj));
+            Wn[i] = (float)(a / sc);
+          });
       __syncthreads();  // the LDS slices become the staged columns
-      // h = V_j^T w over this block's rows (each lane re-reads its own rows of w)
+      // h = V_{<=j}^T w_j over this block's rows (each lane re-reads its own rows)
       double acc = 0.0;
       const int lane = tid % WAVE;
       for (int64_t t = t0 + wid; t < tend; t += SG_NW) {
         const int64_t i = t * WAVE + lane;
         const bool ok = i < n;
         const int64_t ic = ok ? i : n - 1;
-        sy[lane] = ok ? W[ic] : 0.0f;
+        sy[lane] = ok ? Wn[ic] : 0.0f;
         for (int l0 = 0; l0 <= j; l0 += 8) {
           float v8[8];
 #pragma unroll
@@ -265,11 +275,11 @@ __global__ __launch_bounds__(SG_TPB) void k_seg_data(const SegDesc *__restrict__
       col_sums_store(acc, j + 1, red, out);
       break;
     }
-    case SP_A2: {
+    case SP_G: {
       const int j = st.j;
       if (tid <= j) coef[tid] = st.h[tid];
       __syncthreads();
-      float *__restrict__ W = kcol(d, m + 1);
+      float *__restrict__ W = xcol(d, j);
       const float *__restrict__ V = d.kry;
       const size_t ld = (size_t)d.ld;
       const int lane = tid % WAVE;
@@ -300,32 +310,6 @@ __global__ __launch_bounds__(SG_TPB) void k_seg_data(const SegDesc *__restrict__
       col_sums_store(acc, j + 1, red, out);
       __syncthreads();
       block_sum_store<1>(ww, 1, red1, out + j + 1);
-      break;
-    }
-    case SP_A3: {
-      const int j = st.j;
-      const double hn = st.hn;
-      if (tid <= j) coef[tid] = st.h2[tid];
-      __syncthreads();
-      const float *__restrict__ W = kcol(d, m + 1);
-      const float *__restrict__ V = d.kry;
-      float *__restrict__ Vn = kcol(d, j + 1);
-      const size_t ld = (size_t)d.ld;
-      for (int k = 0; k < SG_EW; ++k) {
-        const int64_t i = row0 + k * SG_TPB + tid;
-        if (i < n) {
-          double w = (double)W[i];
-          for (int l0 = 0; l0 <= j; l0 += 8) {
-            float v8[8];
-#pragma unroll
-            for (int u = 0; u < 8; ++u) v8[u] = l0 + u <= j ? V[(l0 + u) * ld + i] : 0.0f;
-#pragma unroll
-            for (int u = 0; u < 8; ++u)
-              if (l0 + u <= j) w = __dadd_rn(w, -__dmul_rn(coef[l0 + u], (double)v8[u]));
-          }
-          Vn[i] = (float)(w / hn);
-        }
-      }
       break;
     }
     case SP_UPD: {
@@ -373,6 +357,41 @@ __global__ __launch_bounds__(SG_TPB) void k_seg_data(const SegDesc *__restrict__
   }
 }
 
+// A resident grid that strides over the work items (item i: block i - blk0[s] of the
+// segment s owning it).  Each block first reads, with one load per item, which of its
+// items belong to a segment still running, so finished segments cost no memory trips.
+constexpr int SG_MAXIT = 64;  // work items per block at most (the grid is sized for it)
+
+template <int C>
+__global__ __launch_bounds__(SG_TPB) void k_seg_data(const SegDesc *__restrict__ D, const SegState *__restrict__ S,
+                                                    const int *__restrict__ blkseg, const int *__restrict__ blk0,
+                                                    int nitems) {
+  // LDS: the SpMV tiles' column / value slices, or the staged V columns of the dots
+  constexpr int SPMV_B = SG_NW * WT_CAP * (int)(sizeof(int) + sizeof(float));
+  constexpr int DOTS_B = SG_NW * ((SG_R + 1) * SG_LDV + WAVE) * (int)sizeof(float);
+  __shared__ __align__(16) char lds[SPMV_B > DOTS_B ? SPMV_B : DOTS_B];
+  __shared__ double red[SG_NW * 32];
+  __shared__ double red1[SG_NW];
+  __shared__ double coef[SG_R + 1], coef2[SG_R + 1];
+  __shared__ int iseg[SG_MAXIT], iph[SG_MAXIT];
+  const int G = gridDim.x;
+  const int mine = (nitems - (int)blockIdx.x + G - 1) / G;
+  for (int k = threadIdx.x; k < mine && k < SG_MAXIT; k += blockDim.x) {
+    const int s = blkseg[blockIdx.x + k * G];
+    iseg[k] = s;
+    iph[k] = S[s].phase;
+  }
+  __syncthreads();
+  for (int k = 0; k < mine && k < SG_MAXIT; ++k) {
+    const int phase = iph[k];
+    if (phase == SP_DONE) continue;
+    const int s = iseg[k];
+    const SegDesc d = D[s];
+    seg_item<C>(d, S[s], phase, (int)blockIdx.x + k * G - blk0[s], lds, red, red1, coef, coef2);
+    __syncthreads();  // LDS reuse by the next item
+  }
+}
+
 // ---------------------------------------------------------------------------- close kernel
 // Givens rotation [c s; -s c] [a; b] = [rho; 0] (c = 1, s = 0 when a = b = 0)
 __device__ inline void givens(double a, double b, double &c, double &s, double &rho) {
@@ -396,6 +415,16 @@ __device__ inline void seg_finish(SegState &st, int status, int s, volatile int 
 __device__ inline void inner_end(SegState &st) {
   st.restarts += st.cycles > 1 ? st.cycles - 1 : 0;
   st.phase = SP_XUPD;
+}
+
+// a GMRES cycle from the residual in xcol(d, 1) with norm beta: F(0) forms v_0 = r / beta
+__device__ inline void cycle_start(SegState &st, double beta) {
+  st.beta = beta;
+  st.g[0] = beta;
+  st.hn = beta;
+  st.c[0] = 0.0;
+  st.j = 0;
+  st.phase = SP_F;
 }
 
 __device__ void seg_logic(const SegDesc &d, SegState &st, const double *tot, int s, volatile int *done) {
@@ -429,9 +458,10 @@ __device__ void seg_logic(const SegDesc &d, SegState &st, const double *tot, int
           st.first = 1;
           st.par = 0;
           st.phase = ibn <= st.ith ? SP_XUPD : SP_CGQ;
+        } else if (ibn > st.ith) {
+          cycle_start(st, ibn);
         } else {
-          st.beta = ibn;
-          st.phase = ibn > st.ith ? SP_V0 : SP_XUPD;
+          st.phase = SP_XUPD;
         }
       }
       return;
@@ -466,27 +496,23 @@ __device__ void seg_logic(const SegDesc &d, SegState &st, const double *tot, int
       }
       return;
     }
-    case SP_V0:
-      st.g[0] = st.beta;
-      st.j = 0;
-      st.phase = SP_A1;
-      return;
-    case SP_A1:
+    case SP_F:
       for (int l = 0; l <= st.j; ++l) st.h[l] = tot[l];
-      st.phase = SP_A2;
+      st.phase = SP_G;
       return;
-    case SP_A2: {
+    case SP_G: {
       const int j = st.j;
+      double *Hr = st.Hraw + j * (SG_R + 1);
       double *Hc = st.H + j * (SG_R + 1);
       double h2sq = 0.0;
       for (int l = 0; l <= j; ++l) {
         st.h2[l] = tot[l];
-        Hc[l] = st.h[l] + tot[l];
+        Hr[l] = Hc[l] = st.h[l] + tot[l];
         h2sq += tot[l] * tot[l];
       }
       const double wsq = tot[j + 1] - h2sq;
       const double hnext = wsq > 0.0 ? sqrt(wsq) : 0.0;
-      st.hn = hnext;
+      Hr[j + 1] = hnext;
       for (int l = 0; l < j; ++l) {
         const double t = st.cs[l] * Hc[l] + st.sn[l] * Hc[l + 1];
         Hc[l + 1] = -st.sn[l] * Hc[l] + st.cs[l] * Hc[l + 1];
@@ -512,14 +538,18 @@ __device__ void seg_logic(const SegDesc &d, SegState &st, const double *tot, int
         }
         st.phase = SP_UPD;
       } else {
-        st.phase = SP_A3;
+        // F(j + 1): sum_{l<=j} h2_l A v_l = sum_{k<=j+1} c_k v_k, A v_l = V Hraw[:, l]
+        for (int k = 0; k <= j + 1; ++k) {
+          double t = 0.0;
+          for (int l = k > 0 ? k - 1 : 0; l <= j; ++l) t += st.h2[l] * st.Hraw[l * (SG_R + 1) + k];
+          st.c[k] = t;
+        }
+        st.hn = hnext;
+        st.j = j + 1;
+        st.phase = SP_F;
       }
       return;
     }
-    case SP_A3:
-      st.j += 1;
-      st.phase = SP_A1;
-      return;
     case SP_UPD:
       st.phase = SP_GRES;
       return;
@@ -535,8 +565,7 @@ __device__ void seg_logic(const SegDesc &d, SegState &st, const double *tot, int
       } else if (st.inner_it >= st.icap_cur) {
         inner_end(st);
       } else {
-        st.beta = beta;
-        st.phase = SP_V0;
+        cycle_start(st, beta);
       }
       return;
     }
@@ -545,19 +574,29 @@ __device__ void seg_logic(const SegDesc &d, SegState &st, const double *tot, int
   }
 }
 
-__global__ __launch_bounds__(SG_TPB) void k_seg_close(const SegDesc *__restrict__ D, SegState *__restrict__ S,
+// One block per segment: the partial rows' sums in a fixed order, then the scalar logic
+// on a copy of the state in LDS (one thread), copied back by the whole block.
+constexpr int SC_TPB = 1024;
+static_assert(sizeof(SegState) % sizeof(double) == 0, "state copied as 8-byte words");
+
+__global__ __launch_bounds__(SC_TPB) void k_seg_close(const SegDesc *__restrict__ D, SegState *__restrict__ S,
                                                      int *done) {
   __shared__ double tot[SG_PW];
-  __shared__ double scratch[SG_TPB];
+  __shared__ double scratch[SC_TPB];
+  __shared__ SegState ls;
   const int s = blockIdx.x;
-  SegState &st = S[s];
-  const int phase = st.phase;
+  SegState &gs = S[s];
+  const int phase = gs.phase;
   if (phase == SP_DONE) return;
+  constexpr int NW8 = (int)(sizeof(SegState) / sizeof(double));
+  for (int k = threadIdx.x; k < NW8; k += SC_TPB) ((double *)&ls)[k] = ((const double *)&gs)[k];
   const SegDesc &d = D[s];
-  const int kc = phase_cols(phase, st.j);
+  const int kc = phase_cols(phase, gs.j);
   if (kc > 0) final_sum(d.part, d.nblk, SG_PW, kc, tot, scratch);
   __syncthreads();
-  if (threadIdx.x == 0) seg_logic(d, st, tot, s, (volatile int *)done);
+  if (threadIdx.x == 0) seg_logic(d, ls, tot, s, (volatile int *)done);
+  __syncthreads();
+  for (int k = threadIdx.x; k < NW8; k += SC_TPB) ((double *)&gs)[k] = ((const double *)&ls)[k];
 }
 
 __global__ void k_seg_init(SegState *S, int nseg) {
@@ -580,6 +619,7 @@ hipError_t seg_step_launch(SegEngine *e, hipStream_t st);
 // ---------------------------------------------------------------------------- host engine
 struct SegEngine {
   int nseg = 0, nblk = 0, chunk = 5;
+  int oversub = 16;           // data-kernel grid: this many times the resident blocks
   std::vector<int64_t> n;
   std::vector<int> blk0h;
   SegDesc *ddesc = nullptr;   // device descriptors
@@ -600,9 +640,16 @@ namespace {
 
 template <int C>
 hipError_t seg_step_launch(SegEngine *e, hipStream_t st) {
-  hipLaunchKernelGGL(HIP_KERNEL_NAME(k_seg_data<C>), dim3(e->nblk), dim3(SG_TPB), 0, st, e->ddesc,
-                     (const SegState *)e->dstate, (const int *)e->dblkseg, (const int *)e->dblk0);
-  hipLaunchKernelGGL(k_seg_close, dim3(e->nseg), dim3(SG_TPB), 0, st, (const SegDesc *)e->ddesc, e->dstate,
+  static int resident = 0;
+  int grid = resident_blocks((const void *)k_seg_data<C>, SG_TPB, resident) * e->oversub;
+  if (grid < 8) grid = 8;
+  grid = grid / 8 * 8;
+  const int need = (e->nblk + SG_MAXIT - 1) / SG_MAXIT;
+  if (grid < need) grid = need;
+  if (grid > e->nblk) grid = e->nblk;
+  hipLaunchKernelGGL(HIP_KERNEL_NAME(k_seg_data<C>), dim3(grid), dim3(SG_TPB), 0, st, e->ddesc,
+                     (const SegState *)e->dstate, (const int *)e->dblkseg, (const int *)e->dblk0, e->nblk);
+  hipLaunchKernelGGL(k_seg_close, dim3(e->nseg), dim3(SC_TPB), 0, st, (const SegDesc *)e->ddesc, e->dstate,
                      e->done_dev);
   return hipGetLastError();
 }
@@ -720,6 +767,19 @@ static long long seg_step_bound(const SegDesc &d) {
 
 hipError_t seg_engine_solve(SegEngine *e, const SegDesc *desc, bool graph, hipStream_t st, SegResult *res) {
   const int nseg = e->nseg;
+  // SACC_SEG_OVERSUB (1..64) overrides the data kernel's grid multiple (a tuning knob)
+  {
+    const char *ev = getenv("SACC_SEG_OVERSUB");
+    const int v = ev ? atoi(ev) : 0;
+    const int want = v >= 1 && v <= 64 ? v : 16;
+    if (want != e->oversub && e->gexec) {
+      (void)hipGraphExecDestroy(e->gexec);
+      (void)hipGraphDestroy(e->graph);
+      e->gexec = nullptr;
+      e->graph = nullptr;
+    }
+    e->oversub = want;
+  }
   long long bound = 0;
   for (int s = 0; s < nseg; ++s) {
     e->hdesc[s] = desc[s];
