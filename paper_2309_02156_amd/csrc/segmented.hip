@@ -23,8 +23,8 @@
 //   GMRES (classical Gram-Schmidt twice, two passes over V per Arnoldi step):
 //         F(j) v_j = fl32((u - V_{<j} h2) / s), with u the once-orthogonalised vector of
 //              step j - 1 (the residual and s = beta at j = 0) and s = ||w''_{j-1}||;
-//              w_j = A v_j = fl32((A u - sum_{l<j} h2_l A v_l) / s), the SpMV taken of
-//              the stored u and each A v_l = V H[:, l] by the Arnoldi relation, so the
+//              w_j = A v_j = fl32((fl32(A u) - sum_{l<j} h2_l A v_l) / s), the SpMV taken
+//              of the stored u and each A v_l = V H[:, l] by the Arnoldi relation, so the
 //              correction is a combination sum_k c_k v_k of the columns the pass reads
 //              anyway; h = V_{<=j}^T w_j
 //         G(j) w' = fl32(w_j - V h), h2 = V_{<=j}^T w', ||w'||^2 -> column j of H =
@@ -105,6 +105,31 @@ __device__ inline double tile_col_dots(const float *sV, const float *sy, int jc)
     for (int r = 0; r < 32; ++r) s += (double)sV[c * SG_LDV + r0 + r] * (double)sy[r0 + r];
   }
   return s;
+}
+
+// Row ic of V's columns 0..NV-1 into v, all loads issued before any use (columns past
+// `last` re-read column `last`; callers ignore them)
+template <int NV>
+__device__ inline void load_cols(const float *__restrict__ V, size_t ld, int64_t ic, int last, float (&v)[NV]) {
+#pragma unroll
+  for (int l = 0; l < NV; ++l) v[l] = V[(size_t)(l <= last ? l : last) * ld + ic];
+}
+
+// fn(Nch<k>) for k = nch clamped to 0..4: the number of 8-column chunks a phase touches
+// as a compile-time constant
+template <int N>
+struct Nch {
+  static constexpr int value = N;
+};
+template <typename Fn>
+__device__ inline void with_nch(int nch, const Fn &fn) {
+  switch (nch) {
+    case 0: fn(Nch<0>{}); break;
+    case 1: fn(Nch<1>{}); break;
+    case 2: fn(Nch<2>{}); break;
+    case 3: fn(Nch<3>{}); break;
+    default: fn(Nch<4>{}); break;
+  }
 }
 
 // the block's column sums (columns < kc <= 32) of per-lane sums laid out as in
@@ -225,53 +250,51 @@ __device__ inline void seg_item(const SegDesc &d, const SegState &st, int phase,
       const double sc = st.hn;
       if (tid < j) coef[tid] = st.h2[tid];
       if (tid <= j) coef2[tid] = st.c[tid];
-      __syncthreads();
       const float *__restrict__ U = xcol(d, j + 1);
       float *__restrict__ Wn = xcol(d, j);
       float *__restrict__ Vj = kcol(d, j);
       const float *__restrict__ V = d.kry;
       const size_t ld = (size_t)d.ld;
+      // y = A u (stored in float32 where w_j goes), then per tile: v_j, w_j and the dots
       wave_tiles_spmv<C>(
           d.rowptr, d.col, d.val, [&](int c) { return U[c]; }, n, t0 + wid, tend, SG_NW, lcol[wid], lval[wid],
-          [&](int64_t ic) { return (double)U[ic]; },
-          [&](int64_t i, double u, double au) {
-            double v = u, a = au;
-            for (int l0 = 0; l0 < j; l0 += 8) {
-              float v8[8];
-#pragma unroll
-              for (int e = 0; e < 8; ++e) v8[e] = l0 + e < j ? V[(l0 + e) * ld + i] : 0.0f;
-#pragma unroll
-              for (int e = 0; e < 8; ++e)
-                if (l0 + e < j) {
-                  v = __dadd_rn(v, -__dmul_rn(coef[l0 + e], (double)v8[e]));
-                  a = __dadd_rn(a, -__dmul_rn(coef2[l0 + e], (double)v8[e]));
-                }
-            }
-            const float vj = (float)(v / sc);
-            Vj[i] = vj;
-            a = __dadd_rn(a, -__dmul_rn(coef2[j], (double)vj));
-            Wn[i] = (float)(a / sc);
-          });
-      __syncthreads();  // the LDS slices become the staged columns
-      // h = V_{<=j}^T w_j over this block's rows (each lane re-reads its own rows)
+          [&](int64_t) { return 0.0; }, [&](int64_t i, double, double au) { Wn[i] = (float)au; });
+      __syncthreads();  // coefficients in; the LDS slices become the staged columns
       double acc = 0.0;
       const int lane = tid % WAVE;
-      for (int64_t t = t0 + wid; t < tend; t += SG_NW) {
-        const int64_t i = t * WAVE + lane;
-        const bool ok = i < n;
-        const int64_t ic = ok ? i : n - 1;
-        sy[lane] = ok ? Wn[ic] : 0.0f;
-        for (int l0 = 0; l0 <= j; l0 += 8) {
-          float v8[8];
+      with_nch((j + 8) / 8, [&](auto kk) {
+        constexpr int NV = (decltype(kk)::value > 0 ? decltype(kk)::value : 1) * 8;  // columns l <= j
+        for (int64_t t = t0 + wid; t < tend; t += SG_NW) {
+          const int64_t i = t * WAVE + lane;
+          const bool ok = i < n;
+          const int64_t ic = ok ? i : n - 1;
+          float vv[NV];
+          load_cols<NV>(V, ld, ic, j > 0 ? j - 1 : 0, vv);
+          // coefficients read from LDS at each use (z: an offset the compiler cannot
+          // hoist; kept in registers they would take 128 per lane and halve occupancy)
+          const int z = vzero();
+          double v = (double)U[ic], a = (double)Wn[ic];
 #pragma unroll
-          for (int u = 0; u < 8; ++u) v8[u] = l0 + u <= j ? V[(l0 + u) * ld + ic] : 0.0f;
-#pragma unroll
-          for (int u = 0; u < 8; ++u) sV[(l0 + u) * SG_LDV + lane] = ok ? v8[u] : 0.0f;
+          for (int l = 0; l < NV; ++l)
+            if (l < j) {
+              v = __dadd_rn(v, -__dmul_rn(coef[l + z], (double)vv[l]));
+              a = __dadd_rn(a, -__dmul_rn(coef2[l + z], (double)vv[l]));
+              sV[l * SG_LDV + lane] = ok ? vv[l] : 0.0f;
+            }
+          const float vj = (float)(v / sc);
+          a = __dadd_rn(a, -__dmul_rn(coef2[j], (double)vj));
+          const float wf = (float)(a / sc);
+          if (ok) {
+            Vj[i] = vj;
+            Wn[i] = wf;
+          }
+          sV[j * SG_LDV + lane] = ok ? vj : 0.0f;
+          sy[lane] = ok ? wf : 0.0f;
+          wave_lds_sync();
+          acc += tile_col_dots(sV, sy, j + 1);
+          wave_lds_sync();
         }
-        wave_lds_sync();
-        acc += tile_col_dots(sV, sy, j + 1);
-        wave_lds_sync();
-      }
+      });
       col_sums_store(acc, j + 1, red, out);
       break;
     }
@@ -284,29 +307,31 @@ __device__ inline void seg_item(const SegDesc &d, const SegState &st, int phase,
       const size_t ld = (size_t)d.ld;
       const int lane = tid % WAVE;
       double acc = 0.0, ww[1] = {0.0};
-      for (int64_t t = t0 + wid; t < tend; t += SG_NW) {
-        const int64_t i = t * WAVE + lane;
-        const bool ok = i < n;
-        const int64_t ic = ok ? i : n - 1;
-        double w = (double)W[ic];
-        for (int l0 = 0; l0 <= j; l0 += 8) {
-          float v8[8];
+      with_nch((j + 8) / 8, [&](auto kk) {
+        constexpr int NV = (decltype(kk)::value > 0 ? decltype(kk)::value : 1) * 8;  // columns l <= j
+        for (int64_t t = t0 + wid; t < tend; t += SG_NW) {
+          const int64_t i = t * WAVE + lane;
+          const bool ok = i < n;
+          const int64_t ic = ok ? i : n - 1;
+          float vv[NV];
+          load_cols<NV>(V, ld, ic, j, vv);
+          const int z = vzero();
+          double w = (double)W[ic];
 #pragma unroll
-          for (int u = 0; u < 8; ++u) v8[u] = l0 + u <= j ? V[(l0 + u) * ld + ic] : 0.0f;
-#pragma unroll
-          for (int u = 0; u < 8; ++u) {
-            sV[(l0 + u) * SG_LDV + lane] = ok ? v8[u] : 0.0f;
-            if (l0 + u <= j) w = __dadd_rn(w, -__dmul_rn(coef[l0 + u], (double)v8[u]));
-          }
+          for (int l = 0; l < NV; ++l)
+            if (l <= j) {
+              sV[l * SG_LDV + lane] = ok ? vv[l] : 0.0f;
+              w = __dadd_rn(w, -__dmul_rn(coef[l + z], (double)vv[l]));
+            }
+          const float wf = (float)w;
+          if (ok) W[i] = wf;
+          sy[lane] = ok ? wf : 0.0f;
+          if (ok) ww[0] += (double)wf * (double)wf;
+          wave_lds_sync();
+          acc += tile_col_dots(sV, sy, j + 1);
+          wave_lds_sync();
         }
-        const float wf = (float)w;
-        if (ok) W[i] = wf;
-        sy[lane] = ok ? wf : 0.0f;
-        if (ok) ww[0] += (double)wf * (double)wf;
-        wave_lds_sync();
-        acc += tile_col_dots(sV, sy, j + 1);
-        wave_lds_sync();
-      }
+      });
       col_sums_store(acc, j + 1, red, out);
       __syncthreads();
       block_sum_store<1>(ww, 1, red1, out + j + 1);
@@ -319,21 +344,24 @@ __device__ inline void seg_item(const SegDesc &d, const SegState &st, int phase,
       const float *__restrict__ V = d.kry;
       float *__restrict__ dd = d.d32;
       const size_t ld = (size_t)d.ld;
-      for (int k = 0; k < SG_EW; ++k) {
-        const int64_t i = row0 + k * SG_TPB + tid;
-        if (i < n) {
-          double u = 0.0;
-          for (int l0 = 0; l0 < jend; l0 += 8) {
-            float v8[8];
+      with_nch((jend + 7) / 8, [&](auto kk) {
+        constexpr int NV = decltype(kk)::value * 8;  // columns l < jend
+        if constexpr (NV > 0) {
+          for (int k = 0; k < SG_EW; ++k) {
+            const int64_t i = row0 + k * SG_TPB + tid;
+            if (i < n) {
+              float vv[NV];
+              load_cols<NV>(V, ld, i, jend - 1, vv);
+              const int z = vzero();
+              double u = 0.0;
 #pragma unroll
-            for (int e = 0; e < 8; ++e) v8[e] = l0 + e < jend ? V[(l0 + e) * ld + i] : 0.0f;
-#pragma unroll
-            for (int e = 0; e < 8; ++e)
-              if (l0 + e < jend) u = __dadd_rn(u, __dmul_rn((double)v8[e], coef[l0 + e]));
+              for (int l = 0; l < NV; ++l)
+                if (l < jend) u = __dadd_rn(u, __dmul_rn((double)vv[l], coef[l + z]));
+              dd[i] = (float)((double)dd[i] + u);
+            }
           }
-          dd[i] = (float)((double)dd[i] + u);
         }
-      }
+      });
       break;
     }
     case SP_GRES: {
@@ -363,7 +391,7 @@ __device__ inline void seg_item(const SegDesc &d, const SegState &st, int phase,
 constexpr int SG_MAXIT = 64;  // work items per block at most (the grid is sized for it)
 
 template <int C>
-__global__ __launch_bounds__(SG_TPB) void k_seg_data(const SegDesc *__restrict__ D, const SegState *__restrict__ S,
+__global__ __launch_bounds__(SG_TPB, 4) void k_seg_data(const SegDesc *__restrict__ D, const SegState *__restrict__ S,
                                                     const int *__restrict__ blkseg, const int *__restrict__ blk0,
                                                     int nitems) {
   // LDS: the SpMV tiles' column / value slices, or the staged V columns of the dots
@@ -538,12 +566,7 @@ __device__ void seg_logic(const SegDesc &d, SegState &st, const double *tot, int
         }
         st.phase = SP_UPD;
       } else {
-        // F(j + 1): sum_{l<=j} h2_l A v_l = sum_{k<=j+1} c_k v_k, A v_l = V Hraw[:, l]
-        for (int k = 0; k <= j + 1; ++k) {
-          double t = 0.0;
-          for (int l = k > 0 ? k - 1 : 0; l <= j; ++l) t += st.h2[l] * st.Hraw[l * (SG_R + 1) + k];
-          st.c[k] = t;
-        }
+        // F(j + 1) next; its coefficients c (seg_coefs) are formed by the whole block
         st.hn = hnext;
         st.j = j + 1;
         st.phase = SP_F;
@@ -574,8 +597,20 @@ __device__ void seg_logic(const SegDesc &d, SegState &st, const double *tot, int
   }
 }
 
+// F(j)'s coefficients after G(j - 1): sum_{l<j} h2_l A v_l = sum_{k<=j} c_k v_k with
+// A v_l = V Hraw[:, l] (the Arnoldi relation); thread k forms c_k.
+__device__ inline void seg_coefs(SegState &st) {
+  const int j = st.j, k = threadIdx.x;
+  if (k <= j) {
+    double t = 0.0;
+    for (int l = k > 0 ? k - 1 : 0; l < j; ++l) t += st.h2[l] * st.Hraw[l * (SG_R + 1) + k];
+    st.c[k] = t;
+  }
+}
+
 // One block per segment: the partial rows' sums in a fixed order, then the scalar logic
-// on a copy of the state in LDS (one thread), copied back by the whole block.
+// on a copy of the state in LDS (one thread; the coefficients of the next F step by
+// the block), copied back by the whole block.
 constexpr int SC_TPB = 1024;
 static_assert(sizeof(SegState) % sizeof(double) == 0, "state copied as 8-byte words");
 
@@ -596,6 +631,10 @@ __global__ __launch_bounds__(SC_TPB) void k_seg_close(const SegDesc *__restrict_
   __syncthreads();
   if (threadIdx.x == 0) seg_logic(d, ls, tot, s, (volatile int *)done);
   __syncthreads();
+  if (phase == SP_G && ls.phase == SP_F) {
+    seg_coefs(ls);
+    __syncthreads();
+  }
   for (int k = threadIdx.x; k < NW8; k += SC_TPB) ((double *)&gs)[k] = ((const double *)&ls)[k];
 }
 
@@ -619,7 +658,7 @@ hipError_t seg_step_launch(SegEngine *e, hipStream_t st);
 // ---------------------------------------------------------------------------- host engine
 struct SegEngine {
   int nseg = 0, nblk = 0, chunk = 5;
-  int oversub = 16;           // data-kernel grid: this many times the resident blocks
+  int oversub = 8;            // data-kernel grid: this many times the resident blocks
   std::vector<int64_t> n;
   std::vector<int> blk0h;
   SegDesc *ddesc = nullptr;   // device descriptors
@@ -771,7 +810,7 @@ hipError_t seg_engine_solve(SegEngine *e, const SegDesc *desc, bool graph, hipSt
   {
     const char *ev = getenv("SACC_SEG_OVERSUB");
     const int v = ev ? atoi(ev) : 0;
-    const int want = v >= 1 && v <= 64 ? v : 16;
+    const int want = v >= 1 && v <= 64 ? v : 8;
     if (want != e->oversub && e->gexec) {
       (void)hipGraphExecDestroy(e->gexec);
       (void)hipGraphDestroy(e->graph);
