@@ -466,7 +466,8 @@ def learned_cmp(sacc, torch, np, n_train, n_eval, epochs=60, batch=32, n_hist=8)
     return out
 
 
-def batch_cmp(sacc, torch, np, warmup, steps, max_streams=8, seed=4, nseq=64, precision=None, lo=96, hi=768):
+def batch_cmp(sacc, torch, np, warmup, steps, max_streams=8, seed=4, nseq=64, precision=None, lo=96, hi=768,
+              mode="auto", fixed_modes=("streams", "segmented")):
     """The batched workload: 64 independent 2-D sequences (sides U{96..768}, M in
     {8, 16, 24}, half advective with GMRES(30), the rest CG), float32 values with FP64
     refinement to 1e-8, stepped together by the library's batch driver on up to
@@ -491,6 +492,8 @@ def batch_cmp(sacc, torch, np, warmup, steps, max_streams=8, seed=4, nseq=64, pr
         nnz_tot += st.nnz
         n_tot += p.n
     batch = sacc.Batch(seqs, max_streams=max_streams, tune_warmup=fill)
+    if mode != "auto":
+        batch.set_mode(mode)
 
     def run(i):
         return batch.step([s.A(i) for s in sts], [s.rhs[i] for s in sts], xs)
@@ -522,17 +525,25 @@ def batch_cmp(sacc, torch, np, warmup, steps, max_streams=8, seed=4, nseq=64, pr
     # in the segmented engine (graph replays)
     fixed = {}
     k = fill + warmup + steps
-    for mode in ("streams", "segmented"):
-        batch.set_mode(mode)
+    for fm in fixed_modes:
+        batch.set_mode(fm)
         torch.cuda.synchronize()
         t1 = time.perf_counter()
-        its_m = 0
+        its_m, by, ms = 0, 0.0, 0.0
         for _ in range(extra):
             its_m += sum(d["iters"] for d in run(k))
+            b_, m_ = batch.solve_stats()
+            by, ms = by + b_, ms + m_
             k += 1
         torch.cuda.synchronize()
-        fixed[mode] = dict(ms_per_step=round(1e3 * (time.perf_counter() - t1) / extra, 3),
-                           krylov_iters_per_step=its_m / extra, steps=f"{k - extra}..{k - 1}")
+        fixed[fm] = dict(ms_per_step=round(1e3 * (time.perf_counter() - t1) / extra, 3),
+                         krylov_iters_per_step=its_m / extra, steps=f"{k - extra}..{k - 1}")
+        if fm == "segmented" and ms > 0:
+            # the engine's solve: algorithmic bytes (CSR once and each Krylov vector
+            # read or written once per phase) over its wall time, against the HBM peak
+            tbs = by / (ms * 1e-3) / 1e12
+            fixed[fm].update(solve_ms_per_step=round(ms / extra, 3), solve_gb_per_step=round(by / extra / 1e9, 2),
+                             solve_tb_per_s=round(tbs, 3), solve_frac_of_hbm_peak=round(tbs / 8.0, 3))
     batch.close()
     for s in seqs:
         s.close()
@@ -562,6 +573,11 @@ def main():
     ap.add_argument("--batch-warmup", type=int, default=11,
                     help="batch steps after the histories fill, before timing (the plan tuner times 11 candidates)")
     ap.add_argument("--batch-steps", type=int, default=4)
+    ap.add_argument("--batch-mode", choices=["auto", "streams", "segmented"], default="auto",
+                    help="plan of the timed batch steps (auto: tuned)")
+    ap.add_argument("--batch-max-streams", type=int, default=8)
+    ap.add_argument("--batch-which", choices=["both", "large", "small"], default="both")
+    ap.add_argument("--batch-no-fixed", action="store_true", help="skip the steps in each fixed mode")
     ap.add_argument("--no-batch", action="store_true")
     ap.add_argument("--only-batch", action="store_true", help="run only the batched workload")
     ap.add_argument("--only-advdiff", action="store_true",
@@ -583,9 +599,14 @@ def main():
     import paper_2309_02156_amd as sacc
 
     if args.only_batch:
-        print(json.dumps({"batch64": batch_cmp(sacc, torch, np, args.batch_warmup, args.batch_steps),
-                          "batch64_small": batch_cmp(sacc, torch, np, args.batch_warmup, args.batch_steps, lo=32,
-                                                     hi=128)}), flush=True)
+        kw = dict(max_streams=args.batch_max_streams, mode=args.batch_mode,
+                  fixed_modes=() if args.batch_no_fixed else ("streams", "segmented"))
+        out = {}
+        if args.batch_which in ("both", "large"):
+            out["batch64"] = batch_cmp(sacc, torch, np, args.batch_warmup, args.batch_steps, **kw)
+        if args.batch_which in ("both", "small"):
+            out["batch64_small"] = batch_cmp(sacc, torch, np, args.batch_warmup, args.batch_steps, lo=32, hi=128, **kw)
+        print(json.dumps(out), flush=True)
         return
     if args.only_advdiff:
         if args.copy_calibration:

@@ -337,6 +337,12 @@ int sa_batch_plan(const sa_batch *b, int *streams, int *poll, int *tuned, int *s
 #define SA_BATCH_SEGMENTED_EAGER 3
 int sa_batch_set_mode(sa_batch *b, int mode);
 
+/* The last step's segmented solve: its algorithmic bytes (the CSR arrays once and every
+ * Krylov vector read or written once per phase of each system; FP64 x and b, float32
+ * values and columns) and its host wall time in ms, from the first engine launch to the
+ * end of the last; both 0 when the last step ran on streams.  Errors: SA_EINVAL. */
+int sa_batch_solve_stats(const sa_batch *b, double *bytes, double *ms);
+
 /* Copy internal state to host memory for inspection:
  *   what = 0: SX, s x M float64 column-major, columns in ring-slot order;
  *   what = 1: X, n x M column-major in ring-slot order, float32 for SA_MIXED, else

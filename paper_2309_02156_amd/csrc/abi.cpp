@@ -1533,6 +1533,7 @@ struct sa_batch {
   int mode = SA_BATCH_AUTO;
   bool seg_ok = false;        // every sequence is mixed-precision without a preconditioner
   SegEngine *seg = nullptr;   // created on first segmented step
+  double seg_bytes = 0.0, seg_ms = 0.0;  // the last step's segmented solve (0 after a stream step)
 };
 
 namespace {
@@ -1612,6 +1613,7 @@ int batch_step_seg(sa_batch *b, const Plan &plan, const std::vector<std::vector<
     d.d32 = q->d32;
     d.n = c.n;
     d.ld = q->ld;
+    d.nnz = A[i]->nnz;
     d.solver = c.solver;
     d.m = c.solver == SA_GMRES ? c.restart : 0;
     d.max_refine = c.max_refine;
@@ -1628,6 +1630,9 @@ int batch_step_seg(sa_batch *b, const Plan &plan, const std::vector<std::vector<
     if (res[i].state == ST_ZERO_RHS) HIP_TRY(hipMemsetAsync(x[i], 0, (size_t)desc[i].n * sizeof(double), st));
   HIP_TRY(hipStreamSynchronize(st));
   const float ms = (float)(1e3 * std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count());
+  b->seg_bytes = 0.0;
+  for (int i = 0; i < nseq; ++i) b->seg_bytes += res[i].bytes;
+  b->seg_ms = ms;
   for (int i = 0; i < nseq; ++i) {
     const SegResult &r = res[i];
     if (r.state < ST_RUN || r.state > ST_ZERO_RHS) return SA_EHIP;
@@ -1727,6 +1732,13 @@ int sa_batch_plan(const sa_batch *b, int *streams, int *poll, int *tuned, int *s
   return SA_OK;
 }
 
+int sa_batch_solve_stats(const sa_batch *b, double *bytes, double *ms) {
+  if (!b || !bytes || !ms) return SA_EINVAL;
+  *bytes = b->seg_bytes;
+  *ms = b->seg_ms;
+  return SA_OK;
+}
+
 int sa_batch_set_mode(sa_batch *b, int mode) {
   if (!b || mode < SA_BATCH_AUTO || mode > SA_BATCH_SEGMENTED_EAGER) return SA_EINVAL;
   if ((mode == SA_BATCH_SEGMENTED || mode == SA_BATCH_SEGMENTED_EAGER) && !b->seg_ok) return SA_EINVAL;
@@ -1789,6 +1801,7 @@ int sa_batch_step(sa_batch *b, const sa_csr *const *A, const void *const *rhs, v
     }
   };
   const auto t0 = std::chrono::steady_clock::now();
+  b->seg_bytes = b->seg_ms = 0.0;
   if (seg) {
     const int r = batch_step_seg(b, plan, lists, A, rhs, x, inf, b->mode != SA_BATCH_SEGMENTED_EAGER);
     if (r != SA_OK) return r;

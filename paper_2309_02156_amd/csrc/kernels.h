@@ -229,7 +229,7 @@ struct SegDesc {
   double *x;          // in: the initial guess; out: the solution
   float *kry, *r32, *d32;
   double *part;       // set by the engine
-  int64_t n, ld;
+  int64_t n, ld, nnz;
   int nblk;           // set by the engine
   int solver, m, max_refine, maxit, icap;
   double tol, itol;
@@ -238,6 +238,7 @@ struct SegDesc {
 struct SegResult {
   int state, iters, restarts, sweeps;
   double relres0, relres;
+  double bytes;  // algorithmic bytes of the system's row work in the solve
 };
 struct SegEngine;
 // an engine for systems of sizes n[0..nseg); chunk: gathers per lane of its SpMV tiles

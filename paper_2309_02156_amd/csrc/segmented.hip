@@ -66,6 +66,7 @@ struct SegState {
   int phase, status, sweep, sweeps, iters, restarts;
   int inner_it, icap_cur, j, jend, cycles, par, first, pad;
   double bnorm, relres0, relres;
+  double bytes;  // algorithmic bytes of the row work done so far in this solve
   double ith, rho, alpha, beta, hn;
   double h[SG_R + 1], h2[SG_R + 1], c[SG_R + 1], g[SG_R + 1], cs[SG_R], sn[SG_R], y[SG_R];
   double Hraw[SG_R * (SG_R + 1)];  // Hessenberg columns as built: column j at Hraw[j * (SG_R + 1)]
@@ -455,8 +456,26 @@ __device__ inline void cycle_start(SegState &st, double beta) {
   st.phase = SP_F;
 }
 
+// Algorithmic bytes of one phase's row work (float32 operator values and Krylov
+// columns, FP64 x and b): the CSR arrays once, each vector read or written once.
+__device__ inline double phase_bytes(int phase, int j, int jend, int64_t n, int64_t nnz) {
+  const double csr = 4.0 * (double)(n + 1) + 8.0 * (double)nnz, N = (double)n;
+  switch (phase) {
+    case SP_RES: return csr + 28.0 * N;             // x, b; r32, r, d
+    case SP_XUPD: return 20.0 * N;                  // x read and written, d
+    case SP_CGQ: return csr + 16.0 * N;             // r, p; p', q
+    case SP_CGU: return 24.0 * N;                   // p, q, d, r; d, r
+    case SP_F: return csr + (12.0 + 4.0 * j) * N;   // u, V_{<j}; v_j, w_j
+    case SP_G: return (12.0 + 4.0 * j) * N;         // w, V_{<=j}; w'
+    case SP_UPD: return (8.0 + 4.0 * jend) * N;     // V_{<jend}, d; d
+    case SP_GRES: return csr + 12.0 * N;            // d, r32; u
+    default: return 0.0;
+  }
+}
+
 __device__ void seg_logic(const SegDesc &d, SegState &st, const double *tot, int s, volatile int *done) {
   const bool gm = d.solver == SA_GMRES;
+  st.bytes += phase_bytes(st.phase, st.j, st.jend, d.n, d.nnz);
   switch (st.phase) {
     case SP_RES: {
       const double nr = sqrt(tot[0]);
@@ -647,6 +666,7 @@ __global__ void k_seg_init(SegState *S, int nseg) {
   st.sweep = st.sweeps = st.iters = st.restarts = 0;
   st.inner_it = st.icap_cur = st.j = st.jend = st.cycles = st.par = st.first = 0;
   st.bnorm = st.relres0 = st.relres = 0.0;
+  st.bytes = 0.0;
   st.ith = st.rho = st.alpha = st.beta = st.hn = 0.0;
 }
 
@@ -858,6 +878,7 @@ hipError_t seg_engine_solve(SegEngine *e, const SegDesc *desc, bool graph, hipSt
     res[s].sweeps = sm.sweeps;
     res[s].relres0 = sm.relres0;
     res[s].relres = sm.relres;
+    res[s].bytes = sm.bytes;
   }
   return hipSuccess;
 }

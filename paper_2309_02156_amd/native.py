@@ -26,7 +26,7 @@ EXPORTS = ("sa_workspace_bytes", "sa_init_sequence", "sa_push_solution", "sa_ini
            "sa_solve", "sa_step", "sa_destroy_sequence", "sa_status_string", "sa_spmv", "sa_copy_state",
            "sa_profile_enable", "sa_profile_read", "sa_mlp_create", "sa_mlp_destroy", "sa_mlp_set_scaling",
            "sa_mlp_forward", "sa_mlp_train_step", "sa_mlp_get", "sa_learned_attach", "sa_set_time",
-           "sa_batch_create", "sa_batch_destroy", "sa_batch_step", "sa_batch_plan", "sa_batch_set_mode", "sa_solve_static",
+           "sa_batch_create", "sa_batch_destroy", "sa_batch_step", "sa_batch_plan", "sa_batch_set_mode", "sa_batch_solve_stats", "sa_solve_static",
            "sa_static_scratch_bytes", "sa_state_bytes", "sa_export_state", "sa_import_state")
 
 
@@ -122,6 +122,7 @@ def lib() -> ctypes.CDLL:
     L.sa_batch_step.argtypes = [vp, P(vp), P(vp), P(vp), P(SaInfo)]
     L.sa_batch_plan.argtypes = [vp, P(i32), P(i32), P(i32), P(i32)]
     L.sa_batch_set_mode.argtypes = [vp, i32]
+    L.sa_batch_solve_stats.argtypes = [vp, P(ctypes.c_double), P(ctypes.c_double)]
     L.sa_solve_static.argtypes = [P(SaConfig), P(SaCsr), vp, vp, P(SaInfo), vp]
     L.sa_static_scratch_bytes.argtypes = [P(SaConfig), P(sz), P(sz)]
     L.sa_state_bytes.argtypes = [vp, P(sz)]

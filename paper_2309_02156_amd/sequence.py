@@ -359,6 +359,13 @@ class Batch:
         """"auto" (tuned), "streams", "segmented" (graph replays) or "segmented_eager"."""
         nv.check(nv.lib().sa_batch_set_mode(self._h, self.MODES[mode]), "sa_batch_set_mode")
 
+    def solve_stats(self):
+        """(algorithmic bytes, ms) of the last step's segmented solve; zeros after a
+        stream step."""
+        b, ms = ctypes.c_double(), ctypes.c_double()
+        nv.check(nv.lib().sa_batch_solve_stats(self._h, ctypes.byref(b), ctypes.byref(ms)), "sa_batch_solve_stats")
+        return b.value, ms.value
+
     def plan(self):
         s, p, t, g = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32()
         nv.check(nv.lib().sa_batch_plan(self._h, ctypes.byref(s), ctypes.byref(p), ctypes.byref(t), ctypes.byref(g)),
