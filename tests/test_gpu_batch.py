@@ -184,3 +184,79 @@ def test_batch_matches_oracle(sacc, mode):
             oseqs[j].push(xg)   # the oracle's history follows the GPU's
     print_case("(step, seq, iters gpu, iters oracle, oracle spread, k)", rows)
     assert abs(tot_g - tot_o) <= 0.03 * tot_o, (tot_g, tot_o)
+
+
+def _edge_matrix(n, kind, seed):
+    import scipy.sparse as sp
+
+    if n == 1:
+        A = sp.csr_matrix(np.array([[3.0]]))
+    else:
+        R = sp.random(n, n, density=min(1.0, 4.0 / n), random_state=seed, format="csr")
+        if kind == "cg":  # symmetric, diagonally dominant: SPD
+            S = R + R.T
+            A = S + sp.diags(np.asarray(abs(S).sum(axis=1)).ravel() + 1.0)
+        else:  # nonsymmetric, diagonally dominant
+            A = R - 0.5 * R.T + sp.diags(np.asarray(abs(R).sum(axis=1)).ravel() + 2.0)
+    A = sp.csr_matrix(A, dtype=np.float32)
+    A.sort_indices()
+    return A
+
+
+def test_batch_segmented_edge_cases(sacc):
+    """The segmented engine on ragged and tiny systems (n = 1 .. 3000, not multiples of
+    its 64-row tiles or 1024-row work items), GMRES restart lengths 1, 2, 7 and 30, a
+    zero right-hand side in the second step, and an iteration cap of 3: each system
+    against the oracle's refinement solve from the same zero start (guess "zero"),
+    equal stopping status, the cap's count exact, zero x for b = 0, converged counts
+    within max(sweeps, 2 spread + 1, 10 %) of the oracle's and the tolerance met."""
+    import math
+
+    import torch
+
+    from oracle import mixed as omx
+    from tests.gpu_helpers import reversed_order
+
+    cases = [(1, "cg", 30, 0), (5, "gmres", 1, 0), (63, "cg", 30, 0), (65, "gmres", 2, 0),
+             (1025, "gmres", 30, 0), (1025, "cg", 30, 0), (3000, "gmres", 7, 0), (700, "cg", 30, 3),
+             (900, "gmres", 30, 3)]
+    mats = [_edge_matrix(n, kind, 40 + k) for k, (n, kind, _, _) in enumerate(cases)]
+    seqs = [sacc.Sequence(n, 2, s=4, solver=kind, restart=r, tol=1e-8, precision="mixed_krylov", max_refine=20,
+                          guess="zero", maxit=mx if mx else 200000)
+            for (n, kind, r, mx) in cases]
+    batch = sacc.Batch(seqs, max_streams=2)
+    batch.set_mode("segmented")
+    rng = np.random.default_rng(9)
+    As = [sacc.DeviceCSR(A.indptr, A.indices, A.data) for A in mats]
+    for step in range(2):
+        bs_h = [rng.standard_normal(n) for (n, _, _, _) in cases]
+        if step == 1:
+            bs_h[2] = np.zeros(cases[2][0])
+            bs_h[4] = np.zeros(cases[4][0])
+        bs = [dev(b) for b in bs_h]
+        xs = [torch.empty(n, dtype=torch.float64, device="cuda") for (n, _, _, _) in cases]
+        infos = batch.step(As, bs, xs)
+        for j, (n, kind, r, mx) in enumerate(cases):
+            print_case("edge", step, n, kind, r, mx, infos[j]["iters"], infos[j]["status"])
+            A64 = mats[j].astype(np.float64)
+            b = bs_h[j]
+            xg = host(xs[j])
+            gi = infos[j]
+            if not b.any():
+                assert np.array_equal(xg, np.zeros(n)) and gi["iters"] == 0 and gi["status"] == 0
+                continue
+            maxit = mx if mx else 200000
+            xo, oi = omx.solve_ir(A64, b, np.zeros(n), 1e-8, kind, r, 1e-4, 20, maxit)
+            if mx:
+                assert oi["status"] == 1 and gi["status"] != 0, (j, oi["status"], gi["status"])
+                assert gi["iters"] == oi["iters"] == mx, (j, gi["iters"], oi["iters"])
+                continue
+            rel = np.linalg.norm(b - A64 @ xg) / np.linalg.norm(b)
+            assert gi["status"] == 0 and oi["status"] == 0, (j, gi["status"], oi["status"])
+            assert rel <= 1e-8 * (1 + 1e-6), (j, rel)
+            assert abs(gi["relres"] - rel) <= 1e-6 * rel + 1e-15, (j, gi["relres"], rel)
+            _, o2 = omx.solve_ir(reversed_order(A64.tocsr()), b, np.zeros(n), 1e-8, kind, r, 1e-4, 20, maxit)
+            spread = abs(o2["iters"] - oi["iters"])
+            sweeps = max(gi["refinements"], oi["refinements"], 1)
+            allowed = max(sweeps, 2 * spread + 1, math.ceil(0.1 * oi["iters"]))
+            assert abs(gi["iters"] - oi["iters"]) <= allowed, (j, gi["iters"], oi["iters"], allowed)
