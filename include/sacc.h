@@ -315,8 +315,9 @@ int sa_batch_plan(const sa_batch *b, int *streams, int *poll, int *tuned, int *s
 
 /* Execution of a batch's solves.
  *   SA_BATCH_AUTO: the tuner times the stream plans and, where every sequence is
- *     SA_MIXED or SA_MIXED_KRYLOV without a preconditioner, the segmented ones, and
- *     keeps the fastest (the default);
+ *     SA_MIXED or SA_MIXED_KRYLOV without a preconditioner, the segmented ones (host
+ *     threads for the guesses, the engine's grid size), and keeps the fastest (the
+ *     default);
  *   SA_BATCH_STREAMS: every sequence's solve on its own stream (max_streams threads);
  *   SA_BATCH_SEGMENTED: the solves of all sequences advanced together by the
  *     segmented engine: per engine step one launch over the rows of every unfinished

@@ -247,7 +247,10 @@ int seg_engine_create(const int64_t *n, int nseg, int chunk, SegEngine **out);
 void seg_engine_destroy(SegEngine *e);
 // Solves every system (desc[i].n must equal the engine's n[i]) on stream st, eager
 // launches or replays of one captured hipGraph per chunk of steps; synchronous.
-hipError_t seg_engine_solve(SegEngine *e, const SegDesc *desc, bool graph, hipStream_t st, SegResult *res);
+// oversub: the data kernel's grid in multiples of the blocks the device holds at once
+// (1..64; 0: the default 8).
+hipError_t seg_engine_solve(SegEngine *e, const SegDesc *desc, bool graph, int oversub, hipStream_t st,
+                            SegResult *res);
 int seg_rows_per_block();
 
 }  // namespace sacc

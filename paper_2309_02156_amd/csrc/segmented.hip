@@ -824,13 +824,15 @@ static long long seg_step_bound(const SegDesc &d) {
   return 2 * sw + 6 * it + 16;
 }
 
-hipError_t seg_engine_solve(SegEngine *e, const SegDesc *desc, bool graph, hipStream_t st, SegResult *res) {
+hipError_t seg_engine_solve(SegEngine *e, const SegDesc *desc, bool graph, int oversub, hipStream_t st,
+                            SegResult *res) {
   const int nseg = e->nseg;
-  // SACC_SEG_OVERSUB (1..64) overrides the data kernel's grid multiple (a tuning knob)
+  // the data kernel's grid multiple: the caller's (the batch tuner's), 8 by default;
+  // SACC_SEG_OVERSUB (1..64) pins it (reproducible measurements)
   {
     const char *ev = getenv("SACC_SEG_OVERSUB");
     const int v = ev ? atoi(ev) : 0;
-    const int want = v >= 1 && v <= 64 ? v : 8;
+    const int want = v >= 1 && v <= 64 ? v : (oversub >= 1 && oversub <= 64 ? oversub : 8);
     if (want != e->oversub && e->gexec) {
       (void)hipGraphExecDestroy(e->gexec);
       (void)hipGraphDestroy(e->graph);
