@@ -647,7 +647,7 @@ def main():
         "vs_baseline": None,
         "dtype": "f32+f64",
         "data": "synthetic",
-        "config": {"workload": f"lognormal3d 128^3 (n={p.n}, nnz=14581760, float32 values, int32 indices), "
+        "config": {"workload": f"lognormal3d 128^3 (n={p.n}, nnz=14581760, float32 values, int32 indices packed by the solve to 16-bit row offsets), "
                                f"M={M}, Gaussian s={method['s']}, Galerkin, CG in float32 with FP64 "
                                f"refinement to relres {method['tol']:g}, float32 history",
                    "history_fill_steps": M, "steps_timed": f"{first}..{first + args.steps - 1}"},

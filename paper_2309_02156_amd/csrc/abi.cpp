@@ -54,6 +54,8 @@ struct sa_seq {
   double *SX = nullptr, *partials = nullptr;
   void *kry = nullptr;               // Krylov vectors (double, or float for inner solves)
   float *r32 = nullptr, *d32 = nullptr;  // mixed: inner right-hand side and correction
+  short *col16 = nullptr;  // mixed CG: packed 16-bit column offsets of the current matrix
+  size_t col16_cap = 0;    // (allocated on first use, grown with the matrix's nonzeros)
   long long *srht_rows = nullptr;
   unsigned long long *srht_signs = nullptr;  // SRHT sign words (one bit per row of x)
   unsigned short *sketch_bf16 = nullptr;     // SA_MIXED Gaussian sketch: BF16 normals (MFMA push)
@@ -430,11 +432,12 @@ int run_cg(sa_seq *q, const CsrView &v, Ctl *ctl, const TV *b, TV *x, int maxit,
   TV *r = (TV *)q->kry, *p2 = r + q->ld, *qq = r + 3 * q->ld;
   SA_TRY(prof_begin(q, ctl, st));
   const size_t w = sizeof(TV), wv = v.fp32 ? 4 : 8;
-  const double csr = 4.0 * (v.n + 1) + (4.0 + wv) * v.nnz;
+  const double wi = v.col16 ? 2.0 : 4.0;  // bytes per column index
+  const double csr = 4.0 * (v.n + 1) + (wi + wv) * v.nnz;
   // wave-tile shape of the CG kernels: tuned on first use of this operator shape
   const int chunk = q->tune ? cg_tile_tune<TV>(v, b, x, r, q->partials, ctl, st) : cg_tile_chunk(v.n, v.nnz);
-  const std::string pname =
-      std::string("k_cg_p<") + tname(wv) + ", " + tname(w) + ", " + std::to_string(chunk) + ">";
+  const std::string pname = std::string("k_cg_p<") + tname(wv) + ", " + tname(w) + ", " + std::to_string(chunk) +
+                            (v.col16 ? ", i16>" : ">");
   Progress pg = progress_of(q, ctl);
   pg.reset();
   const int ahead = c.poll > MIR_EVERY ? c.poll : MIR_EVERY;  // progress arrives every MIR_EVERY steps
@@ -862,14 +865,38 @@ static int inner_cap(const sa_config &c) {
   return c.solver == SA_GMRES ? 10 * c.restart : 1000;
 }
 
+// Mixed CG: the inner solves' kernels read the matrix's column indices as 16-bit offsets
+// from the row (half the index bytes of the bandwidth-bound SpMV) when every offset fits;
+// packed once per solve, the fit reported with the first residual's poll.  The array is
+// allocated on first use and grown with the nonzeros; SACC_NO_COL16 turns it off.
+static int col16_prepare(sa_seq *q, const CsrView &v, hipStream_t st) {
+  const bool want = q->cfg.solver == SA_CG && v.nnz > 0 && !getenv("SACC_NO_COL16");
+  if (want && (size_t)v.nnz > q->col16_cap) {
+    if (q->col16) (void)hipFree(q->col16);
+    q->col16 = nullptr;
+    q->col16_cap = 0;
+    if (hipMalloc((void **)&q->col16, (size_t)v.nnz * sizeof(short)) != hipSuccess) {
+      q->col16 = nullptr;
+      return launch_set_int(&q->ctl->col16_ok, 0, st) == hipSuccess ? SA_OK : SA_EHIP;
+    }
+    q->col16_cap = (size_t)v.nnz;
+  }
+  HIP_TRY(launch_set_int(&q->ctl->col16_ok, want ? 1 : 0, st));
+  if (want) HIP_TRY(launch_col_rel16(v, q->col16, &q->ctl->col16_ok, st));
+  return SA_OK;
+}
+
 static int solve_mixed(sa_seq *q, const CsrView &v, const double *b, double *x, int *iters, int *restarts,
                        int *sweeps, hipStream_t st) {
   const sa_config &c = q->cfg;
   int *hs = q->hbuf;
   *iters = *restarts = *sweeps = 0;
+  SA_TRY(col16_prepare(q, v, st));
+  CsrView vi = v;  // the inner solves' view
   for (int sweep = 0;; ++sweep) {
     HIP_TRY(launch_ir_resid(v, b, x, q->r32, q->partials, sweep, c.max_refine, q->ctl, st));
     SA_TRY(poll(q, q->ctl, st));
+    if (sweep == 0 && hs[7] == 1 && q->col16) vi.col16 = q->col16;
     const int outer = hs[0];
     if (outer < ST_RUN || outer > ST_ZERO_RHS) return SA_EHIP;
     if (outer != ST_RUN || *iters >= c.maxit) {
@@ -884,7 +911,7 @@ static int solve_mixed(sa_seq *q, const CsrView &v, const double *b, double *x, 
     hs[40] = c.maxit - *iters < inner_cap(c) ? c.maxit - *iters : inner_cap(c);
     HIP_TRY(launch_set_int(&q->ctl_in->maxit, hs[40], st));
     HIP_TRY(hipMemsetAsync(q->d32, 0, (size_t)c.n * sizeof(float), st));
-    SA_TRY(run_krylov<float>(q, v, q->ctl_in, q->r32, q->d32, hs[40], st));
+    SA_TRY(run_krylov<float>(q, vi, q->ctl_in, q->r32, q->d32, hs[40], st));
     const int inner_state = hs[0];
     *iters += hs[1];
     *restarts += hs[2];
@@ -1003,6 +1030,7 @@ int sa_destroy_sequence(sa_seq *q) {
   if (q->ctl) (void)hipFree(q->ctl);
   if (q->ctl_in) (void)hipFree(q->ctl_in);
   if (q->hbuf) (void)hipHostFree(q->hbuf);
+  if (q->col16) (void)hipFree(q->col16);
   for (auto m : q->mir)
     if (m) (void)hipHostFree(m);
   for (int e = 0; e < 4; ++e)

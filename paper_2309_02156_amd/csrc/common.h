@@ -35,7 +35,8 @@ struct Ctl {
   // Krylov state (read by the host poll: state .. pad0 are contiguous)
   double bnorm, relres0, relres, tol;
   int state, iters, restarts, maxit;
-  int active, jend, restart, pad0;
+  int active, jend, restart, col16_ok;  // col16_ok: the packed column offsets of the current
+                                         // matrix fit in 16 bits (mixed CG)
   int kcur;                     // CG: number of the iteration in flight
   int fresh_at;                 // CG: iteration whose direction restarts from p = r
   int ibase;                    // GMRES: iterations done before the current cycle
@@ -631,7 +632,9 @@ __device__ inline void wave_lds_sync() {
 // its last entry, a tile with no nonzero up to it re-reads entry 0, so col and val must
 // hold at least one entry even for a matrix without nonzeros (callers pass stand-ins),
 // and the loads of the last tile's successor re-read the last tile.  lcol / lval: the
-// wave's LDS slices of WT_CAP entries.
+// wave's LDS slices of WT_CAP entries.  IT: the column index type, int (columns) or
+// short (each entry's column minus its row, for matrices whose offsets fit in 16 bits:
+// half the index bytes; the products and their order are the same).
 // The row pointers of a wave's first tile, for a caller that requests them before its
 // own prologue (wave_tiles_spmv's `first` argument); in bounds for any t.
 struct TileRows0 {
@@ -643,12 +646,13 @@ __device__ inline TileRows0 wave_tile_first_rows(const int *__restrict__ rowptr,
   return TileRows0{rowptr[ic], rowptr[ic + 1]};
 }
 
-template <int C, typename VT, typename G, typename PRE, typename EPI>
-__device__ inline void wave_tiles_spmv(const int *__restrict__ rowptr, const int *__restrict__ col,
+template <int C, typename IT, typename VT, typename G, typename PRE, typename EPI>
+__device__ inline void wave_tiles_spmv(const int *__restrict__ rowptr, const IT *__restrict__ col,
                                        const VT *__restrict__ val, const G &gx, int64_t n, int64_t t, int64_t end,
                                        int64_t step, int *lcol, VT *lval, const PRE &pre, const EPI &epi,
                                        const TileRows0 *first = nullptr) {
   using XT = decltype(gx(0));
+  constexpr bool REL = sizeof(IT) == 2;
   const int lane = threadIdx.x % WAVE;
   if (t >= end) return;
   int a, b, p0, p1, cc[C];
@@ -728,7 +732,7 @@ __device__ inline void wave_tiles_spmv(const int *__restrict__ rowptr, const int
         for (int u = 0; u < C; ++u) {
           const int k = k0 + u;
           const int idx = k < len ? off + k : 0;
-          c[u] = k < len ? lcol[idx] : (int)ic;
+          c[u] = k < len ? (REL ? (int)ic + lcol[idx] : lcol[idx]) : (int)ic;
           v[u] = lval[idx];
         }
 #pragma unroll
@@ -739,7 +743,8 @@ __device__ inline void wave_tiles_spmv(const int *__restrict__ rowptr, const int
       }
       wave_lds_sync();  // the slices are rewritten by the wave's next tile
     } else {
-      for (int pp = a; pp < a + len; ++pp) s += __dmul_rn((double)val[pp], (double)gx(col[pp]));
+      for (int pp = a; pp < a + len; ++pp)
+        s += __dmul_rn((double)val[pp], (double)gx(REL ? (int)ic + (int)col[pp] : (int)col[pp]));
     }
     if (i < n) epi(i, own, s);
     if (!more) break;

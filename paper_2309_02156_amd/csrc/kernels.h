@@ -13,6 +13,9 @@ struct CsrView {
   const int *rowptr, *col;
   const void *val;
   int fp32;
+  // optional: col[p] - row(p) for every entry, all within 16 bits (the CG kernels then
+  // read these instead of col)
+  const short *col16 = nullptr;
 };
 
 // y = A x
@@ -204,6 +207,10 @@ hipError_t launch_learn_pick(const CsrView &A, const double *b, double *x0, cons
 hipError_t launch_ctl_reset(Ctl *ctl, double tol, int maxit, int restart, int trust_est, hipStream_t st);
 // *p = v in stream order, from a kernel (no host-side copy)
 hipError_t launch_set_int(int *p, int v, hipStream_t st);
+
+// packed 16-bit column offsets of A (out: nnz entries) for the CG kernels; *ok is set to
+// 0 when an offset does not fit (the caller sets it to 1 first)
+hipError_t launch_col_rel16(const CsrView &A, short *out, int *ok, hipStream_t st);
 
 // x = 0 by a fill kernel
 hipError_t launch_zero(double *x, int64_t n, hipStream_t st);

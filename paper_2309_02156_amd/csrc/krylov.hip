@@ -158,8 +158,8 @@ __device__ inline double pick4(const double (&r)[4], int e) {
 // recursive-residual stop (state CHECK) the host's batch-end confirmation recomputes
 // the true residual; if it fails the direction restarts (p = r).
 
-template <typename VT, typename TV, int C, bool PC>
-__global__ __launch_bounds__(KTPB) void k_cg_start(const int *rowptr, const int *col, const VT *val,
+template <typename VT, typename TV, int C, bool PC, typename IT>
+__global__ __launch_bounds__(KTPB) void k_cg_start(const int *rowptr, const IT *col, const VT *val,
                                                    const TV *b, const TV *x, TV *r, int64_t n, int mode,
                                                    double *Pout, Ctl *ctl, const TV *dinv) {
   __shared__ double red[KNW * 4];
@@ -249,8 +249,8 @@ struct GatherDir {
 // C = gathers per lane and round of a wave tile
 // Also applies the x update of the previous iteration, x += alpha_{k-1} p_{k-1}, for its
 // own rows (the x / r kernel leaves it pending: p_{k-1} is this kernel's input direction).
-template <typename VT, typename TV, int C, bool PC>
-__global__ __launch_bounds__(KTPB) void k_cg_p(const int *rowptr, const int *col, const VT *val, const TV *r,
+template <typename VT, typename TV, int C, bool PC, typename IT>
+__global__ __launch_bounds__(KTPB) void k_cg_p(const int *rowptr, const IT *col, const VT *val, const TV *r,
                                                TV *P0, TV *P1, TV *q, int64_t n, const double *Pin, int nblk,
                                                double *Pout, Ctl *ctl, int lidx, const TV *dinv, TV *x) {
   __shared__ double red[KNW];
@@ -452,14 +452,25 @@ __global__ __launch_bounds__(KTPB) void k_cg_xr(TV *x, TV *r, const TV *P0, cons
 // Grid of the CG iteration kernels: one wave tile per wave, at most the blocks the device
 // holds at once (every block of the grid-stride loop resident, so no tail of late
 // blocks), a multiple of NXCD.  The p / q kernel's registers decide the occupancy.
-template <typename VT, typename TV, int C, bool PC>
+// the column array of the CG kernels: the packed 16-bit offsets or the columns; without
+// nonzeros a stand-in (the SpMV reads one entry; never used in a product)
+template <typename IT>
+static inline const IT *cg_cols(const CsrView &A, const void *standin) {
+  if (A.nnz == 0) return (const IT *)standin;
+  if constexpr (sizeof(IT) == 2)
+    return A.col16;
+  else
+    return A.col;
+}
+
+template <typename VT, typename TV, int C, bool PC, typename IT>
 static int cg_grid(int64_t n) {
-  static int resident = 0;  // blocks of k_cg_p<VT, TV, C, PC> the device holds at once
+  static int resident = 0;  // blocks of k_cg_p<VT, TV, C, PC, IT> the device holds at once
   if (resident == 0) {
     int dev = 0, ncu = 0, per = 0;
     if (hipGetDevice(&dev) != hipSuccess ||
         hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
-        hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, k_cg_p<VT, TV, C, PC>, KTPB, 0) != hipSuccess ||
+        hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, k_cg_p<VT, TV, C, PC, IT>, KTPB, 0) != hipSuccess ||
         per < 1)
       return cgblocks(n);
     const int r = per * ncu / NXCD * NXCD;
@@ -476,7 +487,7 @@ static inline int cg_rows(int64_t n, int nb) {
   return per >= 4 ? 4 : (per >= 2 ? 2 : 1);
 }
 
-template <typename VT, typename TV, int C, int U, bool PC>
+template <typename VT, typename TV, int C, int U, bool PC, typename IT>
 static void cg_iter_launch(const CsrView &A, TV *x, TV *r, TV *P0, TV *P1, TV *q, double *partials, Ctl *ctl,
                            hipStream_t st, const KTiming *tm, int serial, int nb, const TV *dinv) {
   // timed launches record their start/stop events in the kernel's own dispatch
@@ -484,46 +495,52 @@ static void cg_iter_launch(const CsrView &A, TV *x, TV *r, TV *P0, TV *P1, TV *q
   const int lidx = tm ? tm->lidx : -1;
   // the SpMV reads one column / value entry even without nonzeros: stand-in arrays then
   // (the row pointers and the workspace's residual, never used in a product)
-  const int *colp = A.nnz > 0 ? A.col : A.rowptr;
+  const IT *colp = cg_cols<IT>(A, r);
   const VT *valp = A.nnz > 0 ? (const VT *)A.val : (const VT *)r;
-  hipExtLaunchKernelGGL((k_cg_p<VT, TV, C, PC>), dim3(nb), dim3(KTPB), 0, st, e0, e1, 0, A.rowptr, colp, valp, r,
+  hipExtLaunchKernelGGL((k_cg_p<VT, TV, C, PC, IT>), dim3(nb), dim3(KTPB), 0, st, e0, e1, 0, A.rowptr, colp, valp, r,
                         P0, P1, q, A.n, PA(partials), nb, PB(partials), ctl, lidx, dinv, x);
   hipLaunchKernelGGL((k_cg_xr<TV, U, PC>), dim3(nb), dim3(KTPB), 0, st, x, r, P0, P1, q, A.n, PB(partials), nb,
                      PA(partials), ctl, serial, dinv);
 }
 
-template <typename VT, typename TV, int C, bool PC>
+template <typename VT, typename TV, int C, bool PC, typename IT>
 static void cg_iter_u(const CsrView &A, TV *x, TV *r, TV *P0, TV *P1, TV *q, double *partials, Ctl *ctl,
                       hipStream_t st, const KTiming *tm, int serial, const TV *dinv) {
-  const int nb = cg_grid<VT, TV, C, PC>(A.n);
+  const int nb = cg_grid<VT, TV, C, PC, IT>(A.n);
   const int U = cg_rows(A.n, nb);
   if (U == 4)
-    cg_iter_launch<VT, TV, C, 4, PC>(A, x, r, P0, P1, q, partials, ctl, st, tm, serial, nb, dinv);
+    cg_iter_launch<VT, TV, C, 4, PC, IT>(A, x, r, P0, P1, q, partials, ctl, st, tm, serial, nb, dinv);
   else if (U == 2)
-    cg_iter_launch<VT, TV, C, 2, PC>(A, x, r, P0, P1, q, partials, ctl, st, tm, serial, nb, dinv);
+    cg_iter_launch<VT, TV, C, 2, PC, IT>(A, x, r, P0, P1, q, partials, ctl, st, tm, serial, nb, dinv);
   else
-    cg_iter_launch<VT, TV, C, 1, PC>(A, x, r, P0, P1, q, partials, ctl, st, tm, serial, nb, dinv);
+    cg_iter_launch<VT, TV, C, 1, PC, IT>(A, x, r, P0, P1, q, partials, ctl, st, tm, serial, nb, dinv);
 }
 
-template <typename VT, typename TV, int C, bool PC>
+template <typename VT, typename TV, int C, bool PC, typename IT>
 static int cg_start_c(const CsrView &A, const TV *b, const TV *x, TV *r, int mode, double *partials, Ctl *ctl,
                       hipStream_t st, const TV *dinv) {
-  const int nb = cg_grid<VT, TV, C, PC>(A.n);
-  // stand-ins without nonzeros, as for the iteration kernel (r: workspace of >= 576 entries)
-  const int *colp = A.nnz > 0 ? A.col : A.rowptr;
+  const int nb = cg_grid<VT, TV, C, PC, IT>(A.n);
+  const IT *colp = cg_cols<IT>(A, r);
   const VT *valp = A.nnz > 0 ? (const VT *)A.val : (const VT *)r;
-  hipLaunchKernelGGL((k_cg_start<VT, TV, C, PC>), dim3(nb), dim3(KTPB), 0, st, A.rowptr, colp, valp, b, x, r, A.n,
-                     mode, PA(partials), ctl, dinv);
+  hipLaunchKernelGGL((k_cg_start<VT, TV, C, PC, IT>), dim3(nb), dim3(KTPB), 0, st, A.rowptr, colp, valp, b, x, r,
+                     A.n, mode, PA(partials), ctl, dinv);
   return nb;
+}
+
+template <typename VT, typename TV, bool PC, typename IT>
+static int cg_start_it(const CsrView &A, const TV *b, const TV *x, TV *r, int mode, double *partials, Ctl *ctl,
+                       hipStream_t st, const TV *dinv, int chunk) {
+  const int C = chunk > 0 ? chunk : wave_tile_chunk(A.n, A.nnz);
+  if (C <= 5) return cg_start_c<VT, TV, 5, PC, IT>(A, b, x, r, mode, partials, ctl, st, dinv);
+  if (C <= 7) return cg_start_c<VT, TV, 7, PC, IT>(A, b, x, r, mode, partials, ctl, st, dinv);
+  return cg_start_c<VT, TV, 9, PC, IT>(A, b, x, r, mode, partials, ctl, st, dinv);
 }
 
 template <typename VT, typename TV, bool PC>
 static int cg_start_launch(const CsrView &A, const TV *b, const TV *x, TV *r, int mode, double *partials,
                            Ctl *ctl, hipStream_t st, const TV *dinv, int chunk) {
-  const int C = chunk > 0 ? chunk : wave_tile_chunk(A.n, A.nnz);
-  if (C <= 5) return cg_start_c<VT, TV, 5, PC>(A, b, x, r, mode, partials, ctl, st, dinv);
-  if (C <= 7) return cg_start_c<VT, TV, 7, PC>(A, b, x, r, mode, partials, ctl, st, dinv);
-  return cg_start_c<VT, TV, 9, PC>(A, b, x, r, mode, partials, ctl, st, dinv);
+  return A.col16 && A.nnz > 0 ? cg_start_it<VT, TV, PC, short>(A, b, x, r, mode, partials, ctl, st, dinv, chunk)
+                              : cg_start_it<VT, TV, PC, int>(A, b, x, r, mode, partials, ctl, st, dinv, chunk);
 }
 
 template <typename TV>
@@ -541,16 +558,25 @@ hipError_t launch_cg_start_k(const CsrView &A, const TV *b, const TV *x, TV *r, 
   return hipGetLastError();
 }
 
-template <typename VT, typename TV, bool PC>
-static void cg_iter_vt(const CsrView &A, TV *x, TV *r, TV *P0, TV *P1, TV *q, double *partials, Ctl *ctl,
+template <typename VT, typename TV, bool PC, typename IT>
+static void cg_iter_it(const CsrView &A, TV *x, TV *r, TV *P0, TV *P1, TV *q, double *partials, Ctl *ctl,
                        hipStream_t st, const KTiming *tm, int serial, const TV *dinv, int chunk) {
   const int C = chunk > 0 ? chunk : wave_tile_chunk(A.n, A.nnz);
   if (C <= 5)
-    cg_iter_u<VT, TV, 5, PC>(A, x, r, P0, P1, q, partials, ctl, st, tm, serial, dinv);
+    cg_iter_u<VT, TV, 5, PC, IT>(A, x, r, P0, P1, q, partials, ctl, st, tm, serial, dinv);
   else if (C <= 7)
-    cg_iter_u<VT, TV, 7, PC>(A, x, r, P0, P1, q, partials, ctl, st, tm, serial, dinv);
+    cg_iter_u<VT, TV, 7, PC, IT>(A, x, r, P0, P1, q, partials, ctl, st, tm, serial, dinv);
   else
-    cg_iter_u<VT, TV, 9, PC>(A, x, r, P0, P1, q, partials, ctl, st, tm, serial, dinv);
+    cg_iter_u<VT, TV, 9, PC, IT>(A, x, r, P0, P1, q, partials, ctl, st, tm, serial, dinv);
+}
+
+template <typename VT, typename TV, bool PC>
+static void cg_iter_vt(const CsrView &A, TV *x, TV *r, TV *P0, TV *P1, TV *q, double *partials, Ctl *ctl,
+                       hipStream_t st, const KTiming *tm, int serial, const TV *dinv, int chunk) {
+  if (A.col16 && A.nnz > 0)
+    cg_iter_it<VT, TV, PC, short>(A, x, r, P0, P1, q, partials, ctl, st, tm, serial, dinv, chunk);
+  else
+    cg_iter_it<VT, TV, PC, int>(A, x, r, P0, P1, q, partials, ctl, st, tm, serial, dinv, chunk);
 }
 
 template <typename TV>
@@ -588,10 +614,10 @@ hipError_t launch_cg_xfix(const CsrView &A, TV *x, TV *p2, Ctl *ctl, hipStream_t
 // process; the first solve of a new shape pays about 40 launches and three waits.
 template <typename TV>
 int cg_tile_tune(const CsrView &A, const TV *b, const TV *x, TV *r, double *partials, Ctl *ctl, hipStream_t st) {
-  using Key = std::tuple<int64_t, int64_t, int, int>;
+  using Key = std::tuple<int64_t, int64_t, int, int, int>;
   static std::map<Key, int> cache;
   static std::mutex mu;
-  const Key key{A.n, A.nnz, A.fp32, (int)sizeof(TV)};
+  const Key key{A.n, A.nnz, A.fp32, (int)sizeof(TV), A.col16 ? 1 : 0};
   {
     std::lock_guard<std::mutex> lk(mu);
     auto it = cache.find(key);
@@ -1662,6 +1688,28 @@ hipError_t launch_jacobi_dinv(const CsrView &A, TV *dinv, hipStream_t st) {
   else
     hipLaunchKernelGGL((k_jacobi_dinv<double, TV>), dim3(nb), dim3(KTPB), 0, st, A.rowptr, A.col,
                        (const double *)A.val, dinv, A.n);
+  return hipGetLastError();
+}
+
+// Packed 16-bit column offsets: out[p] = col[p] - row for every entry; *ok = 0 when an
+// offset does not fit (the caller sets *ok = 1 first; every failing row writes 0).
+__global__ __launch_bounds__(KTPB) void k_col_rel16(const int *rowptr, const int *col, int64_t n, short *out,
+                                                    int *ok) {
+  bool fits = true;
+  GRID_ROWS(i, n) {
+    const int a = rowptr[i], b = rowptr[i + 1];
+    for (int p = a; p < b; ++p) {
+      const int64_t d = (int64_t)col[p] - i;
+      fits = fits && d >= -32768 && d <= 32767;
+      out[p] = (short)d;
+    }
+  }
+  if (!fits) *ok = 0;
+}
+
+hipError_t launch_col_rel16(const CsrView &A, short *out, int *ok, hipStream_t st) {
+  if (A.nnz > 0)
+    hipLaunchKernelGGL(k_col_rel16, dim3(kblocks(A.n)), dim3(KTPB), 0, st, A.rowptr, A.col, A.n, out, ok);
   return hipGetLastError();
 }
 

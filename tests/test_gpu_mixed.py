@@ -194,3 +194,67 @@ def test_mixed_full_size_3d(sacc):
     assert sinfo["rc"] == 0 and true <= m["tol"] * (1 + 1e-6)
     assert abs(true - sinfo["relres"]) <= 1e-3 * m["tol"]
     assert sinfo["refinements"] >= 1
+
+
+@pytest.mark.parametrize("N", [24, 48])
+def test_mixed_cg_packed_columns_bitwise(sacc, N):
+    """Mixed CG reads the matrix's columns as 16-bit offsets from the row when every
+    offset fits (a 3-D seven-point operator: offsets up to N^2): the same products in
+    the same order, so solution, counts and residuals equal, bit for bit, those of the
+    solve with the full column indices (SACC_NO_COL16 set)."""
+    import os
+
+    p, _ = config(2, N)
+    A, As = _A(p, 3)
+    b = p.rhs(3)
+    Ad = sacc.DeviceCSR.from_csr(A)
+    out = []
+    for off in (False, True):
+        if off:
+            os.environ["SACC_NO_COL16"] = "1"
+        try:
+            seq = sacc.Sequence(p.n, 2, s=4, solver="cg", tol=1e-8, precision="mixed", inner_tol=1e-4, max_refine=10)
+            xd, info = seq.solve(Ad, dev(b), dev(np.zeros(p.n)))
+            out.append((host(xd), info))
+        finally:
+            os.environ.pop("SACC_NO_COL16", None)
+    (x1, i1), (x2, i2) = out
+    print_case("packed / full: iters", i1["iters"], i2["iters"], "sweeps", i1["refinements"], i2["refinements"])
+    assert np.array_equal(x1, x2)
+    for key in ("iters", "refinements", "relres", "relres0", "status"):
+        assert i1[key] == i2[key], (key, i1[key], i2[key])
+    assert np.linalg.norm(b - As @ x1) / np.linalg.norm(b) <= 1e-8 * (1 + 1e-6)
+
+
+def test_mixed_cg_far_offsets_fall_back(sacc):
+    """A matrix with a column 40000 rows from its row (beyond 16 bits) solves with the
+    full column indices: bitwise the result with packing turned off, tolerance met, the
+    oracle's count within one per sweep."""
+    import os
+
+    import scipy.sparse as sp
+
+    n, far = 70000, 40000
+    main = np.full(n, 4.0)
+    off1 = np.full(n - 1, -1.0)
+    offf = np.full(n - far, -0.5)
+    A = sp.diags([main, off1, off1, offf, offf], [0, 1, -1, far, -far], format="csr").astype(np.float32)
+    A.sort_indices()
+    As = A.astype(np.float64)
+    b = np.random.default_rng(5).standard_normal(n)
+    Ad = sacc.DeviceCSR(A.indptr, A.indices, A.data)
+    out = []
+    for off in (False, True):
+        if off:
+            os.environ["SACC_NO_COL16"] = "1"
+        try:
+            seq = sacc.Sequence(n, 2, s=4, solver="cg", tol=1e-8, precision="mixed", inner_tol=1e-4, max_refine=10)
+            xd, info = seq.solve(Ad, dev(b), dev(np.zeros(n)))
+            out.append((host(xd), info))
+        finally:
+            os.environ.pop("SACC_NO_COL16", None)
+    (x1, i1), (x2, i2) = out
+    assert np.array_equal(x1, x2) and i1["iters"] == i2["iters"]
+    assert np.linalg.norm(b - As @ x1) / np.linalg.norm(b) <= 1e-8 * (1 + 1e-6)
+    xo, oi = omx.solve_ir(As, b, np.zeros(n), 1e-8, "cg", 30, 1e-4, 10, 200000)
+    assert abs(i1["iters"] - oi["iters"]) <= max(1, i1["refinements"]), (i1["iters"], oi["iters"])
