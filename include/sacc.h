@@ -190,7 +190,11 @@ int sa_initial_guess(sa_seq *q, const sa_csr *A, const void *b_dev, void *x0_dev
  * inner_maxit iterations, and updates x += d (iters sums the inner iterations).
  * CG tunes its SpMV tile shape on the first solve of an operator shape (n, nnz, value
  * and vector types) by timing a few launches that change no solver state (cached for
- * the process; the environment variable SACC_CG_CHUNK = 5, 7 or 9 pins it).
+ * the process; the environment variable SACC_CG_CHUNK = 5, 7 or 9 pins it).  Mixed CG
+ * reads the column indices as 16-bit offsets from the row when every offset fits and
+ * 2 nnz bytes fit in the workspace region of the basis (n M words): packed once per
+ * solve into that region, so the next guess recomputes its basis (the same products in
+ * the same order: results as with the 32-bit indices; SACC_NO_COL16 turns it off).
  * Waits for the stream; fills info if non-NULL (iters, restarts, refinements,
  * relres0, relres, status, ms_solve).  Returns SA_OK, SA_NOTCONV or an error code. */
 int sa_solve(sa_seq *q, const sa_csr *A, const void *b_dev, void *x_dev, sa_info *info,

@@ -54,8 +54,8 @@ struct sa_seq {
   double *SX = nullptr, *partials = nullptr;
   void *kry = nullptr;               // Krylov vectors (double, or float for inner solves)
   float *r32 = nullptr, *d32 = nullptr;  // mixed: inner right-hand side and correction
-  short *col16 = nullptr;  // mixed CG: packed 16-bit column offsets of the current matrix
-  size_t col16_cap = 0;    // (allocated on first use, grown with the matrix's nonzeros)
+  size_t q1_bytes = 0;     // bytes of the workspace region of Q1 (the packed column
+                           // offsets of a mixed CG solve use it during the solve)
   long long *srht_rows = nullptr;
   unsigned long long *srht_signs = nullptr;  // SRHT sign words (one bit per row of x)
   unsigned short *sketch_bf16 = nullptr;     // SA_MIXED Gaussian sketch: BF16 normals (MFMA push)
@@ -662,6 +662,7 @@ int sa_init_sequence(const sa_config *cfg, void *dev_ws, size_t ws_bytes, void *
   q->X = q->ws + L.X;
   q->SX = (double *)(q->ws + L.SX);
   q->Q1 = q->ws + L.Q1;
+  q->q1_bytes = L.kry - L.Q1;
   q->kry = q->ws + L.kry;
   q->partials = (double *)(q->ws + L.partials);
   q->srht_rows = (long long *)(q->ws + L.rows);
@@ -867,22 +868,18 @@ static int inner_cap(const sa_config &c) {
 
 // Mixed CG: the inner solves' kernels read the matrix's column indices as 16-bit offsets
 // from the row (half the index bytes of the bandwidth-bound SpMV) when every offset fits;
-// packed once per solve, the fit reported with the first residual's poll.  The array is
-// allocated on first use and grown with the nonzeros; SACC_NO_COL16 turns it off.
+// packed once per solve into the workspace region of the basis Q1 (free from the guess's
+// last use of Q1 to the next basis, which the next guess then recomputes), the fit
+// reported with the first residual's poll.  Matrices with more than q1_bytes / 2
+// nonzeros keep the 32-bit indices; SACC_NO_COL16 turns the packing off.
 static int col16_prepare(sa_seq *q, const CsrView &v, hipStream_t st) {
-  const bool want = q->cfg.solver == SA_CG && v.nnz > 0 && !getenv("SACC_NO_COL16");
-  if (want && (size_t)v.nnz > q->col16_cap) {
-    if (q->col16) (void)hipFree(q->col16);
-    q->col16 = nullptr;
-    q->col16_cap = 0;
-    if (hipMalloc((void **)&q->col16, (size_t)v.nnz * sizeof(short)) != hipSuccess) {
-      q->col16 = nullptr;
-      return launch_set_int(&q->ctl->col16_ok, 0, st) == hipSuccess ? SA_OK : SA_EHIP;
-    }
-    q->col16_cap = (size_t)v.nnz;
-  }
+  const bool want = q->cfg.solver == SA_CG && v.nnz > 0 && (size_t)v.nnz * sizeof(short) <= q->q1_bytes &&
+                    !getenv("SACC_NO_COL16");
   HIP_TRY(launch_set_int(&q->ctl->col16_ok, want ? 1 : 0, st));
-  if (want) HIP_TRY(launch_col_rel16(v, q->col16, &q->ctl->col16_ok, st));
+  if (want) {
+    HIP_TRY(launch_col_rel16(v, (short *)q->Q1, &q->ctl->col16_ok, st));
+    q->basis_for = -1;  // Q1's space holds the offsets now
+  }
   return SA_OK;
 }
 
@@ -896,7 +893,7 @@ static int solve_mixed(sa_seq *q, const CsrView &v, const double *b, double *x, 
   for (int sweep = 0;; ++sweep) {
     HIP_TRY(launch_ir_resid(v, b, x, q->r32, q->partials, sweep, c.max_refine, q->ctl, st));
     SA_TRY(poll(q, q->ctl, st));
-    if (sweep == 0 && hs[7] == 1 && q->col16) vi.col16 = q->col16;
+    if (sweep == 0 && hs[7] == 1) vi.col16 = (const short *)q->Q1;
     const int outer = hs[0];
     if (outer < ST_RUN || outer > ST_ZERO_RHS) return SA_EHIP;
     if (outer != ST_RUN || *iters >= c.maxit) {
@@ -1030,7 +1027,6 @@ int sa_destroy_sequence(sa_seq *q) {
   if (q->ctl) (void)hipFree(q->ctl);
   if (q->ctl_in) (void)hipFree(q->ctl_in);
   if (q->hbuf) (void)hipHostFree(q->hbuf);
-  if (q->col16) (void)hipFree(q->col16);
   for (auto m : q->mir)
     if (m) (void)hipHostFree(m);
   for (int e = 0; e < 4; ++e)

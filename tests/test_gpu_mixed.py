@@ -213,12 +213,16 @@ def test_mixed_cg_packed_columns_bitwise(sacc, N):
         if off:
             os.environ["SACC_NO_COL16"] = "1"
         try:
-            seq = sacc.Sequence(p.n, 2, s=4, solver="cg", tol=1e-8, precision="mixed", inner_tol=1e-4, max_refine=10)
+            # M = 4: the basis region (4 n floats) holds the 2 nnz bytes of the offsets
+            seq = sacc.Sequence(p.n, 4, s=8, solver="cg", tol=1e-8, precision="mixed", inner_tol=1e-4, max_refine=10)
+            seq.profile_enable(True)
             xd, info = seq.solve(Ad, dev(b), dev(np.zeros(p.n)))
-            out.append((host(xd), info))
+            names = [r["name"] for r in seq.profile_read()]
+            out.append((host(xd), info, names))
         finally:
             os.environ.pop("SACC_NO_COL16", None)
-    (x1, i1), (x2, i2) = out
+    (x1, i1, n1), (x2, i2, n2) = out
+    assert any("i16" in nm for nm in n1) and not any("i16" in nm for nm in n2), (n1, n2)
     print_case("packed / full: iters", i1["iters"], i2["iters"], "sweeps", i1["refinements"], i2["refinements"])
     assert np.array_equal(x1, x2)
     for key in ("iters", "refinements", "relres", "relres0", "status"):
