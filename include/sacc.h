@@ -302,7 +302,11 @@ int sa_set_time(sa_seq *q, double t);
 typedef struct sa_batch sa_batch;
 
 /* seqs: nseq sequences created by sa_init_sequence (not owned; each must not be used
- * elsewhere while the batch steps).  Errors: SA_EINVAL, SA_ENOMEM, SA_EHIP. */
+ * elsewhere while the batch steps).  Creates the streams and host threads and, when every
+ * sequence is SA_MIXED or SA_MIXED_KRYLOV without a preconditioner, the segmented
+ * engine's device and pinned memory (descriptors, states, and one partial row of 34
+ * float64 per 1024 rows); steps allocate nothing.  Errors: SA_EINVAL, SA_ENOMEM,
+ * SA_EHIP. */
 int sa_batch_create(sa_seq *const *seqs, int nseq, int max_streams, int tune_warmup, sa_batch **out);
 int sa_batch_destroy(sa_batch *b);
 

@@ -1557,7 +1557,7 @@ struct sa_batch {
   long long steps = 0;
   int mode = SA_BATCH_AUTO;
   bool seg_ok = false;        // every sequence is mixed-precision without a preconditioner
-  SegEngine *seg = nullptr;   // created on first segmented step
+  SegEngine *seg = nullptr;   // the segmented engine (created with the batch when seg_ok)
   double seg_bytes = 0.0, seg_ms = 0.0;  // the last step's segmented solve (0 after a stream step)
 };
 
@@ -1612,15 +1612,11 @@ int batch_step_seg(sa_batch *b, const Plan &plan, const std::vector<std::vector<
   });
   for (int r : rc)
     if (r != SA_OK) return r;
-  if (!b->seg) {
-    std::vector<int64_t> ns(nseq);
-    int64_t tn = 0, tnnz = 0;
-    for (int i = 0; i < nseq; ++i) {
-      ns[i] = b->seqs[i]->cfg.n;
-      tn += A[i]->n;
-      tnnz += A[i]->nnz;
-    }
-    if (seg_engine_create(ns.data(), nseq, wave_tile_chunk(tn, tnnz), &b->seg) != 0) return SA_ENOMEM;
+  if (!b->seg) return SA_ESTATE;
+  int64_t tn = 0, tnnz = 0;
+  for (int i = 0; i < nseq; ++i) {
+    tn += A[i]->n;
+    tnnz += A[i]->nnz;
   }
   std::vector<SegDesc> desc(nseq);
   for (int i = 0; i < nseq; ++i) {
@@ -1650,7 +1646,9 @@ int batch_step_seg(sa_batch *b, const Plan &plan, const std::vector<std::vector<
   hipStream_t st = b->streams[0];
   std::vector<SegResult> res(nseq);
   const auto t0 = std::chrono::steady_clock::now();
-  if (seg_engine_solve(b->seg, desc.data(), graph, plan.over, st, res.data()) != hipSuccess) return SA_EHIP;
+  if (seg_engine_solve(b->seg, desc.data(), graph, plan.over, wave_tile_chunk(tn, tnnz), st, res.data()) !=
+      hipSuccess)
+    return SA_EHIP;
   for (int i = 0; i < nseq; ++i)
     if (res[i].state == ST_ZERO_RHS) HIP_TRY(hipMemsetAsync(x[i], 0, (size_t)desc[i].n * sizeof(double), st));
   HIP_TRY(hipStreamSynchronize(st));
@@ -1709,6 +1707,15 @@ int sa_batch_create(sa_seq *const *seqs, int nseq, int max_streams, int tune_war
   b->seg_ok = true;
   for (int i = 0; i < nseq; ++i)
     b->seg_ok = b->seg_ok && seqs[i]->mixed && seqs[i]->cfg.precond == SA_PRECOND_NONE;
+  if (b->seg_ok) {
+    std::vector<int64_t> ns(nseq);
+    for (int i = 0; i < nseq; ++i) ns[i] = seqs[i]->cfg.n;
+    if (seg_engine_create(ns.data(), nseq, &b->seg) != 0) {
+      for (auto &t : b->streams) (void)hipStreamDestroy(t);
+      delete b;
+      return SA_ENOMEM;
+    }
+  }
   b->tune_warm = tune_warmup;
   b->tune_next = 0;
   BatchPool &P = b->pool;

@@ -248,15 +248,15 @@ struct SegResult {
   double bytes;  // algorithmic bytes of the system's row work in the solve
 };
 struct SegEngine;
-// an engine for systems of sizes n[0..nseg); chunk: gathers per lane of its SpMV tiles
-// (5, 7 or 9).  Returns 0, or -1 when device or pinned memory is short.
-int seg_engine_create(const int64_t *n, int nseg, int chunk, SegEngine **out);
+// an engine for systems of sizes n[0..nseg) (all its device and pinned memory).  Returns
+// 0, or -1 when device or pinned memory is short.
+int seg_engine_create(const int64_t *n, int nseg, SegEngine **out);
 void seg_engine_destroy(SegEngine *e);
 // Solves every system (desc[i].n must equal the engine's n[i]) on stream st, eager
 // launches or replays of one captured hipGraph per chunk of steps; synchronous.
 // oversub: the data kernel's grid in multiples of the blocks the device holds at once
-// (1..64; 0: the default 8).
-hipError_t seg_engine_solve(SegEngine *e, const SegDesc *desc, bool graph, int oversub, hipStream_t st,
+// (1..64; 0: the default 8); chunk: gathers per lane of its SpMV tiles (5, 7 or 9).
+hipError_t seg_engine_solve(SegEngine *e, const SegDesc *desc, bool graph, int oversub, int chunk, hipStream_t st,
                             SegResult *res);
 int seg_rows_per_block();
 

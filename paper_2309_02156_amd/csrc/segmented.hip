@@ -763,13 +763,13 @@ hipError_t seg_chunk(SegEngine *e, bool graph, hipStream_t st) {
 
 int seg_rows_per_block() { return SG_ROWS; }
 
-int seg_engine_create(const int64_t *n, int nseg, int chunk, SegEngine **out) {
+int seg_engine_create(const int64_t *n, int nseg, SegEngine **out) {
   *out = nullptr;
   if (nseg < 1) return -1;
   SegEngine *e = new (std::nothrow) SegEngine();
   if (!e) return -1;
   e->nseg = nseg;
-  e->chunk = chunk == 7 || chunk == 9 ? chunk : 5;
+  e->chunk = 5;
   e->n.assign(n, n + nseg);
   std::vector<int> blkseg;
   for (int s = 0; s < nseg; ++s) {
@@ -824,9 +824,20 @@ static long long seg_step_bound(const SegDesc &d) {
   return 2 * sw + 6 * it + 16;
 }
 
-hipError_t seg_engine_solve(SegEngine *e, const SegDesc *desc, bool graph, int oversub, hipStream_t st,
+hipError_t seg_engine_solve(SegEngine *e, const SegDesc *desc, bool graph, int oversub, int chunk, hipStream_t st,
                             SegResult *res) {
   const int nseg = e->nseg;
+  // the SpMV tile shape of this solve's matrices (a change re-captures the graph)
+  {
+    const int c = chunk == 7 || chunk == 9 ? chunk : 5;
+    if (c != e->chunk && e->gexec) {
+      (void)hipGraphExecDestroy(e->gexec);
+      (void)hipGraphDestroy(e->graph);
+      e->gexec = nullptr;
+      e->graph = nullptr;
+    }
+    e->chunk = c;
+  }
   // the data kernel's grid multiple: the caller's (the batch tuner's), 8 by default;
   // SACC_SEG_OVERSUB (1..64) pins it (reproducible measurements)
   {
