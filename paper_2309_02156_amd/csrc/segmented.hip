@@ -3,14 +3,14 @@
 // GMRES(m) inner solves, the same method as one sequence's mixed-mode solve, for every
 // system of a batch in lockstep.
 //
-// The systems are segments of one launch.  Each segment owns a contiguous range of
-// blocks (1024 rows per block: four waves of four 64-row tiles) and a state record in
-// device memory that holds its phase and scalars.  A step of the engine is two
-// launches over all segments: the data kernel does the row work of every segment's
-// current phase (a masked-out segment, finished or in a phase without row work,
-// returns at once) and leaves one partial row per block; the close kernel (one block
-// per segment) reduces those rows in a fixed order and runs the segment's scalar
-// logic, which picks its next phase.  No cross-block atomics or device-scope fences:
+// The systems are segments of one launch.  Each segment owns a contiguous range of work
+// items (1024 rows each: four waves of four 64-row tiles) and a state record in device
+// memory that holds its phase and scalars.  A step of the engine is two launches over
+// all segments: the data kernel (a resident grid striding over the items) does the row
+// work of every item's segment in its current phase (items of finished segments are
+// skipped) and leaves one partial row per item; the close kernel (one block per
+// segment) reduces those rows in a fixed order and runs the segment's scalar logic,
+// which picks its next phase.  No cross-block atomics or device-scope fences:
 // the launch boundary orders the partial rows, as in the single-sequence kernels.  The
 // host enqueues steps in chunks (a captured hipGraph of the chunk, or eager launches)
 // and stops once every segment reports its end through a word in pinned host memory.
@@ -817,8 +817,8 @@ void seg_engine_destroy(SegEngine *e) {
 }
 
 // Upper bound on engine steps for a segment: every step advances it by one phase; a
-// sweep takes RES and XUPD, every inner iteration at most three phases (A1, A2, A3 or
-// CGQ, CGU) and every GMRES cycle (at least one iteration) three more (V0, UPD, GRES).
+// sweep takes RES and XUPD, every inner iteration two phases (F, G or CGQ, CGU) and every
+// GMRES cycle (at least one iteration) two more (UPD, GRES).
 static long long seg_step_bound(const SegDesc &d) {
   const long long it = d.maxit, sw = (long long)d.max_refine + 1;
   return 2 * sw + 6 * it + 16;
