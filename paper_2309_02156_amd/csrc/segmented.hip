@@ -631,7 +631,9 @@ __device__ inline void seg_coefs(SegState &st) {
 // on a copy of the state in LDS (one thread; the coefficients of the next F step by
 // the block), copied back by the whole block.
 constexpr int SC_TPB = 1024;
-static_assert(sizeof(SegState) % sizeof(double) == 0, "state copied as 8-byte words");
+static_assert(sizeof(SegState) % sizeof(double) == 0 && offsetof(SegState, Hraw) % sizeof(double) == 0 &&
+                  offsetof(SegState, H) > offsetof(SegState, Hraw),
+              "state copied as 8-byte words, the Hessenberg arrays last");
 
 __global__ __launch_bounds__(SC_TPB) void k_seg_close(const SegDesc *__restrict__ D, SegState *__restrict__ S,
                                                      int *done) {
@@ -642,8 +644,11 @@ __global__ __launch_bounds__(SC_TPB) void k_seg_close(const SegDesc *__restrict_
   SegState &gs = S[s];
   const int phase = gs.phase;
   if (phase == SP_DONE) return;
+  // the Hessenberg arrays (most of the state) are read and written only by a G close
   constexpr int NW8 = (int)(sizeof(SegState) / sizeof(double));
-  for (int k = threadIdx.x; k < NW8; k += SC_TPB) ((double *)&ls)[k] = ((const double *)&gs)[k];
+  constexpr int NSMALL = (int)(offsetof(SegState, Hraw) / sizeof(double));
+  const int ncopy = phase == SP_G ? NW8 : NSMALL;
+  for (int k = threadIdx.x; k < ncopy; k += SC_TPB) ((double *)&ls)[k] = ((const double *)&gs)[k];
   const SegDesc &d = D[s];
   const int kc = phase_cols(phase, gs.j);
   if (kc > 0) final_sum(d.part, d.nblk, SG_PW, kc, tot, scratch);
@@ -654,7 +659,7 @@ __global__ __launch_bounds__(SC_TPB) void k_seg_close(const SegDesc *__restrict_
     seg_coefs(ls);
     __syncthreads();
   }
-  for (int k = threadIdx.x; k < NW8; k += SC_TPB) ((double *)&gs)[k] = ((const double *)&ls)[k];
+  for (int k = threadIdx.x; k < ncopy; k += SC_TPB) ((double *)&gs)[k] = ((const double *)&ls)[k];
 }
 
 __global__ void k_seg_init(SegState *S, int nseg) {
