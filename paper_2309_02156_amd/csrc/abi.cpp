@@ -1595,20 +1595,24 @@ int batch_step_seg(sa_batch *b, const Plan &plan, const std::vector<std::vector<
                    const void *const *rhs, void *const *x, std::vector<sa_info> &inf, bool graph) {
   const int nseq = (int)b->seqs.size();
   std::vector<int> rc(plan.streams, SA_OK);
+  // every guess of a stream's list enqueued, one wait per stream, then their records
   pool_run(b, plan.streams, [&](int s) {
     hipStream_t st = b->streams[s];
-    for (int i : lists[s]) {
+    std::vector<int> cnts(lists[s].size(), 0);
+    int r = SA_OK;
+    for (size_t k = 0; k < lists[s].size() && r == SA_OK; ++k) {
+      const int i = lists[s][k];
       memset(&inf[i], 0, sizeof(sa_info));
+      r = b->seqs[i]->alive ? guess_enqueue(b->seqs[i], A[i], rhs[i], x[i], true, st, &cnts[k]) : SA_ESTATE;
+    }
+    if (r == SA_OK) r = hipStreamSynchronize(st) == hipSuccess ? SA_OK : SA_EHIP;
+    for (size_t k = 0; k < lists[s].size() && r == SA_OK; ++k) {
       sa_info g;
       memset(&g, 0, sizeof(g));
-      int r = sa_initial_guess(b->seqs[i], A[i], rhs[i], x[i], &g, st);
-      if (r == SA_OK) r = hipStreamSynchronize(st) == hipSuccess ? SA_OK : SA_EHIP;
-      guess_into(inf[i], g);
-      if (r != SA_OK) {
-        rc[s] = r;
-        return;
-      }
+      r = guess_info(b->seqs[lists[s][k]], cnts[k], &g);
+      guess_into(inf[lists[s][k]], g);
     }
+    if (r != SA_OK) rc[s] = r;
   });
   for (int r : rc)
     if (r != SA_OK) return r;
@@ -1669,14 +1673,10 @@ int batch_step_seg(sa_batch *b, const Plan &plan, const std::vector<std::vector<
   }
   pool_run(b, plan.streams, [&](int s) {
     hipStream_t sp = b->streams[s];
-    for (int i : lists[s]) {
-      int r = sa_push_solution(b->seqs[i], x[i], sp);
-      if (r == SA_OK) r = hipStreamSynchronize(sp) == hipSuccess ? SA_OK : SA_EHIP;
-      if (r != SA_OK) {
-        rc[s] = r;
-        return;
-      }
-    }
+    int r = SA_OK;
+    for (size_t k = 0; k < lists[s].size() && r == SA_OK; ++k) r = sa_push_solution(b->seqs[lists[s][k]], x[lists[s][k]], sp);
+    if (r == SA_OK) r = hipStreamSynchronize(sp) == hipSuccess ? SA_OK : SA_EHIP;
+    if (r != SA_OK) rc[s] = r;
   });
   for (int r : rc)
     if (r != SA_OK) return r;
