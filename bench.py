@@ -426,6 +426,8 @@ def learned_cmp(sacc, torch, np, n_train, n_eval, epochs=60, batch=32, n_hist=8)
         step(seq, i, x)
         targets.append(seq.last_target())
         step(plain, i, xp)
+        if (i + 1) % 500 == 0:
+            log(f"learned: {i + 1} of {n_train} training steps run")
     F = np.array([np.concatenate(targets[i - n_hist:i] + [np.array([np.sin(p.t(i)), np.cos(p.t(i))])])
                   for i in range(n_hist + M, n_train)])
     T = np.array(targets[n_hist + M:n_train])
@@ -585,6 +587,8 @@ def main():
     ap.add_argument("--learned-train", type=int, default=200)
     ap.add_argument("--learned-eval", type=int, default=100)
     ap.add_argument("--no-learned", action="store_true")
+    ap.add_argument("--only-learned", action="store_true",
+                    help="run only the learned-predictor comparator (window set by --learned-train / --learned-eval)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py: this benchmark runs on one GPU; --gpus {args.gpus} is not supported "
@@ -607,6 +611,9 @@ def main():
         if args.batch_which in ("both", "small"):
             out["batch64_small"] = batch_cmp(sacc, torch, np, args.batch_warmup, args.batch_steps, lo=32, hi=128, **kw)
         print(json.dumps(out), flush=True)
+        return
+    if args.only_learned:
+        print(json.dumps({"learned": learned_cmp(sacc, torch, np, args.learned_train, args.learned_eval)}), flush=True)
         return
     if args.only_advdiff:
         if args.copy_calibration:
