@@ -831,7 +831,9 @@ __global__ __launch_bounds__(GRAM_TPB) void k_spmm_gram(const int *rowptr, const
       }
     }
     wave_lds_sync();
-    // the Gram operands of the tile's rows (independent of the SpMM): requested first
+    // the Gram operands of the tile's rows and the row's b (independent of the SpMM):
+    // requested first, so that their trips overlap the gathers'
+    const double bv = b[valid ? row : n - 1];
     const int i16 = lane % 16, kq = lane / 16;
     TX aqr[GRAM_ROWS / 4][NA];
 #pragma unroll
@@ -891,7 +893,7 @@ __global__ __launch_bounds__(GRAM_TPB) void k_spmm_gram(const int *rowptr, const
 #pragma unroll
     for (int u = 0; u < (NWB * 16 - KB) / 4; ++u) Wl[rr * LDW + KB + q * ((NWB * 16 - KB) / 4) + u] = 0.0;
     wave_lds_sync();
-    if (q == 0) Wl[rr * LDW + k] = valid ? b[row] : 0.0;
+    if (q == 0) Wl[rr * LDW + k] = valid ? bv : 0.0;
     wave_lds_sync();
 #pragma unroll
     for (int s4 = 0; s4 < GRAM_ROWS / 4; ++s4) {
