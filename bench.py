@@ -572,8 +572,8 @@ def main():
     ap.add_argument("--only-headline", action="store_true", help="the headline workload only (no other workloads)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="run 3 plain 256 MiB device copies first (reference for HBM byte counters)")
-    ap.add_argument("--batch-warmup", type=int, default=13,
-                    help="batch steps after the histories fill, before timing (the plan tuner times 13 candidates)")
+    ap.add_argument("--batch-warmup", type=int, default=15,
+                    help="batch steps after the histories fill, before timing (the plan tuner times 15 candidates)")
     ap.add_argument("--batch-steps", type=int, default=4)
     ap.add_argument("--batch-mode", choices=["auto", "streams", "segmented"], default="auto",
                     help="plan of the timed batch steps (auto: tuned)")

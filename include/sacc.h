@@ -318,7 +318,8 @@ int sa_batch_step(sa_batch *b, const sa_csr *const *A, const void *const *rhs, v
                   sa_info *info);
 
 /* The plan in use, whether tuning has finished (always, in a fixed mode) and whether the
- * solves run in the segmented engine. */
+ * solves run in the segmented engine: *segmented = 0, or the rows of the engine's work
+ * items (512 or 1024, picked by the tuner; 1024 in the fixed segmented modes). */
 int sa_batch_plan(const sa_batch *b, int *streams, int *poll, int *tuned, int *segmented);
 
 /* Execution of a batch's solves.

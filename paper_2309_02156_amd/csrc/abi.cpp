@@ -1515,15 +1515,18 @@ namespace batchplan {
 // streams: host threads / streams in use; poll: Krylov steps enqueued ahead (stream
 // plans); seg: the solves run in the segmented engine (the streams then carry the
 // guesses and pushes), its data kernel's grid `over` times the resident blocks
+// streams and poll: the per-sequence plan; seg: the segmented engine, over: its data
+// grid in multiples of the resident blocks, rows: its work-item rows (512 or 1024)
 struct Plan {
-  int streams, poll, seg, over;
+  int streams, poll, seg, over, rows;
 };
 
 // candidates the autotuner times, one step each (after the history is full); the
 // segmented ones only where every sequence can use the engine
-const Plan kCandidates[] = {{1, 8, 0, 0}, {2, 8, 0, 0},  {4, 8, 0, 0}, {4, 4, 0, 0},  {4, 16, 0, 0},
-                            {4, 30, 0, 0}, {2, 16, 0, 0}, {8, 8, 0, 0}, {8, 16, 0, 0}, {4, 8, 1, 8},
-                            {8, 8, 1, 4},  {8, 8, 1, 8},  {8, 8, 1, 16}};
+const Plan kCandidates[] = {{1, 8, 0, 0, 0},     {2, 8, 0, 0, 0},     {4, 8, 0, 0, 0},    {4, 4, 0, 0, 0},
+                            {4, 16, 0, 0, 0},    {4, 30, 0, 0, 0},    {2, 16, 0, 0, 0},   {8, 8, 0, 0, 0},
+                            {8, 16, 0, 0, 0},    {4, 8, 1, 8, 1024},  {8, 8, 1, 4, 1024}, {8, 8, 1, 8, 1024},
+                            {8, 8, 1, 16, 1024}, {8, 8, 1, 4, 512},   {8, 8, 1, 8, 512}};
 constexpr int kNumCandidates = sizeof(kCandidates) / sizeof(kCandidates[0]);
 
 }  // namespace batchplan
@@ -1549,11 +1552,11 @@ struct sa_batch {
   std::vector<hipStream_t> streams;
   BatchPool pool;
   std::vector<double> cost;  // estimated cost of a sequence's step (nnz x (iterations + 10))
-  Plan plan{4, 8, 0, 0};
+  Plan plan{4, 8, 0, 0, 0};
   int tune_next = 0;        // next candidate to time; kNumCandidates when tuned
   int tune_warm = 0;        // steps before timing starts (history filling)
   double tune_best = 1e300;
-  Plan tune_best_plan{4, 8, 0, 0};
+  Plan tune_best_plan{4, 8, 0, 0, 0};
   long long steps = 0;
   int mode = SA_BATCH_AUTO;
   bool seg_ok = false;        // every sequence is mixed-precision without a preconditioner
@@ -1650,7 +1653,7 @@ int batch_step_seg(sa_batch *b, const Plan &plan, const std::vector<std::vector<
   hipStream_t st = b->streams[0];
   std::vector<SegResult> res(nseq);
   const auto t0 = std::chrono::steady_clock::now();
-  if (seg_engine_solve(b->seg, desc.data(), graph, plan.over, wave_tile_chunk(tn, tnnz), st, res.data()) !=
+  if (seg_engine_solve(b->seg, desc.data(), graph, plan.over, wave_tile_chunk(tn, tnnz), plan.rows, st, res.data()) !=
       hipSuccess)
     return SA_EHIP;
   for (int i = 0; i < nseq; ++i)
@@ -1703,7 +1706,7 @@ int sa_batch_create(sa_seq *const *seqs, int nseq, int max_streams, int tune_war
       delete b;
       return SA_EHIP;
     }
-  b->plan = Plan{max_streams, 8, 0, 0};
+  b->plan = Plan{max_streams, 8, 0, 0, 0};
   b->seg_ok = true;
   for (int i = 0; i < nseq; ++i)
     b->seg_ok = b->seg_ok && seqs[i]->mixed && seqs[i]->cfg.precond == SA_PRECOND_NONE;
@@ -1760,7 +1763,7 @@ int sa_batch_plan(const sa_batch *b, int *streams, int *poll, int *tuned, int *s
   *streams = b->plan.streams;
   *poll = b->plan.poll;
   *tuned = (b->mode != SA_BATCH_AUTO || b->tune_next >= kNumCandidates) ? 1 : 0;
-  *segmented = b->plan.seg;
+  *segmented = b->plan.seg ? (b->plan.rows == 512 ? 512 : 1024) : 0;
   return SA_OK;
 }
 
@@ -1775,7 +1778,10 @@ int sa_batch_set_mode(sa_batch *b, int mode) {
   if (!b || mode < SA_BATCH_AUTO || mode > SA_BATCH_SEGMENTED_EAGER) return SA_EINVAL;
   if ((mode == SA_BATCH_SEGMENTED || mode == SA_BATCH_SEGMENTED_EAGER) && !b->seg_ok) return SA_EINVAL;
   b->mode = mode;
-  if (mode != SA_BATCH_AUTO) b->plan = Plan{(int)b->streams.size(), 8, mode == SA_BATCH_STREAMS ? 0 : 1, 8};
+  if (mode != SA_BATCH_AUTO) {
+    const bool sg = mode != SA_BATCH_STREAMS;
+    b->plan = Plan{(int)b->streams.size(), 8, sg ? 1 : 0, sg ? 8 : 0, sg ? 1024 : 0};
+  }
   return SA_OK;
 }
 

@@ -255,9 +255,9 @@ void seg_engine_destroy(SegEngine *e);
 // Solves every system (desc[i].n must equal the engine's n[i]) on stream st, eager
 // launches or replays of one captured hipGraph per chunk of steps; synchronous.
 // oversub: the data kernel's grid in multiples of the blocks the device holds at once
-// (1..64; 0: the default 8); chunk: gathers per lane of its SpMV tiles (5, 7 or 9).
-hipError_t seg_engine_solve(SegEngine *e, const SegDesc *desc, bool graph, int oversub, int chunk, hipStream_t st,
-                            SegResult *res);
-int seg_rows_per_block();
+// (1..64; 0: the default 8); chunk: gathers per lane of its SpMV tiles (5, 7 or 9);
+// rows: rows per work item, 512 or 1024 (any other value: 1024).
+hipError_t seg_engine_solve(SegEngine *e, const SegDesc *desc, bool graph, int oversub, int chunk, int rows,
+                            hipStream_t st, SegResult *res);
 
 }  // namespace sacc

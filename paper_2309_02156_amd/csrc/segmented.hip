@@ -52,9 +52,12 @@ namespace {
 
 constexpr int SG_TPB = 256;                    // threads per block
 constexpr int SG_NW = SG_TPB / WAVE;           // waves per block
-constexpr int SG_TW = 4;                       // 64-row tiles per wave
-constexpr int SG_ROWS = SG_NW * SG_TW * WAVE;  // rows per block
-constexpr int SG_EW = SG_ROWS / SG_TPB;        // rows per thread in the element-wise phases
+// A work item is TW 64-row tiles per wave: SG_NW TW 64 rows, TW rows per thread in the
+// element-wise phases.  TW = 4 (1024 rows) or 2 (512 rows), chosen per batch: larger
+// items leave fewer partial rows, smaller ones shorten a block's chain of tiles, which
+// sets the step time when every system is small.
+constexpr int SG_TW_MAX = 4;
+__host__ __device__ constexpr int item_rows(int tw) { return SG_NW * tw * WAVE; }
 constexpr int SG_R = MAXR;                     // longest GMRES cycle
 constexpr int SG_PW = SG_R + 2;                // doubles per partial row
 
@@ -147,9 +150,9 @@ __device__ inline void col_sums_store(double acc, int kc, double *red, double *o
   }
 }
 
-// The row work of one work item (a segment's block of SG_ROWS rows) in the segment's
-// current phase; leaves the item's partial row.
-template <int C>
+// The row work of one work item (a segment's block of item_rows(TW) rows) in the
+// segment's current phase; leaves the item's partial row.
+template <int C, int TW>
 __device__ inline void seg_item(const SegDesc &d, const SegState &st, int phase, int lb, char *lds, double *red,
                                 double *red1, double *coef, double *coef2) {
   int(*lcol)[WT_CAP] = (int(*)[WT_CAP])lds;
@@ -159,9 +162,9 @@ __device__ inline void seg_item(const SegDesc &d, const SegState &st, int phase,
   const int tid = threadIdx.x, wid = tid / WAVE;
   const int64_t n = d.n;
   const int64_t T = (n + WAVE - 1) / WAVE;
-  const int64_t t0 = (int64_t)lb * (SG_NW * SG_TW);
-  const int64_t tend = t0 + SG_NW * SG_TW < T ? t0 + SG_NW * SG_TW : T;
-  const int64_t row0 = (int64_t)lb * SG_ROWS;
+  const int64_t t0 = (int64_t)lb * (SG_NW * TW);
+  const int64_t tend = t0 + SG_NW * TW < T ? t0 + SG_NW * TW : T;
+  const int64_t row0 = (int64_t)lb * item_rows(TW);
   double *out = d.part + (size_t)lb * SG_PW;
   const int gm = d.solver == SA_GMRES;
   const int m = d.m;
@@ -194,7 +197,7 @@ __device__ inline void seg_item(const SegDesc &d, const SegState &st, int phase,
       double *__restrict__ x = d.x;
       const float *__restrict__ dd = d.d32;
 #pragma unroll
-      for (int k = 0; k < SG_EW; ++k) {
+      for (int k = 0; k < TW; ++k) {
         const int64_t i = row0 + k * SG_TPB + tid;
         if (i < n) x[i] = x[i] + (double)dd[i];
       }
@@ -233,7 +236,7 @@ __device__ inline void seg_item(const SegDesc &d, const SegState &st, int phase,
       float *__restrict__ dd = d.d32;
       double acc[1] = {0.0};
 #pragma unroll
-      for (int k = 0; k < SG_EW; ++k) {
+      for (int k = 0; k < TW; ++k) {
         const int64_t i = row0 + k * SG_TPB + tid;
         if (i < n) {
           const float dn = (float)__dadd_rn((double)dd[i], __dmul_rn(alpha, (double)P[i]));
@@ -348,7 +351,7 @@ __device__ inline void seg_item(const SegDesc &d, const SegState &st, int phase,
       with_nch((jend + 7) / 8, [&](auto kk) {
         constexpr int NV = decltype(kk)::value * 8;  // columns l < jend
         if constexpr (NV > 0) {
-          for (int k = 0; k < SG_EW; ++k) {
+          for (int k = 0; k < TW; ++k) {
             const int64_t i = row0 + k * SG_TPB + tid;
             if (i < n) {
               float vv[NV];
@@ -391,7 +394,7 @@ __device__ inline void seg_item(const SegDesc &d, const SegState &st, int phase,
 // items belong to a segment still running, so finished segments cost no memory trips.
 constexpr int SG_MAXIT = 64;  // work items per block at most (the grid is sized for it)
 
-template <int C>
+template <int C, int TW>
 __global__ __launch_bounds__(SG_TPB, 4) void k_seg_data(const SegDesc *__restrict__ D, const SegState *__restrict__ S,
                                                     const int *__restrict__ blkseg, const int *__restrict__ blk0,
                                                     int nitems) {
@@ -416,7 +419,7 @@ __global__ __launch_bounds__(SG_TPB, 4) void k_seg_data(const SegDesc *__restric
     if (phase == SP_DONE) continue;
     const int s = iseg[k];
     const SegDesc d = D[s];
-    seg_item<C>(d, S[s], phase, (int)blockIdx.x + k * G - blk0[s], lds, red, red1, coef, coef2);
+    seg_item<C, TW>(d, S[s], phase, (int)blockIdx.x + k * G - blk0[s], lds, red, red1, coef, coef2);
     __syncthreads();  // LDS reuse by the next item
   }
 }
@@ -675,7 +678,7 @@ __global__ void k_seg_init(SegState *S, int nseg) {
   st.ith = st.rho = st.alpha = st.beta = st.hn = 0.0;
 }
 
-template <int C>
+template <int C, int TW>
 hipError_t seg_step_launch(SegEngine *e, hipStream_t st);
 
 }  // namespace
@@ -683,6 +686,7 @@ hipError_t seg_step_launch(SegEngine *e, hipStream_t st);
 // ---------------------------------------------------------------------------- host engine
 struct SegEngine {
   int nseg = 0, nblk = 0, chunk = 5;
+  int tw = SG_TW_MAX;         // tiles per wave of a work item (the items below are for it)
   int oversub = 8;            // data-kernel grid: this many times the resident blocks
   std::vector<int64_t> n;
   std::vector<int> blk0h;
@@ -702,28 +706,50 @@ struct SegEngine {
 
 namespace {
 
-template <int C>
+template <int C, int TW>
 hipError_t seg_step_launch(SegEngine *e, hipStream_t st) {
   static int resident = 0;
-  int grid = resident_blocks((const void *)k_seg_data<C>, SG_TPB, resident) * e->oversub;
+  int grid = resident_blocks((const void *)k_seg_data<C, TW>, SG_TPB, resident) * e->oversub;
   if (grid < 8) grid = 8;
   grid = grid / 8 * 8;
   const int need = (e->nblk + SG_MAXIT - 1) / SG_MAXIT;
   if (grid < need) grid = need;
   if (grid > e->nblk) grid = e->nblk;
-  hipLaunchKernelGGL(HIP_KERNEL_NAME(k_seg_data<C>), dim3(grid), dim3(SG_TPB), 0, st, e->ddesc,
+  hipLaunchKernelGGL(HIP_KERNEL_NAME(k_seg_data<C, TW>), dim3(grid), dim3(SG_TPB), 0, st, e->ddesc,
                      (const SegState *)e->dstate, (const int *)e->dblkseg, (const int *)e->dblk0, e->nblk);
   hipLaunchKernelGGL(k_seg_close, dim3(e->nseg), dim3(SC_TPB), 0, st, (const SegDesc *)e->ddesc, e->dstate,
                      e->done_dev);
   return hipGetLastError();
 }
 
-hipError_t seg_step(SegEngine *e, hipStream_t st) {
+template <int TW>
+hipError_t seg_step_tw(SegEngine *e, hipStream_t st) {
   switch (e->chunk) {
-    case 7: return seg_step_launch<7>(e, st);
-    case 9: return seg_step_launch<9>(e, st);
-    default: return seg_step_launch<5>(e, st);
+    case 7: return seg_step_launch<7, TW>(e, st);
+    case 9: return seg_step_launch<9, TW>(e, st);
+    default: return seg_step_launch<5, TW>(e, st);
   }
+}
+
+hipError_t seg_step(SegEngine *e, hipStream_t st) {
+  return e->tw == 2 ? seg_step_tw<2>(e, st) : seg_step_tw<SG_TW_MAX>(e, st);
+}
+
+// the item tables (segment of each item, first item of each segment) for e->tw; the
+// device arrays are sized for the smallest items
+hipError_t seg_items_build(SegEngine *e) {
+  std::vector<int> blkseg;
+  e->blk0h.clear();
+  const int rows = item_rows(e->tw);
+  for (int s = 0; s < e->nseg; ++s) {
+    const int nb = (int)((e->n[s] + rows - 1) / rows);
+    e->blk0h.push_back((int)blkseg.size());
+    for (int k = 0; k < (nb > 0 ? nb : 1); ++k) blkseg.push_back(s);
+  }
+  e->nblk = (int)blkseg.size();
+  hipError_t r = hipMemcpy(e->dblkseg, blkseg.data(), e->nblk * sizeof(int), hipMemcpyHostToDevice);
+  if (r == hipSuccess) r = hipMemcpy(e->dblk0, e->blk0h.data(), e->nseg * sizeof(int), hipMemcpyHostToDevice);
+  return r;
 }
 
 constexpr int SG_CHUNK = 16;  // engine steps per chunk (one graph launch)
@@ -766,8 +792,6 @@ hipError_t seg_chunk(SegEngine *e, bool graph, hipStream_t st) {
 
 }  // namespace
 
-int seg_rows_per_block() { return SG_ROWS; }
-
 int seg_engine_create(const int64_t *n, int nseg, SegEngine **out) {
   *out = nullptr;
   if (nseg < 1) return -1;
@@ -775,27 +799,27 @@ int seg_engine_create(const int64_t *n, int nseg, SegEngine **out) {
   if (!e) return -1;
   e->nseg = nseg;
   e->chunk = 5;
+  e->tw = SG_TW_MAX;
   e->n.assign(n, n + nseg);
-  std::vector<int> blkseg;
-  for (int s = 0; s < nseg; ++s) {
-    const int nb = (int)((n[s] + SG_ROWS - 1) / SG_ROWS);
-    e->blk0h.push_back((int)blkseg.size());
-    for (int k = 0; k < (nb > 0 ? nb : 1); ++k) blkseg.push_back(s);
+  int64_t maxitems = 0;  // items with the smallest work items
+  for (int s = 0; s < nseg; ++s) maxitems += std::max<int64_t>(1, (n[s] + item_rows(2) - 1) / item_rows(2));
+  if (maxitems > (int64_t)1 << 30) {
+    delete e;
+    return -1;
   }
-  e->nblk = (int)blkseg.size();
+  const int mi = (int)maxitems;
   bool ok = hipMalloc((void **)&e->ddesc, nseg * sizeof(SegDesc)) == hipSuccess &&
             hipHostMalloc((void **)&e->hdesc, nseg * sizeof(SegDesc), hipHostMallocDefault) == hipSuccess &&
             hipMalloc((void **)&e->dstate, nseg * sizeof(SegState)) == hipSuccess &&
             hipHostMalloc((void **)&e->hsum, nseg * SG_SUMMARY, hipHostMallocDefault) == hipSuccess &&
-            hipMalloc((void **)&e->dblkseg, e->nblk * sizeof(int)) == hipSuccess &&
+            hipMalloc((void **)&e->dblkseg, mi * sizeof(int)) == hipSuccess &&
             hipMalloc((void **)&e->dblk0, nseg * sizeof(int)) == hipSuccess &&
-            hipMalloc((void **)&e->dpart, (size_t)e->nblk * SG_PW * sizeof(double)) == hipSuccess &&
+            hipMalloc((void **)&e->dpart, (size_t)mi * SG_PW * sizeof(double)) == hipSuccess &&
             hipHostMalloc((void **)&e->done, nseg * sizeof(int), hipHostMallocDefault) == hipSuccess &&
             hipHostGetDevicePointer((void **)&e->done_dev, e->done, 0) == hipSuccess &&
             hipEventCreateWithFlags(&e->ev[0], hipEventDisableTiming) == hipSuccess &&
             hipEventCreateWithFlags(&e->ev[1], hipEventDisableTiming) == hipSuccess;
-  ok = ok && hipMemcpy(e->dblkseg, blkseg.data(), e->nblk * sizeof(int), hipMemcpyHostToDevice) == hipSuccess &&
-       hipMemcpy(e->dblk0, e->blk0h.data(), nseg * sizeof(int), hipMemcpyHostToDevice) == hipSuccess;
+  ok = ok && seg_items_build(e) == hipSuccess;
   if (!ok) {
     seg_engine_destroy(e);
     return -1;
@@ -829,9 +853,29 @@ static long long seg_step_bound(const SegDesc &d) {
   return 2 * sw + 6 * it + 16;
 }
 
-hipError_t seg_engine_solve(SegEngine *e, const SegDesc *desc, bool graph, int oversub, int chunk, hipStream_t st,
-                            SegResult *res) {
+hipError_t seg_engine_solve(SegEngine *e, const SegDesc *desc, bool graph, int oversub, int chunk, int rows,
+                            hipStream_t st, SegResult *res) {
   const int nseg = e->nseg;
+  // work-item size: 512 or 1024 rows (anything else: 1024), pinned by SACC_SEG_ROWS when
+  // that is set to one of them; a change rebuilds the item tables and re-captures the graph
+  {
+    const char *ev = getenv("SACC_SEG_ROWS");
+    const int v = ev ? atoi(ev) : 0;
+    if (v == item_rows(2) || v == item_rows(SG_TW_MAX)) rows = v;
+    const int tw = rows == item_rows(2) ? 2 : SG_TW_MAX;
+    if (tw != e->tw) {
+      if (e->gexec) {
+        (void)hipGraphExecDestroy(e->gexec);
+        (void)hipGraphDestroy(e->graph);
+        e->gexec = nullptr;
+        e->graph = nullptr;
+      }
+      hipError_t r = hipStreamSynchronize(st);  // no step of the previous layout still queued
+      e->tw = tw;
+      if (r == hipSuccess) r = seg_items_build(e);
+      if (r != hipSuccess) return r;
+    }
+  }
   // the SpMV tile shape of this solve's matrices (a change re-captures the graph)
   {
     const int c = chunk == 7 || chunk == 9 ? chunk : 5;
@@ -861,7 +905,7 @@ hipError_t seg_engine_solve(SegEngine *e, const SegDesc *desc, bool graph, int o
   for (int s = 0; s < nseg; ++s) {
     e->hdesc[s] = desc[s];
     e->hdesc[s].part = e->dpart + (size_t)e->blk0h[s] * SG_PW;
-    e->hdesc[s].nblk = (int)((e->n[s] + SG_ROWS - 1) / SG_ROWS);
+    e->hdesc[s].nblk = (int)((e->n[s] + item_rows(e->tw) - 1) / item_rows(e->tw));
     e->done[s] = 0;
     bound = std::max(bound, seg_step_bound(desc[s]));
   }

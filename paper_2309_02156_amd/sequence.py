@@ -370,4 +370,5 @@ class Batch:
         s, p, t, g = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32()
         nv.check(nv.lib().sa_batch_plan(self._h, ctypes.byref(s), ctypes.byref(p), ctypes.byref(t), ctypes.byref(g)),
                  "sa_batch_plan")
-        return dict(streams=s.value, poll=p.value, tuned=bool(t.value), segmented=bool(g.value))
+        return dict(streams=s.value, poll=p.value, tuned=bool(t.value), segmented=bool(g.value),
+                    item_rows=g.value)

@@ -62,12 +62,13 @@ def test_batch_streams_equals_sequential(sacc):
 
 
 def test_batch_auto_tunes(sacc):
-    """The tuner times every stream plan and both segmented plans, one step each after
-    the warm-up, and keeps one; every step meets the tolerance whichever plan ran it."""
+    """The tuner times every stream plan and the segmented plans (both work-item sizes),
+    one step each after the warm-up, and keeps one; every step meets the tolerance
+    whichever plan ran it."""
     import torch
 
     probs = batch_problems(seed=5, nseq=5, lo=16, hi=32, steps=40)
-    warm, steps = 3, 16
+    warm, steps = 3, 20
     seqs = [_seq(sacc, p, m) for p, m in probs]
     batch = sacc.Batch(seqs, max_streams=8, tune_warmup=warm)
     seen_seg = False
@@ -121,8 +122,8 @@ def test_batch_segmented_graph_equals_eager(sacc):
     assert ga.plan()["segmented"] and ea.plan()["segmented"]
 
 
-@pytest.mark.parametrize("mode", ["streams", "segmented"])
-def test_batch_matches_oracle(sacc, mode):
+@pytest.mark.parametrize("mode,rows", [("streams", None), ("segmented", 1024), ("segmented", 512)])
+def test_batch_matches_oracle(sacc, mode, rows, monkeypatch):
     """Each sequence of a batch, stepped by the batch driver in its own configuration
     (float32 operator and Krylov vectors, FP64 history and refinement, up to 100 sweeps),
     against the oracle on the same history: before every step the oracle's history holds
@@ -131,7 +132,8 @@ def test_batch_matches_oracle(sacc, mode):
     perturbation (reversed summation order of A x, or its start perturbed by 1e-15
     relative), at least one per refinement sweep and 10 % (each side starts from its own
     guess, and the float32 inner solves of the first steps' two sweeps move by several
-    iterations under such perturbations); the totals over all steps within 3 %."""
+    iterations under such perturbations); the totals over all steps within 3 %.  The
+    segmented engine runs with each of its work-item sizes (pinned by SACC_SEG_ROWS)."""
     import math
 
     import torch
@@ -145,6 +147,8 @@ def test_batch_matches_oracle(sacc, mode):
     seqs = [_seq(sacc, p, m) for p, m in probs]
     batch = sacc.Batch(seqs, max_streams=4, tune_warmup=4)
     batch.set_mode(mode)
+    if rows is not None:
+        monkeypatch.setenv("SACC_SEG_ROWS", str(rows))
     oseqs = [OSeq(p.n, m["M"], m["sketch"], m["s"], m["method_seed"], m["solver"], m["restart"], m["tol"],
                   precision=m["prec"], max_refine=m["max_refine"]) for p, m in probs]
     rows = []
@@ -203,9 +207,10 @@ def _edge_matrix(n, kind, seed):
     return A
 
 
-def test_batch_segmented_edge_cases(sacc):
+@pytest.mark.parametrize("rows", [1024, 512])
+def test_batch_segmented_edge_cases(sacc, rows, monkeypatch):
     """The segmented engine on ragged and tiny systems (n = 1 .. 3000, not multiples of
-    its 64-row tiles or 1024-row work items), GMRES restart lengths 1, 2, 7 and 30, a
+    its 64-row tiles or its 512- or 1024-row work items), GMRES restart lengths 1, 2, 7 and 30, a
     zero right-hand side in the second step, and an iteration cap of 3: each system
     against the oracle's refinement solve from the same zero start (guess "zero"),
     equal stopping status, the cap's count exact, zero x for b = 0, converged counts
@@ -226,6 +231,7 @@ def test_batch_segmented_edge_cases(sacc):
             for (n, kind, r, mx) in cases]
     batch = sacc.Batch(seqs, max_streams=2)
     batch.set_mode("segmented")
+    monkeypatch.setenv("SACC_SEG_ROWS", str(rows))
     rng = np.random.default_rng(9)
     As = [sacc.DeviceCSR(A.indptr, A.indices, A.data) for A in mats]
     for step in range(2):
