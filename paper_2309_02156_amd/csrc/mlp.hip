@@ -29,58 +29,68 @@ __device__ inline float silu_grad_f(float z) {
 
 enum { EPI_FWD = 0, EPI_STORE = 1, EPI_DA = 2 };
 
-constexpr int GT = 32;  // C tile of the small GEMM: GT x GT, 256 threads (2 x 2 each)
+constexpr int GT = 32;  // C tile of the small GEMM: GT x GT, 256 threads (one 16 x 16 quarter per wave)
+constexpr int GTP = GT + 4;  // LDS row stride of the staged tiles (16-bit words)
+
+typedef short mlp_s4 __attribute__((ext_vector_type(4)));
+typedef float mlp_f4 __attribute__((ext_vector_type(4)));
+
+__device__ inline unsigned short bf16_word(float x) { return (unsigned short)(__float_as_uint(bf16r(x)) >> 16); }
 
 // C[m][n] = sum_k bf16(L(m, k)) bf16(R(k, n)), float32 accumulate, with
 // L(m, k) = L[m lsm + k lsk] and R(k, n) = R[k rsk + n rsn]; epilogues:
 //   EPI_FWD:   Z = C + bias[n]; Aout = act ? silu(Z) : Z  (row-major M x N)
 //   EPI_STORE: Out = C
 //   EPI_DA:    Out = C * silu'(Zprev)
+// The block stages GT x GT tiles of L and of R (transposed) in LDS as BF16 words (the
+// strides and the bounds are handled there) and each wave accumulates one 16 x 16
+// quarter of the C tile with v_mfma_f32_16x16x16bf16_1k, two per staged tile.  Operand
+// layout: A[i][4 kq + e] from lane i + 16 kq, B[4 kq + e][j] from lane j + 16 kq
+// (e = 0..3), D[4 kq + v][j] in lane j + 16 kq, element v.  The products of two BF16
+// values are exact in float32; only the order of the float32 sums differs from a plain
+// loop over k.
 template <int EPI>
 __global__ __launch_bounds__(256) void k_mlp_gemm(int M, int N, int K, const float *L, int lsm, int lsk,
                                                   const float *R, int rsk, int rsn, const float *bias, float *Z,
                                                   float *Aout, int act, const float *Zprev, float *Out) {
-  __shared__ float Ls[GT][GT + 1], Rs[GT][GT + 1];
-  const int tx = threadIdx.x % 16, ty = threadIdx.x / 16;
+  __shared__ __align__(8) unsigned short Ls[GT][GTP], Rt[GT][GTP];  // Rt[n][k]: R transposed
+  const int lane = threadIdx.x % WAVE, wid = threadIdx.x / WAVE;
+  const int i16 = lane % 16, kq = lane / 16;
+  const int wm = wid / 2, wn = wid % 2;  // the wave's quarter of the C tile
   const int m0 = blockIdx.y * GT, n0 = blockIdx.x * GT;
-  float acc[2][2] = {{0.f, 0.f}, {0.f, 0.f}};
+  mlp_f4 acc = {0.f, 0.f, 0.f, 0.f};
   for (int k0 = 0; k0 < K; k0 += GT) {
     for (int e = threadIdx.x; e < GT * GT; e += 256) {
       const int r = e / GT, c = e % GT;
       const int m = m0 + r, kk = k0 + c;
-      Ls[r][c] = (m < M && kk < K) ? bf16r(L[(size_t)m * lsm + (size_t)kk * lsk]) : 0.f;
+      Ls[r][c] = (m < M && kk < K) ? bf16_word(L[(size_t)m * lsm + (size_t)kk * lsk]) : (unsigned short)0;
       const int kr = k0 + r, n = n0 + c;
-      Rs[r][c] = (kr < K && n < N) ? bf16r(R[(size_t)kr * rsk + (size_t)n * rsn]) : 0.f;
+      Rt[c][r] = (kr < K && n < N) ? bf16_word(R[(size_t)kr * rsk + (size_t)n * rsn]) : (unsigned short)0;
     }
     __syncthreads();
-#pragma unroll 8
-    for (int kk = 0; kk < GT; ++kk) {
-      const float l0 = Ls[ty * 2][kk], l1 = Ls[ty * 2 + 1][kk];
-      const float r0 = Rs[kk][tx * 2], r1 = Rs[kk][tx * 2 + 1];
-      acc[0][0] = fmaf(l0, r0, acc[0][0]);
-      acc[0][1] = fmaf(l0, r1, acc[0][1]);
-      acc[1][0] = fmaf(l1, r0, acc[1][0]);
-      acc[1][1] = fmaf(l1, r1, acc[1][1]);
+#pragma unroll
+    for (int kh = 0; kh < GT; kh += 16) {
+      const mlp_s4 a = *(const mlp_s4 *)&Ls[wm * 16 + i16][kh + 4 * kq];
+      const mlp_s4 b = *(const mlp_s4 *)&Rt[wn * 16 + i16][kh + 4 * kq];
+      acc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, b, acc, 0, 0, 0);
     }
     __syncthreads();
   }
 #pragma unroll
-  for (int a = 0; a < 2; ++a)
-#pragma unroll
-    for (int b = 0; b < 2; ++b) {
-      const int m = m0 + ty * 2 + a, n = n0 + tx * 2 + b;
-      if (m >= M || n >= N) continue;
-      const size_t o = (size_t)m * N + n;
-      if (EPI == EPI_FWD) {
-        const float z = acc[a][b] + bias[n];
-        Z[o] = z;
-        Aout[o] = act ? silu_f(z) : z;
-      } else if (EPI == EPI_STORE) {
-        Out[o] = acc[a][b];
-      } else {
-        Out[o] = acc[a][b] * silu_grad_f(Zprev[o]);
-      }
+  for (int v = 0; v < 4; ++v) {
+    const int m = m0 + wm * 16 + 4 * kq + v, n = n0 + wn * 16 + i16;
+    if (m >= M || n >= N) continue;
+    const size_t o = (size_t)m * N + n;
+    if (EPI == EPI_FWD) {
+      const float z = acc[v] + bias[n];
+      Z[o] = z;
+      Aout[o] = act ? silu_f(z) : z;
+    } else if (EPI == EPI_STORE) {
+      Out[o] = acc[v];
+    } else {
+      Out[o] = acc[v] * silu_grad_f(Zprev[o]);
     }
+  }
 }
 
 template <int EPI>
