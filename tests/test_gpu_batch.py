@@ -88,12 +88,15 @@ def test_batch_auto_tunes(sacc):
     assert plan["tuned"] and 1 <= plan["streams"] <= 8
 
 
-def test_batch_segmented_graph_equals_eager(sacc):
+@pytest.mark.parametrize("rows", [1024, 512])
+def test_batch_segmented_graph_equals_eager(sacc, rows, monkeypatch):
     """The segmented engine replaying its captured hipGraph of 16 steps (many replays per
     solve, the guesses' eager launches and host waits between solves) gives bitwise the
-    solutions and counts of the same engine launched eagerly, step after step; every
-    solve meets the tolerance."""
+    solutions and counts of the same engine launched eagerly, step after step, with each
+    work-item size; every solve meets the tolerance."""
     import torch
+
+    monkeypatch.setenv("SACC_SEG_ROWS", str(rows))
 
     probs = batch_problems(seed=6, nseq=6, lo=12, hi=40, steps=40)
     steps = 14
