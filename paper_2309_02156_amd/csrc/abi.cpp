@@ -594,17 +594,30 @@ int basis_enqueue(sa_seq *q, int cnt, hipStream_t st) {
   return SA_OK;
 }
 
-// Alg. 1 (basis and reduced problem) on the device: Q1 = X T1, SpMM + Gram, reduced solve, x0 = Q1 c.
+// Alg. 1 (basis and reduced problem) on the device: Q1 = X T1, SpMM + Gram, reduced solve,
+// x0 = Q1 c.  guess_projection_begin enqueues the basis (when the history changed since
+// it was formed) and the SpMM + Gram pass and describes the reduced solve in *job (the
+// caller launches it alone or batched with other sequences'); guess_projection_finish
+// enqueues x0.
 template <typename TX>
-int guess_projection(sa_seq *q, const CsrView &v, const double *b, double *x0, int cnt, hipStream_t st) {
+int guess_projection_begin(sa_seq *q, const CsrView &v, const double *b, int cnt, hipStream_t st, SolveJob *job) {
   const sa_config &c = q->cfg;
   int nblk = 0;
   if (q->basis_for != q->pushes) SA_TRY(basis_enqueue<TX>(q, cnt, st));
   const int mr = c.projection == SA_MINRES ? 1 : 0;
   HIP_TRY(launch_spmm_gram<TX>(v, (const TX *)q->Q1, q->ld, b, cnt, mr, q->partials, &nblk, q->ctl, st));
   HIP_TRY(launch_colsum(q->partials, nblk, gram_width(cnt, mr), q->ctl, st));
-  HIP_TRY(launch_small_solve(cnt, mr, c.solver == SA_CG ? 1 : 0, q->tau_c, q->ctl, st));
-  HIP_TRY(launch_x0<TX>((const TX *)q->Q1, (const TX *)q->X, x0, c.n, q->ld, q->ctl, st));
+  job->cnt = cnt;
+  job->minres = mr;
+  job->spd = c.solver == SA_CG ? 1 : 0;
+  job->tau_c = q->tau_c;
+  job->ctl = q->ctl;
+  return SA_OK;
+}
+
+template <typename TX>
+int guess_projection_finish(sa_seq *q, double *x0, hipStream_t st) {
+  HIP_TRY(launch_x0<TX>((const TX *)q->Q1, (const TX *)q->X, x0, q->cfg.n, q->ld, q->ctl, st));
   return SA_OK;
 }
 
@@ -742,7 +755,9 @@ ZRows zrows_push(sa_seq *q) {
 }
 
 // push x into the history; zero_rhs: push zero if the last solve ended with b = 0
-int push_enqueue(sa_seq *q, const void *x_dev, int zero_rhs, hipStream_t st) {
+// A push up to its sketched QR, which it describes in *job (launched alone by
+// push_enqueue, or batched with other sequences' by the segmented batch step)
+int push_begin(sa_seq *q, const void *x_dev, int zero_rhs, hipStream_t st, QrcpJob *job) {
   const sa_config &c = q->cfg;
   const int slot = (int)(q->pushes % c.M);
   if (q->sketch_bf16)
@@ -764,7 +779,23 @@ int push_enqueue(sa_seq *q, const void *x_dev, int zero_rhs, hipStream_t st) {
     q->ltargets += 1;
   }
   q->pushes += 1;
-  HIP_TRY(launch_qrcp(q->SX, c.s, count(q), slot, q->tau_s, q->partials, c.n, q->ctl, zrows_push(q), c.seed, st));
+  job->SX = q->SX;
+  job->s = c.s;
+  job->cnt = count(q);
+  job->newest = slot;
+  job->tau = q->tau_s;
+  job->partials = q->partials;
+  job->nbx = push_blocks_x(c.n, c.s);
+  job->ctl = q->ctl;
+  job->zr = zrows_push(q);
+  job->seed = c.seed;
+  return SA_OK;
+}
+
+int push_enqueue(sa_seq *q, const void *x_dev, int zero_rhs, hipStream_t st) {
+  QrcpJob j;
+  SA_TRY(push_begin(q, x_dev, zero_rhs, st, &j));
+  HIP_TRY(launch_qrcp(j.SX, j.s, j.cnt, j.newest, j.tau, j.partials, q->cfg.n, j.ctl, j.zr, j.seed, st));
   return SA_OK;
 }
 
@@ -785,9 +816,12 @@ namespace {
 // Enqueues the initial guess of the next step into x0; with `want_info` also its timing
 // events (the reduced solve and the learned choice write their ranks and decision into
 // the pinned guess record, read by guess_info after the stream has passed them).
-// *cnt = history columns used.
-int guess_enqueue(sa_seq *q, const sa_csr *A, const void *b_dev, void *x0_dev, bool want_info, hipStream_t st,
-                  int *cnt_out) {
+// *cnt = history columns used.  guess_begin enqueues it up to the reduced solve of a
+// projection guess (then *deferred = true and *job describes the solve, which the
+// caller launches alone or batched), guess_finish the rest.
+int guess_begin(sa_seq *q, const sa_csr *A, const void *b_dev, void *x0_dev, bool want_info, hipStream_t st,
+                int *cnt_out, SolveJob *job, bool *deferred) {
+  *deferred = false;
   int rc = check_csr(q, A);
   if (rc != SA_OK) return rc;
   if (!b_dev || !x0_dev) return SA_EINVAL;
@@ -808,13 +842,36 @@ int guess_enqueue(sa_seq *q, const sa_csr *A, const void *b_dev, void *x0_dev, b
   } else {
     CsrView v = view(A);
     if (q->x32)
-      SA_TRY(guess_projection<float>(q, v, (const double *)b_dev, (double *)x0_dev, cnt, st));
+      SA_TRY(guess_projection_begin<float>(q, v, (const double *)b_dev, cnt, st, job));
     else
-      SA_TRY(guess_projection<double>(q, v, (const double *)b_dev, (double *)x0_dev, cnt, st));
-    if (q->mlp && q->ltargets >= q->lhist) SA_TRY(guess_learned(q, v, (const double *)b_dev, (double *)x0_dev, cnt, st));
+      SA_TRY(guess_projection_begin<double>(q, v, (const double *)b_dev, cnt, st, job));
+    *deferred = true;
+  }
+  return SA_OK;
+}
+
+int guess_finish(sa_seq *q, const sa_csr *A, const void *b_dev, void *x0_dev, bool want_info, hipStream_t st,
+                 int cnt) {
+  const sa_config &c = q->cfg;
+  if (cnt > 0 && c.guess == SA_GUESS_PROJECTION) {
+    if (q->x32)
+      SA_TRY(guess_projection_finish<float>(q, (double *)x0_dev, st));
+    else
+      SA_TRY(guess_projection_finish<double>(q, (double *)x0_dev, st));
+    if (q->mlp && q->ltargets >= q->lhist)
+      SA_TRY(guess_learned(q, view(A), (const double *)b_dev, (double *)x0_dev, cnt, st));
   }
   if (want_info) HIP_TRY(hipEventRecord(q->ev[1], st));
   return SA_OK;
+}
+
+int guess_enqueue(sa_seq *q, const sa_csr *A, const void *b_dev, void *x0_dev, bool want_info, hipStream_t st,
+                  int *cnt_out) {
+  SolveJob job;
+  bool deferred = false;
+  SA_TRY(guess_begin(q, A, b_dev, x0_dev, want_info, st, cnt_out, &job, &deferred));
+  if (deferred) HIP_TRY(launch_small_solve(job.cnt, job.minres, job.spd, job.tau_c, job.ctl, st));
+  return guess_finish(q, A, b_dev, x0_dev, want_info, st, *cnt_out);
 }
 
 // After a step's push: the next projection guess's basis Q1 = X T1 depends on the history
@@ -1561,6 +1618,12 @@ struct sa_batch {
   int mode = SA_BATCH_AUTO;
   bool seg_ok = false;        // every sequence is mixed-precision without a preconditioner
   SegEngine *seg = nullptr;   // the segmented engine (created with the batch when seg_ok)
+  // the segmented step's batched QRCP and reduced-solve launches: per-stream events,
+  // the batch stream's event, pinned staging and device copies of the jobs
+  std::vector<hipEvent_t> sev;
+  hipEvent_t bev = nullptr;
+  SolveJob *hsolve = nullptr, *dsolve = nullptr;
+  QrcpJob *hqrcp = nullptr, *dqrcp = nullptr;
   double seg_bytes = 0.0, seg_ms = 0.0;  // the last step's segmented solve (0 after a stream step)
 };
 
@@ -1598,21 +1661,52 @@ int batch_step_seg(sa_batch *b, const Plan &plan, const std::vector<std::vector<
                    const void *const *rhs, void *const *x, std::vector<sa_info> &inf, bool graph) {
   const int nseq = (int)b->seqs.size();
   std::vector<int> rc(plan.streams, SA_OK);
-  // every guess of a stream's list enqueued, one wait per stream, then their records
+  hipStream_t bs = b->streams[0];  // the batched launches' stream
+  // the guesses up to their reduced solves, every sequence of a stream's list enqueued
+  // on it; then every reduced solve in one launch; then the rest of each guess, one
+  // wait per stream, and the guess records
+  std::vector<int> cnts(nseq, 0);
+  std::vector<SolveJob> sj(nseq);
+  std::vector<char> deferred(nseq, 0);
   pool_run(b, plan.streams, [&](int s) {
     hipStream_t st = b->streams[s];
-    std::vector<int> cnts(lists[s].size(), 0);
     int r = SA_OK;
     for (size_t k = 0; k < lists[s].size() && r == SA_OK; ++k) {
       const int i = lists[s][k];
       memset(&inf[i], 0, sizeof(sa_info));
-      r = b->seqs[i]->alive ? guess_enqueue(b->seqs[i], A[i], rhs[i], x[i], true, st, &cnts[k]) : SA_ESTATE;
+      bool d = false;
+      r = b->seqs[i]->alive ? guess_begin(b->seqs[i], A[i], rhs[i], x[i], true, st, &cnts[i], &sj[i], &d)
+                            : SA_ESTATE;
+      deferred[i] = d ? 1 : 0;
+    }
+    if (r == SA_OK) r = hipEventRecord(b->sev[s], st) == hipSuccess ? SA_OK : SA_EHIP;
+    if (r != SA_OK) rc[s] = r;
+  });
+  for (int r : rc)
+    if (r != SA_OK) return r;
+  {
+    int nj = 0;
+    for (int i = 0; i < nseq; ++i)
+      if (deferred[i]) b->hsolve[nj++] = sj[i];
+    for (int s = 1; s < plan.streams; ++s) HIP_TRY(hipStreamWaitEvent(bs, b->sev[s], 0));
+    if (nj > 0) {
+      HIP_TRY(hipMemcpyAsync(b->dsolve, b->hsolve, nj * sizeof(SolveJob), hipMemcpyHostToDevice, bs));
+      HIP_TRY(launch_small_solve_batch(b->dsolve, b->hsolve, nj, bs));
+    }
+    HIP_TRY(hipEventRecord(b->bev, bs));
+  }
+  pool_run(b, plan.streams, [&](int s) {
+    hipStream_t st = b->streams[s];
+    int r = s == 0 ? SA_OK : (hipStreamWaitEvent(st, b->bev, 0) == hipSuccess ? SA_OK : SA_EHIP);
+    for (size_t k = 0; k < lists[s].size() && r == SA_OK; ++k) {
+      const int i = lists[s][k];
+      r = guess_finish(b->seqs[i], A[i], rhs[i], x[i], true, st, cnts[i]);
     }
     if (r == SA_OK) r = hipStreamSynchronize(st) == hipSuccess ? SA_OK : SA_EHIP;
     for (size_t k = 0; k < lists[s].size() && r == SA_OK; ++k) {
       sa_info g;
       memset(&g, 0, sizeof(g));
-      r = guess_info(b->seqs[lists[s][k]], cnts[k], &g);
+      r = guess_info(b->seqs[lists[s][k]], cnts[lists[s][k]], &g);
       guess_into(inf[lists[s][k]], g);
     }
     if (r != SA_OK) rc[s] = r;
@@ -1674,16 +1768,51 @@ int batch_step_seg(sa_batch *b, const Plan &plan, const std::vector<std::vector<
     inf[i].status = status_of(r.state);
     inf[i].ms_solve = ms;
   }
+  // the pushes up to their sketched QRs on the streams, then every QRCP in one launch
+  // (the small instantiation's jobs first) and one wait
+  std::vector<QrcpJob> qj(nseq);
   pool_run(b, plan.streams, [&](int s) {
     hipStream_t sp = b->streams[s];
     int r = SA_OK;
-    for (size_t k = 0; k < lists[s].size() && r == SA_OK; ++k) r = sa_push_solution(b->seqs[lists[s][k]], x[lists[s][k]], sp);
-    if (r == SA_OK) r = hipStreamSynchronize(sp) == hipSuccess ? SA_OK : SA_EHIP;
+    for (size_t k = 0; k < lists[s].size() && r == SA_OK; ++k) {
+      const int i = lists[s][k];
+      r = b->seqs[i]->alive ? push_begin(b->seqs[i], x[i], 0, sp, &qj[i]) : SA_ESTATE;
+    }
+    if (r == SA_OK) r = hipEventRecord(b->sev[s], sp) == hipSuccess ? SA_OK : SA_EHIP;
     if (r != SA_OK) rc[s] = r;
   });
   for (int r : rc)
     if (r != SA_OK) return r;
+  int nj = 0;
+  for (int pass = 0; pass < 2; ++pass)
+    for (int i = 0; i < nseq; ++i)
+      if (qrcp_job_small(qj[i]) == (pass == 0)) b->hqrcp[nj++] = qj[i];
+  for (int s = 1; s < plan.streams; ++s) HIP_TRY(hipStreamWaitEvent(bs, b->sev[s], 0));
+  HIP_TRY(hipMemcpyAsync(b->dqrcp, b->hqrcp, nj * sizeof(QrcpJob), hipMemcpyHostToDevice, bs));
+  HIP_TRY(launch_qrcp_batch(b->dqrcp, b->hqrcp, nj, bs));
+  HIP_TRY(hipStreamSynchronize(bs));
   return SA_OK;
+}
+
+}  // namespace
+
+namespace {
+
+// the segmented step's engine and batched-launch resources (each released if present)
+void batch_seg_free(sa_batch *b) {
+  if (b->seg) seg_engine_destroy(b->seg);
+  b->seg = nullptr;
+  for (auto &e : b->sev)
+    if (e) (void)hipEventDestroy(e);
+  b->sev.clear();
+  if (b->bev) (void)hipEventDestroy(b->bev);
+  if (b->hsolve) (void)hipHostFree(b->hsolve);
+  if (b->dsolve) (void)hipFree(b->dsolve);
+  if (b->hqrcp) (void)hipHostFree(b->hqrcp);
+  if (b->dqrcp) (void)hipFree(b->dqrcp);
+  b->bev = nullptr;
+  b->hsolve = b->dsolve = nullptr;
+  b->hqrcp = b->dqrcp = nullptr;
 }
 
 }  // namespace
@@ -1713,7 +1842,16 @@ int sa_batch_create(sa_seq *const *seqs, int nseq, int max_streams, int tune_war
   if (b->seg_ok) {
     std::vector<int64_t> ns(nseq);
     for (int i = 0; i < nseq; ++i) ns[i] = seqs[i]->cfg.n;
-    if (seg_engine_create(ns.data(), nseq, &b->seg) != 0) {
+    bool ok = seg_engine_create(ns.data(), nseq, &b->seg) == 0;
+    b->sev.assign(max_streams, nullptr);
+    for (auto &e : b->sev) ok = ok && hipEventCreateWithFlags(&e, hipEventDisableTiming) == hipSuccess;
+    ok = ok && hipEventCreateWithFlags(&b->bev, hipEventDisableTiming) == hipSuccess &&
+         hipHostMalloc((void **)&b->hsolve, nseq * sizeof(SolveJob), hipHostMallocDefault) == hipSuccess &&
+         hipMalloc((void **)&b->dsolve, nseq * sizeof(SolveJob)) == hipSuccess &&
+         hipHostMalloc((void **)&b->hqrcp, nseq * sizeof(QrcpJob), hipHostMallocDefault) == hipSuccess &&
+         hipMalloc((void **)&b->dqrcp, nseq * sizeof(QrcpJob)) == hipSuccess;
+    if (!ok) {
+      batch_seg_free(b);
       for (auto &t : b->streams) (void)hipStreamDestroy(t);
       delete b;
       return SA_ENOMEM;
@@ -1751,7 +1889,7 @@ int sa_batch_destroy(sa_batch *b) {
   }
   b->pool.go.notify_all();
   for (auto &t : b->pool.th) t.join();
-  if (b->seg) seg_engine_destroy(b->seg);
+  batch_seg_free(b);
   for (auto &s : b->streams)
     if (s) (void)hipStreamDestroy(s);
   delete b;

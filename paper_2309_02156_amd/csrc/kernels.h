@@ -61,6 +61,23 @@ struct ZRows {
 hipError_t launch_qrcp(double *SX, int s, int cnt, int newest, double tau, const double *partials, int64_t n,
                        Ctl *ctl, const ZRows &zr, uint64_t seed, hipStream_t st);
 
+// One sequence's QRCP (the arguments of launch_qrcp), for a batched launch
+struct QrcpJob {
+  double *SX;
+  int s, cnt, newest;
+  double tau;
+  const double *partials;
+  int nbx;  // the push kernel's blocks along n (push_blocks_x)
+  Ctl *ctl;
+  ZRows zr;
+  uint64_t seed;
+};
+// whether the job takes the small instantiation (a batch lists those first)
+bool qrcp_job_small(const QrcpJob &j);
+// jobs_dev: device copy of jobs_host[0..njobs); block b of a launch runs job b, with the
+// same code and results as launch_qrcp of that job
+hipError_t launch_qrcp_batch(const QrcpJob *jobs_dev, const QrcpJob *jobs_host, int njobs, hipStream_t st);
+
 // Q1 = X T1 (first ctl->k columns)
 template <typename TX>
 hipError_t launch_basis(const TX *X, TX *Q1, int64_t n, int64_t ld, int cnt, Ctl *ctl, hipStream_t st);
@@ -86,6 +103,13 @@ hipError_t launch_colsum(const double *partials, int nblk, int W, Ctl *ctl, hipS
 
 // pivoted Cholesky of G, reduced solve -> c, cX, k2, fallback
 hipError_t launch_small_solve(int cnt, int minres, int spd, double tau_c, Ctl *ctl, hipStream_t st);
+// one sequence's reduced solve (the arguments of launch_small_solve), for a batched launch
+struct SolveJob {
+  int cnt, minres, spd;
+  double tau_c;
+  Ctl *ctl;
+};
+hipError_t launch_small_solve_batch(const SolveJob *jobs_dev, const SolveJob *jobs_host, int njobs, hipStream_t st);
 
 // x0 = Q1 c (or the fallback)
 template <typename TX>

@@ -17,6 +17,8 @@
 // floating-point atomics.
 #include <math.h>
 
+#include <algorithm>
+
 #include "common.h"
 #include "kernels.h"
 
@@ -353,9 +355,9 @@ hipError_t launch_push_bf16(const double *x, TX *X, const unsigned short *G, dou
 // swap, and every wave applies the reflector to its columns (the dots batched the same
 // way).  Three barriers a step.  MC = columns a wave owns at most, RW = 64-row chunks.
 template <int MC, int RW>
-__global__ __launch_bounds__(TPB) void k_qrcp(double *SX, int s, int cnt, int newest, double tau,
-                                              const double *partials, int nbx, Ctl *ctl, ZRows zr,
-                                              uint64_t seed) {
+__device__ __forceinline__ void qrcp_body(double *SX, int s, int cnt, int newest, double tau,
+                                          const double *partials, int nbx, Ctl *ctl, const ZRows &zr,
+                                          uint64_t seed) {
   extern __shared__ double sh[];
   // zr.m > 0: the range finder's Z (cnt x m) multiplies S X first (Alg. 3: the sketch of
   // Omega = X Z), and the QR runs over the m columns of Y = (S X) Z
@@ -605,12 +607,61 @@ __global__ __launch_bounds__(TPB) void k_qrcp(double *SX, int s, int cnt, int ne
   }
 }
 
-hipError_t launch_qrcp(double *SX, int s, int cnt, int newest, double tau, const double *partials, int64_t n,
-                       Ctl *ctl, const ZRows &zr, uint64_t seed, hipStream_t st) {
+template <int MC, int RW>
+__global__ __launch_bounds__(TPB) void k_qrcp(double *SX, int s, int cnt, int newest, double tau,
+                                              const double *partials, int nbx, Ctl *ctl, ZRows zr,
+                                              uint64_t seed) {
+  qrcp_body<MC, RW>(SX, s, cnt, newest, tau, partials, nbx, ctl, zr, seed);
+}
+
+// many sequences' QRCPs in one launch: block b runs job b (the same body as k_qrcp)
+template <int MC, int RW>
+__global__ __launch_bounds__(TPB) void k_qrcp_batch(const QrcpJob *__restrict__ jobs) {
+  const QrcpJob &j = jobs[blockIdx.x];
+  qrcp_body<MC, RW>(j.SX, j.s, j.cnt, j.newest, j.tau, j.partials, j.nbx, j.ctl, j.zr, j.seed);
+}
+
+// dynamic LDS bytes of a QRCP, and whether it takes the small instantiation
+static size_t qrcp_lds(int s, int cnt, const ZRows &zr) {
   const int nq = zr.m > 0 ? zr.m : cnt;
   size_t lds = ((size_t)s * cnt + (size_t)nq * nq) * sizeof(double);
   if (zr.m > 0) lds += ((size_t)cnt * zr.m + (size_t)s * zr.m) * sizeof(double);
-  if (nq <= 2 * NWAVE * 4 && s <= 2 * WAVE)
+  return lds;
+}
+static bool qrcp_small(int s, int cnt, const ZRows &zr) {
+  const int nq = zr.m > 0 ? zr.m : cnt;
+  return nq <= 2 * NWAVE * 4 && s <= 2 * WAVE;
+}
+
+hipError_t launch_qrcp_batch(const QrcpJob *jobs_dev, const QrcpJob *jobs_host, int njobs, hipStream_t st) {
+  // one launch per instantiation; the jobs are sorted by it (small ones first)
+  int nsmall = 0;
+  size_t lds_s = sizeof(double), lds_l = sizeof(double);
+  for (int i = 0; i < njobs; ++i) {
+    const QrcpJob &j = jobs_host[i];
+    const size_t b = qrcp_lds(j.s, j.cnt, j.zr);
+    if (qrcp_small(j.s, j.cnt, j.zr)) {
+      if (i != nsmall) return hipErrorInvalidValue;  // not sorted
+      ++nsmall;
+      lds_s = std::max(lds_s, b);
+    } else {
+      lds_l = std::max(lds_l, b);
+    }
+  }
+  if (nsmall > 0)
+    hipLaunchKernelGGL((k_qrcp_batch<8, 2>), dim3(nsmall), dim3(TPB), lds_s, st, jobs_dev);
+  if (njobs > nsmall)
+    hipLaunchKernelGGL((k_qrcp_batch<MAXM / NWAVE, MAXS / WAVE>), dim3(njobs - nsmall), dim3(TPB), lds_l, st,
+                       jobs_dev + nsmall);
+  return hipGetLastError();
+}
+
+bool qrcp_job_small(const QrcpJob &j) { return qrcp_small(j.s, j.cnt, j.zr); }
+
+hipError_t launch_qrcp(double *SX, int s, int cnt, int newest, double tau, const double *partials, int64_t n,
+                       Ctl *ctl, const ZRows &zr, uint64_t seed, hipStream_t st) {
+  const size_t lds = qrcp_lds(s, cnt, zr);
+  if (qrcp_small(s, cnt, zr))
     hipLaunchKernelGGL((k_qrcp<8, 2>), dim3(1), dim3(TPB), lds, st, SX, s, cnt, newest, tau, partials,
                        push_blocks_x(n, s), ctl, zr, seed);
   else
@@ -1311,7 +1362,7 @@ hipError_t launch_colsum(const double *partials, int nblk, int W, Ctl *ctl, hipS
 // tau_c max(diag G) gives R2 (k2 x k2) and perm2; H = R2^-T Ht_pp R2^-1,
 // g = R2^-T gt_p; H y = g by Cholesky (SPD path, and always for the minimum residual)
 // or LU with partial pivoting; c[perm2[i]] = (R2^-1 y)_i, cX = T1 c.
-__global__ __launch_bounds__(TPB) void k_small_solve(int cnt, int minres, int spd, double tau_c, Ctl *ctl) {
+__device__ __forceinline__ void small_solve_body(int cnt, int minres, int spd, double tau_c, Ctl *ctl) {
   extern __shared__ double sh[];
   const int k = ctl->k;
   const int tid = threadIdx.x, lane = tid % WAVE, wid = tid / WAVE;
@@ -1598,10 +1649,31 @@ __global__ __launch_bounds__(TPB) void k_small_solve(int cnt, int minres, int sp
   }
 }
 
+__global__ __launch_bounds__(TPB) void k_small_solve(int cnt, int minres, int spd, double tau_c, Ctl *ctl) {
+  small_solve_body(cnt, minres, spd, tau_c, ctl);
+}
+
+// many sequences' reduced solves in one launch: block b runs job b
+__global__ __launch_bounds__(TPB) void k_small_solve_batch(const SolveJob *__restrict__ jobs) {
+  const SolveJob &j = jobs[blockIdx.x];
+  small_solve_body(j.cnt, j.minres, j.minres ? 1 : j.spd, j.tau_c, j.ctl);
+}
+
+static size_t small_solve_lds(int cnt, int minres) {
+  const size_t lds = ((size_t)3 * cnt * cnt + (size_t)gram_width(cnt, minres)) * sizeof(double);
+  return lds == 0 ? sizeof(double) : lds;
+}
+
 hipError_t launch_small_solve(int cnt, int minres, int spd, double tau_c, Ctl *ctl, hipStream_t st) {
-  size_t lds = ((size_t)3 * cnt * cnt + (size_t)gram_width(cnt, minres)) * sizeof(double);
-  if (lds == 0) lds = sizeof(double);
-  hipLaunchKernelGGL(k_small_solve, dim3(1), dim3(TPB), lds, st, cnt, minres, minres ? 1 : spd, tau_c, ctl);
+  hipLaunchKernelGGL(k_small_solve, dim3(1), dim3(TPB), small_solve_lds(cnt, minres), st, cnt, minres,
+                     minres ? 1 : spd, tau_c, ctl);
+  return hipGetLastError();
+}
+
+hipError_t launch_small_solve_batch(const SolveJob *jobs_dev, const SolveJob *jobs_host, int njobs, hipStream_t st) {
+  size_t lds = sizeof(double);
+  for (int i = 0; i < njobs; ++i) lds = std::max(lds, small_solve_lds(jobs_host[i].cnt, jobs_host[i].minres));
+  if (njobs > 0) hipLaunchKernelGGL(k_small_solve_batch, dim3(njobs), dim3(TPB), lds, st, jobs_dev);
   return hipGetLastError();
 }
 
