@@ -1571,9 +1571,9 @@ namespace batchplan {
 
 // streams: host threads / streams in use; poll: Krylov steps enqueued ahead (stream
 // plans); seg: the solves run in the segmented engine (the streams then carry the
-// guesses and pushes), its data kernel's grid `over` times the resident blocks
-// streams and poll: the per-sequence plan; seg: the segmented engine, over: its data
-// grid in multiples of the resident blocks, rows: its work-item rows (512 or 1024)
+// guesses and pushes up to their batched QRCP and reduced-solve launches); over: the
+// engine's data grid in multiples of the resident blocks; rows: its work-item rows
+// (512 or 1024)
 struct Plan {
   int streams, poll, seg, over, rows;
 };
