@@ -876,7 +876,7 @@ int guess_enqueue(sa_seq *q, const sa_csr *A, const void *b_dev, void *x0_dev, b
 
 // After a step's push: the next projection guess's basis Q1 = X T1 depends on the history
 // only, so it is enqueued at once (it runs while the host returns and prepares the next
-// system); guess_projection then skips it.
+// system); guess_projection_begin then skips it.
 int basis_ahead(sa_seq *q, hipStream_t st) {
   const int cnt = count(q);
   if (cnt == 0 || q->cfg.guess != SA_GUESS_PROJECTION) return SA_OK;
