@@ -339,8 +339,9 @@ int sa_batch_plan(const sa_batch *b, int *streams, int *poll, int *tuned, int *s
  *   SA_BATCH_SEGMENTED_EAGER: the same launches without the graph (bitwise the same
  *     results).
  * The guesses and pushes of a segmented step run on the batch's streams, except the
- * sketched QR of every push and the reduced solve of every projection guess, which run
- * as one launch each (a workgroup per sequence, the same code as one sequence's).  A step whose
+ * sketched QR of every push and the column sums, reduced solve and x0 of every
+ * projection guess, which run as one launch each on the first stream (the same code as
+ * one sequence's).  A step whose
  * matrices include one without nonzeros runs on streams.  Errors: SA_EINVAL (segmented
  * modes for a batch with an FP64 or preconditioned sequence). */
 #define SA_BATCH_AUTO 0

@@ -596,9 +596,9 @@ int basis_enqueue(sa_seq *q, int cnt, hipStream_t st) {
 
 // Alg. 1 (basis and reduced problem) on the device: Q1 = X T1, SpMM + Gram, reduced solve,
 // x0 = Q1 c.  guess_projection_begin enqueues the basis (when the history changed since
-// it was formed) and the SpMM + Gram pass and describes the reduced solve in *job (the
-// caller launches it alone or batched with other sequences'); guess_projection_finish
-// enqueues x0.
+// it was formed) and the SpMM + Gram pass and describes the column sums of its partial
+// rows and the reduced solve in *job (the caller launches them alone or batched with
+// other sequences'); guess_projection_finish enqueues x0.
 template <typename TX>
 int guess_projection_begin(sa_seq *q, const CsrView &v, const double *b, int cnt, hipStream_t st, SolveJob *job) {
   const sa_config &c = q->cfg;
@@ -606,7 +606,9 @@ int guess_projection_begin(sa_seq *q, const CsrView &v, const double *b, int cnt
   if (q->basis_for != q->pushes) SA_TRY(basis_enqueue<TX>(q, cnt, st));
   const int mr = c.projection == SA_MINRES ? 1 : 0;
   HIP_TRY(launch_spmm_gram<TX>(v, (const TX *)q->Q1, q->ld, b, cnt, mr, q->partials, &nblk, q->ctl, st));
-  HIP_TRY(launch_colsum(q->partials, nblk, gram_width(cnt, mr), q->ctl, st));
+  job->partials = q->partials;
+  job->nblk = nblk;
+  job->W = gram_width(cnt, mr);
   job->cnt = cnt;
   job->minres = mr;
   job->spd = c.solver == SA_CG ? 1 : 0;
@@ -816,9 +818,10 @@ namespace {
 // Enqueues the initial guess of the next step into x0; with `want_info` also its timing
 // events (the reduced solve and the learned choice write their ranks and decision into
 // the pinned guess record, read by guess_info after the stream has passed them).
-// *cnt = history columns used.  guess_begin enqueues it up to the reduced solve of a
-// projection guess (then *deferred = true and *job describes the solve, which the
-// caller launches alone or batched), guess_finish the rest.
+// *cnt = history columns used.  guess_begin enqueues it up to the SpMM + Gram pass of a
+// projection guess (then *deferred = true and *job describes the column sums and the
+// reduced solve, which the caller launches alone or batched), guess_finish the rest
+// (x0 unless the caller has launched it, the learned choice, the closing event).
 int guess_begin(sa_seq *q, const sa_csr *A, const void *b_dev, void *x0_dev, bool want_info, hipStream_t st,
                 int *cnt_out, SolveJob *job, bool *deferred) {
   *deferred = false;
@@ -851,13 +854,15 @@ int guess_begin(sa_seq *q, const sa_csr *A, const void *b_dev, void *x0_dev, boo
 }
 
 int guess_finish(sa_seq *q, const sa_csr *A, const void *b_dev, void *x0_dev, bool want_info, hipStream_t st,
-                 int cnt) {
+                 int cnt, bool x0_done) {
   const sa_config &c = q->cfg;
   if (cnt > 0 && c.guess == SA_GUESS_PROJECTION) {
-    if (q->x32)
-      SA_TRY(guess_projection_finish<float>(q, (double *)x0_dev, st));
-    else
-      SA_TRY(guess_projection_finish<double>(q, (double *)x0_dev, st));
+    if (!x0_done) {
+      if (q->x32)
+        SA_TRY(guess_projection_finish<float>(q, (double *)x0_dev, st));
+      else
+        SA_TRY(guess_projection_finish<double>(q, (double *)x0_dev, st));
+    }
     if (q->mlp && q->ltargets >= q->lhist)
       SA_TRY(guess_learned(q, view(A), (const double *)b_dev, (double *)x0_dev, cnt, st));
   }
@@ -870,8 +875,11 @@ int guess_enqueue(sa_seq *q, const sa_csr *A, const void *b_dev, void *x0_dev, b
   SolveJob job;
   bool deferred = false;
   SA_TRY(guess_begin(q, A, b_dev, x0_dev, want_info, st, cnt_out, &job, &deferred));
-  if (deferred) HIP_TRY(launch_small_solve(job.cnt, job.minres, job.spd, job.tau_c, job.ctl, st));
-  return guess_finish(q, A, b_dev, x0_dev, want_info, st, *cnt_out);
+  if (deferred) {
+    HIP_TRY(launch_colsum(job.partials, job.nblk, job.W, job.ctl, st));
+    HIP_TRY(launch_small_solve(job.cnt, job.minres, job.spd, job.tau_c, job.ctl, st));
+  }
+  return guess_finish(q, A, b_dev, x0_dev, want_info, st, *cnt_out, false);
 }
 
 // After a step's push: the next projection guess's basis Q1 = X T1 depends on the history
@@ -1623,6 +1631,7 @@ struct sa_batch {
   std::vector<hipEvent_t> sev;
   hipEvent_t bev = nullptr;
   SolveJob *hsolve = nullptr, *dsolve = nullptr;
+  X0Job *hx0 = nullptr, *dx0 = nullptr;
   QrcpJob *hqrcp = nullptr, *dqrcp = nullptr;
   double seg_bytes = 0.0, seg_ms = 0.0;  // the last step's segmented solve (0 after a stream step)
 };
@@ -1662,9 +1671,9 @@ int batch_step_seg(sa_batch *b, const Plan &plan, const std::vector<std::vector<
   const int nseq = (int)b->seqs.size();
   std::vector<int> rc(plan.streams, SA_OK);
   hipStream_t bs = b->streams[0];  // the batched launches' stream
-  // the guesses up to their reduced solves, every sequence of a stream's list enqueued
-  // on it; then every reduced solve in one launch; then the rest of each guess, one
-  // wait per stream, and the guess records
+  // the guesses up to their SpMM + Gram passes, every sequence of a stream's list
+  // enqueued on it; then on the batch stream every sequence's column sums, reduced solve
+  // and x0 in one launch each, the learned choices, one wait, and the guess records
   std::vector<int> cnts(nseq, 0);
   std::vector<SolveJob> sj(nseq);
   std::vector<char> deferred(nseq, 0);
@@ -1684,35 +1693,36 @@ int batch_step_seg(sa_batch *b, const Plan &plan, const std::vector<std::vector<
   });
   for (int r : rc)
     if (r != SA_OK) return r;
+  for (int s = 1; s < plan.streams; ++s) HIP_TRY(hipStreamWaitEvent(bs, b->sev[s], 0));
   {
-    int nj = 0;
+    int nj = 0, n32 = 0, n64 = 0;
     for (int i = 0; i < nseq; ++i)
       if (deferred[i]) b->hsolve[nj++] = sj[i];
-    for (int s = 1; s < plan.streams; ++s) HIP_TRY(hipStreamWaitEvent(bs, b->sev[s], 0));
+    // x0 jobs: float32 histories first, then float64 ones
+    for (int pass = 0; pass < 2; ++pass)
+      for (int i = 0; i < nseq; ++i) {
+        const sa_seq *q = b->seqs[i];
+        if (!deferred[i] || q->x32 != (pass == 0)) continue;
+        b->hx0[n32 + n64] = X0Job{q->Q1, q->X, (double *)x[i], q->cfg.n, q->ld, q->ctl};
+        (pass == 0 ? n32 : n64) += 1;
+      }
     if (nj > 0) {
       HIP_TRY(hipMemcpyAsync(b->dsolve, b->hsolve, nj * sizeof(SolveJob), hipMemcpyHostToDevice, bs));
+      HIP_TRY(hipMemcpyAsync(b->dx0, b->hx0, nj * sizeof(X0Job), hipMemcpyHostToDevice, bs));
+      HIP_TRY(launch_colsum_batch(b->dsolve, b->hsolve, nj, bs));
       HIP_TRY(launch_small_solve_batch(b->dsolve, b->hsolve, nj, bs));
+      if (n32 > 0) HIP_TRY(launch_x0_batch<float>(b->dx0, b->hx0, n32, bs));
+      if (n64 > 0) HIP_TRY(launch_x0_batch<double>(b->dx0 + n32, b->hx0 + n32, n64, bs));
     }
-    HIP_TRY(hipEventRecord(b->bev, bs));
-  }
-  pool_run(b, plan.streams, [&](int s) {
-    hipStream_t st = b->streams[s];
-    int r = s == 0 ? SA_OK : (hipStreamWaitEvent(st, b->bev, 0) == hipSuccess ? SA_OK : SA_EHIP);
-    for (size_t k = 0; k < lists[s].size() && r == SA_OK; ++k) {
-      const int i = lists[s][k];
-      r = guess_finish(b->seqs[i], A[i], rhs[i], x[i], true, st, cnts[i]);
-    }
-    if (r == SA_OK) r = hipStreamSynchronize(st) == hipSuccess ? SA_OK : SA_EHIP;
-    for (size_t k = 0; k < lists[s].size() && r == SA_OK; ++k) {
+    for (int i = 0; i < nseq; ++i) SA_TRY(guess_finish(b->seqs[i], A[i], rhs[i], x[i], true, bs, cnts[i], true));
+    HIP_TRY(hipStreamSynchronize(bs));
+    for (int i = 0; i < nseq; ++i) {
       sa_info g;
       memset(&g, 0, sizeof(g));
-      r = guess_info(b->seqs[lists[s][k]], cnts[lists[s][k]], &g);
-      guess_into(inf[lists[s][k]], g);
+      SA_TRY(guess_info(b->seqs[i], cnts[i], &g));
+      guess_into(inf[i], g);
     }
-    if (r != SA_OK) rc[s] = r;
-  });
-  for (int r : rc)
-    if (r != SA_OK) return r;
+  }
   if (!b->seg) return SA_ESTATE;
   int64_t tn = 0, tnnz = 0;
   for (int i = 0; i < nseq; ++i) {
@@ -1808,6 +1818,9 @@ void batch_seg_free(sa_batch *b) {
   if (b->bev) (void)hipEventDestroy(b->bev);
   if (b->hsolve) (void)hipHostFree(b->hsolve);
   if (b->dsolve) (void)hipFree(b->dsolve);
+  if (b->hx0) (void)hipHostFree(b->hx0);
+  if (b->dx0) (void)hipFree(b->dx0);
+  b->hx0 = b->dx0 = nullptr;
   if (b->hqrcp) (void)hipHostFree(b->hqrcp);
   if (b->dqrcp) (void)hipFree(b->dqrcp);
   b->bev = nullptr;
@@ -1848,6 +1861,8 @@ int sa_batch_create(sa_seq *const *seqs, int nseq, int max_streams, int tune_war
     ok = ok && hipEventCreateWithFlags(&b->bev, hipEventDisableTiming) == hipSuccess &&
          hipHostMalloc((void **)&b->hsolve, nseq * sizeof(SolveJob), hipHostMallocDefault) == hipSuccess &&
          hipMalloc((void **)&b->dsolve, nseq * sizeof(SolveJob)) == hipSuccess &&
+         hipHostMalloc((void **)&b->hx0, nseq * sizeof(X0Job), hipHostMallocDefault) == hipSuccess &&
+         hipMalloc((void **)&b->dx0, nseq * sizeof(X0Job)) == hipSuccess &&
          hipHostMalloc((void **)&b->hqrcp, nseq * sizeof(QrcpJob), hipHostMallocDefault) == hipSuccess &&
          hipMalloc((void **)&b->dqrcp, nseq * sizeof(QrcpJob)) == hipSuccess;
     if (!ok) {

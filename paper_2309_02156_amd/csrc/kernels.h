@@ -103,17 +103,30 @@ hipError_t launch_colsum(const double *partials, int nblk, int W, Ctl *ctl, hipS
 
 // pivoted Cholesky of G, reduced solve -> c, cX, k2, fallback
 hipError_t launch_small_solve(int cnt, int minres, int spd, double tau_c, Ctl *ctl, hipStream_t st);
-// one sequence's reduced solve (the arguments of launch_small_solve), for a batched launch
+// one sequence's column sums and reduced solve (the arguments of launch_colsum and
+// launch_small_solve), for batched launches
 struct SolveJob {
   int cnt, minres, spd;
   double tau_c;
   Ctl *ctl;
+  const double *partials;  // the SpMM + Gram kernel's partial rows: nblk rows of W entries
+  int nblk, W;
 };
+hipError_t launch_colsum_batch(const SolveJob *jobs_dev, const SolveJob *jobs_host, int njobs, hipStream_t st);
 hipError_t launch_small_solve_batch(const SolveJob *jobs_dev, const SolveJob *jobs_host, int njobs, hipStream_t st);
 
 // x0 = Q1 c (or the fallback)
 template <typename TX>
 hipError_t launch_x0(const TX *Q1, const TX *X, double *x0, int64_t n, int64_t ld, Ctl *ctl, hipStream_t st);
+// one sequence's x0 (the arguments of launch_x0; Q1 and X of the batch's storage type)
+struct X0Job {
+  const void *Q1, *X;
+  double *x0;
+  int64_t n, ld;
+  const Ctl *ctl;
+};
+template <typename TX>
+hipError_t launch_x0_batch(const X0Job *jobs_dev, const X0Job *jobs_host, int njobs, hipStream_t st);
 template <typename TX>
 hipError_t launch_to_double(const TX *x, double *y, int64_t n, hipStream_t st);
 

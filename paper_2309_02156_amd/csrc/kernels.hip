@@ -1331,10 +1331,11 @@ hipError_t launch_pod_eig(int cnt, int m, double tau, Ctl *ctl, hipStream_t st) 
 }
 
 // ---------------------------------------------------------------------------- column sums
-// gram[e] = sum_b partials[b][e]; block = 16 entries x 16 block-groups.
-__global__ __launch_bounds__(TPB) void k_colsum(const double *partials, int nblk, int W, Ctl *ctl) {
+// gram[e] = sum_b partials[b][e]; block = 16 entries x 16 block-groups (block bx: entries
+// 16 bx ..).
+__device__ __forceinline__ void colsum_body(int bx, const double *partials, int nblk, int W, Ctl *ctl) {
   __shared__ double sc[TPB];
-  const int e = blockIdx.x * 16 + threadIdx.x % 16, grp = threadIdx.x / 16;
+  const int e = bx * 16 + threadIdx.x % 16, grp = threadIdx.x / 16;
   double s = 0.0;
   // (unrolled so that a thread's row loads go out together: 18.8 -> 6.7 us over 768 rows)
   if (e < W)
@@ -1349,8 +1350,26 @@ __global__ __launch_bounds__(TPB) void k_colsum(const double *partials, int nblk
   if (threadIdx.x < 16 && e < W) ctl->gram[e] = sc[threadIdx.x];
 }
 
+__global__ __launch_bounds__(TPB) void k_colsum(const double *partials, int nblk, int W, Ctl *ctl) {
+  colsum_body(blockIdx.x, partials, nblk, W, ctl);
+}
+
+// many sequences' column sums in one launch: grid row y runs job y (blocks past a job's
+// entries write nothing)
+__global__ __launch_bounds__(TPB) void k_colsum_batch(const SolveJob *__restrict__ jobs) {
+  const SolveJob &j = jobs[blockIdx.y];
+  colsum_body(blockIdx.x, j.partials, j.nblk, j.W, j.ctl);
+}
+
 hipError_t launch_colsum(const double *partials, int nblk, int W, Ctl *ctl, hipStream_t st) {
   hipLaunchKernelGGL(k_colsum, dim3((W + 15) / 16), dim3(TPB), 0, st, partials, nblk, W, ctl);
+  return hipGetLastError();
+}
+
+hipError_t launch_colsum_batch(const SolveJob *jobs_dev, const SolveJob *jobs_host, int njobs, hipStream_t st) {
+  int gx = 1;
+  for (int i = 0; i < njobs; ++i) gx = std::max(gx, (jobs_host[i].W + 15) / 16);
+  if (njobs > 0) hipLaunchKernelGGL(k_colsum_batch, dim3(gx, njobs), dim3(TPB), 0, st, jobs_dev);
   return hipGetLastError();
 }
 
@@ -1679,8 +1698,8 @@ hipError_t launch_small_solve_batch(const SolveJob *jobs_dev, const SolveJob *jo
 
 // ============================================================================ x0
 template <int MC, typename TX>
-__global__ __launch_bounds__(TPB) void k_x0(const TX *Q1, const TX *X, double *x0, int64_t n, int64_t ld,
-                                            const Ctl *ctl) {
+__device__ __forceinline__ void x0_body(const TX *Q1, const TX *X, double *x0, int64_t n, int64_t ld,
+                                        const Ctl *ctl) {
   __shared__ double cc[MC];
   const int k = ctl->k;
   const int fb = ctl->fallback;
@@ -1699,9 +1718,30 @@ __global__ __launch_bounds__(TPB) void k_x0(const TX *Q1, const TX *X, double *x
   }
 }
 
+template <int MC, typename TX>
+__global__ __launch_bounds__(TPB) void k_x0(const TX *Q1, const TX *X, double *x0, int64_t n, int64_t ld,
+                                            const Ctl *ctl) {
+  x0_body<MC, TX>(Q1, X, x0, n, ld, ctl);
+}
+
+// many sequences' x0 in one launch: grid row y runs job y over its rows
+template <typename TX>
+__global__ __launch_bounds__(TPB) void k_x0_batch(const X0Job *__restrict__ jobs) {
+  const X0Job &j = jobs[blockIdx.y];
+  x0_body<MAXM, TX>((const TX *)j.Q1, (const TX *)j.X, j.x0, j.n, j.ld, j.ctl);
+}
+
 template <typename TX>
 hipError_t launch_x0(const TX *Q1, const TX *X, double *x0, int64_t n, int64_t ld, Ctl *ctl, hipStream_t st) {
   hipLaunchKernelGGL((k_x0<MAXM, TX>), dim3(stream_blocks(n)), dim3(TPB), 0, st, Q1, X, x0, n, ld, ctl);
+  return hipGetLastError();
+}
+
+template <typename TX>
+hipError_t launch_x0_batch(const X0Job *jobs_dev, const X0Job *jobs_host, int njobs, hipStream_t st) {
+  int64_t nmax = 1;
+  for (int i = 0; i < njobs; ++i) nmax = std::max(nmax, jobs_host[i].n);
+  if (njobs > 0) hipLaunchKernelGGL((k_x0_batch<TX>), dim3(stream_blocks(nmax), njobs), dim3(TPB), 0, st, jobs_dev);
   return hipGetLastError();
 }
 
@@ -1857,6 +1897,7 @@ hipError_t launch_zero(double *x, int64_t n, hipStream_t st) {
   template hipError_t launch_spmm_gram<TX>(const CsrView &, const TX *, int64_t, const double *, int, int,    \
                                            double *, int *, Ctl *, hipStream_t);                               \
   template hipError_t launch_x0<TX>(const TX *, const TX *, double *, int64_t, int64_t, Ctl *, hipStream_t);   \
+  template hipError_t launch_x0_batch<TX>(const X0Job *, const X0Job *, int, hipStream_t);                     \
   template hipError_t launch_gram_x<TX>(const TX *, int64_t, int64_t, int, double *, int *, hipStream_t);     \
   template hipError_t launch_to_double<TX>(const TX *, double *, int64_t, hipStream_t);
 
