@@ -1580,9 +1580,8 @@ namespace batchplan {
 // streams: host threads / streams in use; poll: Krylov steps enqueued ahead (stream
 // plans); seg: the solves run in the segmented engine (the streams then carry the
 // guesses and pushes up to their batched QRCP, column-sum, reduced-solve and x0
-// launches); over: the
-// engine's data grid in multiples of the resident blocks; rows: its work-item rows
-// (512 or 1024)
+// launches); over: the engine's data grid in multiples of the resident blocks; rows:
+// its work-item rows (512 or 1024)
 struct Plan {
   int streams, poll, seg, over, rows;
 };
