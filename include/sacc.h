@@ -137,8 +137,10 @@ typedef struct {
   int32_t history;       /* number of history columns used (min(pushes, M))            */
   double relres0;        /* ||b - A x0|| / ||b|| at the start of the last solve        */
   double relres;         /* final ||b - A x|| / ||b|| (true residual)                  */
-  float ms_guess;        /* device time of the last initial guess                     */
-  float ms_solve;        /* device time of the last solve                             */
+  float ms_guess;        /* device time of the last initial guess (segmented batch
+                            step: wall time of the batch's whole guess phase)         */
+  float ms_solve;        /* device time of the last solve (segmented batch step: wall
+                            time of the engine's solve of the whole batch)            */
   int32_t used_learned;  /* 1 if the last guess kept the learned prediction            */
   int32_t reserved;
 } sa_info;

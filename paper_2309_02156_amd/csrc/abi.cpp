@@ -892,10 +892,11 @@ int basis_ahead(sa_seq *q, hipStream_t st) {
 }
 
 // the guess fields of info, after the stream has synchronized past guess_enqueue
-int guess_info(sa_seq *q, int cnt, sa_info *info) {
+// (timed: ms_guess from the guess's events; otherwise the caller fills it)
+int guess_info(sa_seq *q, int cnt, sa_info *info, bool timed = true) {
   const sa_config &c = q->cfg;
   float ms = 0.f;
-  HIP_TRY(hipEventElapsedTime(&ms, q->ev[0], q->ev[1]));
+  if (timed) HIP_TRY(hipEventElapsedTime(&ms, q->ev[0], q->ev[1]));
   const bool proj = cnt > 0 && c.guess == SA_GUESS_PROJECTION;
   const volatile int *rec = (const volatile int *)(q->mir[0] + 2);  // the pinned guess record
   info->k_sketch = proj ? rec[0] : 0;
@@ -1674,6 +1675,8 @@ int batch_step_seg(sa_batch *b, const Plan &plan, const std::vector<std::vector<
   // the guesses up to their SpMM + Gram passes, every sequence of a stream's list
   // enqueued on it; then on the batch stream every sequence's column sums, reduced solve
   // and x0 in one launch each, the learned choices, one wait, and the guess records
+  // (ms_guess: the whole guess phase's wall time, as ms_solve is the engine's)
+  const auto tg0 = std::chrono::steady_clock::now();
   std::vector<int> cnts(nseq, 0);
   std::vector<SolveJob> sj(nseq);
   std::vector<char> deferred(nseq, 0);
@@ -1684,7 +1687,7 @@ int batch_step_seg(sa_batch *b, const Plan &plan, const std::vector<std::vector<
       const int i = lists[s][k];
       memset(&inf[i], 0, sizeof(sa_info));
       bool d = false;
-      r = b->seqs[i]->alive ? guess_begin(b->seqs[i], A[i], rhs[i], x[i], true, st, &cnts[i], &sj[i], &d)
+      r = b->seqs[i]->alive ? guess_begin(b->seqs[i], A[i], rhs[i], x[i], false, st, &cnts[i], &sj[i], &d)
                             : SA_ESTATE;
       deferred[i] = d ? 1 : 0;
     }
@@ -1714,12 +1717,14 @@ int batch_step_seg(sa_batch *b, const Plan &plan, const std::vector<std::vector<
       if (n32 > 0) HIP_TRY(launch_x0_batch<float>(b->dx0, b->hx0, n32, bs));
       if (n64 > 0) HIP_TRY(launch_x0_batch<double>(b->dx0 + n32, b->hx0 + n32, n64, bs));
     }
-    for (int i = 0; i < nseq; ++i) SA_TRY(guess_finish(b->seqs[i], A[i], rhs[i], x[i], true, bs, cnts[i], true));
+    for (int i = 0; i < nseq; ++i) SA_TRY(guess_finish(b->seqs[i], A[i], rhs[i], x[i], false, bs, cnts[i], true));
     HIP_TRY(hipStreamSynchronize(bs));
+    const float gms = (float)(1e3 * std::chrono::duration<double>(std::chrono::steady_clock::now() - tg0).count());
     for (int i = 0; i < nseq; ++i) {
       sa_info g;
       memset(&g, 0, sizeof(g));
-      SA_TRY(guess_info(b->seqs[i], cnts[i], &g));
+      SA_TRY(guess_info(b->seqs[i], cnts[i], &g, false));
+      g.ms_guess = gms;
       guess_into(inf[i], g);
     }
   }
