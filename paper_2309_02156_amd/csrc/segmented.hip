@@ -634,6 +634,30 @@ __device__ inline void seg_coefs(SegState &st) {
 // on a copy of the state in LDS (one thread; the coefficients of the next F step by
 // the block), copied back by the whole block.
 constexpr int SC_TPB = 1024;
+
+// final_sum with U rows per thread and round: the same rows in the same order whatever
+// U, so the sums are the same; U is picked from the segment's partial rows so that a
+// system of few work items does not issue 32 clamped loads per thread
+template <int U>
+__device__ inline void close_sum_u(const double *partials, int nblk, int W, int kc, double *out, double *scratch) {
+  for (int e0 = 0; e0 < kc; e0 += WAVE) {
+    const int ec = kc - e0 < WAVE ? kc - e0 : WAVE;
+    final_tree(final_part<U>(partials + e0, nblk, W, ec), ec, out + e0, scratch);
+  }
+}
+
+__device__ inline void close_sum(const double *partials, int nblk, int W, int kc, double *out, double *scratch) {
+  int ep = 1;
+  while (ep < (kc < WAVE ? kc : WAVE)) ep <<= 1;
+  const int ngrp = SC_TPB / ep;
+  const int rows = (nblk + ngrp - 1) / ngrp;  // rows per thread
+  if (rows <= 1)
+    close_sum_u<1>(partials, nblk, W, kc, out, scratch);
+  else if (rows <= 4)
+    close_sum_u<4>(partials, nblk, W, kc, out, scratch);
+  else
+    close_sum_u<32>(partials, nblk, W, kc, out, scratch);
+}
 static_assert(sizeof(SegState) % sizeof(double) == 0 && offsetof(SegState, Hraw) % sizeof(double) == 0 &&
                   offsetof(SegState, H) > offsetof(SegState, Hraw),
               "state copied as 8-byte words, the Hessenberg arrays last");
@@ -654,7 +678,7 @@ __global__ __launch_bounds__(SC_TPB) void k_seg_close(const SegDesc *__restrict_
   for (int k = threadIdx.x; k < ncopy; k += SC_TPB) ((double *)&ls)[k] = ((const double *)&gs)[k];
   const SegDesc &d = D[s];
   const int kc = phase_cols(phase, gs.j);
-  if (kc > 0) final_sum(d.part, d.nblk, SG_PW, kc, tot, scratch);
+  if (kc > 0) close_sum(d.part, d.nblk, SG_PW, kc, tot, scratch);
   __syncthreads();
   if (threadIdx.x == 0) seg_logic(d, ls, tot, s, (volatile int *)done);
   __syncthreads();
