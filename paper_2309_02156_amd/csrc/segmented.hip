@@ -630,14 +630,12 @@ __device__ inline void seg_coefs(SegState &st) {
   }
 }
 
-// One block per segment: the partial rows' sums in a fixed order, then the scalar logic
-// on a copy of the state in LDS (one thread; the coefficients of the next F step by
-// the block), copied back by the whole block.
-constexpr int SC_TPB = 1024;
+constexpr int SC_TPB = 1024;  // threads of a close block
 
-// final_sum with U rows per thread and round: the same rows in the same order whatever
-// U, so the sums are the same; U is picked from the segment's partial rows so that a
-// system of few work items does not issue 32 clamped loads per thread
+// The close kernel's sum of a segment's partial rows: final_sum with U rows per thread
+// and round.  The rows and their order are the same whatever U, so are the sums; U is
+// picked from the segment's item count so that a system of few work items does not
+// issue 32 clamped loads per thread.
 template <int U>
 __device__ inline void close_sum_u(const double *partials, int nblk, int W, int kc, double *out, double *scratch) {
   for (int e0 = 0; e0 < kc; e0 += WAVE) {
@@ -658,6 +656,10 @@ __device__ inline void close_sum(const double *partials, int nblk, int W, int kc
   else
     close_sum_u<32>(partials, nblk, W, kc, out, scratch);
 }
+
+// One block per segment: the partial rows' sums in a fixed order, then the scalar logic
+// on a copy of the state in LDS (one thread; the coefficients of the next F step by
+// the block), copied back by the whole block.
 static_assert(sizeof(SegState) % sizeof(double) == 0 && offsetof(SegState, Hraw) % sizeof(double) == 0 &&
                   offsetof(SegState, H) > offsetof(SegState, Hraw),
               "state copied as 8-byte words, the Hessenberg arrays last");
