@@ -125,8 +125,9 @@ def test_batch_segmented_graph_equals_eager(sacc, rows, monkeypatch):
     assert ga.plan()["segmented"] and ea.plan()["segmented"]
 
 
-@pytest.mark.parametrize("mode,rows", [("streams", None), ("segmented", 1024), ("segmented", 512)])
-def test_batch_matches_oracle(sacc, mode, rows, monkeypatch):
+@pytest.mark.parametrize("mode,rows,mix", [("streams", None, False), ("segmented", 1024, False),
+                                           ("segmented", 512, False), ("segmented", 1024, True)])
+def test_batch_matches_oracle(sacc, mode, rows, mix, monkeypatch):
     """Each sequence of a batch, stepped by the batch driver in its own configuration
     (float32 operator and Krylov vectors, FP64 history and refinement, up to 100 sweeps),
     against the oracle on the same history: before every step the oracle's history holds
@@ -136,7 +137,10 @@ def test_batch_matches_oracle(sacc, mode, rows, monkeypatch):
     relative), at least one per refinement sweep and 10 % (each side starts from its own
     guess, and the float32 inner solves of the first steps' two sweeps move by several
     iterations under such perturbations); the totals over all steps within 3 %.  The
-    segmented engine runs with each of its work-item sizes (pinned by SACC_SEG_ROWS)."""
+    segmented engine runs with each of its work-item sizes (pinned by SACC_SEG_ROWS);
+    `mix`: two sequences keep float32 histories with the BF16 sketch (`mixed`) and one
+    takes a 160-row sketch, so that the segmented step's batched launches run both
+    storage types (x0) and both QRCP instantiations."""
     import math
 
     import torch
@@ -146,7 +150,10 @@ def test_batch_matches_oracle(sacc, mode, rows, monkeypatch):
 
     probs = batch_problems(seed=4, nseq=5, lo=16, hi=36, steps=40)
     steps = 20
-    print_case("batch vs oracle", [(p.N, m["M"], m["solver"]) for p, m in probs], steps)
+    if mix:
+        probs[0][1]["prec"] = probs[1][1]["prec"] = "mixed"
+        probs[2][1]["s"] = 160
+    print_case("batch vs oracle", [(p.N, m["M"], m["s"], m["solver"], m["prec"]) for p, m in probs], steps)
     seqs = [_seq(sacc, p, m) for p, m in probs]
     batch = sacc.Batch(seqs, max_streams=4, tune_warmup=4)
     batch.set_mode(mode)
